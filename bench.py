@@ -1,0 +1,149 @@
+"""Benchmark: CE factorization + FP64 PCG on one MI355X.
+
+Workload (default): 2D 5-point Dirichlet Laplacian on a 1024 x 1024 grid
+(N = 1,048,576), 8 x 8 Morton patches (B = 64), eps = 1e-6, 16 right-hand
+sides N(0,1) from default_rng(1), PCG in FP64 to a relative residual of 1e-8.
+One step = numeric factorization (all levels, dense remainder) + PCG for the
+16 right-hand sides.  The matrix, permutation and right-hand sides are
+resident on the GPU before the timed region; the host symbolic analysis is
+timed separately (``analysis_ms``) and also inside the step when
+``--with-analysis`` is given.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def _cpu_baseline(side, patch, eps, nrhs_full, full_n):
+    """The FP64 oracle as it stands, on a bounded sample of the workload: the
+    same stencil, patch size and eps on a side x side grid, factorization and
+    PCG for one right-hand side, scaled linearly in N (the method is O(N) on
+    tensor grids) and in the number of right-hand sides."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    import problems
+    with threadpool_limits(limits=1):
+        A = problems.laplacian((side, side))
+        ip, ix, dv = problems.to_csr_arrays(A)
+        perm, bp, co = oracle.grid_order((side, side), patch)
+        t0 = time.perf_counter()
+        f = oracle.ce_factor(ip, ix, dv, perm, bp, co, oracle.CEOptions(eps=eps, order="multicolour"))
+        t1 = time.perf_counter()
+        b = problems.rhs_normal(A.shape[0], 1, seed=1)[:, 0]
+        _, it, rel = oracle.pcg(A, b, lambda r: oracle.ce_solve(f, r), tol=1e-8)
+        t2 = time.perf_counter()
+    scale = full_n / A.shape[0]
+    est = (t1 - t0) * scale + (t2 - t1) * scale * nrhs_full
+    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"{side}x{side} grid (N={A.shape[0]}), same patch/eps, factor {t1 - t0:.2f} s + "
+                       f"PCG 1 RHS {t2 - t1:.2f} s ({it} it); scaled x{scale:.0f} in N and x{nrhs_full} RHS "
+                       f"for the PCG part")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--patch", type=int, default=8)
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--nrhs", type=int, default=16)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--order", choices=["multicolour", "paper"], default="multicolour")
+    ap.add_argument("--with-analysis", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-side", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1603_09133_amd as cae
+    import problems
+
+    dims = (args.side, args.side)
+    patch = (args.patch, args.patch)
+    A = problems.laplacian(dims)
+    ip, ix, dv = problems.to_csr_arrays(A)
+    N = A.shape[0]
+    B = problems.rhs_normal(N, args.nrhs, seed=1)
+    perm, bp, co = cae.grid_order(dims, patch)
+    order = cae.ORDER_MULTICOLOUR if args.order == "multicolour" else cae.ORDER_PAPER
+    t = time.perf_counter()
+    an = cae.Analysis(ip, ix, perm, bp, co, order=order)
+    analysis_ms = (time.perf_counter() - t) * 1e3
+    dev = torch.device("cuda:0")
+    vals = torch.from_numpy(dv).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
+    x = torch.empty_like(b)
+    prec = cae.FP32 if args.precision == "fp32" else cae.FP64
+
+    def step():
+        a = cae.Analysis(ip, ix, perm, bp, co, order=order) if args.with_analysis else an
+        f = cae.Factor(a, vals, args.eps, precision=prec)
+        _, it, rel = f.pcg(b, rtol=1e-8, maxit=1000, x=x)
+        return f, it, rel
+
+    for _ in range(args.warmup):
+        f, it, rel = step()
+        f.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac_ms = []
+    for _ in range(args.steps):
+        f, it, rel = step()
+        fac_ms.append(f.stats()["factor_ms"])
+        st = f.stats()
+        f.close()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    ok = bool(np.all(rel <= 1.0001e-8))
+    # reference FP64 GPU factor iterations (same workload)
+    f64 = cae.Factor(an, vals, args.eps, precision=cae.FP64)
+    _, it64, rel64 = f64.pcg(b, rtol=1e-8, maxit=1000, x=x)
+    f64.close()
+    out = {
+        "metric": "factor+PCG time to 1e-8 residual (2D/3D Laplacian); block-op TFLOP/s vs peak",
+        "value": dt,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 factor + f64 PCG" if prec == cae.FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D 5-point Laplacian {args.side}x{args.side} (N={N}), {args.patch}x{args.patch} "
+                               f"Morton patches (B={args.patch * args.patch}), eps={args.eps}, {args.nrhs} RHS "
+                               f"N(0,1) seed 1, PCG FP64 to 1e-8, {args.order} order",
+                   "factor_ms_mean": float(np.mean(fac_ms)), "analysis_ms": analysis_ms,
+                   "analysis_in_step": bool(args.with_analysis),
+                   "pcg_iters": it.tolist(), "pcg_iters_fp64_factor": it64.tolist(),
+                   "relres_max": float(np.max(rel)), "converged": ok, "levels": st["nlevels"],
+                   "coarse_dim": st["coarse_dim"], "factor_bytes": st["factor_bytes"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(args.cpu_side, patch, args.eps, args.nrhs, N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * cae.h -- C ABI of the compress-and-eliminate (CE) preconditioner for
+ * sparse symmetric positive definite matrices on one MI355X (gfx950).
+ *
+ * The method (Sushnikova & Oseledets, "Compress and eliminate" solver for
+ * symmetric positive definite sparse matrices):
+ *   A0 = P A P^T is split into blocks by the permutation P and the block
+ *   partition (Section 2, eq. (init_perm)).  Level by level, every block row
+ *   i is compressed -- the far blocks F_i of the row are approximated by a
+ *   low-rank factor, U_i^T F_i = [F^_i; E_i] with ||E_i|| below the tolerance
+ *   (eq. (rreav), Remark 2.1) -- and the trailing b_i - r_i rotated unknowns
+ *   are eliminated by block Cholesky (eq. (sm_L)).  The remaining (basis)
+ *   unknowns of 2^d Morton siblings form the blocks of the next level
+ *   (Section 2.6, eq. (bsp)); the last remainder is factored densely.  The
+ *   result is A ~ Q^T L L^T Q (Proposition 2.1); the solve is
+ *   x = Q^T L^{-T} L^{-1} Q b (Proposition 2.2).
+ *
+ * Conventions for every entry point:
+ *   - Return value: 0 (CAE_OK) or a negative cae_status_t.  On error no
+ *     output handle is created and nothing leaks; cae_last_error() returns a
+ *     description (thread-local, valid until the next call on the thread).
+ *   - "host" pointers are read during the call only and never retained.
+ *   - "device" pointers are HIP device memory owned by the caller.  They
+ *     must stay valid until the call returns; work is issued on the stream
+ *     given in cae_options_t (0 = the null stream) and every entry point
+ *     synchronises that stream before it returns.
+ *   - Vectors are FP64, column-major n x nrhs with leading dimension >= n,
+ *     in the ORIGINAL (unpermuted) ordering.
+ *   - A handle may be used by one host thread / stream at a time.
+ */
+#ifndef CAE_H_
+#define CAE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CAE_OK = 0,
+  CAE_EINVAL = -1,    /* invalid argument (shape, range, pattern) */
+  CAE_ENOMEM = -2,    /* device or host allocation failed */
+  CAE_ENOTSPD = -3,   /* a pivot block is not positive definite */
+  CAE_ENOCONV = -4,   /* PCG did not reach the tolerance in maxit */
+  CAE_EDEVICE = -5    /* a HIP call failed */
+} cae_status_t;
+
+typedef enum { CAE_RANK_EPS = 0, CAE_RANK_FIXED = 1 } cae_rank_mode_t;
+typedef enum { CAE_FP64 = 0, CAE_FP32 = 1 } cae_precision_t;
+typedef enum { CAE_ORDER_PAPER = 0, CAE_ORDER_MULTICOLOUR = 1 } cae_order_t;
+
+typedef struct {
+  int32_t struct_size;     /* sizeof(cae_options_t) */
+  int32_t rank_mode;       /* CE(eps) (Remark 2.1, first strategy) or CE(r) (second) */
+  int32_t fixed_rank;      /* r for CE(r) */
+  int32_t precision;       /* arithmetic of the block factorization; the coarse
+                              remainder, the apply vectors and PCG are FP64 */
+  int32_t order;           /* elimination order of every level: PAPER = block order
+                              (Algorithm 2, i = 1..M_j); MULTICOLOUR = greedy colouring
+                              of the block graph at distance 2, blocks ordered by
+                              (colour, index) */
+  int32_t max_levels;      /* K of Algorithm 1; 0 = until one block is left or the
+                              remainder dimension is <= coarse_max_dim */
+  int64_t coarse_max_dim;  /* remainder size factored densely (default 2048) */
+  void* stream;            /* hipStream_t; NULL = null stream */
+} cae_options_t;
+
+/* Fill *opt with the defaults (CE(eps), FP64, MULTICOLOUR, coarse 2048). */
+void cae_default_options(cae_options_t* opt);
+
+typedef struct cae_analysis_s* cae_analysis_t;
+typedef struct cae_factor_s* cae_handle_t;
+
+/*
+ * Initial permutation for a tensor grid (Section 2, eq. (init_perm); Section
+ * 2.9 on the choice of P): patches of patch[k] points per axis, visited in
+ * Z (Morton) order of their coordinates; x fastest inside a patch.  The grid
+ * is numbered naturally with axis 0 fastest.  Partial patches at the high end
+ * of an axis keep their smaller size.
+ *   ndim in {1,2,3}; dims, patch: host, ndim entries, all > 0.
+ *   Query mode: perm == NULL writes only *nblocks.
+ *   Outputs (host, caller-allocated): perm[new] = old (n entries),
+ *   block_ptr (nblocks+1), coords (nblocks*ndim patch coordinates).
+ */
+int cae_grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch,
+                   int32_t* perm, int32_t* block_ptr, int32_t* coords, int32_t* nblocks);
+
+/*
+ * Symbolic analysis (host only, no GPU call): level-1 block pattern of A0
+ * (close blocks, Section 2), elimination order and dependency waves of every
+ * level, the far blocks created by the eliminations (eq. (A_st); remark after
+ * eq. (sm_L)), blocks eliminated whole (empty far row: the first-row
+ * elimination of Section 2.1), and the Morton coarsening (Section 2.6).
+ *   n, row_ptr (n+1), col_idx (row_ptr[n]): host CSR structure of the full
+ *   symmetric matrix A (both triangles, sorted columns, diagonal present).
+ *   perm: host, n entries, A0[i][j] = A[perm[i]][perm[j]].
+ *   block_ptr: host, nblocks+1 bounds of the blocks of A0; NULL = uniform
+ *   blocks of B (the last one may be smaller).
+ *   coords: host, nblocks*ndim block coordinates used for coarsening (parent =
+ *   coordinate >> 1, Morton siblings); NULL = consecutive groups of 2^ndim.
+ *   opt: order and level options (the numeric fields are ignored here).
+ *   The analysis may be shared by several factorizations and outlives them
+ *   only if the caller destroys it last.
+ */
+int cae_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                const int32_t* perm, const int32_t* block_ptr, int32_t nblocks,
+                int32_t B, const int32_t* coords, int32_t ndim,
+                const cae_options_t* opt, cae_analysis_t* out);
+
+typedef struct {
+  int32_t M;            /* blocks of the level */
+  int32_t nclose;       /* close pairs p < q at the start of the level */
+  int32_t nfar;         /* far pairs created during the level */
+  int32_t nremoved;     /* blocks eliminated whole */
+  int32_t nwaves;       /* dependency waves of the order */
+  int32_t Mnext;        /* blocks of the next level */
+} cae_level_info_t;
+
+/* Number of structural levels (until one block is left). */
+int cae_analysis_levels(cae_analysis_t a, int32_t* nlevels);
+int cae_analysis_level_info(cae_analysis_t a, int32_t level, cae_level_info_t* info);
+/* Host arrays, sized from cae_level_info_t; any may be NULL.
+ *   order[M] (elimination order), wave[M] (wave of every block),
+ *   close_pairs[2*nclose], far_pairs[2*nfar] (p<q, sorted),
+ *   removed[M] (1 = eliminated whole), parent[M] (block of the next level). */
+int cae_analysis_level_arrays(cae_analysis_t a, int32_t level, int32_t* order, int32_t* wave,
+                              int32_t* close_pairs, int32_t* far_pairs, uint8_t* removed,
+                              int32_t* parent);
+/* Permutation and level-1 blocks the analysis uses (host, n and nblocks+1). */
+int cae_analysis_perm(cae_analysis_t a, int32_t* perm, int32_t* block_ptr);
+void cae_analysis_destroy(cae_analysis_t a);
+
+/*
+ * Numeric CE factorization on the GPU (Algorithm 1 with Algorithm 2 per
+ * level), A ~ Q^T L L^T Q.
+ *   vals: DEVICE pointer, row_ptr[n] FP64 values of A in the CSR order given
+ *   to cae_analyze.  eps: tolerance of CE(eps); the kept rank of a far row is
+ *   the number of its singular values > eps * max_i A_ii (spectral-norm
+ *   reading of ||E_i|| < eps).  The handle keeps a reference to the analysis
+ *   (destroy the handle first) and a device copy of A for PCG.
+ *   Errors: CAE_ENOTSPD (message names level and block), CAE_EDEVICE.
+ */
+int cae_factor_numeric(cae_analysis_t a, const double* vals, double eps,
+                       const cae_options_t* opt, cae_handle_t* out);
+
+/* z = M^{-1} r, M = Q^T L L^T Q (Proposition 2.2).  r, z: device, n x nrhs. */
+int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr,
+                      double* z, int64_t ldz);
+
+/* y = M x with the stored factor (the approximation of A itself). */
+int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx,
+                     double* y, int64_t ldy);
+
+/*
+ * FP64 preconditioned conjugate gradients with M^{-1} as preconditioner,
+ * x0 = 0, every column stops when ||r_k||_2 <= rtol ||b||_2 (recurrence
+ * residual), at most maxit iterations.
+ *   b, x: device n x nrhs.  iters, relres: host, nrhs entries (iterations and
+ *   true residual ||b - A x|| / ||b|| at exit).  Returns CAE_ENOCONV when a
+ *   column did not converge (x still holds the last iterate).
+ */
+int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
+                  double* x, int64_t ldx, double rtol, int32_t maxit,
+                  int32_t* iters, double* relres);
+
+typedef struct {
+  int32_t nlevels;          /* levels factored (K) */
+  int64_t coarse_dim;       /* dimension of the dense remainder */
+  double tau;               /* max diagonal of A0; threshold = eps * tau */
+  double dropped_sq;        /* sum over all steps of ||E_i||_F^2 */
+  double min_pivot;         /* smallest diagonal entry of L */
+  int64_t factor_bytes;     /* device bytes of the stored factor */
+  double factor_ms;         /* wall time of the last numeric factorization */
+} cae_stats_t;
+
+int cae_get_stats(cae_handle_t h, cae_stats_t* s);
+/* Ranks r_i of a factored level (host, M entries, block index order). */
+int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks);
+/* Block sizes b_i of a factored level (host, M entries). */
+int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes);
+void cae_destroy(cae_handle_t h);
+
+const char* cae_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAE_H_ */

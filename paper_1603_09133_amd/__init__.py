@@ -1,0 +1,215 @@
+"""Compress-and-eliminate (CE) approximate block Cholesky on MI355X.
+
+Thin Python layer over the C ABI of ``libcae.so`` (``include/cae.h``):
+
+* :func:`grid_order` -- Morton patch permutation of a tensor grid;
+* :class:`Analysis` -- host symbolic analysis (patterns, orders, waves);
+* :class:`Factor` -- GPU factorization ``A ~ Q^T L L^T Q`` with
+  :meth:`Factor.apply` (``M^{-1}``), :meth:`Factor.multiply` (``M``) and
+  :meth:`Factor.pcg` (FP64 PCG preconditioned by ``M^{-1}``).
+
+Vectors are PyTorch FP64 tensors on the GPU of shape ``(N,)`` or
+``(nrhs, N)`` (one right-hand side per row, i.e. column-major ``N x nrhs``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (CAEError, FP32, FP64, ORDER_MULTICOLOUR, ORDER_PAPER, RANK_EPS, RANK_FIXED, check, lib,
+                   ptr)
+
+__all__ = ["grid_order", "Analysis", "Factor", "CAEError", "FP64", "FP32", "ORDER_PAPER",
+           "ORDER_MULTICOLOUR", "RANK_EPS", "RANK_FIXED", "lib"]
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _i64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+def grid_order(dims, patch):
+    """Morton patch permutation: returns ``perm`` (new -> old), ``block_ptr``
+    and the patch ``coords`` (int32 NumPy arrays)."""
+    nd = len(dims)
+    d, p = _i32(dims), _i32(patch)
+    nb = C.c_int32()
+    check(lib().cae_grid_order(nd, ptr(d), ptr(p), None, None, None, C.byref(nb)))
+    n = int(np.prod(d.astype(np.int64)))
+    perm = np.empty(n, np.int32)
+    bp = np.empty(nb.value + 1, np.int32)
+    co = np.empty((nb.value, nd), np.int32)
+    check(lib().cae_grid_order(nd, ptr(d), ptr(p), ptr(perm), ptr(bp), ptr(co), C.byref(nb)))
+    return perm, bp, co
+
+
+def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
+             coarse_max_dim=2048, stream=None):
+    o = _lib.Options()
+    lib().cae_default_options(C.byref(o))
+    o.order = order
+    o.precision = precision
+    o.rank_mode = rank_mode
+    o.fixed_rank = fixed_rank
+    o.max_levels = max_levels
+    o.coarse_max_dim = coarse_max_dim
+    o.stream = stream
+    return o
+
+
+class Analysis:
+    """Symbolic analysis of a CSR pattern with a permutation and blocks."""
+
+    def __init__(self, indptr, indices, perm, block_ptr=None, coords=None, B=0, order=ORDER_MULTICOLOUR):
+        self._ip, self._ix = _i64(indptr), _i32(indices)
+        self._perm = _i32(perm)
+        n = len(self._ip) - 1
+        bp = None if block_ptr is None else _i32(block_ptr)
+        co = None if coords is None else _i32(coords)
+        ndim = 0 if co is None else (co.shape[1] if co.ndim == 2 else 1)
+        nb = 0 if bp is None else len(bp) - 1
+        self.order = order
+        self.n = n
+        o = _options(order=order)
+        h = C.c_void_p()
+        check(lib().cae_analyze(n, ptr(self._ip), ptr(self._ix), ptr(self._perm), ptr(bp), nb, int(B), ptr(co),
+                                ndim, C.byref(o), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def nlevels(self):
+        v = C.c_int32()
+        check(lib().cae_analysis_levels(self._h, C.byref(v)))
+        return v.value
+
+    def level_info(self, level):
+        info = _lib.LevelInfo()
+        check(lib().cae_analysis_level_info(self._h, level, C.byref(info)))
+        return {k: getattr(info, k) for k, _ in _lib.LevelInfo._fields_}
+
+    def level_arrays(self, level):
+        inf = self.level_info(level)
+        M = inf["M"]
+        order = np.empty(M, np.int32)
+        wave = np.empty(M, np.int32)
+        cp = np.empty((inf["nclose"], 2), np.int32)
+        fp = np.empty((inf["nfar"], 2), np.int32)
+        rem = np.empty(M, np.uint8)
+        par = np.empty(M, np.int32)
+        check(lib().cae_analysis_level_arrays(self._h, level, ptr(order), ptr(wave), ptr(cp), ptr(fp), ptr(rem),
+                                              ptr(par)))
+        return dict(order=order, wave=wave, close_pairs=cp, far_pairs=fp, removed=rem, parent=par)
+
+    def perm(self):
+        perm = np.empty(self.n, np.int32)
+        nb = self.level_info(0)["M"]
+        bp = np.empty(nb + 1, np.int32)
+        check(lib().cae_analysis_perm(self._h, ptr(perm), ptr(bp)))
+        return perm, bp
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cae_analysis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _as_cols(t):
+    """(N,) or (nrhs, N) tensor -> (tensor (nrhs, N) contiguous, nrhs, squeeze)."""
+    if t.dim() == 1:
+        return t.reshape(1, -1).contiguous(), 1, True
+    return t.contiguous(), t.shape[0], False
+
+
+class Factor:
+    """CE factorization on the GPU (``cae_factor_numeric``)."""
+
+    def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
+                 max_levels=0, coarse_max_dim=2048, stream=None):
+        import torch
+        if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.float64):
+            raise TypeError("vals must be a float64 CUDA tensor")
+        self.analysis = analysis
+        self.n = analysis.n
+        self._stream = stream
+        sptr = None if stream is None else stream.cuda_stream
+        self._opts = _options(order=analysis.order, precision=precision, rank_mode=rank_mode,
+                              fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
+                              stream=sptr)
+        h = C.c_void_p()
+        self._vals = vals.contiguous()
+        check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),
+                                       C.byref(h)))
+        self._h = h
+
+    def stats(self):
+        s = _lib.Stats()
+        check(lib().cae_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
+
+    def ranks(self, level):
+        M = self.analysis.level_info(level)["M"]
+        out = np.empty(M, np.int32)
+        check(lib().cae_get_ranks(self._h, level, ptr(out)))
+        return out
+
+    def sizes(self, level):
+        M = self.analysis.level_info(level)["M"]
+        out = np.empty(M, np.int32)
+        check(lib().cae_get_sizes(self._h, level, ptr(out)))
+        return out
+
+    def apply(self, r):
+        """``M^{-1} r``."""
+        import torch
+        rr, k, sq = _as_cols(r)
+        z = torch.empty_like(rr)
+        check(lib().cae_apply_precond(self._h, k, rr.data_ptr(), self.n, z.data_ptr(), self.n))
+        return z.reshape(-1) if sq else z
+
+    def multiply(self, x):
+        """``M x`` with the stored factor."""
+        import torch
+        xx, k, sq = _as_cols(x)
+        y = torch.empty_like(xx)
+        check(lib().cae_apply_factor(self._h, k, xx.data_ptr(), self.n, y.data_ptr(), self.n))
+        return y.reshape(-1) if sq else y
+
+    def pcg(self, b, rtol=1e-8, maxit=1000, x=None):
+        """FP64 PCG; returns ``(x, iters, relres)``; raises on non-convergence
+        unless ``maxit`` is reached on purpose (``CAE_ENOCONV`` is returned as
+        ``converged = False`` in the third element's companion)."""
+        import torch
+        bb, k, sq = _as_cols(b)
+        if x is None:
+            x = torch.empty_like(bb)
+        it = np.zeros(k, np.int32)
+        rel = np.zeros(k, np.float64)
+        rc = check(lib().cae_pcg_solve(self._h, k, bb.data_ptr(), self.n, x.data_ptr(), self.n, float(rtol),
+                                       int(maxit), ptr(it), ptr(rel)), allow=(_lib.CAE_ENOCONV,))
+        self.converged = rc == _lib.CAE_OK
+        return (x.reshape(-1) if sq else x), it, rel
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cae_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

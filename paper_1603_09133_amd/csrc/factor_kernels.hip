@@ -1,0 +1,806 @@
+// HIP kernels (gfx950) of the numeric CE factorization.
+//
+// One level of Algorithm 2 runs as a sequence of dependency waves; inside a
+// wave every step (block row) is independent, and each step is split into
+// five batched kernels:
+//   k_compress : far row F_i -> U_i, r_i                    (eq. (rreav))
+//   k_rotate   : row/column i and stored factor rows by U_i (eq. (q), (big_L))
+//   k_potrf    : Cholesky of S_ii and L(basis_i, n_i)       (eq. (sm_L))
+//   k_trsm     : factor panels L(c, n_i) of close blocks c  (eq. (sm_L))
+//   k_schur    : Schur complement into close and far blocks (eq. (A_st))
+// Every workgroup keeps its operands in LDS when they fit (the `work`
+// pointer), otherwise in a global scratch slice of its own.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "cae_internal.h"
+#include "kernels.h"
+
+namespace cae {
+
+constexpr int NT = 256;
+
+template <typename T>
+struct Eps;
+template <>
+struct Eps<double> {
+  static __device__ double v() { return DBL_EPSILON; }
+  // squared column norms below this are treated as zero by the reflectors:
+  // 2 / tiny stays finite, and such columns are far below any threshold
+  static __device__ double tiny() { return 1e-290; }
+};
+template <>
+struct Eps<float> {
+  static __device__ float v() { return FLT_EPSILON; }
+  static __device__ float tiny() { return 1e-30f; }
+};
+
+// Element (a, c) of the view (i, x) of a step: b_i x b_x.
+template <typename T>
+__device__ inline T* view_ptr(T* base, int trans, int bi, int bx, int a, int c) {
+  return trans ? base + (int64_t)c * bi + a : base + (int64_t)a * bx + c;
+}
+
+template <typename T>
+__device__ inline T* dyn_work(T* gscratch, int64_t per_wg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (gscratch) return gscratch + per_wg * blockIdx.x;
+  return reinterpret_cast<T*>(smem_raw);
+}
+
+// ---------------------------------------------------------------------------
+// Compression: Householder QR of F_i^T, streamed over the far blocks in chunks
+// of 64 rows ([R; C] -> R), then one-sided (Hestenes) Jacobi on the columns of
+// R: R V = X S, so V holds the right singular vectors of R, which are the left
+// singular vectors of F_i.  U_i = V with columns sorted by decreasing sigma.
+// ---------------------------------------------------------------------------
+constexpr int QR_CH = 64;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* gscratch, int64_t per_wg) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int tid = threadIdx.x;
+  T* Ug = A.U + A.u_off[i];
+  if (st.nfar == 0 || b == 0) {
+    for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
+    if (tid == 0) {
+      A.rank[i] = 0;
+      A.edrop[i] = 0.0;
+    }
+    return;
+  }
+  T* work = dyn_work<T>(gscratch, per_wg);
+  const int ld = b + 1;
+  T* R = work;                       // b x ld
+  T* C = R + (int64_t)b * ld;        // max(QR_CH, b) x ld  (chunk, then V)
+  T* part = C + (int64_t)max(QR_CH, b) * ld;   // 4 x b partial dots, then sigma
+  T* cf = part + 4 * b;                        // b reflector coefficients
+  for (int e = tid; e < b * ld; e += NT) R[e] = T(0);
+  __syncthreads();
+
+  const int jl = tid & 63, g = tid >> 6;   // column lane, row group (4 groups)
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    T* base = A.arena + A.slot_off[v.slot];
+    for (int c0 = 0; c0 < w; c0 += QR_CH) {
+      const int m = min(QR_CH, w - c0);
+      // chunk row t = column c0 + t of F_i (row j of the chunk = unknown j of block i)
+      for (int e = tid; e < m * b; e += NT) {
+        int t = e % m, j = e / m;
+        C[t * ld + j] = *view_ptr(base, v.trans, b, bx, j, c0 + t);
+      }
+      __syncthreads();
+      for (int k = 0; k < b; ++k) {
+        // (a) partial dots of column k with columns j >= k over rows t = g mod 4
+        for (int j = k + jl; j < b; j += 64) {
+          T s = 0;
+          for (int t = g; t < m; t += 4) s += C[t * ld + k] * C[t * ld + j];
+          part[g * b + j] = s;
+        }
+        __syncthreads();
+        // (b) reflector H = I - tau v v^T with v = [R_kk - alpha; C(:,k)]
+        const T xn2 = part[k] + part[b + k] + part[2 * b + k] + part[3 * b + k];
+        const bool reflect = xn2 > Eps<T>::tiny();
+        if (reflect) {
+          const T rkk = R[k * ld + k];
+          const T nrm = sqrt(rkk * rkk + xn2);
+          const T alpha = rkk >= T(0) ? -nrm : nrm;
+          const T v0 = rkk - alpha;
+          const T tau = T(2) / (v0 * v0 + xn2);
+          for (int j = k + 1 + jl; j < b; j += 64) {
+            const T s = v0 * R[k * ld + j] + part[j] + part[b + j] + part[2 * b + j] + part[3 * b + j];
+            const T coef = tau * s;
+            if (g == 0) cf[j] = coef;
+            for (int t = g; t < m; t += 4) C[t * ld + j] -= coef * C[t * ld + k];
+          }
+        }
+        __syncthreads();
+        // (c) row k of R: every thread has read it; wave 0 updates it while
+        // the other waves start the next column (they touch C and part only)
+        if (g == 0 && reflect) {
+          const T rkk = R[k * ld + k];
+          const T nrm = sqrt(rkk * rkk + xn2);
+          const T alpha = rkk >= T(0) ? -nrm : nrm;
+          const T v0 = rkk - alpha;
+          for (int j = k + 1 + jl; j < b; j += 64) R[k * ld + j] -= cf[j] * v0;
+          if (jl == 0) R[k * ld + k] = alpha;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // one-sided Jacobi on the columns of R; V accumulates the rotations
+  T* V = C;
+  for (int e = tid; e < b * ld; e += NT) V[e] = (e / ld == e % ld) ? T(1) : T(0);
+  __syncthreads();
+  const int nb = b + (b & 1);
+  const int npair = nb / 2;
+  // rotation threshold: the computed a_p^T a_q of exactly orthogonal columns
+  // carries a rounding error of a few b*eps, so the threshold must be above it
+  const T tol = T(max(b, 16)) * Eps<T>::v();
+  const int lane8 = tid & 7;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int round = 0; round < nb - 1; ++round) {
+      for (int pp = tid >> 3; pp < npair; pp += NT / 8) {
+        int p, q;
+        if (pp == 0) {
+          p = nb - 1;
+          q = round;
+        } else {
+          p = (round + pp) % (nb - 1);
+          q = (round - pp + (nb - 1)) % (nb - 1);
+        }
+        if (p >= b || q >= b) continue;
+        T a = 0, c = 0, d = 0;
+        for (int l = lane8; l < b; l += 8) {
+          const T x = R[l * ld + p], y = R[l * ld + q];
+          a += x * x;
+          c += y * y;
+          d += x * y;
+        }
+        for (int o = 1; o < 8; o <<= 1) {
+          a += __shfl_xor(a, o, 8);
+          c += __shfl_xor(c, o, 8);
+          d += __shfl_xor(d, o, 8);
+        }
+        if (d != T(0) && fabs(d) > tol * sqrt(a * c)) {
+          const T zeta = (c - a) / (T(2) * d);
+          T t;
+          if (fabs(zeta) > T(1e15))
+            t = T(0.5) / zeta;
+          else
+            t = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+          const T cs = T(1) / sqrt(T(1) + t * t), sn = cs * t;
+          for (int l = lane8; l < b; l += 8) {
+            const T x = R[l * ld + p], y = R[l * ld + q];
+            R[l * ld + p] = cs * x - sn * y;
+            R[l * ld + q] = sn * x + cs * y;
+            const T u = V[l * ld + p], z = V[l * ld + q];
+            V[l * ld + p] = cs * u - sn * z;
+            V[l * ld + q] = sn * u + cs * z;
+          }
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  // singular values = column norms; sort decreasing (ties by index)
+  T* sig = part;
+  for (int j = tid; j < b; j += NT) {
+    T s = 0;
+    for (int l = 0; l < b; ++l) s += R[l * ld + j] * R[l * ld + j];
+    sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  const double theta = *A.theta;
+  int r;
+  if (A.rank_mode == 0) {
+    int cnt = 0;
+    for (int j = 0; j < b; ++j) cnt += (double)sig[j] > theta ? 1 : 0;
+    r = cnt;
+  } else {
+    r = min(A.fixed_rank, b);
+  }
+  for (int j = tid; j < b; j += NT) {
+    const T sj = sig[j];
+    int pos = 0;
+    for (int k = 0; k < b; ++k) pos += (sig[k] > sj || (sig[k] == sj && k < j)) ? 1 : 0;
+    for (int l = 0; l < b; ++l) Ug[(int64_t)l * b + pos] = V[l * ld + j];
+    part[b + j] = (T)pos;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double e = 0.0;
+    for (int j = 0; j < b; ++j)
+      if ((int)part[b + j] >= r) e += (double)sig[j] * (double)sig[j];
+    A.rank[i] = r;
+    A.edrop[i] = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rotation: V_ix <- U_i^T V_ix for close and far views (far views then lose
+// their rows r_i..b_i-1), D <- U_i^T D U_i for the diagonal block.
+// ---------------------------------------------------------------------------
+constexpr int ROT_TC = 64;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rotate(LevelArgs<T> A, int32_t it0, T* gscratch, int64_t per_wg) {
+  const Item item = A.items[it0 + blockIdx.x];
+  const Step st = A.steps[item.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int tid = threadIdx.x;
+  if (b == 0) return;
+  const T* Ug = A.U + A.u_off[i];
+  T* work = dyn_work<T>(gscratch, per_wg);
+  const int ld = b + 1;
+  T* Us = work;                         // U, b x ld
+  T* X = Us + (int64_t)b * ld;          // b x (ROT_TC+1)  or  b x ld for the diagonal
+  for (int e = tid; e < b * b; e += NT) Us[(e / b) * ld + e % b] = Ug[e];
+  if (item.view < 0) {
+    T* D = A.arena + A.slot_off[i];
+    T* Y = X;
+    __syncthreads();
+    // Y = U^T D  (D read from memory)
+    for (int e = tid; e < b * b; e += NT) {
+      const int a = e / b, c = e % b;
+      T s = 0;
+      for (int k = 0; k < b; ++k) s += Us[k * ld + a] * D[(int64_t)k * b + c];
+      Y[a * ld + c] = s;
+    }
+    __syncthreads();
+    // D = Y U
+    for (int e = tid; e < b * b; e += NT) {
+      const int a = e / b, c = e % b;
+      T s = 0;
+      for (int k = 0; k < b; ++k) s += Y[a * ld + k] * Us[k * ld + c];
+      D[e] = s;
+    }
+    return;
+  }
+  const View v = A.views[item.view];
+  const int bx = A.bsz[v.x];
+  const bool far = (item.view - st.view0) >= st.nclose;
+  const int r = A.rank[i];
+  T* base = A.arena + A.slot_off[v.slot];
+  const int ldx = ROT_TC + 1;
+  for (int c0 = 0; c0 < bx; c0 += ROT_TC) {
+    const int tc = min(ROT_TC, bx - c0);
+    __syncthreads();
+    for (int e = tid; e < b * tc; e += NT) {
+      const int a = e / tc, c = e % tc;
+      X[a * ldx + c] = *view_ptr(base, v.trans, b, bx, a, c0 + c);
+    }
+    __syncthreads();
+    for (int e = tid; e < b * tc; e += NT) {
+      const int a = e / tc, c = e % tc;
+      T s = 0;
+      if (!(far && a >= r))
+        for (int k = 0; k < b; ++k) s += Us[k * ld + a] * X[k * ldx + c];
+      *view_ptr(base, v.trans, b, bx, a, c0 + c) = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Elimination of S_i: Cholesky of the trailing n x n block of the rotated
+// diagonal block and L(basis_i, n_i)^T = L^{-1} D[n, basis].
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void chol_inplace(T* S, int n, int ld, int* bad) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      T p = S[k * ld + k];
+      if (!(p > T(0))) {
+        *bad = 1;
+        p = T(1);
+      }
+      S[k * ld + k] = sqrt(p);
+    }
+    __syncthreads();
+    const T d = S[k * ld + k];
+    for (int j = k + 1 + tid; j < n; j += NT) S[j * ld + k] /= d;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int e = tid; e < m * m; e += NT) {
+      const int j = k + 1 + e / m, l = k + 1 + e % m;
+      if (l <= j) S[j * ld + l] -= S[j * ld + k] * S[l * ld + k];
+    }
+    __syncthreads();
+  }
+}
+
+// X (n x w, ld ldx) <- L^{-1} X with L lower (n x n, ld ldl).
+template <typename T>
+__device__ void trsm_lower(const T* L, int ldl, T* X, int n, int w, int ldx) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    const T d = L[k * ldl + k];
+    for (int c = tid; c < w; c += NT) X[k * ldx + c] /= d;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int e = tid; e < m * w; e += NT) {
+      const int j = k + 1 + e / w, c = e % w;
+      X[j * ldx + c] -= L[j * ldl + k] * X[k * ldx + c];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_potrf(LevelArgs<T> A, int32_t s0, T* gscratch, int64_t per_wg) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  const int n = b - r;
+  const int tid = threadIdx.x;
+  if (n <= 0) return;
+  T* D = A.arena + A.slot_off[i];
+  T* work = dyn_work<T>(gscratch, per_wg);
+  const int ld = b + 1;
+  T* S = work;                      // n x ld
+  T* X = S + (int64_t)n * ld;       // n x ld (basis columns)
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < n * b; e += NT) {
+    const int j = e / b, c = e % b;
+    const T val = D[(int64_t)(r + j) * b + c];
+    if (c >= r)
+      S[j * ld + (c - r)] = val;
+    else
+      X[j * ld + c] = val;
+  }
+  __syncthreads();
+  chol_inplace(S, n, ld, &bad);
+  if (r > 0) trsm_lower(S, ld, X, n, r, ld);
+  __syncthreads();
+  for (int e = tid; e < n * b; e += NT) {
+    const int j = e / b, c = e % b;
+    T val;
+    if (c >= r)
+      val = (c - r) <= j ? S[j * ld + (c - r)] : T(0);
+    else
+      val = X[j * ld + c];
+    D[(int64_t)(r + j) * b + c] = val;
+  }
+  for (int e = tid; e < r * n; e += NT) D[(int64_t)(e / n) * b + r + e % n] = T(0);
+  if (tid == 0) {
+    double mp = 1e300;
+    for (int k = 0; k < n; ++k) mp = fmin(mp, (double)S[k * ld + k]);
+    A.minpiv[i] = mp;
+    if (bad) {
+      if (atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
+    }
+  }
+}
+
+// L(c, n_i)^T = L^{-1} V_ic[n_i, live_c] for a close block c.
+constexpr int TRSM_TC = 64;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_trsm(LevelArgs<T> A, int32_t it0, T* gscratch, int64_t per_wg) {
+  const Item item = A.items[it0 + blockIdx.x];
+  const Step st = A.steps[item.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const View v = A.views[item.view];
+  const int bx = A.bsz[v.x];
+  const int lc = v.proc ? A.rank[v.x] : bx;
+  if (lc == 0) return;
+  const int tid = threadIdx.x;
+  const T* D = A.arena + A.slot_off[i];
+  T* base = A.arena + A.slot_off[v.slot];
+  T* work = dyn_work<T>(gscratch, per_wg);
+  const int ld = n + 1, ldx = TRSM_TC + 1;
+  T* Ls = work;                       // n x ld
+  T* X = Ls + (int64_t)n * ld;        // n x ldx
+  for (int e = tid; e < n * n; e += NT) {
+    const int j = e / n, c = e % n;
+    Ls[j * ld + c] = D[(int64_t)(r + j) * b + r + c];
+  }
+  for (int c0 = 0; c0 < lc; c0 += TRSM_TC) {
+    const int tc = min(TRSM_TC, lc - c0);
+    __syncthreads();
+    for (int e = tid; e < n * tc; e += NT) {
+      const int j = e / tc, c = e % tc;
+      X[j * ldx + c] = *view_ptr(base, v.trans, b, bx, r + j, c0 + c);
+    }
+    __syncthreads();
+    trsm_lower(Ls, ld, X, n, tc, ldx);
+    for (int e = tid; e < n * tc; e += NT) {
+      const int j = e / tc, c = e % tc;
+      *view_ptr(base, v.trans, b, bx, r + j, c0 + c) = X[j * ldx + c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Schur complement: T(a, c) -= P_a^T P_c with P_a = rows n_i of view a
+// (a = 0: basis columns of the diagonal block).
+// ---------------------------------------------------------------------------
+constexpr int SCH_TC = 64;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur(LevelArgs<T> A, int32_t p0, T* gscratch, int64_t per_wg) {
+  const Pair pr = A.pairs[p0 + blockIdx.x];
+  const Step st = A.steps[pr.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const int tid = threadIdx.x;
+  T* D = A.arena + A.slot_off[i];
+  // panel a
+  int la, lc, ba = b, bc = b, ta = 0, tc_ = 0;
+  T* pa;
+  T* pc;
+  if (pr.a == 0) {
+    la = r;
+    pa = D;
+  } else {
+    const View va = A.views[st.view0 + pr.a - 1];
+    ba = A.bsz[va.x];
+    la = va.proc ? A.rank[va.x] : ba;
+    pa = A.arena + A.slot_off[va.slot];
+    ta = va.trans;
+  }
+  if (pr.c == 0) {
+    lc = r;
+    pc = D;
+  } else {
+    const View vc = A.views[st.view0 + pr.c - 1];
+    bc = A.bsz[vc.x];
+    lc = vc.proc ? A.rank[vc.x] : bc;
+    pc = A.arena + A.slot_off[vc.slot];
+    tc_ = vc.trans;
+  }
+  if (la == 0 || lc == 0) return;
+  // target accessor
+  T* tbase;
+  int64_t ts_a, ts_c;       // strides for (alpha, gamma)
+  if (pr.a == 0) {
+    if (pr.c == 0) {
+      tbase = D;
+      ts_a = b;
+      ts_c = 1;
+    } else {
+      tbase = pc;           // rows 0..r-1 of view c
+      ts_a = tc_ ? 1 : bc;
+      ts_c = tc_ ? b : 1;
+    }
+  } else {
+    tbase = A.arena + A.slot_off[pr.slot];
+    if (pr.trans) {         // stored with the rows of x_c: (gamma, alpha)
+      ts_a = 1;
+      ts_c = ba;
+    } else {
+      ts_a = bc;
+      ts_c = 1;
+    }
+  }
+  T* work = dyn_work<T>(gscratch, per_wg);
+  const int lda = la + 1, ldc = SCH_TC + 1;
+  T* Pa = work;                         // n x lda
+  T* Pc = Pa + (int64_t)n * lda;        // n x ldc
+  for (int e = tid; e < n * la; e += NT) {
+    const int t = e / la, al = e % la;
+    Pa[t * lda + al] = *view_ptr(pa, ta, b, ba, r + t, al);
+  }
+  for (int c0 = 0; c0 < lc; c0 += SCH_TC) {
+    const int tcn = min(SCH_TC, lc - c0);
+    __syncthreads();
+    for (int e = tid; e < n * tcn; e += NT) {
+      const int t = e / tcn, gm = e % tcn;
+      Pc[t * ldc + gm] = *view_ptr(pc, tc_, b, bc, r + t, c0 + gm);
+    }
+    __syncthreads();
+    for (int e = tid; e < la * tcn; e += NT) {
+      const int al = e / tcn, gm = e % tcn;
+      T s = 0;
+      for (int t = 0; t < n; ++t) s += Pa[t * lda + al] * Pc[t * ldc + gm];
+      tbase[al * ts_a + (int64_t)(c0 + gm) * ts_c] -= s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level set-up and transition.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_scatter_a0(T* arena, const double* vals, const int64_t* dst, int64_t nnz) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = dst[e];
+    if (d >= 0) arena[d] = (T)vals[e];
+  }
+}
+
+// out[0] = eps * max_i A_ii, out[1] = max_i A_ii.  Diagonal entries of an SPD
+// matrix are positive, so their IEEE bit patterns order like the values;
+// out[1] is cleared beforehand.
+__global__ void k_theta_max(const double* vals, const int64_t* diag_pos, int64_t n, unsigned long long* out_bits) {
+  __shared__ double red[NT];
+  double m = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    m = fmax(m, vals[diag_pos[i]]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] > 0.0) atomicMax(out_bits, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void k_theta_fin(double eps, double* out) { out[0] = eps * out[1]; }
+
+template <typename T>
+__global__ void k_gather_next(const Trans* items, const T* src, const int64_t* src_off, const int32_t* bsz,
+                              const int32_t* rank, const int32_t* parent, const int32_t* off_in_parent,
+                              T* dst, const int64_t* dst_off, const int32_t* bsz_next) {
+  const Trans t = items[blockIdx.x];
+  const int rp = rank[t.p], rq = rank[t.q];
+  if (rp == 0 || rq == 0) return;
+  const int bq = bsz[t.q];
+  const int ldn = bsz_next[parent[t.q]];
+  const int op = off_in_parent[t.p], oq = off_in_parent[t.q];
+  const T* s = src + src_off[t.src_slot];
+  T* d = dst + dst_off[t.dst_slot];
+  const bool mirror = (t.p != t.q) && (parent[t.p] == parent[t.q]);
+  for (int e = threadIdx.x; e < rp * rq; e += blockDim.x) {
+    const int a = e / rq, c = e % rq;
+    const T val = s[(int64_t)a * bq + c];
+    d[(int64_t)(op + a) * ldn + oq + c] = val;
+    if (mirror) d[(int64_t)(oq + c) * ldn + op + a] = val;
+  }
+}
+
+// Dense remainder A_K (FP64, row-major dim x dim) from the slots of a level.
+template <typename T>
+__global__ void k_coarse_assemble(const int32_t* slot_p, const int32_t* slot_q, const T* arena,
+                                  const int64_t* slot_off, const int32_t* bsz, const int64_t* dof_off,
+                                  double* Ad, int64_t dim) {
+  const int s = blockIdx.x;
+  const int p = slot_p[s], q = slot_q[s];
+  const int bp = bsz[p], bq = bsz[q];
+  const T* src = arena + slot_off[s];
+  const int64_t op = dof_off[p], oq = dof_off[q];
+  for (int e = threadIdx.x; e < bp * bq; e += blockDim.x) {
+    const int a = e / bq, c = e % bq;
+    const double v = (double)src[e];
+    Ad[(op + a) * dim + oq + c] = v;
+    if (p != q) Ad[(oq + c) * dim + op + a] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense inverse of the remainder by symmetric block Gauss-Jordan sweeps:
+// after sweeping every pivot block the matrix holds -A_K^{-1}.
+// ---------------------------------------------------------------------------
+constexpr int GJ = 64;
+
+__global__ __launch_bounds__(NT) void k_gj_pivot(double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv,
+                                                 int32_t* err) {
+  __shared__ double S[GJ][GJ + 1];
+  __shared__ double Li[GJ][GJ + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < kb * kb; e += NT) S[e / kb][e % kb] = Ad[(k0 + e / kb) * dim + k0 + e % kb];
+  __syncthreads();
+  chol_inplace(&S[0][0], kb, GJ + 1, &bad);
+  // Li = L^{-1} (lower), column by column via X = I
+  for (int e = tid; e < kb * kb; e += NT) Li[e / kb][e % kb] = (e / kb == e % kb) ? 1.0 : 0.0;
+  __syncthreads();
+  trsm_lower(&S[0][0], GJ + 1, &Li[0][0], kb, kb, GJ + 1);
+  // Pinv = Li^T Li
+  for (int e = tid; e < kb * kb; e += NT) {
+    const int a = e / kb, c = e % kb;
+    double s = 0;
+    for (int t = max(a, c); t < kb; ++t) s += Li[t][a] * Li[t][c];
+    Pinv[a * GJ + c] = s;
+  }
+  if (tid == 0 && bad) {
+    if (atomicCAS(err, 0, 1) == 0) err[1] = -1;
+  }
+}
+
+// W = Pinv * A[k-block, :] and R0 = A[k-block, :]  (kb x dim each, ld dim)
+__global__ __launch_bounds__(NT) void k_gj_rows(const double* Ad, int64_t dim, int64_t k0, int kb,
+                                                const double* Pinv, double* W, double* R0) {
+  __shared__ double P[GJ][GJ + 1];
+  __shared__ double X[GJ][GJ + 1];
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * GJ;
+  const int tc = (int)min<int64_t>(GJ, dim - c0);
+  for (int e = tid; e < kb * kb; e += NT) P[e / kb][e % kb] = Pinv[(e / kb) * GJ + e % kb];
+  for (int e = tid; e < kb * tc; e += NT) {
+    const int t = e / tc, c = e % tc;
+    const double v = Ad[(k0 + t) * dim + c0 + c];
+    X[t][c] = v;
+    R0[t * dim + c0 + c] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kb * tc; e += NT) {
+    const int a = e / tc, c = e % tc;
+    double s = 0;
+    for (int t = 0; t < kb; ++t) s += P[a][t] * X[t][c];
+    W[a * dim + c0 + c] = s;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64_t k0, int kb,
+                                                  const double* Pinv, const double* W, const double* R0) {
+  __shared__ double Ri[GJ][GJ + 1];
+  __shared__ double Wj[GJ][GJ + 1];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * GJ, j0 = (int64_t)blockIdx.x * GJ;
+  const int ti = (int)min<int64_t>(GJ, dim - i0), tj = (int)min<int64_t>(GJ, dim - j0);
+  for (int e = tid; e < kb * ti; e += NT) Ri[e / ti][e % ti] = R0[(e / ti) * dim + i0 + e % ti];
+  for (int e = tid; e < kb * tj; e += NT) Wj[e / tj][e % tj] = W[(e / tj) * dim + j0 + e % tj];
+  __syncthreads();
+  for (int e = tid; e < ti * tj; e += NT) {
+    const int64_t i = i0 + e / tj, j = j0 + e % tj;
+    const bool ik = i >= k0 && i < k0 + kb, jk = j >= k0 && j < k0 + kb;
+    double v;
+    if (ik && jk) {
+      v = -Pinv[(i - k0) * GJ + (j - k0)];
+    } else if (ik) {
+      v = W[(i - k0) * dim + j];
+    } else if (jk) {
+      v = W[(j - k0) * dim + i];
+    } else {
+      double s = 0;
+      for (int t = 0; t < kb; ++t) s += Ri[t][e / tj] * Wj[t][e % tj];
+      v = Ad[i * dim + j] - s;
+    }
+    Ad[i * dim + j] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename T>
+static void launch(void (*kern)(LevelArgs<T>, int32_t, T*, int64_t), const LevelArgs<T>& A, int32_t start,
+                   int32_t count, size_t work_elems, T* gscratch, hipStream_t stream) {
+  if (count <= 0) return;
+  const size_t bytes = work_elems * sizeof(T);
+  if (bytes <= max_lds_bytes()) {
+    hipLaunchKernelGGL(kern, dim3(count), dim3(NT), bytes, stream, A, start, (T*)nullptr, (int64_t)0);
+  } else {
+    hipLaunchKernelGGL(kern, dim3(count), dim3(NT), 0, stream, A, start, gscratch, (int64_t)work_elems);
+  }
+}
+
+template <typename T>
+size_t work_compress(int bmax) {
+  return (size_t)bmax * (bmax + 1) + (size_t)(bmax > QR_CH ? bmax : QR_CH) * (bmax + 1) + 5 * (size_t)bmax + 8;
+}
+template <typename T>
+size_t work_rotate(int bmax) {
+  return (size_t)bmax * (bmax + 1) + (size_t)bmax * (bmax > ROT_TC ? bmax + 1 : ROT_TC + 1);
+}
+template <typename T>
+size_t work_potrf(int bmax) {
+  return (size_t)2 * bmax * (bmax + 1);
+}
+template <typename T>
+size_t work_trsm(int bmax) {
+  return (size_t)bmax * (bmax + 1) + (size_t)bmax * (TRSM_TC + 1);
+}
+template <typename T>
+size_t work_schur(int bmax) {
+  return (size_t)bmax * (bmax + 1) + (size_t)bmax * (SCH_TC + 1);
+}
+
+template <typename T>
+size_t factor_scratch_elems(int bmax) {
+  size_t m = work_compress<T>(bmax);
+  m = m > work_rotate<T>(bmax) ? m : work_rotate<T>(bmax);
+  m = m > work_potrf<T>(bmax) ? m : work_potrf<T>(bmax);
+  m = m > work_trsm<T>(bmax) ? m : work_trsm<T>(bmax);
+  m = m > work_schur<T>(bmax) ? m : work_schur<T>(bmax);
+  return m;
+}
+
+template <typename T>
+bool factor_needs_global(int bmax) {
+  return factor_scratch_elems<T>(bmax) * sizeof(T) > max_lds_bytes();
+}
+
+template <typename T>
+void launch_wave(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
+  T* gs = gscratch;
+  launch<T>(k_compress<T>, A, w.s0, w.s1 - w.s0, work_compress<T>(bmax), gs, stream);
+  LevelArgs<T> B = A;
+  B.items = A.rot;
+  launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
+  launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
+  B.items = A.trsm;
+  launch<T>(k_trsm<T>, B, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream);
+  launch<T>(k_schur<T>, A, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream);
+}
+
+template <typename T>
+void launch_scatter_a0(T* arena, const double* vals, const int64_t* dst, int64_t nnz, hipStream_t stream) {
+  int64_t blocks = (nnz + NT - 1) / NT;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_scatter_a0<T>, dim3((unsigned)blocks), dim3(NT), 0, stream, arena, vals, dst, nnz);
+}
+
+void launch_theta(const double* vals, const int64_t* diag_pos, int64_t n, double eps, double* out,
+                  hipStream_t stream) {
+  (void)hipMemsetAsync(out, 0, 2 * sizeof(double), stream);
+  int64_t blocks = (n + NT - 1) / NT;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_theta_max, dim3((unsigned)blocks), dim3(NT), 0, stream, vals, diag_pos, n,
+                     reinterpret_cast<unsigned long long*>(out + 1));
+  hipLaunchKernelGGL(k_theta_fin, dim3(1), dim3(1), 0, stream, eps, out);
+}
+
+template <typename T>
+void launch_gather_next(const Trans* items, int32_t nitems, const T* src, const int64_t* src_off,
+                        const int32_t* bsz, const int32_t* rank, const int32_t* parent,
+                        const int32_t* off_in_parent, T* dst, const int64_t* dst_off, const int32_t* bsz_next,
+                        hipStream_t stream) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_gather_next<T>, dim3(nitems), dim3(NT), 0, stream, items, src, src_off, bsz, rank, parent,
+                     off_in_parent, dst, dst_off, bsz_next);
+}
+
+template <typename T>
+void launch_coarse_assemble(const int32_t* slot_p, const int32_t* slot_q, int32_t nslots, const T* arena,
+                            const int64_t* slot_off, const int32_t* bsz, const int64_t* dof_off, double* Ad,
+                            int64_t dim, hipStream_t stream) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_coarse_assemble<T>, dim3(nslots), dim3(NT), 0, stream, slot_p, slot_q, arena, slot_off, bsz,
+                     dof_off, Ad, dim);
+}
+
+void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double* R0, int32_t* err,
+                       hipStream_t stream) {
+  const unsigned nt = (unsigned)((dim + GJ - 1) / GJ);
+  for (int64_t k0 = 0; k0 < dim; k0 += GJ) {
+    const int kb = (int)std::min<int64_t>(GJ, dim - k0);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), 0, stream, Ad, dim, k0, kb, Pinv, err);
+    hipLaunchKernelGGL(k_gj_rows, dim3(nt), dim3(NT), 0, stream, (const double*)Ad, dim, k0, kb,
+                       (const double*)Pinv, W, R0);
+    hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(NT), 0, stream, Ad, dim, k0, kb, (const double*)Pinv,
+                       (const double*)W, (const double*)R0);
+  }
+}
+
+#define CAE_INST(T)                                                                                         \
+  template size_t factor_scratch_elems<T>(int);                                                            \
+  template bool factor_needs_global<T>(int);                                                               \
+  template void launch_wave<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);               \
+  template void launch_scatter_a0<T>(T*, const double*, const int64_t*, int64_t, hipStream_t);             \
+  template void launch_gather_next<T>(const Trans*, int32_t, const T*, const int64_t*, const int32_t*,     \
+                                      const int32_t*, const int32_t*, const int32_t*, T*, const int64_t*,  \
+                                      const int32_t*, hipStream_t);                                        \
+  template void launch_coarse_assemble<T>(const int32_t*, const int32_t*, int32_t, const T*, const int64_t*, \
+                                          const int32_t*, const int64_t*, double*, int64_t, hipStream_t);
+CAE_INST(double)
+CAE_INST(float)
+
+}  // namespace cae

@@ -1,0 +1,132 @@
+// Launch interfaces of the HIP kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "cae_internal.h"
+
+namespace cae {
+
+// Largest dynamic LDS allocation of one workgroup (set from the device).
+size_t max_lds_bytes();
+void set_max_lds_bytes(size_t b);
+
+template <typename T>
+struct LevelArgs {
+  T* arena;                 // slots of the level
+  const int64_t* slot_off;  // element offset of every slot
+  const int32_t* bsz;       // block sizes b_i
+  T* U;                     // U_i, b_i x b_i row-major
+  const int64_t* u_off;
+  int32_t* rank;            // r_i (written by the compression of step i)
+  double* edrop;            // ||E_i||_F^2
+  double* minpiv;           // smallest diagonal entry of the Cholesky factor of S_ii
+  const Step* steps;
+  const View* views;
+  const Item* items;        // set per kernel (rotation or triangular-solve items)
+  const Item* rot;
+  const Item* trsm;
+  const Pair* pairs;
+  int32_t* err;             // [0] non-SPD flag, [1] block
+  const double* theta;      // eps * max diag(A0)
+  int32_t rank_mode;        // 0 CE(eps), 1 CE(r)
+  int32_t fixed_rank;
+};
+
+struct WaveRange {
+  int32_t s0, s1;   // steps
+  int32_t r0, r1;   // rotation items
+  int32_t t0, t1;   // triangular-solve items
+  int32_t p0, p1;   // Schur targets
+};
+
+template <typename T>
+size_t factor_scratch_elems(int bmax);
+template <typename T>
+bool factor_needs_global(int bmax);
+template <typename T>
+void launch_wave(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);
+template <typename T>
+void launch_scatter_a0(T* arena, const double* vals, const int64_t* dst, int64_t nnz, hipStream_t stream);
+void launch_theta(const double* vals, const int64_t* diag_pos, int64_t n, double eps, double* out,
+                  hipStream_t stream);
+template <typename T>
+void launch_gather_next(const Trans* items, int32_t nitems, const T* src, const int64_t* src_off,
+                        const int32_t* bsz, const int32_t* rank, const int32_t* parent,
+                        const int32_t* off_in_parent, T* dst, const int64_t* dst_off, const int32_t* bsz_next,
+                        hipStream_t stream);
+template <typename T>
+void launch_coarse_assemble(const int32_t* slot_p, const int32_t* slot_q, int32_t nslots, const T* arena,
+                            const int64_t* slot_off, const int32_t* bsz, const int64_t* dof_off, double* Ad,
+                            int64_t dim, hipStream_t stream);
+// In place: Ad (dim x dim, symmetric positive definite) -> -Ad^{-1}.
+// Pinv: 64*64, W and R0: 64*dim scratch.  err[0] set on a non-positive pivot.
+void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double* R0, int32_t* err,
+                       hipStream_t stream);
+
+// ------------------------------------------------------------------ apply ---
+template <typename T>
+struct ApplyArgs {
+  const T* arena;
+  const int64_t* slot_off;
+  const int32_t* bsz;
+  const int32_t* rank;
+  const T* U;
+  const int64_t* u_off;
+  const int64_t* dof_off;   // first unknown of every block in the level vector
+  const Step* steps;
+  const View* views;
+  int32_t nrhs;
+};
+
+// y_i <- U_i^T y_i (dir 0) or U_i y_i (dir 1) for every block with a far row.
+template <typename T>
+void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir, int bmax, hipStream_t stream);
+// forward / backward block solves of one wave
+template <typename T>
+void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream);
+template <typename T>
+void launch_ap_bwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream);
+// multiply: w = Lcheck^T z (all steps), out += Lcheck w (one wave)
+template <typename T>
+void launch_mul_w(const ApplyArgs<T>& A, int32_t nsteps, const double* z, double* w, int bmax,
+                  hipStream_t stream);
+template <typename T>
+void launch_mul_lw(const ApplyArgs<T>& A, int32_t s0, int32_t s1, const double* w, double* out, int bmax,
+                   hipStream_t stream);
+// basis parts between a level vector and the next level vector
+void launch_to_next(int32_t M, const int64_t* dof_off, const int32_t* rank, const int32_t* parent,
+                    const int32_t* off_in_parent, const int64_t* dof_off_next, int32_t nrhs, const double* y,
+                    double* ynext, int dir, hipStream_t stream);
+// out = -Ainv_store * y  (Ainv_store holds -A_K^{-1})
+void launch_coarse_apply(const double* Aneg_inv, int64_t dim, int32_t nrhs, const double* y, double* out,
+                         hipStream_t stream);
+void launch_coarse_mul(const double* Ad, int64_t dim, int32_t nrhs, const double* y, double* out,
+                       hipStream_t stream);
+// permutations between column-major user vectors and the level-1 layout
+void launch_perm_in(int64_t n, int32_t nrhs, const int32_t* perm, const double* x, int64_t ldx, double* y,
+                    hipStream_t stream);
+void launch_perm_out(int64_t n, int32_t nrhs, const int32_t* perm, const double* y, double* x, int64_t ldx,
+                     hipStream_t stream);
+
+// -------------------------------------------------------------------- PCG ---
+void launch_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals, int32_t nrhs,
+                 const double* x, int64_t ldx, double* y, int64_t ldy, hipStream_t stream);
+// out[k] = sum_i a[i + k*lda] * b[i + k*ldb]; partial: scratch of nrhs * 1024
+void launch_dots(int64_t n, int32_t nrhs, const double* a, int64_t lda, const double* b, int64_t ldb,
+                 double* partial, double* out, hipStream_t stream);
+// x += alpha p, r -= alpha q with alpha[k] = active[k] ? rz[k] / pq[k] : 0
+void launch_pcg_xr(int64_t n, int32_t nrhs, const double* rz, const double* pq, const int32_t* active,
+                   double* x, int64_t ldx, const double* p, double* r, const double* q, hipStream_t stream);
+// p = z + beta p with beta[k] = rz_new[k] / rz[k] (active columns), then rz = rz_new
+void launch_pcg_p(int64_t n, int32_t nrhs, double* rz, const double* rz_new, const int32_t* active,
+                  const double* z, double* p, double* beta, hipStream_t stream);
+void launch_copy_cols(int64_t n, int32_t nrhs, const double* a, int64_t lda, double* b, int64_t ldb,
+                      hipStream_t stream);
+void launch_fill(double* a, int64_t count, double v, hipStream_t stream);
+// r = b - r (true residual after r = A x)
+void launch_residual(int64_t n, int32_t nrhs, const double* b, int64_t ldb, double* r, hipStream_t stream);
+
+}  // namespace cae

@@ -1,0 +1,772 @@
+// Runtime and C ABI of the compress-and-eliminate preconditioner.
+//
+// The host drives the levels of Algorithm 1: per level it uploads the sizes
+// that depend on the ranks of the previous level (one device-to-host copy of
+// the ranks per level is the only synchronisation of the factorization),
+// launches the dependency waves of Algorithm 2, and gathers the basis parts of
+// 2^d siblings into the next level.  The dense remainder is inverted on the
+// device.  Apply, product and PCG run entirely on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cae.h"
+#include "kernels.h"
+#include "symbolic.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(call)                                         \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) throw HipError{e_, #call};         \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    if (b == 0) b = 8;
+    HIPCHK(hipMalloc(&p, b));
+    bytes = b;
+  }
+  template <typename U>
+  U* as() const {
+    return static_cast<U*>(p);
+  }
+};
+
+template <typename U>
+void upload(DevBuf& d, const std::vector<U>& h, hipStream_t s) {
+  d.alloc(h.size() * sizeof(U));
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice, s));
+}
+
+void init_device_limits() {
+  static bool done = false;
+  if (done) return;
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0) {
+    // leave room for the static LDS of the kernels
+    cae::set_max_lds_bytes((size_t)lds > 8192 ? (size_t)lds - 4096 : (size_t)lds);
+  }
+  done = true;
+}
+
+struct DevLevelSym {
+  DevBuf steps, views, rot, trsm, pairs, trans, slot_p, slot_q, parent;
+};
+
+}  // namespace
+
+struct cae_analysis_s {
+  cae::Analysis a;
+  bool uploaded = false;
+  std::vector<DevLevelSym> dlev;
+  DevBuf row_ptr, col_idx, perm, a0_dst, diag_pos;
+};
+
+namespace {
+
+struct NumLevel {
+  int32_t M = 0, bmax = 0;
+  int64_t dim = 0;
+  std::vector<int32_t> sizes, ranks;
+  std::vector<int64_t> slot_off, u_off, dof_off;
+  std::vector<int32_t> off_in_parent;
+  std::vector<cae::WaveRange> waves;
+  DevBuf arena, U, bsz, d_slot_off, d_u_off, d_dof_off, d_off_in_parent, rank, edrop, minpiv;
+};
+
+}  // namespace
+
+struct cae_factor_s {
+  cae_analysis_t an = nullptr;
+  int precision = 0;
+  size_t esize = 8;
+  cae_options_t opt{};
+  hipStream_t stream = nullptr;
+  std::vector<NumLevel> lev;      // lev[0..K]; lev[K] is the dense remainder
+  int32_t K = 0;                  // factored levels
+  int64_t coarse_dim = 0;
+  DevBuf Ainv, Acopy, vals, theta, err, gscratch, gj_p, gj_w, gj_r;
+  double tau = 0, dropped = 0, min_pivot = 0, factor_ms = 0;
+  int64_t factor_bytes = 0;
+  // apply / multiply / PCG work vectors
+  int32_t vec_nrhs = 0;
+  std::vector<DevBuf> ybuf, wbuf, obuf;
+  DevBuf ctmp;
+  int32_t pcg_nrhs = 0;
+  DevBuf pr, pz, pp, pq, sc, act, partial;
+};
+
+namespace {
+
+void upload_symbolic(cae_analysis_s* A, hipStream_t s) {
+  if (A->uploaded) return;
+  const cae::Analysis& a = A->a;
+  A->dlev.clear();
+  A->dlev.resize(a.levels.size());
+  for (size_t l = 0; l < a.levels.size(); ++l) {
+    const cae::LevelSym& L = a.levels[l];
+    DevLevelSym& D = A->dlev[l];
+    upload(D.steps, L.steps, s);
+    upload(D.views, L.views, s);
+    upload(D.rot, L.rot, s);
+    upload(D.trsm, L.trsm, s);
+    upload(D.pairs, L.pairs, s);
+    upload(D.trans, L.trans, s);
+    upload(D.slot_p, L.slot_p, s);
+    upload(D.slot_q, L.slot_q, s);
+    upload(D.parent, L.parent, s);
+  }
+  upload(A->row_ptr, a.row_ptr, s);
+  upload(A->col_idx, a.col_idx, s);
+  upload(A->perm, a.perm, s);
+  upload(A->a0_dst, a.a0_dst, s);
+  upload(A->diag_pos, a.diag_pos, s);
+  HIPCHK(hipStreamSynchronize(s));
+  A->uploaded = true;
+}
+
+// Sizes of a level -> slot offsets, U offsets, unknown offsets, wave ranges.
+void level_layout(const cae::LevelSym& L, NumLevel& N, size_t esize, hipStream_t s) {
+  N.M = L.M;
+  N.bmax = 0;
+  for (int32_t b : N.sizes) N.bmax = std::max(N.bmax, b);
+  N.slot_off.assign(L.nslots + 1, 0);
+  for (int32_t k = 0; k < L.nslots; ++k)
+    N.slot_off[k + 1] = N.slot_off[k] + (int64_t)N.sizes[L.slot_p[k]] * N.sizes[L.slot_q[k]];
+  N.u_off.assign(L.M + 1, 0);
+  N.dof_off.assign(L.M + 1, 0);
+  for (int32_t i = 0; i < L.M; ++i) {
+    N.u_off[i + 1] = N.u_off[i] + (int64_t)N.sizes[i] * N.sizes[i];
+    N.dof_off[i + 1] = N.dof_off[i] + N.sizes[i];
+  }
+  N.dim = N.dof_off[L.M];
+  N.waves.resize(L.nwaves);
+  for (int32_t w = 0; w < L.nwaves; ++w) {
+    N.waves[w] = cae::WaveRange{L.wave_ptr[w], L.wave_ptr[w + 1], L.rot_ptr[w], L.rot_ptr[w + 1],
+                                L.trsm_ptr[w], L.trsm_ptr[w + 1], L.pair_ptr[w], L.pair_ptr[w + 1]};
+  }
+  upload(N.bsz, N.sizes, s);
+  upload(N.d_slot_off, N.slot_off, s);
+  upload(N.d_u_off, N.u_off, s);
+  upload(N.d_dof_off, N.dof_off, s);
+  N.arena.alloc((size_t)N.slot_off[L.nslots] * esize);
+  HIPCHK(hipMemsetAsync(N.arena.p, 0, (size_t)N.slot_off[L.nslots] * esize, s));
+}
+
+template <typename T>
+cae::LevelArgs<T> level_args(cae_factor_s* h, int l) {
+  const DevLevelSym& D = h->an->dlev[l];
+  NumLevel& N = h->lev[l];
+  cae::LevelArgs<T> A;
+  A.arena = N.arena.as<T>();
+  A.slot_off = N.d_slot_off.as<int64_t>();
+  A.bsz = N.bsz.as<int32_t>();
+  A.U = N.U.as<T>();
+  A.u_off = N.d_u_off.as<int64_t>();
+  A.rank = N.rank.as<int32_t>();
+  A.edrop = N.edrop.as<double>();
+  A.minpiv = N.minpiv.as<double>();
+  A.steps = D.steps.as<cae::Step>();
+  A.views = D.views.as<cae::View>();
+  A.items = nullptr;
+  A.rot = D.rot.as<cae::Item>();
+  A.trsm = D.trsm.as<cae::Item>();
+  A.pairs = D.pairs.as<cae::Pair>();
+  A.err = h->err.as<int32_t>();
+  A.theta = h->theta.as<double>();
+  A.rank_mode = h->opt.rank_mode;
+  A.fixed_rank = h->opt.fixed_rank;
+  return A;
+}
+
+template <typename T>
+cae::ApplyArgs<T> apply_args(cae_factor_s* h, int l, int nrhs) {
+  const DevLevelSym& D = h->an->dlev[l];
+  NumLevel& N = h->lev[l];
+  cae::ApplyArgs<T> A;
+  A.arena = N.arena.as<T>();
+  A.slot_off = N.d_slot_off.as<int64_t>();
+  A.bsz = N.bsz.as<int32_t>();
+  A.rank = N.rank.as<int32_t>();
+  A.U = N.U.as<T>();
+  A.u_off = N.d_u_off.as<int64_t>();
+  A.dof_off = N.d_dof_off.as<int64_t>();
+  A.steps = D.steps.as<cae::Step>();
+  A.views = D.views.as<cae::View>();
+  A.nrhs = nrhs;
+  return A;
+}
+
+template <typename T>
+int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
+  cae_analysis_s* AN = h->an;
+  const cae::Analysis& a = AN->a;
+  hipStream_t s = h->stream;
+  const int64_t nnz = a.row_ptr[a.n];
+  auto t0 = std::chrono::steady_clock::now();
+  upload_symbolic(AN, s);
+  h->vals.alloc(nnz * sizeof(double));
+  HIPCHK(hipMemcpyAsync(h->vals.p, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  h->theta.alloc(2 * sizeof(double));
+  h->err.alloc(2 * sizeof(int32_t));
+  HIPCHK(hipMemsetAsync(h->err.p, 0, 2 * sizeof(int32_t), s));
+  cae::launch_theta(h->vals.as<double>(), AN->diag_pos.as<int64_t>(), a.n, eps, h->theta.as<double>(), s);
+
+  h->lev.clear();
+  h->lev.reserve(a.levels.size());
+  h->lev.emplace_back();
+  {
+    NumLevel& N = h->lev[0];
+    N.sizes.resize(a.levels[0].M);
+    for (int32_t b = 0; b < a.levels[0].M; ++b) N.sizes[b] = a.block_ptr[b + 1] - a.block_ptr[b];
+    level_layout(a.levels[0], N, sizeof(T), s);
+    cae::launch_scatter_a0<T>(N.arena.as<T>(), h->vals.as<double>(), AN->a0_dst.as<int64_t>(), nnz, s);
+  }
+  double dropped = 0.0, minpiv = 1e300;
+  int l = 0;
+  while (true) {
+    const cae::LevelSym& L = a.levels[l];
+    NumLevel& N = h->lev[l];
+    const bool stop = L.M <= 1 || N.dim <= h->opt.coarse_max_dim ||
+                      (h->opt.max_levels > 0 && l >= h->opt.max_levels) || l + 1 >= (int)a.levels.size();
+    if (stop) break;
+    N.U.alloc((size_t)N.u_off[L.M] * sizeof(T));
+    N.rank.alloc((size_t)L.M * sizeof(int32_t));
+    N.edrop.alloc((size_t)L.M * sizeof(double));
+    N.minpiv.alloc((size_t)L.M * sizeof(double));
+    cae::launch_fill(N.minpiv.as<double>(), L.M, 1e300, s);
+    // per-workgroup global scratch when a kernel's operands exceed the LDS
+    size_t maxitems = 0;
+    for (auto& w : N.waves)
+      maxitems = std::max({maxitems, (size_t)(w.s1 - w.s0), (size_t)(w.r1 - w.r0), (size_t)(w.t1 - w.t0),
+                           (size_t)(w.p1 - w.p0)});
+    T* gs = nullptr;
+    if (cae::factor_needs_global<T>(N.bmax)) {
+      h->gscratch.alloc(maxitems * cae::factor_scratch_elems<T>(N.bmax) * sizeof(T));
+      gs = h->gscratch.as<T>();
+    }
+    cae::LevelArgs<T> A = level_args<T>(h, l);
+    for (auto& w : N.waves) cae::launch_wave<T>(A, w, N.bmax, gs, s);
+    HIPCHK(hipGetLastError());
+    // the ranks decide the sizes of the next level
+    N.ranks.resize(L.M);
+    std::vector<double> ed(L.M), mp(L.M);
+    int32_t herr[2];
+    HIPCHK(hipMemcpyAsync(N.ranks.data(), N.rank.p, L.M * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ed.data(), N.edrop.p, L.M * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(mp.data(), N.minpiv.p, L.M * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(herr, h->err.p, sizeof(herr), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (herr[0]) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "non-SPD pivot block at level %d, block %d", l + 1, herr[1]);
+      return fail(CAE_ENOTSPD, buf);
+    }
+    for (int32_t i = 0; i < L.M; ++i) {
+      dropped += ed[i];
+      minpiv = std::min(minpiv, mp[i]);
+    }
+    h->lev.emplace_back();
+    NumLevel& Nn = h->lev[l + 1];
+    NumLevel& Nc = h->lev[l];
+    Nn.sizes.assign(L.Mnext, 0);
+    Nc.off_in_parent.assign(L.M, 0);
+    for (int32_t c = 0; c < L.M; ++c) {
+      Nc.off_in_parent[c] = Nn.sizes[L.parent[c]];
+      Nn.sizes[L.parent[c]] += Nc.ranks[c];
+    }
+    upload(Nc.d_off_in_parent, Nc.off_in_parent, s);
+    level_layout(a.levels[l + 1], Nn, sizeof(T), s);
+    const DevLevelSym& D = AN->dlev[l];
+    cae::launch_gather_next<T>(D.trans.as<cae::Trans>(), (int32_t)L.trans.size(), Nc.arena.as<T>(),
+                               Nc.d_slot_off.as<int64_t>(), Nc.bsz.as<int32_t>(), Nc.rank.as<int32_t>(),
+                               D.parent.as<int32_t>(), Nc.d_off_in_parent.as<int32_t>(), Nn.arena.as<T>(),
+                               Nn.d_slot_off.as<int64_t>(), Nn.bsz.as<int32_t>(), s);
+    ++l;
+  }
+  h->K = l;
+  // dense remainder: assemble, keep a copy for the product, invert in place
+  NumLevel& N = h->lev[l];
+  const cae::LevelSym& L = a.levels[l];
+  const int64_t dim = N.dim;
+  h->coarse_dim = dim;
+  if (dim > 0) {
+    h->Ainv.alloc((size_t)dim * dim * sizeof(double));
+    h->Acopy.alloc((size_t)dim * dim * sizeof(double));
+    HIPCHK(hipMemsetAsync(h->Ainv.p, 0, (size_t)dim * dim * sizeof(double), s));
+    const DevLevelSym& D = AN->dlev[l];
+    cae::launch_coarse_assemble<T>(D.slot_p.as<int32_t>(), D.slot_q.as<int32_t>(), L.nslots, N.arena.as<T>(),
+                                   N.d_slot_off.as<int64_t>(), N.bsz.as<int32_t>(), N.d_dof_off.as<int64_t>(),
+                                   h->Ainv.as<double>(), dim, s);
+    HIPCHK(hipMemcpyAsync(h->Acopy.p, h->Ainv.p, (size_t)dim * dim * sizeof(double), hipMemcpyDeviceToDevice, s));
+    h->gj_p.alloc(64 * 64 * sizeof(double));
+    h->gj_w.alloc((size_t)64 * dim * sizeof(double));
+    h->gj_r.alloc((size_t)64 * dim * sizeof(double));
+    cae::launch_gj_inverse(h->Ainv.as<double>(), dim, h->gj_p.as<double>(), h->gj_w.as<double>(),
+                           h->gj_r.as<double>(), h->err.as<int32_t>(), s);
+    HIPCHK(hipGetLastError());
+  }
+  int32_t herr[2];
+  double th[2];
+  HIPCHK(hipMemcpyAsync(herr, h->err.p, sizeof(herr), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(th, h->theta.p, sizeof(th), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (herr[0]) return fail(CAE_ENOTSPD, "non-SPD pivot in the dense remainder");
+  h->tau = th[1];
+  h->dropped = dropped;
+  h->min_pivot = minpiv;
+  int64_t bytes = 0;
+  for (int k = 0; k < h->K; ++k)
+    bytes += (h->lev[k].slot_off.back() + h->lev[k].u_off.back()) * (int64_t)sizeof(T);
+  bytes += dim * dim * (int64_t)sizeof(double);
+  h->factor_bytes = bytes;
+  h->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return CAE_OK;
+}
+
+void ensure_vectors(cae_factor_s* h, int32_t nrhs) {
+  if (h->vec_nrhs >= nrhs && (int)h->ybuf.size() == h->K + 1) return;
+  h->ybuf.clear();
+  h->wbuf.clear();
+  h->obuf.clear();
+  h->ybuf.resize(h->K + 1);
+  h->wbuf.resize(h->K + 1);
+  h->obuf.resize(h->K + 1);
+  for (int l = 0; l <= h->K; ++l) {
+    size_t b = (size_t)std::max<int64_t>(h->lev[l].dim, 1) * nrhs * sizeof(double);
+    h->ybuf[l].alloc(b);
+    h->wbuf[l].alloc(b);
+    h->obuf[l].alloc(b);
+  }
+  h->ctmp.alloc((size_t)std::max<int64_t>(h->coarse_dim, 1) * nrhs * sizeof(double));
+  h->vec_nrhs = nrhs;
+}
+
+template <typename T>
+void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+  hipStream_t s = h->stream;
+  const cae::Analysis& a = h->an->a;
+  ensure_vectors(h, nrhs);
+  cae::launch_perm_in(a.n, nrhs, h->an->perm.as<int32_t>(), r, ldr, h->ybuf[0].as<double>(), s);
+  for (int l = 0; l < h->K; ++l) {
+    NumLevel& N = h->lev[l];
+    const cae::LevelSym& L = a.levels[l];
+    auto A = apply_args<T>(h, l, nrhs);
+    double* y = h->ybuf[l].as<double>();
+    cae::launch_ap_rotate<T>(A, L.M, y, 0, N.bmax, s);
+    for (auto& w : N.waves) cae::launch_ap_fwd<T>(A, w.s0, w.s1, y, N.bmax, s);
+    cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
+                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
+                        h->ybuf[l + 1].as<double>(), 0, s);
+  }
+  const int64_t dim = h->coarse_dim;
+  if (dim > 0) {
+    cae::launch_coarse_apply(h->Ainv.as<double>(), dim, nrhs, h->ybuf[h->K].as<double>(), h->ctmp.as<double>(), s);
+    HIPCHK(hipMemcpyAsync(h->ybuf[h->K].p, h->ctmp.p, (size_t)dim * nrhs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  for (int l = h->K - 1; l >= 0; --l) {
+    NumLevel& N = h->lev[l];
+    const cae::LevelSym& L = a.levels[l];
+    auto A = apply_args<T>(h, l, nrhs);
+    double* y = h->ybuf[l].as<double>();
+    cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
+                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
+                        h->ybuf[l + 1].as<double>(), 1, s);
+    for (int w = (int)N.waves.size() - 1; w >= 0; --w)
+      cae::launch_ap_bwd<T>(A, N.waves[w].s0, N.waves[w].s1, y, N.bmax, s);
+    cae::launch_ap_rotate<T>(A, L.M, y, 1, N.bmax, s);
+  }
+  cae::launch_perm_out(a.n, nrhs, h->an->perm.as<int32_t>(), h->ybuf[0].as<double>(), z, ldz, s);
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+void apply_factor(cae_factor_s* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
+  hipStream_t s = h->stream;
+  const cae::Analysis& a = h->an->a;
+  ensure_vectors(h, nrhs);
+  cae::launch_perm_in(a.n, nrhs, h->an->perm.as<int32_t>(), x, ldx, h->ybuf[0].as<double>(), s);
+  for (int l = 0; l < h->K; ++l) {
+    NumLevel& N = h->lev[l];
+    const cae::LevelSym& L = a.levels[l];
+    auto A = apply_args<T>(h, l, nrhs);
+    double* z = h->ybuf[l].as<double>();
+    cae::launch_ap_rotate<T>(A, L.M, z, 0, N.bmax, s);
+    cae::launch_mul_w<T>(A, L.M, z, h->wbuf[l].as<double>(), N.bmax, s);
+    cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
+                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, z,
+                        h->ybuf[l + 1].as<double>(), 0, s);
+  }
+  const int64_t dim = h->coarse_dim;
+  if (dim > 0)
+    cae::launch_coarse_mul(h->Acopy.as<double>(), dim, nrhs, h->ybuf[h->K].as<double>(), h->obuf[h->K].as<double>(), s);
+  for (int l = h->K - 1; l >= 0; --l) {
+    NumLevel& N = h->lev[l];
+    const cae::LevelSym& L = a.levels[l];
+    auto A = apply_args<T>(h, l, nrhs);
+    double* out = h->obuf[l].as<double>();
+    cae::launch_fill(out, N.dim * nrhs, 0.0, s);
+    cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
+                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, out,
+                        h->obuf[l + 1].as<double>(), 1, s);
+    for (auto& w : N.waves) cae::launch_mul_lw<T>(A, w.s0, w.s1, h->wbuf[l].as<double>(), out, N.bmax, s);
+    cae::launch_ap_rotate<T>(A, L.M, out, 1, N.bmax, s);
+  }
+  cae::launch_perm_out(a.n, nrhs, h->an->perm.as<int32_t>(), h->obuf[0].as<double>(), y, ldy, s);
+  HIPCHK(hipGetLastError());
+}
+
+void do_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+  if (h->precision == CAE_FP32)
+    apply_precond<float>(h, nrhs, r, ldr, z, ldz);
+  else
+    apply_precond<double>(h, nrhs, r, ldr, z, ldz);
+}
+
+int check_handle(cae_factor_s* h) {
+  if (!h) return fail(CAE_EINVAL, "null handle");
+  return CAE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cae_default_options(cae_options_t* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->struct_size = sizeof(cae_options_t);
+  opt->rank_mode = CAE_RANK_EPS;
+  opt->fixed_rank = 0;
+  opt->precision = CAE_FP64;
+  opt->order = CAE_ORDER_MULTICOLOUR;
+  opt->max_levels = 0;
+  opt->coarse_max_dim = 2048;
+  opt->stream = nullptr;
+}
+
+const char* cae_last_error(void) { return g_err.c_str(); }
+
+int cae_grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch, int32_t* perm, int32_t* block_ptr,
+                   int32_t* coords, int32_t* nblocks) {
+  if (!dims || !patch || !nblocks) return fail(CAE_EINVAL, "dims, patch and nblocks are required");
+  try {
+    std::vector<int32_t> p, bp, co;
+    std::string e = cae::grid_order(ndim, dims, patch, p, bp, co);
+    if (!e.empty()) return fail(CAE_EINVAL, e);
+    *nblocks = (int32_t)bp.size() - 1;
+    if (perm) std::memcpy(perm, p.data(), p.size() * sizeof(int32_t));
+    if (block_ptr) std::memcpy(block_ptr, bp.data(), bp.size() * sizeof(int32_t));
+    if (coords) std::memcpy(coords, co.data(), co.size() * sizeof(int32_t));
+  } catch (const std::bad_alloc&) {
+    return fail(CAE_ENOMEM, "host allocation failed");
+  }
+  return CAE_OK;
+}
+
+int cae_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* perm,
+                const int32_t* block_ptr, int32_t nblocks, int32_t B, const int32_t* coords, int32_t ndim,
+                const cae_options_t* opt, cae_analysis_t* out) {
+  if (!out) return fail(CAE_EINVAL, "out is required");
+  *out = nullptr;
+  cae_options_t o;
+  cae_default_options(&o);
+  if (opt) {
+    if (opt->struct_size != (int32_t)sizeof(cae_options_t)) return fail(CAE_EINVAL, "options struct_size mismatch");
+    o = *opt;
+  }
+  try {
+    std::unique_ptr<cae_analysis_s> A(new cae_analysis_s);
+    std::string e = cae::analyze(n, row_ptr, col_idx, perm, block_ptr, nblocks, B, coords, ndim, o.order, A->a);
+    if (!e.empty()) return fail(CAE_EINVAL, e);
+    *out = A.release();
+  } catch (const std::bad_alloc&) {
+    return fail(CAE_ENOMEM, "host allocation failed");
+  }
+  return CAE_OK;
+}
+
+int cae_analysis_levels(cae_analysis_t a, int32_t* nlevels) {
+  if (!a || !nlevels) return fail(CAE_EINVAL, "null argument");
+  *nlevels = (int32_t)a->a.levels.size();
+  return CAE_OK;
+}
+
+int cae_analysis_level_info(cae_analysis_t a, int32_t level, cae_level_info_t* info) {
+  if (!a || !info) return fail(CAE_EINVAL, "null argument");
+  if (level < 0 || level >= (int32_t)a->a.levels.size()) return fail(CAE_EINVAL, "level out of range");
+  const cae::LevelSym& L = a->a.levels[level];
+  info->M = L.M;
+  info->nclose = (int32_t)L.close_pairs.size() / 2;
+  info->nfar = (int32_t)L.far_pairs.size() / 2;
+  int32_t nr = 0;
+  for (uint8_t r : L.removed) nr += r;
+  info->nremoved = nr;
+  info->nwaves = L.nwaves;
+  info->Mnext = L.Mnext;
+  return CAE_OK;
+}
+
+int cae_analysis_level_arrays(cae_analysis_t a, int32_t level, int32_t* order, int32_t* wave, int32_t* close_pairs,
+                              int32_t* far_pairs, uint8_t* removed, int32_t* parent) {
+  if (!a) return fail(CAE_EINVAL, "null analysis");
+  if (level < 0 || level >= (int32_t)a->a.levels.size()) return fail(CAE_EINVAL, "level out of range");
+  const cae::LevelSym& L = a->a.levels[level];
+  if (order) std::memcpy(order, L.order.data(), L.order.size() * sizeof(int32_t));
+  if (wave) std::memcpy(wave, L.wave.data(), L.wave.size() * sizeof(int32_t));
+  if (close_pairs) std::memcpy(close_pairs, L.close_pairs.data(), L.close_pairs.size() * sizeof(int32_t));
+  if (far_pairs) std::memcpy(far_pairs, L.far_pairs.data(), L.far_pairs.size() * sizeof(int32_t));
+  if (removed) std::memcpy(removed, L.removed.data(), L.removed.size());
+  if (parent) std::memcpy(parent, L.parent.data(), L.parent.size() * sizeof(int32_t));
+  return CAE_OK;
+}
+
+int cae_analysis_perm(cae_analysis_t a, int32_t* perm, int32_t* block_ptr) {
+  if (!a) return fail(CAE_EINVAL, "null analysis");
+  if (perm) std::memcpy(perm, a->a.perm.data(), a->a.perm.size() * sizeof(int32_t));
+  if (block_ptr) std::memcpy(block_ptr, a->a.block_ptr.data(), a->a.block_ptr.size() * sizeof(int32_t));
+  return CAE_OK;
+}
+
+void cae_analysis_destroy(cae_analysis_t a) { delete a; }
+
+int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const cae_options_t* opt,
+                       cae_handle_t* out) {
+  if (!out) return fail(CAE_EINVAL, "out is required");
+  *out = nullptr;
+  if (!an || !vals) return fail(CAE_EINVAL, "analysis and vals are required");
+  if (!(eps >= 0.0)) return fail(CAE_EINVAL, "eps must be >= 0");
+  cae_options_t o;
+  cae_default_options(&o);
+  if (opt) {
+    if (opt->struct_size != (int32_t)sizeof(cae_options_t)) return fail(CAE_EINVAL, "options struct_size mismatch");
+    o = *opt;
+  }
+  if (o.precision != CAE_FP64 && o.precision != CAE_FP32) return fail(CAE_EINVAL, "unknown precision");
+  if (o.rank_mode != CAE_RANK_EPS && o.rank_mode != CAE_RANK_FIXED) return fail(CAE_EINVAL, "unknown rank mode");
+  if (o.rank_mode == CAE_RANK_FIXED && o.fixed_rank < 0) return fail(CAE_EINVAL, "fixed_rank must be >= 0");
+  if (o.order != an->a.order_kind) return fail(CAE_EINVAL, "order differs from the analysis");
+  try {
+    init_device_limits();
+    std::unique_ptr<cae_factor_s> h(new cae_factor_s);
+    h->an = an;
+    h->opt = o;
+    h->precision = o.precision;
+    h->stream = (hipStream_t)o.stream;
+    int rc = o.precision == CAE_FP32 ? factor_numeric<float>(h.get(), vals, eps)
+                                     : factor_numeric<double>(h.get(), vals, eps);
+    if (rc != CAE_OK) {
+      (void)hipStreamSynchronize(h->stream);
+      return rc;
+    }
+    *out = h.release();
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    return fail(CAE_ENOMEM, "host allocation failed");
+  }
+  return CAE_OK;
+}
+
+int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+  if (check_handle(h)) return CAE_EINVAL;
+  const int64_t n = h->an->a.n;
+  if (nrhs <= 0 || !r || !z || ldr < n || ldz < n) return fail(CAE_EINVAL, "bad vector arguments");
+  try {
+    do_apply(h, nrhs, r, ldr, z, ldz);
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return CAE_OK;
+}
+
+int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
+  if (check_handle(h)) return CAE_EINVAL;
+  const int64_t n = h->an->a.n;
+  if (nrhs <= 0 || !x || !y || ldx < n || ldy < n) return fail(CAE_EINVAL, "bad vector arguments");
+  try {
+    if (h->precision == CAE_FP32)
+      apply_factor<float>(h, nrhs, x, ldx, y, ldy);
+    else
+      apply_factor<double>(h, nrhs, x, ldx, y, ldy);
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return CAE_OK;
+}
+
+int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
+                  int32_t maxit, int32_t* iters, double* relres) {
+  if (check_handle(h)) return CAE_EINVAL;
+  const int64_t n = h->an->a.n;
+  if (nrhs <= 0 || !b || !x || ldb < n || ldx < n || !iters || !relres || maxit < 0 || !(rtol >= 0))
+    return fail(CAE_EINVAL, "bad PCG arguments");
+  hipStream_t s = h->stream;
+  try {
+    const cae_analysis_s* A = h->an;
+    const size_t vb = (size_t)n * nrhs * sizeof(double);
+    h->pr.alloc(vb);
+    h->pz.alloc(vb);
+    h->pp.alloc(vb);
+    h->pq.alloc(vb);
+    h->sc.alloc((size_t)8 * nrhs * sizeof(double));
+    h->act.alloc((size_t)nrhs * sizeof(int32_t));
+    h->partial.alloc((size_t)nrhs * 1024 * sizeof(double));
+    double* r = h->pr.as<double>();
+    double* z = h->pz.as<double>();
+    double* p = h->pp.as<double>();
+    double* q = h->pq.as<double>();
+    double* rz = h->sc.as<double>();
+    double* rz_new = rz + nrhs;
+    double* pq = rz + 2 * nrhs;
+    double* rr = rz + 3 * nrhs;
+    double* beta = rz + 4 * nrhs;
+    double* part = h->partial.as<double>();
+    int32_t* active = h->act.as<int32_t>();
+    const int64_t* rp = A->row_ptr.as<int64_t>();
+    const int32_t* ci = A->col_idx.as<int32_t>();
+    const double* av = h->vals.as<double>();
+
+    for (int k = 0; k < nrhs; ++k) cae::launch_fill(x + k * ldx, n, 0.0, s);
+    cae::launch_copy_cols(n, nrhs, b, ldb, r, n, s);
+    std::vector<double> bn(nrhs), hrr(nrhs);
+    cae::launch_dots(n, nrhs, b, ldb, b, ldb, part, rr, s);
+    HIPCHK(hipMemcpyAsync(bn.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int32_t> hact(nrhs);
+    int nact = 0;
+    for (int k = 0; k < nrhs; ++k) {
+      bn[k] = std::sqrt(bn[k]);
+      hact[k] = bn[k] > 0.0 ? 1 : 0;
+      nact += hact[k];
+      iters[k] = 0;
+    }
+    HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (nact > 0) {
+      do_apply(h, nrhs, r, n, z, n);
+      cae::launch_copy_cols(n, nrhs, z, n, p, n, s);
+      cae::launch_dots(n, nrhs, r, n, z, n, part, rz, s);
+    }
+    int it = 0;
+    while (nact > 0 && it < maxit) {
+      cae::launch_spmv(n, rp, ci, av, nrhs, p, n, q, n, s);
+      cae::launch_dots(n, nrhs, p, n, q, n, part, pq, s);
+      cae::launch_pcg_xr(n, nrhs, rz, pq, active, x, ldx, p, r, q, s);
+      ++it;
+      cae::launch_dots(n, nrhs, r, n, r, n, part, rr, s);
+      HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int k = 0; k < nrhs; ++k) {
+        if (hact[k] && std::sqrt(hrr[k]) <= rtol * bn[k]) {
+          hact[k] = 0;
+          iters[k] = it;
+          --nact;
+        }
+      }
+      if (nact == 0) break;
+      HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      do_apply(h, nrhs, r, n, z, n);
+      cae::launch_dots(n, nrhs, r, n, z, n, part, rz_new, s);
+      cae::launch_pcg_p(n, nrhs, rz, rz_new, active, z, p, beta, s);
+    }
+    for (int k = 0; k < nrhs; ++k)
+      if (hact[k]) iters[k] = it;
+    // true residual
+    cae::launch_spmv(n, rp, ci, av, nrhs, x, ldx, q, n, s);
+    cae::launch_residual(n, nrhs, b, ldb, q, s);
+    cae::launch_dots(n, nrhs, q, n, q, n, part, rr, s);
+    HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < nrhs; ++k) relres[k] = bn[k] > 0 ? std::sqrt(hrr[k]) / bn[k] : 0.0;
+    if (nact > 0) return fail(CAE_ENOCONV, "PCG did not converge within maxit");
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return CAE_OK;
+}
+
+int cae_get_stats(cae_handle_t h, cae_stats_t* st) {
+  if (check_handle(h) || !st) return fail(CAE_EINVAL, "null argument");
+  st->nlevels = h->K;
+  st->coarse_dim = h->coarse_dim;
+  st->tau = h->tau;
+  st->dropped_sq = h->dropped;
+  st->min_pivot = h->min_pivot;
+  st->factor_bytes = h->factor_bytes;
+  st->factor_ms = h->factor_ms;
+  return CAE_OK;
+}
+
+int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks) {
+  if (check_handle(h) || !ranks) return fail(CAE_EINVAL, "null argument");
+  if (level < 0 || level >= h->K) return fail(CAE_EINVAL, "level out of range");
+  std::memcpy(ranks, h->lev[level].ranks.data(), h->lev[level].ranks.size() * sizeof(int32_t));
+  return CAE_OK;
+}
+
+int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes) {
+  if (check_handle(h) || !sizes) return fail(CAE_EINVAL, "null argument");
+  if (level < 0 || level > h->K) return fail(CAE_EINVAL, "level out of range");
+  std::memcpy(sizes, h->lev[level].sizes.data(), h->lev[level].sizes.size() * sizeof(int32_t));
+  return CAE_OK;
+}
+
+void cae_destroy(cae_handle_t h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+"""GPU parity: the HIP factorization against the FP64 oracle, element by
+element on the same seeded inputs, through the C ABI.
+
+Tolerances (FP64 path, readings of the parity bar):
+* ranks of every level equal (a mismatch is allowed only where the oracle's
+  singular value lies within 1e-10 sigma_1 of the threshold);
+* M X with eight N(0,1) probes (default_rng(12345)):
+  ||(M_gpu - M_orc) X||_F <= 1e-12 ||M_orc X||_F;
+* sum of ||E_i||_F^2 within 1e-10 relative;
+* M^{-1} X within 1e-10 relative (amplified by the condition number);
+* PCG iteration counts equal.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import problems
+import oracle
+from oracle import CEOptions, ce_factor, ce_multiply, ce_solve
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _cae():
+    import paper_1603_09133_amd as cae
+    cae.lib()
+    return cae
+
+
+def _probes(N, k=8):
+    return np.random.default_rng(12345).standard_normal((N, k))
+
+
+def _setup(dims, patch, A=None):
+    if A is None:
+        A = problems.laplacian(dims)
+    csr = problems.to_csr_arrays(A)
+    perm, bp, co = oracle.grid_order(dims, patch)
+    return A, csr, perm, bp, co
+
+
+def _gpu_factor(cae, csr, perm, bp, co, eps, order, precision=0, coarse=2048, rank_mode=0, fixed_rank=0):
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co,
+                      order=cae.ORDER_PAPER if order == "paper" else cae.ORDER_MULTICOLOUR)
+    vals = torch.from_numpy(csr[2]).cuda()
+    f = cae.Factor(an, vals, eps, precision=precision, coarse_max_dim=coarse, rank_mode=rank_mode,
+                   fixed_rank=fixed_rank)
+    return an, f
+
+
+def _to_gpu_cols(X):
+    return torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+
+
+def _from_gpu_cols(T):
+    return T.cpu().numpy().T
+
+
+def _check_ranks(f, fo):
+    for l, lf in enumerate(fo.levels):
+        rg = f.ranks(l)
+        bad = np.nonzero(rg != lf.r)[0]
+        for i in bad:
+            s = lf.sigma[i]
+            k = min(rg[i], lf.r[i])
+            assert abs(s[k] - fo.theta) <= 1e-10 * s[0], (l, i, rg[i], lf.r[i])
+
+
+CASES = [
+    ((16, 16), (4, 4), 1e-4, "paper", 0),
+    ((16, 16), (4, 4), 1e-4, "multicolour", 0),
+    ((18, 13), (4, 4), 1e-5, "multicolour", 0),
+    ((40, 24), (8, 8), 1e-6, "multicolour", 0),
+    ((40, 24), (8, 8), 1e-6, "paper", 100),
+    ((8, 8, 8), (2, 2, 2), 1e-3, "multicolour", 0),
+    ((7, 9, 6), (2, 2, 2), 1e-4, "paper", 0),
+    ((64, 64), (4, 4), 1e-8, "multicolour", 2048),
+    ((64, 64), (4, 4), 1e-8, "paper", 0),
+]
+
+
+@pytest.mark.parametrize("dims,patch,eps,order,coarse", CASES)
+def test_factor_matches_oracle_fp64(dims, patch, eps, order, coarse):
+    cae = _cae()
+    A, csr, perm, bp, co = _setup(dims, patch)
+    print(f"case dims={dims} patch={patch} eps={eps} order={order} coarse={coarse}", flush=True)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order=order, coarse_max_dim=coarse))
+    an, f = _gpu_factor(cae, csr, perm, bp, co, eps, order, coarse=coarse)
+    st = f.stats()
+    assert st["nlevels"] == len(fo.levels)
+    assert st["coarse_dim"] == fo.coarse_L.shape[0]
+    _check_ranks(f, fo)
+    for l, lf in enumerate(fo.levels):
+        assert np.array_equal(f.sizes(l), lf.sizes)
+    assert abs(st["tau"] - float(A.diagonal().max())) == 0.0
+    X = _probes(A.shape[0])
+    Mo = ce_multiply(fo, X)
+    Mg = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    assert np.linalg.norm(Mg - Mo) <= 1e-12 * np.linalg.norm(Mo)
+    Zo = ce_solve(fo, X)
+    Zg = _from_gpu_cols(f.apply(_to_gpu_cols(X)))
+    assert np.linalg.norm(Zg - Zo) <= 1e-10 * np.linalg.norm(Zo)
+    # sum of ||E_i||^2: a backward-stable SVD (LAPACK's and the one-sided
+    # Jacobi alike) gives every singular value to within c*u*sigma_1 absolutely,
+    # so |delta e_i| <= 2 c u sigma_1(F_i) sum_{k>r} sigma_k <= 2 c u sigma_1 sqrt(b e_i)
+    d_o = fo.dropped()
+    u = np.finfo(float).eps
+    bound = sum(2 * 64 * u * lf.sigma[i][0] * math.sqrt(lf.sizes[i] * lf.e[i])
+                for lf in fo.levels for i in range(lf.M) if lf.sigma[i].size)
+    assert abs(st["dropped_sq"] - d_o) <= 1e-10 * d_o + bound
+
+
+def test_eps_zero_exact_and_frobenius_identity_on_gpu():
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((20, 20), (4, 4))
+    Ad = A.toarray()
+    an, f0 = _gpu_factor(cae, csr, perm, bp, co, 0.0, "multicolour", coarse=0)
+    I = np.eye(A.shape[0])
+    M0 = _from_gpu_cols(f0.multiply(_to_gpu_cols(I)))
+    assert np.linalg.norm(M0 - Ad) <= 1e-13 * np.linalg.norm(Ad)
+    an, f = _gpu_factor(cae, csr, perm, bp, co, 1e-3, "multicolour", coarse=0)
+    M = _from_gpu_cols(f.multiply(_to_gpu_cols(I)))
+    pred = math.sqrt(2 * f.stats()["dropped_sq"])
+    assert pred > 0
+    assert abs(np.linalg.norm(Ad - M) - pred) <= 1e-8 * pred + 1e-13 * np.linalg.norm(Ad)
+
+
+@pytest.mark.parametrize("order", ["paper", "multicolour"])
+def test_pcg_iterations_match_oracle(order):
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((64, 64), (4, 4))
+    b = problems.rhs_uniform(A.shape[0], 0)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=1e-8, order=order))
+    _, it_o, rel_o = oracle.pcg(A, b, lambda r: ce_solve(fo, r), tol=1e-10)
+    an, f = _gpu_factor(cae, csr, perm, bp, co, 1e-8, order)
+    x, it, rel = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-10, maxit=1000)
+    assert f.converged
+    assert int(it[0]) == it_o
+    xr = x.cpu().numpy()
+    assert np.linalg.norm(b - A @ xr) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+    assert abs(rel[0] - np.linalg.norm(b - A @ xr) / np.linalg.norm(b)) <= 1e-3 * rel[0] + 1e-16
+
+
+def test_multi_rhs_pcg_and_fp32_factor():
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((48, 40), (8, 8))
+    B = problems.rhs_normal(A.shape[0], 4, seed=1)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=1e-6, order="multicolour"))
+    its_o = [oracle.pcg(A, B[:, k], lambda r: ce_solve(fo, r), tol=1e-8)[1] for k in range(4)]
+    an, f = _gpu_factor(cae, csr, perm, bp, co, 1e-6, "multicolour")
+    x, it, rel = f.pcg(_to_gpu_cols(B), rtol=1e-8)
+    assert it.tolist() == its_o
+    assert np.all(rel <= 1.0001e-8)
+    an, f32 = _gpu_factor(cae, csr, perm, bp, co, 1e-6, "multicolour", precision=cae.FP32)
+    X = _probes(A.shape[0])
+    Mo = ce_multiply(fo, X)
+    M32 = _from_gpu_cols(f32.multiply(_to_gpu_cols(X)))
+    err32 = np.linalg.norm(M32 - Mo) / np.linalg.norm(Mo)
+    print(f"fp32 factor probe error vs oracle: {err32:.3e}")
+    assert err32 <= 1e-5
+    x, it32, rel32 = f32.pcg(_to_gpu_cols(B), rtol=1e-8)
+    assert np.all(rel32 <= 1.0001e-8)
+    assert np.all(it32 <= np.array(its_o) + 2)
+
+
+def test_indefinite_matrix_reports_not_spd():
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((16, 16), (4, 4))
+    vals = csr[2].copy()
+    rows = np.repeat(np.arange(256), np.diff(csr[0]))
+    vals[csr[1] == rows] -= 5.0
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    with pytest.raises(cae.CAEError) as e:
+        cae.Factor(an, torch.from_numpy(vals).cuda(), 1e-6, coarse_max_dim=0)
+    assert e.value.code == -3
+
+
+def test_fixed_rank_mode_matches_oracle():
+    """CE(r) element parity where every kept subspace is unique (r = 3 on
+    4x4 patches: the smallest relative gap sigma_r - sigma_{r+1} is 4e-4)."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((32, 32), (4, 4))
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=0.0, rank_mode="fixed", fixed_rank=3, order="multicolour",
+                                                 coarse_max_dim=0))
+    an, f = _gpu_factor(cae, csr, perm, bp, co, 0.0, "multicolour", coarse=0, rank_mode=1, fixed_rank=3)
+    for l, lf in enumerate(fo.levels):
+        assert np.array_equal(f.ranks(l), lf.r)
+    X = _probes(A.shape[0])
+    Mo = ce_multiply(fo, X)
+    Mg = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    assert np.linalg.norm(Mg - Mo) <= 1e-12 * np.linalg.norm(Mo)
+
+
+def test_fixed_rank_paper_parameters_converge():
+    """CE(r) with the paper's recommended r = 4 = B/2 on B = 8 patches: the
+    kept subspace is not unique at every step (tied zero singular values), so
+    the check is the Frobenius identity of the GPU factor and PCG."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((24, 24), (4, 2))
+    an, f = _gpu_factor(cae, csr, perm, bp, co, 0.0, "multicolour", coarse=0, rank_mode=1, fixed_rank=4)
+    Ad = A.toarray()
+    M = _from_gpu_cols(f.multiply(_to_gpu_cols(np.eye(A.shape[0]))))
+    pred = math.sqrt(2 * f.stats()["dropped_sq"])
+    assert abs(np.linalg.norm(Ad - M) - pred) <= 1e-8 * pred + 1e-13 * np.linalg.norm(Ad)
+    b = problems.rhs_uniform(A.shape[0], 0)
+    x, it, rel = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-8)
+    assert f.converged and rel[0] <= 1.0001e-8
