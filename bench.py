@@ -96,7 +96,7 @@ def main():
 
     def step():
         a = cae.Analysis(ip, ix, perm, bp, co, order=order) if args.with_analysis else an
-        f = cae.Factor(a, vals, args.eps, precision=prec)
+        f = cae.Factor(a, vals, args.eps, precision=prec, timing=True)
         _, it, rel = f.pcg(b, rtol=1e-8, maxit=1000, x=x)
         return f, it, rel
 
@@ -106,10 +106,14 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fac_ms = []
+    comp = {"ms": 0.0, "launches": 0, "flops": 0.0}
     for _ in range(args.steps):
         f, it, rel = step()
-        fac_ms.append(f.stats()["factor_ms"])
         st = f.stats()
+        fac_ms.append(st["factor_ms"])
+        comp["ms"] += st["compress_ms"]
+        comp["launches"] += st["compress_launches"]
+        comp["flops"] += st["compress_flops"]
         f.close()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(args.steps, 1)
@@ -140,6 +144,17 @@ def main():
                    "relres_max": float(np.max(rel)), "converged": ok, "levels": st["nlevels"],
                    "coarse_dim": st["coarse_dim"], "factor_bytes": st["factor_bytes"]},
     }
+    # roofline of the dominant kernel (the far-row compression, plain vector
+    # arithmetic: QR + one-sided Jacobi), from HIP events around its launches
+    peak = 157.3 if prec == cae.FP32 else 78.6
+    if comp["launches"]:
+        per_launch_s = comp["ms"] / comp["launches"] / 1e3
+        flops_per_launch = comp["flops"] / comp["launches"]
+        ach = flops_per_launch / per_launch_s / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "k_compress_wave (far-row QR + Jacobi SVD)",
+                           "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                           "traffic": None, "launches_per_step": comp["launches"] / args.steps,
+                           "avg_launch_us": per_launch_s * 1e6, "algorithmic_flops_per_launch": flops_per_launch}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(args.cpu_side, patch, args.eps, args.nrhs, N)
     print(json.dumps(out), flush=True)

@@ -63,6 +63,9 @@ typedef struct {
                               (colour, index) */
   int32_t max_levels;      /* K of Algorithm 1; 0 = until one block is left or the
                               remainder dimension is <= coarse_max_dim */
+  int32_t timing;          /* 1 = time the compression launches with HIP events
+                              (reported by cae_get_stats) */
+  int32_t reserved;        /* 0 */
   int64_t coarse_max_dim;  /* remainder size factored densely (default 2048) */
   void* stream;            /* hipStream_t; NULL = null stream */
 } cae_options_t;
@@ -173,6 +176,13 @@ typedef struct {
   double min_pivot;         /* smallest diagonal entry of L */
   int64_t factor_bytes;     /* device bytes of the stored factor */
   double factor_ms;         /* wall time of the last numeric factorization */
+  /* with cae_options_t.timing: the compression kernels (far row -> U_i, r_i) */
+  int32_t compress_launches;
+  double compress_ms;       /* summed device time of those launches */
+  double compress_flops;    /* algorithmic flops: per far row b x w,
+                               2 w b^2 - 2 b^3 / 3 (QR, w >= b; else 2 b w^2 - 2 w^3 / 3)
+                               + 12 b^3 (SVD of the triangular factor) */
+  int32_t compressions;     /* far rows compressed (steps with a non-empty far row) */
 } cae_stats_t;
 
 int cae_get_stats(cae_handle_t h, cae_stats_t* s);

@@ -49,7 +49,7 @@ def grid_order(dims, patch):
 
 
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
-             coarse_max_dim=2048, stream=None):
+             coarse_max_dim=2048, stream=None, timing=False):
     o = _lib.Options()
     lib().cae_default_options(C.byref(o))
     o.order = order
@@ -59,6 +59,7 @@ def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_
     o.max_levels = max_levels
     o.coarse_max_dim = coarse_max_dim
     o.stream = stream
+    o.timing = 1 if timing else 0
     return o
 
 
@@ -138,7 +139,7 @@ class Factor:
     """CE factorization on the GPU (``cae_factor_numeric``)."""
 
     def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
-                 max_levels=0, coarse_max_dim=2048, stream=None):
+                 max_levels=0, coarse_max_dim=2048, stream=None, timing=False):
         import torch
         if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.float64):
             raise TypeError("vals must be a float64 CUDA tensor")
@@ -148,7 +149,7 @@ class Factor:
         sptr = None if stream is None else stream.cuda_stream
         self._opts = _options(order=analysis.order, precision=precision, rank_mode=rank_mode,
                               fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
-                              stream=sptr)
+                              stream=sptr, timing=timing)
         h = C.c_void_p()
         self._vals = vals.contiguous()
         check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),

@@ -30,6 +30,7 @@ class CAEError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("rank_mode", C.c_int32), ("fixed_rank", C.c_int32),
                 ("precision", C.c_int32), ("order", C.c_int32), ("max_levels", C.c_int32),
+                ("timing", C.c_int32), ("reserved", C.c_int32),
                 ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p)]
 
 
@@ -41,7 +42,8 @@ class LevelInfo(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("coarse_dim", C.c_int64), ("tau", C.c_double),
                 ("dropped_sq", C.c_double), ("min_pivot", C.c_double), ("factor_bytes", C.c_int64),
-                ("factor_ms", C.c_double)]
+                ("factor_ms", C.c_double), ("compress_launches", C.c_int32), ("compress_ms", C.c_double),
+                ("compress_flops", C.c_double), ("compressions", C.c_int32)]
 
 
 _lib = None

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(NT) void k_ap_rotate(ApplyArgs<T> A, double* y, int
 
 // Forward block solve of one step: t = L_nn^{-1} y_i[n]; y_c -= L(c, n) t.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_ap_fwd(ApplyArgs<T> A, int32_t s0, double* y) {
+__global__ __launch_bounds__(NT) void k_ap_fwd_generic(ApplyArgs<T> A, int32_t s0, double* y) {
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(NT) void k_ap_fwd(ApplyArgs<T> A, int32_t s0, doubl
 
 // Backward block solve of one step: z_n = L_nn^{-T} (u - sum_c L(c,n)^T z_c).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_ap_bwd(ApplyArgs<T> A, int32_t s0, double* y) {
+__global__ __launch_bounds__(NT) void k_ap_bwd_generic(ApplyArgs<T> A, int32_t s0, double* y) {
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -155,6 +155,191 @@ __global__ __launch_bounds__(NT) void k_ap_bwd(ApplyArgs<T> A, int32_t s0, doubl
       __syncthreads();
     }
     for (int e = threadIdx.x; e < n * kc; e += NT) yi[(r + e / kc) * nrhs + k0 + e % kc] = t[(e / kc) * RC + e % kc];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block solves with the stored inverse L_nn^{-1} (computed at factorization):
+// every step is a few small matrix products staged in LDS, with no sequential
+// dependency inside the step.  Operand tiles are loaded with consecutive
+// threads on consecutive addresses of the slot that holds them.
+// ---------------------------------------------------------------------------
+constexpr int PT = 64;          // panel column tile
+
+struct ApLds {
+  int ldl, ldp;
+  size_t off_l, off_p, off_y, off_t, off_z, total;
+};
+
+template <typename T>
+__host__ __device__ inline ApLds ap_layout(int bmax) {
+  ApLds L;
+  L.ldl = bmax + 1;
+  L.ldp = PT + 1;
+  size_t o = 0;
+  L.off_l = o;
+  o += (size_t)bmax * L.ldl * sizeof(T);
+  o = (o + 15) & ~(size_t)15;
+  L.off_p = o;
+  o += (size_t)bmax * L.ldp * sizeof(T);
+  o = (o + 15) & ~(size_t)15;
+  L.off_y = o;
+  o += (size_t)bmax * (RC + 1) * sizeof(double);
+  L.off_t = o;
+  o += (size_t)bmax * (RC + 1) * sizeof(double);
+  L.off_z = o;
+  o += (size_t)PT * (RC + 1) * sizeof(double);
+  L.total = o;
+  return L;
+}
+
+// Stage rows n (r..b-1) and columns [g0, g0+tc) of a panel view into Ps[t][g].
+template <typename T>
+__device__ inline void stage_panel(T* Ps, int ldp, const T* P, int trans, int b, int bx, int r, int n, int g0,
+                                   int tc) {
+  if (!trans) {
+    for (int e = threadIdx.x; e < n * tc; e += NT) {
+      const int t = e / tc, g = e % tc;
+      Ps[t * ldp + g] = P[(int64_t)(r + t) * bx + g0 + g];
+    }
+  } else {   // slot rows are the panel columns: read along them
+    for (int e = threadIdx.x; e < n * tc; e += NT) {
+      const int g = e / n, t = e % n;
+      Ps[t * ldp + g] = P[(int64_t)(g0 + g) * b + r + t];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_ap_fwd(ApplyArgs<T> A, int32_t s0, double* y, int bmax) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const int nrhs = A.nrhs;
+  const ApLds Lay = ap_layout<T>(bmax);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Ls = reinterpret_cast<T*>(smem_raw + Lay.off_l);
+  T* Ps = reinterpret_cast<T*>(smem_raw + Lay.off_p);
+  double* yn = reinterpret_cast<double*>(smem_raw + Lay.off_y);
+  double* tn = reinterpret_cast<double*>(smem_raw + Lay.off_t);
+  const int ldl = Lay.ldl, ldp = Lay.ldp, ldv = RC + 1;
+  const T* Lig = A.Li + A.u_off[i];
+  const T* D = A.arena + A.slot_off[i];
+  double* yi = y + A.dof_off[i] * nrhs;
+  for (int e = threadIdx.x; e < n * n; e += NT) Ls[(e / n) * ldl + e % n] = Lig[e];
+  for (int k0 = 0; k0 < nrhs; k0 += RC) {
+    const int kc = min(RC, nrhs - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * kc; e += NT) yn[(e / kc) * ldv + e % kc] = yi[(r + e / kc) * nrhs + k0 + e % kc];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * kc; e += NT) {
+      const int row = e / kc, k = e % kc;
+      double s = 0;
+      for (int c = 0; c <= row; ++c) s += (double)Ls[row * ldl + c] * yn[c * ldv + k];
+      tn[row * ldv + k] = s;
+      yi[(r + row) * nrhs + k0 + k] = s;
+    }
+    // panels: v = -1 is the basis of i (columns 0..r-1 of rows n of the diagonal block)
+    for (int v = -1; v < st.nclose; ++v) {
+      const T* P;
+      int trans, bx, lc;
+      double* yx;
+      if (v < 0) {
+        P = D;
+        trans = 0;
+        bx = b;
+        lc = r;
+        yx = yi;
+      } else {
+        const View vw = A.views[st.view0 + v];
+        bx = A.bsz[vw.x];
+        lc = vw.proc ? A.rank[vw.x] : bx;
+        P = A.arena + A.slot_off[vw.slot];
+        trans = vw.trans;
+        yx = y + A.dof_off[vw.x] * nrhs;
+      }
+      for (int g0 = 0; g0 < lc; g0 += PT) {
+        const int tc = min(PT, lc - g0);
+        __syncthreads();
+        stage_panel(Ps, ldp, P, trans, b, bx, r, n, g0, tc);
+        __syncthreads();
+        for (int e = threadIdx.x; e < tc * kc; e += NT) {
+          const int g = e / kc, k = e % kc;
+          double s = 0;
+          for (int t = 0; t < n; ++t) s += (double)Ps[t * ldp + g] * tn[t * ldv + k];
+          yx[(g0 + g) * nrhs + k0 + k] -= s;
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_ap_bwd(ApplyArgs<T> A, int32_t s0, double* y, int bmax) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const int nrhs = A.nrhs;
+  const ApLds Lay = ap_layout<T>(bmax);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Ls = reinterpret_cast<T*>(smem_raw + Lay.off_l);
+  T* Ps = reinterpret_cast<T*>(smem_raw + Lay.off_p);
+  double* tn = reinterpret_cast<double*>(smem_raw + Lay.off_t);
+  double* zt = reinterpret_cast<double*>(smem_raw + Lay.off_z);
+  const int ldl = Lay.ldl, ldp = Lay.ldp, ldv = RC + 1;
+  const T* Lig = A.Li + A.u_off[i];
+  const T* D = A.arena + A.slot_off[i];
+  double* yi = y + A.dof_off[i] * nrhs;
+  for (int e = threadIdx.x; e < n * n; e += NT) Ls[(e / n) * ldl + e % n] = Lig[e];
+  for (int k0 = 0; k0 < nrhs; k0 += RC) {
+    const int kc = min(RC, nrhs - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * kc; e += NT) tn[(e / kc) * ldv + e % kc] = yi[(r + e / kc) * nrhs + k0 + e % kc];
+    for (int v = -1; v < st.nclose; ++v) {
+      const T* P;
+      int trans, bx, lc;
+      const double* zx;
+      if (v < 0) {
+        P = D;
+        trans = 0;
+        bx = b;
+        lc = r;
+        zx = yi;
+      } else {
+        const View vw = A.views[st.view0 + v];
+        bx = A.bsz[vw.x];
+        lc = vw.proc ? A.rank[vw.x] : bx;
+        P = A.arena + A.slot_off[vw.slot];
+        trans = vw.trans;
+        zx = y + A.dof_off[vw.x] * nrhs;
+      }
+      for (int g0 = 0; g0 < lc; g0 += PT) {
+        const int tc = min(PT, lc - g0);
+        __syncthreads();
+        stage_panel(Ps, ldp, P, trans, b, bx, r, n, g0, tc);
+        for (int e = threadIdx.x; e < tc * kc; e += NT) zt[(e / kc) * ldv + e % kc] = zx[(g0 + e / kc) * nrhs + k0 + e % kc];
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * kc; e += NT) {
+          const int t = e / kc, k = e % kc;
+          double s = 0;
+          for (int g = 0; g < tc; ++g) s += (double)Ps[t * ldp + g] * zt[g * ldv + k];
+          tn[t * ldv + k] -= s;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * kc; e += NT) {
+      const int c = e / kc, k = e % kc;
+      double s = 0;
+      for (int row = c; row < n; ++row) s += (double)Ls[row * ldl + c] * tn[row * ldv + k];
+      yi[(r + c) * nrhs + k0 + k] = s;
+    }
   }
 }
 
@@ -394,12 +579,22 @@ void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir,
 template <typename T>
 void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
   if (s1 <= s0) return;
-  hipLaunchKernelGGL(k_ap_fwd<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A, s0, y);
+  const size_t lds = ap_layout<T>(bmax).total;
+  if (lds <= max_lds_bytes())
+    hipLaunchKernelGGL(k_ap_fwd<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
+  else
+    hipLaunchKernelGGL(k_ap_fwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
+                       s0, y);
 }
 template <typename T>
 void launch_ap_bwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
   if (s1 <= s0) return;
-  hipLaunchKernelGGL(k_ap_bwd<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A, s0, y);
+  const size_t lds = ap_layout<T>(bmax).total;
+  if (lds <= max_lds_bytes())
+    hipLaunchKernelGGL(k_ap_bwd<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
+  else
+    hipLaunchKernelGGL(k_ap_bwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
+                       s0, y);
 }
 template <typename T>
 void launch_mul_w(const ApplyArgs<T>& A, int32_t nsteps, const double* z, double* w, int bmax, hipStream_t stream) {

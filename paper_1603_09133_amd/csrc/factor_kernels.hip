@@ -65,6 +65,7 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
   const int i = st.blk;
   const int b = A.bsz[i];
   const int tid = threadIdx.x;
+  if (A.small_by_wave && b <= A.small_by_wave) return;   // done by the wavefront kernel
   T* Ug = A.U + A.u_off[i];
   if (st.nfar == 0 || b == 0) {
     for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
@@ -140,7 +141,26 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
   // one-sided Jacobi on the columns of R; V accumulates the rotations
   T* V = C;
   for (int e = tid; e < b * ld; e += NT) V[e] = (e / ld == e % ld) ? T(1) : T(0);
+  // ||R||_F^2: columns below eps * ||R||_F are rounding noise of the QR; a
+  // pair of two such columns is left alone (their mixing only touches
+  // directions far below any resolvable singular value)
+  {
+    T s = 0;
+    for (int e = tid; e < b * b; e += NT) {
+      const T x = R[(e / b) * ld + e % b];
+      s += x * x;
+    }
+    part[tid] = s;     // the part/cf area holds at least NT entries
+  }
   __syncthreads();
+  __shared__ T sh_norm2;
+  if (tid == 0) {
+    T s = 0;
+    for (int k = 0; k < NT; ++k) s += part[k];
+    sh_norm2 = s;
+  }
+  __syncthreads();
+  const T noise = Eps<T>::v() * sqrt(sh_norm2);
   const int nb = b + (b & 1);
   const int npair = nb / 2;
   // rotation threshold: the computed a_p^T a_q of exactly orthogonal columns
@@ -172,7 +192,8 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
           c += __shfl_xor(c, o, 8);
           d += __shfl_xor(d, o, 8);
         }
-        if (d != T(0) && fabs(d) > tol * sqrt(a * c)) {
+        const T na = sqrt(a), nc = sqrt(c);
+        if (d != T(0) && fabs(d) > tol * na * nc && (na > noise || nc > noise)) {
           const T zeta = (c - a) / (T(2) * d);
           T t;
           if (fabs(zeta) > T(1e15))
@@ -226,6 +247,395 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
       if ((int)part[b + j] >= r) e += (double)sig[j] * (double)sig[j];
     A.rank[i] = r;
     A.edrop[i] = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Compression, one wavefront per step (b <= 64 * NCOL).  Same mathematics as
+// k_compress, organised for one 64-lane wavefront without workgroup
+// barriers:
+//   1. TSQR of F_i^T: lane j owns column j of a chunk of rows (registers);
+//      column k is broadcast with readlane; R stays in LDS;
+//   2. rows of R below eps * ||R||_F are rounding noise of the QR and are set
+//      aside (their directions carry no resolvable singular value);
+//   3. one-sided Jacobi on the remaining rows of R (the columns of R^T): the
+//      rows converge to sigma_k v_k^T, v_k the right singular vectors of R =
+//      the left singular vectors of F_i; no rotation has to be accumulated;
+//   4. the r_i leading directions are completed to an orthonormal U_i by
+//      Householder reflections (U_i is unique only up to rotations inside the
+//      kept and the dropped subspaces, which leave the factorization intact).
+// ---------------------------------------------------------------------------
+constexpr int WV = 64;
+
+__device__ inline float rdl(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double rdl(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WV);
+  return v;
+}
+
+template <typename T>
+struct WaveCh;
+template <>
+struct WaveCh<float> {
+  static constexpr int CH = 64;
+};
+template <>
+struct WaveCh<double> {
+  static constexpr int CH = 32;
+};
+
+// Sum of products with four independent accumulators.
+template <typename T, int N>
+__device__ inline T dot_u(const T (&x)[N], const T (&y)[N]) {
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+  for (int t = 0; t < N; t += 4) {
+    s0 += x[t] * y[t];
+    if (t + 1 < N) s1 += x[t + 1] * y[t + 1];
+    if (t + 2 < N) s2 += x[t + 2] * y[t + 2];
+    if (t + 3 < N) s3 += x[t + 3] * y[t + 3];
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+template <int WB>
+struct WaveLd {
+  static constexpr int LD = WB + 4;   // LDS row stride (16-byte aligned rows)
+};
+
+template <typename T, int WB>
+size_t work_compress_wave() {
+  return (size_t)2 * WB * WaveLd<WB>::LD + 4 * (size_t)WB + 16;
+}
+
+// Partial dot products over the entries t = sub, sub + LP, ... of two LDS rows.
+template <typename T, int LP>
+__device__ inline void pair_dots(const T* x, const T* y, int b, int sub, T& a, T& c, T& d) {
+  T a0 = 0, c0 = 0, d0 = 0, a1 = 0, c1 = 0, d1 = 0;
+  int t = sub;
+  for (; t + LP < b; t += 2 * LP) {
+    const T x0 = x[t], y0 = y[t], x1 = x[t + LP], y1 = y[t + LP];
+    a0 += x0 * x0;
+    c0 += y0 * y0;
+    d0 += x0 * y0;
+    a1 += x1 * x1;
+    c1 += y1 * y1;
+    d1 += x1 * y1;
+  }
+  if (t < b) {
+    const T x0 = x[t], y0 = y[t];
+    a0 += x0 * x0;
+    c0 += y0 * y0;
+    d0 += x0 * y0;
+  }
+  a = a0 + a1;
+  c = c0 + c1;
+  d = d0 + d1;
+}
+
+template <typename T, int WB>
+__global__ __launch_bounds__(WV) void k_compress_wave(LevelArgs<T> A, int32_t s0) {
+  constexpr int NCOL = WB / WV;                    // columns of F_i^T per lane in the TSQR
+  constexpr int CH = WaveCh<T>::CH / NCOL;         // rows of F_i^T per TSQR chunk
+  constexpr int LD = WaveLd<WB>::LD;
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > WB || (WB > WV && b <= WB / 2)) return;   // another size class handles it
+  const int lane = threadIdx.x;
+  T* Ug = A.U + A.u_off[i];
+  if (st.nfar == 0 || b == 0) {
+    for (int e = lane; e < b * b; e += WV) Ug[e] = (e / b == e % b) ? T(1) : T(0);
+    if (lane == 0) {
+      A.rank[i] = 0;
+      A.edrop[i] = 0.0;
+    }
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* R = reinterpret_cast<T*>(smem_raw);  // WB x LD: R, the active rows X, then Q
+  T* Bv = R + WB * LD;                    // WB x LD: broadcast row, then kept directions / reflectors
+  T* sg = Bv + WB * LD;                   // singular values
+  T* tau = sg + WB;
+  int* posv = reinterpret_cast<int*>(tau + WB);
+  for (int e = lane; e < WB * LD; e += WV) R[e] = T(0);
+  __syncthreads();
+  const int64_t t_start = clock64();
+  int wtot = 0;
+
+  // ---- 1. TSQR: lane j keeps columns j, j+64, ... of the chunk in registers --
+  T* bc = Bv;
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    wtot += w;
+    for (int c0 = 0; c0 < w; c0 += CH) {
+      const int m = min(CH, w - c0);
+      T c[NCOL][CH];
+#pragma unroll
+      for (int ci = 0; ci < NCOL; ++ci) {
+        const int j = lane + WV * ci;
+#pragma unroll
+        for (int t = 0; t < CH; ++t) c[ci][t] = (j < b && t < m) ? *view_ptr(base, v.trans, b, bx, j, c0 + t) : T(0);
+      }
+      for (int k = 0; k < b; ++k) {
+        const int kl = k % WV, kc = k / WV;
+        if (lane == kl) {
+#pragma unroll
+          for (int t = 0; t < CH; ++t) bc[t] = (kc == 0) ? c[0][t] : c[NCOL - 1][t];
+        }
+        __syncthreads();
+        T ck[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) ck[t] = bc[t];
+        T sdot[NCOL];
+#pragma unroll
+        for (int ci = 0; ci < NCOL; ++ci) sdot[ci] = dot_u(ck, c[ci]);
+        const T xn2 = rdl(kc == 0 ? sdot[0] : sdot[NCOL - 1], kl);
+        if (xn2 > Eps<T>::tiny()) {
+          const T rkk = R[k * LD + k];
+          const T nrm = sqrt(rkk * rkk + xn2);
+          const T alpha = rkk >= T(0) ? -nrm : nrm;
+          const T v0 = rkk - alpha;
+          const T tk = T(2) / (v0 * v0 + xn2);
+#pragma unroll
+          for (int ci = 0; ci < NCOL; ++ci) {
+            const int j = lane + WV * ci;
+            T coef = T(0);
+            if (j > k && j < b) {
+              coef = tk * (v0 * R[k * LD + j] + sdot[ci]);
+              R[k * LD + j] -= coef * v0;
+            }
+#pragma unroll
+            for (int t = 0; t < CH; ++t) c[ci][t] -= coef * ck[t];
+          }
+          __syncthreads();
+          if (lane == kl) R[k * LD + k] = alpha;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const int64_t t_qr = clock64();
+
+  // ---- 2. active rows ---------------------------------------------------------
+  T rn[NCOL];
+  T fro = 0;
+#pragma unroll
+  for (int ci = 0; ci < NCOL; ++ci) {
+    const int k = lane + WV * ci;
+    T s2 = 0;
+    for (int j = k; j < b; ++j) s2 += R[k * LD + j] * R[k * LD + j];   // rows >= b are zero
+    rn[ci] = k < b ? s2 : T(0);
+    fro += rn[ci];
+  }
+  fro = wave_sum(fro);
+  const T noise = Eps<T>::v() * sqrt(fro);
+  uint64_t mask[NCOL];
+  int before[NCOL];
+  int ma = 0;
+  double inactive = 0.0;
+#pragma unroll
+  for (int ci = 0; ci < NCOL; ++ci) {
+    const int k = lane + WV * ci;
+    const bool act = k < b && sqrt(rn[ci]) > noise;
+    mask[ci] = __ballot(act);
+    before[ci] = ma + __popcll(mask[ci] & ((1ull << lane) - 1ull));
+    ma += __popcll(mask[ci]);
+    if (k < b && !act) inactive += (double)rn[ci];
+  }
+  inactive = wave_sum(inactive);
+  T* X = R;
+  // compact in place, 16 columns at a time: every lane loads before any stores
+#pragma unroll
+  for (int ci = 0; ci < NCOL; ++ci) {
+    const int k = lane + WV * ci;
+    const bool act = (mask[ci] >> lane) & 1ull;
+    for (int j0 = 0; j0 < b; j0 += 16) {
+      T tmp[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) tmp[t] = (j0 + t < LD) ? R[k * LD + j0 + t] : T(0);
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          if (j0 + t < LD) X[before[ci] * LD + j0 + t] = tmp[t];
+      }
+      __syncthreads();
+    }
+  }
+  const int64_t t_cmp = clock64();
+
+  // ---- 3. one-sided Jacobi: LP lanes rotate the pair (p, q) of round rho ------
+  const int mm = ma + (ma & 1);
+  const T tol = T(max(b, 16)) * Eps<T>::v();
+  const int LPs = (mm / 2 <= 16) ? 4 : ((mm / 2 <= 32) ? 2 : 1);
+  const int pp = lane / LPs, sub = lane % LPs;
+  int nsweep = 0;
+  for (int sweep = 0; sweep < 40 && ma > 1; ++sweep) {
+    ++nsweep;
+    int rotated = 0;
+    for (int rho = 0; rho < mm - 1; ++rho) {
+      for (int pbase = 0; pbase < mm / 2; pbase += WV / LPs) {
+        const int mypair = pbase + pp;
+        int p = -1, q = -1;
+        if (mypair < mm / 2) {
+          if (mypair == 0) {
+            p = mm - 1;
+            q = rho;
+          } else {
+            p = (rho + mypair) % (mm - 1);
+            q = (rho - mypair + (mm - 1)) % (mm - 1);
+          }
+          if (p > q) {
+            const int tmp = p;
+            p = q;
+            q = tmp;
+          }
+          if (q >= ma) p = -1;
+        }
+        T a = 0, cc = 0, d = 0;
+        if (p >= 0) {
+          if (LPs == 4)
+            pair_dots<T, 4>(X + p * LD, X + q * LD, b, sub, a, cc, d);
+          else if (LPs == 2)
+            pair_dots<T, 2>(X + p * LD, X + q * LD, b, sub, a, cc, d);
+          else
+            pair_dots<T, 1>(X + p * LD, X + q * LD, b, sub, a, cc, d);
+        }
+        for (int o = 1; o < LPs; o <<= 1) {
+          a += __shfl_xor(a, o, WV);
+          cc += __shfl_xor(cc, o, WV);
+          d += __shfl_xor(d, o, WV);
+        }
+        if (p >= 0) {
+          const T na = sqrt(a), nc = sqrt(cc);
+          if (d != T(0) && fabs(d) > tol * na * nc && (na > noise || nc > noise)) {
+            const T zeta = (cc - a) / (T(2) * d);
+            T tt;
+            if (fabs(zeta) > T(1e15))
+              tt = T(0.5) / zeta;
+            else
+              tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+            const T cs = T(1) / sqrt(T(1) + tt * tt), sn = cs * tt;
+            T* xp = X + p * LD;
+            T* xq = X + q * LD;
+            for (int t = sub; t < b; t += LPs) {
+              const T x = xp[t], y = xq[t];
+              xp[t] = cs * x - sn * y;
+              xq[t] = sn * x + cs * y;
+            }
+            rotated = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  const int64_t t_jac = clock64();
+
+  // ---- singular values, order, rank -----------------------------------------
+  for (int p = lane; p < ma; p += WV) {
+    T s2 = 0;
+    for (int t = 0; t < b; ++t) s2 += X[p * LD + t] * X[p * LD + t];
+    sg[p] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int p = lane; p < ma; p += WV) {
+    const T sp = sg[p];
+    int pos = 0;
+    for (int q = 0; q < ma; ++q) pos += (sg[q] > sp || (sg[q] == sp && q < p)) ? 1 : 0;
+    posv[p] = pos;
+  }
+  __syncthreads();
+  const double theta = *A.theta;
+  int r;
+  double edrop = 0.0;
+  {
+    int cnt = 0;
+    for (int p = lane; p < ma; p += WV) cnt += (double)sg[p] > theta ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, WV);
+    r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
+    for (int p = lane; p < ma; p += WV)
+      if (posv[p] >= r) edrop += (double)sg[p] * (double)sg[p];
+    edrop = wave_sum(edrop) + inactive;
+  }
+
+  // ---- 4. orthonormal completion of the kb leading directions ----------------
+  const int kb = min(r, ma);
+  for (int p = 0; p < ma; ++p) {
+    const int c2 = posv[p];
+    if (c2 < kb) {
+      const T inv = sg[p] > T(0) ? T(1) / sg[p] : T(0);
+      for (int t = lane; t < LD; t += WV) Bv[c2 * LD + t] = t < b ? X[p * LD + t] * inv : T(0);
+    }
+  }
+  __syncthreads();
+  for (int cv = 0; cv < kb; ++cv) {
+    T loc = 0;
+    for (int t = cv + lane; t < b; t += WV) loc += Bv[cv * LD + t] * Bv[cv * LD + t];
+    const T nrm2 = wave_sum(loc);
+    const T x0 = Bv[cv * LD + cv];
+    const T nrm = sqrt(nrm2);
+    const T alpha = x0 >= T(0) ? -nrm : nrm;
+    const T v0 = x0 - alpha;
+    const T vv = v0 * v0 + (nrm2 - x0 * x0);
+    const T tc = vv > T(0) ? T(2) / vv : T(0);
+    __syncthreads();
+    if (lane == 0) {
+      Bv[cv * LD + cv] = v0;
+      tau[cv] = tc;
+    }
+    for (int t = lane; t < cv; t += WV) Bv[cv * LD + t] = T(0);
+    __syncthreads();
+    for (int c2 = cv + 1 + lane; c2 < kb; c2 += WV) {
+      T dd = 0;
+      for (int t = cv; t < b; ++t) dd += Bv[cv * LD + t] * Bv[c2 * LD + t];
+      dd *= tc;
+      for (int t = cv; t < b; ++t) Bv[c2 * LD + t] -= dd * Bv[cv * LD + t];
+    }
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{kb-1}: lane col updates column col (in X's space)
+  T* Q = X;
+  for (int e = lane; e < WB * LD; e += WV) Q[e] = (e / LD == e % LD) ? T(1) : T(0);
+  __syncthreads();
+  for (int cv = kb - 1; cv >= 0; --cv) {
+    const T tc = tau[cv];
+    for (int col = lane; col < b; col += WV) {
+      T dd = 0;
+      for (int t = cv; t < b; ++t) dd += Bv[cv * LD + t] * Q[t * LD + col];
+      dd *= tc;
+      for (int t = cv; t < b; ++t) Q[t * LD + col] -= dd * Bv[cv * LD + t];
+    }
+    __syncthreads();
+  }
+  for (int e = lane; e < b * b; e += WV) Ug[e] = Q[(e / b) * LD + e % b];
+  if (lane == 0) {
+    A.rank[i] = r;
+    A.edrop[i] = edrop;
+    if (A.dbg) {
+      int64_t* dd = A.dbg + 8 * (int64_t)i;
+      dd[0] = ma;
+      dd[1] = nsweep;
+      dd[2] = wtot;
+      dd[3] = b;
+      dd[4] = t_qr - t_start;
+      dd[5] = t_cmp - t_qr;
+      dd[6] = t_jac - t_cmp;
+      dd[7] = clock64() - t_jac;
+    }
   }
 }
 
@@ -377,6 +787,13 @@ __global__ __launch_bounds__(NT) void k_potrf(LevelArgs<T> A, int32_t s0, T* gsc
       val = X[j * ld + c];
     D[(int64_t)(r + j) * b + c] = val;
   }
+  // L^{-1} for the preconditioner apply (X is free now)
+  __syncthreads();
+  for (int e = tid; e < n * n; e += NT) X[(e / n) * ld + e % n] = (e / n == e % n) ? T(1) : T(0);
+  __syncthreads();
+  trsm_lower(S, ld, X, n, n, ld);
+  T* Lig = A.Li + A.u_off[i];
+  for (int e = tid; e < n * n; e += NT) Lig[e] = X[(e / n) * ld + e % n];
   for (int e = tid; e < r * n; e += NT) D[(int64_t)(e / n) * b + r + e % n] = T(0);
   if (tid == 0) {
     double mp = 1e300;
@@ -692,7 +1109,8 @@ static void launch(void (*kern)(LevelArgs<T>, int32_t, T*, int64_t), const Level
 
 template <typename T>
 size_t work_compress(int bmax) {
-  return (size_t)bmax * (bmax + 1) + (size_t)(bmax > QR_CH ? bmax : QR_CH) * (bmax + 1) + 5 * (size_t)bmax + 8;
+  return (size_t)bmax * (bmax + 1) + (size_t)(bmax > QR_CH ? bmax : QR_CH) * (bmax + 1) +
+         (5 * (size_t)bmax > (size_t)NT ? 5 * (size_t)bmax : (size_t)NT) + 8;
 }
 template <typename T>
 size_t work_rotate(int bmax) {
@@ -727,9 +1145,27 @@ bool factor_needs_global(int bmax) {
 }
 
 template <typename T>
-void launch_wave(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
+void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
   T* gs = gscratch;
-  launch<T>(k_compress<T>, A, w.s0, w.s1 - w.s0, work_compress<T>(bmax), gs, stream);
+  if (w.s1 > w.s0) {
+    const int ns = w.s1 - w.s0;
+    const size_t w64 = work_compress_wave<T, 64>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
+    hipLaunchKernelGGL((k_compress_wave<T, 64>), dim3(ns), dim3(WV), w64, stream, A, w.s0);
+    if (bmax > 64) {
+      if (bmax <= 128 && w128 <= max_lds_bytes()) {
+        hipLaunchKernelGGL((k_compress_wave<T, 128>), dim3(ns), dim3(WV), w128, stream, A, w.s0);
+      } else {
+        LevelArgs<T> C = A;
+        C.small_by_wave = 64;
+        launch<T>(k_compress<T>, C, w.s0, ns, work_compress<T>(bmax), gs, stream);
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
+  T* gs = gscratch;
   LevelArgs<T> B = A;
   B.items = A.rot;
   launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
@@ -793,7 +1229,8 @@ void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double*
 #define CAE_INST(T)                                                                                         \
   template size_t factor_scratch_elems<T>(int);                                                            \
   template bool factor_needs_global<T>(int);                                                               \
-  template void launch_wave<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);               \
+  template void launch_wave_compress<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);      \
+  template void launch_wave_rest<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);          \
   template void launch_scatter_a0<T>(T*, const double*, const int64_t*, int64_t, hipStream_t);             \
   template void launch_gather_next<T>(const Trans*, int32_t, const T*, const int64_t*, const int32_t*,     \
                                       const int32_t*, const int32_t*, const int32_t*, T*, const int64_t*,  \

@@ -20,6 +20,7 @@ struct LevelArgs {
   const int32_t* bsz;       // block sizes b_i
   T* U;                     // U_i, b_i x b_i row-major
   const int64_t* u_off;
+  T* Li;                    // L_nn^{-1} of every step, n_i x n_i row-major at u_off
   int32_t* rank;            // r_i (written by the compression of step i)
   double* edrop;            // ||E_i||_F^2
   double* minpiv;           // smallest diagonal entry of the Cholesky factor of S_ii
@@ -33,6 +34,8 @@ struct LevelArgs {
   const double* theta;      // eps * max diag(A0)
   int32_t rank_mode;        // 0 CE(eps), 1 CE(r)
   int32_t fixed_rank;
+  int64_t* dbg;             // optional per-block compression counters (8 per block) or null
+  int32_t small_by_wave;    // blocks of at most this size are compressed by the wavefront kernel
 };
 
 struct WaveRange {
@@ -46,8 +49,11 @@ template <typename T>
 size_t factor_scratch_elems(int bmax);
 template <typename T>
 bool factor_needs_global(int bmax);
+// the compression of a wave, then rotation, elimination and Schur update
 template <typename T>
-void launch_wave(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);
+void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);
+template <typename T>
+void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);
 template <typename T>
 void launch_scatter_a0(T* arena, const double* vals, const int64_t* dst, int64_t nnz, hipStream_t stream);
 void launch_theta(const double* vals, const int64_t* diag_pos, int64_t n, double eps, double* out,
@@ -75,6 +81,7 @@ struct ApplyArgs {
   const int32_t* rank;
   const T* U;
   const int64_t* u_off;
+  const T* Li;              // L_nn^{-1} of every step (n_i x n_i at u_off)
   const int64_t* dof_off;   // first unknown of every block in the level vector
   const Step* steps;
   const View* views;

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -121,7 +122,7 @@ struct NumLevel {
   std::vector<int64_t> slot_off, u_off, dof_off;
   std::vector<int32_t> off_in_parent;
   std::vector<cae::WaveRange> waves;
-  DevBuf arena, U, bsz, d_slot_off, d_u_off, d_dof_off, d_off_in_parent, rank, edrop, minpiv;
+  DevBuf arena, U, Li, bsz, d_slot_off, d_u_off, d_dof_off, d_off_in_parent, rank, edrop, minpiv;
 };
 
 }  // namespace
@@ -138,6 +139,8 @@ struct cae_factor_s {
   DevBuf Ainv, Acopy, vals, theta, err, gscratch, gj_p, gj_w, gj_r;
   double tau = 0, dropped = 0, min_pivot = 0, factor_ms = 0;
   int64_t factor_bytes = 0;
+  int32_t compress_launches = 0, compressions = 0;
+  double compress_ms = 0, compress_flops = 0;
   // apply / multiply / PCG work vectors
   int32_t vec_nrhs = 0;
   std::vector<DevBuf> ybuf, wbuf, obuf;
@@ -213,6 +216,7 @@ cae::LevelArgs<T> level_args(cae_factor_s* h, int l) {
   A.bsz = N.bsz.as<int32_t>();
   A.U = N.U.as<T>();
   A.u_off = N.d_u_off.as<int64_t>();
+  A.Li = N.Li.as<T>();
   A.rank = N.rank.as<int32_t>();
   A.edrop = N.edrop.as<double>();
   A.minpiv = N.minpiv.as<double>();
@@ -226,6 +230,8 @@ cae::LevelArgs<T> level_args(cae_factor_s* h, int l) {
   A.theta = h->theta.as<double>();
   A.rank_mode = h->opt.rank_mode;
   A.fixed_rank = h->opt.fixed_rank;
+  A.dbg = nullptr;
+  A.small_by_wave = 0;
   return A;
 }
 
@@ -240,6 +246,7 @@ cae::ApplyArgs<T> apply_args(cae_factor_s* h, int l, int nrhs) {
   A.rank = N.rank.as<int32_t>();
   A.U = N.U.as<T>();
   A.u_off = N.d_u_off.as<int64_t>();
+  A.Li = N.Li.as<T>();
   A.dof_off = N.d_dof_off.as<int64_t>();
   A.steps = D.steps.as<cae::Step>();
   A.views = D.views.as<cae::View>();
@@ -281,6 +288,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
                       (h->opt.max_levels > 0 && l >= h->opt.max_levels) || l + 1 >= (int)a.levels.size();
     if (stop) break;
     N.U.alloc((size_t)N.u_off[L.M] * sizeof(T));
+    N.Li.alloc((size_t)N.u_off[L.M] * sizeof(T));
     N.rank.alloc((size_t)L.M * sizeof(int32_t));
     N.edrop.alloc((size_t)L.M * sizeof(double));
     N.minpiv.alloc((size_t)L.M * sizeof(double));
@@ -296,8 +304,52 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       gs = h->gscratch.as<T>();
     }
     cae::LevelArgs<T> A = level_args<T>(h, l);
-    for (auto& w : N.waves) cae::launch_wave<T>(A, w, N.bmax, gs, s);
+    // optional compression counters (environment CAE_DEBUG_COMPRESS=1)
+    static const bool dbg_on = getenv("CAE_DEBUG_COMPRESS") != nullptr;
+    DevBuf dbgbuf;
+    if (dbg_on) {
+      dbgbuf.alloc((size_t)8 * L.M * sizeof(int64_t));
+      HIPCHK(hipMemsetAsync(dbgbuf.p, 0, (size_t)8 * L.M * sizeof(int64_t), s));
+      A.dbg = dbgbuf.as<int64_t>();
+    }
+    std::vector<hipEvent_t> evs;
+    for (auto& w : N.waves) {
+      if (h->opt.timing && w.s1 > w.s0) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+        cae::launch_wave_compress<T>(A, w, N.bmax, gs, s);
+        HIPCHK(hipEventRecord(e1, s));
+        evs.push_back(e0);
+        evs.push_back(e1);
+      } else {
+        cae::launch_wave_compress<T>(A, w, N.bmax, gs, s);
+      }
+      cae::launch_wave_rest<T>(A, w, N.bmax, gs, s);
+    }
     HIPCHK(hipGetLastError());
+    if (dbg_on) {
+      std::vector<int64_t> hd((size_t)8 * L.M);
+      HIPCHK(hipMemcpyAsync(hd.data(), dbgbuf.p, hd.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double sum[8] = {0}, mx[8] = {0};
+      int cnt = 0;
+      for (int32_t b2 = 0; b2 < L.M; ++b2) {
+        if (hd[8 * b2 + 3] == 0) continue;
+        ++cnt;
+        for (int k = 0; k < 8; ++k) {
+          sum[k] += (double)hd[8 * b2 + k];
+          mx[k] = std::max(mx[k], (double)hd[8 * b2 + k]);
+        }
+      }
+      if (cnt)
+        fprintf(stderr,
+                "[cae] level %d: %d compressions | ma %.1f/%.0f sweeps %.1f/%.0f w %.0f/%.0f b %.0f | cycles "
+                "qr %.0f/%.0f compact %.0f/%.0f jacobi %.0f/%.0f basis %.0f/%.0f\n",
+                l + 1, cnt, sum[0] / cnt, mx[0], sum[1] / cnt, mx[1], sum[2] / cnt, mx[2], sum[3] / cnt,
+                sum[4] / cnt, mx[4], sum[5] / cnt, mx[5], sum[6] / cnt, mx[6], sum[7] / cnt, mx[7]);
+    }
     // the ranks decide the sizes of the next level
     N.ranks.resize(L.M);
     std::vector<double> ed(L.M), mp(L.M);
@@ -315,6 +367,29 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     for (int32_t i = 0; i < L.M; ++i) {
       dropped += ed[i];
       minpiv = std::min(minpiv, mp[i]);
+    }
+    if (h->opt.timing) {
+      for (size_t k = 0; k < evs.size(); k += 2) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, evs[k], evs[k + 1]));
+        h->compress_ms += ms;
+        h->compress_launches += 1;
+        (void)hipEventDestroy(evs[k]);
+        (void)hipEventDestroy(evs[k + 1]);
+      }
+      // algorithmic flops of the compressions of this level
+      for (const cae::Step& stp : L.steps) {
+        if (stp.nfar == 0) continue;
+        const double b = N.sizes[stp.blk];
+        double w = 0;
+        for (int v = stp.nclose; v < stp.nclose + stp.nfar; ++v) {
+          const cae::View& vw = L.views[stp.view0 + v];
+          w += vw.proc ? N.ranks[vw.x] : N.sizes[vw.x];
+        }
+        const double qr = w >= b ? 2 * w * b * b - 2 * b * b * b / 3 : 2 * b * w * w - 2 * w * w * w / 3;
+        h->compress_flops += qr + 12 * b * b * b;
+        h->compressions += 1;
+      }
     }
     h->lev.emplace_back();
     NumLevel& Nn = h->lev[l + 1];
@@ -746,6 +821,10 @@ int cae_get_stats(cae_handle_t h, cae_stats_t* st) {
   st->min_pivot = h->min_pivot;
   st->factor_bytes = h->factor_bytes;
   st->factor_ms = h->factor_ms;
+  st->compress_launches = h->compress_launches;
+  st->compress_ms = h->compress_ms;
+  st->compress_flops = h->compress_flops;
+  st->compressions = h->compressions;
   return CAE_OK;
 }
 
