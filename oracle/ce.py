@@ -308,7 +308,7 @@ def ce_factor(indptr, indices, data, perm, block_ptr, coords, opts: CEOptions, J
         if M <= 1 or dim <= opts.coarse_max_dim or (opts.max_levels and level_no > opts.max_levels):
             break
         adj = sym.adjacency(M, close_pairs)
-        order = sym.element_order(adj, opts.order)
+        order = sym.element_order(adj, opts.order, coords)
         lf = _factor_level(level_no, sizes, W, close_pairs, order, theta, opts)
         parent, coords = sym.coarsen(coords, M, J)
         Mn = int(parent.max()) + 1

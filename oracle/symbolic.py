@@ -144,30 +144,58 @@ def distance2_sets(adj):
     return d2
 
 
-def colour_order(adj):
-    """Multicolour order: greedy colouring in block index order such that two
-    blocks within graph distance 2 never share a colour; blocks are then
-    ordered by (colour, index).  Returns (order, colour)."""
-    M = len(adj)
+def lattice_colours(adj, coords):
+    """Colouring by a lattice pattern of the block coordinates, when one is
+    valid at distance 2 on this graph: (x + 2y) mod 5 and (x + 2y + 3z) mod 7
+    for nearest-neighbour graphs, the product of (coordinate mod 3) for graphs
+    inside the 3^d-point stencil; candidates are tried in this order."""
+    if coords is None:
+        return None
+    coords = np.asarray(coords)
+    ndim = coords.shape[1]
+    if ndim == 1:
+        cands = [("lin", (1,), 3)]
+    elif ndim == 2:
+        cands = [("lin", (1, 2), 5), ("prod", None, 3)]
+    else:
+        cands = [("lin", (1, 2, 3), 7), ("prod", None, 3)]
     d2 = distance2_sets(adj)
-    colour = [-1] * M
-    for i in range(M):
-        used = {colour[j] for j in d2[i] if j < i}
-        c = 0
-        while c in used:
-            c += 1
-        colour[i] = c
+    for kind, a, q in cands:
+        if kind == "lin":
+            col = [int(sum(a[k] * int(c[k]) for k in range(ndim)) % q) for c in coords]
+        else:
+            col = [int(sum((int(c[k]) % q) * q ** k for k in range(ndim))) for c in coords]
+        if all(col[i] != col[j] for i in range(len(adj)) for j in d2[i]):
+            return col
+    return None
+
+
+def colour_order(adj, coords=None):
+    """Multicolour order: blocks within graph distance 2 never share a colour;
+    blocks are ordered by (colour, index).  The colouring is the lattice one
+    when valid, else greedy in block index order.  Returns (order, colour)."""
+    M = len(adj)
+    colour = lattice_colours(adj, coords)
+    if colour is None:
+        d2 = distance2_sets(adj)
+        colour = [-1] * M
+        for i in range(M):
+            used = {colour[j] for j in d2[i] if j < i}
+            c = 0
+            while c in used:
+                c += 1
+            colour[i] = c
     order = sorted(range(M), key=lambda i: (colour[i], i))
     return order, colour
 
 
-def element_order(adj, kind: str):
+def element_order(adj, kind: str, coords=None):
     """Elimination order of a level: 'paper' is the block order of the level
     (Algorithm 2 loops i = 1..M_j), 'multicolour' is :func:`colour_order`."""
     if kind == "paper":
         return list(range(len(adj)))
     if kind == "multicolour":
-        return colour_order(adj)[0]
+        return colour_order(adj, coords)[0]
     raise ValueError(kind)
 
 

@@ -62,28 +62,80 @@ bool is_close(const LevelSym& L, int32_t a, int32_t c) {
   return std::binary_search(L.cadj.begin() + L.cptr[a], L.cadj.begin() + L.cptr[a + 1], c);
 }
 
-// Greedy colouring in index order; blocks within distance 2 get distinct
-// colours.  Order = (colour, index).
-void colour_order(LevelSym& L) {
-  const int32_t M = L.M;
-  std::vector<int32_t> colour(M, -1), stamp;
-  for (int32_t i = 0; i < M; ++i) {
-    auto mark = [&](int32_t j) {
-      if (j < i) {
-        int32_t c = colour[j];
-        if ((int32_t)stamp.size() <= c) stamp.resize(c + 1, -1);
-        stamp[c] = i;
-      }
-    };
+// Colouring at distance 2 by a lattice pattern of the block coordinates when
+// it is valid on this graph ((x + 2y) mod 5 / (x + 2y + 3z) mod 7, then the
+// product of coordinates mod 3), else greedy in block index order.
+// Order = (colour, index).
+bool valid_colouring(const LevelSym& L, const std::vector<int32_t>& col) {
+  for (int32_t i = 0; i < L.M; ++i)
     for (int32_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k) {
-      int32_t c = L.cadj[k];
-      mark(c);
-      for (int32_t m = L.cptr[c]; m < L.cptr[c + 1]; ++m)
-        if (L.cadj[m] != i) mark(L.cadj[m]);
+      const int32_t c = L.cadj[k];
+      if (col[c] == col[i]) return false;
+      for (int32_t m = L.cptr[c]; m < L.cptr[c + 1]; ++m) {
+        const int32_t d = L.cadj[m];
+        if (d != i && col[d] == col[i]) return false;
+      }
     }
-    int32_t c = 0;
-    while (c < (int32_t)stamp.size() && stamp[c] == i) ++c;
-    colour[i] = c;
+  return true;
+}
+
+bool lattice_colours(const LevelSym& L, int ndim, std::vector<int32_t>& col) {
+  if (L.coords.empty() || ndim < 1) return false;
+  struct Cand {
+    bool lin;
+    int a[3];
+    int q;
+  };
+  std::vector<Cand> cands;
+  if (ndim == 1) cands = {{true, {1, 0, 0}, 3}};
+  if (ndim == 2) cands = {{true, {1, 2, 0}, 5}, {false, {0, 0, 0}, 3}};
+  if (ndim == 3) cands = {{true, {1, 2, 3}, 7}, {false, {0, 0, 0}, 3}};
+  col.assign(L.M, 0);
+  for (const Cand& cd : cands) {
+    for (int32_t i = 0; i < L.M; ++i) {
+      const int32_t* c = &L.coords[(int64_t)i * ndim];
+      int64_t v = 0;
+      if (cd.lin) {
+        for (int k = 0; k < ndim; ++k) v += (int64_t)cd.a[k] * c[k];
+        v %= cd.q;
+      } else {
+        int64_t mul = 1;
+        for (int k = 0; k < ndim; ++k) {
+          v += (int64_t)(c[k] % cd.q) * mul;
+          mul *= cd.q;
+        }
+      }
+      col[i] = (int32_t)v;
+    }
+    if (valid_colouring(L, col)) return true;
+  }
+  return false;
+}
+
+void colour_order(LevelSym& L, int ndim) {
+  const int32_t M = L.M;
+  std::vector<int32_t> colour;
+  if (!lattice_colours(L, ndim, colour)) {
+    colour.assign(M, -1);
+    std::vector<int32_t> stamp;
+    for (int32_t i = 0; i < M; ++i) {
+      auto mark = [&](int32_t j) {
+        if (j < i) {
+          int32_t c = colour[j];
+          if ((int32_t)stamp.size() <= c) stamp.resize(c + 1, -1);
+          stamp[c] = i;
+        }
+      };
+      for (int32_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k) {
+        int32_t c = L.cadj[k];
+        mark(c);
+        for (int32_t m = L.cptr[c]; m < L.cptr[c + 1]; ++m)
+          if (L.cadj[m] != i) mark(L.cadj[m]);
+      }
+      int32_t c = 0;
+      while (c < (int32_t)stamp.size() && stamp[c] == i) ++c;
+      colour[i] = c;
+    }
   }
   L.order.resize(M);
   std::iota(L.order.begin(), L.order.end(), 0);
@@ -396,7 +448,7 @@ std::string analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
       L.order.resize(M);
       std::iota(L.order.begin(), L.order.end(), 0);
     } else {
-      colour_order(L);
+      colour_order(L, cur_coords.empty() ? 0 : ndim);
     }
     L.pos.assign(M, 0);
     for (int32_t s = 0; s < M; ++s) L.pos[L.order[s]] = s;

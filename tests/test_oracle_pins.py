@@ -256,7 +256,7 @@ def test_level_counts_64x64(order):
     for lev in range(4):
         assert len(pairs) == bound_close[lev] if lev == 0 else len(pairs) <= bound_close[lev]
         adj = adjacency(M, pairs)
-        order_l = list(range(M)) if order == "paper" else colour_order(adj)[0]
+        order_l = list(range(M)) if order == "paper" else colour_order(adj, coords)[0]
         _, far, removed = simulate_level(M, pairs, order_l)
         # far pattern is inside pattern(A^2) \ pattern(A)
         d2 = set()

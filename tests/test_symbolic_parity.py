@@ -49,7 +49,7 @@ def _oracle_levels(csr, perm, bp, co, order):
     out = []
     while True:
         adj = osym.adjacency(M, pairs)
-        ordl = osym.element_order(adj, order) if M > 1 else [0]
+        ordl = osym.element_order(adj, order, coords) if M > 1 else [0]
         _, far, removed = osym.simulate_level(M, pairs, ordl)
         lev = dict(M=M, close=pairs, order=ordl, far=far, removed=removed)
         out.append(lev)
