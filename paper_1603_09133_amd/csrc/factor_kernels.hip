@@ -161,11 +161,18 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
   }
   __syncthreads();
   const T noise = Eps<T>::v() * sqrt(sh_norm2);
+  // two rows that both stay below theta/64 end in the dropped set whatever
+  // their mutual rotation; they are left alone
+  const T negl = A.rank_mode == 0 ? max(noise, (T)(*A.theta / 64.0)) : noise;
   const int nb = b + (b & 1);
   const int npair = nb / 2;
   // rotation threshold: the computed a_p^T a_q of exactly orthogonal columns
   // carries a rounding error of a few b*eps, so the threshold must be above it
   const T tol = T(max(b, 16)) * Eps<T>::v();
+  // a rotation moves the smaller row of a pair by about |d| / max(na, nc);
+  // below the QR's own absolute rounding level (tol * ||R||) it is skipped
+  const T aerr = A.rank_mode == 0 ? max(noise, min(T(max(b, 16)) * noise, (T)(*A.theta / 32.0)))
+                                  : T(max(b, 16)) * noise;
   const int lane8 = tid & 7;
   for (int sweep = 0; sweep < 60; ++sweep) {
     int rotated = 0;
@@ -193,7 +200,8 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
           d += __shfl_xor(d, o, 8);
         }
         const T na = sqrt(a), nc = sqrt(c);
-        if (d != T(0) && fabs(d) > tol * na * nc && (na > noise || nc > noise)) {
+        if (d != T(0) && fabs(d) > tol * na * nc && (na > negl || nc > negl) &&
+            fabs(d) > aerr * max(na, nc)) {
           const T zeta = (c - a) / (T(2) * d);
           T t;
           if (fabs(zeta) > T(1e15))
@@ -441,6 +449,7 @@ __global__ __launch_bounds__(WV) void k_compress_wave(LevelArgs<T> A, int32_t s0
   }
   fro = wave_sum(fro);
   const T noise = Eps<T>::v() * sqrt(fro);
+  const T negl = A.rank_mode == 0 ? max(noise, (T)(*A.theta / 64.0)) : noise;
   uint64_t mask[NCOL];
   int before[NCOL];
   int ma = 0;
@@ -479,6 +488,10 @@ __global__ __launch_bounds__(WV) void k_compress_wave(LevelArgs<T> A, int32_t s0
   // ---- 3. one-sided Jacobi: LP lanes rotate the pair (p, q) of round rho ------
   const int mm = ma + (ma & 1);
   const T tol = T(max(b, 16)) * Eps<T>::v();
+  // a rotation moves the smaller row of a pair by about |d| / max(na, nc);
+  // below the QR's own absolute rounding level (tol * ||R||) it is skipped
+  const T aerr = A.rank_mode == 0 ? max(noise, min(T(max(b, 16)) * noise, (T)(*A.theta / 32.0)))
+                                  : T(max(b, 16)) * noise;
   const int LPs = (mm / 2 <= 16) ? 4 : ((mm / 2 <= 32) ? 2 : 1);
   const int pp = lane / LPs, sub = lane % LPs;
   int nsweep = 0;
@@ -520,7 +533,8 @@ __global__ __launch_bounds__(WV) void k_compress_wave(LevelArgs<T> A, int32_t s0
         }
         if (p >= 0) {
           const T na = sqrt(a), nc = sqrt(cc);
-          if (d != T(0) && fabs(d) > tol * na * nc && (na > noise || nc > noise)) {
+          if (d != T(0) && fabs(d) > tol * na * nc && (na > negl || nc > negl) &&
+            fabs(d) > aerr * max(na, nc)) {
             const T zeta = (cc - a) / (T(2) * d);
             T tt;
             if (fabs(zeta) > T(1e15))
@@ -626,7 +640,434 @@ __global__ __launch_bounds__(WV) void k_compress_wave(LevelArgs<T> A, int32_t s0
     A.rank[i] = r;
     A.edrop[i] = edrop;
     if (A.dbg) {
-      int64_t* dd = A.dbg + 8 * (int64_t)i;
+      int64_t* dd = A.dbg + 72 * (int64_t)i;
+      dd[0] = ma;
+      dd[1] = nsweep;
+      dd[2] = wtot;
+      dd[3] = b;
+      dd[4] = t_qr - t_start;
+      dd[5] = t_cmp - t_qr;
+      dd[6] = t_jac - t_cmp;
+      dd[7] = clock64() - t_jac;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Compression by one 256-thread workgroup per step (b <= 64): the same four
+// phases as k_compress_wave, with the four wavefronts cooperating so that a
+// single step finishes sooner (a wave's compression time is set by its
+// slowest step):
+//   TSQR  : wavefront w owns rows w*RW .. w*RW+RW-1 of each chunk, lane j
+//           column j; one barrier per column (partial dots double-buffered);
+//   Jacobi: LP = 8 or 16 lanes per row pair, shuffle-reduced dots;
+//   basis : reflectors and Q built by all threads.
+// ---------------------------------------------------------------------------
+template <typename T>
+size_t work_compress_wg() {
+  constexpr int LD = WaveLd<64>::LD;
+  return (size_t)2 * 64 * LD + 2 * 4 * 64 + 4 * WaveCh<T>::CH + 4 * 64 + 16;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_compress_wg(LevelArgs<T> A, int32_t s0) {
+  constexpr int CH = WaveCh<T>::CH;   // chunk rows (FP32 64, FP64 32)
+  constexpr int RW = CH / 4;          // rows per wavefront
+  constexpr int LD = WaveLd<64>::LD;
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  T* Ug = A.U + A.u_off[i];
+  if (st.nfar == 0 || b == 0) {
+    for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
+    if (tid == 0) {
+      A.rank[i] = 0;
+      A.edrop[i] = 0.0;
+    }
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* R = reinterpret_cast<T*>(smem_raw);   // 64 x LD: R, then kept directions / reflectors
+  T* X = R + 64 * LD;                      // 64 x LD: active rows, then Q
+  T* part = X + 64 * LD;                   // 2 x 4 x 64 partial dots
+  T* bc = part + 2 * 4 * 64;               // 4 x RW broadcast strips
+  T* sg = bc + 4 * CH;                     // 64 singular values
+  T* tau = sg + 64;                        // 64 reflector coefficients
+  int* posv = reinterpret_cast<int*>(tau + 64);
+  __shared__ double shd[4];
+  __shared__ int shi[4];
+  for (int e = tid; e < 64 * LD; e += NT) R[e] = T(0);
+  __syncthreads();
+  const int64_t t_start = clock64();
+  int wtot = 0;
+
+  // ---- 1. TSQR --------------------------------------------------------------
+  T* bcw = bc + wv * RW;
+  int buf = 0;
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    wtot += w;
+    for (int c0 = 0; c0 < w; c0 += CH) {
+      const int m = min(CH, w - c0);
+      T c[RW];
+#pragma unroll
+      for (int t = 0; t < RW; ++t) {
+        const int row = wv * RW + t;
+        c[t] = (lane < b && row < m) ? *view_ptr(base, v.trans, b, bx, lane, c0 + row) : T(0);
+      }
+      for (int k = 0; k < b; ++k) {
+        if (lane == k) {
+#pragma unroll
+          for (int t = 0; t < RW; ++t) bcw[t] = c[t];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        T ck[RW];
+#pragma unroll
+        for (int t = 0; t < RW; ++t) ck[t] = bcw[t];
+        part[buf * 256 + wv * 64 + lane] = dot_u(ck, c);
+        const T rkk = R[k * LD + k];
+        const T rkj = R[k * LD + lane];
+        __syncthreads();
+        const T* pb = part + buf * 256;
+        const T sdot = pb[lane] + pb[64 + lane] + pb[128 + lane] + pb[192 + lane];
+        const T xn2 = pb[k] + pb[64 + k] + pb[128 + k] + pb[192 + k];
+        buf ^= 1;
+        if (xn2 > Eps<T>::tiny()) {
+          const T nrm = sqrt(rkk * rkk + xn2);
+          const T alpha = rkk >= T(0) ? -nrm : nrm;
+          const T v0 = rkk - alpha;
+          const T tk = T(2) / (v0 * v0 + xn2);
+          const T coef = (lane > k && lane < b) ? tk * (v0 * rkj + sdot) : T(0);
+#pragma unroll
+          for (int t = 0; t < RW; ++t) c[t] -= coef * ck[t];
+          if (wv == 0) {
+            if (lane > k && lane < b) R[k * LD + lane] = rkj - coef * v0;
+            if (lane == k) R[k * LD + k] = alpha;
+          }
+        }
+        // the next column's partials go to the other buffer; row k of R is
+        // read again only after further barriers
+      }
+      __syncthreads();
+    }
+  }
+  const int64_t t_qr = clock64();
+
+  // ---- 2. active rows (wave 0 measures, all copy) ----------------------------
+  if (wv == 0) {
+    T s2 = 0;
+    if (lane < b)
+      for (int j = lane; j < b; ++j) s2 += R[lane * LD + j] * R[lane * LD + j];
+    const T fro = wave_sum(s2);
+    const T noise = Eps<T>::v() * sqrt(fro);
+    const bool act = lane < b && sqrt(s2) > noise;
+    const uint64_t mask = __ballot(act);
+    const double inactive = wave_sum((lane < b && !act) ? (double)s2 : 0.0);
+    posv[lane] = act ? __popcll(mask & ((1ull << lane) - 1ull)) : -1;
+    if (lane == 0) {
+      shi[0] = __popcll(mask);
+      shd[0] = inactive;
+      shd[1] = (double)noise;
+    }
+  }
+  __syncthreads();
+  int ma = shi[0];
+  double inactive = shd[0];
+  const T noise = (T)shd[1];
+  const T negl = A.rank_mode == 0 ? max(noise, (T)(*A.theta / 64.0)) : noise;
+  // a Jacobi rotation moves the smaller row of a pair by about |d| / max(na, nc);
+  // below the QR's absolute rounding level (b * eps * ||R||) it is skipped; in
+  // CE(eps) that level is capped at theta / 32 so that it cannot add to a rank
+  const T aerr = A.rank_mode == 0 ? max(noise, min(T(max(b, 16)) * noise, (T)(*A.theta / 32.0)))
+                                  : T(max(b, 16)) * noise;
+  for (int e = tid; e < 64 * 64; e += NT) {
+    const int k = e >> 6, j = e & 63;
+    const int dst = posv[k];
+    if (dst >= 0) X[dst * LD + j] = R[k * LD + j];
+  }
+
+  // ---- 2b. column-pivoted QR of the active rows (a left orthogonal transform,
+  // so the Gram matrix R^T R and hence the left singular vectors of the far row
+  // are unchanged).  Its rows come out graded, which lets the one-sided Jacobi
+  // converge in a few sweeps (Jacobi preconditioned by a pivoted QR, after
+  // Drmac and Veselic).  It stops once the trailing block is below the
+  // rounding level aerr; that block joins the dropped part.  Columns are
+  // permuted: piv[t] is the coordinate held in column t.
+  T* cn = part;                             // squared trailing column norms
+  T* vh = part + 64;                        // reflector of the current column
+  int* piv = reinterpret_cast<int*>(part + 192);
+  __shared__ T qtau;
+  {
+    const int col = tid >> 2, sb = tid & 3;
+    __syncthreads();
+    T s2 = 0;
+    if (col < b)
+      for (int p = sb; p < ma; p += 4) s2 += X[p * LD + col] * X[p * LD + col];
+    s2 += __shfl_xor(s2, 1, WV);
+    s2 += __shfl_xor(s2, 2, WV);
+    if (sb == 0 && col < 64) {
+      cn[col] = col < b ? s2 : T(0);
+      piv[col] = col;
+    }
+    __syncthreads();
+    const T stop2 = aerr * aerr;
+    const int kmax = min(ma, b);
+    int k = 0;
+    for (; k < kmax; ++k) {
+      if (wv == 0) {
+        const bool in = lane >= k && lane < b;
+        T cv = in ? cn[lane] : T(-1);
+        int ci = lane;
+        const T rs = wave_sum(in ? cn[lane] : T(0));
+        for (int o = 32; o > 0; o >>= 1) {
+          const T ov = __shfl_xor(cv, o, WV);
+          const int oi = __shfl_xor(ci, o, WV);
+          if (ov > cv || (ov == cv && oi < ci)) {
+            cv = ov;
+            ci = oi;
+          }
+        }
+        const bool stop = rs <= stop2;
+        if (!stop) {
+          const int jm = ci;
+          T xk = lane < ma ? X[lane * LD + k] : T(0);
+          if (jm != k) {
+            const T xm = lane < ma ? X[lane * LD + jm] : T(0);
+            if (lane < ma) {
+              X[lane * LD + k] = xm;
+              X[lane * LD + jm] = xk;
+            }
+            xk = xm;
+            if (lane == 0) {
+              const T c0 = cn[k];
+              cn[k] = cn[jm];
+              cn[jm] = c0;
+              const int p0 = piv[k];
+              piv[k] = piv[jm];
+              piv[jm] = p0;
+            }
+          }
+          const T x = (lane >= k && lane < ma) ? xk : T(0);
+          const T nrm2 = wave_sum(x * x);
+          const T x0 = __shfl(xk, k, WV);
+          T tq = 0;
+          if (nrm2 > Eps<T>::tiny()) {
+            const T nrm = sqrt(nrm2);
+            const T alpha = x0 >= T(0) ? -nrm : nrm;
+            const T v0 = x0 - alpha;
+            const T vv = v0 * v0 + (nrm2 - x0 * x0);
+            tq = vv > T(0) ? T(2) / vv : T(0);
+            vh[lane] = lane == k ? v0 : x;
+            if (lane == k) X[k * LD + k] = alpha;
+            if (lane > k && lane < ma) X[lane * LD + k] = T(0);
+          } else {
+            vh[lane] = T(0);
+          }
+          if (lane == 0) qtau = tq;
+        }
+        if (lane == 0) {
+          shi[2] = stop ? 1 : 0;
+          shd[3] = (double)rs;
+        }
+      }
+      __syncthreads();
+      if (shi[2]) break;
+      // apply the reflector to the later columns, then refresh their trailing
+      // norms (4 threads per column)
+      const int j = k + 1 + col;
+      if (j < b) {
+        const T tq = qtau;
+        T dd = 0;
+        for (int p = k + sb; p < ma; p += 4) dd += vh[p] * X[p * LD + j];
+        dd += __shfl_xor(dd, 1, WV);
+        dd += __shfl_xor(dd, 2, WV);
+        T t2 = 0;
+        for (int p = k + sb; p < ma; p += 4) {
+          const T y = X[p * LD + j] - tq * dd * vh[p];
+          X[p * LD + j] = y;
+          if (p > k) t2 += y * y;
+        }
+        t2 += __shfl_xor(t2, 1, WV);
+        t2 += __shfl_xor(t2, 2, WV);
+        if (sb == 0) cn[j] = t2;
+      }
+      __syncthreads();
+    }
+    if (k < kmax) inactive += shd[3];
+    ma = k;
+  }
+  __syncthreads();
+  const int64_t t_cmp = clock64();
+
+  // ---- 3. one-sided Jacobi on the ma rows of X ------------------------------
+  const int mm = ma + (ma & 1);
+  const T tol = T(max(b, 16)) * Eps<T>::v();
+  const int LP = (mm / 2 <= 16) ? 16 : 8;   // lanes per pair (power of two, divides 64)
+  const int pp = tid / LP, sub = tid % LP;
+  int nsweep = 0;
+  for (int sweep = 0; sweep < 40 && ma > 1; ++sweep) {
+    ++nsweep;
+    int rotated = 0;
+    for (int rho = 0; rho < mm - 1; ++rho) {
+      int p = -1, q = -1;
+      if (pp < mm / 2) {
+        if (pp == 0) {
+          p = mm - 1;
+          q = rho;
+        } else {
+          p = (rho + pp) % (mm - 1);
+          q = (rho - pp + (mm - 1)) % (mm - 1);
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q >= ma) p = -1;
+      }
+      T a = 0, cc = 0, d = 0;
+      if (p >= 0) {
+        for (int t = sub; t < b; t += LP) {
+          const T x = X[p * LD + t], y = X[q * LD + t];
+          a += x * x;
+          cc += y * y;
+          d += x * y;
+        }
+      }
+      for (int o = 1; o < LP; o <<= 1) {
+        a += __shfl_xor(a, o, WV);
+        cc += __shfl_xor(cc, o, WV);
+        d += __shfl_xor(d, o, WV);
+      }
+      if (p >= 0) {
+        const T na = sqrt(a), nc = sqrt(cc);
+        if (d != T(0) && fabs(d) > tol * na * nc && (na > negl || nc > negl) &&
+            fabs(d) > aerr * max(na, nc)) {
+          const T zeta = (cc - a) / (T(2) * d);
+          T tt;
+          if (fabs(zeta) > T(1e15))
+            tt = T(0.5) / zeta;
+          else
+            tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+          const T cs = T(1) / sqrt(T(1) + tt * tt), sn = cs * tt;
+          for (int t = sub; t < b; t += LP) {
+            const T x = X[p * LD + t], y = X[q * LD + t];
+            X[p * LD + t] = cs * x - sn * y;
+            X[q * LD + t] = sn * x + cs * y;
+          }
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  const int64_t t_jac = clock64();
+
+  // ---- singular values, order, rank -----------------------------------------
+  if (wv == 0) {
+    T s2 = 0;
+    if (lane < ma)
+      for (int t = 0; t < b; ++t) s2 += X[lane * LD + t] * X[lane * LD + t];
+    if (lane < ma) sg[lane] = sqrt(s2);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    int pos = 0;
+    if (lane < ma) {
+      const T sp = sg[lane];
+      for (int q = 0; q < ma; ++q) pos += (sg[q] > sp || (sg[q] == sp && q < lane)) ? 1 : 0;
+      posv[lane] = pos;
+    }
+    const double theta = *A.theta;
+    const int cnt = __popcll(__ballot(lane < ma && (double)sg[lane] > theta));
+    const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
+    const double ed = wave_sum((lane < ma && pos >= r) ? (double)sg[lane] * (double)sg[lane] : 0.0);
+    if (lane == 0) {
+      shi[1] = r;
+      shd[2] = ed + inactive;
+    }
+  }
+  __syncthreads();
+  const int r = shi[1];
+  const int kb = min(r, ma);
+
+  // ---- 4. orthonormal completion ----------------------------------------------
+  T* Bv = R;
+  for (int e = tid; e < ma * 64; e += NT) {
+    const int p = e >> 6, t = e & 63;
+    const int c2 = posv[p];
+    if (c2 < kb) {
+      const T inv = sg[p] > T(0) ? T(1) / sg[p] : T(0);
+      if (t < b)
+        Bv[c2 * LD + piv[t]] = X[p * LD + t] * inv;
+      else
+        Bv[c2 * LD + t] = T(0);
+    }
+  }
+  __syncthreads();
+  for (int cv = 0; cv < kb; ++cv) {
+    if (wv == 0) {
+      const T x = (lane >= cv && lane < b) ? Bv[cv * LD + lane] : T(0);
+      const T nrm2 = wave_sum(x * x);
+      const T x0 = Bv[cv * LD + cv];
+      const T nrm = sqrt(nrm2);
+      const T alpha = x0 >= T(0) ? -nrm : nrm;
+      const T v0 = x0 - alpha;
+      const T vv = v0 * v0 + (nrm2 - x0 * x0);
+      if (lane < cv) Bv[cv * LD + lane] = T(0);
+      if (lane == cv) {
+        Bv[cv * LD + cv] = v0;
+        tau[cv] = vv > T(0) ? T(2) / vv : T(0);
+      }
+    }
+    __syncthreads();
+    // apply H_cv to the later vectors: 16 lanes per vector
+    {
+      const T tc = tau[cv];
+      for (int c2 = cv + 1 + tid / 16; c2 - tid / 16 < kb; c2 += NT / 16) {
+        const int sb = tid % 16;
+        T dd = 0;
+        if (c2 < kb)
+          for (int t = cv + sb; t < b; t += 16) dd += Bv[cv * LD + t] * Bv[c2 * LD + t];
+        for (int o = 1; o < 16; o <<= 1) dd += __shfl_xor(dd, o, WV);
+        if (c2 < kb)
+          for (int t = cv + sb; t < b; t += 16) Bv[c2 * LD + t] -= tc * dd * Bv[cv * LD + t];
+      }
+    }
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{kb-1}: 4 lanes per column
+  T* Q = X;
+  for (int e = tid; e < 64 * LD; e += NT) Q[e] = (e / LD == e % LD) ? T(1) : T(0);
+  __syncthreads();
+  for (int cv = kb - 1; cv >= 0; --cv) {
+    const T tc = tau[cv];
+    const int col = tid >> 2, sb = tid & 3;
+    T dd = 0;
+    for (int t = cv + sb; t < b; t += 4) dd += Bv[cv * LD + t] * Q[t * LD + col];
+    dd += __shfl_xor(dd, 1, WV);
+    dd += __shfl_xor(dd, 2, WV);
+    for (int t = cv + sb; t < b; t += 4) Q[t * LD + col] -= tc * dd * Bv[cv * LD + t];
+    __syncthreads();
+  }
+  for (int e = tid; e < b * b; e += NT) Ug[e] = Q[(e / b) * LD + e % b];
+  if (A.dbg && tid < ma && tid < 64) {
+    double* sv = reinterpret_cast<double*>(A.dbg + 72 * (int64_t)i + 8);
+    sv[tid] = (double)sg[tid];
+  }
+  if (tid == 0) {
+    A.rank[i] = r;
+    A.edrop[i] = shd[2];
+    if (A.dbg) {
+      int64_t* dd = A.dbg + 72 * (int64_t)i;
       dd[0] = ma;
       dd[1] = nsweep;
       dd[2] = wtot;
@@ -1149,8 +1590,8 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
   T* gs = gscratch;
   if (w.s1 > w.s0) {
     const int ns = w.s1 - w.s0;
-    const size_t w64 = work_compress_wave<T, 64>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
-    hipLaunchKernelGGL((k_compress_wave<T, 64>), dim3(ns), dim3(WV), w64, stream, A, w.s0);
+    const size_t wg = work_compress_wg<T>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
+    hipLaunchKernelGGL(k_compress_wg<T>, dim3(ns), dim3(NT), wg, stream, A, w.s0);
     if (bmax > 64) {
       if (bmax <= 128 && w128 <= max_lds_bytes()) {
         hipLaunchKernelGGL((k_compress_wave<T, 128>), dim3(ns), dim3(WV), w128, stream, A, w.s0);

@@ -308,8 +308,8 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     static const bool dbg_on = getenv("CAE_DEBUG_COMPRESS") != nullptr;
     DevBuf dbgbuf;
     if (dbg_on) {
-      dbgbuf.alloc((size_t)8 * L.M * sizeof(int64_t));
-      HIPCHK(hipMemsetAsync(dbgbuf.p, 0, (size_t)8 * L.M * sizeof(int64_t), s));
+      dbgbuf.alloc((size_t)72 * L.M * sizeof(int64_t));
+      HIPCHK(hipMemsetAsync(dbgbuf.p, 0, (size_t)72 * L.M * sizeof(int64_t), s));
       A.dbg = dbgbuf.as<int64_t>();
     }
     std::vector<hipEvent_t> evs;
@@ -330,18 +330,28 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     }
     HIPCHK(hipGetLastError());
     if (dbg_on) {
-      std::vector<int64_t> hd((size_t)8 * L.M);
+      std::vector<int64_t> hd((size_t)72 * L.M);
       HIPCHK(hipMemcpyAsync(hd.data(), dbgbuf.p, hd.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       double sum[8] = {0}, mx[8] = {0};
       int cnt = 0;
+      int worst = -1;
       for (int32_t b2 = 0; b2 < L.M; ++b2) {
-        if (hd[8 * b2 + 3] == 0) continue;
+        if (hd[72 * b2 + 3] == 0) continue;
         ++cnt;
         for (int k = 0; k < 8; ++k) {
-          sum[k] += (double)hd[8 * b2 + k];
-          mx[k] = std::max(mx[k], (double)hd[8 * b2 + k]);
+          sum[k] += (double)hd[72 * b2 + k];
+          mx[k] = std::max(mx[k], (double)hd[72 * b2 + k]);
         }
+        if (worst < 0 || hd[72 * b2 + 1] > hd[72 * worst + 1]) worst = b2;
+      }
+      if (worst >= 0) {
+        const double* sv = reinterpret_cast<const double*>(&hd[72 * worst + 8]);
+        fprintf(stderr, "[cae] worst block %d: ma %lld sweeps %lld b %lld w %lld sigma:", worst,
+                (long long)hd[72 * worst], (long long)hd[72 * worst + 1], (long long)hd[72 * worst + 3],
+                (long long)hd[72 * worst + 2]);
+        for (int k = 0; k < std::min<int64_t>(hd[72 * worst], 64); ++k) fprintf(stderr, " %.3g", sv[k]);
+        fprintf(stderr, "\n");
       }
       if (cnt)
         fprintf(stderr,
