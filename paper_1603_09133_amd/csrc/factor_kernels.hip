@@ -1092,6 +1092,7 @@ __global__ __launch_bounds__(NT) void k_rotate(LevelArgs<T> A, int32_t it0, T* g
   const Step st = A.steps[item.step];
   const int i = st.blk;
   const int b = A.bsz[i];
+  if (A.small_by_wave && b <= A.small_by_wave) return;
   const int tid = threadIdx.x;
   if (b == 0) return;
   const T* Ug = A.U + A.u_off[i];
@@ -1255,6 +1256,7 @@ __global__ __launch_bounds__(NT) void k_trsm(LevelArgs<T> A, int32_t it0, T* gsc
   const Step st = A.steps[item.step];
   const int i = st.blk;
   const int b = A.bsz[i];
+  if (A.small_by_wave && b <= A.small_by_wave) return;
   const int r = A.rank[i];
   const int n = b - r;
   if (n <= 0) return;
@@ -1301,6 +1303,7 @@ __global__ __launch_bounds__(NT) void k_schur(LevelArgs<T> A, int32_t p0, T* gsc
   const Step st = A.steps[pr.step];
   const int i = st.blk;
   const int b = A.bsz[i];
+  if (A.small_by_wave && b <= A.small_by_wave) return;
   const int r = A.rank[i];
   const int n = b - r;
   if (n <= 0) return;
@@ -1375,6 +1378,283 @@ __global__ __launch_bounds__(NT) void k_schur(LevelArgs<T> A, int32_t p0, T* gsc
       T s = 0;
       for (int t = 0; t < n; ++t) s += Pa[t * lda + al] * Pc[t * ldc + gm];
       tbase[al * ts_a + (int64_t)(c0 + gm) * ts_c] -= s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-tiled variants of rotation, triangular solve and Schur update for
+// steps with b_i <= 64.  Every product is C = A^T B with A (K x 64) and B
+// (K x 64) staged in LDS (row stride TLD); thread (ty, tx) = (tid / 16,
+// tid % 16) accumulates the 4 x 4 tile rows 4ty.., columns 4tx.. in registers,
+// so one k step costs 8 LDS reads for 16 FMAs.  Global tiles are moved with
+// the thread mapping that makes consecutive threads touch consecutive
+// addresses for either storage orientation of a view.
+// ---------------------------------------------------------------------------
+constexpr int TLD = 68;
+
+template <typename T>
+__device__ inline void gemm_tn_4x4(const T* A, const T* B, int K, T acc[4][4]) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const T* a = A + 4 * ty;
+  const T* bb = B + 4 * tx;
+#pragma unroll 2
+  for (int k = 0; k < K; ++k) {
+    T av[4], bv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      av[q] = a[k * TLD + q];
+      bv[q] = bb[k * TLD + q];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] += av[p] * bv[q];
+  }
+}
+
+template <typename T>
+__device__ inline void zero_acc(T acc[4][4]) {
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = T(0);
+}
+
+// S[a][c] = view(rows row0 + a, columns c0 + c) for a < na, c < nc.
+template <typename T>
+__device__ inline void load_view_tile(T* S, const T* base, int trans, int bi, int bx, int row0, int na, int c0,
+                                      int nc) {
+  if (trans) {
+    for (int e = threadIdx.x; e < na * nc; e += NT) {
+      const int c = e / na, a = e % na;
+      S[a * TLD + c] = base[(int64_t)(c0 + c) * bi + row0 + a];
+    }
+  } else {
+    for (int e = threadIdx.x; e < na * nc; e += NT) {
+      const int a = e / nc, c = e % nc;
+      S[a * TLD + c] = base[(int64_t)(row0 + a) * bx + c0 + c];
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void store_view_tile(const T* S, T* base, int trans, int bi, int bx, int row0, int na, int c0,
+                                       int nc) {
+  if (trans) {
+    for (int e = threadIdx.x; e < na * nc; e += NT) {
+      const int c = e / na, a = e % na;
+      base[(int64_t)(c0 + c) * bi + row0 + a] = S[a * TLD + c];
+    }
+  } else {
+    for (int e = threadIdx.x; e < na * nc; e += NT) {
+      const int a = e / nc, c = e % nc;
+      base[(int64_t)(row0 + a) * bx + c0 + c] = S[a * TLD + c];
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void acc_to_lds(const T acc[4][4], T* S) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S[(4 * ty + p) * TLD + 4 * tx + q] = acc[p][q];
+}
+
+template <typename T>
+size_t work_tiled() {
+  return (size_t)2 * 64 * TLD;
+}
+
+// V_ix <- U_i^T V_ix (far views keep rows 0..r_i-1), D_i <- U_i^T D_i U_i.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
+  const Item item = A.items[it0 + blockIdx.x];
+  const Step st = A.steps[item.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b == 0 || b > 64) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Us = reinterpret_cast<T*>(smem_raw);
+  T* X = Us + 64 * TLD;
+  const T* Ug = A.U + A.u_off[i];
+  for (int e = threadIdx.x; e < b * b; e += NT) Us[(e / b) * TLD + e % b] = Ug[e];
+  T acc[4][4];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  if (item.view < 0) {
+    T* D = A.arena + A.slot_off[i];
+    for (int e = threadIdx.x; e < b * b; e += NT) X[(e / b) * TLD + e % b] = D[e];
+    __syncthreads();
+    zero_acc(acc);
+    gemm_tn_4x4(X, Us, b, acc);       // Z = D U (D symmetric)
+    __syncthreads();
+    acc_to_lds(acc, X);
+    __syncthreads();
+    zero_acc(acc);
+    gemm_tn_4x4(Us, X, b, acc);       // U^T Z
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int a = 4 * ty + p;
+      if (a < b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = 4 * tx + q;
+          if (c < b) D[a * b + c] = acc[p][q];
+        }
+    }
+    return;
+  }
+  const View v = A.views[item.view];
+  const int bx = A.bsz[v.x];
+  const bool far = (item.view - st.view0) >= st.nclose;
+  const int r = A.rank[i];
+  T* base = A.arena + A.slot_off[v.slot];
+  for (int c0 = 0; c0 < bx; c0 += 64) {
+    const int tc = min(64, bx - c0);
+    __syncthreads();
+    load_view_tile(X, base, v.trans, b, bx, 0, b, c0, tc);
+    __syncthreads();
+    zero_acc(acc);
+    gemm_tn_4x4(Us, X, b, acc);
+    if (far) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        if (4 * ty + p >= r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[p][q] = T(0);
+    }
+    __syncthreads();
+    acc_to_lds(acc, X);
+    __syncthreads();
+    store_view_tile(X, base, v.trans, b, bx, 0, b, c0, tc);
+  }
+}
+
+// L(c, n_i)^T = L_nn^{-1} V_ic[n_i, live_c] as a product with the stored inverse.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_trsm_t(LevelArgs<T> A, int32_t it0) {
+  const Item item = A.items[it0 + blockIdx.x];
+  const Step st = A.steps[item.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const View v = A.views[item.view];
+  const int bx = A.bsz[v.x];
+  const int lc = v.proc ? A.rank[v.x] : bx;
+  if (lc == 0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Lt = reinterpret_cast<T*>(smem_raw);   // Lt[k][j] = Li[j][k]
+  T* X = Lt + 64 * TLD;
+  const T* Lig = A.Li + A.u_off[i];
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int j = e / n, k = e % n;
+    Lt[k * TLD + j] = Lig[e];
+  }
+  T* base = A.arena + A.slot_off[v.slot];
+  T acc[4][4];
+  for (int c0 = 0; c0 < lc; c0 += 64) {
+    const int tc = min(64, lc - c0);
+    __syncthreads();
+    load_view_tile(X, base, v.trans, b, bx, r, n, c0, tc);
+    __syncthreads();
+    zero_acc(acc);
+    gemm_tn_4x4(Lt, X, n, acc);
+    __syncthreads();
+    acc_to_lds(acc, X);
+    __syncthreads();
+    store_view_tile(X, base, v.trans, b, bx, r, n, c0, tc);
+  }
+}
+
+// T(a, c) -= P_a^T P_c, P_a = rows n_i of panel a (0 = basis columns of D_i).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
+  const Pair pr = A.pairs[p0 + blockIdx.x];
+  const Step st = A.steps[pr.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  T* D = A.arena + A.slot_off[i];
+  int la, lc, ba = b, bc = b, ta = 0, tcv = 0;
+  T* pa;
+  T* pc;
+  if (pr.a == 0) {
+    la = r;
+    pa = D;
+  } else {
+    const View va = A.views[st.view0 + pr.a - 1];
+    ba = A.bsz[va.x];
+    la = va.proc ? A.rank[va.x] : ba;
+    pa = A.arena + A.slot_off[va.slot];
+    ta = va.trans;
+  }
+  if (pr.c == 0) {
+    lc = r;
+    pc = D;
+  } else {
+    const View vc = A.views[st.view0 + pr.c - 1];
+    bc = A.bsz[vc.x];
+    lc = vc.proc ? A.rank[vc.x] : bc;
+    pc = A.arena + A.slot_off[vc.slot];
+    tcv = vc.trans;
+  }
+  if (la == 0 || lc == 0) return;
+  T* tbase;
+  int64_t ts_a, ts_c;
+  if (pr.a == 0) {
+    if (pr.c == 0) {
+      tbase = D;
+      ts_a = b;
+      ts_c = 1;
+    } else {
+      tbase = pc;
+      ts_a = tcv ? 1 : bc;
+      ts_c = tcv ? b : 1;
+    }
+  } else {
+    tbase = A.arena + A.slot_off[pr.slot];
+    if (pr.trans) {
+      ts_a = 1;
+      ts_c = ba;
+    } else {
+      ts_a = bc;
+      ts_c = 1;
+    }
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Pa = reinterpret_cast<T*>(smem_raw);
+  T* Pc = Pa + 64 * TLD;
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  T acc[4][4];
+  for (int a0 = 0; a0 < la; a0 += 64) {
+    const int tan = min(64, la - a0);
+    __syncthreads();
+    load_view_tile(Pa, pa, ta, b, ba, r, n, a0, tan);
+    for (int c0 = 0; c0 < lc; c0 += 64) {
+      const int tcn = min(64, lc - c0);
+      if (c0 > 0) __syncthreads();
+      load_view_tile(Pc, pc, tcv, b, bc, r, n, c0, tcn);
+      __syncthreads();
+      zero_acc(acc);
+      gemm_tn_4x4(Pa, Pc, n, acc);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int al = 4 * ty + p;
+        if (al < tan)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int gm = 4 * tx + q;
+            if (gm < tcn) tbase[(int64_t)(a0 + al) * ts_a + (int64_t)(c0 + gm) * ts_c] -= acc[p][q];
+          }
+      }
     }
   }
 }
@@ -1607,13 +1887,23 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
 template <typename T>
 void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
   T* gs = gscratch;
+  const size_t wt = work_tiled<T>() * sizeof(T);
+  const bool tiled = wt <= max_lds_bytes();
   LevelArgs<T> B = A;
+  if (tiled) B.small_by_wave = 64;   // the generic kernels skip the steps the tiled ones take
+  const bool generic = !tiled || bmax > 64;
   B.items = A.rot;
-  launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
+  if (tiled && w.r1 > w.r0)
+    hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
+  if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
   launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
   B.items = A.trsm;
-  launch<T>(k_trsm<T>, B, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream);
-  launch<T>(k_schur<T>, A, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream);
+  if (tiled && w.t1 > w.t0)
+    hipLaunchKernelGGL(k_trsm_t<T>, dim3(w.t1 - w.t0), dim3(NT), wt, stream, B, w.t0);
+  if (generic) launch<T>(k_trsm<T>, B, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream);
+  if (tiled && w.p1 > w.p0)
+    hipLaunchKernelGGL(k_schur_t<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+  if (generic) launch<T>(k_schur<T>, B, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream);
 }
 
 template <typename T>
