@@ -28,35 +28,6 @@ __device__ inline double vget(const T* base, int trans, int bi, int bx, int a, i
   return (double)(trans ? base[(int64_t)c * bi + a] : base[(int64_t)a * bx + c]);
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_ap_rotate(ApplyArgs<T> A, double* y, int dir) {
-  const Step st = A.steps[blockIdx.x];
-  if (st.nfar == 0) return;                 // U_i = I
-  const int i = st.blk;
-  const int b = A.bsz[i];
-  if (b == 0) return;
-  const int nrhs = A.nrhs;
-  const T* U = A.U + A.u_off[i];
-  double* yi = y + A.dof_off[i] * nrhs;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Ys = reinterpret_cast<double*>(smem_raw);   // b x RC
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int kc = min(RC, nrhs - k0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * kc; e += NT) Ys[(e / kc) * RC + e % kc] = yi[(e / kc) * nrhs + k0 + e % kc];
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * kc; e += NT) {
-      const int a = e / kc, k = e % kc;
-      double s = 0;
-      if (dir == 0)
-        for (int l = 0; l < b; ++l) s += (double)U[(int64_t)l * b + a] * Ys[l * RC + k];
-      else
-        for (int l = 0; l < b; ++l) s += (double)U[(int64_t)a * b + l] * Ys[l * RC + k];
-      yi[a * nrhs + k0 + k] = s;
-    }
-  }
-}
-
 // Forward block solve of one step: t = L_nn^{-1} y_i[n]; y_c -= L(c, n) t.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_ap_fwd_generic(ApplyArgs<T> A, int32_t s0, double* y) {
@@ -159,59 +130,77 @@ __global__ __launch_bounds__(NT) void k_ap_bwd_generic(ApplyArgs<T> A, int32_t s
 }
 
 // ---------------------------------------------------------------------------
-// Block solves with the stored inverse L_nn^{-1} (computed at factorization):
-// every step is a few small matrix products staged in LDS, with no sequential
-// dependency inside the step.  Operand tiles are loaded with consecutive
-// threads on consecutive addresses of the slot that holds them.
+// Lean block-solve kernels: four threads share one output row and split the
+// reduction index four ways, each keeping 16 FP64 accumulators (one per
+// right-hand side of the pass); a two-step shuffle sums the quarters.  Factor
+// entries are read straight from global memory (each quarter walks its own
+// addresses, consecutive rows on consecutive lanes), only the 16-wide vector
+// tiles live in LDS, so a step needs 16 KB of LDS at b = 64 and many steps
+// run on one compute unit at once.
 // ---------------------------------------------------------------------------
-constexpr int PT = 64;          // panel column tile
-
-struct ApLds {
-  int ldl, ldp;
-  size_t off_l, off_p, off_y, off_t, off_z, total;
-};
-
-template <typename T>
-__host__ __device__ inline ApLds ap_layout(int bmax) {
-  ApLds L;
-  L.ldl = bmax + 1;
-  L.ldp = PT + 1;
-  size_t o = 0;
-  L.off_l = o;
-  o += (size_t)bmax * L.ldl * sizeof(T);
-  o = (o + 15) & ~(size_t)15;
-  L.off_p = o;
-  o += (size_t)bmax * L.ldp * sizeof(T);
-  o = (o + 15) & ~(size_t)15;
-  L.off_y = o;
-  o += (size_t)bmax * (RC + 1) * sizeof(double);
-  L.off_t = o;
-  o += (size_t)bmax * (RC + 1) * sizeof(double);
-  L.off_z = o;
-  o += (size_t)PT * (RC + 1) * sizeof(double);
-  L.total = o;
-  return L;
+__device__ inline void quad_sum16(double s[RC]) {
+#pragma unroll
+  for (int k = 0; k < RC; ++k) {
+    s[k] += __shfl_xor(s[k], 1, 64);
+    s[k] += __shfl_xor(s[k], 2, 64);
+  }
 }
 
-// Stage rows n (r..b-1) and columns [g0, g0+tc) of a panel view into Ps[t][g].
-template <typename T>
-__device__ inline void stage_panel(T* Ps, int ldp, const T* P, int trans, int b, int bx, int r, int n, int g0,
-                                   int tc) {
-  if (!trans) {
-    for (int e = threadIdx.x; e < n * tc; e += NT) {
-      const int t = e / tc, g = e % tc;
-      Ps[t * ldp + g] = P[(int64_t)(r + t) * bx + g0 + g];
-    }
-  } else {   // slot rows are the panel columns: read along them
-    for (int e = threadIdx.x; e < n * tc; e += NT) {
-      const int g = e / n, t = e % n;
-      Ps[t * ldp + g] = P[(int64_t)(g0 + g) * b + r + t];
-    }
+__device__ inline void axpy16(double s[RC], double p, const double* v) {
+#pragma unroll
+  for (int k = 0; k < RC; ++k) s[k] += p * v[k];
+}
+
+// Y[t][0..RC) = y[(row0 + t) * nrhs + k0 + k] (0 beyond kc), t < m.
+__device__ inline void load_vec_tile(double* Y, const double* y, int row0, int m, int nrhs, int k0, int kc) {
+  for (int e = threadIdx.x; e < m * RC; e += NT) {
+    const int t = e / RC, k = e % RC;
+    Y[e] = k < kc ? y[(int64_t)(row0 + t) * nrhs + k0 + k] : 0.0;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_ap_fwd(ApplyArgs<T> A, int32_t s0, double* y, int bmax) {
+__global__ __launch_bounds__(NT) void k_ap_rot2(ApplyArgs<T> A, double* y, int dir) {
+  const Step st = A.steps[blockIdx.x];
+  if (st.nfar == 0) return;
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b == 0) return;
+  const int nrhs = A.nrhs;
+  const T* U = A.U + A.u_off[i];
+  double* yi = y + A.dof_off[i] * nrhs;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Ys = reinterpret_cast<double*>(smem_raw);   // b x RC
+  const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
+  for (int k0 = 0; k0 < nrhs; k0 += RC) {
+    const int kc = min(RC, nrhs - k0);
+    __syncthreads();
+    load_vec_tile(Ys, yi, 0, b, nrhs, k0, kc);
+    __syncthreads();
+    for (int a0 = 0; a0 < b; a0 += 64) {
+      const int a = a0 + rl;
+      double s[RC];
+#pragma unroll
+      for (int k = 0; k < RC; ++k) s[k] = 0.0;
+      if (a < b) {
+        if (dir == 0)
+          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)l * b + a], Ys + l * RC);
+        else
+          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)a * b + l], Ys + l * RC);
+      }
+      quad_sum16(s);
+      if (a < b)
+#pragma unroll
+        for (int k = 4 * q; k < 4 * q + 4; ++k)
+          if (k < kc) yi[(int64_t)a * nrhs + k0 + k] = s[k];
+    }
+  }
+}
+
+// Forward block solve of one step: t = L_nn^{-1} y_i[n], y_i[n] = t, and
+// y_c -= L(c, n) t for the basis of i and every close block c.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax) {
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -219,30 +208,35 @@ __global__ __launch_bounds__(NT) void k_ap_fwd(ApplyArgs<T> A, int32_t s0, doubl
   const int n = b - r;
   if (n <= 0) return;
   const int nrhs = A.nrhs;
-  const ApLds Lay = ap_layout<T>(bmax);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Ls = reinterpret_cast<T*>(smem_raw + Lay.off_l);
-  T* Ps = reinterpret_cast<T*>(smem_raw + Lay.off_p);
-  double* yn = reinterpret_cast<double*>(smem_raw + Lay.off_y);
-  double* tn = reinterpret_cast<double*>(smem_raw + Lay.off_t);
-  const int ldl = Lay.ldl, ldp = Lay.ldp, ldv = RC + 1;
-  const T* Lig = A.Li + A.u_off[i];
+  double* yn = reinterpret_cast<double*>(smem_raw);   // n x RC
+  double* tn = yn + (size_t)nmax * RC;                 // n x RC
+  const T* Li = A.Li + A.u_off[i];
   const T* D = A.arena + A.slot_off[i];
   double* yi = y + A.dof_off[i] * nrhs;
-  for (int e = threadIdx.x; e < n * n; e += NT) Ls[(e / n) * ldl + e % n] = Lig[e];
+  const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int kc = min(RC, nrhs - k0);
     __syncthreads();
-    for (int e = threadIdx.x; e < n * kc; e += NT) yn[(e / kc) * ldv + e % kc] = yi[(r + e / kc) * nrhs + k0 + e % kc];
+    load_vec_tile(yn, yi, r, n, nrhs, k0, kc);
     __syncthreads();
-    for (int e = threadIdx.x; e < n * kc; e += NT) {
-      const int row = e / kc, k = e % kc;
-      double s = 0;
-      for (int c = 0; c <= row; ++c) s += (double)Ls[row * ldl + c] * yn[c * ldv + k];
-      tn[row * ldv + k] = s;
-      yi[(r + row) * nrhs + k0 + k] = s;
+    for (int row0 = 0; row0 < n; row0 += 64) {
+      const int row = row0 + rl;
+      double s[RC];
+#pragma unroll
+      for (int k = 0; k < RC; ++k) s[k] = 0.0;
+      if (row < n)
+        for (int c = q; c <= row; c += 4) axpy16(s, (double)Li[(int64_t)row * n + c], yn + c * RC);
+      quad_sum16(s);
+      if (row < n) {
+#pragma unroll
+        for (int k = 4 * q; k < 4 * q + 4; ++k) {
+          tn[row * RC + k] = s[k];
+          if (k < kc) yi[(int64_t)(r + row) * nrhs + k0 + k] = s[k];
+        }
+      }
     }
-    // panels: v = -1 is the basis of i (columns 0..r-1 of rows n of the diagonal block)
+    __syncthreads();
     for (int v = -1; v < st.nclose; ++v) {
       const T* P;
       int trans, bx, lc;
@@ -261,24 +255,31 @@ __global__ __launch_bounds__(NT) void k_ap_fwd(ApplyArgs<T> A, int32_t s0, doubl
         trans = vw.trans;
         yx = y + A.dof_off[vw.x] * nrhs;
       }
-      for (int g0 = 0; g0 < lc; g0 += PT) {
-        const int tc = min(PT, lc - g0);
-        __syncthreads();
-        stage_panel(Ps, ldp, P, trans, b, bx, r, n, g0, tc);
-        __syncthreads();
-        for (int e = threadIdx.x; e < tc * kc; e += NT) {
-          const int g = e / kc, k = e % kc;
-          double s = 0;
-          for (int t = 0; t < n; ++t) s += (double)Ps[t * ldp + g] * tn[t * ldv + k];
-          yx[(g0 + g) * nrhs + k0 + k] -= s;
+      for (int g0 = 0; g0 < lc; g0 += 64) {
+        const int g = g0 + rl;
+        double s[RC];
+#pragma unroll
+        for (int k = 0; k < RC; ++k) s[k] = 0.0;
+        if (g < lc) {
+          if (trans)
+            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)g * b + r + t], tn + t * RC);
+          else
+            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g], tn + t * RC);
         }
+        quad_sum16(s);
+        if (g < lc)
+#pragma unroll
+          for (int k = 4 * q; k < 4 * q + 4; ++k)
+            if (k < kc) yx[(int64_t)g * nrhs + k0 + k] -= s[k];
       }
     }
   }
 }
 
+// Backward block solve of one step: t = y_i[n] - sum_c L(c, n)^T z_c over the
+// basis of i and the close blocks, then y_i[n] = L_nn^{-T} t.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_ap_bwd(ApplyArgs<T> A, int32_t s0, double* y, int bmax) {
+__global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax) {
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -286,21 +287,17 @@ __global__ __launch_bounds__(NT) void k_ap_bwd(ApplyArgs<T> A, int32_t s0, doubl
   const int n = b - r;
   if (n <= 0) return;
   const int nrhs = A.nrhs;
-  const ApLds Lay = ap_layout<T>(bmax);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Ls = reinterpret_cast<T*>(smem_raw + Lay.off_l);
-  T* Ps = reinterpret_cast<T*>(smem_raw + Lay.off_p);
-  double* tn = reinterpret_cast<double*>(smem_raw + Lay.off_t);
-  double* zt = reinterpret_cast<double*>(smem_raw + Lay.off_z);
-  const int ldl = Lay.ldl, ldp = Lay.ldp, ldv = RC + 1;
-  const T* Lig = A.Li + A.u_off[i];
+  double* tn = reinterpret_cast<double*>(smem_raw);   // n x RC
+  double* zt = tn + (size_t)nmax * RC;                 // 64 x RC
+  const T* Li = A.Li + A.u_off[i];
   const T* D = A.arena + A.slot_off[i];
   double* yi = y + A.dof_off[i] * nrhs;
-  for (int e = threadIdx.x; e < n * n; e += NT) Ls[(e / n) * ldl + e % n] = Lig[e];
+  const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int kc = min(RC, nrhs - k0);
     __syncthreads();
-    for (int e = threadIdx.x; e < n * kc; e += NT) tn[(e / kc) * ldv + e % kc] = yi[(r + e / kc) * nrhs + k0 + e % kc];
+    load_vec_tile(tn, yi, r, n, nrhs, k0, kc);
     for (int v = -1; v < st.nclose; ++v) {
       const T* P;
       int trans, bx, lc;
@@ -319,26 +316,42 @@ __global__ __launch_bounds__(NT) void k_ap_bwd(ApplyArgs<T> A, int32_t s0, doubl
         trans = vw.trans;
         zx = y + A.dof_off[vw.x] * nrhs;
       }
-      for (int g0 = 0; g0 < lc; g0 += PT) {
-        const int tc = min(PT, lc - g0);
+      for (int g0 = 0; g0 < lc; g0 += 64) {
+        const int gc = min(64, lc - g0);
         __syncthreads();
-        stage_panel(Ps, ldp, P, trans, b, bx, r, n, g0, tc);
-        for (int e = threadIdx.x; e < tc * kc; e += NT) zt[(e / kc) * ldv + e % kc] = zx[(g0 + e / kc) * nrhs + k0 + e % kc];
+        load_vec_tile(zt, zx, g0, gc, nrhs, k0, kc);
         __syncthreads();
-        for (int e = threadIdx.x; e < n * kc; e += NT) {
-          const int t = e / kc, k = e % kc;
-          double s = 0;
-          for (int g = 0; g < tc; ++g) s += (double)Ps[t * ldp + g] * zt[g * ldv + k];
-          tn[t * ldv + k] -= s;
+        for (int t0 = 0; t0 < n; t0 += 64) {
+          const int t = t0 + rl;
+          double s[RC];
+#pragma unroll
+          for (int k = 0; k < RC; ++k) s[k] = 0.0;
+          if (t < n) {
+            if (trans)
+              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(g0 + g) * b + r + t], zt + g * RC);
+            else
+              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g0 + g], zt + g * RC);
+          }
+          quad_sum16(s);
+          if (t < n)
+#pragma unroll
+            for (int k = 4 * q; k < 4 * q + 4; ++k) tn[t * RC + k] -= s[k];
         }
       }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n * kc; e += NT) {
-      const int c = e / kc, k = e % kc;
-      double s = 0;
-      for (int row = c; row < n; ++row) s += (double)Ls[row * ldl + c] * tn[row * ldv + k];
-      yi[(r + c) * nrhs + k0 + k] = s;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int c = c0 + rl;
+      double s[RC];
+#pragma unroll
+      for (int k = 0; k < RC; ++k) s[k] = 0.0;
+      if (c < n)
+        for (int row = c + q; row < n; row += 4) axpy16(s, (double)Li[(int64_t)row * n + c], tn + row * RC);
+      quad_sum16(s);
+      if (c < n)
+#pragma unroll
+        for (int k = 4 * q; k < 4 * q + 4; ++k)
+          if (k < kc) yi[(int64_t)(r + c) * nrhs + k0 + k] = s[k];
     }
   }
 }
@@ -429,36 +442,41 @@ __global__ void k_to_next(const int64_t* dof_off, const int32_t* rank, const int
   }
 }
 
-// out = sign * A y, A dense row-major dim x dim, y/out dim x nrhs.
-constexpr int MV = 64;
+// out = sign * A y, A dense row-major dim x dim, y/out dim x nrhs: eight rows
+// per workgroup, 32 threads per row each summing every 32nd column for 16
+// right-hand sides, then a shuffle reduction over the 32.
+constexpr int MV_ROWS = 8;
 __global__ __launch_bounds__(NT) void k_dense_mv(const double* A, int64_t dim, int32_t nrhs, const double* y,
                                                  double* out, double sign) {
-  __shared__ double As[MV][MV + 1];
-  __shared__ double Ys[MV][RC + 1];
-  const int64_t i0 = (int64_t)blockIdx.x * MV;
-  const int ti = (int)min<int64_t>(MV, dim - i0);
+  const int rl = threadIdx.x >> 5, part = threadIdx.x & 31;
+  const int64_t row = (int64_t)blockIdx.x * MV_ROWS + rl;
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int kc = min(RC, nrhs - k0);
-    double acc[4] = {0, 0, 0, 0};   // outputs e = threadIdx.x + q*NT, q < 4 (64 x 16 tile)
-    for (int64_t j0 = 0; j0 < dim; j0 += MV) {
-      const int tj = (int)min<int64_t>(MV, dim - j0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < ti * tj; e += NT) As[e / tj][e % tj] = A[(i0 + e / tj) * dim + j0 + e % tj];
-      for (int e = threadIdx.x; e < tj * kc; e += NT) Ys[e / kc][e % kc] = y[(j0 + e / kc) * nrhs + k0 + e % kc];
-      __syncthreads();
-      for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + q * NT;
-        if (e < ti * kc) {
-          const int a = e / kc, c = e % kc;
-          double s = 0;
-          for (int j = 0; j < tj; ++j) s += As[a][j] * Ys[j][c];
-          acc[q] += s;
+    double s[RC];
+#pragma unroll
+    for (int k = 0; k < RC; ++k) s[k] = 0.0;
+    if (row < dim) {
+      const double* Ar = A + row * dim;
+      for (int64_t j = part; j < dim; j += 32) {
+        const double a = Ar[j];
+        const double* yj = y + j * nrhs + k0;
+        if (kc == RC) {
+#pragma unroll
+          for (int k = 0; k < RC; ++k) s[k] += a * yj[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < RC; ++k)
+            if (k < kc) s[k] += a * yj[k];
         }
       }
     }
-    for (int q = 0; q < 4; ++q) {
-      const int e = threadIdx.x + q * NT;
-      if (e < ti * kc) out[(i0 + e / kc) * nrhs + k0 + e % kc] = sign * acc[q];
+#pragma unroll
+    for (int k = 0; k < RC; ++k)
+      for (int o = 1; o < 32; o <<= 1) s[k] += __shfl_xor(s[k], o, 64);
+    if (row < dim) {
+#pragma unroll
+      for (int k = 0; k < RC; ++k)
+        if (part == k && k < kc) out[row * nrhs + k0 + k] = sign * s[k];
     }
   }
 }
@@ -574,14 +592,14 @@ static unsigned grid1(int64_t work) {
 template <typename T>
 void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir, int bmax, hipStream_t stream) {
   if (nsteps <= 0) return;
-  hipLaunchKernelGGL(k_ap_rotate<T>, dim3(nsteps), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A, y, dir);
+  hipLaunchKernelGGL(k_ap_rot2<T>, dim3(nsteps), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A, y, dir);
 }
 template <typename T>
 void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
   if (s1 <= s0) return;
-  const size_t lds = ap_layout<T>(bmax).total;
+  const size_t lds = (size_t)2 * bmax * RC * sizeof(double);
   if (lds <= max_lds_bytes())
-    hipLaunchKernelGGL(k_ap_fwd<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
+    hipLaunchKernelGGL(k_ap_fwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
   else
     hipLaunchKernelGGL(k_ap_fwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
                        s0, y);
@@ -589,9 +607,9 @@ void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int
 template <typename T>
 void launch_ap_bwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
   if (s1 <= s0) return;
-  const size_t lds = ap_layout<T>(bmax).total;
+  const size_t lds = (size_t)(bmax + 64) * RC * sizeof(double);
   if (lds <= max_lds_bytes())
-    hipLaunchKernelGGL(k_ap_bwd<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
+    hipLaunchKernelGGL(k_ap_bwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
   else
     hipLaunchKernelGGL(k_ap_bwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
                        s0, y);
@@ -619,13 +637,13 @@ void launch_to_next(int32_t M, const int64_t* dof_off, const int32_t* rank, cons
 void launch_coarse_apply(const double* Aneg_inv, int64_t dim, int32_t nrhs, const double* y, double* out,
                          hipStream_t stream) {
   if (dim <= 0) return;
-  hipLaunchKernelGGL(k_dense_mv, dim3((unsigned)((dim + MV - 1) / MV)), dim3(NT), 0, stream, Aneg_inv, dim, nrhs, y,
+  hipLaunchKernelGGL(k_dense_mv, dim3((unsigned)((dim + MV_ROWS - 1) / MV_ROWS)), dim3(NT), 0, stream, Aneg_inv, dim, nrhs, y,
                      out, -1.0);
 }
 void launch_coarse_mul(const double* Ad, int64_t dim, int32_t nrhs, const double* y, double* out,
                        hipStream_t stream) {
   if (dim <= 0) return;
-  hipLaunchKernelGGL(k_dense_mv, dim3((unsigned)((dim + MV - 1) / MV)), dim3(NT), 0, stream, Ad, dim, nrhs, y, out,
+  hipLaunchKernelGGL(k_dense_mv, dim3((unsigned)((dim + MV_ROWS - 1) / MV_ROWS)), dim3(NT), 0, stream, Ad, dim, nrhs, y, out,
                      1.0);
 }
 

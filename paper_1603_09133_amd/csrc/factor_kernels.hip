@@ -1197,6 +1197,7 @@ __global__ __launch_bounds__(NT) void k_potrf(LevelArgs<T> A, int32_t s0, T* gsc
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
+  if (A.small_by_wave && b <= A.small_by_wave) return;
   const int r = A.rank[i];
   const int n = b - r;
   const int tid = threadIdx.x;
@@ -1466,6 +1467,116 @@ __device__ inline void acc_to_lds(const T acc[4][4], T* S) {
 template <typename T>
 size_t work_tiled() {
   return (size_t)2 * 64 * TLD;
+}
+
+// Elimination of S_i for n_i <= 64: Cholesky S = L L^T and L^{-1} with one
+// barrier per column each (the scaling of column k and the final write of row
+// k of the inverse are deferred to the next column, which no longer reads
+// them), then L(basis, n)^T = L^{-1} D[n, basis] as a tiled product.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* S = reinterpret_cast<T*>(smem_raw);   // n x n, lower part used
+  T* X = S + 64 * TLD;                      // L^{-1}
+  __shared__ int bad;
+  T* D = A.arena + A.slot_off[i];
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < n * n; e += NT) {
+    const int j = e / n, c = e % n;
+    S[j * TLD + c] = D[(int64_t)(r + j) * b + r + c];
+    X[j * TLD + c] = j == c ? T(1) : T(0);
+  }
+  __syncthreads();
+  // right-looking Cholesky on the unscaled column k: S_jl -= S_jk S_lk / S_kk
+  for (int k = 0; k < n; ++k) {
+    const T p = S[k * TLD + k];
+    if (k > 0) {
+      const T dprev = sqrt(S[(k - 1) * TLD + (k - 1)]);
+      for (int j = k + tid; j < n; j += NT) S[j * TLD + (k - 1)] /= dprev;
+    }
+    if (p > T(0)) {
+      const T ip = T(1) / p;
+      for (int j = k + 1 + ty; j < n; j += 16) {
+        const T f = S[j * TLD + k] * ip;
+        for (int l = k + 1 + tx; l <= j; l += 16) S[j * TLD + l] -= f * S[l * TLD + k];
+      }
+    } else if (tid == 0) {
+      bad = 1;
+    }
+    __syncthreads();
+  }
+  // columns 0..n-2 are scaled (column n-1 has nothing below the diagonal);
+  // the diagonal still holds the pivots p_k, and L_kk = sqrt(p_k)
+  for (int k = tid; k < n; k += NT) S[k * TLD + k] = sqrt(fmax(S[k * TLD + k], T(0)));
+  __syncthreads();
+  // X <- L^{-1}: forward substitution, row k final in the next step
+  for (int k = 0; k < n; ++k) {
+    const T lkk = S[k * TLD + k];
+    if (k > 0) {
+      const T lp = S[(k - 1) * TLD + (k - 1)];
+      for (int c = tid; c < k; c += NT) X[(k - 1) * TLD + c] /= lp;
+    }
+    for (int j = k + 1 + ty; j < n; j += 16) {
+      const T f = S[j * TLD + k] / lkk;
+      for (int c = tx; c <= k; c += 16) X[j * TLD + c] -= f * X[k * TLD + c];
+    }
+    __syncthreads();
+  }
+  {
+    const T lp = S[(n - 1) * TLD + (n - 1)];
+    for (int c = tid; c < n; c += NT) X[(n - 1) * TLD + c] /= lp;
+  }
+  __syncthreads();
+  // store L (lower, zero above) and L^{-1}
+  T* Lig = A.Li + A.u_off[i];
+  for (int e = tid; e < n * n; e += NT) {
+    const int j = e / n, c = e % n;
+    D[(int64_t)(r + j) * b + r + c] = c <= j ? S[j * TLD + c] : T(0);
+    Lig[e] = c <= j ? X[j * TLD + c] : T(0);
+  }
+  if (tid == 0) {
+    double mp = 1e300;
+    for (int k = 0; k < n; ++k) mp = fmin(mp, (double)S[k * TLD + k]);
+    A.minpiv[i] = mp;
+    if (bad) {
+      if (atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
+    }
+  }
+  if (r == 0) return;
+  // L(basis, n)^T = L^{-1} D[n, 0:r]: A operand L^{-T} (S <- X^T), B operand D[n, 0:r]
+  __syncthreads();
+  for (int e = tid; e < n * n; e += NT) {
+    const int j = e / n, c = e % n;
+    S[c * TLD + j] = c <= j ? X[j * TLD + c] : T(0);
+  }
+  __syncthreads();
+  for (int e = tid; e < n * r; e += NT) {
+    const int j = e / r, c = e % r;
+    X[j * TLD + c] = D[(int64_t)(r + j) * b + c];
+  }
+  __syncthreads();
+  T acc[4][4];
+  zero_acc(acc);
+  gemm_tn_4x4(S, X, n, acc);
+#pragma unroll
+  for (int pq = 0; pq < 4; ++pq) {
+    const int j = 4 * ty + pq;
+    if (j < n)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 4 * tx + q;
+        if (c < r) D[(int64_t)(r + j) * b + c] = acc[pq][q];
+      }
+  }
+  for (int e = tid; e < r * n; e += NT) D[(int64_t)(e / n) * b + r + e % n] = T(0);
 }
 
 // V_ix <- U_i^T V_ix (far views keep rows 0..r_i-1), D_i <- U_i^T D_i U_i.
@@ -1896,7 +2007,9 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   if (tiled && w.r1 > w.r0)
     hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
   if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
-  launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
+  if (tiled && w.s1 > w.s0)
+    hipLaunchKernelGGL(k_potrf_t<T>, dim3(w.s1 - w.s0), dim3(NT), wt, stream, B, w.s0);
+  if (generic) launch<T>(k_potrf<T>, B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
   B.items = A.trsm;
   if (tiled && w.t1 > w.t0)
     hipLaunchKernelGGL(k_trsm_t<T>, dim3(w.t1 - w.t0), dim3(NT), wt, stream, B, w.t0);
