@@ -14,7 +14,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -43,6 +45,63 @@ struct HipError {
     if (e_ != hipSuccess) throw HipError{e_, #call};         \
   } while (0)
 
+// Device blocks are cached instead of freed: a factorization allocates its
+// level arenas, bases and vectors again every time it runs, and hipMalloc /
+// hipFree of hundreds of MB cost milliseconds and synchronise the device.  A
+// released block is kept with the stream it was last used on; a later request
+// on another stream first waits for that stream.  When hipMalloc fails the
+// cache is emptied and the allocation retried.
+thread_local hipStream_t g_cur_stream = nullptr;
+
+struct BlockCache {
+  struct Blk {
+    void* p;
+    hipStream_t s;
+  };
+  std::mutex mu;
+  std::multimap<size_t, Blk> free_blocks;
+  size_t cached = 0;
+
+  void* get(size_t& bytes) {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      auto it = free_blocks.lower_bound(bytes);
+      if (it != free_blocks.end() && it->first <= 2 * bytes + (1u << 20)) {
+        Blk b = it->second;
+        bytes = it->first;
+        cached -= it->first;
+        free_blocks.erase(it);
+        if (b.s != g_cur_stream) (void)hipStreamSynchronize(b.s);
+        return b.p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      HIPCHK(hipMalloc(&p, bytes));
+    }
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    free_blocks.emplace(bytes, Blk{p, g_cur_stream});
+    cached += bytes;
+  }
+  void trim() {
+    std::lock_guard<std::mutex> g(mu);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : free_blocks) (void)hipFree(kv.second.p);
+    free_blocks.clear();
+    cached = 0;
+  }
+};
+
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();   // lives until the process ends
+  return *c;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -65,7 +124,7 @@ struct DevBuf {
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) block_cache().put(p, bytes);
     p = nullptr;
     bytes = 0;
   }
@@ -73,7 +132,7 @@ struct DevBuf {
     if (b <= bytes && p) return;
     release();
     if (b == 0) b = 8;
-    HIPCHK(hipMalloc(&p, b));
+    p = block_cache().get(b);
     bytes = b;
   }
   template <typename U>
@@ -688,6 +747,7 @@ int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const 
     h->opt = o;
     h->precision = o.precision;
     h->stream = (hipStream_t)o.stream;
+    g_cur_stream = h->stream;
     int rc = o.precision == CAE_FP32 ? factor_numeric<float>(h.get(), vals, eps)
                                      : factor_numeric<double>(h.get(), vals, eps);
     if (rc != CAE_OK) {
@@ -704,6 +764,7 @@ int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const 
 }
 
 int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+  if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
   const int64_t n = h->an->a.n;
   if (nrhs <= 0 || !r || !z || ldr < n || ldz < n) return fail(CAE_EINVAL, "bad vector arguments");
@@ -717,6 +778,7 @@ int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr
 }
 
 int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
+  if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
   const int64_t n = h->an->a.n;
   if (nrhs <= 0 || !x || !y || ldx < n || ldy < n) return fail(CAE_EINVAL, "bad vector arguments");
@@ -734,6 +796,7 @@ int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx,
 
 int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
                   int32_t maxit, int32_t* iters, double* relres) {
+  if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
   const int64_t n = h->an->a.n;
   if (nrhs <= 0 || !b || !x || ldb < n || ldx < n || !iters || !relres || maxit < 0 || !(rtol >= 0))
@@ -853,6 +916,7 @@ int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes) {
 }
 
 void cae_destroy(cae_handle_t h) {
+  if (h) g_cur_stream = h->stream;
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   delete h;
