@@ -653,6 +653,190 @@ __global__ __launch_bounds__(WV) void k_compress_wave(LevelArgs<T> A, int32_t s0
   }
 }
 
+// Phases shared by the cooperative compression kernels: one-sided Jacobi on
+// the ma rows of X (their Gram matrix is F_i F_i^T, up to the coordinate
+// permutation piv, or none), singular values, rank, ||E_i||_F^2, and the
+// orthonormal completion of the kept directions into U_i (Householder), all
+// in the compute type CT; U_i is written in the factor type T.
+template <typename CT, typename T>
+__device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT* X, CT* R, int LD, const int* piv,
+                                double inactive, CT negl, CT aerr, CT* sg, CT* tau, int* posv, int* shi, double* shd,
+                                T* Ug, int wtot, int64_t t_start, int64_t t_qr, int64_t t_cmp) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // ---- 3. one-sided Jacobi on the ma rows of X ------------------------------
+  const int mm = ma + (ma & 1);
+  const CT tol = CT(max(b, 16)) * Eps<CT>::v();
+  const int LP = (mm / 2 <= 16) ? 16 : 8;   // lanes per pair (power of two, divides 64)
+  const int pp = tid / LP, sub = tid % LP;
+  int nsweep = 0;
+  for (int sweep = 0; sweep < 40 && ma > 1; ++sweep) {
+    ++nsweep;
+    int rotated = 0;
+    for (int rho = 0; rho < mm - 1; ++rho) {
+      int p = -1, q = -1;
+      if (pp < mm / 2) {
+        if (pp == 0) {
+          p = mm - 1;
+          q = rho;
+        } else {
+          p = (rho + pp) % (mm - 1);
+          q = (rho - pp + (mm - 1)) % (mm - 1);
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q >= ma) p = -1;
+      }
+      CT a = 0, cc = 0, d = 0;
+      if (p >= 0) {
+        for (int t = sub; t < b; t += LP) {
+          const CT x = X[p * LD + t], y = X[q * LD + t];
+          a += x * x;
+          cc += y * y;
+          d += x * y;
+        }
+      }
+      for (int o = 1; o < LP; o <<= 1) {
+        a += __shfl_xor(a, o, WV);
+        cc += __shfl_xor(cc, o, WV);
+        d += __shfl_xor(d, o, WV);
+      }
+      if (p >= 0) {
+        const CT na = sqrt(a), nc = sqrt(cc);
+        if (d != CT(0) && fabs(d) > tol * na * nc && (na > negl || nc > negl) &&
+            fabs(d) > aerr * max(na, nc)) {
+          const CT zeta = (cc - a) / (CT(2) * d);
+          CT tt;
+          if (fabs(zeta) > CT(1e15))
+            tt = CT(0.5) / zeta;
+          else
+            tt = (zeta >= CT(0) ? CT(1) : CT(-1)) / (fabs(zeta) + sqrt(CT(1) + zeta * zeta));
+          const CT cs = CT(1) / sqrt(CT(1) + tt * tt), sn = cs * tt;
+          for (int t = sub; t < b; t += LP) {
+            const CT x = X[p * LD + t], y = X[q * LD + t];
+            X[p * LD + t] = cs * x - sn * y;
+            X[q * LD + t] = sn * x + cs * y;
+          }
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  const int64_t t_jac = clock64();
+
+  // ---- singular values, order, rank -----------------------------------------
+  if (wv == 0) {
+    CT s2 = 0;
+    if (lane < ma)
+      for (int t = 0; t < b; ++t) s2 += X[lane * LD + t] * X[lane * LD + t];
+    if (lane < ma) sg[lane] = sqrt(s2);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    int pos = 0;
+    if (lane < ma) {
+      const CT sp = sg[lane];
+      for (int q = 0; q < ma; ++q) pos += (sg[q] > sp || (sg[q] == sp && q < lane)) ? 1 : 0;
+      posv[lane] = pos;
+    }
+    const double theta = *A.theta;
+    const int cnt = __popcll(__ballot(lane < ma && (double)sg[lane] > theta));
+    const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
+    const double ed = wave_sum((lane < ma && pos >= r) ? (double)sg[lane] * (double)sg[lane] : 0.0);
+    if (lane == 0) {
+      shi[1] = r;
+      shd[2] = ed + inactive;
+    }
+  }
+  __syncthreads();
+  const int r = shi[1];
+  const int kb = min(r, ma);
+
+  // ---- 4. orthonormal completion ----------------------------------------------
+  CT* Bv = R;   // R is free: the kept directions, then the reflectors
+  for (int e = tid; e < ma * 64; e += NT) {
+    const int p = e >> 6, t = e & 63;
+    const int c2 = posv[p];
+    if (c2 < kb) {
+      const CT inv = sg[p] > CT(0) ? CT(1) / sg[p] : CT(0);
+      if (t < b)
+        Bv[c2 * LD + (piv ? piv[t] : t)] = X[p * LD + t] * inv;
+      else
+        Bv[c2 * LD + t] = CT(0);
+    }
+  }
+  __syncthreads();
+  for (int cv = 0; cv < kb; ++cv) {
+    if (wv == 0) {
+      const CT x = (lane >= cv && lane < b) ? Bv[cv * LD + lane] : CT(0);
+      const CT nrm2 = wave_sum(x * x);
+      const CT x0 = Bv[cv * LD + cv];
+      const CT nrm = sqrt(nrm2);
+      const CT alpha = x0 >= CT(0) ? -nrm : nrm;
+      const CT v0 = x0 - alpha;
+      const CT vv = v0 * v0 + (nrm2 - x0 * x0);
+      if (lane < cv) Bv[cv * LD + lane] = CT(0);
+      if (lane == cv) {
+        Bv[cv * LD + cv] = v0;
+        tau[cv] = vv > CT(0) ? CT(2) / vv : CT(0);
+      }
+    }
+    __syncthreads();
+    // apply H_cv to the later vectors: 16 lanes per vector
+    {
+      const CT tc = tau[cv];
+      for (int c2 = cv + 1 + tid / 16; c2 - tid / 16 < kb; c2 += NT / 16) {
+        const int sb = tid % 16;
+        CT dd = 0;
+        if (c2 < kb)
+          for (int t = cv + sb; t < b; t += 16) dd += Bv[cv * LD + t] * Bv[c2 * LD + t];
+        for (int o = 1; o < 16; o <<= 1) dd += __shfl_xor(dd, o, WV);
+        if (c2 < kb)
+          for (int t = cv + sb; t < b; t += 16) Bv[c2 * LD + t] -= tc * dd * Bv[cv * LD + t];
+      }
+    }
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{kb-1}: 4 lanes per column
+  CT* Q = X;
+  for (int e = tid; e < 64 * LD; e += NT) Q[e] = (e / LD == e % LD) ? CT(1) : CT(0);
+  __syncthreads();
+  for (int cv = kb - 1; cv >= 0; --cv) {
+    const CT tc = tau[cv];
+    const int col = tid >> 2, sb = tid & 3;
+    CT dd = 0;
+    for (int t = cv + sb; t < b; t += 4) dd += Bv[cv * LD + t] * Q[t * LD + col];
+    dd += __shfl_xor(dd, 1, WV);
+    dd += __shfl_xor(dd, 2, WV);
+    for (int t = cv + sb; t < b; t += 4) Q[t * LD + col] -= tc * dd * Bv[cv * LD + t];
+    __syncthreads();
+  }
+  for (int e = tid; e < b * b; e += NT) Ug[e] = (T)Q[(e / b) * LD + e % b];
+  if (A.dbg && tid < ma && tid < 64) {
+    double* sv = reinterpret_cast<double*>(A.dbg + 72 * (int64_t)i + 8);
+    sv[tid] = (double)sg[tid];
+  }
+  if (tid == 0) {
+    A.rank[i] = r;
+    A.edrop[i] = shd[2];
+    if (A.dbg) {
+      int64_t* dd = A.dbg + 72 * (int64_t)i;
+      dd[0] = ma;
+      dd[1] = nsweep;
+      dd[2] = wtot;
+      dd[3] = b;
+      dd[4] = t_qr - t_start;
+      dd[5] = t_cmp - t_qr;
+      dd[6] = t_jac - t_cmp;
+      dd[7] = clock64() - t_jac;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Compression by one 256-thread workgroup per step (b <= 64): the same four
 // phases as k_compress_wave, with the four wavefronts cooperating so that a
@@ -906,178 +1090,8 @@ __global__ __launch_bounds__(NT) void k_compress_wg(LevelArgs<T> A, int32_t s0) 
   __syncthreads();
   const int64_t t_cmp = clock64();
 
-  // ---- 3. one-sided Jacobi on the ma rows of X ------------------------------
-  const int mm = ma + (ma & 1);
-  const T tol = T(max(b, 16)) * Eps<T>::v();
-  const int LP = (mm / 2 <= 16) ? 16 : 8;   // lanes per pair (power of two, divides 64)
-  const int pp = tid / LP, sub = tid % LP;
-  int nsweep = 0;
-  for (int sweep = 0; sweep < 40 && ma > 1; ++sweep) {
-    ++nsweep;
-    int rotated = 0;
-    for (int rho = 0; rho < mm - 1; ++rho) {
-      int p = -1, q = -1;
-      if (pp < mm / 2) {
-        if (pp == 0) {
-          p = mm - 1;
-          q = rho;
-        } else {
-          p = (rho + pp) % (mm - 1);
-          q = (rho - pp + (mm - 1)) % (mm - 1);
-        }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        if (q >= ma) p = -1;
-      }
-      T a = 0, cc = 0, d = 0;
-      if (p >= 0) {
-        for (int t = sub; t < b; t += LP) {
-          const T x = X[p * LD + t], y = X[q * LD + t];
-          a += x * x;
-          cc += y * y;
-          d += x * y;
-        }
-      }
-      for (int o = 1; o < LP; o <<= 1) {
-        a += __shfl_xor(a, o, WV);
-        cc += __shfl_xor(cc, o, WV);
-        d += __shfl_xor(d, o, WV);
-      }
-      if (p >= 0) {
-        const T na = sqrt(a), nc = sqrt(cc);
-        if (d != T(0) && fabs(d) > tol * na * nc && (na > negl || nc > negl) &&
-            fabs(d) > aerr * max(na, nc)) {
-          const T zeta = (cc - a) / (T(2) * d);
-          T tt;
-          if (fabs(zeta) > T(1e15))
-            tt = T(0.5) / zeta;
-          else
-            tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
-          const T cs = T(1) / sqrt(T(1) + tt * tt), sn = cs * tt;
-          for (int t = sub; t < b; t += LP) {
-            const T x = X[p * LD + t], y = X[q * LD + t];
-            X[p * LD + t] = cs * x - sn * y;
-            X[q * LD + t] = sn * x + cs * y;
-          }
-          rotated = 1;
-        }
-      }
-      __syncthreads();
-    }
-    if (!__syncthreads_or(rotated)) break;
-  }
-  const int64_t t_jac = clock64();
-
-  // ---- singular values, order, rank -----------------------------------------
-  if (wv == 0) {
-    T s2 = 0;
-    if (lane < ma)
-      for (int t = 0; t < b; ++t) s2 += X[lane * LD + t] * X[lane * LD + t];
-    if (lane < ma) sg[lane] = sqrt(s2);
-  }
-  __syncthreads();
-  if (wv == 0) {
-    int pos = 0;
-    if (lane < ma) {
-      const T sp = sg[lane];
-      for (int q = 0; q < ma; ++q) pos += (sg[q] > sp || (sg[q] == sp && q < lane)) ? 1 : 0;
-      posv[lane] = pos;
-    }
-    const double theta = *A.theta;
-    const int cnt = __popcll(__ballot(lane < ma && (double)sg[lane] > theta));
-    const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
-    const double ed = wave_sum((lane < ma && pos >= r) ? (double)sg[lane] * (double)sg[lane] : 0.0);
-    if (lane == 0) {
-      shi[1] = r;
-      shd[2] = ed + inactive;
-    }
-  }
-  __syncthreads();
-  const int r = shi[1];
-  const int kb = min(r, ma);
-
-  // ---- 4. orthonormal completion ----------------------------------------------
-  T* Bv = R;
-  for (int e = tid; e < ma * 64; e += NT) {
-    const int p = e >> 6, t = e & 63;
-    const int c2 = posv[p];
-    if (c2 < kb) {
-      const T inv = sg[p] > T(0) ? T(1) / sg[p] : T(0);
-      if (t < b)
-        Bv[c2 * LD + piv[t]] = X[p * LD + t] * inv;
-      else
-        Bv[c2 * LD + t] = T(0);
-    }
-  }
-  __syncthreads();
-  for (int cv = 0; cv < kb; ++cv) {
-    if (wv == 0) {
-      const T x = (lane >= cv && lane < b) ? Bv[cv * LD + lane] : T(0);
-      const T nrm2 = wave_sum(x * x);
-      const T x0 = Bv[cv * LD + cv];
-      const T nrm = sqrt(nrm2);
-      const T alpha = x0 >= T(0) ? -nrm : nrm;
-      const T v0 = x0 - alpha;
-      const T vv = v0 * v0 + (nrm2 - x0 * x0);
-      if (lane < cv) Bv[cv * LD + lane] = T(0);
-      if (lane == cv) {
-        Bv[cv * LD + cv] = v0;
-        tau[cv] = vv > T(0) ? T(2) / vv : T(0);
-      }
-    }
-    __syncthreads();
-    // apply H_cv to the later vectors: 16 lanes per vector
-    {
-      const T tc = tau[cv];
-      for (int c2 = cv + 1 + tid / 16; c2 - tid / 16 < kb; c2 += NT / 16) {
-        const int sb = tid % 16;
-        T dd = 0;
-        if (c2 < kb)
-          for (int t = cv + sb; t < b; t += 16) dd += Bv[cv * LD + t] * Bv[c2 * LD + t];
-        for (int o = 1; o < 16; o <<= 1) dd += __shfl_xor(dd, o, WV);
-        if (c2 < kb)
-          for (int t = cv + sb; t < b; t += 16) Bv[c2 * LD + t] -= tc * dd * Bv[cv * LD + t];
-      }
-    }
-    __syncthreads();
-  }
-  // Q = H_0 ... H_{kb-1}: 4 lanes per column
-  T* Q = X;
-  for (int e = tid; e < 64 * LD; e += NT) Q[e] = (e / LD == e % LD) ? T(1) : T(0);
-  __syncthreads();
-  for (int cv = kb - 1; cv >= 0; --cv) {
-    const T tc = tau[cv];
-    const int col = tid >> 2, sb = tid & 3;
-    T dd = 0;
-    for (int t = cv + sb; t < b; t += 4) dd += Bv[cv * LD + t] * Q[t * LD + col];
-    dd += __shfl_xor(dd, 1, WV);
-    dd += __shfl_xor(dd, 2, WV);
-    for (int t = cv + sb; t < b; t += 4) Q[t * LD + col] -= tc * dd * Bv[cv * LD + t];
-    __syncthreads();
-  }
-  for (int e = tid; e < b * b; e += NT) Ug[e] = Q[(e / b) * LD + e % b];
-  if (A.dbg && tid < ma && tid < 64) {
-    double* sv = reinterpret_cast<double*>(A.dbg + 72 * (int64_t)i + 8);
-    sv[tid] = (double)sg[tid];
-  }
-  if (tid == 0) {
-    A.rank[i] = r;
-    A.edrop[i] = shd[2];
-    if (A.dbg) {
-      int64_t* dd = A.dbg + 72 * (int64_t)i;
-      dd[0] = ma;
-      dd[1] = nsweep;
-      dd[2] = wtot;
-      dd[3] = b;
-      dd[4] = t_qr - t_start;
-      dd[5] = t_cmp - t_qr;
-      dd[6] = t_jac - t_cmp;
-      dd[7] = clock64() - t_jac;
-    }
-  }
+  jacobi_basis_wg<T, T>(A, i, b, ma, X, R, LD, piv, inactive, negl, aerr, sg, tau, posv, shi, shd, Ug, wtot, t_start,
+                        t_qr, t_cmp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1394,18 +1408,18 @@ __global__ __launch_bounds__(NT) void k_schur(LevelArgs<T> A, int32_t p0, T* gsc
 // ---------------------------------------------------------------------------
 constexpr int TLD = 68;
 
-template <typename T>
-__device__ inline void gemm_tn_4x4(const T* A, const T* B, int K, T acc[4][4]) {
+template <typename TI, typename TA>
+__device__ inline void gemm_tn_4x4(const TI* A, const TI* B, int K, TA acc[4][4]) {
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  const T* a = A + 4 * ty;
-  const T* bb = B + 4 * tx;
+  const TI* a = A + 4 * ty;
+  const TI* bb = B + 4 * tx;
 #pragma unroll 2
   for (int k = 0; k < K; ++k) {
-    T av[4], bv[4];
+    TA av[4], bv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      av[q] = a[k * TLD + q];
-      bv[q] = bb[k * TLD + q];
+      av[q] = (TA)a[k * TLD + q];
+      bv[q] = (TA)bb[k * TLD + q];
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p)
@@ -1413,6 +1427,14 @@ __device__ inline void gemm_tn_4x4(const T* A, const T* B, int K, T acc[4][4]) {
       for (int q = 0; q < 4; ++q) acc[p][q] += av[p] * bv[q];
   }
 }
+
+// accumulator type of the tiled products: FP64 for every factor precision
+// (products of FP32 entries are exact in FP64, so an FP32 factor takes one
+// rounding per stored entry instead of one per term)
+template <typename T>
+struct AccT {
+  using type = double;
+};
 
 template <typename T>
 __device__ inline void zero_acc(T acc[4][4]) {
@@ -1455,13 +1477,13 @@ __device__ inline void store_view_tile(const T* S, T* base, int trans, int bi, i
   }
 }
 
-template <typename T>
-__device__ inline void acc_to_lds(const T acc[4][4], T* S) {
+template <typename TA, typename T>
+__device__ inline void acc_to_lds(const TA acc[4][4], T* S) {
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) S[(4 * ty + p) * TLD + 4 * tx + q] = acc[p][q];
+    for (int q = 0; q < 4; ++q) S[(4 * ty + p) * TLD + 4 * tx + q] = (T)acc[p][q];
 }
 
 template <typename T>
@@ -1483,29 +1505,30 @@ __global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
   const int n = b - r;
   if (n <= 0) return;
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  using CT = typename AccT<T>::type;       // the diagonal block is factored in FP64
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* S = reinterpret_cast<T*>(smem_raw);   // n x n, lower part used
-  T* X = S + 64 * TLD;                      // L^{-1}
+  CT* S = reinterpret_cast<CT*>(smem_raw);  // n x n, lower part used
+  CT* X = S + 64 * TLD;                     // L^{-1}
   __shared__ int bad;
   T* D = A.arena + A.slot_off[i];
   if (tid == 0) bad = 0;
   for (int e = tid; e < n * n; e += NT) {
     const int j = e / n, c = e % n;
-    S[j * TLD + c] = D[(int64_t)(r + j) * b + r + c];
-    X[j * TLD + c] = j == c ? T(1) : T(0);
+    S[j * TLD + c] = (CT)D[(int64_t)(r + j) * b + r + c];
+    X[j * TLD + c] = j == c ? CT(1) : CT(0);
   }
   __syncthreads();
   // right-looking Cholesky on the unscaled column k: S_jl -= S_jk S_lk / S_kk
   for (int k = 0; k < n; ++k) {
-    const T p = S[k * TLD + k];
+    const CT p = S[k * TLD + k];
     if (k > 0) {
-      const T dprev = sqrt(S[(k - 1) * TLD + (k - 1)]);
+      const CT dprev = sqrt(S[(k - 1) * TLD + (k - 1)]);
       for (int j = k + tid; j < n; j += NT) S[j * TLD + (k - 1)] /= dprev;
     }
-    if (p > T(0)) {
-      const T ip = T(1) / p;
+    if (p > CT(0)) {
+      const CT ip = CT(1) / p;
       for (int j = k + 1 + ty; j < n; j += 16) {
-        const T f = S[j * TLD + k] * ip;
+        const CT f = S[j * TLD + k] * ip;
         for (int l = k + 1 + tx; l <= j; l += 16) S[j * TLD + l] -= f * S[l * TLD + k];
       }
     } else if (tid == 0) {
@@ -1515,23 +1538,23 @@ __global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
   }
   // columns 0..n-2 are scaled (column n-1 has nothing below the diagonal);
   // the diagonal still holds the pivots p_k, and L_kk = sqrt(p_k)
-  for (int k = tid; k < n; k += NT) S[k * TLD + k] = sqrt(fmax(S[k * TLD + k], T(0)));
+  for (int k = tid; k < n; k += NT) S[k * TLD + k] = sqrt(fmax(S[k * TLD + k], CT(0)));
   __syncthreads();
   // X <- L^{-1}: forward substitution, row k final in the next step
   for (int k = 0; k < n; ++k) {
-    const T lkk = S[k * TLD + k];
+    const CT lkk = S[k * TLD + k];
     if (k > 0) {
-      const T lp = S[(k - 1) * TLD + (k - 1)];
+      const CT lp = S[(k - 1) * TLD + (k - 1)];
       for (int c = tid; c < k; c += NT) X[(k - 1) * TLD + c] /= lp;
     }
     for (int j = k + 1 + ty; j < n; j += 16) {
-      const T f = S[j * TLD + k] / lkk;
+      const CT f = S[j * TLD + k] / lkk;
       for (int c = tx; c <= k; c += 16) X[j * TLD + c] -= f * X[k * TLD + c];
     }
     __syncthreads();
   }
   {
-    const T lp = S[(n - 1) * TLD + (n - 1)];
+    const CT lp = S[(n - 1) * TLD + (n - 1)];
     for (int c = tid; c < n; c += NT) X[(n - 1) * TLD + c] /= lp;
   }
   __syncthreads();
@@ -1539,8 +1562,8 @@ __global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
   T* Lig = A.Li + A.u_off[i];
   for (int e = tid; e < n * n; e += NT) {
     const int j = e / n, c = e % n;
-    D[(int64_t)(r + j) * b + r + c] = c <= j ? S[j * TLD + c] : T(0);
-    Lig[e] = c <= j ? X[j * TLD + c] : T(0);
+    D[(int64_t)(r + j) * b + r + c] = c <= j ? (T)S[j * TLD + c] : T(0);
+    Lig[e] = c <= j ? (T)X[j * TLD + c] : T(0);
   }
   if (tid == 0) {
     double mp = 1e300;
@@ -1555,15 +1578,15 @@ __global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
   __syncthreads();
   for (int e = tid; e < n * n; e += NT) {
     const int j = e / n, c = e % n;
-    S[c * TLD + j] = c <= j ? X[j * TLD + c] : T(0);
+    S[c * TLD + j] = c <= j ? X[j * TLD + c] : CT(0);
   }
   __syncthreads();
   for (int e = tid; e < n * r; e += NT) {
     const int j = e / r, c = e % r;
-    X[j * TLD + c] = D[(int64_t)(r + j) * b + c];
+    X[j * TLD + c] = (CT)D[(int64_t)(r + j) * b + c];
   }
   __syncthreads();
-  T acc[4][4];
+  typename AccT<T>::type acc[4][4];
   zero_acc(acc);
   gemm_tn_4x4(S, X, n, acc);
 #pragma unroll
@@ -1573,10 +1596,167 @@ __global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = 4 * tx + q;
-        if (c < r) D[(int64_t)(r + j) * b + c] = acc[pq][q];
+        if (c < r) D[(int64_t)(r + j) * b + c] = (T)acc[pq][q];
       }
   }
   for (int e = tid; e < r * n; e += NT) D[(int64_t)(e / n) * b + r + e % n] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Compression of a reduced-precision factor (b <= 64) through the Gram matrix
+// G = F_i F_i^T accumulated in FP64: products of FP32 entries are exact in
+// FP64, so G carries the far row to FP64 accuracy, and its eigenvalues sigma^2
+// resolve singular values down to about 1e-7 sigma_1, well below the FP32
+// rounding level of F_i itself.  A pivoted Cholesky G = R^T R (pivot = largest
+// remaining diagonal, the Gram form of a column-pivoted QR of F_i^T) gives
+// graded rows R, stopped once the trailing diagonal sum is below the rounding
+// level; the one-sided Jacobi and the completion then run in FP64 on R.
+// Replaces the TSQR, whose b sequential column steps per chunk dominate the
+// latency of a step.
+// ---------------------------------------------------------------------------
+constexpr int GLD = 68;
+
+template <typename T>
+size_t work_compress_gram() {
+  return (size_t)2 * 64 * GLD * sizeof(double) + 4 * 64 * sizeof(double) + 2 * 64 * sizeof(int);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ty = tid >> 4, tx = tid & 15;
+  T* Ug = A.U + A.u_off[i];
+  if (st.nfar == 0 || b == 0) {
+    for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
+    if (tid == 0) {
+      A.rank[i] = 0;
+      A.edrop[i] = 0.0;
+    }
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* G = reinterpret_cast<double*>(smem_raw);   // 64 x GLD Gram matrix, then basis vectors
+  double* X = G + 64 * GLD;                          // 64 x GLD rows of R, then Q
+  T* Ft = reinterpret_cast<T*>(X);                   // 64 x TLD tile of F_i^T (Gram phase only)
+  double* dg = X + 64 * GLD;                         // trailing diagonal
+  double* lc = dg + 64;                              // current Cholesky column
+  double* sg = lc + 64;
+  double* tau = sg + 64;
+  int* posv = reinterpret_cast<int*>(tau + 64);
+  int* chosen = posv + 64;
+  __shared__ double shd[4];
+  __shared__ int shi[4];
+  const int64_t t_start = clock64();
+  int wtot = 0;
+
+  // ---- 1. G = sum over far views V V^T (register tiles, FP64 accumulation) --
+  double acc[4][4];
+  zero_acc(acc);
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    wtot += w;
+    for (int c0 = 0; c0 < w; c0 += 64) {
+      const int mc = min(64, w - c0);
+      __syncthreads();
+      if (v.trans) {
+        for (int e = tid; e < mc * b; e += NT) {
+          const int m = e / b, a = e % b;
+          Ft[m * TLD + a] = base[(int64_t)(c0 + m) * b + a];
+        }
+      } else {
+        for (int e = tid; e < mc * b; e += NT) {
+          const int a = e / mc, m = e % mc;
+          Ft[m * TLD + a] = base[(int64_t)a * bx + c0 + m];
+        }
+      }
+      __syncthreads();
+      gemm_tn_4x4(Ft, Ft, mc, acc);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) G[(4 * ty + p) * GLD + 4 * tx + q] = acc[p][q];
+  __syncthreads();
+  const int64_t t_qr = clock64();
+
+  // ---- 2. pivoted Cholesky G = R^T R, rows of R into X ----------------------
+  if (wv == 0) {
+    const double gd = lane < b ? G[lane * GLD + lane] : 0.0;
+    const double fro2 = wave_sum(gd);
+    dg[lane] = gd;
+    chosen[lane] = 0;
+    if (lane == 0) shd[0] = fro2;
+  }
+  __syncthreads();
+  // rounding level of the factor's own entries (its precision T), as in the
+  // other compression kernels
+  const double noise = (double)Eps<T>::v() * sqrt(shd[0]);
+  const double theta = *A.theta;
+  const double negl = A.rank_mode == 0 ? fmax(noise, theta / 64.0) : noise;
+  const double aerr = A.rank_mode == 0 ? fmax(noise, fmin((double)max(b, 16) * noise, theta / 32.0))
+                                       : (double)max(b, 16) * noise;
+  const double stop2 = aerr * aerr;
+  int k = 0;
+  for (; k < b; ++k) {
+    if (wv == 0) {
+      const bool in = lane < b && !chosen[lane];
+      const double dv = in ? dg[lane] : 0.0;
+      const double rs = wave_sum(dv);
+      double cv = in ? dv : -1.0;
+      int ci = lane;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(cv, o, WV);
+        const int oi = __shfl_xor(ci, o, WV);
+        if (ov > cv || (ov == cv && oi < ci)) {
+          cv = ov;
+          ci = oi;
+        }
+      }
+      const bool stop = rs <= stop2 || !(cv > 0.0);
+      if (lane == 0) {
+        shi[3] = stop ? 1 : 0;
+        shd[1] = rs;
+        if (!stop) {
+          shi[2] = ci;
+          shd[3] = sqrt(cv);
+          chosen[ci] = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (shi[3]) break;
+    const int p = shi[2];
+    const double lpp = shd[3];
+    if (tid < 64) {
+      const int t = tid;
+      const double lv = t >= b ? 0.0 : (t == p ? lpp : (chosen[t] ? 0.0 : G[t * GLD + p] / lpp));
+      lc[t] = lv;
+      X[k * GLD + t] = lv;
+    }
+    __syncthreads();
+    for (int t = ty; t < b; t += 16) {
+      const double lt = lc[t];
+      for (int u = tx; u < b; u += 16) {
+        const double g = G[t * GLD + u] - lt * lc[u];
+        G[t * GLD + u] = g;
+        if (u == t) dg[t] = g;
+      }
+    }
+    __syncthreads();
+  }
+  const int ma = k;
+  const double inactive = k < b ? shd[1] : 0.0;
+  const int64_t t_cmp = clock64();
+  jacobi_basis_wg<double, T>(A, i, b, ma, X, G, GLD, nullptr, inactive, negl, aerr, sg, tau, posv, shi, shd, Ug,
+                             wtot, t_start, t_qr, t_cmp);
 }
 
 // V_ix <- U_i^T V_ix (far views keep rows 0..r_i-1), D_i <- U_i^T D_i U_i.
@@ -1592,7 +1772,7 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
   T* X = Us + 64 * TLD;
   const T* Ug = A.U + A.u_off[i];
   for (int e = threadIdx.x; e < b * b; e += NT) Us[(e / b) * TLD + e % b] = Ug[e];
-  T acc[4][4];
+  typename AccT<T>::type acc[4][4];
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   if (item.view < 0) {
     T* D = A.arena + A.slot_off[i];
@@ -1612,7 +1792,7 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int c = 4 * tx + q;
-          if (c < b) D[a * b + c] = acc[p][q];
+          if (c < b) D[a * b + c] = (T)acc[p][q];
         }
     }
     return;
@@ -1634,7 +1814,7 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
       for (int p = 0; p < 4; ++p)
         if (4 * ty + p >= r)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[p][q] = T(0);
+          for (int q = 0; q < 4; ++q) acc[p][q] = 0;
     }
     __syncthreads();
     acc_to_lds(acc, X);
@@ -1667,7 +1847,7 @@ __global__ __launch_bounds__(NT) void k_trsm_t(LevelArgs<T> A, int32_t it0) {
     Lt[k * TLD + j] = Lig[e];
   }
   T* base = A.arena + A.slot_off[v.slot];
-  T acc[4][4];
+  typename AccT<T>::type acc[4][4];
   for (int c0 = 0; c0 < lc; c0 += 64) {
     const int tc = min(64, lc - c0);
     __syncthreads();
@@ -1744,7 +1924,7 @@ __global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
   T* Pa = reinterpret_cast<T*>(smem_raw);
   T* Pc = Pa + 64 * TLD;
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  T acc[4][4];
+  typename AccT<T>::type acc[4][4];
   for (int a0 = 0; a0 < la; a0 += 64) {
     const int tan = min(64, la - a0);
     __syncthreads();
@@ -1763,7 +1943,10 @@ __global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int gm = 4 * tx + q;
-            if (gm < tcn) tbase[(int64_t)(a0 + al) * ts_a + (int64_t)(c0 + gm) * ts_c] -= acc[p][q];
+            if (gm < tcn) {
+              T* tp = tbase + (int64_t)(a0 + al) * ts_a + (int64_t)(c0 + gm) * ts_c;
+              *tp = (T)((double)*tp - acc[p][q]);
+            }
           }
       }
     }
@@ -1982,7 +2165,11 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
   if (w.s1 > w.s0) {
     const int ns = w.s1 - w.s0;
     const size_t wg = work_compress_wg<T>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
-    hipLaunchKernelGGL(k_compress_wg<T>, dim3(ns), dim3(NT), wg, stream, A, w.s0);
+    const size_t wgr = work_compress_gram<T>();
+    if (sizeof(T) < sizeof(double) && wgr <= max_lds_bytes())
+      hipLaunchKernelGGL(k_compress_gram<T>, dim3(ns), dim3(NT), wgr, stream, A, w.s0);
+    else
+      hipLaunchKernelGGL(k_compress_wg<T>, dim3(ns), dim3(NT), wg, stream, A, w.s0);
     if (bmax > 64) {
       if (bmax <= 128 && w128 <= max_lds_bytes()) {
         hipLaunchKernelGGL((k_compress_wave<T, 128>), dim3(ns), dim3(WV), w128, stream, A, w.s0);
@@ -2007,9 +2194,14 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   if (tiled && w.r1 > w.r0)
     hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
   if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
-  if (tiled && w.s1 > w.s0)
-    hipLaunchKernelGGL(k_potrf_t<T>, dim3(w.s1 - w.s0), dim3(NT), wt, stream, B, w.s0);
-  if (generic) launch<T>(k_potrf<T>, B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
+  const size_t wp = work_tiled<T>() * sizeof(typename AccT<T>::type);
+  const bool ptiled = tiled && wp <= max_lds_bytes();
+  if (ptiled && w.s1 > w.s0)
+    hipLaunchKernelGGL(k_potrf_t<T>, dim3(w.s1 - w.s0), dim3(NT), wp, stream, B, w.s0);
+  if (!ptiled)
+    launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
+  else if (generic)
+    launch<T>(k_potrf<T>, B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
   B.items = A.trsm;
   if (tiled && w.t1 > w.t0)
     hipLaunchKernelGGL(k_trsm_t<T>, dim3(w.t1 - w.t0), dim3(NT), wt, stream, B, w.t0);
