@@ -1491,6 +1491,56 @@ size_t work_tiled() {
   return (size_t)2 * 64 * TLD;
 }
 
+// In-place Cholesky S = L L^T of the n x n block (n <= 64, row stride TLD)
+// and X <- L^{-1} (X holds the identity on entry), 256 threads, one barrier
+// per column for each: the scaling of column k and the final write of row k
+// of the inverse are deferred to the next column, which no longer reads them.
+// A non-positive pivot sets *bad.
+template <typename CT>
+__device__ void chol_inv_lds(CT* S, CT* X, int n, int* bad) {
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  // right-looking Cholesky on the unscaled column k: S_jl -= S_jk S_lk / S_kk
+  for (int k = 0; k < n; ++k) {
+    const CT p = S[k * TLD + k];
+    if (k > 0) {
+      const CT dprev = sqrt(S[(k - 1) * TLD + (k - 1)]);
+      for (int j = k + tid; j < n; j += NT) S[j * TLD + (k - 1)] /= dprev;
+    }
+    if (p > CT(0)) {
+      const CT ip = CT(1) / p;
+      for (int j = k + 1 + ty; j < n; j += 16) {
+        const CT f = S[j * TLD + k] * ip;
+        for (int l = k + 1 + tx; l <= j; l += 16) S[j * TLD + l] -= f * S[l * TLD + k];
+      }
+    } else if (tid == 0) {
+      *bad = 1;
+    }
+    __syncthreads();
+  }
+  // columns 0..n-2 are scaled (column n-1 has nothing below the diagonal);
+  // the diagonal still holds the pivots p_k, and L_kk = sqrt(p_k)
+  for (int k = tid; k < n; k += NT) S[k * TLD + k] = sqrt(fmax(S[k * TLD + k], CT(0)));
+  __syncthreads();
+  // X <- L^{-1}: forward substitution, row k final in the next step
+  for (int k = 0; k < n; ++k) {
+    const CT lkk = S[k * TLD + k];
+    if (k > 0) {
+      const CT lp = S[(k - 1) * TLD + (k - 1)];
+      for (int c = tid; c < k; c += NT) X[(k - 1) * TLD + c] /= lp;
+    }
+    for (int j = k + 1 + ty; j < n; j += 16) {
+      const CT f = S[j * TLD + k] / lkk;
+      for (int c = tx; c <= k; c += 16) X[j * TLD + c] -= f * X[k * TLD + c];
+    }
+    __syncthreads();
+  }
+  {
+    const CT lp = S[(n - 1) * TLD + (n - 1)];
+    for (int c = tid; c < n; c += NT) X[(n - 1) * TLD + c] /= lp;
+  }
+  __syncthreads();
+}
+
 // Elimination of S_i for n_i <= 64: Cholesky S = L L^T and L^{-1} with one
 // barrier per column each (the scaling of column k and the final write of row
 // k of the inverse are deferred to the next column, which no longer reads
@@ -1518,46 +1568,7 @@ __global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
     X[j * TLD + c] = j == c ? CT(1) : CT(0);
   }
   __syncthreads();
-  // right-looking Cholesky on the unscaled column k: S_jl -= S_jk S_lk / S_kk
-  for (int k = 0; k < n; ++k) {
-    const CT p = S[k * TLD + k];
-    if (k > 0) {
-      const CT dprev = sqrt(S[(k - 1) * TLD + (k - 1)]);
-      for (int j = k + tid; j < n; j += NT) S[j * TLD + (k - 1)] /= dprev;
-    }
-    if (p > CT(0)) {
-      const CT ip = CT(1) / p;
-      for (int j = k + 1 + ty; j < n; j += 16) {
-        const CT f = S[j * TLD + k] * ip;
-        for (int l = k + 1 + tx; l <= j; l += 16) S[j * TLD + l] -= f * S[l * TLD + k];
-      }
-    } else if (tid == 0) {
-      bad = 1;
-    }
-    __syncthreads();
-  }
-  // columns 0..n-2 are scaled (column n-1 has nothing below the diagonal);
-  // the diagonal still holds the pivots p_k, and L_kk = sqrt(p_k)
-  for (int k = tid; k < n; k += NT) S[k * TLD + k] = sqrt(fmax(S[k * TLD + k], CT(0)));
-  __syncthreads();
-  // X <- L^{-1}: forward substitution, row k final in the next step
-  for (int k = 0; k < n; ++k) {
-    const CT lkk = S[k * TLD + k];
-    if (k > 0) {
-      const CT lp = S[(k - 1) * TLD + (k - 1)];
-      for (int c = tid; c < k; c += NT) X[(k - 1) * TLD + c] /= lp;
-    }
-    for (int j = k + 1 + ty; j < n; j += 16) {
-      const CT f = S[j * TLD + k] / lkk;
-      for (int c = tx; c <= k; c += 16) X[j * TLD + c] -= f * X[k * TLD + c];
-    }
-    __syncthreads();
-  }
-  {
-    const CT lp = S[(n - 1) * TLD + (n - 1)];
-    for (int c = tid; c < n; c += NT) X[(n - 1) * TLD + c] /= lp;
-  }
-  __syncthreads();
+  chol_inv_lds(S, X, n, &bad);
   // store L (lower, zero above) and L^{-1}
   T* Lig = A.Li + A.u_off[i];
   for (int e = tid; e < n * n; e += NT) {
@@ -2030,25 +2041,31 @@ constexpr int GJ = 64;
 
 __global__ __launch_bounds__(NT) void k_gj_pivot(double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv,
                                                  int32_t* err) {
-  __shared__ double S[GJ][GJ + 1];
-  __shared__ double Li[GJ][GJ + 1];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* S = reinterpret_cast<double*>(smem_raw);
+  double* X = S + 64 * TLD;
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   if (tid == 0) bad = 0;
-  for (int e = tid; e < kb * kb; e += NT) S[e / kb][e % kb] = Ad[(k0 + e / kb) * dim + k0 + e % kb];
-  __syncthreads();
-  chol_inplace(&S[0][0], kb, GJ + 1, &bad);
-  // Li = L^{-1} (lower), column by column via X = I
-  for (int e = tid; e < kb * kb; e += NT) Li[e / kb][e % kb] = (e / kb == e % kb) ? 1.0 : 0.0;
-  __syncthreads();
-  trsm_lower(&S[0][0], GJ + 1, &Li[0][0], kb, kb, GJ + 1);
-  // Pinv = Li^T Li
   for (int e = tid; e < kb * kb; e += NT) {
-    const int a = e / kb, c = e % kb;
-    double s = 0;
-    for (int t = max(a, c); t < kb; ++t) s += Li[t][a] * Li[t][c];
-    Pinv[a * GJ + c] = s;
+    const int j = e / kb, c = e % kb;
+    S[j * TLD + c] = Ad[(k0 + j) * dim + k0 + c];
+    X[j * TLD + c] = j == c ? 1.0 : 0.0;
   }
+  __syncthreads();
+  chol_inv_lds(S, X, kb, &bad);
+  __syncthreads();
+  // Pinv = L^{-T} L^{-1}
+  double acc[4][4];
+  zero_acc(acc);
+  gemm_tn_4x4(X, X, kb, acc);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = 4 * ty + p, c = 4 * tx + q;
+      if (a < kb && c < kb) Pinv[a * GJ + c] = acc[p][q];
+    }
   if (tid == 0 && bad) {
     if (atomicCAS(err, 0, 1) == 0) err[1] = -1;
   }
@@ -2057,54 +2074,65 @@ __global__ __launch_bounds__(NT) void k_gj_pivot(double* Ad, int64_t dim, int64_
 // W = Pinv * A[k-block, :] and R0 = A[k-block, :]  (kb x dim each, ld dim)
 __global__ __launch_bounds__(NT) void k_gj_rows(const double* Ad, int64_t dim, int64_t k0, int kb,
                                                 const double* Pinv, double* W, double* R0) {
-  __shared__ double P[GJ][GJ + 1];
-  __shared__ double X[GJ][GJ + 1];
-  const int tid = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* P = reinterpret_cast<double*>(smem_raw);
+  double* X = P + 64 * TLD;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const int64_t c0 = (int64_t)blockIdx.x * GJ;
   const int tc = (int)min<int64_t>(GJ, dim - c0);
-  for (int e = tid; e < kb * kb; e += NT) P[e / kb][e % kb] = Pinv[(e / kb) * GJ + e % kb];
+  for (int e = tid; e < kb * kb; e += NT) P[(e / kb) * TLD + e % kb] = Pinv[(e / kb) * GJ + e % kb];
   for (int e = tid; e < kb * tc; e += NT) {
     const int t = e / tc, c = e % tc;
     const double v = Ad[(k0 + t) * dim + c0 + c];
-    X[t][c] = v;
+    X[t * TLD + c] = v;
     R0[t * dim + c0 + c] = v;
   }
   __syncthreads();
-  for (int e = tid; e < kb * tc; e += NT) {
-    const int a = e / tc, c = e % tc;
-    double s = 0;
-    for (int t = 0; t < kb; ++t) s += P[a][t] * X[t][c];
-    W[a * dim + c0 + c] = s;
-  }
+  double acc[4][4];
+  zero_acc(acc);
+  gemm_tn_4x4(P, X, kb, acc);   // Pinv is symmetric
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = 4 * ty + p, c = 4 * tx + q;
+      if (a < kb && c < tc) W[a * dim + c0 + c] = acc[p][q];
+    }
 }
 
 __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64_t k0, int kb,
                                                   const double* Pinv, const double* W, const double* R0) {
-  __shared__ double Ri[GJ][GJ + 1];
-  __shared__ double Wj[GJ][GJ + 1];
-  const int tid = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Ri = reinterpret_cast<double*>(smem_raw);
+  double* Wj = Ri + 64 * TLD;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const int64_t i0 = (int64_t)blockIdx.y * GJ, j0 = (int64_t)blockIdx.x * GJ;
   const int ti = (int)min<int64_t>(GJ, dim - i0), tj = (int)min<int64_t>(GJ, dim - j0);
-  for (int e = tid; e < kb * ti; e += NT) Ri[e / ti][e % ti] = R0[(e / ti) * dim + i0 + e % ti];
-  for (int e = tid; e < kb * tj; e += NT) Wj[e / tj][e % tj] = W[(e / tj) * dim + j0 + e % tj];
+  for (int e = tid; e < kb * ti; e += NT) Ri[(e / ti) * TLD + e % ti] = R0[(e / ti) * dim + i0 + e % ti];
+  for (int e = tid; e < kb * tj; e += NT) Wj[(e / tj) * TLD + e % tj] = W[(e / tj) * dim + j0 + e % tj];
   __syncthreads();
-  for (int e = tid; e < ti * tj; e += NT) {
-    const int64_t i = i0 + e / tj, j = j0 + e % tj;
-    const bool ik = i >= k0 && i < k0 + kb, jk = j >= k0 && j < k0 + kb;
-    double v;
-    if (ik && jk) {
-      v = -Pinv[(i - k0) * GJ + (j - k0)];
-    } else if (ik) {
-      v = W[(i - k0) * dim + j];
-    } else if (jk) {
-      v = W[(j - k0) * dim + i];
-    } else {
-      double s = 0;
-      for (int t = 0; t < kb; ++t) s += Ri[t][e / tj] * Wj[t][e % tj];
-      v = Ad[i * dim + j] - s;
+  double acc[4][4];
+  zero_acc(acc);
+  gemm_tn_4x4(Ri, Wj, kb, acc);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int li = 4 * ty + p, lj = 4 * tx + q;
+      if (li >= ti || lj >= tj) continue;
+      const int64_t i = i0 + li, j = j0 + lj;
+      const bool ik = i >= k0 && i < k0 + kb, jk = j >= k0 && j < k0 + kb;
+      double v;
+      if (ik && jk)
+        v = -Pinv[(i - k0) * GJ + (j - k0)];
+      else if (ik)
+        v = W[(i - k0) * dim + j];
+      else if (jk)
+        v = W[(j - k0) * dim + i];
+      else
+        v = Ad[i * dim + j] - acc[p][q];
+      Ad[i * dim + j] = v;
     }
-    Ad[i * dim + j] = v;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2254,10 +2282,11 @@ void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double*
   const unsigned nt = (unsigned)((dim + GJ - 1) / GJ);
   for (int64_t k0 = 0; k0 < dim; k0 += GJ) {
     const int kb = (int)std::min<int64_t>(GJ, dim - k0);
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), 0, stream, Ad, dim, k0, kb, Pinv, err);
-    hipLaunchKernelGGL(k_gj_rows, dim3(nt), dim3(NT), 0, stream, (const double*)Ad, dim, k0, kb,
+    const size_t lds = (size_t)2 * 64 * TLD * sizeof(double);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), lds, stream, Ad, dim, k0, kb, Pinv, err);
+    hipLaunchKernelGGL(k_gj_rows, dim3(nt), dim3(NT), lds, stream, (const double*)Ad, dim, k0, kb,
                        (const double*)Pinv, W, R0);
-    hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(NT), 0, stream, Ad, dim, k0, kb, (const double*)Pinv,
+    hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(NT), lds, stream, Ad, dim, k0, kb, (const double*)Pinv,
                        (const double*)W, (const double*)R0);
   }
 }
