@@ -168,6 +168,21 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
                   double* x, int64_t ldx, double rtol, int32_t maxit,
                   int32_t* iters, double* relres);
 
+/*
+ * FP64 preconditioned MINRES (the Krylov method of the paper's Section 4),
+ * with M^{-1} as the symmetric positive definite preconditioner, x0 = 0.  The
+ * iterate minimises ||b - A x||_{M^{-1}} over the preconditioned Krylov space
+ * (Paige-Saunders recurrences: three-term Lanczos with M^{-1}, Givens QR of
+ * the tridiagonal matrix, three-term update of the search directions).
+ * Every column stops when the preconditioned residual norm satisfies
+ * ||r_k||_{M^{-1}} <= rtol ||b||_{M^{-1}}, or at maxit.  Arguments, outputs
+ * (true residual ||b - A x|| / ||b|| in relres) and errors as for
+ * cae_pcg_solve.
+ */
+int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
+                     double* x, int64_t ldx, double rtol, int32_t maxit,
+                     int32_t* iters, double* relres);
+
 typedef struct {
   int32_t nlevels;          /* levels factored (K) */
   int64_t coarse_dim;       /* dimension of the dense remainder */

@@ -9,4 +9,4 @@ matrix and right-hand-side generators, none of the method's arithmetic).
 from .symbolic import (morton_key, grid_order, level1_pattern, coarsen, coarse_pattern,
                        colour_order, element_order, simulate_level, adjacency, live_pairs)
 from .ce import (NotSPD, CEOptions, CEFactor, LevelFactor, ce_factor, ce_solve,
-                 ce_multiply, ce_dense, pcg)
+                 ce_multiply, ce_dense, pcg, minres)

@@ -491,3 +491,62 @@ def pcg(A, b, apply_prec, tol=1e-8, maxit=1000):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, it, float(np.linalg.norm(b - A @ x) / nb)
+
+
+def minres(A, b, apply_prec, tol=1e-10, maxit=1000):
+    """Preconditioned MINRES from ``x0 = 0`` for one column (the Krylov method
+    of the paper's Section 4; Paige-Saunders recurrences).  ``apply_prec`` is
+    ``M^{-1}`` (symmetric positive definite).  The iterate ``x_k`` minimises
+    ``||b - A x||_{M^{-1}}`` over the preconditioned Krylov space of
+    dimension ``k``.  Stops when that norm (``phibar``) is at most
+    ``tol * ||b||_{M^{-1}}``.  Returns ``(x, iterations, ||b - A x|| / ||b||)``.
+
+    Steps per iteration: Lanczos ``v_k = y / beta_k``, ``y = A v_k -
+    (beta_k / beta_{k-1}) r_{k-1}``, ``alpha_k = v_k^T y``, ``y -= (alpha_k /
+    beta_k) r_k``, ``beta_{k+1} = sqrt(y^T M^{-1} y)``; the previous Givens
+    rotation (cs, sn) acts on the new column of the tridiagonal matrix, a new
+    rotation annihilates ``beta_{k+1}``; the search direction is the
+    three-term combination ``w_k = (v_k - eps_k w_{k-2} - delta_k w_{k-1}) /
+    gamma_k`` and ``x += phi_k w_k``."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    nb = np.linalg.norm(b)
+    r1 = b.copy()
+    y = apply_prec(r1)
+    beta1 = float(np.sqrt(max(r1 @ y, 0.0)))
+    if beta1 == 0.0:
+        return x, 0, 0.0
+    r2 = r1.copy()
+    beta, oldb = beta1, 0.0
+    dbar = epsln = 0.0
+    phibar = beta1
+    cs, sn = -1.0, 0.0
+    w = np.zeros_like(b)
+    w2 = np.zeros_like(b)
+    it = 0
+    while it < maxit:
+        v = y / beta
+        y = A @ v
+        if it > 0:
+            y = y - (beta / oldb) * r1
+        alpha = float(v @ y)
+        y = y - (alpha / beta) * r2
+        r1, r2 = r2, y
+        y = apply_prec(r2)
+        oldb, beta = beta, float(np.sqrt(max(r2 @ y, 0.0)))
+        oldeps = epsln
+        delta = cs * dbar + sn * alpha
+        gbar = sn * dbar - cs * alpha
+        epsln = sn * beta
+        dbar = -cs * beta
+        gamma = max(np.hypot(gbar, beta), 1e-300)
+        cs, sn = gbar / gamma, beta / gamma
+        phi = cs * phibar
+        phibar = sn * phibar
+        w1, w2 = w2, w
+        w = (v - oldeps * w1 - delta * w2) / gamma
+        x = x + phi * w
+        it += 1
+        if phibar <= tol * beta1 or not beta > 0.0:
+            break
+    return x, it, float(np.linalg.norm(b - A @ x) / nb) if nb > 0 else 0.0

@@ -204,6 +204,25 @@ class Factor:
         self.converged = rc == _lib.CAE_OK
         return (x.reshape(-1) if sq else x), it, rel
 
+    def minres(self, b, rtol=1e-10, maxit=1000, x=None):
+        """FP64 preconditioned MINRES (``cae_minres_solve``); returns ``(x, iters,
+        relres)`` with the true relative residual at exit."""
+        import torch
+        bb, k, sq = _as_cols(b)
+        if x is None:
+            x = torch.empty_like(bb)
+        it = np.zeros(k, np.int32)
+        rel = np.zeros(k, np.float64)
+        rc = check(lib().cae_minres_solve(self._h, k, bb.data_ptr(), self.n, x.data_ptr(), self.n, float(rtol),
+                                          int(maxit), ptr(it), ptr(rel)), allow=(_lib.CAE_ENOCONV,))
+        self.converged = rc == _lib.CAE_OK
+        return (x.reshape(-1) if sq else x), it, rel
+
+    def solve(self, b):
+        """Direct approximate solve ``x = M^{-1} b`` (CE(eps) used as a direct
+        solver, no Krylov iterations)."""
+        return self.apply(b)
+
     def close(self):
         if getattr(self, "_h", None):
             lib().cae_destroy(self._h)

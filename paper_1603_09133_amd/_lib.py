@@ -51,7 +51,8 @@ _lib = None
 EXPORTS = [
     "cae_default_options", "cae_last_error", "cae_grid_order", "cae_analyze", "cae_analysis_levels",
     "cae_analysis_level_info", "cae_analysis_level_arrays", "cae_analysis_perm", "cae_analysis_destroy",
-    "cae_factor_numeric", "cae_apply_precond", "cae_apply_factor", "cae_pcg_solve", "cae_get_stats",
+    "cae_factor_numeric", "cae_apply_precond", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
+    "cae_get_stats",
     "cae_get_ranks", "cae_get_sizes", "cae_destroy",
 ]
 
@@ -81,6 +82,7 @@ def lib():
     L.cae_apply_precond.argtypes = [p, i32, p, i64, p, i64]
     L.cae_apply_factor.argtypes = [p, i32, p, i64, p, i64]
     L.cae_pcg_solve.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
+    L.cae_minres_solve.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
     L.cae_get_stats.argtypes = [p, C.POINTER(Stats)]
     L.cae_get_ranks.argtypes = [p, i32, p]
     L.cae_get_sizes.argtypes = [p, i32, p]
@@ -88,7 +90,8 @@ def lib():
     L.cae_destroy.restype = None
     for name in ["cae_grid_order", "cae_analyze", "cae_analysis_levels", "cae_analysis_level_info",
                  "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_apply_precond",
-                 "cae_apply_factor", "cae_pcg_solve", "cae_get_stats", "cae_get_ranks", "cae_get_sizes"]:
+                 "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
+                 "cae_get_sizes"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -565,6 +565,65 @@ __global__ void k_pcg_p(int64_t n, const int32_t* active, const double* beta, co
   p[i + k * n] = z[i + k * n] + beta[k] * p[i + k * n];
 }
 
+// ---------------------------------------------------------------- MINRES ----
+// Per-column scalars of preconditioned MINRES live on the device, st[f * nrhs
+// + k] with field f below; only phibar (the preconditioned residual norm) is
+// read back per iteration for the stopping test.
+__global__ void k_mr_v(int64_t n, const int32_t* active, const double* st, int32_t nrhs, const double* y,
+                       double* v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= n || !active[k]) return;
+  v[i + k * n] = y[i + k * n] / st[MR_BETA * nrhs + k];
+}
+
+// y -= c r with c = beta / oldb (which = 0) or alpha / beta (which = 1)
+__global__ void k_mr_y(int64_t n, const int32_t* active, const double* st, int32_t nrhs, const double* r, double* y,
+                       int which) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= n || !active[k]) return;
+  const double c = which == 0 ? st[MR_BETA * nrhs + k] / st[MR_OLDB * nrhs + k]
+                              : st[MR_ALPHA * nrhs + k] / st[MR_BETA * nrhs + k];
+  y[i + k * n] -= c * r[i + k * n];
+}
+
+__global__ void k_mr_scalars(int32_t nrhs, const int32_t* active, double* st) {
+  const int k = threadIdx.x;
+  if (k >= nrhs || !active[k]) return;
+  double* f = st + k;
+  const double alpha = f[MR_ALPHA * nrhs];
+  const double beta = sqrt(fmax(f[MR_BSQ * nrhs], 0.0));
+  const double cs = f[MR_CS * nrhs], sn = f[MR_SN * nrhs], dbar = f[MR_DBAR * nrhs];
+  f[MR_OLDB * nrhs] = f[MR_BETA * nrhs];
+  f[MR_BETA * nrhs] = beta;
+  f[MR_OLDEPS * nrhs] = f[MR_EPSLN * nrhs];
+  f[MR_DELTA * nrhs] = cs * dbar + sn * alpha;
+  const double gbar = sn * dbar - cs * alpha;
+  f[MR_EPSLN * nrhs] = sn * beta;
+  f[MR_DBAR * nrhs] = -cs * beta;
+  const double gamma = fmax(sqrt(gbar * gbar + beta * beta), 1e-300);
+  f[MR_GAMMA * nrhs] = gamma;
+  f[MR_CS * nrhs] = gbar / gamma;
+  f[MR_SN * nrhs] = beta / gamma;
+  const double phibar = f[MR_PHIBAR * nrhs];
+  f[MR_PHI * nrhs] = (gbar / gamma) * phibar;
+  f[MR_PHIBAR * nrhs] = (beta / gamma) * phibar;
+}
+
+// w_new = (v - oldeps w_prev2 - delta w_prev) / gamma into wout; x += phi w_new
+__global__ void k_mr_wx(int64_t n, const int32_t* active, const double* st, int32_t nrhs, const double* v,
+                        const double* wprev2, const double* wprev, double* wout, double* x, int64_t ldx) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= n || !active[k]) return;
+  const double wn = (v[i + k * n] - st[MR_OLDEPS * nrhs + k] * wprev2[i + k * n] -
+                     st[MR_DELTA * nrhs + k] * wprev[i + k * n]) /
+                    st[MR_GAMMA * nrhs + k];
+  wout[i + k * n] = wn;
+  x[i + k * ldx] += st[MR_PHI * nrhs + k] * wn;
+}
+
 __global__ void k_copy_cols(int64_t n, const double* a, int64_t lda, double* b, int64_t ldb) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
@@ -682,6 +741,25 @@ void launch_pcg_p(int64_t n, int32_t nrhs, double* rz, const double* rz_new, con
   hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(NT), 0, stream, nrhs, rz, rz_new, active, beta);
   hipLaunchKernelGGL(k_pcg_p, dim3((unsigned)((n + NT - 1) / NT), nrhs), dim3(NT), 0, stream, n, active,
                      (const double*)beta, z, p);
+}
+
+void launch_mr_v(int64_t n, int32_t nrhs, const int32_t* active, const double* st, const double* y, double* v,
+                 hipStream_t stream) {
+  hipLaunchKernelGGL(k_mr_v, dim3((unsigned)((n + NT - 1) / NT), nrhs), dim3(NT), 0, stream, n, active, st, nrhs, y, v);
+}
+void launch_mr_y(int64_t n, int32_t nrhs, const int32_t* active, const double* st, const double* r, double* y,
+                 int which, hipStream_t stream) {
+  hipLaunchKernelGGL(k_mr_y, dim3((unsigned)((n + NT - 1) / NT), nrhs), dim3(NT), 0, stream, n, active, st, nrhs, r, y,
+                     which);
+}
+void launch_mr_scalars(int32_t nrhs, const int32_t* active, double* st, hipStream_t stream) {
+  hipLaunchKernelGGL(k_mr_scalars, dim3(1), dim3(NT), 0, stream, nrhs, active, st);
+}
+void launch_mr_wx(int64_t n, int32_t nrhs, const int32_t* active, const double* st, const double* v,
+                  const double* wprev2, const double* wprev, double* wout, double* x, int64_t ldx,
+                  hipStream_t stream) {
+  hipLaunchKernelGGL(k_mr_wx, dim3((unsigned)((n + NT - 1) / NT), nrhs), dim3(NT), 0, stream, n, active, st, nrhs, v,
+                     wprev2, wprev, wout, x, ldx);
 }
 
 void launch_copy_cols(int64_t n, int32_t nrhs, const double* a, int64_t lda, double* b, int64_t ldb,

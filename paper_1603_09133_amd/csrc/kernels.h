@@ -130,6 +130,21 @@ void launch_pcg_xr(int64_t n, int32_t nrhs, const double* rz, const double* pq, 
 // p = z + beta p with beta[k] = rz_new[k] / rz[k] (active columns), then rz = rz_new
 void launch_pcg_p(int64_t n, int32_t nrhs, double* rz, const double* rz_new, const int32_t* active,
                   const double* z, double* p, double* beta, hipStream_t stream);
+// ----------------------------------------------------------------- MINRES ---
+// fields of the per-column MINRES state st[f * nrhs + k]
+enum {
+  MR_BETA = 0, MR_OLDB, MR_DBAR, MR_EPSLN, MR_PHIBAR, MR_CS, MR_SN, MR_ALPHA, MR_BSQ, MR_OLDEPS, MR_DELTA,
+  MR_GAMMA, MR_PHI, MR_NFIELDS
+};
+void launch_mr_v(int64_t n, int32_t nrhs, const int32_t* active, const double* st, const double* y, double* v,
+                 hipStream_t stream);
+void launch_mr_y(int64_t n, int32_t nrhs, const int32_t* active, const double* st, const double* r, double* y,
+                 int which, hipStream_t stream);
+void launch_mr_scalars(int32_t nrhs, const int32_t* active, double* st, hipStream_t stream);
+// w_new = (v - oldeps w_prev2 - delta w_prev) / gamma into wout, x += phi w_new
+void launch_mr_wx(int64_t n, int32_t nrhs, const int32_t* active, const double* st, const double* v,
+                  const double* wprev2, const double* wprev, double* wout, double* x, int64_t ldx,
+                  hipStream_t stream);
 void launch_copy_cols(int64_t n, int32_t nrhs, const double* a, int64_t lda, double* b, int64_t ldb,
                       hipStream_t stream);
 void launch_fill(double* a, int64_t count, double v, hipStream_t stream);

@@ -206,6 +206,7 @@ struct cae_factor_s {
   DevBuf ctmp;
   int32_t pcg_nrhs = 0;
   DevBuf pr, pz, pp, pq, sc, act, partial;
+  DevBuf mr[7], mst;   // MINRES vectors and per-column scalars
 };
 
 namespace {
@@ -879,6 +880,120 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, do
     HIPCHK(hipStreamSynchronize(s));
     for (int k = 0; k < nrhs; ++k) relres[k] = bn[k] > 0 ? std::sqrt(hrr[k]) / bn[k] : 0.0;
     if (nact > 0) return fail(CAE_ENOCONV, "PCG did not converge within maxit");
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return CAE_OK;
+}
+
+int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                     double rtol, int32_t maxit, int32_t* iters, double* relres) {
+  if (h) g_cur_stream = h->stream;
+  if (check_handle(h)) return CAE_EINVAL;
+  const int64_t n = h->an->a.n;
+  if (nrhs <= 0 || !b || !x || ldb < n || ldx < n || !iters || !relres || maxit < 0 || !(rtol >= 0))
+    return fail(CAE_EINVAL, "bad MINRES arguments");
+  hipStream_t s = h->stream;
+  try {
+    const cae_analysis_s* A = h->an;
+    const size_t vb = (size_t)n * nrhs * sizeof(double);
+    for (auto& m : h->mr) m.alloc(vb);
+    h->mst.alloc((size_t)cae::MR_NFIELDS * nrhs * sizeof(double));
+    h->act.alloc((size_t)nrhs * sizeof(int32_t));
+    h->partial.alloc((size_t)nrhs * 1024 * sizeof(double));
+    double* st = h->mst.as<double>();
+    double* part = h->partial.as<double>();
+    int32_t* active = h->act.as<int32_t>();
+    const int64_t* rp = A->row_ptr.as<int64_t>();
+    const int32_t* ci = A->col_idx.as<int32_t>();
+    const double* av = h->vals.as<double>();
+    // rotating buffers: r1, r2, y (three-term Lanczos); w1, w2, w hold w_{k-2},
+    // w_{k-1}, w_k after iteration k; and v
+    double* r1 = h->mr[0].as<double>();
+    double* r2 = h->mr[1].as<double>();
+    double* y = h->mr[2].as<double>();
+    double* w1 = h->mr[3].as<double>();
+    double* w2 = h->mr[4].as<double>();
+    double* w = h->mr[5].as<double>();
+    double* v = h->mr[6].as<double>();
+    auto F = [&](int f) { return st + (int64_t)f * nrhs; };
+
+    for (int k = 0; k < nrhs; ++k) cae::launch_fill(x + k * ldx, n, 0.0, s);
+    cae::launch_fill(w, (int64_t)n * nrhs, 0.0, s);
+    cae::launch_fill(w2, (int64_t)n * nrhs, 0.0, s);
+    cae::launch_fill(w1, (int64_t)n * nrhs, 0.0, s);
+    cae::launch_copy_cols(n, nrhs, b, ldb, r1, n, s);
+    cae::launch_copy_cols(n, nrhs, b, ldb, r2, n, s);
+    std::vector<double> bn(nrhs), hv(nrhs), hb(nrhs);
+    cae::launch_dots(n, nrhs, b, ldb, b, ldb, part, F(cae::MR_BSQ), s);
+    HIPCHK(hipMemcpyAsync(bn.data(), F(cae::MR_BSQ), nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    do_apply(h, nrhs, r1, n, y, n);
+    cae::launch_dots(n, nrhs, r1, n, y, n, part, F(cae::MR_BSQ), s);
+    HIPCHK(hipMemcpyAsync(hv.data(), F(cae::MR_BSQ), nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // initial state: beta = phibar = beta_1, cs = -1, the rest 0
+    std::vector<double> init((size_t)cae::MR_NFIELDS * nrhs, 0.0);
+    std::vector<double> beta1(nrhs);
+    std::vector<int32_t> hact(nrhs);
+    int nact = 0;
+    for (int k = 0; k < nrhs; ++k) {
+      bn[k] = std::sqrt(bn[k]);
+      beta1[k] = std::sqrt(std::max(hv[k], 0.0));
+      init[cae::MR_BETA * nrhs + k] = beta1[k];
+      init[cae::MR_PHIBAR * nrhs + k] = beta1[k];
+      init[cae::MR_CS * nrhs + k] = -1.0;
+      hact[k] = beta1[k] > 0.0 ? 1 : 0;
+      nact += hact[k];
+      iters[k] = 0;
+    }
+    HIPCHK(hipMemcpyAsync(st, init.data(), init.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    int it = 0;
+    while (nact > 0 && it < maxit) {
+      cae::launch_mr_v(n, nrhs, active, st, y, v, s);
+      cae::launch_spmv(n, rp, ci, av, nrhs, v, n, y, n, s);
+      if (it > 0) cae::launch_mr_y(n, nrhs, active, st, r1, y, 0, s);
+      cae::launch_dots(n, nrhs, v, n, y, n, part, F(cae::MR_ALPHA), s);
+      cae::launch_mr_y(n, nrhs, active, st, r2, y, 1, s);
+      // r1 <- r2, r2 <- y; the old r1 takes the next y = M^{-1} r2
+      double* t = r1;
+      r1 = r2;
+      r2 = y;
+      y = t;
+      do_apply(h, nrhs, r2, n, y, n);
+      cae::launch_dots(n, nrhs, r2, n, y, n, part, F(cae::MR_BSQ), s);
+      cae::launch_mr_scalars(nrhs, active, st, s);
+      // w_k from w_{k-2} (w2) and w_{k-1} (w); it overwrites w_{k-3} (w1)
+      cae::launch_mr_wx(n, nrhs, active, st, v, w2, w, w1, x, ldx, s);
+      double* u = w1;
+      w1 = w2;
+      w2 = w;
+      w = u;
+      ++it;
+      HIPCHK(hipMemcpyAsync(hv.data(), F(cae::MR_PHIBAR), nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hb.data(), F(cae::MR_BETA), nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool changed = false;
+      for (int k = 0; k < nrhs; ++k) {
+        if (hact[k] && (hv[k] <= rtol * beta1[k] || !(hb[k] > 0.0))) {
+          hact[k] = 0;
+          iters[k] = it;
+          --nact;
+          changed = true;
+        }
+      }
+      if (changed) HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    for (int k = 0; k < nrhs; ++k)
+      if (hact[k]) iters[k] = it;
+    double* q = v;
+    cae::launch_spmv(n, rp, ci, av, nrhs, x, ldx, q, n, s);
+    cae::launch_residual(n, nrhs, b, ldb, q, s);
+    cae::launch_dots(n, nrhs, q, n, q, n, part, F(cae::MR_BSQ), s);
+    HIPCHK(hipMemcpyAsync(hv.data(), F(cae::MR_BSQ), nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < nrhs; ++k) relres[k] = bn[k] > 0 ? std::sqrt(hv[k]) / bn[k] : 0.0;
+    if (nact > 0) return fail(CAE_ENOCONV, "MINRES did not converge within maxit");
   } catch (const HipError& e) {
     return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
   }

@@ -116,27 +116,32 @@ def grf_diffusion_2d(n: int, length: float = 0.05, sigma: float = 1.0,
     return A, rng
 
 
-def anisotropic_diffusion_3d(n: int) -> sp.csr_matrix:
+def anisotropic_diffusion_3d(n) -> sp.csr_matrix:
     """The paper's Section 4 problem, div(k grad u)=f on [0,1]^3, Dirichlet,
-    k = diag(x1^2+0.5, x2^2+0.5, x3^2+0.5), equidistant interior grid n^3.
-    Written with the sign that makes the matrix SPD; face coefficients are
-    evaluated at face midpoints; h^2 is removed."""
-    h = 1.0 / (n + 1)
-    faces = (np.arange(n + 1) + 0.5) * h          # midpoints between nodes i-1..i (i=0..n)
-    kf = faces ** 2 + 0.5                         # coefficient of the matching axis
-    N = n ** 3
-    idx = np.arange(N).reshape(n, n, n)           # idx[z, y, x]
-    diag = np.zeros((n, n, n))
+    k = diag(x1^2+0.5, x2^2+0.5, x3^2+0.5), on the equidistant interior grid
+    ``n`` (an int for n^3, or ``(n1, n2, n3)``, x fastest; spacing h_a =
+    1/(n_a+1) per axis).  Written with the sign that makes the matrix SPD;
+    face coefficients are evaluated at face midpoints and axis a carries
+    k_a / h_a^2, scaled by h_1^2 (so h^2 is removed on a cubic grid)."""
+    dims = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    idx = np.arange(N).reshape(nz, ny, nx)        # idx[z, y, x]
+    diag = np.zeros((nz, ny, nx))
     rows, cols, vals = [], [], []
-    for axis, shape_axis in ((2, "x"), (1, "y"), (0, "z")):
-        # coefficient on the face between node i and i+1 along axis: kf[i+1]
+    h1 = 1.0 / (nx + 1)
+    for axis, na in ((2, nx), (1, ny), (0, nz)):
+        h = 1.0 / (na + 1)
+        faces = (np.arange(na + 1) + 0.5) * h      # midpoints between nodes i-1..i (i=0..na)
+        kf = (faces ** 2 + 0.5) * (h1 / h) ** 2    # coefficient of the matching axis
+        # coefficient on the face between node i and i+1 along the axis: kf[i+1]
         c = kf[1:-1]
         lo = [slice(None)] * 3
         hi = [slice(None)] * 3
-        lo[axis] = slice(0, n - 1)
-        hi[axis] = slice(1, n)
+        lo[axis] = slice(0, na - 1)
+        hi[axis] = slice(1, na)
         shp = [1, 1, 1]
-        shp[axis] = n - 1
+        shp[axis] = na - 1
         cc = np.broadcast_to(c.reshape(shp), idx[tuple(lo)].shape)
         diag[tuple(lo)] += cc
         diag[tuple(hi)] += cc
@@ -147,9 +152,9 @@ def anisotropic_diffusion_3d(n: int) -> sp.csr_matrix:
         first = [slice(None)] * 3
         last = [slice(None)] * 3
         first[axis] = 0
-        last[axis] = n - 1
+        last[axis] = na - 1
         diag[tuple(first)] += kf[0]
-        diag[tuple(last)] += kf[n]
+        diag[tuple(last)] += kf[na]
     rows.append(idx.ravel())
     cols.append(idx.ravel())
     vals.append(diag.ravel())
@@ -157,6 +162,12 @@ def anisotropic_diffusion_3d(n: int) -> sp.csr_matrix:
                       shape=(N, N))
     A.sort_indices()
     return A
+
+
+def rhs_ones(N: int) -> np.ndarray:
+    """The paper's right-hand side f = 1 (with the h^2 of the stencil removed,
+    a constant vector)."""
+    return np.ones(N, dtype=np.float64)
 
 
 def rhs_uniform(N: int, seed: int = 0) -> np.ndarray:
