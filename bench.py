@@ -51,6 +51,25 @@ def _cpu_baseline(side, patch, eps, nrhs_full, full_n):
                        f"for the PCG part")}
 
 
+def _traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (FETCH_SIZE / WRITE_SIZE runs scaled by a plain copy), or None when the
+    kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1603_09133_amd", "csrc", "factor_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md")):
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", " ")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("kernel") == kernel and fields.get("source_sha256") == h:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +84,9 @@ def main():
     ap.add_argument("--with-analysis", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=128)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size before the timed steps "
+                         "(reference dispatch for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -93,6 +115,13 @@ def main():
     b = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
     x = torch.empty_like(b)
     prec = cae.FP32 if args.precision == "fp32" else cae.FP64
+
+    if args.copy_calibration_mib > 0:
+        src = torch.ones(args.copy_calibration_mib * 2**18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         a = cae.Analysis(ip, ix, perm, bp, co, order=order) if args.with_analysis else an
@@ -145,15 +174,17 @@ def main():
                    "coarse_dim": st["coarse_dim"], "factor_bytes": st["factor_bytes"]},
     }
     # roofline of the dominant kernel (the far-row compression, plain vector
-    # arithmetic: QR + one-sided Jacobi), from HIP events around its launches
+    # arithmetic), from HIP events around its launches on the factor's stream
     peak = 157.3 if prec == cae.FP32 else 78.6
+    kname = ("k_compress_gram<float> (FP64 Gram, pivoted Cholesky, one-sided Jacobi)" if prec == cae.FP32
+             else "k_compress_wg<double> (TSQR, pivoted QR, one-sided Jacobi)")
     if comp["launches"]:
         per_launch_s = comp["ms"] / comp["launches"] / 1e3
         flops_per_launch = comp["flops"] / comp["launches"]
         ach = flops_per_launch / per_launch_s / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": "k_compress_wave (far-row QR + Jacobi SVD)",
+        out["roofline"] = {"bound": "alu", "kernel": kname,
                            "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                           "traffic": None, "launches_per_step": comp["launches"] / args.steps,
+                           "traffic": _traffic(kname.split(" ")[0]), "launches_per_step": comp["launches"] / args.steps,
                            "avg_launch_us": per_launch_s * 1e6, "algorithmic_flops_per_launch": flops_per_launch}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(args.cpu_side, patch, args.eps, args.nrhs, N)
