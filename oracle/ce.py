@@ -47,6 +47,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
+from . import learned as lrn
 from . import symbolic as sym
 
 __all__ = ["NotSPD", "CEOptions", "LevelFactor", "CEFactor", "ce_factor",
@@ -65,8 +66,10 @@ class NotSPD(RuntimeError):
 @dataclass
 class CEOptions:
     eps: float = 1e-8
-    rank_mode: str = "eps"          # 'eps' = CE(eps), 'fixed' = CE(r)
+    rank_mode: str = "eps"          # 'eps' = CE(eps), 'fixed' = CE(r), 'learned' = CE(eps) by sketch
     fixed_rank: int = 0
+    mlp_params: object = None       # learned: FP32 parameter vector of the rank MLP
+    seed: int = 0                   # learned: Philox key of the sketches
     order: str = "paper"            # 'paper' | 'multicolour'
     coarse_max_dim: int = 2048
     max_levels: int = 0             # 0 = no limit
@@ -90,6 +93,10 @@ class LevelFactor:
     panel: list = field(default_factory=list)       # dict x -> rows_x x n_i
     parent: np.ndarray = None
     min_pivot: float = np.inf
+    features: list = field(default_factory=list)    # learned: features of every compressed step
+    exact_rank: list = field(default_factory=list)  # learned: the exact-SVD rank of that step
+    accepted: int = 0               # learned: sketches accepted
+    fallbacks: int = 0              # learned: steps that took the exact SVD
 
 
 @dataclass
@@ -155,7 +162,7 @@ def _level1_blocks(A0: sp.csr_matrix, block_ptr):
 def _rank(sig_full, theta, opts: CEOptions, has_far: bool, b: int):
     if not has_far:
         return 0
-    if opts.rank_mode == "eps":
+    if opts.rank_mode in ("eps", "learned"):
         return int(np.count_nonzero(sig_full > theta))
     if opts.rank_mode == "fixed":
         return int(min(opts.fixed_rank, b))
@@ -177,6 +184,9 @@ def _factor_level(level_no, sizes, W: _Blocks, close_pairs, order, theta, opts):
     lf.panel = [None] * M
     lrows = [[] for _ in range(M)]      # steps whose stored panel has rows of block c
     removed = set()
+    pos = {blk: k for k, blk in enumerate(order)}
+    lf.features = [None] * M
+    lf.exact_rank = [None] * M
     for i in order:
         b = int(sizes[i])
         fl = sorted(far[i])
@@ -191,12 +201,35 @@ def _factor_level(level_no, sizes, W: _Blocks, close_pairs, order, theta, opts):
             Uf, sig = np.eye(b), np.zeros(b)
         r = _rank(sig, theta, opts, len(fl) > 0 and F.shape[1] > 0, b)
         U = Uf if (len(fl) > 0 and F.shape[1] > 0) else np.eye(b)
+        e_i = float(np.sum(sig[r:] ** 2))
+        if opts.rank_mode == "learned" and fl and b > 0:
+            # live columns only: a processed far neighbour keeps its r_l basis columns
+            proc = [l for l in fl if pos[l] < pos[i]]
+            F_live = np.hstack([W.get(i, l)[:, :lf.r[l]] if pos[l] < pos[i] else W.get(i, l) for l in fl])
+            x = lrn.features(F_live, theta, level_no - 1, len(close[i]), len(fl), len(proc),
+                             float(sum(lf.r[l] for l in proc)), float(sum(int(sizes[l]) for l in proc)))
+            lf.features[i] = x
+            lf.exact_rank[i] = r
+            if F_live.shape[1] > 0:
+                k = lrn.predicted_rank(float(lrn.mlp_forward(opts.mlp_params, x)[0]), b)
+                ok, Ur, rr, sb, e = lrn.randomized_compress(F_live, theta, k, opts.seed, level_no - 1, i)
+            else:
+                ok, Ur, rr, sb, e = True, np.zeros((b, 0)), 0, np.zeros(0), 0.0
+            if ok:
+                U = lrn.complete_basis(Ur, b)
+                r = rr
+                sig = np.zeros(b)
+                sig[:min(len(sb), b)] = sb[:b]
+                e_i = e
+                lf.accepted += 1
+            else:
+                lf.fallbacks += 1
         if not fl:
             removed.add(i)          # eliminated whole; leaves the graph
         lf.U[i], lf.r[i], lf.sigma[i] = U, r, sig
         if opts.keep_far_rows:
             lf.F[i] = F.copy()
-        lf.e[i] = float(np.sum(sig[r:] ** 2))
+        lf.e[i] = e_i
         # 3. rotation of row/column i, of the stored factor rows of i, drop E_i
         for x in sorted(close[i] | far[i]):
             blk = W.get(i, x)
