@@ -47,13 +47,18 @@ typedef enum {
   CAE_EDEVICE = -5    /* a HIP call failed */
 } cae_status_t;
 
-typedef enum { CAE_RANK_EPS = 0, CAE_RANK_FIXED = 1 } cae_rank_mode_t;
+typedef enum { CAE_RANK_EPS = 0, CAE_RANK_FIXED = 1, CAE_RANK_LEARNED = 2 } cae_rank_mode_t;
 typedef enum { CAE_FP64 = 0, CAE_FP32 = 1 } cae_precision_t;
 typedef enum { CAE_ORDER_PAPER = 0, CAE_ORDER_MULTICOLOUR = 1 } cae_order_t;
 
 typedef struct {
   int32_t struct_size;     /* sizeof(cae_options_t) */
-  int32_t rank_mode;       /* CE(eps) (Remark 2.1, first strategy) or CE(r) (second) */
+  int32_t rank_mode;       /* CE(eps) (Remark 2.1, first strategy), CE(r) (second), or
+                              LEARNED: CE(eps) with the cheaper rank-revealing step the
+                              paper's conclusion proposes -- an MLP predicts the rank, a
+                              Gaussian sketch of that width (plus 8) gives the range, an
+                              a-posteriori check guarantees ||E_i||_2 <= eps * tau and
+                              steps that fail it take the exact SVD (blocks <= 64) */
   int32_t fixed_rank;      /* r for CE(r) */
   int32_t precision;       /* arithmetic of the block factorization; the coarse
                               remainder, the apply vectors and PCG are FP64 */
@@ -68,7 +73,16 @@ typedef struct {
   int32_t reserved;        /* 0 */
   int64_t coarse_max_dim;  /* remainder size factored densely (default 2048) */
   void* stream;            /* hipStream_t; NULL = null stream */
+  const float* mlp_params; /* LEARNED: DEVICE, cae_mlp_param_count() floats (see cae_mlp_train) */
+  uint64_t seed;           /* LEARNED: key of the counter-based (Philox4x32-10) sketches */
+  float* record;           /* DEVICE or NULL: training records, CAE_RECORD_WIDTH floats per block
+                              of every factored level (level after level): 16 features of
+                              the far row, then the rank fraction r_i / b_i of the step
+                              (-1 where the step compressed nothing); CE(eps) or LEARNED */
+  int64_t record_cap;      /* rows available in record */
 } cae_options_t;
+
+#define CAE_RECORD_WIDTH 17
 
 /* Fill *opt with the defaults (CE(eps), FP64, MULTICOLOUR, coarse 2048). */
 void cae_default_options(cae_options_t* opt);
@@ -198,6 +212,9 @@ typedef struct {
                                2 w b^2 - 2 b^3 / 3 (QR, w >= b; else 2 b w^2 - 2 w^3 / 3)
                                + 12 b^3 (SVD of the triangular factor) */
   int32_t compressions;     /* far rows compressed (steps with a non-empty far row) */
+  int32_t sketch_accepted;  /* LEARNED: steps the sketch settled */
+  int32_t sketch_rejected;  /* LEARNED: steps that failed the check and took the exact SVD */
+  int64_t record_rows;      /* rows written to cae_options_t.record */
 } cae_stats_t;
 
 int cae_get_stats(cae_handle_t h, cae_stats_t* s);
@@ -206,6 +223,28 @@ int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks);
 /* Block sizes b_i of a factored level (host, M entries). */
 int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes);
 void cae_destroy(cae_handle_t h);
+
+/*
+ * Rank-predicting MLP of the LEARNED mode: 16 features -> 64 -> 64 -> 1,
+ * ReLU, output z ~ r_i / b_i; the predicted rank is ceil(b_i z) clamped to
+ * [0, b_i].  Parameters (FP32, DEVICE, cae_mlp_param_count() floats): feature
+ * mean[16], std[16], W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * Records (DEVICE, n rows of CAE_RECORD_WIDTH floats) come from a
+ * factorization with cae_options_t.record; rows with a negative label are
+ * skipped.
+ */
+int32_t cae_mlp_param_count(void);
+/* Sets the feature mean/std from the records, then runs `epochs` full-batch
+ * Adam steps (learning rate lr) on 0.5 mean (z - label)^2 from the given
+ * weights.  *loss (host) receives the loss of the last step. */
+int cae_mlp_train(const float* records, int64_t n, float* params, int32_t epochs, float lr,
+                  float* loss, void* stream);
+/* Loss and gradient (DEVICE grad, cae_mlp_param_count() floats, zero for the
+ * normalisation entries) at the given parameters, FP32. */
+int cae_mlp_loss_grad(const float* params, const float* records, int64_t n, float* grad,
+                      float* loss, void* stream);
+/* z for every record (DEVICE, n floats), FP64 arithmetic as in the factorization. */
+int cae_mlp_predict(const float* params, const float* records, int64_t n, float* z, void* stream);
 
 const char* cae_last_error(void);
 

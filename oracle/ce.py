@@ -70,6 +70,7 @@ class CEOptions:
     fixed_rank: int = 0
     mlp_params: object = None       # learned: FP32 parameter vector of the rank MLP
     seed: int = 0                   # learned: Philox key of the sketches
+    record_features: bool = False   # compute the learned-mode features in any mode (tests only)
     order: str = "paper"            # 'paper' | 'multicolour'
     coarse_max_dim: int = 2048
     max_levels: int = 0             # 0 = no limit
@@ -95,6 +96,7 @@ class LevelFactor:
     min_pivot: float = np.inf
     features: list = field(default_factory=list)    # learned: features of every compressed step
     exact_rank: list = field(default_factory=list)  # learned: the exact-SVD rank of that step
+    label: list = field(default_factory=list)       # learned: sketch width an ideal sketch needs
     accepted: int = 0               # learned: sketches accepted
     fallbacks: int = 0              # learned: steps that took the exact SVD
 
@@ -187,6 +189,7 @@ def _factor_level(level_no, sizes, W: _Blocks, close_pairs, order, theta, opts):
     pos = {blk: k for k, blk in enumerate(order)}
     lf.features = [None] * M
     lf.exact_rank = [None] * M
+    lf.label = [None] * M
     for i in order:
         b = int(sizes[i])
         fl = sorted(far[i])
@@ -202,14 +205,17 @@ def _factor_level(level_no, sizes, W: _Blocks, close_pairs, order, theta, opts):
         r = _rank(sig, theta, opts, len(fl) > 0 and F.shape[1] > 0, b)
         U = Uf if (len(fl) > 0 and F.shape[1] > 0) else np.eye(b)
         e_i = float(np.sum(sig[r:] ** 2))
-        if opts.rank_mode == "learned" and fl and b > 0:
+        if (opts.rank_mode == "learned" or opts.record_features) and fl and b > 0:
             # live columns only: a processed far neighbour keeps its r_l basis columns
             proc = [l for l in fl if pos[l] < pos[i]]
-            F_live = np.hstack([W.get(i, l)[:, :lf.r[l]] if pos[l] < pos[i] else W.get(i, l) for l in fl])
+            wl = [int(lf.r[l]) if pos[l] < pos[i] else int(sizes[l]) for l in fl]
+            F_live = np.hstack([W.get(i, l)[:, :wd] for l, wd in zip(fl, wl)])
             x = lrn.features(F_live, theta, level_no - 1, len(close[i]), len(fl), len(proc),
-                             float(sum(lf.r[l] for l in proc)), float(sum(int(sizes[l]) for l in proc)))
+                             float(sum(lf.r[l] for l in proc)), float(sum(int(sizes[l]) for l in proc)), wl)
             lf.features[i] = x
             lf.exact_rank[i] = r
+            lf.label[i] = lrn.sketch_label(sig, r, theta)
+        if opts.rank_mode == "learned" and fl and b > 0:
             if F_live.shape[1] > 0:
                 k = lrn.predicted_rank(float(lrn.mlp_forward(opts.mlp_params, x)[0]), b)
                 ok, Ur, rr, sb, e = lrn.randomized_compress(F_live, theta, k, opts.seed, level_no - 1, i)

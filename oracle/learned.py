@@ -9,7 +9,8 @@ with the GPU path.
 The paper names a cheaper rank-revealing factorization as the way to speed up
 the compression (conclusion); this is that variant:
 
-1. 16 features of the far row ``F_i`` (``b x w``) and of its step;
+1. 16 features of the far row ``F_i`` (``b x w``) and of its step, all
+   invariant under rotations inside a far block's columns;
 2. an MLP 16 -> 64 -> 64 -> 1 (ReLU), evaluated in FP64 on FP32 parameters,
    predicts ``z ~ r_i / b_i``; ``k = clamp(ceil(b z), 0, b)``;
 3. sketch ``Y = F Omega`` with ``l = min(k + p, b, w)`` Gaussian columns drawn
@@ -85,14 +86,20 @@ def _clog10(v, theta):
     return float(np.clip(np.log10(max(v, 1e-300) / theta), -30.0, 30.0))
 
 
-def features(F, theta, level, nclose, nfar, nfar_proc, proc_rank_sum, proc_size_sum):
-    """The 16 features of a far row F (b x w, live columns only) and its step."""
+def features(F, theta, level, nclose, nfar, nfar_proc, proc_rank_sum, proc_size_sum, widths=None):
+    """The 16 features of a far row F (b x w, live columns only, far blocks of
+    the given ``widths`` side by side) and its step.  Every feature is
+    invariant under orthogonal changes of basis inside a far block's columns
+    and inside the rows (kept bases are defined only up to such rotations,
+    and at coarser levels the rows themselves are children's kept bases):
+    Frobenius norms of the row and of its far blocks, widths and counts."""
     b, w = F.shape
+    widths = [w] if widths is None else list(widths)
     rn = np.sqrt(np.sum(F * F, axis=1)) if w > 0 else np.zeros(b)
-    cn = np.sqrt(np.sum(F * F, axis=0)) if w > 0 else np.zeros(0)
+    edges = np.concatenate([[0], np.cumsum(widths)]).astype(int)
+    bn = np.array([np.sqrt(np.sum(F[:, edges[k]:edges[k + 1]] ** 2)) for k in range(len(widths))])
     fro2 = float(np.sum(rn * rn))
-    rmax = float(rn.max()) if b > 0 else 0.0
-    cmax = float(cn.max()) if w > 0 else 0.0
+    bmax = float(bn.max()) if len(bn) else 0.0
     x = np.zeros(NFEAT)
     x[0] = np.log2(b + 1.0)
     x[1] = np.log2(w + 1.0)
@@ -100,12 +107,12 @@ def features(F, theta, level, nclose, nfar, nfar_proc, proc_rank_sum, proc_size_
     x[3] = nfar
     x[4] = nclose
     x[5] = _clog10(np.sqrt(fro2), theta)
-    x[6] = _clog10(rmax, theta)
-    x[7] = _clog10(cmax, theta)
-    x[8] = np.count_nonzero(rn > theta) / max(b, 1)
-    x[9] = np.count_nonzero(cn > theta) / max(w, 1)
-    x[10] = fro2 / (rmax * rmax * b) if rmax > 0 else 0.0
-    x[11] = fro2 / (cmax * cmax * w) if cmax > 0 else 0.0
+    x[6] = _clog10(np.sqrt(fro2 / max(b, 1)), theta)
+    x[7] = _clog10(bmax, theta)
+    x[8] = _clog10(np.sqrt(fro2 / max(w, 1)), theta)
+    x[9] = np.count_nonzero(bn > theta) / max(len(bn), 1)
+    x[10] = float(np.sum(bn ** 4)) / (fro2 * fro2) if fro2 > 0 else 0.0
+    x[11] = fro2 / (bmax * bmax * len(bn)) if bmax > 0 else 0.0
     x[12] = nfar_proc / max(nfar, 1)
     x[13] = proc_rank_sum / proc_size_sum if proc_size_sum > 0 else 0.0
     x[14] = b / 64.0
@@ -164,6 +171,24 @@ def mlp_loss_grad(p, X, y):
     g[OFF_W1:OFF_B1] = (dh1.T @ Xn).ravel()
     g[OFF_B1:OFF_W2] = dh1.sum(axis=0)
     return loss, g
+
+
+def sketch_label(sig, r, theta):
+    """Training target of the predictor: the smallest sketch width k >= r with
+    which an ideal sketch (the top k singular directions) passes the check,
+    sum_{j >= k} sigma_j^2 + (sigma_r^2 if k > r) <= theta^2 (sigma sorted
+    descending, 0-based)."""
+    s2 = np.asarray(sig, dtype=np.float64) ** 2
+    n = len(s2)
+    sr2 = s2[r] if r < n else 0.0
+    kf = n
+    tail = 0.0
+    for k in range(n, r - 1, -1):
+        if k < n:
+            tail += s2[k]
+        if tail + (sr2 if k > r else 0.0) <= theta * theta:
+            kf = k
+    return max(kf, r)
 
 
 def predicted_rank(z, b):

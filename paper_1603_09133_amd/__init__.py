@@ -18,11 +18,11 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (CAEError, FP32, FP64, ORDER_MULTICOLOUR, ORDER_PAPER, RANK_EPS, RANK_FIXED, check, lib,
-                   ptr)
+from ._lib import (CAEError, FP32, FP64, ORDER_MULTICOLOUR, ORDER_PAPER, RANK_EPS, RANK_FIXED, RANK_LEARNED,
+                   RECORD_WIDTH, check, lib, ptr)
 
 __all__ = ["grid_order", "Analysis", "Factor", "CAEError", "FP64", "FP32", "ORDER_PAPER",
-           "ORDER_MULTICOLOUR", "RANK_EPS", "RANK_FIXED", "lib"]
+           "ORDER_MULTICOLOUR", "RANK_EPS", "RANK_FIXED", "RANK_LEARNED", "RECORD_WIDTH", "lib"]
 
 
 def _i32(a):
@@ -49,9 +49,13 @@ def grid_order(dims, patch):
 
 
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
-             coarse_max_dim=2048, stream=None, timing=False):
+             coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None):
     o = _lib.Options()
     lib().cae_default_options(C.byref(o))
+    o.mlp_params = None if mlp_params is None else mlp_params.data_ptr()
+    o.seed = int(seed)
+    o.record = None if record is None else record.data_ptr()
+    o.record_cap = 0 if record is None else record.shape[0]
     o.order = order
     o.precision = precision
     o.rank_mode = rank_mode
@@ -139,17 +143,26 @@ class Factor:
     """CE factorization on the GPU (``cae_factor_numeric``)."""
 
     def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
-                 max_levels=0, coarse_max_dim=2048, stream=None, timing=False):
+                 max_levels=0, coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0,
+                 record=None):
+        """``rank_mode=RANK_LEARNED`` needs ``mlp_params`` (float32 CUDA tensor of
+        ``learned.param_count()`` entries); ``record`` (float32 CUDA tensor of
+        shape ``(rows, RECORD_WIDTH)``) receives the training records."""
         import torch
         if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.float64):
             raise TypeError("vals must be a float64 CUDA tensor")
+        for t in (mlp_params, record):
+            if t is not None and not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+                                      and t.is_contiguous()):
+                raise TypeError("mlp_params / record must be contiguous float32 CUDA tensors")
         self.analysis = analysis
         self.n = analysis.n
         self._stream = stream
+        self._keep = (mlp_params, record)
         sptr = None if stream is None else stream.cuda_stream
         self._opts = _options(order=analysis.order, precision=precision, rank_mode=rank_mode,
                               fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
-                              stream=sptr, timing=timing)
+                              stream=sptr, timing=timing, mlp_params=mlp_params, seed=seed, record=record)
         h = C.c_void_p()
         self._vals = vals.contiguous()
         check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),

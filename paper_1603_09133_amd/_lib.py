@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcae.so")
 
 CAE_OK, CAE_EINVAL, CAE_ENOMEM, CAE_ENOTSPD, CAE_ENOCONV, CAE_EDEVICE = 0, -1, -2, -3, -4, -5
-RANK_EPS, RANK_FIXED = 0, 1
+RANK_EPS, RANK_FIXED, RANK_LEARNED = 0, 1, 2
+RECORD_WIDTH = 17
 FP64, FP32 = 0, 1
 ORDER_PAPER, ORDER_MULTICOLOUR = 0, 1
 
@@ -31,7 +32,8 @@ class Options(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("rank_mode", C.c_int32), ("fixed_rank", C.c_int32),
                 ("precision", C.c_int32), ("order", C.c_int32), ("max_levels", C.c_int32),
                 ("timing", C.c_int32), ("reserved", C.c_int32),
-                ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p)]
+                ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p), ("mlp_params", C.c_void_p),
+                ("seed", C.c_uint64), ("record", C.c_void_p), ("record_cap", C.c_int64)]
 
 
 class LevelInfo(C.Structure):
@@ -43,7 +45,8 @@ class Stats(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("coarse_dim", C.c_int64), ("tau", C.c_double),
                 ("dropped_sq", C.c_double), ("min_pivot", C.c_double), ("factor_bytes", C.c_int64),
                 ("factor_ms", C.c_double), ("compress_launches", C.c_int32), ("compress_ms", C.c_double),
-                ("compress_flops", C.c_double), ("compressions", C.c_int32)]
+                ("compress_flops", C.c_double), ("compressions", C.c_int32), ("sketch_accepted", C.c_int32),
+                ("sketch_rejected", C.c_int32), ("record_rows", C.c_int64)]
 
 
 _lib = None
@@ -53,7 +56,8 @@ EXPORTS = [
     "cae_analysis_level_info", "cae_analysis_level_arrays", "cae_analysis_perm", "cae_analysis_destroy",
     "cae_factor_numeric", "cae_apply_precond", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
     "cae_get_stats",
-    "cae_get_ranks", "cae_get_sizes", "cae_destroy",
+    "cae_get_ranks", "cae_get_sizes", "cae_destroy", "cae_mlp_param_count", "cae_mlp_train", "cae_mlp_loss_grad",
+    "cae_mlp_predict",
 ]
 
 
@@ -88,10 +92,15 @@ def lib():
     L.cae_get_sizes.argtypes = [p, i32, p]
     L.cae_destroy.argtypes = [p]
     L.cae_destroy.restype = None
+    L.cae_mlp_param_count.argtypes = []
+    L.cae_mlp_param_count.restype = i32
+    L.cae_mlp_train.argtypes = [p, i64, p, i32, C.c_float, C.POINTER(C.c_float), p]
+    L.cae_mlp_loss_grad.argtypes = [p, p, i64, p, C.POINTER(C.c_float), p]
+    L.cae_mlp_predict.argtypes = [p, p, i64, p, p]
     for name in ["cae_grid_order", "cae_analyze", "cae_analysis_levels", "cae_analysis_level_info",
                  "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_apply_precond",
                  "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
-                 "cae_get_sizes"]:
+                 "cae_get_sizes", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

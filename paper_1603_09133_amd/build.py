@@ -12,7 +12,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["symbolic.cpp", "factor_kernels.hip", "apply_kernels.hip", "runtime.hip"]
+SOURCES = ["symbolic.cpp", "factor_kernels.hip", "apply_kernels.hip", "mlp_kernels.hip", "runtime.hip"]
 LIB = os.path.join(HERE, "libcae.so")
 ARCH = os.environ.get("CAE_OFFLOAD_ARCH", "gfx950")
 

@@ -661,7 +661,9 @@ __global__ __launch_bounds__(WV) void k_compress_wave(LevelArgs<T> A, int32_t s0
 template <typename CT, typename T>
 __device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT* X, CT* R, int LD, const int* piv,
                                 double inactive, CT negl, CT aerr, CT* sg, CT* tau, int* posv, int* shi, double* shd,
-                                T* Ug, int wtot, int64_t t_start, int64_t t_qr, int64_t t_cmp) {
+                                T* Ug, int wtot, int64_t t_start, int64_t t_qr, int64_t t_cmp, int ncoord = -1,
+                                const CT* Qm = nullptr, double out2 = -1.0) {
+  if (ncoord < 0) ncoord = b;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // ---- 3. one-sided Jacobi on the ma rows of X ------------------------------
   const int mm = ma + (ma & 1);
@@ -691,7 +693,7 @@ __device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT*
       }
       CT a = 0, cc = 0, d = 0;
       if (p >= 0) {
-        for (int t = sub; t < b; t += LP) {
+        for (int t = sub; t < ncoord; t += LP) {
           const CT x = X[p * LD + t], y = X[q * LD + t];
           a += x * x;
           cc += y * y;
@@ -714,7 +716,7 @@ __device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT*
           else
             tt = (zeta >= CT(0) ? CT(1) : CT(-1)) / (fabs(zeta) + sqrt(CT(1) + zeta * zeta));
           const CT cs = CT(1) / sqrt(CT(1) + tt * tt), sn = cs * tt;
-          for (int t = sub; t < b; t += LP) {
+          for (int t = sub; t < ncoord; t += LP) {
             const CT x = X[p * LD + t], y = X[q * LD + t];
             X[p * LD + t] = cs * x - sn * y;
             X[q * LD + t] = sn * x + cs * y;
@@ -732,7 +734,7 @@ __device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT*
   if (wv == 0) {
     CT s2 = 0;
     if (lane < ma)
-      for (int t = 0; t < b; ++t) s2 += X[lane * LD + t] * X[lane * LD + t];
+      for (int t = 0; t < ncoord; ++t) s2 += X[lane * LD + t] * X[lane * LD + t];
     if (lane < ma) sg[lane] = sqrt(s2);
   }
   __syncthreads();
@@ -747,14 +749,49 @@ __device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT*
     const int cnt = __popcll(__ballot(lane < ma && (double)sg[lane] > theta));
     const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
     const double ed = wave_sum((lane < ma && pos >= r) ? (double)sg[lane] * (double)sg[lane] : 0.0);
+    // largest dropped singular value (the sketch's a-posteriori check)
+    double nx = (lane < ma && pos == r) ? (double)sg[lane] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) nx = fmax(nx, __shfl_xor(nx, o, WV));
     if (lane == 0) {
       shi[1] = r;
-      shd[2] = ed + inactive;
+      shd[2] = ed + inactive + (out2 > 0.0 ? out2 : 0.0);
+      shi[2] = (out2 >= 0.0 && out2 + nx * nx > theta * theta) ? 1 : 0;
     }
   }
   __syncthreads();
+  if (shi[2]) {   // sketch rejected: the exact compression takes the step
+    if (threadIdx.x == 0) {
+      A.need_exact[i] = 1;
+      atomicAdd(A.lcount + 1, 1);
+    }
+    return;
+  }
+  if (out2 >= 0.0 && threadIdx.x == 0) atomicAdd(A.lcount, 1);
   const int r = shi[1];
   const int kb = min(r, ma);
+  if (A.rec) {
+    // training label: the smallest sketch width k >= r that an ideal sketch
+    // would need to pass the check, tail(k) + (k > r ? sigma_r^2 : 0) <= theta^2,
+    // tail(k) = sum of sigma_j^2 over positions j >= k plus the inactive energy
+    if (wv == 0) {
+      if (lane < ma) tau[posv[lane]] = sg[lane] * sg[lane];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane == 0) {
+        const double th2 = (*A.theta) * (*A.theta);
+        const double sr2 = r < ma ? (double)tau[r] : 0.0;
+        double tail = inactive;
+        int kf = ma;
+        for (int k = ma; k >= r; --k) {   // tail = sum over positions >= k
+          if (k < ma) tail += (double)tau[k];
+          if (tail + (k > r ? sr2 : 0.0) <= th2) kf = k;
+        }
+        shi[3] = max(kf, r);
+      }
+    }
+    __syncthreads();
+  }
 
   // ---- 4. orthonormal completion ----------------------------------------------
   CT* Bv = R;   // R is free: the kept directions, then the reflectors
@@ -763,10 +800,16 @@ __device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT*
     const int c2 = posv[p];
     if (c2 < kb) {
       const CT inv = sg[p] > CT(0) ? CT(1) / sg[p] : CT(0);
-      if (t < b)
+      if (Qm) {          // sketch coordinates -> block coordinates
+        CT s = 0;
+        if (t < b)
+          for (int u = 0; u < ncoord; ++u) s += Qm[t * LD + u] * X[p * LD + u];
+        Bv[c2 * LD + t] = s * inv;
+      } else if (t < b) {
         Bv[c2 * LD + (piv ? piv[t] : t)] = X[p * LD + t] * inv;
-      else
+      } else {
         Bv[c2 * LD + t] = CT(0);
+      }
     }
   }
   __syncthreads();
@@ -823,6 +866,7 @@ __device__ void jacobi_basis_wg(const LevelArgs<T>& A, int i, int b, int ma, CT*
   if (tid == 0) {
     A.rank[i] = r;
     A.edrop[i] = shd[2];
+    if (A.rec) A.rec[(A.rec_off + i) * REC_W + NFEAT] = (float)shi[3] / (float)b;
     if (A.dbg) {
       int64_t* dd = A.dbg + 72 * (int64_t)i;
       dd[0] = ma;
@@ -860,6 +904,7 @@ __global__ __launch_bounds__(NT) void k_compress_wg(LevelArgs<T> A, int32_t s0) 
   constexpr int LD = WaveLd<64>::LD;
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
+  if (A.need_exact && !A.need_exact[i]) return;   // taken by the sketch kernel
   const int b = A.bsz[i];
   if (b > 64) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1436,6 +1481,28 @@ struct AccT {
   using type = double;
 };
 
+// C = A^T B with A (K x 64, type TA) and B (K x 64, type TB) in LDS, FP64 or
+// FP32 accumulation in TC (the same thread tiling as gemm_tn_4x4)
+template <typename TA, typename TB, typename TC>
+__device__ inline void gemm_tn_4x4m(const TA* A, const TB* B, int K, TC acc[4][4]) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const TA* a = A + 4 * ty;
+  const TB* bb = B + 4 * tx;
+#pragma unroll 2
+  for (int k = 0; k < K; ++k) {
+    TC av[4], bv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      av[q] = (TC)a[k * TLD + q];
+      bv[q] = (TC)bb[k * TLD + q];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] += av[p] * bv[q];
+  }
+}
+
 template <typename T>
 __device__ inline void zero_acc(T acc[4][4]) {
 #pragma unroll
@@ -1636,6 +1703,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0) {
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
+  if (A.need_exact && !A.need_exact[i]) return;   // taken by the sketch kernel
   const int b = A.bsz[i];
   if (b > 64) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ty = tid >> 4, tx = tid & 15;
@@ -1768,6 +1836,397 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
   const int64_t t_cmp = clock64();
   jacobi_basis_wg<double, T>(A, i, b, ma, X, G, GLD, nullptr, inactive, negl, aerr, sg, tau, posv, shi, shd, Ug,
                              wtot, t_start, t_qr, t_cmp);
+}
+
+// ---------------------------------------------------------------------------
+// Learned-rank compression (b <= 64): the cheaper rank-revealing variant of
+// eq. (rreav).  One 256-thread workgroup per step, FP64 arithmetic:
+//   1. features of the far row (Frobenius norms of the row and of its far
+//      blocks against theta, widths, neighbour ranks: all invariant under the
+//      rotations inside kept bases that leave the method unchanged);
+//   2. MLP 16 -> 64 -> 64 -> 1 (ReLU) predicts z ~ r/b, k = ceil(b z);
+//   3. sketch Y = F Omega with l = min(k + p, b, w) columns, Omega drawn by
+//      Philox4x32-10 (counter (column of F, j/2, block, level), key seed),
+//      Box-Muller in FP64;
+//   4. Q = orth(Y) (Householder), B = Q^T F, H = B B^T (l x l);
+//   5. pivoted Cholesky + one-sided Jacobi on H give sigma(B) and its left
+//      singular vectors; r = #{sigma > theta}; accept when
+//      ||F||_F^2 - ||B||_F^2 + sigma_{r+1}^2 <= theta^2 (then ||E_i||_2 <=
+//      theta), else flag the step for the exact kernel.
+// With feat_only the kernel records the features and flags every step.
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// the two normals of sketch entries (m, 2 jp) and (m, 2 jp + 1)
+__device__ inline void sketch_pair(uint64_t seed, int level, int block, int m, int jp, double& n0, double& n1) {
+  uint32_t c[4] = {(uint32_t)m, (uint32_t)jp, (uint32_t)block, (uint32_t)level};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double ua = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) / 9007199254740992.0;
+  const double ub = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) / 9007199254740992.0;
+  const double rad = sqrt(-2.0 * log(ua));
+  n0 = rad * cos(6.283185307179586 * ub);
+  n1 = rad * sin(6.283185307179586 * ub);
+}
+
+__device__ inline double clog10(double v, double theta) {
+  return fmin(fmax(log10(fmax(v, 1e-300) / theta), -30.0), 30.0);
+}
+
+template <typename T>
+size_t work_compress_rand() {
+  return (size_t)4 * 64 * TLD * sizeof(double) + (size_t)(4 * 64 + 3 * 64 + 64 + 16) * sizeof(double) +
+         64 * sizeof(int);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_compress_rand(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ty = tid >> 4, tx = tid & 15;
+  T* Ug = A.U + A.u_off[i];
+  if (tid == 0) A.need_exact[i] = 0;
+  if (A.rec && tid < REC_W) A.rec[(A.rec_off + i) * REC_W + tid] = tid < NFEAT ? 0.0f : -1.0f;
+  if (b > 64 || A.feat_only && (st.nfar == 0 || b == 0)) {
+    if (tid == 0) A.need_exact[i] = 1;
+    return;
+  }
+  if (st.nfar == 0 || b == 0) {
+    for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
+    if (tid == 0) {
+      A.rank[i] = 0;
+      A.edrop[i] = 0.0;
+    }
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* R1 = reinterpret_cast<double*>(smem_raw);   // F tiles (type T)
+  double* R2 = R1 + 64 * TLD;                          // Omega tiles (T), then B^T tiles, then Jacobi rows
+  double* YQ = R2 + 64 * TLD;                          // Y, Householder vectors, then H, then kept vectors
+  double* Qx = YQ + 64 * TLD;                          // explicit Q (b x l)
+  double* red = Qx + 64 * TLD;                         // 4 x 64 partial sums
+  double* sg = red + 4 * 64;
+  double* tau = sg + 64;
+  double* lc = tau + 64;
+  double* hbuf = lc + 64;                              // hidden layer
+  double* xf = hbuf + 64;                              // 16 features
+  int* posv = reinterpret_cast<int*>(xf + 16);
+  __shared__ double shd[8];
+  __shared__ int shi[8];
+  T* Fs = reinterpret_cast<T*>(R1);
+  T* Os = reinterpret_cast<T*>(R2);
+  const double theta = *A.theta;
+  const int64_t t_start = clock64();
+
+  // ---- 1. features ------------------------------------------------------------
+  double racc = 0.0, cmax2 = 0.0, bsum4 = 0.0;   // squared block norms: max, sum of squares, count above theta
+  int ccnt = 0, wtot = 0, nproc = 0;
+  double prs = 0.0, pss = 0.0;
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    wtot += w;
+    if (v.proc) {
+      ++nproc;
+      prs += A.rank[v.x];
+      pss += bx;
+    }
+    double blk = 0.0;   // this thread's part of the block's squared norm
+    for (int c0 = 0; c0 < w; c0 += 64) {
+      const int mc = min(64, w - c0);
+      __syncthreads();
+      load_view_tile(Fs, base, v.trans, b, bx, 0, b, c0, mc);
+      __syncthreads();
+      if (lane < b)
+        for (int m = wv; m < mc; m += 4) {
+          const double x = (double)Fs[lane * TLD + m];
+          racc += x * x;
+          blk += x * x;
+        }
+    }
+    // block norm: reduce blk over the workgroup (uniform control flow)
+    __syncthreads();
+    blk = wave_sum(blk);
+    if (lane == 0) red[wv] = blk;
+    __syncthreads();
+    const double bn2 = red[0] + red[1] + red[2] + red[3];
+    cmax2 = fmax(cmax2, bn2);
+    ccnt += bn2 > theta * theta ? 1 : 0;
+    bsum4 += bn2 * bn2;
+    __syncthreads();
+  }
+  red[wv * 64 + lane] = racc;
+  __syncthreads();
+  {
+    // column statistics: block reductions through red (after the row sums are read)
+    double rn2 = 0.0;
+    if (wv == 0) rn2 = red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
+    __syncthreads();
+    // cmax2 and ccnt are uniform over the workgroup (block norms)
+    if (wv == 0) {
+      const double fro2 = wave_sum(lane < b ? rn2 : 0.0);
+      const double cmx2 = cmax2;
+      const double ccn = (double)ccnt;
+      if (lane == 0) {
+        const double cmax = sqrt(cmx2), fro = sqrt(fro2);
+        xf[0] = log2((double)b + 1.0);
+        xf[1] = log2((double)wtot + 1.0);
+        xf[2] = (double)A.level;
+        xf[3] = (double)st.nfar;
+        xf[4] = (double)st.nclose;
+        xf[5] = clog10(fro, theta);
+        xf[6] = clog10(sqrt(fro2 / max(b, 1)), theta);
+        xf[7] = clog10(cmax, theta);
+        xf[8] = clog10(sqrt(fro2 / max(wtot, 1)), theta);
+        xf[9] = ccn / (double)max(st.nfar, 1);
+        xf[10] = fro2 > 0.0 ? bsum4 / (fro2 * fro2) : 0.0;
+        xf[11] = cmx2 > 0.0 ? fro2 / (cmx2 * st.nfar) : 0.0;
+        xf[12] = (double)nproc / (double)max(st.nfar, 1);
+        xf[13] = pss > 0.0 ? prs / pss : 0.0;
+        xf[14] = b / 64.0;
+        xf[15] = 1.0;
+        shd[0] = fro2;
+      }
+    }
+  }
+  __syncthreads();
+  if (A.rec && tid < NFEAT) A.rec[(A.rec_off + i) * REC_W + tid] = (float)xf[tid];
+  if (A.feat_only) {
+    if (tid == 0) A.need_exact[i] = 1;
+    return;
+  }
+  const double fro2 = shd[0];
+
+  // ---- 2. rank prediction ----------------------------------------------------
+  if (wv == 0) {
+    const float* P = A.mlp;
+    double h = P[MLP_OFF_B1 + lane];
+    for (int k = 0; k < NFEAT; ++k)
+      h += (double)P[MLP_OFF_W1 + lane * NFEAT + k] * ((xf[k] - (double)P[MLP_OFF_MEAN + k]) / (double)P[MLP_OFF_STD + k]);
+    hbuf[lane] = fmax(h, 0.0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double h2 = P[MLP_OFF_B2 + lane];
+    for (int k = 0; k < MLP_H; ++k) h2 += (double)P[MLP_OFF_W2 + lane * MLP_H + k] * hbuf[k];
+    h2 = fmax(h2, 0.0);
+    const double z = wave_sum((double)P[MLP_OFF_W3 + lane] * h2) + (double)P[MLP_OFF_B3];
+    if (lane == 0) {
+      const double bz = z * b;
+      int k = (bz == bz) ? (int)fmin(fmax(ceil(bz), 0.0), (double)b) : b;
+      shi[0] = min(min(k + SKETCH_OVERSAMPLE, b), min(wtot, 64));
+    }
+  }
+  __syncthreads();
+  const int l = shi[0];
+
+  // ---- 3. sketch Y = F Omega ----------------------------------------------------
+  double acc[4][4];
+  zero_acc(acc);
+  int mbase = 0;
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    for (int c0 = 0; c0 < w; c0 += 64) {
+      const int mc = min(64, w - c0);
+      __syncthreads();
+      if (v.trans) {
+        for (int e = tid; e < mc * b; e += NT) {
+          const int m = e / b, a = e % b;
+          Fs[m * TLD + a] = base[(int64_t)(c0 + m) * b + a];
+        }
+      } else {
+        for (int e = tid; e < mc * b; e += NT) {
+          const int a = e / mc, m = e % mc;
+          Fs[m * TLD + a] = base[(int64_t)a * bx + c0 + m];
+        }
+      }
+      const int np = (l + 1) >> 1;
+      for (int e = tid; e < mc * np; e += NT) {
+        const int m = e / np, jp = e % np;
+        double n0, n1;
+        sketch_pair(A.seed, A.level, i, mbase + c0 + m, jp, n0, n1);
+        Os[m * TLD + 2 * jp] = (T)n0;
+        if (2 * jp + 1 < l) Os[m * TLD + 2 * jp + 1] = (T)n1;
+      }
+      __syncthreads();
+      gemm_tn_4x4m(Fs, Os, mc, acc);
+    }
+    mbase += w;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) YQ[(4 * ty + p) * TLD + 4 * tx + q] = acc[p][q];
+  __syncthreads();
+  const int64_t t_qr = clock64();
+
+  // ---- 4a. Householder QR of Y (b x l), explicit Q ----------------------------
+  const int nref = min(l, b);
+  for (int k = 0; k < nref; ++k) {
+    if (wv == 0) {
+      const double x = (lane >= k && lane < b) ? YQ[lane * TLD + k] : 0.0;
+      const double nrm2 = wave_sum(x * x);
+      const double x0 = __shfl(x, k, WV);
+      double tq = 0.0;
+      if (nrm2 > 1e-290) {
+        const double nrm = sqrt(nrm2);
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double vv = v0 * v0 + (nrm2 - x0 * x0);
+        tq = vv > 0.0 ? 2.0 / vv : 0.0;
+        if (lane == k) YQ[k * TLD + k] = v0;
+      }
+      if (lane == 0) tau[k] = tq;
+    }
+    __syncthreads();
+    {
+      const int j = k + 1 + (tid >> 2), pt = tid & 3;
+      const double tq = tau[k];
+      double dd = 0.0;
+      if (j < l)
+        for (int a = k + pt; a < b; a += 4) dd += YQ[a * TLD + k] * YQ[a * TLD + j];
+      dd += __shfl_xor(dd, 1, WV);
+      dd += __shfl_xor(dd, 2, WV);
+      if (j < l && tq != 0.0)
+        for (int a = k + pt; a < b; a += 4) YQ[a * TLD + j] -= tq * dd * YQ[a * TLD + k];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 64 * 64; e += NT) Qx[(e >> 6) * TLD + (e & 63)] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = nref - 1; k >= 0; --k) {
+    const int j = tid >> 2, pt = tid & 3;
+    const double tq = tau[k];
+    double dd = 0.0;
+    if (j < l && tq != 0.0)
+      for (int a = k + pt; a < b; a += 4) dd += YQ[a * TLD + k] * Qx[a * TLD + j];
+    dd += __shfl_xor(dd, 1, WV);
+    dd += __shfl_xor(dd, 2, WV);
+    if (j < l && tq != 0.0)
+      for (int a = k + pt; a < b; a += 4) Qx[a * TLD + j] -= tq * dd * YQ[a * TLD + k];
+    __syncthreads();
+  }
+
+  // ---- 4b. B = Q^T F, H = B B^T ------------------------------------------------
+  double accH[4][4];
+  zero_acc(accH);
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    for (int c0 = 0; c0 < w; c0 += 64) {
+      const int mc = min(64, w - c0);
+      __syncthreads();
+      load_view_tile(Fs, base, v.trans, b, bx, 0, b, c0, mc);
+      __syncthreads();
+      zero_acc(acc);
+      gemm_tn_4x4m(Qx, Fs, b, acc);   // acc[p][q] = B[4ty+p][4tx+q]
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) R2[(4 * tx + q) * TLD + 4 * ty + p] = (4 * tx + q < mc) ? acc[p][q] : 0.0;
+      __syncthreads();
+      gemm_tn_4x4m(R2, R2, mc, accH);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) YQ[(4 * ty + p) * TLD + 4 * tx + q] = accH[p][q];
+  __syncthreads();
+
+  // ---- 5. pivoted Cholesky of H, rows into R2 ------------------------------------
+  double* G = YQ;
+  double* X = R2;
+  if (wv == 0) {
+    const double gd = lane < l ? G[lane * TLD + lane] : 0.0;
+    const double tr = wave_sum(gd);
+    lc[lane] = gd;   // trailing diagonal
+    posv[lane] = 0;  // chosen flags
+    if (lane == 0) shd[1] = tr;
+  }
+  __syncthreads();
+  const double out2 = fmax(fro2 - shd[1], 0.0);
+  const double noise = (double)Eps<T>::v() * sqrt(fro2);
+  const double negl = A.rank_mode == 0 ? fmax(noise, theta / 64.0) : noise;
+  const double aerr = A.rank_mode == 0 ? fmax(noise, fmin((double)max(b, 16) * noise, theta / 32.0))
+                                       : (double)max(b, 16) * noise;
+  const double stop2 = aerr * aerr;
+  int k = 0;
+  for (; k < l; ++k) {
+    if (wv == 0) {
+      const bool in = lane < l && !posv[lane];
+      const double dv = in ? lc[lane] : 0.0;
+      const double rs = wave_sum(dv);
+      double cv = in ? dv : -1.0;
+      int ci = lane;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(cv, o, WV);
+        const int oi = __shfl_xor(ci, o, WV);
+        if (ov > cv || (ov == cv && oi < ci)) {
+          cv = ov;
+          ci = oi;
+        }
+      }
+      const bool stop = rs <= stop2 || !(cv > 0.0);
+      if (lane == 0) {
+        shi[3] = stop ? 1 : 0;
+        shd[2] = rs;
+        if (!stop) {
+          shi[2] = ci;
+          shd[3] = sqrt(cv);
+          posv[ci] = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (shi[3]) break;
+    const int p = shi[2];
+    const double lpp = shd[3];
+    if (tid < 64) {
+      const int t = tid;
+      const double lv = t >= l ? 0.0 : (t == p ? lpp : (posv[t] ? 0.0 : G[t * TLD + p] / lpp));
+      tau[t] = lv;
+      X[k * TLD + t] = lv;
+    }
+    __syncthreads();
+    for (int t = ty; t < l; t += 16) {
+      const double lt = tau[t];
+      for (int u = tx; u < l; u += 16) {
+        const double g = G[t * TLD + u] - lt * tau[u];
+        G[t * TLD + u] = g;
+        if (u == t) lc[t] = g;
+      }
+    }
+    __syncthreads();
+  }
+  const int ma = k;
+  const double inactive = k < l ? shd[2] : 0.0;
+  const int64_t t_cmp = clock64();
+  __syncthreads();
+  jacobi_basis_wg<double, T>(A, i, b, ma, X, YQ, TLD, nullptr, inactive, negl, aerr, sg, tau, posv, shi, shd, Ug,
+                             wtot, t_start, t_qr, t_cmp, l, Qx, out2);
 }
 
 // V_ix <- U_i^T V_ix (far views keep rows 0..r_i-1), D_i <- U_i^T D_i U_i.
@@ -2192,6 +2651,10 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
   T* gs = gscratch;
   if (w.s1 > w.s0) {
     const int ns = w.s1 - w.s0;
+    // learned ranks (or feature recording): the sketch kernel first; the exact
+    // kernels then take only the steps it flags in need_exact
+    if (A.mlp || A.feat_only)
+      hipLaunchKernelGGL(k_compress_rand<T>, dim3(ns), dim3(NT), work_compress_rand<T>(), stream, A, w.s0);
     const size_t wg = work_compress_wg<T>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
     const size_t wgr = work_compress_gram<T>();
     if (sizeof(T) < sizeof(double) && wgr <= max_lds_bytes())

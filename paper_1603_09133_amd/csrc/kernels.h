@@ -36,7 +36,26 @@ struct LevelArgs {
   int32_t fixed_rank;
   int64_t* dbg;             // optional per-block compression counters (8 per block) or null
   int32_t small_by_wave;    // blocks of at most this size are compressed by the wavefront kernel
+  // learned-rank compression (sketch + MLP) and training-data recording
+  const float* mlp;         // MLP parameters (MLP_NPARAM floats) or null
+  uint64_t seed;            // Philox key of the sketches
+  int32_t level;            // level index (0-based), part of the sketch counter
+  int32_t feat_only;        // 1: the sketch kernel only records features and defers every step
+  float* rec;               // REC_W floats per block: 16 features, label r/b (or -1), or null
+  int64_t rec_off;          // first record row of this level
+  int32_t* need_exact;      // per block: 1 = the exact compression must take the step, or null
+  int32_t* lcount;          // [0] sketches accepted, [1] sketches rejected
 };
+
+// learned rank: feature count, record width, MLP parameter layout (floats):
+// mean[16], std[16], W1[64x16], b1[64], W2[64x64], b2[64], w3[64], b3
+constexpr int NFEAT = 16;
+constexpr int REC_W = NFEAT + 1;
+constexpr int MLP_H = 64;
+constexpr int MLP_OFF_MEAN = 0, MLP_OFF_STD = 16, MLP_OFF_W1 = 32, MLP_OFF_B1 = MLP_OFF_W1 + MLP_H * NFEAT,
+              MLP_OFF_W2 = MLP_OFF_B1 + MLP_H, MLP_OFF_B2 = MLP_OFF_W2 + MLP_H * MLP_H,
+              MLP_OFF_W3 = MLP_OFF_B2 + MLP_H, MLP_OFF_B3 = MLP_OFF_W3 + MLP_H, MLP_NPARAM = MLP_OFF_B3 + 1;
+constexpr int SKETCH_OVERSAMPLE = 8;
 
 struct WaveRange {
   int32_t s0, s1;   // steps
@@ -150,5 +169,13 @@ void launch_copy_cols(int64_t n, int32_t nrhs, const double* a, int64_t lda, dou
 void launch_fill(double* a, int64_t count, double v, hipStream_t stream);
 // r = b - r (true residual after r = A x)
 void launch_residual(int64_t n, int32_t nrhs, const double* b, int64_t ldb, double* r, hipStream_t stream);
+
+// ------------------------------------------------------- rank MLP training ---
+void launch_mlp_stats(const float* rec, int64_t n, float* P, int* nvalid, hipStream_t s);
+void launch_mlp_predict(const float* P, const float* rec, int64_t n, float* z, hipStream_t s);
+void launch_mlp_grad(const float* P, const float* rec, int64_t n, float inv_n, float* grad, float* loss,
+                     hipStream_t s);
+void launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, int step, hipStream_t s);
+void launch_mlp_zero(float* a, int n, hipStream_t s);
 
 }  // namespace cae

@@ -182,6 +182,7 @@ struct NumLevel {
   std::vector<int32_t> off_in_parent;
   std::vector<cae::WaveRange> waves;
   DevBuf arena, U, Li, bsz, d_slot_off, d_u_off, d_dof_off, d_off_in_parent, rank, edrop, minpiv;
+  DevBuf need_exact;   // learned ranks: steps the exact compression takes
 };
 
 }  // namespace
@@ -207,6 +208,9 @@ struct cae_factor_s {
   int32_t pcg_nrhs = 0;
   DevBuf pr, pz, pp, pq, sc, act, partial;
   DevBuf mr[7], mst;   // MINRES vectors and per-column scalars
+  DevBuf lcount;       // sketches accepted / rejected
+  int64_t rec_rows = 0;
+  int32_t sketch_acc = 0, sketch_rej = 0;
 };
 
 namespace {
@@ -292,6 +296,14 @@ cae::LevelArgs<T> level_args(cae_factor_s* h, int l) {
   A.fixed_rank = h->opt.fixed_rank;
   A.dbg = nullptr;
   A.small_by_wave = 0;
+  A.mlp = nullptr;
+  A.seed = 0;
+  A.level = l;
+  A.feat_only = 0;
+  A.rec = nullptr;
+  A.rec_off = 0;
+  A.need_exact = nullptr;
+  A.lcount = nullptr;
   return A;
 }
 
@@ -327,6 +339,9 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
   h->theta.alloc(2 * sizeof(double));
   h->err.alloc(2 * sizeof(int32_t));
   HIPCHK(hipMemsetAsync(h->err.p, 0, 2 * sizeof(int32_t), s));
+  h->lcount.alloc(2 * sizeof(int32_t));
+  HIPCHK(hipMemsetAsync(h->lcount.p, 0, 2 * sizeof(int32_t), s));
+  h->rec_rows = 0;
   cae::launch_theta(h->vals.as<double>(), AN->diag_pos.as<int64_t>(), a.n, eps, h->theta.as<double>(), s);
 
   h->lev.clear();
@@ -364,6 +379,23 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       gs = h->gscratch.as<T>();
     }
     cae::LevelArgs<T> A = level_args<T>(h, l);
+    if (h->opt.rank_mode == CAE_RANK_LEARNED || h->opt.record) {
+      N.need_exact.alloc((size_t)L.M * sizeof(int32_t));
+      A.need_exact = N.need_exact.as<int32_t>();
+      A.lcount = h->lcount.as<int32_t>();
+      A.seed = h->opt.seed;
+      if (h->opt.rank_mode == CAE_RANK_LEARNED) {
+        A.mlp = h->opt.mlp_params;
+        A.rank_mode = 0;   // the kept rank is the threshold rank of the sketch
+      }
+      if (h->opt.record) {
+        if (h->rec_rows + L.M > h->opt.record_cap) return fail(CAE_EINVAL, "record buffer too small");
+        A.rec = h->opt.record;
+        A.rec_off = h->rec_rows;
+        A.feat_only = h->opt.rank_mode == CAE_RANK_LEARNED ? 0 : 1;
+        h->rec_rows += L.M;
+      }
+    }
     // optional compression counters (environment CAE_DEBUG_COMPRESS=1)
     static const bool dbg_on = getenv("CAE_DEBUG_COMPRESS") != nullptr;
     DevBuf dbgbuf;
@@ -515,6 +547,13 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     bytes += (h->lev[k].slot_off.back() + h->lev[k].u_off.back()) * (int64_t)sizeof(T);
   bytes += dim * dim * (int64_t)sizeof(double);
   h->factor_bytes = bytes;
+  {
+    int32_t lc[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(lc, h->lcount.p, sizeof(lc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->sketch_acc = lc[0];
+    h->sketch_rej = lc[1];
+  }
   h->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return CAE_OK;
 }
@@ -738,7 +777,12 @@ int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const 
     o = *opt;
   }
   if (o.precision != CAE_FP64 && o.precision != CAE_FP32) return fail(CAE_EINVAL, "unknown precision");
-  if (o.rank_mode != CAE_RANK_EPS && o.rank_mode != CAE_RANK_FIXED) return fail(CAE_EINVAL, "unknown rank mode");
+  if (o.rank_mode != CAE_RANK_EPS && o.rank_mode != CAE_RANK_FIXED && o.rank_mode != CAE_RANK_LEARNED)
+    return fail(CAE_EINVAL, "unknown rank mode");
+  if (o.rank_mode == CAE_RANK_LEARNED && (!o.mlp_params || !(eps > 0.0)))
+    return fail(CAE_EINVAL, "learned ranks need mlp_params and eps > 0");
+  if (o.record && (o.record_cap <= 0 || o.rank_mode == CAE_RANK_FIXED))
+    return fail(CAE_EINVAL, "record needs record_cap > 0 and a threshold rank mode");
   if (o.rank_mode == CAE_RANK_FIXED && o.fixed_rank < 0) return fail(CAE_EINVAL, "fixed_rank must be >= 0");
   if (o.order != an->a.order_kind) return fail(CAE_EINVAL, "order differs from the analysis");
   try {
@@ -1013,6 +1057,84 @@ int cae_get_stats(cae_handle_t h, cae_stats_t* st) {
   st->compress_ms = h->compress_ms;
   st->compress_flops = h->compress_flops;
   st->compressions = h->compressions;
+  st->sketch_accepted = h->sketch_acc;
+  st->sketch_rejected = h->sketch_rej;
+  st->record_rows = h->rec_rows;
+  return CAE_OK;
+}
+
+int32_t cae_mlp_param_count(void) { return cae::MLP_NPARAM; }
+
+int cae_mlp_train(const float* records, int64_t n, float* params, int32_t epochs, float lr, float* loss,
+                  void* stream) {
+  if (!records || !params || n <= 0 || epochs < 0 || !(lr > 0.0f)) return fail(CAE_EINVAL, "bad MLP training arguments");
+  hipStream_t s = (hipStream_t)stream;
+  g_cur_stream = s;
+  try {
+    DevBuf grad, m, v, lossd, nv;
+    grad.alloc(cae::MLP_NPARAM * sizeof(float));
+    m.alloc(cae::MLP_NPARAM * sizeof(float));
+    v.alloc(cae::MLP_NPARAM * sizeof(float));
+    lossd.alloc(sizeof(float));
+    nv.alloc(sizeof(int));
+    cae::launch_mlp_zero(m.as<float>(), cae::MLP_NPARAM, s);
+    cae::launch_mlp_zero(v.as<float>(), cae::MLP_NPARAM, s);
+    cae::launch_mlp_stats(records, n, params, nv.as<int>(), s);
+    int nvalid = 0;
+    HIPCHK(hipMemcpyAsync(&nvalid, nv.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (nvalid == 0) return fail(CAE_EINVAL, "no training rows (all labels negative)");
+    for (int e = 0; e < epochs; ++e) {
+      cae::launch_mlp_grad(params, records, n, 1.0f / (float)nvalid, grad.as<float>(), lossd.as<float>(), s);
+      cae::launch_mlp_adam(params, grad.as<float>(), m.as<float>(), v.as<float>(), lr, e + 1, s);
+    }
+    float hl = 0.0f;
+    cae::launch_mlp_grad(params, records, n, 1.0f / (float)nvalid, grad.as<float>(), lossd.as<float>(), s);
+    HIPCHK(hipMemcpyAsync(&hl, lossd.p, sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (loss) *loss = hl;
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return CAE_OK;
+}
+
+int cae_mlp_loss_grad(const float* params, const float* records, int64_t n, float* grad, float* loss, void* stream) {
+  if (!records || !params || !grad || n <= 0) return fail(CAE_EINVAL, "bad MLP gradient arguments");
+  hipStream_t s = (hipStream_t)stream;
+  g_cur_stream = s;
+  try {
+    // count the valid rows on the device through the statistics kernel (on a copy of the parameters)
+    DevBuf tmp, lossd, nv;
+    tmp.alloc(cae::MLP_NPARAM * sizeof(float));
+    lossd.alloc(sizeof(float));
+    nv.alloc(sizeof(int));
+    cae::launch_mlp_stats(records, n, tmp.as<float>(), nv.as<int>(), s);
+    int nvalid = 0;
+    HIPCHK(hipMemcpyAsync(&nvalid, nv.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (nvalid == 0) return fail(CAE_EINVAL, "no training rows (all labels negative)");
+    cae::launch_mlp_grad(params, records, n, 1.0f / (float)nvalid, grad, lossd.as<float>(), s);
+    float hl = 0.0f;
+    HIPCHK(hipMemcpyAsync(&hl, lossd.p, sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (loss) *loss = hl;
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return CAE_OK;
+}
+
+int cae_mlp_predict(const float* params, const float* records, int64_t n, float* z, void* stream) {
+  if (!records || !params || !z || n < 0) return fail(CAE_EINVAL, "bad MLP prediction arguments");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    cae::launch_mlp_predict(params, records, n, z, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
   return CAE_OK;
 }
 

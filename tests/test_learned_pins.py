@@ -140,3 +140,18 @@ def test_learned_mode_with_exact_predictor_matches_exact_ranks():
     for a, b in zip(fe.levels, fl.levels):
         assert np.array_equal(a.r, b.r)
         assert b.fallbacks == 0
+
+
+def test_sketch_label_is_the_smallest_passing_width():
+    theta = 1.0
+    sig = np.array([5.0, 3.0, 0.9, 0.5, 0.3, 0.1])
+    r = 2
+    k = L.sketch_label(sig, r, theta)
+    tail = lambda kk: float(np.sum(sig[kk:] ** 2))
+    ok = lambda kk: tail(kk) + (sig[r] ** 2 if kk > r else 0.0) <= theta ** 2
+    assert ok(k) and all(not ok(kk) for kk in range(r, k))
+    # an ideal sketch of that width passes the randomized check
+    F, s = _low_rank_far_row(12, 40, sig, 4)
+    kk = L.sketch_label(s, int(np.count_nonzero(s > theta)), theta)
+    ok2, Ur, rr, sb, e = L.randomized_compress(F, theta, kk, seed=2, level=0, block=0, p=12)
+    assert ok2
