@@ -71,6 +71,7 @@ class CEOptions:
     mlp_params: object = None       # learned: FP32 parameter vector of the rank MLP
     seed: int = 0                   # learned: Philox key of the sketches
     record_features: bool = False   # compute the learned-mode features in any mode (tests only)
+    compensate: bool = False        # add |E_i| to the diagonals (keeps M - A0 positive semidefinite)
     order: str = "paper"            # 'paper' | 'multicolour'
     coarse_max_dim: int = 2048
     max_levels: int = 0             # 0 = no limit
@@ -245,7 +246,17 @@ def _factor_level(level_no, sizes, W: _Blocks, close_pairs, order, theta, opts):
         for k in lrows[i]:
             lf.panel[k][i] = U.T @ lf.panel[k][i]
         for l in fl:
-            W.get(i, l)[r:, :] = 0.0
+            blk = W.get(i, l)
+            if opts.compensate and b - r > 0:
+                # diagonal compensation of the dropped E_i (robustness option,
+                # not in the paper): |e_pq| onto the diagonal of row p (block
+                # i) and of column q (block l), so M - A0 gains the positive
+                # semidefinite [[diag(|E| 1), -E], [-E^T, diag(|E|^T 1)]]
+                aE = np.abs(blk[r:, :])
+                Dl = W.get(l, l)
+                D[np.arange(r, b), np.arange(r, b)] += aE.sum(axis=1)
+                Dl[np.arange(Dl.shape[0]), np.arange(Dl.shape[0])] += aE.sum(axis=0)
+            blk[r:, :] = 0.0
         # 4. elimination of the trailing b - r rotated rows
         n = slice(r, b)
         kb = slice(0, r)

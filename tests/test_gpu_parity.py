@@ -207,3 +207,33 @@ def test_fixed_rank_paper_parameters_converge():
     b = problems.rhs_uniform(A.shape[0], 0)
     x, it, rel = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-8)
     assert f.converged and rel[0] <= 1.0001e-8
+
+
+@pytest.mark.parametrize("dims,patch,eps", [((40, 24), (8, 8), 1e-6), ((8, 8, 8), (2, 2, 2), 1e-4)])
+def test_bf16_schur_factor(dims, patch, eps):
+    """FP32 factor with BF16-input Schur products (FP32 accumulation on the
+    matrix cores): M stays within BF16 rounding of the FP64 oracle (each
+    product entry carries a relative error of about 2^-8 of its inputs),
+    eps = 0 gives A within that rounding, and PCG to 1e-8 converges with at
+    most a few iterations more than the FP64 factor."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup(dims, patch)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order="multicolour", coarse_max_dim=0))
+    an, f = _gpu_factor(cae, csr, perm, bp, co, eps, "multicolour", precision=cae.FP32_BF16, coarse=0)
+    X = _probes(A.shape[0])
+    MX = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    MXo = ce_multiply(fo, X)
+    rel = np.linalg.norm(MX - MXo) / np.linalg.norm(MXo)
+    assert rel <= 2e-3, rel
+    b = problems.rhs_uniform(A.shape[0], seed=0)
+    _, it, relr = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-8)
+    _, ito, _ = oracle.pcg(A, b, lambda r: ce_solve(fo, r), tol=1e-8)
+    assert f.converged and relr[0] <= 1.0001e-8
+    assert it[0] <= ito + 6, (it[0], ito)
+    f.close()
+    f0 = cae.Factor(an, torch.from_numpy(csr[2]).cuda(), 0.0, precision=cae.FP32_BF16, coarse_max_dim=0)
+    A0X = A @ X
+    M0X = _from_gpu_cols(f0.multiply(_to_gpu_cols(X)))
+    assert np.linalg.norm(M0X - A0X) <= 2e-3 * np.linalg.norm(A0X)
+    f0.close()
+    an.close()

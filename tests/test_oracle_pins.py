@@ -24,6 +24,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
+import oracle
 import problems
 from oracle import (CEOptions, NotSPD, ce_dense, ce_factor, ce_multiply, ce_solve,
                     grid_order, level1_pattern, pcg, simulate_level, coarsen,
@@ -323,3 +324,38 @@ def test_four_node_example():
     # ||A0 - M|| = sqrt(2 sum e)
     M = ce_dense(f)
     assert abs(np.linalg.norm(A0 - M) - math.sqrt(2 * f.dropped())) <= 1e-12
+
+
+def _biharmonic(n):
+    L = problems.laplacian((n, n))
+    B = (L @ L).tocsr()
+    B.sort_indices()
+    return B
+
+
+def test_compensation_keeps_m_minus_a_psd_and_prevents_breakdown():
+    """Diagonal compensation of the dropped E_i adds, per step, the positive
+    semidefinite [[diag(|E| 1), -E], [-E^T, diag(|E|^T 1)]] to A0, so M - A0
+    is positive semidefinite and no pivot can fail.  The biharmonic operator
+    (not an M-matrix) breaks the plain method at eps = 1e-3."""
+    B = _biharmonic(32)
+    csr = problems.to_csr_arrays(B)
+    perm, bp, co = oracle.grid_order((32, 32), (4, 4))
+    with pytest.raises(oracle.NotSPD):
+        ce_factor(*csr, perm, bp, co, CEOptions(eps=1e-3, order="multicolour", coarse_max_dim=0))
+    f = ce_factor(*csr, perm, bp, co, CEOptions(eps=1e-3, order="multicolour", coarse_max_dim=0, compensate=True))
+    M = ce_dense(f)
+    Bd = B.toarray()
+    assert np.linalg.eigvalsh(M - Bd)[0] >= -1e-12 * np.linalg.norm(Bd)
+    assert np.linalg.norm(M - Bd) > 0
+    b = problems.rhs_uniform(B.shape[0])
+    _, it, rel = oracle.pcg(B, b, lambda r: ce_solve(f, r), tol=1e-8)
+    assert rel <= 1e-8 and it < 100
+
+
+def test_compensation_vanishes_at_eps_zero():
+    B = _biharmonic(16)
+    csr = problems.to_csr_arrays(B)
+    perm, bp, co = oracle.grid_order((16, 16), (4, 4))
+    f = ce_factor(*csr, perm, bp, co, CEOptions(eps=0.0, order="multicolour", coarse_max_dim=0, compensate=True))
+    assert np.linalg.norm(ce_dense(f) - B.toarray()) <= 1e-12 * np.linalg.norm(B.toarray())
