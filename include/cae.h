@@ -48,7 +48,9 @@ typedef enum {
 } cae_status_t;
 
 typedef enum { CAE_RANK_EPS = 0, CAE_RANK_FIXED = 1, CAE_RANK_LEARNED = 2 } cae_rank_mode_t;
-typedef enum { CAE_FP64 = 0, CAE_FP32 = 1 } cae_precision_t;
+/* FP32_BF16: FP32 factor whose Schur-complement products take BF16 inputs
+ * with FP32 accumulation on the matrix cores */
+typedef enum { CAE_FP64 = 0, CAE_FP32 = 1, CAE_FP32_BF16 = 2 } cae_precision_t;
 typedef enum { CAE_ORDER_PAPER = 0, CAE_ORDER_MULTICOLOUR = 1 } cae_order_t;
 
 typedef struct {
@@ -70,7 +72,10 @@ typedef struct {
                               remainder dimension is <= coarse_max_dim */
   int32_t timing;          /* 1 = time the compression launches with HIP events
                               (reported by cae_get_stats) */
-  int32_t reserved;        /* 0 */
+  int32_t compensate;      /* 1: for every dropped far block E_il add its Frobenius norm to the
+                              diagonal of i's eliminated rows and of l's live columns
+                              (robustness option, not in the paper): M - A0 is then
+                              positive semidefinite and no pivot can fail */
   int64_t coarse_max_dim;  /* remainder size factored densely (default 2048) */
   void* stream;            /* hipStream_t; NULL = null stream */
   const float* mlp_params; /* LEARNED: DEVICE, cae_mlp_param_count() floats (see cae_mlp_train) */

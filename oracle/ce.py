@@ -248,14 +248,17 @@ def _factor_level(level_no, sizes, W: _Blocks, close_pairs, order, theta, opts):
         for l in fl:
             blk = W.get(i, l)
             if opts.compensate and b - r > 0:
-                # diagonal compensation of the dropped E_i (robustness option,
-                # not in the paper): |e_pq| onto the diagonal of row p (block
-                # i) and of column q (block l), so M - A0 gains the positive
-                # semidefinite [[diag(|E| 1), -E], [-E^T, diag(|E|^T 1)]]
-                aE = np.abs(blk[r:, :])
+                # diagonal compensation of the dropped block E_il (robustness
+                # option, not in the paper): its Frobenius norm e is added to
+                # the diagonal of i's eliminated rows and of l's live columns,
+                # so M - A0 gains [[e I, -E], [-E^T, e I]], positive
+                # semidefinite because ||E||_2 <= e; e and the identities do
+                # not depend on the bases chosen inside the subspaces
+                wl = int(lf.r[l]) if pos[l] < pos[i] else int(sizes[l])
+                eF = float(np.linalg.norm(blk[r:, :wl]))
                 Dl = W.get(l, l)
-                D[np.arange(r, b), np.arange(r, b)] += aE.sum(axis=1)
-                Dl[np.arange(Dl.shape[0]), np.arange(Dl.shape[0])] += aE.sum(axis=0)
+                D[np.arange(r, b), np.arange(r, b)] += eF
+                Dl[np.arange(wl), np.arange(wl)] += eF
             blk[r:, :] = 0.0
         # 4. elimination of the trailing b - r rotated rows
         n = slice(r, b)

@@ -18,10 +18,10 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (CAEError, FP32, FP64, ORDER_MULTICOLOUR, ORDER_PAPER, RANK_EPS, RANK_FIXED, RANK_LEARNED,
+from ._lib import (CAEError, FP32, FP32_BF16, FP64, ORDER_MULTICOLOUR, ORDER_PAPER, RANK_EPS, RANK_FIXED, RANK_LEARNED,
                    RECORD_WIDTH, check, lib, ptr)
 
-__all__ = ["grid_order", "Analysis", "Factor", "CAEError", "FP64", "FP32", "ORDER_PAPER",
+__all__ = ["grid_order", "Analysis", "Factor", "CAEError", "FP64", "FP32", "FP32_BF16", "ORDER_PAPER",
            "ORDER_MULTICOLOUR", "RANK_EPS", "RANK_FIXED", "RANK_LEARNED", "RECORD_WIDTH", "lib"]
 
 
@@ -49,9 +49,11 @@ def grid_order(dims, patch):
 
 
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
-             coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None):
+             coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None,
+             compensate=False):
     o = _lib.Options()
     lib().cae_default_options(C.byref(o))
+    o.compensate = 1 if compensate else 0
     o.mlp_params = None if mlp_params is None else mlp_params.data_ptr()
     o.seed = int(seed)
     o.record = None if record is None else record.data_ptr()
@@ -144,7 +146,7 @@ class Factor:
 
     def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
                  max_levels=0, coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0,
-                 record=None):
+                 record=None, compensate=False):
         """``rank_mode=RANK_LEARNED`` needs ``mlp_params`` (float32 CUDA tensor of
         ``learned.param_count()`` entries); ``record`` (float32 CUDA tensor of
         shape ``(rows, RECORD_WIDTH)``) receives the training records."""
@@ -162,7 +164,8 @@ class Factor:
         sptr = None if stream is None else stream.cuda_stream
         self._opts = _options(order=analysis.order, precision=precision, rank_mode=rank_mode,
                               fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
-                              stream=sptr, timing=timing, mlp_params=mlp_params, seed=seed, record=record)
+                              stream=sptr, timing=timing, mlp_params=mlp_params, seed=seed, record=record,
+                              compensate=compensate)
         h = C.c_void_p()
         self._vals = vals.contiguous()
         check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),

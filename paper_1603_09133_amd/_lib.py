@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcae.so")
 CAE_OK, CAE_EINVAL, CAE_ENOMEM, CAE_ENOTSPD, CAE_ENOCONV, CAE_EDEVICE = 0, -1, -2, -3, -4, -5
 RANK_EPS, RANK_FIXED, RANK_LEARNED = 0, 1, 2
 RECORD_WIDTH = 17
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_BF16 = 0, 1, 2
 ORDER_PAPER, ORDER_MULTICOLOUR = 0, 1
 
 
@@ -31,7 +31,7 @@ class CAEError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("rank_mode", C.c_int32), ("fixed_rank", C.c_int32),
                 ("precision", C.c_int32), ("order", C.c_int32), ("max_levels", C.c_int32),
-                ("timing", C.c_int32), ("reserved", C.c_int32),
+                ("timing", C.c_int32), ("compensate", C.c_int32),
                 ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p), ("mlp_params", C.c_void_p),
                 ("seed", C.c_uint64), ("record", C.c_void_p), ("record_cap", C.c_int64)]
 

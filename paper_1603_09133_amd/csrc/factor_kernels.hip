@@ -1198,7 +1198,7 @@ __global__ __launch_bounds__(NT) void k_rotate(LevelArgs<T> A, int32_t it0, T* g
     for (int e = tid; e < b * tc; e += NT) {
       const int a = e / tc, c = e % tc;
       T s = 0;
-      if (!(far && a >= r))
+      if (!(far && a >= r && !A.compensate))
         for (int k = 0; k < b; ++k) s += Us[k * ld + a] * X[k * ldx + c];
       *view_ptr(base, v.trans, b, bx, a, c0 + c) = s;
     }
@@ -1606,6 +1606,51 @@ __device__ void chol_inv_lds(CT* S, CT* X, int n, int* bad) {
     for (int c = tid; c < n; c += NT) X[(n - 1) * TLD + c] /= lp;
   }
   __syncthreads();
+}
+
+// Diagonal compensation of the dropped E_i (rows r_i.. of the rotated far
+// views): for every far block the Frobenius norm e of its dropped part is
+// added to the diagonal of i's eliminated rows and of the neighbour's live
+// columns, then E_i is zeroed.  M - A0 gains [[e I, -E], [-E^T, e I]] per far
+// block, positive semidefinite since ||E||_2 <= e, so no pivot can fail; e
+// and the identities do not depend on the bases chosen inside the kept and
+// dropped subspaces.  One workgroup per step; the neighbour's diagonal may be
+// shared by other steps of the wave (atomics), D_i is not.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_compensate(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  if (st.nfar == 0 || b - r <= 0) return;
+  __shared__ double red[NT / WV];
+  T* D = A.arena + A.slot_off[i];
+  double dsum = 0.0;   // compensation of i's eliminated rows (uniform over the workgroup)
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    T* base = A.arena + A.slot_off[v.slot];
+    double s2 = 0.0;
+    for (int e = threadIdx.x; e < (b - r) * w; e += NT) {
+      const double x = (double)*view_ptr(base, v.trans, b, bx, r + e / w, e % w);
+      s2 += x * x;
+    }
+    s2 = wave_sum(s2);
+    if ((threadIdx.x & (WV - 1)) == 0) red[threadIdx.x / WV] = s2;
+    __syncthreads();
+    const double eF = sqrt(red[0] + red[1] + red[2] + red[3]);
+    __syncthreads();
+    dsum += eF;
+    T* Dx = A.arena + A.slot_off[v.x];
+    if (eF > 0.0)
+      for (int c = threadIdx.x; c < w; c += NT) atomicAdd(Dx + (int64_t)c * bx + c, (T)eF);
+    for (int e = threadIdx.x; e < (b - r) * bx; e += NT) *view_ptr(base, v.trans, b, bx, r + e / bx, e % bx) = T(0);
+  }
+  for (int a = r + threadIdx.x; a < b; a += NT) {
+    T* dp = D + (int64_t)a * b + a;
+    *dp = (T)((double)*dp + dsum);
+  }
 }
 
 // Elimination of S_i for n_i <= 64: Cholesky S = L L^T and L^{-1} with one
@@ -2279,7 +2324,7 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
     __syncthreads();
     zero_acc(acc);
     gemm_tn_4x4(Us, X, b, acc);
-    if (far) {
+    if (far && !A.compensate) {   // with compensation k_compensate zeroes E_i after using it
 #pragma unroll
       for (int p = 0; p < 4; ++p)
         if (4 * ty + p >= r)
@@ -2418,6 +2463,127 @@ __global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
               *tp = (T)((double)*tp - acc[p][q]);
             }
           }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Schur update with BF16 inputs and FP32 accumulation on the matrix cores
+// (FP32 factor, reduced-precision mode): the 64 x 64 target tile is four
+// 32 x 32 MFMA tiles, one per wavefront, v_mfma_f32_32x32x8bf16_1k over the
+// n_i rows of the panels (zero-padded to a multiple of 8).  Operand lanes: A
+// row i = lane % 32, k = 4 (lane / 32) + 0..3; B column j = lane % 32, same k;
+// result register v holds row 8 (v / 4) + 4 (lane / 32) + v % 4, column
+// lane % 32.  Panels are staged in LDS in FP32 and rounded to BF16 (nearest
+// even) when loaded into the operands.
+// ---------------------------------------------------------------------------
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ inline short to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_bf16(LevelArgs<T> A, int32_t p0) {
+  const Pair pr = A.pairs[p0 + blockIdx.x];
+  const Step st = A.steps[pr.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  T* D = A.arena + A.slot_off[i];
+  int la, lc, ba = b, bc = b, ta = 0, tcv = 0;
+  T* pa;
+  T* pc;
+  if (pr.a == 0) {
+    la = r;
+    pa = D;
+  } else {
+    const View va = A.views[st.view0 + pr.a - 1];
+    ba = A.bsz[va.x];
+    la = va.proc ? A.rank[va.x] : ba;
+    pa = A.arena + A.slot_off[va.slot];
+    ta = va.trans;
+  }
+  if (pr.c == 0) {
+    lc = r;
+    pc = D;
+  } else {
+    const View vc = A.views[st.view0 + pr.c - 1];
+    bc = A.bsz[vc.x];
+    lc = vc.proc ? A.rank[vc.x] : bc;
+    pc = A.arena + A.slot_off[vc.slot];
+    tcv = vc.trans;
+  }
+  if (la == 0 || lc == 0) return;
+  T* tbase;
+  int64_t ts_a, ts_c;
+  if (pr.a == 0) {
+    if (pr.c == 0) {
+      tbase = D;
+      ts_a = b;
+      ts_c = 1;
+    } else {
+      tbase = pc;
+      ts_a = tcv ? 1 : bc;
+      ts_c = tcv ? b : 1;
+    }
+  } else {
+    tbase = A.arena + A.slot_off[pr.slot];
+    if (pr.trans) {
+      ts_a = 1;
+      ts_c = ba;
+    } else {
+      ts_a = bc;
+      ts_c = 1;
+    }
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Pa = reinterpret_cast<T*>(smem_raw);
+  T* Pc = Pa + 64 * TLD;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int si = wv >> 1, sj = wv & 1;
+  const int nk = (n + 7) & ~7;
+  for (int a0 = 0; a0 < la; a0 += 64) {
+    const int tan = min(64, la - a0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) Pa[(e >> 6) * TLD + (e & 63)] = T(0);
+    __syncthreads();
+    load_view_tile(Pa, pa, ta, b, ba, r, n, a0, tan);
+    for (int c0 = 0; c0 < lc; c0 += 64) {
+      const int tcn = min(64, lc - c0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < 64 * 64; e += NT) Pc[(e >> 6) * TLD + (e & 63)] = T(0);
+      __syncthreads();
+      load_view_tile(Pc, pc, tcv, b, bc, r, n, c0, tcn);
+      __syncthreads();
+      f32x16_t acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      const int ia = si * 32 + (lane & 31), jb = sj * 32 + (lane & 31);
+      for (int k0 = 0; k0 < nk; k0 += 8) {
+        bf16x4_t av, bv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int k = k0 + 4 * (lane >> 5) + t;
+          av[t] = to_bf16((float)Pa[k * TLD + ia]);
+          bv[t] = to_bf16((float)Pc[k * TLD + jb]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int al = si * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int gm = sj * 32 + (lane & 31);
+        if (al < tan && gm < tcn) {
+          T* tp = tbase + (int64_t)(a0 + al) * ts_a + (int64_t)(c0 + gm) * ts_c;
+          *tp = (T)((float)*tp - acc[v]);
+        }
       }
     }
   }
@@ -2685,6 +2851,8 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   if (tiled && w.r1 > w.r0)
     hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
   if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
+  if (A.compensate && w.s1 > w.s0)
+    hipLaunchKernelGGL(k_compensate<T>, dim3(w.s1 - w.s0), dim3(NT), 0, stream, A, w.s0);
   const size_t wp = work_tiled<T>() * sizeof(typename AccT<T>::type);
   const bool ptiled = tiled && wp <= max_lds_bytes();
   if (ptiled && w.s1 > w.s0)
@@ -2697,8 +2865,12 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   if (tiled && w.t1 > w.t0)
     hipLaunchKernelGGL(k_trsm_t<T>, dim3(w.t1 - w.t0), dim3(NT), wt, stream, B, w.t0);
   if (generic) launch<T>(k_trsm<T>, B, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream);
-  if (tiled && w.p1 > w.p0)
-    hipLaunchKernelGGL(k_schur_t<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+  if (tiled && w.p1 > w.p0) {
+    if (A.bf16_schur && sizeof(T) == sizeof(float))
+      hipLaunchKernelGGL(k_schur_bf16<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+    else
+      hipLaunchKernelGGL(k_schur_t<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+  }
   if (generic) launch<T>(k_schur<T>, B, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream);
 }
 

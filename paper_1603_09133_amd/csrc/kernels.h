@@ -45,6 +45,8 @@ struct LevelArgs {
   int64_t rec_off;          // first record row of this level
   int32_t* need_exact;      // per block: 1 = the exact compression must take the step, or null
   int32_t* lcount;          // [0] sketches accepted, [1] sketches rejected
+  int32_t bf16_schur;       // FP32 factor: Schur products with BF16 inputs on the matrix cores
+  int32_t compensate;       // add |E_i| to the diagonals (k_compensate) instead of plain dropping
 };
 
 // learned rank: feature count, record width, MLP parameter layout (floats):

@@ -304,6 +304,8 @@ cae::LevelArgs<T> level_args(cae_factor_s* h, int l) {
   A.rec_off = 0;
   A.need_exact = nullptr;
   A.lcount = nullptr;
+  A.bf16_schur = h->precision == CAE_FP32_BF16 ? 1 : 0;
+  A.compensate = h->opt.compensate ? 1 : 0;
   return A;
 }
 
@@ -651,7 +653,7 @@ void apply_factor(cae_factor_s* h, int32_t nrhs, const double* x, int64_t ldx, d
 }
 
 void do_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
-  if (h->precision == CAE_FP32)
+  if (h->precision != CAE_FP64)
     apply_precond<float>(h, nrhs, r, ldr, z, ldz);
   else
     apply_precond<double>(h, nrhs, r, ldr, z, ldz);
@@ -776,7 +778,8 @@ int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const 
     if (opt->struct_size != (int32_t)sizeof(cae_options_t)) return fail(CAE_EINVAL, "options struct_size mismatch");
     o = *opt;
   }
-  if (o.precision != CAE_FP64 && o.precision != CAE_FP32) return fail(CAE_EINVAL, "unknown precision");
+  if (o.precision != CAE_FP64 && o.precision != CAE_FP32 && o.precision != CAE_FP32_BF16)
+    return fail(CAE_EINVAL, "unknown precision");
   if (o.rank_mode != CAE_RANK_EPS && o.rank_mode != CAE_RANK_FIXED && o.rank_mode != CAE_RANK_LEARNED)
     return fail(CAE_EINVAL, "unknown rank mode");
   if (o.rank_mode == CAE_RANK_LEARNED && (!o.mlp_params || !(eps > 0.0)))
@@ -793,7 +796,7 @@ int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const 
     h->precision = o.precision;
     h->stream = (hipStream_t)o.stream;
     g_cur_stream = h->stream;
-    int rc = o.precision == CAE_FP32 ? factor_numeric<float>(h.get(), vals, eps)
+    int rc = o.precision != CAE_FP64 ? factor_numeric<float>(h.get(), vals, eps)
                                      : factor_numeric<double>(h.get(), vals, eps);
     if (rc != CAE_OK) {
       (void)hipStreamSynchronize(h->stream);
@@ -828,7 +831,7 @@ int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx,
   const int64_t n = h->an->a.n;
   if (nrhs <= 0 || !x || !y || ldx < n || ldy < n) return fail(CAE_EINVAL, "bad vector arguments");
   try {
-    if (h->precision == CAE_FP32)
+    if (h->precision != CAE_FP64)
       apply_factor<float>(h, nrhs, x, ldx, y, ldy);
     else
       apply_factor<double>(h, nrhs, x, ldx, y, ldy);

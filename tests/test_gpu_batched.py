@@ -1,0 +1,71 @@
+"""A batch of independent problems factored in one joint analysis equals the
+problems factored one by one with the same threshold theta = eps * max diag
+of the joint matrix (block-diagonal independence, FP64, M X per problem to
+1e-10), every problem's PCG residual reaches the tolerance, and
+the autotuner picks and caches a patch shape."""
+import json
+
+import numpy as np
+import pytest
+
+import problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _cae():
+    import paper_1603_09133_amd as cae
+    cae.lib()
+    return cae
+
+
+def test_batch_equals_individual_factorizations():
+    cae = _cae()
+    from paper_1603_09133_amd import batched
+    spec = [(0, 40, (8, 8)), (1, 12, (4, 4, 4)), (0, 33, (4, 4)), (1, 8, (2, 2, 4)), (0, 64, (8, 8))]
+    mats, dims, patches = [], [], []
+    for kind, side, patch in spec:
+        d = (side, side) if kind == 0 else (side,) * 3
+        mats.append(problems.laplacian(d))
+        dims.append(d)
+        patches.append(patch)
+    eps = 1e-6
+    # both run every level down to one block in the block order of Algorithm 2
+    # (the multicolour order of a 2D problem differs once it sits among 3D
+    # ones), so every problem sees the same compressions; the joint analysis
+    # only adds exact eliminations of single-block problems
+    bt = batched.Batch(mats, dims, patches, eps, precision=cae.FP64, order=cae.ORDER_PAPER, coarse_max_dim=0)
+    bt.factorize()
+    N = bt.A.shape[0]
+    X = np.random.default_rng(12345).standard_normal((N, 3))
+    MX = bt.factor.multiply(torch.from_numpy(np.ascontiguousarray(X.T)).cuda()).cpu().numpy().T
+    tau = bt.A.diagonal().max()
+    for t, (A, d, patch) in enumerate(zip(mats, dims, patches)):
+        s = slice(bt.row_off[t], bt.row_off[t + 1])
+        perm, bp, co = cae.grid_order(d, patch)
+        ip, ix, dv = problems.to_csr_arrays(A)
+        an = cae.Analysis(ip, ix, perm, bp, co, order=cae.ORDER_PAPER)
+        # the joint threshold is eps * max diag of the joint matrix
+        eps_t = eps * tau / A.diagonal().max()
+        f = cae.Factor(an, torch.from_numpy(dv).cuda(), eps_t, precision=cae.FP64, coarse_max_dim=0)
+        Mt = f.multiply(torch.from_numpy(np.ascontiguousarray(X[s].T)).cuda()).cpu().numpy().T
+        assert np.linalg.norm(MX[s] - Mt) <= 1e-10 * np.linalg.norm(Mt), t
+        f.close()
+        an.close()
+    B = torch.from_numpy(np.ascontiguousarray(problems.rhs_normal(N, 4, seed=1).T)).cuda()
+    x, it, rel = bt.pcg(B, rtol=1e-10)
+    res = bt.problem_residuals(B, x)
+    assert res.max() <= 1e-8, res.max()
+    bt.close()
+
+
+def test_autotune_caches_a_choice(tmp_path):
+    _cae()
+    from paper_1603_09133_amd import batched
+    cache = str(tmp_path / "tune.json")
+    p = batched.autotune(2, 64, lambda s: problems.laplacian((s, s)), cache=cache)
+    assert p in [tuple(c) for c in batched.CANDIDATES[2]]
+    table = json.load(open(cache))
+    assert len(table) == 1 and list(table.values())[0]["patch"] == list(p)
+    assert batched.autotune(2, 64, lambda s: problems.laplacian((s, s)), cache=cache) == p

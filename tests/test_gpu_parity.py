@@ -237,3 +237,35 @@ def test_bf16_schur_factor(dims, patch, eps):
     assert np.linalg.norm(M0X - A0X) <= 2e-3 * np.linalg.norm(A0X)
     f0.close()
     an.close()
+
+
+def test_compensation_matches_oracle_and_prevents_breakdown():
+    """Diagonal compensation on the biharmonic operator, which breaks the
+    plain method at eps = 1e-3: the GPU reports CAE_ENOTSPD without it, and
+    with it matches the oracle's compensated factor (M X to 1e-10, FP64) and
+    converges in PCG."""
+    cae = _cae()
+    L = problems.laplacian((32, 32))
+    B = (L @ L).tocsr()
+    B.sort_indices()
+    A, csr, perm, bp, co = _setup((32, 32), (4, 4), A=B)
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    vals = torch.from_numpy(csr[2]).cuda()
+    with pytest.raises(cae.CAEError) as ei:
+        cae.Factor(an, vals, 1e-3, precision=cae.FP64, coarse_max_dim=0)
+    assert ei.value.code == -3
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=1e-3, order="multicolour", coarse_max_dim=0, compensate=True))
+    f = cae.Factor(an, vals, 1e-3, precision=cae.FP64, coarse_max_dim=0, compensate=True)
+    X = _probes(A.shape[0])
+    MX = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    MXo = ce_multiply(fo, X)
+    assert np.linalg.norm(MX - MXo) <= 1e-10 * np.linalg.norm(MXo)
+    b = problems.rhs_uniform(A.shape[0], seed=0)
+    _, it, rel = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-8)
+    assert f.converged and rel[0] <= 1.0001e-8
+    f.close()
+    f32 = cae.Factor(an, vals, 1e-3, precision=cae.FP32, coarse_max_dim=0, compensate=True)
+    _, it32, rel32 = f32.pcg(torch.from_numpy(b).cuda(), rtol=1e-8)
+    assert f32.converged
+    f32.close()
+    an.close()

@@ -334,10 +334,10 @@ def _biharmonic(n):
 
 
 def test_compensation_keeps_m_minus_a_psd_and_prevents_breakdown():
-    """Diagonal compensation of the dropped E_i adds, per step, the positive
-    semidefinite [[diag(|E| 1), -E], [-E^T, diag(|E|^T 1)]] to A0, so M - A0
-    is positive semidefinite and no pivot can fail.  The biharmonic operator
-    (not an M-matrix) breaks the plain method at eps = 1e-3."""
+    """Diagonal compensation adds, per dropped far block E, the positive
+    semidefinite [[e I, -E], [-E^T, e I]] (e = ||E||_F >= ||E||_2) to A0, so
+    M - A0 is positive semidefinite and no pivot can fail.  The biharmonic
+    operator (not an M-matrix) breaks the plain method at eps = 1e-3."""
     B = _biharmonic(32)
     csr = problems.to_csr_arrays(B)
     perm, bp, co = oracle.grid_order((32, 32), (4, 4))
