@@ -110,6 +110,21 @@ int cae_grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch,
                    int32_t* perm, int32_t* block_ptr, int32_t* coords, int32_t* nblocks);
 
 /*
+ * Ordering for a general sparse SPD matrix with no grid (robustness and
+ * generality option, not in the paper, which orders grids geometrically,
+ * Section 2.9): nested bisection of the graph of A -- each part split into
+ * halves along the breadth-first order from a pseudo-peripheral vertex --
+ * to a uniform depth so that every block has at most B unknowns.  The halves
+ * of a part are consecutive, so cae_analyze with coords = NULL and ndim = 1
+ * (groups of J = 2 blocks) coarsens along the bisection tree.
+ *   n, row_ptr, col_idx: host CSR structure (both triangles).
+ *   Query mode: perm == NULL writes only *nblocks.
+ *   Outputs (host, caller-allocated): perm[new] = old (n), block_ptr (nblocks+1).
+ */
+int cae_graph_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t B,
+                    int32_t* perm, int32_t* block_ptr, int32_t* nblocks);
+
+/*
  * Symbolic analysis (host only, no GPU call): level-1 block pattern of A0
  * (close blocks, Section 2), elimination order and dependency waves of every
  * level, the far blocks created by the eliminations (eq. (A_st); remark after

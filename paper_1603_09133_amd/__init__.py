@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import (CAEError, FP32, FP32_BF16, FP64, ORDER_MULTICOLOUR, ORDER_PAPER, RANK_EPS, RANK_FIXED, RANK_LEARNED,
                    RECORD_WIDTH, check, lib, ptr)
 
-__all__ = ["grid_order", "Analysis", "Factor", "CAEError", "FP64", "FP32", "FP32_BF16", "ORDER_PAPER",
+__all__ = ["grid_order", "graph_order", "Analysis", "Factor", "CAEError", "FP64", "FP32", "FP32_BF16", "ORDER_PAPER",
            "ORDER_MULTICOLOUR", "RANK_EPS", "RANK_FIXED", "RANK_LEARNED", "RECORD_WIDTH", "lib"]
 
 
@@ -48,6 +48,20 @@ def grid_order(dims, patch):
     return perm, bp, co
 
 
+def graph_order(indptr, indices, B):
+    """Nested-bisection permutation of a general sparse graph: returns
+    ``perm`` (new -> old) and ``block_ptr`` (blocks of at most ``B``); analyse
+    with ``coords=None`` and ``J=2`` (``Analysis(..., coords=None, ndim=1)``)."""
+    ip, ix = _i64(indptr), _i32(indices)
+    n = len(ip) - 1
+    nb = C.c_int32()
+    check(lib().cae_graph_order(n, ptr(ip), ptr(ix), int(B), None, None, C.byref(nb)))
+    perm = np.empty(n, np.int32)
+    bp = np.empty(nb.value + 1, np.int32)
+    check(lib().cae_graph_order(n, ptr(ip), ptr(ix), int(B), ptr(perm), ptr(bp), C.byref(nb)))
+    return perm, bp
+
+
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
              coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None,
              compensate=False):
@@ -72,13 +86,19 @@ def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_
 class Analysis:
     """Symbolic analysis of a CSR pattern with a permutation and blocks."""
 
-    def __init__(self, indptr, indices, perm, block_ptr=None, coords=None, B=0, order=ORDER_MULTICOLOUR):
+    def __init__(self, indptr, indices, perm, block_ptr=None, coords=None, B=0, order=ORDER_MULTICOLOUR,
+                 ndim=None):
+        """Without ``coords`` consecutive groups of ``2**ndim`` blocks form the
+        next level (``ndim=1``: pairs, as for :func:`graph_order`)."""
         self._ip, self._ix = _i64(indptr), _i32(indices)
         self._perm = _i32(perm)
         n = len(self._ip) - 1
         bp = None if block_ptr is None else _i32(block_ptr)
         co = None if coords is None else _i32(coords)
-        ndim = 0 if co is None else (co.shape[1] if co.ndim == 2 else 1)
+        if co is not None:
+            ndim = co.shape[1] if co.ndim == 2 else 1
+        elif ndim is None:
+            ndim = 0
         nb = 0 if bp is None else len(bp) - 1
         self.order = order
         self.n = n

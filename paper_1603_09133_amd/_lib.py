@@ -52,7 +52,7 @@ class Stats(C.Structure):
 _lib = None
 
 EXPORTS = [
-    "cae_default_options", "cae_last_error", "cae_grid_order", "cae_analyze", "cae_analysis_levels",
+    "cae_default_options", "cae_last_error", "cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels",
     "cae_analysis_level_info", "cae_analysis_level_arrays", "cae_analysis_perm", "cae_analysis_destroy",
     "cae_factor_numeric", "cae_apply_precond", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
     "cae_get_stats",
@@ -75,6 +75,7 @@ def lib():
     L.cae_last_error.argtypes = []
     L.cae_last_error.restype = C.c_char_p
     L.cae_grid_order.argtypes = [i32, p, p, p, p, p, p]
+    L.cae_graph_order.argtypes = [i64, p, p, i32, p, p, p]
     L.cae_analyze.argtypes = [i64, p, p, p, p, i32, i32, p, i32, C.POINTER(Options), C.POINTER(p)]
     L.cae_analysis_levels.argtypes = [p, p]
     L.cae_analysis_level_info.argtypes = [p, i32, C.POINTER(LevelInfo)]
@@ -97,7 +98,7 @@ def lib():
     L.cae_mlp_train.argtypes = [p, i64, p, i32, C.c_float, C.POINTER(C.c_float), p]
     L.cae_mlp_loss_grad.argtypes = [p, p, i64, p, C.POINTER(C.c_float), p]
     L.cae_mlp_predict.argtypes = [p, p, i64, p, p]
-    for name in ["cae_grid_order", "cae_analyze", "cae_analysis_levels", "cae_analysis_level_info",
+    for name in ["cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels", "cae_analysis_level_info",
                  "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_apply_precond",
                  "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
                  "cae_get_sizes", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:

@@ -683,6 +683,22 @@ void cae_default_options(cae_options_t* opt) {
 
 const char* cae_last_error(void) { return g_err.c_str(); }
 
+int cae_graph_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t B, int32_t* perm,
+                    int32_t* block_ptr, int32_t* nblocks) {
+  if (!row_ptr || !col_idx || !nblocks) return fail(CAE_EINVAL, "row_ptr, col_idx and nblocks are required");
+  try {
+    std::vector<int32_t> p, bp;
+    std::string e = cae::graph_order(n, row_ptr, col_idx, B, p, bp);
+    if (!e.empty()) return fail(CAE_EINVAL, e);
+    *nblocks = (int32_t)bp.size() - 1;
+    if (perm) std::memcpy(perm, p.data(), p.size() * sizeof(int32_t));
+    if (block_ptr) std::memcpy(block_ptr, bp.data(), bp.size() * sizeof(int32_t));
+  } catch (const std::bad_alloc&) {
+    return fail(CAE_ENOMEM, "host allocation failed");
+  }
+  return CAE_OK;
+}
+
 int cae_grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch, int32_t* perm, int32_t* block_ptr,
                    int32_t* coords, int32_t* nblocks) {
   if (!dims || !patch || !nblocks) return fail(CAE_EINVAL, "dims, patch and nblocks are required");

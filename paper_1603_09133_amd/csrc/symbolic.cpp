@@ -320,6 +320,75 @@ int32_t LevelSym::slot_of(int32_t p, int32_t q) const {
   return up_slot[it - up_q.begin()];
 }
 
+std::string graph_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t B,
+                        std::vector<int32_t>& perm, std::vector<int32_t>& block_ptr) {
+  if (n <= 0 || B <= 0) return "n and B must be positive";
+  if (n > INT32_MAX) return "too many unknowns";
+  int depth = 0;
+  while (((n + ((int64_t)1 << depth) - 1) >> depth) > B && ((int64_t)2 << depth) <= n) ++depth;
+  std::vector<int32_t> ord(n), part(n, 0), dist(n, -1), queue;
+  for (int64_t v = 0; v < n; ++v) ord[v] = (int32_t)v;
+  queue.reserve(n);
+  // breadth-first order of ord[b..e) inside the part `id`, from `start`,
+  // restarting at the first unvisited vertex for disconnected parts
+  auto bfs = [&](int64_t b, int64_t e, int32_t id, int32_t start, std::vector<int32_t>& out) -> int32_t {
+    out.clear();
+    for (int64_t k = b; k < e; ++k) dist[ord[k]] = -1;
+    int32_t last = start;
+    int64_t next_seed = b;
+    int32_t s = start;
+    while ((int64_t)out.size() < e - b) {
+      if (dist[s] >= 0) {
+        while (next_seed < e && dist[ord[next_seed]] >= 0) ++next_seed;
+        s = ord[next_seed];
+      }
+      size_t head = out.size();
+      dist[s] = 0;
+      out.push_back(s);
+      while (head < out.size()) {
+        const int32_t u = out[head++];
+        last = u;
+        for (int64_t q = row_ptr[u]; q < row_ptr[u + 1]; ++q) {
+          const int32_t w = col_idx[q];
+          if (w < 0 || w >= n || part[w] != id || dist[w] >= 0) continue;
+          dist[w] = dist[u] + 1;
+          out.push_back(w);
+        }
+      }
+    }
+    return last;
+  };
+  std::vector<int32_t> tmp;
+  std::vector<std::pair<int64_t, int64_t>> level{{0, n}};
+  int32_t next_id = 1;
+  for (int d = 0; d < depth; ++d) {
+    std::vector<std::pair<int64_t, int64_t>> nxt;
+    for (auto [b, e] : level) {
+      const int32_t id = part[ord[b]];
+      // pseudo-peripheral vertex: the last vertex of two breadth-first sweeps
+      int32_t v = ord[b];
+      for (int64_t k = b + 1; k < e; ++k) v = std::min(v, ord[k]);
+      v = bfs(b, e, id, v, tmp);
+      v = bfs(b, e, id, v, tmp);
+      bfs(b, e, id, v, tmp);
+      const int64_t m = e - b, h = (m + 1) / 2;
+      const int32_t idl = next_id++, idr = next_id++;
+      for (int64_t k = 0; k < m; ++k) {
+        ord[b + k] = tmp[k];
+        part[tmp[k]] = k < h ? idl : idr;
+      }
+      nxt.push_back({b, b + h});
+      nxt.push_back({b + h, e});
+    }
+    level.swap(nxt);
+  }
+  perm.assign(ord.begin(), ord.end());
+  block_ptr.clear();
+  for (auto [b, e] : level) block_ptr.push_back((int32_t)b);
+  block_ptr.push_back((int32_t)n);
+  return {};
+}
+
 std::string grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch,
                        std::vector<int32_t>& perm, std::vector<int32_t>& block_ptr,
                        std::vector<int32_t>& coords) {

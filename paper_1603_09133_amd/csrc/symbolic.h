@@ -50,6 +50,14 @@ struct Analysis {
 };
 
 // Returns an empty string on success, else the error message.
+// Nested bisection of a general sparse graph (both triangles, diagonal
+// allowed): every part is split into halves by the breadth-first order from a
+// pseudo-peripheral vertex of the part, to a uniform depth so that the leaves
+// have at most B vertices; leaves in depth-first order are the blocks, and
+// the two halves of a part are consecutive, so coarsening by pairs (J = 2)
+// follows the bisection tree.
+std::string graph_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t B,
+                        std::vector<int32_t>& perm, std::vector<int32_t>& block_ptr);
 std::string grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch,
                        std::vector<int32_t>& perm, std::vector<int32_t>& block_ptr,
                        std::vector<int32_t>& coords);

@@ -170,6 +170,32 @@ def rhs_ones(N: int) -> np.ndarray:
     return np.ones(N, dtype=np.float64)
 
 
+def disk_laplacian(n: int) -> sp.csr_matrix:
+    """5-point Laplacian (4/-1, Dirichlet) on the nodes of an n x n grid that
+    lie inside the inscribed disk: an irregular domain without a tensor-grid
+    block structure (for graph orderings)."""
+    c = (n - 1) / 2.0
+    yy, xx = np.mgrid[0:n, 0:n]
+    inside = (xx - c) ** 2 + (yy - c) ** 2 <= (n / 2.0) ** 2
+    idx = -np.ones((n, n), dtype=np.int64)
+    idx[inside] = np.arange(int(inside.sum()))
+    rows, cols, vals = [], [], []
+    N = int(inside.sum())
+    rows.append(np.arange(N))
+    cols.append(np.arange(N))
+    vals.append(np.full(N, 4.0))
+    for dy, dx in ((0, 1), (1, 0)):
+        a = idx[: n - dy, : n - dx]
+        b = idx[dy:, dx:]
+        m = (a >= 0) & (b >= 0)
+        rows += [a[m], b[m]]
+        cols += [b[m], a[m]]
+        vals += [-np.ones(m.sum()), -np.ones(m.sum())]
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+    A.sort_indices()
+    return A
+
+
 def rhs_uniform(N: int, seed: int = 0) -> np.ndarray:
     """One RHS, i.i.d. U(-1, 1)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, N)

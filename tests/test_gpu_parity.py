@@ -269,3 +269,29 @@ def test_compensation_matches_oracle_and_prevents_breakdown():
     assert f32.converged
     f32.close()
     an.close()
+
+
+@pytest.mark.parametrize("eps,order", [(1e-6, "multicolour"), (1e-4, "paper")])
+def test_general_sparse_graph_ordering(eps, order):
+    """An irregular domain (the grid nodes inside a disk) ordered by nested
+    bisection of its graph, blocks of at most 32, pairs of blocks coarsened
+    (no coordinates): GPU factor against the oracle on the same ordering."""
+    cae = _cae()
+    A = problems.disk_laplacian(44)
+    csr = problems.to_csr_arrays(A)
+    perm, bp = cae.graph_order(csr[0], csr[1], 32)
+    fo = ce_factor(*csr, perm, bp, None, CEOptions(eps=eps, order=order, coarse_max_dim=0), J=2)
+    an = cae.Analysis(csr[0], csr[1], perm, bp, None,
+                      order=cae.ORDER_PAPER if order == "paper" else cae.ORDER_MULTICOLOUR, ndim=1)
+    f = cae.Factor(an, torch.from_numpy(csr[2]).cuda(), eps, precision=cae.FP64, coarse_max_dim=0)
+    _check_ranks(f, fo)
+    X = _probes(A.shape[0])
+    MX = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    MXo = ce_multiply(fo, X)
+    assert np.linalg.norm(MX - MXo) <= 1e-12 * np.linalg.norm(MXo)
+    b = problems.rhs_uniform(A.shape[0], seed=0)
+    _, it, rel = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-10)
+    _, ito, _ = oracle.pcg(A, b, lambda r: ce_solve(fo, r), tol=1e-10)
+    assert it[0] == ito and rel[0] <= 1e-9
+    f.close()
+    an.close()
