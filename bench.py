@@ -84,6 +84,10 @@ def main():
     ap.add_argument("--with-analysis", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=128)
+    ap.add_argument("--config", choices=["c2", "c3", "c4", "c5"], default="c2",
+                    help="c2: 2D Laplacian 1024^2 (default, the headline); c3: 3D Laplacian 128^3, B=64, eps=1e-4, "
+                         "1 RHS, BF16 Schur, learned ranks; c4: 2D diffusion with a random coefficient 2048^2, "
+                         "eps=1e-5, 64 RHS; c5: 256 independent 2D/3D problems in one factorization, 4 RHS each")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size before the timed steps "
                          "(reference dispatch for the HBM byte counters)")
@@ -99,22 +103,72 @@ def main():
     import paper_1603_09133_amd as cae
     import problems
 
-    dims = (args.side, args.side)
-    patch = (args.patch, args.patch)
-    A = problems.laplacian(dims)
+    dev = torch.device("cuda:0")
+    coarsen = "siblings"
+    order = cae.ORDER_MULTICOLOUR if args.order == "multicolour" else cae.ORDER_PAPER
+    prec = cae.FP32 if args.precision == "fp32" else cae.FP64
+    fkw = {}
+    if args.config == "c2":
+        dims = (args.side, args.side)
+        patch = (args.patch, args.patch)
+        A = problems.laplacian(dims)
+        B = problems.rhs_normal(A.shape[0], args.nrhs, seed=1)
+        workload = (f"2D 5-point Laplacian {args.side}x{args.side} (N={A.shape[0]}), {args.patch}x{args.patch} "
+                    f"Morton patches (B={args.patch * args.patch}), eps={args.eps}, {args.nrhs} RHS N(0,1) seed 1, "
+                    f"PCG FP64 to 1e-8, {args.order} order")
+    elif args.config == "c3":
+        dims, patch = (128, 128, 128), (4, 4, 4)
+        coarsen = "pairs"
+        args.eps, args.nrhs = 1e-4, 1
+        A = problems.laplacian(dims)
+        B = problems.rhs_normal(A.shape[0], 1, seed=0)
+        prec = cae.FP32_BF16
+        workload = ("3D 7-point Laplacian 128^3 (N=2097152), 4x4x4 Morton patches (B=64), pairs of blocks along "
+                    "the Morton curve per level, eps=1e-4, 1 RHS N(0,1) seed 0, FP32 factor with BF16 Schur products, "
+                    "learned ranks (MLP trained on a 48^3 problem before timing), PCG FP64 to 1e-8")
+    elif args.config == "c4":
+        dims, patch = (2048, 2048), (8, 8)
+        args.eps, args.nrhs = 1e-5, 64
+        A, rng = problems.grf_diffusion_2d(2048)
+        B = rng.standard_normal((64, A.shape[0])).T
+        workload = ("2D -div(k grad u), k = exp(GRF, l=0.05, sigma=1, seed 2), 2048^2 (N=4194304), 8x8 patches "
+                    "(B=64), eps=1e-5, FP32 factor, 64 RHS N(0,1), PCG FP64 to 1e-8")
+    else:
+        from paper_1603_09133_amd import batched
+        kind, sides, rng = problems.batched_problem_draws(256, seed=3)
+        mats, dl, pl = [], [], []
+        for k, sd in zip(kind, sides):
+            d = (int(sd), int(sd)) if k == 0 else (int(sd),) * 3
+            mats.append(problems.laplacian(d))
+            dl.append(d)
+            pl.append((8, 8) if k == 0 else (2, 2, 4))
+        A, perm, bp, co, _ = batched.assemble(mats, dl, pl)
+        B = np.concatenate([rng.standard_normal((4, m.shape[0])) for m in mats], axis=1).T
+        args.nrhs = 4
+        workload = (f"256 independent Laplacians (2D side 64..512 with 8x8 patches, 3D side 16..64 with 2x2x4 "
+                    f"patches; draws default_rng(3)), N={A.shape[0]} in one joint factorization, eps=1e-6, FP32 "
+                    f"factor, 4 RHS per problem, PCG FP64 to 1e-8")
     ip, ix, dv = problems.to_csr_arrays(A)
     N = A.shape[0]
-    B = problems.rhs_normal(N, args.nrhs, seed=1)
-    perm, bp, co = cae.grid_order(dims, patch)
-    order = cae.ORDER_MULTICOLOUR if args.order == "multicolour" else cae.ORDER_PAPER
+    if args.config != "c5":
+        perm, bp, co = cae.grid_order(dims, patch)
     t = time.perf_counter()
-    an = cae.Analysis(ip, ix, perm, bp, co, order=order)
+    an = cae.Analysis(ip, ix, perm, bp, co, order=order, coarsen=coarsen)
     analysis_ms = (time.perf_counter() - t) * 1e3
-    dev = torch.device("cuda:0")
     vals = torch.from_numpy(dv).to(dev)
     b = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
     x = torch.empty_like(b)
-    prec = cae.FP32 if args.precision == "fp32" else cae.FP64
+    if args.config == "c3":
+        from paper_1603_09133_amd import learned
+        d2 = (48, 48, 48)
+        A2 = problems.laplacian(d2)
+        i2, x2, v2 = problems.to_csr_arrays(A2)
+        p2, b2, c2 = cae.grid_order(d2, patch)
+        an2 = cae.Analysis(i2, x2, p2, b2, c2, order=order, coarsen=coarsen)
+        rec = learned.record(an2, torch.from_numpy(v2).to(dev), args.eps, precision=cae.FP32)
+        an2.close()
+        params, _ = learned.train(rec, epochs=800, lr=1e-3)
+        fkw = dict(rank_mode=cae.RANK_LEARNED, mlp_params=params, seed=1)
 
     if args.copy_calibration_mib > 0:
         src = torch.ones(args.copy_calibration_mib * 2**18, dtype=torch.float32, device=dev)
@@ -124,8 +178,8 @@ def main():
         del src, dst
 
     def step():
-        a = cae.Analysis(ip, ix, perm, bp, co, order=order) if args.with_analysis else an
-        f = cae.Factor(a, vals, args.eps, precision=prec, timing=True)
+        a = cae.Analysis(ip, ix, perm, bp, co, order=order, coarsen=coarsen) if args.with_analysis else an
+        f = cae.Factor(a, vals, args.eps, precision=prec, timing=True, **fkw)
         _, it, rel = f.pcg(b, rtol=1e-8, maxit=1000, x=x)
         return f, it, rel
 
@@ -147,10 +201,14 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(args.steps, 1)
     ok = bool(np.all(rel <= 1.0001e-8))
-    # reference FP64 GPU factor iterations (same workload)
-    f64 = cae.Factor(an, vals, args.eps, precision=cae.FP64)
-    _, it64, rel64 = f64.pcg(b, rtol=1e-8, maxit=1000, x=x)
-    f64.close()
+    # reference FP64 GPU factor iterations (same workload; the headline only)
+    it64 = None
+    if args.config == "c2":
+        f64 = cae.Factor(an, vals, args.eps, precision=cae.FP64)
+        _, it64, rel64 = f64.pcg(b, rtol=1e-8, maxit=1000, x=x)
+        f64.close()
+    dtype = {cae.FP32: "f32 factor + f64 PCG", cae.FP64: "f64",
+             cae.FP32_BF16: "f32 factor with bf16-input Schur products + f64 PCG"}[prec]
     out = {
         "metric": "factor+PCG time to 1e-8 residual (2D/3D Laplacian); block-op TFLOP/s vs peak",
         "value": dt,
@@ -162,22 +220,21 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 factor + f64 PCG" if prec == cae.FP32 else "f64",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"2D 5-point Laplacian {args.side}x{args.side} (N={N}), {args.patch}x{args.patch} "
-                               f"Morton patches (B={args.patch * args.patch}), eps={args.eps}, {args.nrhs} RHS "
-                               f"N(0,1) seed 1, PCG FP64 to 1e-8, {args.order} order",
+        "config": {"workload": workload,
                    "factor_ms_mean": float(np.mean(fac_ms)), "analysis_ms": analysis_ms,
                    "analysis_in_step": bool(args.with_analysis),
-                   "pcg_iters": it.tolist(), "pcg_iters_fp64_factor": it64.tolist(),
+                   "pcg_iters": it.tolist(), "pcg_iters_fp64_factor": None if it64 is None else it64.tolist(),
                    "relres_max": float(np.max(rel)), "converged": ok, "levels": st["nlevels"],
                    "coarse_dim": st["coarse_dim"], "factor_bytes": st["factor_bytes"]},
     }
     # roofline of the dominant kernel (the far-row compression, plain vector
     # arithmetic), from HIP events around its launches on the factor's stream
-    peak = 157.3 if prec == cae.FP32 else 78.6
-    kname = ("k_compress_gram<float> (FP64 Gram, pivoted Cholesky, one-sided Jacobi)" if prec == cae.FP32
-             else "k_compress_wg<double> (TSQR, pivoted QR, one-sided Jacobi)")
+    peak = 78.6 if prec == cae.FP64 else 157.3
+    kname = ("k_compress_wg<double> (TSQR, pivoted QR, one-sided Jacobi)" if prec == cae.FP64 else
+             "k_compress_rand<float> (learned-rank sketch) + k_compress_gram<float> fallback" if fkw else
+             "k_compress_gram<float> (FP64 Gram, pivoted Cholesky, one-sided Jacobi)")
     if comp["launches"]:
         per_launch_s = comp["ms"] / comp["launches"] / 1e3
         flops_per_launch = comp["flops"] / comp["launches"]
@@ -186,7 +243,10 @@ def main():
                            "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                            "traffic": _traffic(kname.split(" ")[0]), "launches_per_step": comp["launches"] / args.steps,
                            "avg_launch_us": per_launch_s * 1e6, "algorithmic_flops_per_launch": flops_per_launch}
-    if not args.no_cpu_baseline:
+    if fkw:
+        out["config"]["sketch_accepted"] = st["sketch_accepted"]
+        out["config"]["sketch_rejected"] = st["sketch_rejected"]
+    if not args.no_cpu_baseline and args.config == "c2":
         out["cpu_baseline"] = _cpu_baseline(args.cpu_side, patch, args.eps, args.nrhs, N)
     print(json.dumps(out), flush=True)
 

@@ -85,6 +85,11 @@ typedef struct {
                               the far row, then the rank fraction r_i / b_i of the step
                               (-1 where the step compressed nothing); CE(eps) or LEARNED */
   int64_t record_cap;      /* rows available in record */
+  int32_t coarsen;         /* cae_analyze with coordinates: 0 = the 2^d Morton siblings form a
+                              block of the next level; 1 = pairs of blocks along the Morton
+                              curve (axis x, y, z in turn: J = 2, keeping J r ~ B, Section
+                              2.6, when ranks are about half the block) */
+  int32_t pad;             /* 0 */
 } cae_options_t;
 
 #define CAE_RECORD_WIDTH 17

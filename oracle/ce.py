@@ -72,6 +72,7 @@ class CEOptions:
     seed: int = 0                   # learned: Philox key of the sketches
     record_features: bool = False   # compute the learned-mode features in any mode (tests only)
     compensate: bool = False        # add |E_i| to the diagonals (keeps M - A0 positive semidefinite)
+    coarsen: str = "siblings"       # 'siblings' (2^d Morton siblings) | 'pairs' (along the Morton curve)
     order: str = "paper"            # 'paper' | 'multicolour'
     coarse_max_dim: int = 2048
     max_levels: int = 0             # 0 = no limit
@@ -363,7 +364,10 @@ def ce_factor(indptr, indices, data, perm, block_ptr, coords, opts: CEOptions, J
         adj = sym.adjacency(M, close_pairs)
         order = sym.element_order(adj, opts.order, coords)
         lf = _factor_level(level_no, sizes, W, close_pairs, order, theta, opts)
-        parent, coords = sym.coarsen(coords, M, J)
+        axis = None
+        if opts.coarsen == "pairs" and coords is not None:
+            axis = (level_no - 1) % np.asarray(coords).shape[1]
+        parent, coords = sym.coarsen(coords, M, J, axis=axis)
         Mn = int(parent.max()) + 1
         lf.parent = parent
         levels.append(lf)

@@ -100,15 +100,21 @@ def adjacency(M, pairs):
     return adj
 
 
-def coarsen(coords, M=None, J=None):
+def coarsen(coords, M=None, J=None, axis=None):
     """Parent of every block: Morton siblings (coordinate >> 1) when
-    coordinates are known, else consecutive groups of J blocks.  Returns
-    ``parent`` (len M) and the parents' coordinates (or None)."""
+    coordinates are known, else consecutive groups of J blocks.  With
+    ``axis`` only that coordinate is halved: pairs of blocks along the Morton
+    curve (the lowest remaining bit of the Morton key).  Returns ``parent``
+    (len M) and the parents' coordinates (or None)."""
     if coords is None:
         parent = np.arange(M) // J
         return parent, None
     coords = np.asarray(coords)
-    pc = coords >> 1
+    if axis is None:
+        pc = coords >> 1
+    else:
+        pc = coords.copy()
+        pc[:, axis] >>= 1
     parent = np.empty(len(coords), dtype=np.int64)
     seen = {}
     out = []

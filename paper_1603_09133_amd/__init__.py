@@ -87,9 +87,11 @@ class Analysis:
     """Symbolic analysis of a CSR pattern with a permutation and blocks."""
 
     def __init__(self, indptr, indices, perm, block_ptr=None, coords=None, B=0, order=ORDER_MULTICOLOUR,
-                 ndim=None):
+                 ndim=None, coarsen="siblings"):
         """Without ``coords`` consecutive groups of ``2**ndim`` blocks form the
-        next level (``ndim=1``: pairs, as for :func:`graph_order`)."""
+        next level (``ndim=1``: pairs, as for :func:`graph_order`).  With
+        coordinates, ``coarsen="siblings"`` joins the 2^d Morton siblings,
+        ``"pairs"`` joins pairs along the Morton curve (axes in turn)."""
         self._ip, self._ix = _i64(indptr), _i32(indices)
         self._perm = _i32(perm)
         n = len(self._ip) - 1
@@ -103,6 +105,7 @@ class Analysis:
         self.order = order
         self.n = n
         o = _options(order=order)
+        o.coarsen = {"siblings": 0, "pairs": 1}[coarsen]
         h = C.c_void_p()
         check(lib().cae_analyze(n, ptr(self._ip), ptr(self._ix), ptr(self._perm), ptr(bp), nb, int(B), ptr(co),
                                 ndim, C.byref(o), C.byref(h)))

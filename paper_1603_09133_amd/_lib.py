@@ -33,7 +33,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("order", C.c_int32), ("max_levels", C.c_int32),
                 ("timing", C.c_int32), ("compensate", C.c_int32),
                 ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p), ("mlp_params", C.c_void_p),
-                ("seed", C.c_uint64), ("record", C.c_void_p), ("record_cap", C.c_int64)]
+                ("seed", C.c_uint64), ("record", C.c_void_p), ("record_cap", C.c_int64), ("coarsen", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class LevelInfo(C.Structure):

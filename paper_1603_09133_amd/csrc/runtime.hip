@@ -729,7 +729,8 @@ int cae_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const
   }
   try {
     std::unique_ptr<cae_analysis_s> A(new cae_analysis_s);
-    std::string e = cae::analyze(n, row_ptr, col_idx, perm, block_ptr, nblocks, B, coords, ndim, o.order, A->a);
+    std::string e = cae::analyze(n, row_ptr, col_idx, perm, block_ptr, nblocks, B, coords, ndim, o.order, A->a,
+                                 o.coarsen);
     if (!e.empty()) return fail(CAE_EINVAL, e);
     *out = A.release();
   } catch (const std::bad_alloc&) {

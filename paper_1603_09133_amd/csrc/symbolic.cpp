@@ -435,7 +435,7 @@ std::string grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch,
 std::string analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                     const int32_t* perm, const int32_t* block_ptr, int32_t nblocks,
                     int32_t B, const int32_t* coords, int32_t ndim, int32_t order_kind,
-                    Analysis& A) {
+                    Analysis& A, int32_t coarsen_kind) {
   if (n <= 0 || n > INT32_MAX) return "n out of range";
   if (!row_ptr || !col_idx || !perm) return "row_ptr, col_idx and perm are required";
   if (order_kind != 0 && order_kind != 1) return "unknown elimination order";
@@ -535,15 +535,24 @@ std::string analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
     L.parent.assign(M, 0);
     std::vector<int32_t> next_coords;
     if (!cur_coords.empty()) {
+      // siblings: 2^d blocks sharing coordinate >> 1 on every axis, or (pairs)
+      // 2 blocks sharing coordinate >> 1 on axis (level mod d) -- the lowest
+      // remaining bit of the Morton key, so the axes alternate
+      const int lev = (int)A.levels.size() - 1;
+      const int ax = coarsen_kind == 1 ? lev % ndim : -1;
       int32_t P = -1;
       std::vector<int32_t> last(ndim, INT32_MIN);
       for (int32_t i = 0; i < M; ++i) {
         bool same = P >= 0;
-        for (int k = 0; k < ndim; ++k) same = same && ((cur_coords[(int64_t)i * ndim + k] >> 1) == last[k]);
+        for (int k = 0; k < ndim; ++k) {
+          const int sh = (ax < 0 || k == ax) ? 1 : 0;
+          same = same && ((cur_coords[(int64_t)i * ndim + k] >> sh) == last[k]);
+        }
         if (!same) {
           ++P;
           for (int k = 0; k < ndim; ++k) {
-            last[k] = cur_coords[(int64_t)i * ndim + k] >> 1;
+            const int sh = (ax < 0 || k == ax) ? 1 : 0;
+            last[k] = cur_coords[(int64_t)i * ndim + k] >> sh;
             next_coords.push_back(last[k]);
           }
         }
@@ -551,10 +560,22 @@ std::string analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
       }
       L.Mnext = P + 1;
       // the siblings must be consecutive (Morton order of the blocks)
-      std::vector<uint64_t> seen;
-      for (int32_t P2 = 0; P2 < L.Mnext; ++P2) seen.push_back(morton(&next_coords[(int64_t)P2 * ndim], ndim));
-      for (size_t k = 1; k < seen.size(); ++k)
-        if (seen[k] <= seen[k - 1]) return "blocks are not in Morton order of their coordinates";
+      if (ax < 0) {
+        std::vector<uint64_t> seen;
+        for (int32_t P2 = 0; P2 < L.Mnext; ++P2) seen.push_back(morton(&next_coords[(int64_t)P2 * ndim], ndim));
+        for (size_t k = 1; k < seen.size(); ++k)
+          if (seen[k] <= seen[k - 1]) return "blocks are not in Morton order of their coordinates";
+      } else {
+        std::vector<uint64_t> seen;
+        for (int32_t P2 = 0; P2 < L.Mnext; ++P2) {
+          uint64_t key = 0;
+          for (int k = 0; k < ndim; ++k) key = key * 2097152u + (uint64_t)(uint32_t)next_coords[(int64_t)P2 * ndim + k];
+          seen.push_back(key);
+        }
+        std::sort(seen.begin(), seen.end());
+        for (size_t k = 1; k < seen.size(); ++k)
+          if (seen[k] == seen[k - 1]) return "blocks are not in Morton order of their coordinates";
+      }
     } else {
       for (int32_t i = 0; i < M; ++i) L.parent[i] = i / J;
       L.Mnext = (M + J - 1) / J;

@@ -65,6 +65,6 @@ std::string grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch,
 std::string analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                     const int32_t* perm, const int32_t* block_ptr, int32_t nblocks,
                     int32_t B, const int32_t* coords, int32_t ndim, int32_t order_kind,
-                    Analysis& out);
+                    Analysis& out, int32_t coarsen_kind = 0);
 
 }  // namespace cae

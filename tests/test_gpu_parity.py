@@ -295,3 +295,20 @@ def test_general_sparse_graph_ordering(eps, order):
     assert it[0] == ito and rel[0] <= 1e-9
     f.close()
     an.close()
+
+
+@pytest.mark.parametrize("dims,patch,eps", [((16, 16, 16), (4, 4, 4), 1e-4), ((40, 24), (8, 8), 1e-6)])
+def test_pairs_coarsening_matches_oracle(dims, patch, eps):
+    """Coarsening by pairs along the Morton curve: GPU factor against the
+    oracle with the same coarsening (ranks, M X to 1e-12)."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup(dims, patch)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order="multicolour", coarse_max_dim=256, coarsen="pairs"))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co, order=cae.ORDER_MULTICOLOUR, coarsen="pairs")
+    f = cae.Factor(an, torch.from_numpy(csr[2]).cuda(), eps, precision=cae.FP64, coarse_max_dim=256)
+    _check_ranks(f, fo)
+    X = _probes(A.shape[0])
+    MX = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    assert np.linalg.norm(MX - ce_multiply(fo, X)) <= 1e-12 * np.linalg.norm(MX)
+    f.close()
+    an.close()

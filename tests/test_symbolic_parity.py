@@ -104,3 +104,29 @@ def test_uniform_blocks_and_errors():
         cae.Analysis(csr[0], csr[1], np.zeros(100), None, None, B=7)        # not a permutation
     with pytest.raises(cae.CAEError):
         cae.Analysis(csr[0], csr[1], np.arange(100), [0, 50, 99], None)      # blocks do not span n
+
+
+@pytest.mark.parametrize("dims,patch", [((16, 16, 16), (4, 4, 4)), ((12, 10), (4, 4)), ((10, 9, 7), (2, 2, 2))])
+def test_pairs_coarsening_matches_oracle(dims, patch):
+    """Coarsening by pairs along the Morton curve (axes in turn): parents and
+    levels bit-exact with the oracle's twin."""
+    import paper_1603_09133_amd as cae
+    A = problems.laplacian(dims)
+    ip, ix, _ = problems.to_csr_arrays(A)
+    perm, bp, co = osym.grid_order(dims, patch)
+    an = cae.Analysis(ip, ix, perm, bp, co, order=cae.ORDER_PAPER, coarsen="pairs")
+    coords = np.asarray(co)
+    M = len(bp) - 1
+    pairs = osym.level1_pattern(ip, ix, perm, bp)
+    for lvl in range(an.nlevels()):
+        arr = an.level_arrays(lvl)
+        order = osym.element_order(osym.adjacency(M, pairs), "paper", coords)
+        assert np.array_equal(arr["order"], np.asarray(order))
+        far, farp, removed = osym.simulate_level(M, pairs, order)
+        if M == 1:
+            break
+        parent, coords = osym.coarsen(coords, M, None, axis=lvl % coords.shape[1])
+        assert np.array_equal(arr["parent"], parent), lvl
+        pairs = osym.coarse_pattern(parent, osym.live_pairs(sorted(set(map(tuple, pairs)) | set(farp)), removed))
+        M = int(parent.max()) + 1
+    an.close()
