@@ -1172,12 +1172,14 @@ __global__ __launch_bounds__(NT) void k_rotate(LevelArgs<T> A, int32_t it0, T* g
       Y[a * ld + c] = s;
     }
     __syncthreads();
-    // D = Y U
+    // D = Y U, stored exactly symmetric (lower triangle mirrored)
     for (int e = tid; e < b * b; e += NT) {
       const int a = e / b, c = e % b;
+      if (c > a) continue;
       T s = 0;
       for (int k = 0; k < b; ++k) s += Y[a * ld + k] * Us[k * ld + c];
       D[e] = s;
+      D[(int64_t)c * b + a] = s;
     }
     return;
   }
@@ -1653,78 +1655,6 @@ __global__ __launch_bounds__(NT) void k_compensate(LevelArgs<T> A, int32_t s0) {
   }
 }
 
-// Elimination of S_i for n_i <= 64: Cholesky S = L L^T and L^{-1} with one
-// barrier per column each (the scaling of column k and the final write of row
-// k of the inverse are deferred to the next column, which no longer reads
-// them), then L(basis, n)^T = L^{-1} D[n, basis] as a tiled product.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
-  const Step st = A.steps[s0 + blockIdx.x];
-  const int i = st.blk;
-  const int b = A.bsz[i];
-  if (b > 64) return;
-  const int r = A.rank[i];
-  const int n = b - r;
-  if (n <= 0) return;
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  using CT = typename AccT<T>::type;       // the diagonal block is factored in FP64
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  CT* S = reinterpret_cast<CT*>(smem_raw);  // n x n, lower part used
-  CT* X = S + 64 * TLD;                     // L^{-1}
-  __shared__ int bad;
-  T* D = A.arena + A.slot_off[i];
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < n * n; e += NT) {
-    const int j = e / n, c = e % n;
-    S[j * TLD + c] = (CT)D[(int64_t)(r + j) * b + r + c];
-    X[j * TLD + c] = j == c ? CT(1) : CT(0);
-  }
-  __syncthreads();
-  chol_inv_lds(S, X, n, &bad);
-  // store L (lower, zero above) and L^{-1}
-  T* Lig = A.Li + A.u_off[i];
-  for (int e = tid; e < n * n; e += NT) {
-    const int j = e / n, c = e % n;
-    D[(int64_t)(r + j) * b + r + c] = c <= j ? (T)S[j * TLD + c] : T(0);
-    Lig[e] = c <= j ? (T)X[j * TLD + c] : T(0);
-  }
-  if (tid == 0) {
-    double mp = 1e300;
-    for (int k = 0; k < n; ++k) mp = fmin(mp, (double)S[k * TLD + k]);
-    A.minpiv[i] = mp;
-    if (bad) {
-      if (atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
-    }
-  }
-  if (r == 0) return;
-  // L(basis, n)^T = L^{-1} D[n, 0:r]: A operand L^{-T} (S <- X^T), B operand D[n, 0:r]
-  __syncthreads();
-  for (int e = tid; e < n * n; e += NT) {
-    const int j = e / n, c = e % n;
-    S[c * TLD + j] = c <= j ? X[j * TLD + c] : CT(0);
-  }
-  __syncthreads();
-  for (int e = tid; e < n * r; e += NT) {
-    const int j = e / r, c = e % r;
-    X[j * TLD + c] = (CT)D[(int64_t)(r + j) * b + c];
-  }
-  __syncthreads();
-  typename AccT<T>::type acc[4][4];
-  zero_acc(acc);
-  gemm_tn_4x4(S, X, n, acc);
-#pragma unroll
-  for (int pq = 0; pq < 4; ++pq) {
-    const int j = 4 * ty + pq;
-    if (j < n)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int c = 4 * tx + q;
-        if (c < r) D[(int64_t)(r + j) * b + c] = (T)acc[pq][q];
-      }
-  }
-  for (int e = tid; e < r * n; e += NT) D[(int64_t)(e / n) * b + r + e % n] = T(0);
-}
-
 // ---------------------------------------------------------------------------
 // Compression of a reduced-precision factor (b <= 64) through the Gram matrix
 // G = F_i F_i^T accumulated in FP64: products of FP32 entries are exact in
@@ -1734,153 +1664,608 @@ __global__ __launch_bounds__(NT) void k_potrf_t(LevelArgs<T> A, int32_t s0) {
 // remaining diagonal, the Gram form of a column-pivoted QR of F_i^T) gives
 // graded rows R, stopped once the trailing diagonal sum is below the rounding
 // level; the one-sided Jacobi and the completion then run in FP64 on R.
-// Replaces the TSQR, whose b sequential column steps per chunk dominate the
-// latency of a step.
+//
+// The kernel is organised for the latency of one step, which bounds every
+// dependency wave with fewer steps than the chip holds at once:
+//   * the far row is gathered through a column map (one descriptor per far
+//     view, staged in parallel), so a chunk of 64 columns of F_i mixes views
+//     and its 16 loads per thread are all in flight together; the next chunk
+//     is loaded while the current one is multiplied (one barrier per chunk);
+//   * the pivoted Cholesky is left-looking and runs in one wavefront (no
+//     workgroup barriers): row k of R is written over row p_k of G, which no
+//     later pivot reads;
+//   * the Jacobi rounds run in one wavefront with the pair reductions done by
+//     DPP lane exchanges inside rows of 16 lanes;
+//   * the reflectors of the completion are built by one wavefront, and the
+//     four wavefronts then form 16 columns of U_i each with no barrier.
+// LDS: 47 KB per workgroup (three workgroups per compute unit).
 // ---------------------------------------------------------------------------
-constexpr int GLD = 68;
+constexpr int GLD = 65;     // row stride of G (doubles)
+constexpr int GCW = 64;     // columns of F_i per staged chunk
+constexpr int GVB = 256;    // far-view descriptors staged at once
+constexpr int GCOLS = 512;  // columns of F_i mapped at once
+
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int DPP_MIRROR8 = 0x141;      // row_half_mirror: lane i <-> 7 - i within 8
+constexpr int DPP_MIRROR16 = 0x140;     // row_mirror: lane i <-> 15 - i within 16
+
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)bits, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of G lanes (G = 2, 4, 8, 16), all lanes active:
+// every lane of a group ends with the same bits (each stage adds two equal
+// partial sums in either order).
+template <int G>
+__device__ inline double group_sum(double v) {
+  v += dpp_f64<DPP_XOR1>(v);
+  if (G >= 4) v += dpp_f64<DPP_XOR2>(v);
+  if (G >= 8) v += dpp_f64<DPP_MIRROR8>(v);
+  if (G >= 16) v += dpp_f64<DPP_MIRROR16>(v);
+  return v;
+}
+
+// Sum over the wavefront, the same value in every lane.
+__device__ inline double wave_sum_u(double v) {
+  v = group_sum<16>(v);
+  return (rdl(v, 0) + rdl(v, 16)) + (rdl(v, 32) + rdl(v, 48));
+}
+
+__device__ inline void amax_step(double& v, int& ix, double ov, int oi) {
+  if (ov > v || (ov == v && oi < ix)) {
+    v = ov;
+    ix = oi;
+  }
+}
+template <int CTRL>
+__device__ inline void amax_dpp(double& v, int& ix) {
+  amax_step(v, ix, dpp_f64<CTRL>(v), __builtin_amdgcn_mov_dpp(ix, CTRL, 0xF, 0xF, false));
+}
+// Largest value over the wavefront and its lane (ties: the lower index), the
+// same in every lane.
+__device__ inline void wave_argmax_u(double& v, int& ix) {
+  amax_dpp<DPP_XOR1>(v, ix);
+  amax_dpp<DPP_XOR2>(v, ix);
+  amax_dpp<DPP_MIRROR8>(v, ix);
+  amax_dpp<DPP_MIRROR16>(v, ix);
+  double bv = rdl(v, 0);
+  int bi = __builtin_amdgcn_readlane(ix, 0);
+  amax_step(bv, bi, rdl(v, 16), __builtin_amdgcn_readlane(ix, 16));
+  amax_step(bv, bi, rdl(v, 32), __builtin_amdgcn_readlane(ix, 32));
+  amax_step(bv, bi, rdl(v, 48), __builtin_amdgcn_readlane(ix, 48));
+  v = bv;
+  ix = bi;
+}
+
+// LDS writes of one lane visible to the other lanes of its wavefront.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One-sided Jacobi on the ma rows R[row[k]] (64 coordinates, zero beyond b)
+// by one wavefront: LP lanes per row pair, 64 / LP pairs per pass, the
+// round-robin pairing of the rows, the rotation tests of jacobi_basis_wg.
+// ---------------------------------------------------------------------------
+// Elimination of the trailing n_i unknowns of a step (eq. (sm_L)) by one
+// wavefront, FP64 arithmetic: the left-looking Cholesky S_ii = L L^T and the
+// forward substitution L [X | P] = [I | D(n, basis)] in one pass over k, so
+// that X = L^{-1} and the panel P = L(basis_i, n_i)^T come out together.
+// Lane j owns row j of L and column j of [X | P] (n + r = b <= 64 columns);
+// step k needs only the broadcast row k of L, so the pivot chain has no
+// workgroup barrier.  LDS: one 64 x 64 array of (L column m, [X | P] row m)
+// pairs, read as one 16-byte load per lane per term.
+// ---------------------------------------------------------------------------
+constexpr int PW_LDS = 64 * 64 * 2 * 8;
+
+template <typename T>
+__global__ __launch_bounds__(WV) void k_potrf_w(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const int lane = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* W = reinterpret_cast<double2*>(smem_raw);   // W[m * 64 + l] = (L(l, m), [X | P](m, l))
+  T* D = A.arena + A.slot_off[i];
+  T* Lig = A.Li + A.u_off[i];
+  // row k of S_ii (lanes < n) and of D(n, basis) (lanes n .. b-1)
+  // (all loads in flight before the first use); S_ii is read from its lower
+  // triangle, column k for step k
+  T pre[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    const int kk = min(k, n - 1);
+    pre[k] = lane < n ? D[(int64_t)(r + lane) * b + r + kk] : (lane < b ? D[(int64_t)(r + kk) * b + lane - n] : T(0));
+  }
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    if (k < n) {
+      const double s = (double)pre[k];
+      W[k * 64 + lane] = make_double2(lane < n ? s : 0.0, lane < n ? (lane == k ? 1.0 : 0.0) : s);
+    }
+  }
+  wave_sync();
+  bool bad = false;
+  double mp = 1e300;
+  for (int k = 0; k < n; ++k) {
+    double2 sx = W[k * 64 + lane];
+    double s = sx.x, x = sx.y;
+    int m = 0;
+    for (; m + 2 <= k; m += 2) {
+      const double2 w0 = W[m * 64 + lane], w1 = W[(m + 1) * 64 + lane];
+      const double b0 = W[m * 64 + k].x, b1 = W[(m + 1) * 64 + k].x;
+      s -= w0.x * b0 + w1.x * b1;
+      x -= b0 * w0.y + b1 * w1.y;
+    }
+    if (m < k) {
+      const double2 w0 = W[m * 64 + lane];
+      const double b0 = W[m * 64 + k].x;
+      s -= w0.x * b0;
+      x -= b0 * w0.y;
+    }
+    const double d = rdl(s, k);
+    double inv = 0.0, lkk = 0.0;
+    if (d > 0.0) {
+      inv = 1.0 / sqrt(d);
+      lkk = d * inv;
+    } else {
+      bad = true;
+    }
+    mp = fmin(mp, lkk);
+    const double lv = (lane > k && lane < n) ? s * inv : (lane == k ? lkk : 0.0);
+    const double xv = x * inv;
+    W[k * 64 + lane] = make_double2(lv, xv);
+    if (lane < n) {
+      D[(int64_t)(r + lane) * b + r + k] = (T)lv;
+      Lig[k * n + lane] = (T)xv;
+    } else if (lane < b) {
+      D[(int64_t)(r + k) * b + (lane - n)] = (T)xv;
+    }
+    wave_sync();
+  }
+  // the basis rows of the eliminated columns are zero after the elimination
+  for (int e = lane; e < r * n; e += WV) D[(int64_t)(e / n) * b + r + e % n] = T(0);
+  if (lane == 0) {
+    A.minpiv[i] = mp;
+    if (bad && atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
+  }
+}
+
+// 1/sqrt(x) for x >= 1: the hardware estimate refined by two Newton steps
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, r, y);
+  }
+  return y;
+}
+
+template <int LP>
+__device__ int jacobi_rows_wave(double* R, const int* row, int ma, double negl, double aerr, double tol) {
+  constexpr int NC = 64 / LP, PPASS = 64 / LP;
+  const int lane = threadIdx.x & 63, sub = lane % LP;
+  const int mm = ma + (ma & 1), np = mm / 2, m1 = mm - 1;
+  const double negl2 = negl * negl, aerr2 = aerr * aerr, tol2 = tol * tol;
+  int nsweep = 0;
+  for (int sweep = 0; sweep < 40 && ma > 1; ++sweep) {
+    ++nsweep;
+    bool rotated = false;
+    for (int rho = 0; rho < m1; ++rho) {
+      for (int pb = 0; pb < np; pb += PPASS) {
+        const int pp = pb + lane / LP;
+        int p = -1, q = -1;
+        if (pp < np) {
+          if (pp == 0) {
+            p = m1;
+            q = rho;
+          } else {
+            p = rho + pp;
+            if (p >= m1) p -= m1;
+            q = rho - pp;
+            if (q < 0) q += m1;
+          }
+          if (p > q) {
+            const int tmp = p;
+            p = q;
+            q = tmp;
+          }
+          if (q >= ma) p = -1;
+        }
+        double x[NC], y[NC];
+        double a = 0.0, c = 0.0, d = 0.0;
+        double* xr = R;
+        double* yr = R;
+        if (p >= 0) {
+          xr = R + row[p] * GLD;
+          yr = R + row[q] * GLD;
+#pragma unroll
+          for (int u = 0; u < NC; ++u) {
+            x[u] = xr[sub + LP * u];
+            y[u] = yr[sub + LP * u];
+            a += x[u] * x[u];
+            c += y[u] * y[u];
+            d += x[u] * y[u];
+          }
+        }
+        a = group_sum<LP>(a);
+        c = group_sum<LP>(c);
+        d = group_sum<LP>(d);
+        // the tests of jacobi_basis_wg on squares: |d| > tol |x||y|, one of
+        // the rows above negl, |d| > aerr max(|x|, |y|)
+        const double d2 = d * d;
+        if (p >= 0 && d != 0.0 && d2 > tol2 * a * c && (a > negl2 || c > negl2) && d2 > aerr2 * fmax(a, c)) {
+          // t = tan of the rotation angle, the smaller root of
+          // t^2 + 2 zeta t - 1 = 0 with zeta = (c - a) / 2d
+          const double e = c - a, f = 2.0 * d;
+          const double h = sqrt(e * e + f * f);
+          const double tt = (e >= 0.0 ? f : -f) / (fabs(e) + h);
+          const double cs = rsqrt_nr(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+          for (int u = 0; u < NC; ++u) {
+            xr[sub + LP * u] = cs * x[u] - sn * y[u];
+            yr[sub + LP * u] = sn * x[u] + cs * y[u];
+          }
+          rotated = true;
+        }
+        wave_sync();
+      }
+    }
+    if (__ballot(rotated) == 0) break;
+  }
+  return nsweep;
+}
 
 template <typename T>
 size_t work_compress_gram() {
-  return (size_t)2 * 64 * GLD * sizeof(double) + 4 * 64 * sizeof(double) + 2 * 64 * sizeof(int);
+  const size_t gram = (size_t)2 * GCW * TLD * sizeof(T) + (size_t)GCOLS * (8 + 4) + (size_t)GVB * (8 + 4 + 4) +
+                      (size_t)(GVB + 1) * 4;
+  const size_t fact = (size_t)64 * GLD * sizeof(double);
+  return (((gram > fact ? gram : fact) + 15) & ~(size_t)15) + 3 * 64 * sizeof(double) + 3 * 64 * sizeof(int);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0) {
-  const Step st = A.steps[s0 + blockIdx.x];
-  const int i = st.blk;
-  if (A.need_exact && !A.need_exact[i]) return;   // taken by the sketch kernel
-  const int b = A.bsz[i];
-  if (b > 64) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ty = tid >> 4, tx = tid & 15;
-  T* Ug = A.U + A.u_off[i];
-  if (st.nfar == 0 || b == 0) {
-    for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
-    if (tid == 0) {
-      A.rank[i] = 0;
-      A.edrop[i] = 0.0;
+  if constexpr (sizeof(T) != sizeof(float)) {
+    return;   // FP64 factors take k_compress_wg
+  } else {
+    const Step st = A.steps[s0 + blockIdx.x];
+    const int i = st.blk;
+    if (A.need_exact && !A.need_exact[i]) return;   // taken by the sketch kernel
+    const int b = A.bsz[i];
+    if (b > 64) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ty = tid >> 4, tx = tid & 15;
+    T* Ug = A.U + A.u_off[i];
+    if (st.nfar == 0 || b == 0) {
+      for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
+      if (tid == 0) {
+        A.rank[i] = 0;
+        A.edrop[i] = 0.0;
+      }
+      return;
     }
-    return;
-  }
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* G = reinterpret_cast<double*>(smem_raw);   // 64 x GLD Gram matrix, then basis vectors
-  double* X = G + 64 * GLD;                          // 64 x GLD rows of R, then Q
-  T* Ft = reinterpret_cast<T*>(X);                   // 64 x TLD tile of F_i^T (Gram phase only)
-  double* dg = X + 64 * GLD;                         // trailing diagonal
-  double* lc = dg + 64;                              // current Cholesky column
-  double* sg = lc + 64;
-  double* tau = sg + 64;
-  int* posv = reinterpret_cast<int*>(tau + 64);
-  int* chosen = posv + 64;
-  __shared__ double shd[4];
-  __shared__ int shi[4];
-  const int64_t t_start = clock64();
-  int wtot = 0;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // Gram phase: two staged chunks, the column map, the view descriptors
+    T* stg0 = reinterpret_cast<T*>(smem_raw);
+    T* stg1 = stg0 + GCW * TLD;
+    int64_t* coff = reinterpret_cast<int64_t*>(stg1 + GCW * TLD);
+    int64_t* voff = coff + GCOLS;
+    int* cstr = reinterpret_cast<int*>(voff + GVB);
+    int* vbx = cstr + GCOLS;
+    int* vtr = vbx + GVB;
+    int* vst = vtr + GVB;   // GVB + 1 column starts
+    // factor phases: G (64 x GLD); rows of R overwrite the pivot rows of G
+    double* G = reinterpret_cast<double*>(smem_raw);
+    size_t big = (size_t)2 * GCW * TLD * sizeof(T) + (size_t)GCOLS * 12 + (size_t)GVB * 16 + (size_t)(GVB + 1) * 4;
+    if (big < (size_t)64 * GLD * sizeof(double)) big = (size_t)64 * GLD * sizeof(double);
+    big = (big + 15) & ~(size_t)15;
+    double* sg = reinterpret_cast<double*>(smem_raw + big);
+    double* tau = sg + 64;
+    double* isg = tau + 64;
+    int* prow = reinterpret_cast<int*>(isg + 64);   // G row holding row k of R
+    int* posv = prow + 64;                          // rank order of row k
+    int* brow = posv + 64;                          // G row holding kept direction c
+    __shared__ int wsum[4];
+    __shared__ double shd[4];
+    __shared__ int shi[4];
+    __shared__ int64_t shj;
+    const int64_t t_start = clock64();
 
-  // ---- 1. G = sum over far views V V^T (register tiles, FP64 accumulation) --
-  double acc[4][4];
-  zero_acc(acc);
-  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
-    const View v = A.views[st.view0 + f];
-    const int bx = A.bsz[v.x];
-    const int w = v.proc ? A.rank[v.x] : bx;
-    const T* base = A.arena + A.slot_off[v.slot];
-    wtot += w;
-    for (int c0 = 0; c0 < w; c0 += 64) {
-      const int mc = min(64, w - c0);
+    // ---- 1. G = F_i F_i^T ----------------------------------------------------
+    double acc[4][4];
+    zero_acc(acc);
+    int wtot = 0;
+    for (int f0 = 0; f0 < st.nfar;) {
+      const int nv = min(GVB, st.nfar - f0);
       __syncthreads();
-      if (v.trans) {
-        for (int e = tid; e < mc * b; e += NT) {
-          const int m = e / b, a = e % b;
-          Ft[m * TLD + a] = base[(int64_t)(c0 + m) * b + a];
+      int wme = 0;
+      if (tid < nv) {
+        const View v = A.views[st.view0 + st.nclose + f0 + tid];
+        const int bx = A.bsz[v.x];
+        wme = v.proc ? A.rank[v.x] : bx;
+        voff[tid] = A.slot_off[v.slot];
+        vbx[tid] = bx;
+        vtr[tid] = v.trans;
+      }
+      int incl = wme;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, WV);
+        if (lane >= o) incl += y;
+      }
+      if (lane == 63) wsum[wv] = incl;
+      __syncthreads();
+      int base = 0;
+      for (int k = 0; k < wv; ++k) base += wsum[k];
+      if (tid < nv) vst[tid + 1] = base + incl;
+      if (tid == 0) vst[0] = 0;
+      __syncthreads();
+      // the views whose columns end within the map (at least one: w <= 64)
+      const int nb = __syncthreads_count(tid < nv && vst[tid + 1] <= GCOLS);
+      const int Wb = vst[nb];
+      for (int c = tid; c < Wb; c += NT) {
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (vst[mid] <= c) lo = mid;
+          else hi = mid - 1;
         }
-      } else {
-        for (int e = tid; e < mc * b; e += NT) {
-          const int a = e / mc, m = e % mc;
-          Ft[m * TLD + a] = base[(int64_t)a * bx + c0 + m];
-        }
+        const int m = c - vst[lo];
+        coff[c] = voff[lo] + (vtr[lo] ? (int64_t)m * b : (int64_t)m);
+        cstr[c] = vtr[lo] ? 1 : vbx[lo];
       }
       __syncthreads();
-      gemm_tn_4x4(Ft, Ft, mc, acc);
+      const int nch = (Wb + GCW - 1) / GCW;
+      T rg[GCW / 4];
+      auto load = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < GCW / 4; ++k) {
+          const int c = c0 + wv + 4 * k;
+          rg[k] = (lane < b && c < Wb) ? A.arena[coff[c] + (int64_t)lane * cstr[c]] : T(0);
+        }
+      };
+      auto store = [&](T* S) {
+#pragma unroll
+        for (int k = 0; k < GCW / 4; ++k) S[(wv + 4 * k) * TLD + lane] = rg[k];
+      };
+      load(0);
+      store(stg0);
+      __syncthreads();
+      for (int ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) load((ch + 1) * GCW);
+        T* S = (ch & 1) ? stg1 : stg0;
+        gemm_tn_4x4<T, double>(S, S, min(GCW, Wb - ch * GCW), acc);
+        if (ch + 1 < nch) store((ch & 1) ? stg0 : stg1);
+        __syncthreads();
+      }
+      wtot += Wb;
+      f0 += nb;
     }
-  }
-  __syncthreads();
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) G[(4 * ty + p) * GLD + 4 * tx + q] = acc[p][q];
-  __syncthreads();
-  const int64_t t_qr = clock64();
+      for (int q = 0; q < 4; ++q) G[(4 * ty + p) * GLD + 4 * tx + q] = acc[p][q];
+    __syncthreads();
+    const int64_t t_qr = clock64();
 
-  // ---- 2. pivoted Cholesky G = R^T R, rows of R into X ----------------------
-  if (wv == 0) {
-    const double gd = lane < b ? G[lane * GLD + lane] : 0.0;
-    const double fro2 = wave_sum(gd);
-    dg[lane] = gd;
-    chosen[lane] = 0;
-    if (lane == 0) shd[0] = fro2;
-  }
-  __syncthreads();
-  // rounding level of the factor's own entries (its precision T), as in the
-  // other compression kernels
-  const double noise = (double)Eps<T>::v() * sqrt(shd[0]);
-  const double theta = *A.theta;
-  const double negl = A.rank_mode == 0 ? fmax(noise, theta / 64.0) : noise;
-  const double aerr = A.rank_mode == 0 ? fmax(noise, fmin((double)max(b, 16) * noise, theta / 32.0))
-                                       : (double)max(b, 16) * noise;
-  const double stop2 = aerr * aerr;
-  int k = 0;
-  for (; k < b; ++k) {
+    // ---- 2-4. one wavefront: pivoted Cholesky, Jacobi, rank, reflectors -------
     if (wv == 0) {
-      const bool in = lane < b && !chosen[lane];
-      const double dv = in ? dg[lane] : 0.0;
-      const double rs = wave_sum(dv);
-      double cv = in ? dv : -1.0;
-      int ci = lane;
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(cv, o, WV);
-        const int oi = __shfl_xor(ci, o, WV);
-        if (ov > cv || (ov == cv && oi < ci)) {
-          cv = ov;
-          ci = oi;
+      const double theta = *A.theta;
+      double dgl = lane < b ? G[lane * GLD + lane] : 0.0;
+      const double fro2 = wave_sum_u(dgl);
+      // rounding level of the factor's own entries (its precision T), as in
+      // the other compression kernels
+      const double noise = (double)Eps<T>::v() * sqrt(fro2);
+      const double negl = A.rank_mode == 0 ? fmax(noise, theta / 64.0) : noise;
+      const double aerr = A.rank_mode == 0 ? fmax(noise, fmin((double)max(b, 16) * noise, theta / 32.0))
+                                           : (double)max(b, 16) * noise;
+      const double stop2 = aerr * aerr;
+      bool chosen = false;
+      double inactive = 0.0;
+      int prl = 0;   // lane j: the G row holding row j of R
+      int k = 0;
+      for (; k < b; ++k) {
+        const bool in = lane < b && !chosen;
+        const double rs = wave_sum_u(in ? dgl : 0.0);
+        double cv = in ? dgl : -1.0;
+        int ci = lane;
+        wave_argmax_u(cv, ci);
+        if (rs <= stop2 || !(cv > 0.0)) {
+          inactive = rs;
+          break;
+        }
+        const int p = ci;
+        const double ilpp = 1.0 / sqrt(cv), lpp = cv * ilpp;
+        // column p of the trailing matrix: G(:, p) - sum_j R(j, :)^T R(j, p)
+        double s = G[p * GLD + lane];
+        int j = 0;
+        for (; j + 4 <= k; j += 4) {
+          const double* r0 = G + __builtin_amdgcn_readlane(prl, j) * GLD;
+          const double* r1 = G + __builtin_amdgcn_readlane(prl, j + 1) * GLD;
+          const double* r2 = G + __builtin_amdgcn_readlane(prl, j + 2) * GLD;
+          const double* r3 = G + __builtin_amdgcn_readlane(prl, j + 3) * GLD;
+          const double a0 = r0[lane] * r0[p], a1 = r1[lane] * r1[p], a2 = r2[lane] * r2[p], a3 = r3[lane] * r3[p];
+          s -= (a0 + a1) + (a2 + a3);
+        }
+        for (; j < k; ++j) {
+          const double* rj = G + __builtin_amdgcn_readlane(prl, j) * GLD;
+          s -= rj[lane] * rj[p];
+        }
+        const double lv = (lane >= b || chosen) ? 0.0 : (lane == p ? lpp : s * ilpp);
+        G[p * GLD + lane] = lv;   // row k of R replaces row p of G
+        if (lane == k) prl = p;
+        if (lane == p) chosen = true;
+        else if (in) dgl -= lv * lv;
+        wave_sync();
+      }
+      const int ma = k;
+      if (lane < ma) prow[lane] = prl;
+      wave_sync();
+      const int64_t t_cmp = clock64();
+      // ---- Jacobi on the ma rows of R
+      const double tol = (double)max(b, 16) * DBL_EPSILON;
+      const int np = (ma + 1) / 2;
+      int nsweep;
+      if (np <= 4) nsweep = jacobi_rows_wave<16>(G, prow, ma, negl, aerr, tol);
+      else if (np <= 8) nsweep = jacobi_rows_wave<8>(G, prow, ma, negl, aerr, tol);
+      else nsweep = jacobi_rows_wave<4>(G, prow, ma, negl, aerr, tol);
+      const int64_t t_jac = clock64();
+      // ---- singular values, order, rank
+      double sgl = 0.0;
+      if (lane < ma) {
+        const double* rr = G + prow[lane] * GLD;
+        double s0 = 0.0, s1 = 0.0;
+        for (int t = 0; t < 64; t += 2) {
+          s0 += rr[t] * rr[t];
+          s1 += rr[t + 1] * rr[t + 1];
+        }
+        sgl = sqrt(s0 + s1);
+        sg[lane] = sgl;
+      }
+      wave_sync();
+      int pos = 0;
+      if (lane < ma) {
+        for (int q = 0; q < ma; ++q) pos += (sg[q] > sgl || (sg[q] == sgl && q < lane)) ? 1 : 0;
+        posv[lane] = pos;
+      }
+      const int cnt = __popcll(__ballot(lane < ma && sgl > theta));
+      const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
+      const double ed = wave_sum_u((lane < ma && pos >= r) ? sgl * sgl : 0.0);
+      const int kb = min(r, ma);
+      int label = 0;
+      if (A.rec) {
+        // training label: the smallest sketch width k >= r that an ideal
+        // sketch would need to pass the a-posteriori check,
+        // tail(k) + (k > r ? sigma_r^2 : 0) <= theta^2, tail(k) = sum of
+        // sigma_j^2 over positions j >= k plus the inactive energy
+        if (lane < ma) tau[pos] = sgl * sgl;
+        wave_sync();
+        const double th2 = theta * theta;
+        const double sr2 = r < ma ? tau[r] : 0.0;
+        double tail = inactive;
+        int kf = ma;
+        for (int kk = ma; kk >= r; --kk) {
+          if (kk < ma) tail += tau[kk];
+          if (tail + (kk > r ? sr2 : 0.0) <= th2) kf = kk;
+        }
+        label = max(kf, r);
+        wave_sync();
+      }
+      // kept directions, normalised, in rank order
+      if (lane < ma && pos < kb) {
+        brow[pos] = prow[lane];
+        isg[pos] = sgl > 0.0 ? 1.0 / sgl : 0.0;
+      }
+      wave_sync();
+      for (int c2 = 0; c2 < kb; ++c2) G[brow[c2] * GLD + lane] *= isg[c2];
+      wave_sync();
+      // ---- Householder reflectors of the kept directions
+      for (int cv = 0; cv < kb; ++cv) {
+        double* vr = G + brow[cv] * GLD;
+        const double xl = vr[lane];
+        const double x = (lane >= cv && lane < b) ? xl : 0.0;
+        const double nrm2 = wave_sum_u(x * x);
+        const double x0 = vr[cv];
+        const double nrm = sqrt(nrm2);
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double vv = v0 * v0 + (nrm2 - x0 * x0);
+        const double tc = vv > 0.0 ? 2.0 / vv : 0.0;
+        wave_sync();
+        if (lane < cv) vr[lane] = 0.0;
+        if (lane == cv) vr[cv] = v0;
+        if (lane == 0) tau[cv] = tc;
+        wave_sync();
+        // H_cv on the later directions: 4 lanes per direction
+        for (int cb = cv + 1; cb < kb; cb += 16) {
+          const int c2 = cb + (lane >> 2), sb = lane & 3;
+          double vreg[16], breg[16];
+          double dd = 0.0;
+          double* br = G + brow[min(c2, kb - 1)] * GLD;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            vreg[u] = vr[sb + 4 * u];
+            breg[u] = br[sb + 4 * u];
+            dd += vreg[u] * breg[u];
+          }
+          dd = group_sum<4>(dd);
+          if (c2 < kb) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) br[sb + 4 * u] = breg[u] - tc * dd * vreg[u];
+          }
+          wave_sync();
         }
       }
-      const bool stop = rs <= stop2 || !(cv > 0.0);
       if (lane == 0) {
-        shi[3] = stop ? 1 : 0;
-        shd[1] = rs;
-        if (!stop) {
-          shi[2] = ci;
-          shd[3] = sqrt(cv);
-          chosen[ci] = 1;
+        shi[0] = kb;
+        shi[1] = r;
+        shi[2] = label;
+        shd[0] = ed + inactive;
+        if (A.dbg) {
+          int64_t* dd = A.dbg + 72 * (int64_t)i;
+          dd[0] = ma;
+          dd[1] = nsweep;
+          dd[2] = wtot;
+          dd[3] = b;
+          dd[4] = t_qr - t_start;
+          dd[5] = t_cmp - t_qr;
+          dd[6] = t_jac - t_cmp;
+          shj = t_jac;
+        }
+      }
+      if (A.dbg && lane < ma) {
+        double* sv = reinterpret_cast<double*>(A.dbg + 72 * (int64_t)i + 8);
+        sv[lane] = sg[lane];
+      }
+    }
+    __syncthreads();
+
+    // ---- 5. U_i = H_0 ... H_{kb-1}: each wavefront 16 columns, 4 lanes each --
+    const int kb = shi[0];
+    {
+      const int col = wv * 16 + (lane >> 2), sb = lane & 3;
+      double qv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) qv[u] = (sb + 4 * u == col) ? 1.0 : 0.0;
+      for (int cv = kb - 1; cv >= 0; --cv) {
+        const double* vr = G + brow[cv] * GLD;
+        const double tc = tau[cv];
+        double vreg[16];
+        double dd = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          vreg[u] = vr[sb + 4 * u];
+          dd += vreg[u] * qv[u];
+        }
+        dd = group_sum<4>(dd);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) qv[u] -= tc * dd * vreg[u];
+      }
+      if (col < b) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = sb + 4 * u;
+          if (t < b) Ug[t * b + col] = (T)qv[u];
         }
       }
     }
-    __syncthreads();
-    if (shi[3]) break;
-    const int p = shi[2];
-    const double lpp = shd[3];
-    if (tid < 64) {
-      const int t = tid;
-      const double lv = t >= b ? 0.0 : (t == p ? lpp : (chosen[t] ? 0.0 : G[t * GLD + p] / lpp));
-      lc[t] = lv;
-      X[k * GLD + t] = lv;
+    if (tid == 0) {
+      A.rank[i] = shi[1];
+      A.edrop[i] = shd[0];
+      if (A.rec) A.rec[(A.rec_off + i) * REC_W + NFEAT] = (float)shi[2] / (float)b;
+      if (A.dbg) A.dbg[72 * (int64_t)i + 7] = clock64() - shj;
     }
-    __syncthreads();
-    for (int t = ty; t < b; t += 16) {
-      const double lt = lc[t];
-      for (int u = tx; u < b; u += 16) {
-        const double g = G[t * GLD + u] - lt * lc[u];
-        G[t * GLD + u] = g;
-        if (u == t) dg[t] = g;
-      }
-    }
-    __syncthreads();
   }
-  const int ma = k;
-  const double inactive = k < b ? shd[1] : 0.0;
-  const int64_t t_cmp = clock64();
-  jacobi_basis_wg<double, T>(A, i, b, ma, X, G, GLD, nullptr, inactive, negl, aerr, sg, tau, posv, shi, shd, Ug,
-                             wtot, t_start, t_qr, t_cmp);
 }
 
 // ---------------------------------------------------------------------------
@@ -2300,6 +2685,8 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
     __syncthreads();
     zero_acc(acc);
     gemm_tn_4x4(Us, X, b, acc);       // U^T Z
+    // the rotated block is stored exactly symmetric: the lower triangle is
+    // mirrored (the two triangles of U^T Z differ by the rounding of Z)
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int a = 4 * ty + p;
@@ -2307,7 +2694,11 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int c = 4 * tx + q;
-          if (c < b) D[a * b + c] = (T)acc[p][q];
+          if (c <= a) {
+            const T v = (T)acc[p][q];
+            D[a * b + c] = v;
+            D[c * b + a] = v;
+          }
         }
     }
     return;
@@ -2323,8 +2714,12 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
     load_view_tile(X, base, v.trans, b, bx, 0, b, c0, tc);
     __syncthreads();
     zero_acc(acc);
-    gemm_tn_4x4(Us, X, b, acc);
-    if (far && !A.compensate) {   // with compensation k_compensate zeroes E_i after using it
+    // a far view keeps only its rows < r_i (E_i is dropped): wavefronts whose
+    // rows all lie beyond r_i skip the product (with compensation k_compensate
+    // reads E_i and zeroes it afterwards)
+    const bool drop = far && !A.compensate;
+    if (!drop || 4 * ty < r) gemm_tn_4x4(Us, X, b, acc);
+    if (drop) {
 #pragma unroll
       for (int p = 0; p < 4; ++p)
         if (4 * ty + p >= r)
@@ -2853,10 +3248,9 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
   if (A.compensate && w.s1 > w.s0)
     hipLaunchKernelGGL(k_compensate<T>, dim3(w.s1 - w.s0), dim3(NT), 0, stream, A, w.s0);
-  const size_t wp = work_tiled<T>() * sizeof(typename AccT<T>::type);
-  const bool ptiled = tiled && wp <= max_lds_bytes();
+  const bool ptiled = tiled && (size_t)PW_LDS <= max_lds_bytes();
   if (ptiled && w.s1 > w.s0)
-    hipLaunchKernelGGL(k_potrf_t<T>, dim3(w.s1 - w.s0), dim3(NT), wp, stream, B, w.s0);
+    hipLaunchKernelGGL(k_potrf_w<T>, dim3(w.s1 - w.s0), dim3(WV), PW_LDS, stream, B, w.s0);
   if (!ptiled)
     launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
   else if (generic)
