@@ -1764,6 +1764,61 @@ __device__ inline void wave_sync() {
 // ---------------------------------------------------------------------------
 constexpr int PW_LDS = 64 * 64 * 2 * 8;
 
+// The pass over k of one wavefront on W (n <= 64 rows filled with
+// (S(l, m), RHS(m, l))): on exit W[m * 64 + l] = (L(l, m), L^{-1} RHS (m, l)).
+// The sums over m take eight terms per round of LDS loads (two partial sums
+// per quantity).  emit(k, lv, xv) receives each finished step; returns false
+// on a non-positive pivot, mp = smallest L_kk.
+template <typename Emit>
+__device__ bool chol_fwd_wave(double2* W, int n, double& mp, Emit emit) {
+  const int lane = threadIdx.x & 63;
+  bool ok = true;
+  mp = 1e300;
+  for (int k = 0; k < n; ++k) {
+    const double2 sx = W[k * 64 + lane];
+    double s0 = sx.x, x0 = sx.y, s1 = 0.0, x1 = 0.0;
+    int m = 0;
+    for (; m + 8 <= k; m += 8) {
+      double2 w[8];
+      double bk[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        w[u] = W[(m + u) * 64 + lane];
+        bk[u] = W[(m + u) * 64 + k].x;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        s0 -= w[u].x * bk[u];
+        x0 -= bk[u] * w[u].y;
+        s1 -= w[u + 1].x * bk[u + 1];
+        x1 -= bk[u + 1] * w[u + 1].y;
+      }
+    }
+    for (; m < k; ++m) {
+      const double2 w0 = W[m * 64 + lane];
+      const double b0 = W[m * 64 + k].x;
+      s0 -= w0.x * b0;
+      x0 -= b0 * w0.y;
+    }
+    const double s = s0 + s1, x = x0 + x1;
+    const double d = rdl(s, k);
+    double inv = 0.0, lkk = 0.0;
+    if (d > 0.0) {
+      inv = 1.0 / sqrt(d);
+      lkk = d * inv;
+    } else {
+      ok = false;
+    }
+    mp = fmin(mp, lkk);
+    const double lv = (lane > k && lane < n) ? s * inv : (lane == k ? lkk : 0.0);
+    const double xv = x * inv;
+    W[k * 64 + lane] = make_double2(lv, xv);
+    emit(k, lv, xv);
+    wave_sync();
+  }
+  return ok;
+}
+
 template <typename T>
 __global__ __launch_bounds__(WV) void k_potrf_w(LevelArgs<T> A, int32_t s0) {
   const Step st = A.steps[s0 + blockIdx.x];
@@ -1795,49 +1850,20 @@ __global__ __launch_bounds__(WV) void k_potrf_w(LevelArgs<T> A, int32_t s0) {
     }
   }
   wave_sync();
-  bool bad = false;
-  double mp = 1e300;
-  for (int k = 0; k < n; ++k) {
-    double2 sx = W[k * 64 + lane];
-    double s = sx.x, x = sx.y;
-    int m = 0;
-    for (; m + 2 <= k; m += 2) {
-      const double2 w0 = W[m * 64 + lane], w1 = W[(m + 1) * 64 + lane];
-      const double b0 = W[m * 64 + k].x, b1 = W[(m + 1) * 64 + k].x;
-      s -= w0.x * b0 + w1.x * b1;
-      x -= b0 * w0.y + b1 * w1.y;
-    }
-    if (m < k) {
-      const double2 w0 = W[m * 64 + lane];
-      const double b0 = W[m * 64 + k].x;
-      s -= w0.x * b0;
-      x -= b0 * w0.y;
-    }
-    const double d = rdl(s, k);
-    double inv = 0.0, lkk = 0.0;
-    if (d > 0.0) {
-      inv = 1.0 / sqrt(d);
-      lkk = d * inv;
-    } else {
-      bad = true;
-    }
-    mp = fmin(mp, lkk);
-    const double lv = (lane > k && lane < n) ? s * inv : (lane == k ? lkk : 0.0);
-    const double xv = x * inv;
-    W[k * 64 + lane] = make_double2(lv, xv);
+  double mp;
+  const bool ok = chol_fwd_wave(W, n, mp, [&](int k, double lv, double xv) {
     if (lane < n) {
       D[(int64_t)(r + lane) * b + r + k] = (T)lv;
       Lig[k * n + lane] = (T)xv;
     } else if (lane < b) {
       D[(int64_t)(r + k) * b + (lane - n)] = (T)xv;
     }
-    wave_sync();
-  }
+  });
   // the basis rows of the eliminated columns are zero after the elimination
   for (int e = lane; e < r * n; e += WV) D[(int64_t)(e / n) * b + r + e % n] = T(0);
   if (lane == 0) {
     A.minpiv[i] = mp;
-    if (bad && atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
+    if (!ok && atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
   }
 }
 
@@ -3062,23 +3088,35 @@ constexpr int GJ = 64;
 __global__ __launch_bounds__(NT) void k_gj_pivot(double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv,
                                                  int32_t* err) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* S = reinterpret_cast<double*>(smem_raw);
-  double* X = S + 64 * TLD;
+  double2* W = reinterpret_cast<double2*>(smem_raw);   // (L(l, m), L^{-1}(m, l))
   __shared__ int bad;
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < kb * kb; e += NT) {
-    const int j = e / kb, c = e % kb;
-    S[j * TLD + c] = Ad[(k0 + j) * dim + k0 + c];
-    X[j * TLD + c] = j == c ? 1.0 : 0.0;
+  for (int e = tid; e < kb * 64; e += NT) {
+    const int m = e >> 6, l = e & 63;
+    W[e] = make_double2(l < kb ? Ad[(k0 + l) * dim + k0 + m] : 0.0, l == m ? 1.0 : 0.0);   // lower triangle
   }
   __syncthreads();
-  chol_inv_lds(S, X, kb, &bad);
+  if (tid < WV) {
+    double mp;
+    const bool ok = chol_fwd_wave(W, kb, mp, [](int, double, double) {});
+    if (tid == 0) bad = ok ? 0 : 1;
+  }
   __syncthreads();
   // Pinv = L^{-T} L^{-1}
   double acc[4][4];
   zero_acc(acc);
-  gemm_tn_4x4(X, X, kb, acc);
+  for (int k = 0; k < kb; ++k) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      av[q] = W[k * 64 + 4 * ty + q].y;
+      bv[q] = W[k * 64 + 4 * tx + q].y;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] += av[p] * bv[q];
+  }
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
