@@ -51,6 +51,11 @@ def _cpu_baseline(side, patch, eps, nrhs_full, full_n):
                        f"for the PCG part")}
 
 
+def _log(msg):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     (FETCH_SIZE / WRITE_SIZE runs scaled by a plain copy), or None when the
@@ -152,9 +157,11 @@ def main():
     N = A.shape[0]
     if args.config != "c5":
         perm, bp, co = cae.grid_order(dims, patch)
+    _log(f"{args.config}: N={A.shape[0]}, symbolic analysis")
     t = time.perf_counter()
     an = cae.Analysis(ip, ix, perm, bp, co, order=order, coarsen=coarsen)
     analysis_ms = (time.perf_counter() - t) * 1e3
+    _log(f"analysis {analysis_ms:.0f} ms, {an.nlevels()} levels")
     vals = torch.from_numpy(dv).to(dev)
     b = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
     x = torch.empty_like(b)
@@ -183,15 +190,20 @@ def main():
         _, it, rel = f.pcg(b, rtol=1e-8, maxit=1000, x=x)
         return f, it, rel
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
+        tw = time.perf_counter()
         f, it, rel = step()
         f.close()
+        torch.cuda.synchronize()
+        _log(f"warmup step {k + 1}/{args.warmup}: {(time.perf_counter() - tw) * 1e3:.0f} ms, PCG iterations "
+             f"max {int(np.max(it))}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fac_ms = []
     comp = {"ms": 0.0, "launches": 0, "flops": 0.0}
-    for _ in range(args.steps):
+    for k in range(args.steps):
         f, it, rel = step()
+        _log(f"timed step {k + 1}/{args.steps} done")
         st = f.stats()
         fac_ms.append(st["factor_ms"])
         comp["ms"] += st["compress_ms"]

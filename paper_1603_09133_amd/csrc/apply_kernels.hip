@@ -498,15 +498,29 @@ __global__ void k_perm_out(int64_t n, int32_t nrhs, const int32_t* perm, const d
 }
 
 // ------------------------------------------------------------------ PCG ----
+// y = A x for all right-hand sides: one thread per row, the row's entries
+// read once per group of eight right-hand sides (the matrix is streamed
+// nrhs / 8 times, not nrhs times).
 __global__ void k_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
-                       const double* x, int64_t ldx, double* y, int64_t ldy) {
+                       int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
   if (i >= n) return;
-  const double* xk = x + k * ldx;
-  double s = 0;
-  for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += vals[e] * xk[col_idx[e]];
-  y[i + k * ldy] = s;
+  const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+  for (int k0 = 0; k0 < nrhs; k0 += 8) {
+    double s[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+      const double v = vals[e];
+      const int64_t c = col_idx[e];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (k0 + j < nrhs) s[j] += v * x[(int64_t)(k0 + j) * ldx + c];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k0 + j < nrhs) y[(int64_t)(k0 + j) * ldy + i] = s[j];
+  }
 }
 
 constexpr int DOT_BLOCKS = 1024;
@@ -717,8 +731,8 @@ void launch_perm_out(int64_t n, int32_t nrhs, const int32_t* perm, const double*
 
 void launch_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals, int32_t nrhs,
                  const double* x, int64_t ldx, double* y, int64_t ldy, hipStream_t stream) {
-  hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n + NT - 1) / NT), nrhs), dim3(NT), 0, stream, n, row_ptr, col_idx,
-                     vals, x, ldx, y, ldy);
+  hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, stream, n, row_ptr, col_idx, vals,
+                     nrhs, x, ldx, y, ldy);
 }
 
 void launch_dots(int64_t n, int32_t nrhs, const double* a, int64_t lda, const double* b, int64_t ldb,

@@ -3197,14 +3197,20 @@ __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64
 // Launchers.
 // ---------------------------------------------------------------------------
 template <typename T>
+int32_t scratch_group(int bmax);
+template <typename T>
 static void launch(void (*kern)(LevelArgs<T>, int32_t, T*, int64_t), const LevelArgs<T>& A, int32_t start,
-                   int32_t count, size_t work_elems, T* gscratch, hipStream_t stream) {
+                   int32_t count, size_t work_elems, T* gscratch, hipStream_t stream, int bmax) {
   if (count <= 0) return;
   const size_t bytes = work_elems * sizeof(T);
   if (bytes <= max_lds_bytes()) {
     hipLaunchKernelGGL(kern, dim3(count), dim3(NT), bytes, stream, A, start, (T*)nullptr, (int64_t)0);
   } else {
-    hipLaunchKernelGGL(kern, dim3(count), dim3(NT), 0, stream, A, start, gscratch, (int64_t)work_elems);
+    // the scratch holds scratch_group(bmax) slices: launch in chunks of that many
+    const int32_t g = scratch_group<T>(bmax);
+    for (int32_t c0 = 0; c0 < count; c0 += g)
+      hipLaunchKernelGGL(kern, dim3(min(g, count - c0)), dim3(NT), 0, stream, A, start + c0, gscratch,
+                         (int64_t)work_elems);
   }
 }
 
@@ -3241,6 +3247,15 @@ size_t factor_scratch_elems(int bmax) {
 }
 
 template <typename T>
+int32_t scratch_group(int bmax) {
+  const size_t per = factor_scratch_elems<T>(bmax) * sizeof(T);
+  size_t g = ((size_t)4 << 30) / (per ? per : 1);   // at most 4 GiB of scratch
+  if (g > 4096) g = 4096;
+  if (g < 64) g = 64;
+  return (int32_t)g;
+}
+
+template <typename T>
 bool factor_needs_global(int bmax) {
   return factor_scratch_elems<T>(bmax) * sizeof(T) > max_lds_bytes();
 }
@@ -3266,7 +3281,7 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
       } else {
         LevelArgs<T> C = A;
         C.small_by_wave = 64;
-        launch<T>(k_compress<T>, C, w.s0, ns, work_compress<T>(bmax), gs, stream);
+        launch<T>(k_compress<T>, C, w.s0, ns, work_compress<T>(bmax), gs, stream, bmax);
       }
     }
   }
@@ -3283,27 +3298,27 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   B.items = A.rot;
   if (tiled && w.r1 > w.r0)
     hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
-  if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream);
+  if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream, bmax);
   if (A.compensate && w.s1 > w.s0)
     hipLaunchKernelGGL(k_compensate<T>, dim3(w.s1 - w.s0), dim3(NT), 0, stream, A, w.s0);
   const bool ptiled = tiled && (size_t)PW_LDS <= max_lds_bytes();
   if (ptiled && w.s1 > w.s0)
     hipLaunchKernelGGL(k_potrf_w<T>, dim3(w.s1 - w.s0), dim3(WV), PW_LDS, stream, B, w.s0);
   if (!ptiled)
-    launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
+    launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
   else if (generic)
-    launch<T>(k_potrf<T>, B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream);
+    launch<T>(k_potrf<T>, B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
   B.items = A.trsm;
   if (tiled && w.t1 > w.t0)
     hipLaunchKernelGGL(k_trsm_t<T>, dim3(w.t1 - w.t0), dim3(NT), wt, stream, B, w.t0);
-  if (generic) launch<T>(k_trsm<T>, B, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream);
+  if (generic) launch<T>(k_trsm<T>, B, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream, bmax);
   if (tiled && w.p1 > w.p0) {
     if (A.bf16_schur && sizeof(T) == sizeof(float))
       hipLaunchKernelGGL(k_schur_bf16<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
     else
       hipLaunchKernelGGL(k_schur_t<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
   }
-  if (generic) launch<T>(k_schur<T>, B, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream);
+  if (generic) launch<T>(k_schur<T>, B, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream, bmax);
 }
 
 template <typename T>
@@ -3361,6 +3376,7 @@ void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double*
 #define CAE_INST(T)                                                                                         \
   template size_t factor_scratch_elems<T>(int);                                                            \
   template bool factor_needs_global<T>(int);                                                               \
+  template int32_t scratch_group<T>(int);                                                                  \
   template void launch_wave_compress<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);      \
   template void launch_wave_rest<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);          \
   template void launch_scatter_a0<T>(T*, const double*, const int64_t*, int64_t, hipStream_t);             \

@@ -70,6 +70,9 @@ template <typename T>
 size_t factor_scratch_elems(int bmax);
 template <typename T>
 bool factor_needs_global(int bmax);
+// workgroups sharing the global scratch at once (generic kernels run in chunks)
+template <typename T>
+int32_t scratch_group(int bmax);
 // the compression of a wave, then rotation, elimination and Schur update
 template <typename T>
 void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);

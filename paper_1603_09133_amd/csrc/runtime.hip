@@ -377,6 +377,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
                            (size_t)(w.p1 - w.p0)});
     T* gs = nullptr;
     if (cae::factor_needs_global<T>(N.bmax)) {
+      maxitems = std::min(maxitems, (size_t)cae::scratch_group<T>(N.bmax));
       h->gscratch.alloc(maxitems * cae::factor_scratch_elems<T>(N.bmax) * sizeof(T));
       gs = h->gscratch.as<T>();
     }
