@@ -1656,7 +1656,7 @@ __global__ __launch_bounds__(NT) void k_compensate(LevelArgs<T> A, int32_t s0) {
 }
 
 // ---------------------------------------------------------------------------
-// Compression of a reduced-precision factor (b <= 64) through the Gram matrix
+// Compression of a reduced-precision factor (b <= 128) through the Gram matrix
 // G = F_i F_i^T accumulated in FP64: products of FP32 entries are exact in
 // FP64, so G carries the far row to FP64 accuracy, and its eigenvalues sigma^2
 // resolve singular values down to about 1e-7 sigma_1, well below the FP32
@@ -1678,9 +1678,9 @@ __global__ __launch_bounds__(NT) void k_compensate(LevelArgs<T> A, int32_t s0) {
 //     DPP lane exchanges inside rows of 16 lanes;
 //   * the reflectors of the completion are built by one wavefront, and the
 //     four wavefronts then form 16 columns of U_i each with no barrier.
-// LDS: 47 KB per workgroup (three workgroups per compute unit).
+// Two instances: b <= 64 (LDS 48 KB, three workgroups per compute unit) and
+// 64 < b <= 128 (LDS 139 KB, each lane owning two coordinates).
 // ---------------------------------------------------------------------------
-constexpr int GLD = 65;     // row stride of G (doubles)
 constexpr int GCW = 64;     // columns of F_i per staged chunk
 constexpr int GVB = 256;    // far-view descriptors staged at once
 constexpr int GCOLS = 512;  // columns of F_i mapped at once
@@ -1878,9 +1878,13 @@ __device__ inline double rsqrt_nr(double x) {
   return y;
 }
 
-template <int LP>
-__device__ int jacobi_rows_wave(double* R, const int* row, int ma, double negl, double aerr, double tol) {
-  constexpr int NC = 64 / LP, PPASS = 64 / LP;
+// One-sided Jacobi on the ma rows R[row[k]] (BM coordinates, zero beyond b,
+// row stride ld) by one wavefront: LP lanes per row pair, 64 / LP pairs per
+// pass, the round-robin pairing of the rows, the rotation tests of
+// jacobi_basis_wg.
+template <int LP, int BM>
+__device__ int jacobi_rows_wave(double* R, int ld, const int* row, int ma, double negl, double aerr, double tol) {
+  constexpr int NC = BM / LP, PPASS = 64 / LP;
   const int lane = threadIdx.x & 63, sub = lane % LP;
   const int mm = ma + (ma & 1), np = mm / 2, m1 = mm - 1;
   const double negl2 = negl * negl, aerr2 = aerr * aerr, tol2 = tol * tol;
@@ -1914,8 +1918,8 @@ __device__ int jacobi_rows_wave(double* R, const int* row, int ma, double negl, 
         double* xr = R;
         double* yr = R;
         if (p >= 0) {
-          xr = R + row[p] * GLD;
-          yr = R + row[q] * GLD;
+          xr = R + row[p] * ld;
+          yr = R + row[q] * ld;
 #pragma unroll
           for (int u = 0; u < NC; ++u) {
             x[u] = xr[sub + LP * u];
@@ -1953,24 +1957,59 @@ __device__ int jacobi_rows_wave(double* R, const int* row, int ma, double negl, 
   return nsweep;
 }
 
-template <typename T>
-size_t work_compress_gram() {
-  const size_t gram = (size_t)2 * GCW * TLD * sizeof(T) + (size_t)GCOLS * (8 + 4) + (size_t)GVB * (8 + 4 + 4) +
-                      (size_t)(GVB + 1) * 4;
-  const size_t fact = (size_t)64 * GLD * sizeof(double);
-  return (((gram > fact ? gram : fact) + 15) & ~(size_t)15) + 3 * 64 * sizeof(double) + 3 * 64 * sizeof(int);
+// C[TM x TM tile of thread (ty, tx)] += A^T A over K rows of the staged chunk
+// S (row stride ld, BM = 16 TM columns), FP64 accumulation.
+template <int TM, typename T>
+__device__ inline void gram_tile(const T* S, int ld, int K, double acc[TM][TM]) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const T* a = S + TM * ty;
+  const T* bb = S + TM * tx;
+#pragma unroll 2
+  for (int k = 0; k < K; ++k) {
+    double av[TM], bv[TM];
+#pragma unroll
+    for (int q = 0; q < TM; ++q) {
+      av[q] = (double)a[k * ld + q];
+      bv[q] = (double)bb[k * ld + q];
+    }
+#pragma unroll
+    for (int p = 0; p < TM; ++p)
+#pragma unroll
+      for (int q = 0; q < TM; ++q) acc[p][q] += av[p] * bv[q];
+  }
 }
 
-template <typename T>
+// LDS layout of the Gram compression for blocks of at most BM unknowns.
+template <typename T, int BM>
+struct GramLds {
+  static constexpr int GL = BM + 1;                // row stride of G (doubles)
+  static constexpr int SL = BM + 4;                // row stride of a staged chunk
+  static constexpr size_t gram_phase =
+      (size_t)2 * GCW * SL * sizeof(T) + (size_t)GCOLS * 12 + (size_t)GVB * 16 + (size_t)(GVB + 1) * 4;
+  static constexpr size_t factor_phase = (size_t)BM * GL * sizeof(double);
+  static constexpr size_t big =
+      ((gram_phase > factor_phase ? gram_phase : factor_phase) + 15) & ~(size_t)15;
+  static constexpr size_t total = big + 3 * BM * sizeof(double) + 3 * BM * sizeof(int);
+};
+
+template <typename T, int BM>
+size_t work_compress_gram() {
+  return GramLds<T, BM>::total;
+}
+
+// Blocks with BM - 64 < b <= BM (all b <= 64 for BM = 64).
+template <typename T, int BM>
 __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0) {
   if constexpr (sizeof(T) != sizeof(float)) {
     return;   // FP64 factors take k_compress_wg
   } else {
+    using L = GramLds<T, BM>;
+    constexpr int GL = L::GL, SL = L::SL, NL = BM / 64, TM = BM / 16;
     const Step st = A.steps[s0 + blockIdx.x];
     const int i = st.blk;
     if (A.need_exact && !A.need_exact[i]) return;   // taken by the sketch kernel
     const int b = A.bsz[i];
-    if (b > 64) return;
+    if (b > BM || b <= BM - 64) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ty = tid >> 4, tx = tid & 15;
     T* Ug = A.U + A.u_off[i];
     if (st.nfar == 0 || b == 0) {
@@ -1984,24 +2023,21 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // Gram phase: two staged chunks, the column map, the view descriptors
     T* stg0 = reinterpret_cast<T*>(smem_raw);
-    T* stg1 = stg0 + GCW * TLD;
-    int64_t* coff = reinterpret_cast<int64_t*>(stg1 + GCW * TLD);
+    T* stg1 = stg0 + GCW * SL;
+    int64_t* coff = reinterpret_cast<int64_t*>(stg1 + GCW * SL);
     int64_t* voff = coff + GCOLS;
     int* cstr = reinterpret_cast<int*>(voff + GVB);
     int* vbx = cstr + GCOLS;
     int* vtr = vbx + GVB;
     int* vst = vtr + GVB;   // GVB + 1 column starts
-    // factor phases: G (64 x GLD); rows of R overwrite the pivot rows of G
+    // factor phases: G (BM x GL); rows of R overwrite the pivot rows of G
     double* G = reinterpret_cast<double*>(smem_raw);
-    size_t big = (size_t)2 * GCW * TLD * sizeof(T) + (size_t)GCOLS * 12 + (size_t)GVB * 16 + (size_t)(GVB + 1) * 4;
-    if (big < (size_t)64 * GLD * sizeof(double)) big = (size_t)64 * GLD * sizeof(double);
-    big = (big + 15) & ~(size_t)15;
-    double* sg = reinterpret_cast<double*>(smem_raw + big);
-    double* tau = sg + 64;
-    double* isg = tau + 64;
-    int* prow = reinterpret_cast<int*>(isg + 64);   // G row holding row k of R
-    int* posv = prow + 64;                          // rank order of row k
-    int* brow = posv + 64;                          // G row holding kept direction c
+    double* sg = reinterpret_cast<double*>(smem_raw + L::big);
+    double* tau = sg + BM;
+    double* isg = tau + BM;
+    int* prow = reinterpret_cast<int*>(isg + BM);   // G row holding row k of R
+    int* posv = prow + BM;                          // rank order of row k
+    int* brow = posv + BM;                          // G row holding kept direction c
     __shared__ int wsum[4];
     __shared__ double shd[4];
     __shared__ int shi[4];
@@ -2009,8 +2045,11 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
     const int64_t t_start = clock64();
 
     // ---- 1. G = F_i F_i^T ----------------------------------------------------
-    double acc[4][4];
-    zero_acc(acc);
+    double acc[TM][TM];
+#pragma unroll
+    for (int p = 0; p < TM; ++p)
+#pragma unroll
+      for (int q = 0; q < TM; ++q) acc[p][q] = 0.0;
     int wtot = 0;
     for (int f0 = 0; f0 < st.nfar;) {
       const int nv = min(GVB, st.nfar - f0);
@@ -2036,7 +2075,7 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
       if (tid < nv) vst[tid + 1] = base + incl;
       if (tid == 0) vst[0] = 0;
       __syncthreads();
-      // the views whose columns end within the map (at least one: w <= 64)
+      // the views whose columns end within the map (at least one: w <= BM)
       const int nb = __syncthreads_count(tid < nv && vst[tid + 1] <= GCOLS);
       const int Wb = vst[nb];
       for (int c = tid; c < Wb; c += NT) {
@@ -2052,17 +2091,21 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
       }
       __syncthreads();
       const int nch = (Wb + GCW - 1) / GCW;
-      T rg[GCW / 4];
+      T rg[NL][GCW / 4];
       auto load = [&](int c0) {
 #pragma unroll
-        for (int k = 0; k < GCW / 4; ++k) {
-          const int c = c0 + wv + 4 * k;
-          rg[k] = (lane < b && c < Wb) ? A.arena[coff[c] + (int64_t)lane * cstr[c]] : T(0);
-        }
+        for (int h = 0; h < NL; ++h)
+#pragma unroll
+          for (int k = 0; k < GCW / 4; ++k) {
+            const int c = c0 + wv + 4 * k, a = lane + 64 * h;
+            rg[h][k] = (a < b && c < Wb) ? A.arena[coff[c] + (int64_t)a * cstr[c]] : T(0);
+          }
       };
       auto store = [&](T* S) {
 #pragma unroll
-        for (int k = 0; k < GCW / 4; ++k) S[(wv + 4 * k) * TLD + lane] = rg[k];
+        for (int h = 0; h < NL; ++h)
+#pragma unroll
+          for (int k = 0; k < GCW / 4; ++k) S[(wv + 4 * k) * SL + lane + 64 * h] = rg[h][k];
       };
       load(0);
       store(stg0);
@@ -2070,7 +2113,7 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
       for (int ch = 0; ch < nch; ++ch) {
         if (ch + 1 < nch) load((ch + 1) * GCW);
         T* S = (ch & 1) ? stg1 : stg0;
-        gemm_tn_4x4<T, double>(S, S, min(GCW, Wb - ch * GCW), acc);
+        gram_tile<TM, T>(S, SL, min(GCW, Wb - ch * GCW), acc);
         if (ch + 1 < nch) store((ch & 1) ? stg0 : stg1);
         __syncthreads();
       }
@@ -2078,17 +2121,25 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
       f0 += nb;
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < TM; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) G[(4 * ty + p) * GLD + 4 * tx + q] = acc[p][q];
+      for (int q = 0; q < TM; ++q) G[(TM * ty + p) * GL + TM * tx + q] = acc[p][q];
     __syncthreads();
     const int64_t t_qr = clock64();
 
     // ---- 2-4. one wavefront: pivoted Cholesky, Jacobi, rank, reflectors -------
+    // lane owns the coordinates t = lane + 64 h, h < NL
     if (wv == 0) {
       const double theta = *A.theta;
-      double dgl = lane < b ? G[lane * GLD + lane] : 0.0;
-      const double fro2 = wave_sum_u(dgl);
+      double dgl[NL];
+      double tr0 = 0.0;
+#pragma unroll
+      for (int h = 0; h < NL; ++h) {
+        const int t = lane + 64 * h;
+        dgl[h] = t < b ? G[t * GL + t] : 0.0;
+        tr0 += dgl[h];
+      }
+      const double fro2 = wave_sum_u(tr0);
       // rounding level of the factor's own entries (its precision T), as in
       // the other compression kernels
       const double noise = (double)Eps<T>::v() * sqrt(fro2);
@@ -2096,15 +2147,25 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
       const double aerr = A.rank_mode == 0 ? fmax(noise, fmin((double)max(b, 16) * noise, theta / 32.0))
                                            : (double)max(b, 16) * noise;
       const double stop2 = aerr * aerr;
-      bool chosen = false;
+      bool chosen[NL];
+#pragma unroll
+      for (int h = 0; h < NL; ++h) chosen[h] = false;
       double inactive = 0.0;
-      int prl = 0;   // lane j: the G row holding row j of R
       int k = 0;
       for (; k < b; ++k) {
-        const bool in = lane < b && !chosen;
-        const double rs = wave_sum_u(in ? dgl : 0.0);
-        double cv = in ? dgl : -1.0;
+        double rsl = 0.0, cv = -1.0;
         int ci = lane;
+#pragma unroll
+        for (int h = 0; h < NL; ++h) {
+          const int t = lane + 64 * h;
+          const bool in = t < b && !chosen[h];
+          if (in) rsl += dgl[h];
+          if (in && dgl[h] > cv) {
+            cv = dgl[h];
+            ci = t;
+          }
+        }
+        const double rs = wave_sum_u(rsl);
         wave_argmax_u(cv, ci);
         if (rs <= stop2 || !(cv > 0.0)) {
           inactive = rs;
@@ -2113,60 +2174,86 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
         const int p = ci;
         const double ilpp = 1.0 / sqrt(cv), lpp = cv * ilpp;
         // column p of the trailing matrix: G(:, p) - sum_j R(j, :)^T R(j, p)
-        double s = G[p * GLD + lane];
+        double s[NL];
+#pragma unroll
+        for (int h = 0; h < NL; ++h) s[h] = G[p * GL + lane + 64 * h];
         int j = 0;
         for (; j + 4 <= k; j += 4) {
-          const double* r0 = G + __builtin_amdgcn_readlane(prl, j) * GLD;
-          const double* r1 = G + __builtin_amdgcn_readlane(prl, j + 1) * GLD;
-          const double* r2 = G + __builtin_amdgcn_readlane(prl, j + 2) * GLD;
-          const double* r3 = G + __builtin_amdgcn_readlane(prl, j + 3) * GLD;
-          const double a0 = r0[lane] * r0[p], a1 = r1[lane] * r1[p], a2 = r2[lane] * r2[p], a3 = r3[lane] * r3[p];
-          s -= (a0 + a1) + (a2 + a3);
+          const double* r0 = G + prow[j] * GL;
+          const double* r1 = G + prow[j + 1] * GL;
+          const double* r2 = G + prow[j + 2] * GL;
+          const double* r3 = G + prow[j + 3] * GL;
+          const double b0 = r0[p], b1 = r1[p], b2 = r2[p], b3 = r3[p];
+#pragma unroll
+          for (int h = 0; h < NL; ++h) {
+            const int t = lane + 64 * h;
+            s[h] -= (r0[t] * b0 + r1[t] * b1) + (r2[t] * b2 + r3[t] * b3);
+          }
         }
         for (; j < k; ++j) {
-          const double* rj = G + __builtin_amdgcn_readlane(prl, j) * GLD;
-          s -= rj[lane] * rj[p];
+          const double* rj = G + prow[j] * GL;
+          const double bj = rj[p];
+#pragma unroll
+          for (int h = 0; h < NL; ++h) s[h] -= rj[lane + 64 * h] * bj;
         }
-        const double lv = (lane >= b || chosen) ? 0.0 : (lane == p ? lpp : s * ilpp);
-        G[p * GLD + lane] = lv;   // row k of R replaces row p of G
-        if (lane == k) prl = p;
-        if (lane == p) chosen = true;
-        else if (in) dgl -= lv * lv;
+#pragma unroll
+        for (int h = 0; h < NL; ++h) {
+          const int t = lane + 64 * h;
+          const bool in = t < b && !chosen[h];
+          const double lv = (t >= b || chosen[h]) ? 0.0 : (t == p ? lpp : s[h] * ilpp);
+          G[p * GL + t] = lv;   // row k of R replaces row p of G
+          if (t == p) chosen[h] = true;
+          else if (in) dgl[h] -= lv * lv;
+        }
+        if (lane == 0) prow[k] = p;
         wave_sync();
       }
       const int ma = k;
-      if (lane < ma) prow[lane] = prl;
-      wave_sync();
       const int64_t t_cmp = clock64();
       // ---- Jacobi on the ma rows of R
       const double tol = (double)max(b, 16) * DBL_EPSILON;
       const int np = (ma + 1) / 2;
       int nsweep;
-      if (np <= 4) nsweep = jacobi_rows_wave<16>(G, prow, ma, negl, aerr, tol);
-      else if (np <= 8) nsweep = jacobi_rows_wave<8>(G, prow, ma, negl, aerr, tol);
-      else nsweep = jacobi_rows_wave<4>(G, prow, ma, negl, aerr, tol);
+      if (np <= 4) nsweep = jacobi_rows_wave<16, BM>(G, GL, prow, ma, negl, aerr, tol);
+      else if (np <= 8) nsweep = jacobi_rows_wave<8, BM>(G, GL, prow, ma, negl, aerr, tol);
+      else nsweep = jacobi_rows_wave<4, BM>(G, GL, prow, ma, negl, aerr, tol);
       const int64_t t_jac = clock64();
-      // ---- singular values, order, rank
-      double sgl = 0.0;
-      if (lane < ma) {
-        const double* rr = G + prow[lane] * GLD;
-        double s0 = 0.0, s1 = 0.0;
-        for (int t = 0; t < 64; t += 2) {
-          s0 += rr[t] * rr[t];
-          s1 += rr[t + 1] * rr[t + 1];
+      // ---- singular values, order, rank (lane owns rows lane + 64 h)
+      double sgl[NL];
+#pragma unroll
+      for (int h = 0; h < NL; ++h) {
+        const int q = lane + 64 * h;
+        sgl[h] = 0.0;
+        if (q < ma) {
+          const double* rr = G + prow[q] * GL;
+          double s0 = 0.0, s1 = 0.0;
+          for (int t = 0; t < BM; t += 2) {
+            s0 += rr[t] * rr[t];
+            s1 += rr[t + 1] * rr[t + 1];
+          }
+          sgl[h] = sqrt(s0 + s1);
+          sg[q] = sgl[h];
         }
-        sgl = sqrt(s0 + s1);
-        sg[lane] = sgl;
       }
       wave_sync();
-      int pos = 0;
-      if (lane < ma) {
-        for (int q = 0; q < ma; ++q) pos += (sg[q] > sgl || (sg[q] == sgl && q < lane)) ? 1 : 0;
-        posv[lane] = pos;
+      int pos[NL];
+      int cnt = 0;
+      double edl = 0.0;
+#pragma unroll
+      for (int h = 0; h < NL; ++h) {
+        const int q0 = lane + 64 * h;
+        pos[h] = 0;
+        if (q0 < ma) {
+          for (int q = 0; q < ma; ++q) pos[h] += (sg[q] > sgl[h] || (sg[q] == sgl[h] && q < q0)) ? 1 : 0;
+          posv[q0] = pos[h];
+        }
+        cnt += __popcll(__ballot(q0 < ma && sgl[h] > theta));
       }
-      const int cnt = __popcll(__ballot(lane < ma && sgl > theta));
       const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
-      const double ed = wave_sum_u((lane < ma && pos >= r) ? sgl * sgl : 0.0);
+#pragma unroll
+      for (int h = 0; h < NL; ++h)
+        if (lane + 64 * h < ma && pos[h] >= r) edl += sgl[h] * sgl[h];
+      const double ed = wave_sum_u(edl);
       const int kb = min(r, ma);
       int label = 0;
       if (A.rec) {
@@ -2174,7 +2261,9 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
         // sketch would need to pass the a-posteriori check,
         // tail(k) + (k > r ? sigma_r^2 : 0) <= theta^2, tail(k) = sum of
         // sigma_j^2 over positions j >= k plus the inactive energy
-        if (lane < ma) tau[pos] = sgl * sgl;
+#pragma unroll
+        for (int h = 0; h < NL; ++h)
+          if (lane + 64 * h < ma) tau[pos[h]] = sgl[h] * sgl[h];
         wave_sync();
         const double th2 = theta * theta;
         const double sr2 = r < ma ? tau[r] : 0.0;
@@ -2188,19 +2277,32 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
         wave_sync();
       }
       // kept directions, normalised, in rank order
-      if (lane < ma && pos < kb) {
-        brow[pos] = prow[lane];
-        isg[pos] = sgl > 0.0 ? 1.0 / sgl : 0.0;
+#pragma unroll
+      for (int h = 0; h < NL; ++h) {
+        const int q = lane + 64 * h;
+        if (q < ma && pos[h] < kb) {
+          brow[pos[h]] = prow[q];
+          isg[pos[h]] = sgl[h] > 0.0 ? 1.0 / sgl[h] : 0.0;
+        }
       }
       wave_sync();
-      for (int c2 = 0; c2 < kb; ++c2) G[brow[c2] * GLD + lane] *= isg[c2];
+      for (int c2 = 0; c2 < kb; ++c2) {
+        const double f = isg[c2];
+#pragma unroll
+        for (int h = 0; h < NL; ++h) G[brow[c2] * GL + lane + 64 * h] *= f;
+      }
       wave_sync();
       // ---- Householder reflectors of the kept directions
       for (int cv = 0; cv < kb; ++cv) {
-        double* vr = G + brow[cv] * GLD;
-        const double xl = vr[lane];
-        const double x = (lane >= cv && lane < b) ? xl : 0.0;
-        const double nrm2 = wave_sum_u(x * x);
+        double* vr = G + brow[cv] * GL;
+        double xs = 0.0;
+#pragma unroll
+        for (int h = 0; h < NL; ++h) {
+          const int t = lane + 64 * h;
+          const double x = (t >= cv && t < b) ? vr[t] : 0.0;
+          xs += x * x;
+        }
+        const double nrm2 = wave_sum_u(xs);
         const double x0 = vr[cv];
         const double nrm = sqrt(nrm2);
         const double alpha = x0 >= 0.0 ? -nrm : nrm;
@@ -2208,18 +2310,23 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
         const double vv = v0 * v0 + (nrm2 - x0 * x0);
         const double tc = vv > 0.0 ? 2.0 / vv : 0.0;
         wave_sync();
-        if (lane < cv) vr[lane] = 0.0;
-        if (lane == cv) vr[cv] = v0;
+#pragma unroll
+        for (int h = 0; h < NL; ++h) {
+          const int t = lane + 64 * h;
+          if (t < cv) vr[t] = 0.0;
+          if (t == cv) vr[cv] = v0;
+        }
         if (lane == 0) tau[cv] = tc;
         wave_sync();
-        // H_cv on the later directions: 4 lanes per direction
+        // H_cv on the later directions: 4 lanes per direction, BM / 4
+        // coordinates per lane
         for (int cb = cv + 1; cb < kb; cb += 16) {
           const int c2 = cb + (lane >> 2), sb = lane & 3;
-          double vreg[16], breg[16];
+          double vreg[BM / 4], breg[BM / 4];
           double dd = 0.0;
-          double* br = G + brow[min(c2, kb - 1)] * GLD;
+          double* br = G + brow[min(c2, kb - 1)] * GL;
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
+          for (int u = 0; u < BM / 4; ++u) {
             vreg[u] = vr[sb + 4 * u];
             breg[u] = br[sb + 4 * u];
             dd += vreg[u] * breg[u];
@@ -2227,7 +2334,7 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
           dd = group_sum<4>(dd);
           if (c2 < kb) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) br[sb + 4 * u] = breg[u] - tc * dd * vreg[u];
+            for (int u = 0; u < BM / 4; ++u) br[sb + 4 * u] = breg[u] - tc * dd * vreg[u];
           }
           wave_sync();
         }
@@ -2237,6 +2344,7 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
         shi[1] = r;
         shi[2] = label;
         shd[0] = ed + inactive;
+        shj = t_jac;
         if (A.dbg) {
           int64_t* dd = A.dbg + 72 * (int64_t)i;
           dd[0] = ma;
@@ -2246,40 +2354,40 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
           dd[4] = t_qr - t_start;
           dd[5] = t_cmp - t_qr;
           dd[6] = t_jac - t_cmp;
-          shj = t_jac;
         }
       }
-      if (A.dbg && lane < ma) {
+      if (A.dbg && lane < ma && lane < 64) {
         double* sv = reinterpret_cast<double*>(A.dbg + 72 * (int64_t)i + 8);
         sv[lane] = sg[lane];
       }
     }
     __syncthreads();
 
-    // ---- 5. U_i = H_0 ... H_{kb-1}: each wavefront 16 columns, 4 lanes each --
+    // ---- 5. U_i = H_0 ... H_{kb-1}: 4 lanes per column, BM / 4 coordinates
+    // per lane, 16 columns per wavefront and pass --------------------------------
     const int kb = shi[0];
-    {
-      const int col = wv * 16 + (lane >> 2), sb = lane & 3;
-      double qv[16];
+    for (int col0 = 16 * wv; col0 < BM; col0 += 64) {
+      const int col = col0 + (lane >> 2), sb = lane & 3;
+      double qv[BM / 4];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) qv[u] = (sb + 4 * u == col) ? 1.0 : 0.0;
+      for (int u = 0; u < BM / 4; ++u) qv[u] = (sb + 4 * u == col) ? 1.0 : 0.0;
       for (int cv = kb - 1; cv >= 0; --cv) {
-        const double* vr = G + brow[cv] * GLD;
+        const double* vr = G + brow[cv] * GL;
         const double tc = tau[cv];
-        double vreg[16];
+        double vreg[BM / 4];
         double dd = 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < BM / 4; ++u) {
           vreg[u] = vr[sb + 4 * u];
           dd += vreg[u] * qv[u];
         }
         dd = group_sum<4>(dd);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) qv[u] -= tc * dd * vreg[u];
+        for (int u = 0; u < BM / 4; ++u) qv[u] -= tc * dd * vreg[u];
       }
       if (col < b) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < BM / 4; ++u) {
           const int t = sb + 4 * u;
           if (t < b) Ug[t * b + col] = (T)qv[u];
         }
@@ -3270,12 +3378,21 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
     if (A.mlp || A.feat_only)
       hipLaunchKernelGGL(k_compress_rand<T>, dim3(ns), dim3(NT), work_compress_rand<T>(), stream, A, w.s0);
     const size_t wg = work_compress_wg<T>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
-    const size_t wgr = work_compress_gram<T>();
-    if (sizeof(T) < sizeof(double) && wgr <= max_lds_bytes())
-      hipLaunchKernelGGL(k_compress_gram<T>, dim3(ns), dim3(NT), wgr, stream, A, w.s0);
+    const size_t wgr = work_compress_gram<T, 64>(), wgr2 = work_compress_gram<T, 128>();
+    const bool gram = sizeof(T) < sizeof(double) && wgr <= max_lds_bytes();
+    const bool gram2 = gram && wgr2 <= max_lds_bytes();
+    if (gram)
+      hipLaunchKernelGGL((k_compress_gram<T, 64>), dim3(ns), dim3(NT), wgr, stream, A, w.s0);
     else
       hipLaunchKernelGGL(k_compress_wg<T>, dim3(ns), dim3(NT), wg, stream, A, w.s0);
-    if (bmax > 64) {
+    if (bmax > 64 && gram2) {
+      hipLaunchKernelGGL((k_compress_gram<T, 128>), dim3(ns), dim3(NT), wgr2, stream, A, w.s0);
+      if (bmax > 128) {
+        LevelArgs<T> C = A;
+        C.small_by_wave = 128;
+        launch<T>(k_compress<T>, C, w.s0, ns, work_compress<T>(bmax), gs, stream, bmax);
+      }
+    } else if (bmax > 64) {
       if (bmax <= 128 && w128 <= max_lds_bytes()) {
         hipLaunchKernelGGL((k_compress_wave<T, 128>), dim3(ns), dim3(WV), w128, stream, A, w.s0);
       } else {

@@ -165,6 +165,33 @@ def test_multi_rhs_pcg_and_fp32_factor():
     assert np.all(it32 <= np.array(its_o) + 2)
 
 
+def test_fp32_factor_with_blocks_above_64():
+    """FP32 factor of a 3D Laplacian whose second level holds blocks of 65..128
+    unknowns (the Gram compression's two-coordinates-per-lane instance):
+    probe error against the FP64 oracle within the FP32 bound, and the ranks
+    of that level equal to the oracle's wherever the oracle's singular values
+    are not within the FP32 rounding level of the threshold."""
+    cae = _cae()
+    dims, patch, eps = (16, 16, 16), (2, 2, 4), 1e-4
+    A, csr, perm, bp, co = _setup(dims, patch)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order="multicolour", coarse_max_dim=0))
+    an, f = _gpu_factor(cae, csr, perm, bp, co, eps, "multicolour", precision=cae.FP32, coarse=0)
+    big = [l for l in range(len(fo.levels)) if 64 < int(f.sizes(l).max()) <= 128 and fo.levels[l].sigma]
+    assert big, "no level with blocks of 65..128 unknowns"
+    for l in big:
+        rg, lf = f.ranks(l), fo.levels[l]
+        for i in np.nonzero(rg != lf.r)[0]:
+            s = lf.sigma[i]
+            k = min(rg[i], lf.r[i])
+            assert abs(s[k] - fo.theta) <= 1e-5 * s[0], (l, i, rg[i], lf.r[i])
+    X = _probes(A.shape[0])
+    Mo = ce_multiply(fo, X)
+    M32 = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    err = np.linalg.norm(M32 - Mo) / np.linalg.norm(Mo)
+    print(f"fp32 (b <= 128) probe error vs oracle: {err:.3e}")
+    assert err <= 1e-5
+
+
 def test_indefinite_matrix_reports_not_spd():
     cae = _cae()
     A, csr, perm, bp, co = _setup((16, 16), (4, 4))
