@@ -241,12 +241,14 @@ def main():
                    "relres_max": float(np.max(rel)), "converged": ok, "levels": st["nlevels"],
                    "coarse_dim": st["coarse_dim"], "factor_bytes": st["factor_bytes"]},
     }
-    # roofline of the dominant kernel (the far-row compression, plain vector
-    # arithmetic), from HIP events around its launches on the factor's stream
-    peak = 78.6 if prec == cae.FP64 else 157.3
+    # roofline of the far-row compression, from HIP events around its launches
+    # on the factor's stream; its arithmetic is FP64 vector work for either
+    # factor precision (the FP32 factor's Gram matrix, Cholesky, Jacobi and
+    # reflectors run in FP64), so the peak is the FP64 vector rate
+    peak = 78.6
     kname = ("k_compress_wg<double> (TSQR, pivoted QR, one-sided Jacobi)" if prec == cae.FP64 else
-             "k_compress_rand<float> (learned-rank sketch) + k_compress_gram<float> fallback" if fkw else
-             "k_compress_gram<float> (FP64 Gram, pivoted Cholesky, one-sided Jacobi)")
+             "k_compress_rand<float> (learned-rank sketch) + k_compress_gram<float,64|128> fallback" if fkw else
+             "k_compress_gram<float,64> (FP64 Gram, pivoted Cholesky, one-sided Jacobi)")
     if comp["launches"]:
         per_launch_s = comp["ms"] / comp["launches"] / 1e3
         flops_per_launch = comp["flops"] / comp["launches"]

@@ -1513,10 +1513,37 @@ __device__ inline void zero_acc(T acc[4][4]) {
     for (int q = 0; q < 4; ++q) acc[p][q] = T(0);
 }
 
-// S[a][c] = view(rows row0 + a, columns c0 + c) for a < na, c < nc.
+// S[a][c] = view(rows row0 + a, columns c0 + c) for a < na, c < nc (both
+// <= 64): 16 slots per thread of the 64 x 64 window, the unit-stride index on
+// consecutive threads, loads issued in two groups of eight before their stores.
 template <typename T>
 __device__ inline void load_view_tile(T* S, const T* base, int trans, int bi, int bx, int row0, int na, int c0,
                                       int nc) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + NT * (8 * h + u);
+      const int a = trans ? (e & 63) : (e >> 6), c = trans ? (e >> 6) : (e & 63);
+      v[u] = (a < na && c < nc)
+                 ? (trans ? base[(int64_t)(c0 + c) * bi + row0 + a] : base[(int64_t)(row0 + a) * bx + c0 + c])
+                 : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + NT * (8 * h + u);
+      const int a = trans ? (e & 63) : (e >> 6), c = trans ? (e >> 6) : (e & 63);
+      if (a < na && c < nc) S[a * TLD + c] = v[u];
+    }
+  }
+}
+
+// The same tile with one element per thread and iteration (fewer live
+// registers: the Schur kernels keep their occupancy).
+template <typename T>
+__device__ inline void load_view_tile_lean(T* S, const T* base, int trans, int bi, int bx, int row0, int na, int c0,
+                                           int nc) {
   if (trans) {
     for (int e = threadIdx.x; e < na * nc; e += NT) {
       const int c = e / na, a = e % na;
@@ -1533,15 +1560,13 @@ __device__ inline void load_view_tile(T* S, const T* base, int trans, int bi, in
 template <typename T>
 __device__ inline void store_view_tile(const T* S, T* base, int trans, int bi, int bx, int row0, int na, int c0,
                                        int nc) {
-  if (trans) {
-    for (int e = threadIdx.x; e < na * nc; e += NT) {
-      const int c = e / na, a = e % na;
-      base[(int64_t)(c0 + c) * bi + row0 + a] = S[a * TLD + c];
-    }
-  } else {
-    for (int e = threadIdx.x; e < na * nc; e += NT) {
-      const int a = e / nc, c = e % nc;
-      base[(int64_t)(row0 + a) * bx + c0 + c] = S[a * TLD + c];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + NT * u;
+    const int a = trans ? (e & 63) : (e >> 6), c = trans ? (e >> 6) : (e & 63);
+    if (a < na && c < nc) {
+      if (trans) base[(int64_t)(c0 + c) * bi + row0 + a] = S[a * TLD + c];
+      else base[(int64_t)(row0 + a) * bx + c0 + c] = S[a * TLD + c];
     }
   }
 }
@@ -2805,12 +2830,12 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
   T* Us = reinterpret_cast<T*>(smem_raw);
   T* X = Us + 64 * TLD;
   const T* Ug = A.U + A.u_off[i];
-  for (int e = threadIdx.x; e < b * b; e += NT) Us[(e / b) * TLD + e % b] = Ug[e];
+  load_view_tile(Us, Ug, 0, b, b, 0, b, 0, b);
   typename AccT<T>::type acc[4][4];
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   if (item.view < 0) {
     T* D = A.arena + A.slot_off[i];
-    for (int e = threadIdx.x; e < b * b; e += NT) X[(e / b) * TLD + e % b] = D[e];
+    load_view_tile(X, D, 0, b, b, 0, b, 0, b);
     __syncthreads();
     zero_acc(acc);
     gemm_tn_4x4(X, Us, b, acc);       // Z = D U (D symmetric)
@@ -2886,10 +2911,7 @@ __global__ __launch_bounds__(NT) void k_trsm_t(LevelArgs<T> A, int32_t it0) {
   T* Lt = reinterpret_cast<T*>(smem_raw);   // Lt[k][j] = Li[j][k]
   T* X = Lt + 64 * TLD;
   const T* Lig = A.Li + A.u_off[i];
-  for (int e = threadIdx.x; e < n * n; e += NT) {
-    const int j = e / n, k = e % n;
-    Lt[k * TLD + j] = Lig[e];
-  }
+  load_view_tile(Lt, Lig, 1, n, n, 0, n, 0, n);   // Lt[k][j] = Li(j, k)
   T* base = A.arena + A.slot_off[v.slot];
   typename AccT<T>::type acc[4][4];
   for (int c0 = 0; c0 < lc; c0 += 64) {
@@ -2972,11 +2994,11 @@ __global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
   for (int a0 = 0; a0 < la; a0 += 64) {
     const int tan = min(64, la - a0);
     __syncthreads();
-    load_view_tile(Pa, pa, ta, b, ba, r, n, a0, tan);
+    load_view_tile_lean(Pa, pa, ta, b, ba, r, n, a0, tan);
     for (int c0 = 0; c0 < lc; c0 += 64) {
       const int tcn = min(64, lc - c0);
       if (c0 > 0) __syncthreads();
-      load_view_tile(Pc, pc, tcv, b, bc, r, n, c0, tcn);
+      load_view_tile_lean(Pc, pc, tcv, b, bc, r, n, c0, tcn);
       __syncthreads();
       zero_acc(acc);
       gemm_tn_4x4(Pa, Pc, n, acc);
@@ -3083,13 +3105,13 @@ __global__ __launch_bounds__(NT) void k_schur_bf16(LevelArgs<T> A, int32_t p0) {
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * 64; e += NT) Pa[(e >> 6) * TLD + (e & 63)] = T(0);
     __syncthreads();
-    load_view_tile(Pa, pa, ta, b, ba, r, n, a0, tan);
+    load_view_tile_lean(Pa, pa, ta, b, ba, r, n, a0, tan);
     for (int c0 = 0; c0 < lc; c0 += 64) {
       const int tcn = min(64, lc - c0);
       __syncthreads();
       for (int e = threadIdx.x; e < 64 * 64; e += NT) Pc[(e >> 6) * TLD + (e & 63)] = T(0);
       __syncthreads();
-      load_view_tile(Pc, pc, tcv, b, bc, r, n, c0, tcn);
+      load_view_tile_lean(Pc, pc, tcv, b, bc, r, n, c0, tcn);
       __syncthreads();
       f32x16_t acc;
 #pragma unroll
