@@ -89,12 +89,16 @@ typedef struct {
                               block of the next level; 1 = pairs of blocks along the Morton
                               curve (axis x, y, z in turn: J = 2, keeping J r ~ B, Section
                               2.6, when ranks are about half the block) */
-  int32_t pad;             /* 0 */
+  int32_t graphs;          /* 1 (default): the iterative solvers (cae_pcg_solve,
+                              cae_minres_solve) capture the preconditioner apply of a
+                              handle once into a HIP graph and replay it every iteration
+                              (the same kernels, launched as one graph); 0 = launch the
+                              kernels one by one */
 } cae_options_t;
 
 #define CAE_RECORD_WIDTH 17
 
-/* Fill *opt with the defaults (CE(eps), FP64, MULTICOLOUR, coarse 2048). */
+/* Fill *opt with the defaults (CE(eps), FP64, MULTICOLOUR, coarse 2048, graphs on). */
 void cae_default_options(cae_options_t* opt);
 
 typedef struct cae_analysis_s* cae_analysis_t;

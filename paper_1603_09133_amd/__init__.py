@@ -64,10 +64,11 @@ def graph_order(indptr, indices, B):
 
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
              coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None,
-             compensate=False):
+             compensate=False, graphs=True):
     o = _lib.Options()
     lib().cae_default_options(C.byref(o))
     o.compensate = 1 if compensate else 0
+    o.graphs = 1 if graphs else 0
     o.mlp_params = None if mlp_params is None else mlp_params.data_ptr()
     o.seed = int(seed)
     o.record = None if record is None else record.data_ptr()
@@ -169,10 +170,12 @@ class Factor:
 
     def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
                  max_levels=0, coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0,
-                 record=None, compensate=False):
+                 record=None, compensate=False, graphs=True):
         """``rank_mode=RANK_LEARNED`` needs ``mlp_params`` (float32 CUDA tensor of
         ``learned.param_count()`` entries); ``record`` (float32 CUDA tensor of
-        shape ``(rows, RECORD_WIDTH)``) receives the training records."""
+        shape ``(rows, RECORD_WIDTH)``) receives the training records;
+        ``graphs=False`` makes the iterative solvers launch the apply kernels
+        one by one instead of replaying a captured HIP graph."""
         import torch
         if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.float64):
             raise TypeError("vals must be a float64 CUDA tensor")
@@ -188,7 +191,7 @@ class Factor:
         self._opts = _options(order=analysis.order, precision=precision, rank_mode=rank_mode,
                               fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
                               stream=sptr, timing=timing, mlp_params=mlp_params, seed=seed, record=record,
-                              compensate=compensate)
+                              compensate=compensate, graphs=graphs)
         h = C.c_void_p()
         self._vals = vals.contiguous()
         check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),

@@ -211,6 +211,24 @@ struct cae_factor_s {
   DevBuf lcount;       // sketches accepted / rejected
   int64_t rec_rows = 0;
   int32_t sketch_acc = 0, sketch_rej = 0;
+  // the preconditioner apply of the iterative solvers, captured once per
+  // (right-hand sides, vectors) and replayed every iteration (MINRES
+  // alternates two input vectors, hence a few entries)
+  struct ApGraph {
+    hipGraphExec_t exec = nullptr;
+    int32_t nrhs = 0;
+    const double* r = nullptr;
+    double* z = nullptr;
+    int64_t ldr = 0, ldz = 0;
+  };
+  ApGraph ap[4];
+  int32_t ap_next = 0;
+  hipStream_t ap_stream = nullptr;   // non-blocking stream the captures run on
+  ~cae_factor_s() {
+    for (auto& g : ap)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (ap_stream) (void)hipStreamDestroy(ap_stream);
+  }
 };
 
 namespace {
@@ -599,7 +617,7 @@ void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, 
   const int64_t dim = h->coarse_dim;
   if (dim > 0) {
     cae::launch_coarse_apply(h->Ainv.as<double>(), dim, nrhs, h->ybuf[h->K].as<double>(), h->ctmp.as<double>(), s);
-    HIPCHK(hipMemcpyAsync(h->ybuf[h->K].p, h->ctmp.p, (size_t)dim * nrhs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    cae::launch_copy_cols(dim * nrhs, 1, h->ctmp.as<double>(), dim * nrhs, h->ybuf[h->K].as<double>(), dim * nrhs, s);
   }
   for (int l = h->K - 1; l >= 0; --l) {
     NumLevel& N = h->lev[l];
@@ -660,6 +678,53 @@ void do_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, doubl
     apply_precond<double>(h, nrhs, r, ldr, z, ldz);
 }
 
+// The apply of an iterative solver: with cae_options_t.graphs, its kernel
+// sequence is captured on a stream of its own the first time (work vectors
+// allocated before, so the capture holds kernel launches only) and the graph
+// is launched on the handle's stream from then on.
+void solver_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+  if (!h->opt.graphs) {
+    do_apply(h, nrhs, r, ldr, z, ldz);
+    return;
+  }
+  cae_factor_s::ApGraph* hit = nullptr;
+  for (auto& g : h->ap)
+    if (g.exec && g.nrhs == nrhs && g.r == r && g.z == z && g.ldr == ldr && g.ldz == ldz) hit = &g;
+  if (!hit) {
+    hit = &h->ap[h->ap_next];
+    h->ap_next = (h->ap_next + 1) % 4;
+    if (hit->exec) {
+      HIPCHK(hipGraphExecDestroy(hit->exec));
+      hit->exec = nullptr;
+    }
+    ensure_vectors(h, nrhs);
+    if (!h->ap_stream) HIPCHK(hipStreamCreateWithFlags(&h->ap_stream, hipStreamNonBlocking));
+    hipStream_t keep = h->stream;
+    h->stream = h->ap_stream;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(h->ap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      do_apply(h, nrhs, r, ldr, z, ldz);
+    } catch (...) {
+      (void)hipStreamEndCapture(h->ap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      h->stream = keep;
+      throw;
+    }
+    h->stream = keep;
+    HIPCHK(hipStreamEndCapture(h->ap_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&hit->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    hit->nrhs = nrhs;
+    hit->r = r;
+    hit->z = z;
+    hit->ldr = ldr;
+    hit->ldz = ldz;
+  }
+  HIPCHK(hipGraphLaunch(hit->exec, h->stream));
+}
+
 int check_handle(cae_factor_s* h) {
   if (!h) return fail(CAE_EINVAL, "null handle");
   return CAE_OK;
@@ -679,6 +744,7 @@ void cae_default_options(cae_options_t* opt) {
   opt->order = CAE_ORDER_MULTICOLOUR;
   opt->max_levels = 0;
   opt->coarse_max_dim = 2048;
+  opt->graphs = 1;
   opt->stream = nullptr;
 }
 
@@ -909,7 +975,7 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, do
     }
     HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (nact > 0) {
-      do_apply(h, nrhs, r, n, z, n);
+      solver_apply(h, nrhs, r, n, z, n);
       cae::launch_copy_cols(n, nrhs, z, n, p, n, s);
       cae::launch_dots(n, nrhs, r, n, z, n, part, rz, s);
     }
@@ -931,7 +997,7 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, do
       }
       if (nact == 0) break;
       HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
-      do_apply(h, nrhs, r, n, z, n);
+      solver_apply(h, nrhs, r, n, z, n);
       cae::launch_dots(n, nrhs, r, n, z, n, part, rz_new, s);
       cae::launch_pcg_p(n, nrhs, rz, rz_new, active, z, p, beta, s);
     }
@@ -992,7 +1058,7 @@ int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
     std::vector<double> bn(nrhs), hv(nrhs), hb(nrhs);
     cae::launch_dots(n, nrhs, b, ldb, b, ldb, part, F(cae::MR_BSQ), s);
     HIPCHK(hipMemcpyAsync(bn.data(), F(cae::MR_BSQ), nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    do_apply(h, nrhs, r1, n, y, n);
+    solver_apply(h, nrhs, r1, n, y, n);
     cae::launch_dots(n, nrhs, r1, n, y, n, part, F(cae::MR_BSQ), s);
     HIPCHK(hipMemcpyAsync(hv.data(), F(cae::MR_BSQ), nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1025,7 +1091,7 @@ int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
       r1 = r2;
       r2 = y;
       y = t;
-      do_apply(h, nrhs, r2, n, y, n);
+      solver_apply(h, nrhs, r2, n, y, n);
       cae::launch_dots(n, nrhs, r2, n, y, n, part, F(cae::MR_BSQ), s);
       cae::launch_mr_scalars(nrhs, active, st, s);
       // w_k from w_{k-2} (w2) and w_{k-1} (w); it overwrites w_{k-3} (w1)

@@ -197,6 +197,33 @@ def test_fp32_factor_with_blocks_above_64():
     assert err <= 1e-5
 
 
+def test_solver_apply_graph_replays_equal_eager_launches():
+    """The iterative solvers replay the captured apply graph: three PCG solves
+    on one handle (the later ones replaying the graph captured by the first,
+    with the solver's own eager kernels, host reads and synchronisations in
+    between) and a MINRES solve (two captured inputs alternating) give
+    bitwise the iterates of a handle that launches the apply kernels one by
+    one (the same kernels in the same order)."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((96, 80), (8, 8))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    vals = torch.from_numpy(csr[2]).cuda()
+    fg = cae.Factor(an, vals, 1e-4, precision=cae.FP32, coarse_max_dim=0)
+    fe = cae.Factor(an, vals, 1e-4, precision=cae.FP32, coarse_max_dim=0, graphs=False)
+    B1 = problems.rhs_normal(A.shape[0], 4, seed=5)
+    B2 = problems.rhs_normal(A.shape[0], 4, seed=6)
+    for B in (B1, B2, B1):
+        xg, itg, relg = fg.pcg(_to_gpu_cols(B), rtol=1e-10)
+        xe, ite, rele = fe.pcg(_to_gpu_cols(B), rtol=1e-10)
+        assert itg.tolist() == ite.tolist()
+        assert np.array_equal(_from_gpu_cols(xg), _from_gpu_cols(xe))
+        assert np.all(relg <= 1.0001e-10)
+    xg, itg, relg = fg.minres(_to_gpu_cols(B2), rtol=1e-8)
+    xe, ite, rele = fe.minres(_to_gpu_cols(B2), rtol=1e-8)
+    assert itg.tolist() == ite.tolist()
+    assert np.array_equal(_from_gpu_cols(xg), _from_gpu_cols(xe))
+
+
 def test_indefinite_matrix_reports_not_spd():
     cae = _cae()
     A, csr, perm, bp, co = _setup((16, 16), (4, 4))
