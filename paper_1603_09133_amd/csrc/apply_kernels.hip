@@ -16,6 +16,10 @@ namespace cae {
 
 constexpr int NT = 256;
 constexpr int RC = 16;   // right-hand sides per pass of a block kernel
+// row stride (doubles) of the LDS vector tiles of the lean kernels: 144 bytes
+// puts the four rows that the four threads of an output row read at once on
+// different LDS banks
+constexpr int RCP = RC + 2;
 
 namespace {
 size_t g_max_lds = 64 * 1024;
@@ -151,11 +155,55 @@ __device__ inline void axpy16(double s[RC], double p, const double* v) {
   for (int k = 0; k < RC; ++k) s[k] += p * v[k];
 }
 
-// Y[t][0..RC) = y[(row0 + t) * nrhs + k0 + k] (0 beyond kc), t < m.
+// Y[t][0..RC) = y[(row0 + t) * nrhs + k0 + k] (0 beyond kc), t < m, row
+// stride RCP.
 __device__ inline void load_vec_tile(double* Y, const double* y, int row0, int m, int nrhs, int k0, int kc) {
   for (int e = threadIdx.x; e < m * RC; e += NT) {
     const int t = e / RC, k = e % RC;
-    Y[e] = k < kc ? y[(int64_t)(row0 + t) * nrhs + k0 + k] : 0.0;
+    Y[t * RCP + k] = k < kc ? y[(int64_t)(row0 + t) * nrhs + k0 + k] : 0.0;
+  }
+}
+
+// Descriptors of the close views of a step, loaded by parallel threads into
+// LDS before the panel loop: read per panel, they formed a chain of
+// dependent scalar loads (view, then its block's size, rank and offsets)
+// that the counters showed as the kernels' main wait.
+constexpr int APV = 64;   // views staged (more are read directly)
+struct ViewDesc {
+  int64_t poff[APV];
+  int64_t yoff[APV];
+  int lc[APV];
+  int bx[APV];
+  int tr[APV];
+};
+template <typename T>
+__device__ inline void stage_views(const ApplyArgs<T>& A, const Step& st, ViewDesc* vd) {
+  for (int v = threadIdx.x; v < min(st.nclose, APV); v += NT) {
+    const View vw = A.views[st.view0 + v];
+    const int bx = A.bsz[vw.x];
+    vd->poff[v] = A.slot_off[vw.slot];
+    vd->yoff[v] = A.dof_off[vw.x] * A.nrhs;
+    vd->lc[v] = vw.proc ? A.rank[vw.x] : bx;
+    vd->bx[v] = bx;
+    vd->tr[v] = vw.trans;
+  }
+}
+template <typename T>
+__device__ inline void view_desc(const ApplyArgs<T>& A, const Step& st, const ViewDesc* vd, int v, int64_t& poff,
+                                 int64_t& yoff, int& lc, int& bx, int& tr) {
+  if (v < APV) {
+    poff = vd->poff[v];
+    yoff = vd->yoff[v];
+    lc = vd->lc[v];
+    bx = vd->bx[v];
+    tr = vd->tr[v];
+  } else {
+    const View vw = A.views[st.view0 + v];
+    bx = A.bsz[vw.x];
+    poff = A.slot_off[vw.slot];
+    yoff = A.dof_off[vw.x] * A.nrhs;
+    lc = vw.proc ? A.rank[vw.x] : bx;
+    tr = vw.trans;
   }
 }
 
@@ -184,9 +232,9 @@ __global__ __launch_bounds__(NT) void k_ap_rot2(ApplyArgs<T> A, double* y, int d
       for (int k = 0; k < RC; ++k) s[k] = 0.0;
       if (a < b) {
         if (dir == 0)
-          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)l * b + a], Ys + l * RC);
+          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)l * b + a], Ys + l * RCP);
         else
-          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)a * b + l], Ys + l * RC);
+          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)a * b + l], Ys + l * RCP);
       }
       quad_sum16(s);
       if (a < b)
@@ -210,11 +258,13 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
   const int nrhs = A.nrhs;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* yn = reinterpret_cast<double*>(smem_raw);   // n x RC
-  double* tn = yn + (size_t)nmax * RC;                 // n x RC
+  double* tn = yn + (size_t)nmax * RCP;                // n x RC, row stride RCP
+  ViewDesc* vd = reinterpret_cast<ViewDesc*>(tn + (size_t)nmax * RCP);
   const T* Li = A.Li + A.u_off[i];
   const T* D = A.arena + A.slot_off[i];
   double* yi = y + A.dof_off[i] * nrhs;
   const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
+  stage_views(A, st, vd);
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int kc = min(RC, nrhs - k0);
     __syncthreads();
@@ -226,12 +276,12 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
 #pragma unroll
       for (int k = 0; k < RC; ++k) s[k] = 0.0;
       if (row < n)
-        for (int c = q; c <= row; c += 4) axpy16(s, (double)Li[(int64_t)row * n + c], yn + c * RC);
+        for (int c = q; c <= row; c += 4) axpy16(s, (double)Li[(int64_t)row * n + c], yn + c * RCP);
       quad_sum16(s);
       if (row < n) {
 #pragma unroll
         for (int k = 4 * q; k < 4 * q + 4; ++k) {
-          tn[row * RC + k] = s[k];
+          tn[row * RCP + k] = s[k];
           if (k < kc) yi[(int64_t)(r + row) * nrhs + k0 + k] = s[k];
         }
       }
@@ -248,12 +298,10 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
         lc = r;
         yx = yi;
       } else {
-        const View vw = A.views[st.view0 + v];
-        bx = A.bsz[vw.x];
-        lc = vw.proc ? A.rank[vw.x] : bx;
-        P = A.arena + A.slot_off[vw.slot];
-        trans = vw.trans;
-        yx = y + A.dof_off[vw.x] * nrhs;
+        int64_t poff, yoff;
+        view_desc(A, st, vd, v, poff, yoff, lc, bx, trans);
+        P = A.arena + poff;
+        yx = y + yoff;
       }
       for (int g0 = 0; g0 < lc; g0 += 64) {
         const int g = g0 + rl;
@@ -262,9 +310,9 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
         for (int k = 0; k < RC; ++k) s[k] = 0.0;
         if (g < lc) {
           if (trans)
-            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)g * b + r + t], tn + t * RC);
+            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)g * b + r + t], tn + t * RCP);
           else
-            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g], tn + t * RC);
+            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g], tn + t * RCP);
         }
         quad_sum16(s);
         if (g < lc)
@@ -289,11 +337,13 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
   const int nrhs = A.nrhs;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* tn = reinterpret_cast<double*>(smem_raw);   // n x RC
-  double* zt = tn + (size_t)nmax * RC;                 // 64 x RC
+  double* zt = tn + (size_t)nmax * RCP;                // 64 x RC, row stride RCP
+  ViewDesc* vd = reinterpret_cast<ViewDesc*>(zt + (size_t)64 * RCP);
   const T* Li = A.Li + A.u_off[i];
   const T* D = A.arena + A.slot_off[i];
   double* yi = y + A.dof_off[i] * nrhs;
   const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
+  stage_views(A, st, vd);
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int kc = min(RC, nrhs - k0);
     __syncthreads();
@@ -309,12 +359,10 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
         lc = r;
         zx = yi;
       } else {
-        const View vw = A.views[st.view0 + v];
-        bx = A.bsz[vw.x];
-        lc = vw.proc ? A.rank[vw.x] : bx;
-        P = A.arena + A.slot_off[vw.slot];
-        trans = vw.trans;
-        zx = y + A.dof_off[vw.x] * nrhs;
+        int64_t poff, yoff;
+        view_desc(A, st, vd, v, poff, yoff, lc, bx, trans);
+        P = A.arena + poff;
+        zx = y + yoff;
       }
       for (int g0 = 0; g0 < lc; g0 += 64) {
         const int gc = min(64, lc - g0);
@@ -328,14 +376,14 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
           for (int k = 0; k < RC; ++k) s[k] = 0.0;
           if (t < n) {
             if (trans)
-              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(g0 + g) * b + r + t], zt + g * RC);
+              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(g0 + g) * b + r + t], zt + g * RCP);
             else
-              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g0 + g], zt + g * RC);
+              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g0 + g], zt + g * RCP);
           }
           quad_sum16(s);
           if (t < n)
 #pragma unroll
-            for (int k = 4 * q; k < 4 * q + 4; ++k) tn[t * RC + k] -= s[k];
+            for (int k = 4 * q; k < 4 * q + 4; ++k) tn[t * RCP + k] -= s[k];
         }
       }
     }
@@ -346,7 +394,7 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
 #pragma unroll
       for (int k = 0; k < RC; ++k) s[k] = 0.0;
       if (c < n)
-        for (int row = c + q; row < n; row += 4) axpy16(s, (double)Li[(int64_t)row * n + c], tn + row * RC);
+        for (int row = c + q; row < n; row += 4) axpy16(s, (double)Li[(int64_t)row * n + c], tn + row * RCP);
       quad_sum16(s);
       if (c < n)
 #pragma unroll
@@ -665,12 +713,12 @@ static unsigned grid1(int64_t work) {
 template <typename T>
 void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir, int bmax, hipStream_t stream) {
   if (nsteps <= 0) return;
-  hipLaunchKernelGGL(k_ap_rot2<T>, dim3(nsteps), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A, y, dir);
+  hipLaunchKernelGGL(k_ap_rot2<T>, dim3(nsteps), dim3(NT), (size_t)bmax * RCP * sizeof(double), stream, A, y, dir);
 }
 template <typename T>
 void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
   if (s1 <= s0) return;
-  const size_t lds = (size_t)2 * bmax * RC * sizeof(double);
+  const size_t lds = (size_t)2 * bmax * RCP * sizeof(double) + sizeof(ViewDesc);
   if (lds <= max_lds_bytes())
     hipLaunchKernelGGL(k_ap_fwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
   else
@@ -680,7 +728,7 @@ void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int
 template <typename T>
 void launch_ap_bwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
   if (s1 <= s0) return;
-  const size_t lds = (size_t)(bmax + 64) * RC * sizeof(double);
+  const size_t lds = (size_t)(bmax + 64) * RCP * sizeof(double) + sizeof(ViewDesc);
   if (lds <= max_lds_bytes())
     hipLaunchKernelGGL(k_ap_bwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
   else
