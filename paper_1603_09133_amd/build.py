@@ -2,7 +2,8 @@
 
 Every source is compiled to an object in parallel under ``_build/`` and
 linked into ``paper_1603_09133_amd/libcae.so``.  Packed FP32 instructions
-are disabled on the device side (``-packed-fp32-ops``).
+are disabled on the device side (``-packed-fp32-ops``), and matrix-core
+instructions take their accumulators in VGPRs (``-amdgpu-mfma-vgpr-form``).
 """
 from __future__ import annotations
 
@@ -27,6 +28,9 @@ def _hipcc():
 def _flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # matrix-core results in ordinary VGPRs: loop-carried accumulators
+            # are not copied between register files on every iteration
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-Wno-unused-command-line-argument",
             "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
 

@@ -1454,6 +1454,7 @@ __global__ __launch_bounds__(NT) void k_schur(LevelArgs<T> A, int32_t p0, T* gsc
 // addresses for either storage orientation of a view.
 // ---------------------------------------------------------------------------
 constexpr int TLD = 68;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <typename TI, typename TA>
 __device__ inline void gemm_tn_4x4(const TI* A, const TI* B, int K, TA acc[4][4]) {
@@ -1554,6 +1555,42 @@ __device__ inline void load_view_tile_lean(T* S, const T* base, int trans, int b
       const int a = e / nc, c = e % nc;
       S[a * TLD + c] = base[(int64_t)(row0 + a) * bx + c0 + c];
     }
+  }
+}
+
+// Two view tiles (as load_view_tile_lean, operand Q into S + 64 TLD only when
+// nq > 0) with their elements enumerated densely and, per round of 16 per
+// thread, every load issued before the first LDS store, with 32-bit offsets
+// into the views: many loads in flight for few registers.
+struct TileSrc {
+  int trans, bi, bx, c0, nc;
+};
+template <typename T>
+__device__ inline void load_tile_pair(T* S, const T* pb, TileSrc P, const T* qb, TileSrc Q, int row0, int na) {
+  const int tp = P.nc > 0 ? na * P.nc : 0;
+  const int tot = tp + (Q.nc > 0 ? na * Q.nc : 0);
+  for (int e0 = 0; e0 < tot; e0 += 16 * NT) {
+    T v[16];
+    int so[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      int e = e0 + threadIdx.x + NT * u;
+      so[u] = -1;
+      if (e < tot) {
+        const bool q = e >= tp;
+        if (q) e -= tp;
+        const TileSrc& V = q ? Q : P;
+        const T* base = q ? qb : pb;
+        const int ld = V.trans ? na : V.nc;
+        const int x = e / ld, m = e - x * ld;
+        const int a = V.trans ? m : x, c = V.trans ? x : m;
+        v[u] = V.trans ? base[(V.c0 + c) * V.bi + row0 + a] : base[(row0 + a) * V.bx + V.c0 + c];
+        so[u] = (q ? 64 * TLD : 0) + a * TLD + c;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (so[u] >= 0) S[so[u]] = v[u];
   }
 }
 
@@ -2965,7 +3002,7 @@ __global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
   }
   if (la == 0 || lc == 0) return;
   T* tbase;
-  int64_t ts_a, ts_c;
+  int ts_a, ts_c;   // target strides (a slot of at most 64 x bmax entries)
   if (pr.a == 0) {
     if (pr.c == 0) {
       tbase = D;
@@ -2989,37 +3026,63 @@ __global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Pa = reinterpret_cast<T*>(smem_raw);
   T* Pc = Pa + 64 * TLD;
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  typename AccT<T>::type acc[4][4];
+  // FP64 matrix cores: wavefront w owns rows 16w .. 16w + 15 of the 64 x 64
+  // target tile, as four 16 x 16 tiles; v_mfma_f64_16x16x4f64 operand
+  // lanes: A (row l % 16, k l / 16), B (k l / 16, column l % 16); result
+  // register j of lane l holds (row 4 j + l / 16, column l % 16)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  // rows n .. n4 - 1 of both tiles stay zero: the k loop runs in whole steps
+  // of four without predicates (the loads only write rows below n)
+  const int n4 = (n + 3) & ~3;
+  for (int e = threadIdx.x; e < (n4 - n) * 64; e += NT) {
+    Pa[(n + (e >> 6)) * TLD + (e & 63)] = T(0);
+    Pc[(n + (e >> 6)) * TLD + (e & 63)] = T(0);
+  }
+  const T* fa = Pa + fk * TLD + 16 * wv + fr;
+  const T* fc = Pc + fk * TLD + fr;
   for (int a0 = 0; a0 < la; a0 += 64) {
     const int tan = min(64, la - a0);
-    __syncthreads();
-    load_view_tile_lean(Pa, pa, ta, b, ba, r, n, a0, tan);
     for (int c0 = 0; c0 < lc; c0 += 64) {
       const int tcn = min(64, lc - c0);
-      if (c0 > 0) __syncthreads();
-      load_view_tile_lean(Pc, pc, tcv, b, bc, r, n, c0, tcn);
       __syncthreads();
-      zero_acc(acc);
-      gemm_tn_4x4(Pa, Pc, n, acc);
+      // both operand tiles in one round of loads, then the target entries
+      // this lane updates, in flight while the products run
+      // the Pa tile is loaded with the first Pc tile of its row of targets
+      load_tile_pair(Pa, pa, TileSrc{ta, b, ba, a0, c0 == 0 ? tan : 0}, pc, TileSrc{tcv, b, bc, c0, tcn}, r, n);
+      T tv[4][4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int al = 4 * ty + p;
-        if (al < tan)
+      for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int gm = 4 * tx + q;
-            if (gm < tcn) {
-              T* tp = tbase + (int64_t)(a0 + al) * ts_a + (int64_t)(c0 + gm) * ts_c;
-              *tp = (T)((double)*tp - acc[p][q]);
-            }
-          }
+        for (int j = 0; j < 4; ++j) {
+          const int al = 16 * wv + 4 * j + fk, gm = 16 * tj + fr;
+          tv[tj][j] = (al < tan && gm < tcn) ? tbase[(a0 + al) * ts_a + (c0 + gm) * ts_c] : T(0);
+        }
+      __syncthreads();
+      dbl4 dacc[4];
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) dacc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int k0 = 0; k0 < n4; k0 += 4) {
+        const double av = (double)fa[k0 * TLD];
+        double bv[4];
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) bv[tj] = (double)fc[k0 * TLD + 16 * tj];
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) dacc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], dacc[tj], 0, 0, 0);
       }
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int al = 16 * wv + 4 * j + fk, gm = 16 * tj + fr;
+          if (al < tan && gm < tcn)
+            tbase[(a0 + al) * ts_a + (c0 + gm) * ts_c] = (T)((double)tv[tj][j] - dacc[tj][j]);
+        }
     }
   }
 }
 
-// ---------------------------------------------------------------------------
 // Schur update with BF16 inputs and FP32 accumulation on the matrix cores
 // (FP32 factor, reduced-precision mode): the 64 x 64 target tile is four
 // 32 x 32 MFMA tiles, one per wavefront, v_mfma_f32_32x32x8bf16_1k over the
@@ -3215,111 +3278,214 @@ __global__ void k_coarse_assemble(const int32_t* slot_p, const int32_t* slot_q, 
 // ---------------------------------------------------------------------------
 constexpr int GJ = 64;
 
-__global__ __launch_bounds__(NT) void k_gj_pivot(double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv,
-                                                 int32_t* err) {
+constexpr int GJP = 4;                            // pivot inverse: a GJP x GJP tile per thread
+constexpr int GJT = (64 / GJP) * (64 / GJP);      // its threads
+
+__global__ __launch_bounds__(GJT) void k_gj_pivot(double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv,
+                                                  int32_t* err) {
+  // Gauss-Jordan elimination without pivoting of the kb x kb pivot block
+  // (read from its lower triangle), in place: after step k the leading k + 1
+  // rows and columns hold the inverse of the leading block, the rest its Schur
+  // complement.  Each thread keeps a GJP x GJP tile of the 64 x 64 array in
+  // registers (identity beyond kb); row k and column k reach the other
+  // threads through LDS, two alternating buffers, one barrier per step, and
+  // the step itself is straight-line code (the steps unrolled by GJP, so the
+  // row and column a thread publishes are fixed registers).  The pivots are
+  // the leading entries of the successive Schur complements: all positive
+  // exactly when the block is positive definite.
+  constexpr int TS = 64 / GJP;
+  __shared__ double Rb[2][64], Cb[2][64];
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2* W = reinterpret_cast<double2*>(smem_raw);   // (L(l, m), L^{-1}(m, l))
-  __shared__ int bad;
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  for (int e = tid; e < kb * 64; e += NT) {
-    const int m = e >> 6, l = e & 63;
-    W[e] = make_double2(l < kb ? Ad[(k0 + l) * dim + k0 + m] : 0.0, l == m ? 1.0 : 0.0);   // lower triangle
-  }
-  __syncthreads();
-  if (tid < WV) {
-    double mp;
-    const bool ok = chol_fwd_wave(W, kb, mp, [](int, double, double) {});
-    if (tid == 0) bad = ok ? 0 : 1;
-  }
-  __syncthreads();
-  // Pinv = L^{-T} L^{-1}
-  double acc[4][4];
-  zero_acc(acc);
-  for (int k = 0; k < kb; ++k) {
-    double av[4], bv[4];
+  double* Sy = reinterpret_cast<double*>(smem_raw);   // 64 x TLD, the result before symmetrisation
+  const int tid = threadIdx.x, ty = tid / TS, tx = tid % TS;
+  double a[GJP][GJP];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      av[q] = W[k * 64 + 4 * ty + q].y;
-      bv[q] = W[k * 64 + 4 * tx + q].y;
+  for (int p = 0; p < GJP; ++p)
+#pragma unroll
+    for (int q = 0; q < GJP; ++q) {
+      const int i = GJP * ty + p, j = GJP * tx + q;
+      a[p][q] = (i < kb && j < kb) ? Ad[(k0 + max(i, j)) * dim + k0 + min(i, j)] : (i == j ? 1.0 : 0.0);
     }
+  bool bad = false;
+  for (int kg = 0; kg < kb; kg += GJP)
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int kq = 0; kq < GJP; ++kq) {
+      const int k = kg + kq, h = kq & 1;
+      if (k >= kb) break;
+      if (ty == kg / GJP)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] += av[p] * bv[q];
-  }
+        for (int q = 0; q < GJP; ++q) Rb[h][GJP * tx + q] = a[kq][q];
+      if (tx == kg / GJP)
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < GJP; ++p) Cb[h][GJP * ty + p] = a[p][kq];
+      __syncthreads();
+      const double piv = Rb[h][k];
+      bad = bad || !(piv > 0.0);
+      // 1 / piv: the hardware estimate and two Newton steps
+      const double pv = piv > 0.0 ? piv : 1.0;
+      double ip = __builtin_amdgcn_rcp(pv);
+      ip = fma(ip, fma(-pv, ip, 1.0), ip);
+      ip = fma(ip, fma(-pv, ip, 1.0), ip);
+      double rk[GJP], ck[GJP];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int a = 4 * ty + p, c = 4 * tx + q;
-      if (a < kb && c < kb) Pinv[a * GJ + c] = acc[p][q];
+      for (int q = 0; q < GJP; ++q) rk[q] = Rb[h][GJP * tx + q] * ip;
+#pragma unroll
+      for (int p = 0; p < GJP; ++p) ck[p] = Cb[h][GJP * ty + p];
+#pragma unroll
+      for (int p = 0; p < GJP; ++p) {
+        const bool ri = GJP * ty + p == k;
+        const double nc = -ck[p] * ip;
+#pragma unroll
+        for (int q = 0; q < GJP; ++q) {
+          const bool cj = GJP * tx + q == k;
+          const double g = fma(-ck[p], rk[q], a[p][q]);
+          const double rv = cj ? ip : rk[q];
+          const double ov = cj ? nc : g;
+          a[p][q] = ri ? rv : ov;
+        }
+      }
+    }
+  // the inverse is symmetric: store the mean of the two triangles
+#pragma unroll
+  for (int p = 0; p < GJP; ++p)
+#pragma unroll
+    for (int q = 0; q < GJP; ++q) Sy[(GJP * ty + p) * TLD + GJP * tx + q] = a[p][q];
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < GJP; ++p)
+#pragma unroll
+    for (int q = 0; q < GJP; ++q) {
+      const int i = GJP * ty + p, j = GJP * tx + q;
+      if (i < kb && j < kb) Pinv[i * GJ + j] = 0.5 * (a[p][q] + Sy[j * TLD + i]);
     }
   if (tid == 0 && bad) {
     if (atomicCAS(err, 0, 1) == 0) err[1] = -1;
   }
 }
 
-// W = Pinv * A[k-block, :] and R0 = A[k-block, :]  (kb x dim each, ld dim)
+// W = Pinv * A[k-block, :] and R0 = A[k-block, :]  (kb x dim each, ld dim);
+// the product on the FP64 matrix cores as in k_gj_update (Pinv symmetric).
+__device__ inline void stage_panel64(double* S, const double* src, int64_t ld, int64_t c0, int kb, int kb4, int nc);
 __global__ __launch_bounds__(NT) void k_gj_rows(const double* Ad, int64_t dim, int64_t k0, int kb,
                                                 const double* Pinv, double* W, double* R0) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* P = reinterpret_cast<double*>(smem_raw);
   double* X = P + 64 * TLD;
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const int64_t c0 = (int64_t)blockIdx.x * GJ;
   const int tc = (int)min<int64_t>(GJ, dim - c0);
-  for (int e = tid; e < kb * kb; e += NT) P[(e / kb) * TLD + e % kb] = Pinv[(e / kb) * GJ + e % kb];
-  for (int e = tid; e < kb * tc; e += NT) {
-    const int t = e / tc, c = e % tc;
-    const double v = Ad[(k0 + t) * dim + c0 + c];
-    X[t * TLD + c] = v;
-    R0[t * dim + c0 + c] = v;
-  }
+  const int kb4 = (kb + 3) & ~3;
+  stage_panel64(P, Pinv, GJ, 0, kb, kb4, kb);
+  stage_panel64(X, Ad + k0 * dim, dim, c0, kb, kb4, tc);
   __syncthreads();
-  double acc[4][4];
-  zero_acc(acc);
-  gemm_tn_4x4(P, X, kb, acc);   // Pinv is symmetric
+  for (int e = threadIdx.x; e < kb * 64; e += NT) {
+    const int t = e >> 6, c = e & 63;
+    if (c < tc) R0[t * dim + c0 + c] = X[t * TLD + c];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  dbl4 acc[4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const double* fa = P + fk * TLD + 16 * wv + fr;
+  const double* fb = X + fk * TLD + fr;
+#pragma unroll 2
+  for (int t0 = 0; t0 < kb4; t0 += 4) {
+    const double av = fa[t0 * TLD];
+    double bv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int a = 4 * ty + p, c = 4 * tx + q;
-      if (a < kb && c < tc) W[a * dim + c0 + c] = acc[p][q];
+    for (int c = 0; c < 4; ++c) bv[c] = fb[t0 * TLD + 16 * c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int ra = 16 * wv + 4 * j + fk, cc = 16 * c + fr;
+      if (ra < kb && cc < tc) W[ra * dim + c0 + cc] = acc[c][j];
     }
 }
 
+// Rows t < kb4 of the 64-column window [c0, c0 + nc) of the kb x ? row panel
+// src (leading dimension ld) into S (row stride TLD), zero in rows kb .. kb4 - 1
+// and in the columns beyond nc; eight loads in flight per thread.
+__device__ inline void stage_panel64(double* S, const double* src, int64_t ld, int64_t c0, int kb, int kb4, int nc) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + NT * (8 * h + u), t = e >> 6, c = e & 63;
+      v[u] = (t < kb && c < nc) ? src[t * ld + c0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + NT * (8 * h + u), t = e >> 6;
+      if (t < kb4) S[t * TLD + (e & 63)] = v[u];
+    }
+  }
+}
+
+// A <- A - R0^T W on the 64 x 64 tile (i0, j0), the pivot rows and columns
+// replaced by the corresponding rows of W and -Pinv (the Gauss-Jordan step).
+// The product on the FP64 matrix cores: wavefront w owns tile rows
+// 16w .. 16w + 15 as four 16 x 16 tiles of v_mfma_f64_16x16x4f64 (operand
+// lanes: A (row l % 16, k l / 16), B (k l / 16, column l % 16); result
+// register j of lane l: (row 4 j + l / 16, column l % 16)).
 __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64_t k0, int kb,
                                                   const double* Pinv, const double* W, const double* R0) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Ri = reinterpret_cast<double*>(smem_raw);
   double* Wj = Ri + 64 * TLD;
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const int64_t i0 = (int64_t)blockIdx.y * GJ, j0 = (int64_t)blockIdx.x * GJ;
   const int ti = (int)min<int64_t>(GJ, dim - i0), tj = (int)min<int64_t>(GJ, dim - j0);
-  for (int e = tid; e < kb * ti; e += NT) Ri[(e / ti) * TLD + e % ti] = R0[(e / ti) * dim + i0 + e % ti];
-  for (int e = tid; e < kb * tj; e += NT) Wj[(e / tj) * TLD + e % tj] = W[(e / tj) * dim + j0 + e % tj];
+  const int kb4 = (kb + 3) & ~3;
+  stage_panel64(Ri, R0, dim, i0, kb, kb4, ti);
+  stage_panel64(Wj, W, dim, j0, kb, kb4, tj);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  // the tile entries this lane rewrites, in flight while the products run
+  double old[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int li = 16 * wv + 4 * j + fk, lj = 16 * c + fr;
+      old[c][j] = (li < ti && lj < tj) ? Ad[(i0 + li) * dim + j0 + lj] : 0.0;
+    }
   __syncthreads();
-  double acc[4][4];
-  zero_acc(acc);
-  gemm_tn_4x4(Ri, Wj, kb, acc);
+  dbl4 acc[4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const double* fa = Ri + fk * TLD + 16 * wv + fr;
+  const double* fb = Wj + fk * TLD + fr;
+#pragma unroll 2
+  for (int t0 = 0; t0 < kb4; t0 += 4) {
+    const double av = fa[t0 * TLD];
+    double bv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int li = 4 * ty + p, lj = 4 * tx + q;
+    for (int c = 0; c < 4; ++c) bv[c] = fb[t0 * TLD + 16 * c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int li = 16 * wv + 4 * j + fk, lj = 16 * c + fr;
       if (li >= ti || lj >= tj) continue;
-      const int64_t i = i0 + li, j = j0 + lj;
-      const bool ik = i >= k0 && i < k0 + kb, jk = j >= k0 && j < k0 + kb;
+      const int64_t i = i0 + li, jj = j0 + lj;
+      const bool ik = i >= k0 && i < k0 + kb, jk = jj >= k0 && jj < k0 + kb;
       double v;
       if (ik && jk)
-        v = -Pinv[(i - k0) * GJ + (j - k0)];
+        v = -Pinv[(i - k0) * GJ + (jj - k0)];
       else if (ik)
-        v = W[(i - k0) * dim + j];
+        v = W[(i - k0) * dim + jj];
       else if (jk)
-        v = W[(j - k0) * dim + i];
+        v = W[(jj - k0) * dim + i];
       else
-        v = Ad[i * dim + j] - acc[p][q];
-      Ad[i * dim + j] = v;
+        v = old[c][j] - acc[c][j];
+      Ad[i * dim + jj] = v;
     }
 }
 
@@ -3504,7 +3670,7 @@ void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double*
   for (int64_t k0 = 0; k0 < dim; k0 += GJ) {
     const int kb = (int)std::min<int64_t>(GJ, dim - k0);
     const size_t lds = (size_t)2 * 64 * TLD * sizeof(double);
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), lds, stream, Ad, dim, k0, kb, Pinv, err);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(GJT), lds, stream, Ad, dim, k0, kb, Pinv, err);
     hipLaunchKernelGGL(k_gj_rows, dim3(nt), dim3(NT), lds, stream, (const double*)Ad, dim, k0, kb,
                        (const double*)Pinv, W, R0);
     hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(NT), lds, stream, Ad, dim, k0, kb, (const double*)Pinv,
