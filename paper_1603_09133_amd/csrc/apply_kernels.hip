@@ -142,25 +142,94 @@ __global__ __launch_bounds__(NT) void k_ap_bwd_generic(ApplyArgs<T> A, int32_t s
 // tiles live in LDS, so a step needs 16 KB of LDS at b = 64 and many steps
 // run on one compute unit at once.
 // ---------------------------------------------------------------------------
-__device__ inline void quad_sum16(double s[RC]) {
-#pragma unroll
-  for (int k = 0; k < RC; ++k) {
-    s[k] += __shfl_xor(s[k], 1, 64);
-    s[k] += __shfl_xor(s[k], 2, 64);
-  }
-}
-
 __device__ inline void axpy16(double s[RC], double p, const double* v) {
 #pragma unroll
   for (int k = 0; k < RC; ++k) s[k] += p * v[k];
 }
 
+// s += sum over t = t0, t0 + 4, ... < tend of P[t * stride] V[t * RCP]: the
+// panel entries loaded eight at a time (all in flight before the first is
+// used), the LDS rows of V read only for t < tend.
+template <typename T>
+__device__ inline void axpy_run(double s[RC], const T* P, int64_t stride, int t0, int tend, const double* V) {
+  for (int t = t0; t < tend; t += 32) {
+    T pv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int tu = t + 4 * u;
+      pv[u] = tu < tend ? P[(int64_t)tu * stride] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int tu = t + 4 * u;
+      if (tu < tend) axpy16(s, (double)pv[u], V + tu * RCP);
+    }
+  }
+}
+
+// Sum of the RC partial sums over the four lanes of a row (lanes 4 rl + q),
+// reduce-scattered: lane q returns in o[0..3] the totals of columns
+// 4 q .. 4 q + 3 (12 exchanges instead of a 32-exchange butterfly).
+__device__ inline void quad_rs16(const double s[RC], int q, double o[4]) {
+  const bool hi2 = (q & 2) != 0, hi1 = (q & 1) != 0;
+  double h[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double send = hi2 ? s[j] : s[8 + j];
+    h[j] = (hi2 ? s[8 + j] : s[j]) + __shfl_xor(send, 2, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double send = hi1 ? h[j] : h[4 + j];
+    o[j] = (hi1 ? h[4 + j] : h[j]) + __shfl_xor(send, 1, 64);
+  }
+}
+
+// y[4 q + j] (op)= o[j] for the columns 4 q + j < kc of one RHS row (y at
+// column k0 of that row): two 16-byte accesses when the row chunk is whole.
+__device__ inline void store_row4(double* y, int q, int kc, const double o[4]) {
+  double* p = y + 4 * q;
+  if (4 * q + 4 <= kc) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(o[0], o[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(o[2], o[3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * q + j < kc) p[j] = o[j];
+  }
+}
+__device__ inline void sub_row4(double* y, int q, int kc, const double o[4]) {
+  double* p = y + 4 * q;
+  if (4 * q + 4 <= kc) {
+    double2 a = reinterpret_cast<double2*>(p)[0], c = reinterpret_cast<double2*>(p)[1];
+    a.x -= o[0];
+    a.y -= o[1];
+    c.x -= o[2];
+    c.y -= o[3];
+    reinterpret_cast<double2*>(p)[0] = a;
+    reinterpret_cast<double2*>(p)[1] = c;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * q + j < kc) p[j] -= o[j];
+  }
+}
+
 // Y[t][0..RC) = y[(row0 + t) * nrhs + k0 + k] (0 beyond kc), t < m, row
-// stride RCP.
+// stride RCP; eight loads in flight per thread.
 __device__ inline void load_vec_tile(double* Y, const double* y, int row0, int m, int nrhs, int k0, int kc) {
-  for (int e = threadIdx.x; e < m * RC; e += NT) {
-    const int t = e / RC, k = e % RC;
-    Y[t * RCP + k] = k < kc ? y[(int64_t)(row0 + t) * nrhs + k0 + k] : 0.0;
+  for (int e0 = 0; e0 < m * RC; e0 += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + threadIdx.x + NT * u, t = e / RC, k = e % RC;
+      v[u] = (e < m * RC && k < kc) ? y[(int64_t)(row0 + t) * nrhs + k0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + threadIdx.x + NT * u;
+      if (e < m * RC) Y[(e / RC) * RCP + e % RC] = v[u];
+    }
   }
 }
 
@@ -232,23 +301,22 @@ __global__ __launch_bounds__(NT) void k_ap_rot2(ApplyArgs<T> A, double* y, int d
       for (int k = 0; k < RC; ++k) s[k] = 0.0;
       if (a < b) {
         if (dir == 0)
-          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)l * b + a], Ys + l * RCP);
+          axpy_run(s, U + a, b, q, b, Ys);
         else
-          for (int l = q; l < b; l += 4) axpy16(s, (double)U[(int64_t)a * b + l], Ys + l * RCP);
+          axpy_run(s, U + (int64_t)a * b, 1, q, b, Ys);
       }
-      quad_sum16(s);
-      if (a < b)
-#pragma unroll
-        for (int k = 4 * q; k < 4 * q + 4; ++k)
-          if (k < kc) yi[(int64_t)a * nrhs + k0 + k] = s[k];
+      double o[4];
+      quad_rs16(s, q, o);
+      if (a < b) store_row4(yi + (int64_t)a * nrhs + k0, q, kc, o);
     }
   }
 }
 
 // Forward block solve of one step: t = L_nn^{-1} y_i[n], y_i[n] = t, and
-// y_c -= L(c, n) t for the basis of i and every close block c.
+// y_c -= L(c, n) t for the basis of i and (views != 0) every close block c;
+// with views = 0 the close blocks are left to k_ap_fview.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax) {
+__global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax, int views) {
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -275,19 +343,18 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
       double s[RC];
 #pragma unroll
       for (int k = 0; k < RC; ++k) s[k] = 0.0;
-      if (row < n)
-        for (int c = q; c <= row; c += 4) axpy16(s, (double)Li[(int64_t)row * n + c], yn + c * RCP);
-      quad_sum16(s);
+      if (row < n) axpy_run(s, Li + (int64_t)row * n, 1, q, row + 1, yn);
+      double o[4];
+      quad_rs16(s, q, o);
       if (row < n) {
-#pragma unroll
-        for (int k = 4 * q; k < 4 * q + 4; ++k) {
-          tn[row * RCP + k] = s[k];
-          if (k < kc) yi[(int64_t)(r + row) * nrhs + k0 + k] = s[k];
-        }
+        *reinterpret_cast<double2*>(tn + row * RCP + 4 * q) = make_double2(o[0], o[1]);
+        *reinterpret_cast<double2*>(tn + row * RCP + 4 * q + 2) = make_double2(o[2], o[3]);
+        store_row4(yi + (int64_t)(r + row) * nrhs + k0, q, kc, o);
       }
     }
     __syncthreads();
-    for (int v = -1; v < st.nclose; ++v) {
+    const int nv = views ? st.nclose : 0;
+    for (int v = -1; v < nv; ++v) {
       const T* P;
       int trans, bx, lc;
       double* yx;
@@ -310,24 +377,25 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
         for (int k = 0; k < RC; ++k) s[k] = 0.0;
         if (g < lc) {
           if (trans)
-            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)g * b + r + t], tn + t * RCP);
+            axpy_run(s, P + (int64_t)g * b + r, 1, q, n, tn);
           else
-            for (int t = q; t < n; t += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g], tn + t * RCP);
+            axpy_run(s, P + (int64_t)r * bx + g, bx, q, n, tn);
         }
-        quad_sum16(s);
-        if (g < lc)
-#pragma unroll
-          for (int k = 4 * q; k < 4 * q + 4; ++k)
-            if (k < kc) yx[(int64_t)g * nrhs + k0 + k] -= s[k];
+        double o[4];
+        quad_rs16(s, q, o);
+        if (g < lc) sub_row4(yx + (int64_t)g * nrhs + k0, q, kc, o);
       }
     }
   }
 }
 
 // Backward block solve of one step: t = y_i[n] - sum_c L(c, n)^T z_c over the
-// basis of i and the close blocks, then y_i[n] = L_nn^{-T} t.
+// basis of i and the close blocks, then y_i[n] = L_nn^{-T} t.  With part the
+// close blocks' products come precomputed (k_ap_bpart, maxclose slots of
+// nmax x nrhs per step).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax) {
+__global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax, const double* part,
+                                                int maxclose) {
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -348,7 +416,8 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
     const int kc = min(RC, nrhs - k0);
     __syncthreads();
     load_vec_tile(tn, yi, r, n, nrhs, k0, kc);
-    for (int v = -1; v < st.nclose; ++v) {
+    const int nv = part ? 0 : st.nclose;
+    for (int v = -1; v < nv; ++v) {
       const T* P;
       int trans, bx, lc;
       const double* zx;
@@ -376,30 +445,174 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
           for (int k = 0; k < RC; ++k) s[k] = 0.0;
           if (t < n) {
             if (trans)
-              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(g0 + g) * b + r + t], zt + g * RCP);
+              axpy_run(s, P + (int64_t)g0 * b + r + t, b, q, gc, zt);
             else
-              for (int g = q; g < gc; g += 4) axpy16(s, (double)P[(int64_t)(r + t) * bx + g0 + g], zt + g * RCP);
+              axpy_run(s, P + (int64_t)(r + t) * bx + g0, 1, q, gc, zt);
           }
-          quad_sum16(s);
-          if (t < n)
-#pragma unroll
-            for (int k = 4 * q; k < 4 * q + 4; ++k) tn[t * RCP + k] -= s[k];
+          double o[4];
+          quad_rs16(s, q, o);
+          if (t < n) {
+            double2* tp = reinterpret_cast<double2*>(tn + t * RCP + 4 * q);
+            double2 a0 = tp[0], a1 = tp[1];
+            a0.x -= o[0];
+            a0.y -= o[1];
+            a1.x -= o[2];
+            a1.y -= o[3];
+            tp[0] = a0;
+            tp[1] = a1;
+          }
         }
       }
     }
     __syncthreads();
+    if (part) {
+      // the close blocks' products L(c, n)^T z_c from k_ap_bpart, subtracted
+      // in view order (eight loads in flight per element)
+      const double* pp = part + (int64_t)blockIdx.x * maxclose * nmax * nrhs;
+      const int64_t pstride = (int64_t)nmax * nrhs;
+      for (int e = threadIdx.x; e < n * RC; e += NT) {
+        const int t = e / RC, k = e % RC;
+        if (k >= kc) continue;
+        double acc = tn[t * RCP + k];
+        for (int v0 = 0; v0 < st.nclose; v0 += 8) {
+          double pv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pv[u] = v0 + u < st.nclose ? pp[(v0 + u) * pstride + t * nrhs + k0 + k] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (v0 + u < st.nclose) acc -= pv[u];
+        }
+        tn[t * RCP + k] = acc;
+      }
+      __syncthreads();
+    }
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int c = c0 + rl;
       double s[RC];
 #pragma unroll
       for (int k = 0; k < RC; ++k) s[k] = 0.0;
-      if (c < n)
-        for (int row = c + q; row < n; row += 4) axpy16(s, (double)Li[(int64_t)row * n + c], tn + row * RCP);
-      quad_sum16(s);
-      if (c < n)
+      if (c < n) axpy_run(s, Li + c, n, c + q, n, tn);
+      double o[4];
+      quad_rs16(s, q, o);
+      if (c < n) store_row4(yi + (int64_t)(r + c) * nrhs + k0, q, kc, o);
+    }
+  }
+}
+
+// Forward update of one close block of one step (grid: steps x close views),
+// after k_ap_fwd2 with views = 0 has left t = L_nn^{-1} y_i[n] in y_i[n]:
+// y_c -= L(c, n) t.  Steps of one wave share no close block, so the
+// workgroups of a launch write disjoint rows; a step's views run in parallel
+// instead of one after another (the waves of the upper levels hold too few
+// steps to hide that chain of memory round trips).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_ap_fview(ApplyArgs<T> A, int32_t s0, double* y, int nmax) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int v = blockIdx.y;
+  if (v >= st.nclose) return;
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const View vw = A.views[st.view0 + v];
+  const int bx = A.bsz[vw.x];
+  const int lc = vw.proc ? A.rank[vw.x] : bx;
+  if (lc <= 0) return;
+  const int nrhs = A.nrhs;
+  const T* P = A.arena + A.slot_off[vw.slot];
+  const double* yi = y + A.dof_off[i] * nrhs;
+  double* yx = y + A.dof_off[vw.x] * nrhs;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* tn = reinterpret_cast<double*>(smem_raw);   // n x RC, row stride RCP
+  const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
+  for (int k0 = 0; k0 < nrhs; k0 += RC) {
+    const int kc = min(RC, nrhs - k0);
+    __syncthreads();
+    load_vec_tile(tn, yi, r, n, nrhs, k0, kc);
+    __syncthreads();
+    for (int g0 = 0; g0 < lc; g0 += 64) {
+      const int g = g0 + rl;
+      double s[RC];
 #pragma unroll
-        for (int k = 4 * q; k < 4 * q + 4; ++k)
-          if (k < kc) yi[(int64_t)(r + c) * nrhs + k0 + k] = s[k];
+      for (int k = 0; k < RC; ++k) s[k] = 0.0;
+      if (g < lc) {
+        if (vw.trans)
+          axpy_run(s, P + (int64_t)g * b + r, 1, q, n, tn);
+        else
+          axpy_run(s, P + (int64_t)r * bx + g, bx, q, n, tn);
+      }
+      double o[4];
+      quad_rs16(s, q, o);
+      if (g < lc) sub_row4(yx + (int64_t)g * nrhs + k0, q, kc, o);
+    }
+  }
+}
+
+// Backward product of one close block of one step (grid: steps x close
+// views): part = L(c, n)^T z_c (n x nrhs, zero when c has no live rows), in
+// slot (step, view) of maxclose per step; k_ap_bwd2 subtracts them in view
+// order.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_ap_bpart(ApplyArgs<T> A, int32_t s0, const double* y, double* part, int nmax,
+                                                 int maxclose) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int v = blockIdx.y;
+  if (v >= st.nclose) return;
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const View vw = A.views[st.view0 + v];
+  const int bx = A.bsz[vw.x];
+  const int lc = vw.proc ? A.rank[vw.x] : bx;
+  const int nrhs = A.nrhs;
+  const T* P = A.arena + A.slot_off[vw.slot];
+  const double* zx = y + A.dof_off[vw.x] * nrhs;
+  double* pp = part + ((int64_t)blockIdx.x * maxclose + v) * nmax * nrhs;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* pt = reinterpret_cast<double*>(smem_raw);   // n x RC, row stride RCP
+  double* zt = pt + (size_t)nmax * RCP;                // 64 x RC, row stride RCP
+  const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
+  for (int k0 = 0; k0 < nrhs; k0 += RC) {
+    const int kc = min(RC, nrhs - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * RCP; e += NT) pt[e] = 0.0;
+    for (int g0 = 0; g0 < lc; g0 += 64) {
+      const int gc = min(64, lc - g0);
+      __syncthreads();
+      load_vec_tile(zt, zx, g0, gc, nrhs, k0, kc);
+      __syncthreads();
+      for (int t0 = 0; t0 < n; t0 += 64) {
+        const int t = t0 + rl;
+        double s[RC];
+#pragma unroll
+        for (int k = 0; k < RC; ++k) s[k] = 0.0;
+        if (t < n) {
+          if (vw.trans)
+            axpy_run(s, P + (int64_t)g0 * b + r + t, b, q, gc, zt);
+          else
+            axpy_run(s, P + (int64_t)(r + t) * bx + g0, 1, q, gc, zt);
+        }
+        double o[4];
+        quad_rs16(s, q, o);
+        if (t < n) {
+          double2* tp = reinterpret_cast<double2*>(pt + t * RCP + 4 * q);
+          double2 a0 = tp[0], a1 = tp[1];
+          a0.x += o[0];
+          a0.y += o[1];
+          a1.x += o[2];
+          a1.y += o[3];
+          tp[0] = a0;
+          tp[1] = a1;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * RC; e += NT) {
+      const int t = e / RC, k = e % RC;
+      if (k < kc) pp[t * nrhs + k0 + k] = pt[t * RCP + k];
     }
   }
 }
@@ -549,9 +762,19 @@ __global__ void k_perm_out(int64_t n, int32_t nrhs, const int32_t* perm, const d
 // y = A x for all right-hand sides: one thread per row, the row's entries
 // read once per group of eight right-hand sides (the matrix is streamed
 // nrhs / 8 times, not nrhs times).
+// Workgroup b of nb (dispatched round-robin over the eight XCDs, each with
+// its own L2) mapped to a contiguous range of logical workgroups per XCD, so
+// that rows close in index (grid neighbours) share an L2.  A bijection of
+// [0, nb).
+__device__ inline int64_t xcd_swizzle(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
+  return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+}
+
+// y = A x for nrhs columns, one thread per row, eight columns per pass.
 __global__ void k_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                        int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_swizzle(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
   for (int k0 = 0; k0 < nrhs; k0 += 8) {
@@ -715,25 +938,52 @@ void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir,
   if (nsteps <= 0) return;
   hipLaunchKernelGGL(k_ap_rot2<T>, dim3(nsteps), dim3(NT), (size_t)bmax * RCP * sizeof(double), stream, A, y, dir);
 }
+// Waves with fewer steps than this run their close-block updates as one
+// workgroup per (step, view) (k_ap_fview / k_ap_bpart).
+constexpr int32_t AP_SPLIT_STEPS = 1024;
+
 template <typename T>
-void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
+bool ap_split(const WaveRange& w, int bmax) {
+  const size_t lds = (size_t)2 * bmax * RCP * sizeof(double) + sizeof(ViewDesc);
+  return w.s1 - w.s0 < AP_SPLIT_STEPS && w.maxclose > 0 && lds <= max_lds_bytes();
+}
+
+size_t ap_part_elems(const WaveRange& w, int bmax, int nrhs) {
+  return (size_t)(w.s1 - w.s0) * w.maxclose * bmax * nrhs;
+}
+
+template <typename T>
+void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, hipStream_t stream) {
+  const int32_t s0 = w.s0, s1 = w.s1;
   if (s1 <= s0) return;
   const size_t lds = (size_t)2 * bmax * RCP * sizeof(double) + sizeof(ViewDesc);
-  if (lds <= max_lds_bytes())
-    hipLaunchKernelGGL(k_ap_fwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
-  else
+  if (lds <= max_lds_bytes()) {
+    const bool split = ap_split<T>(w, bmax);
+    hipLaunchKernelGGL(k_ap_fwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax, split ? 0 : 1);
+    if (split)
+      hipLaunchKernelGGL(k_ap_fview<T>, dim3(s1 - s0, w.maxclose), dim3(NT), (size_t)bmax * RCP * sizeof(double),
+                         stream, A, s0, y, bmax);
+  } else {
     hipLaunchKernelGGL(k_ap_fwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
                        s0, y);
+  }
 }
 template <typename T>
-void launch_ap_bwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream) {
+void launch_ap_bwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, double* part, hipStream_t stream) {
+  const int32_t s0 = w.s0, s1 = w.s1;
   if (s1 <= s0) return;
   const size_t lds = (size_t)(bmax + 64) * RCP * sizeof(double) + sizeof(ViewDesc);
-  if (lds <= max_lds_bytes())
-    hipLaunchKernelGGL(k_ap_bwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax);
-  else
+  if (lds <= max_lds_bytes()) {
+    const bool split = part != nullptr && ap_split<T>(w, bmax);
+    if (split)
+      hipLaunchKernelGGL(k_ap_bpart<T>, dim3(s1 - s0, w.maxclose), dim3(NT), (size_t)(bmax + 64) * RCP * sizeof(double),
+                         stream, A, s0, (const double*)y, part, bmax, (int)w.maxclose);
+    hipLaunchKernelGGL(k_ap_bwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax,
+                       split ? (const double*)part : (const double*)nullptr, (int)w.maxclose);
+  } else {
     hipLaunchKernelGGL(k_ap_bwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
                        s0, y);
+  }
 }
 template <typename T>
 void launch_mul_w(const ApplyArgs<T>& A, int32_t nsteps, const double* z, double* w, int bmax, hipStream_t stream) {
@@ -840,8 +1090,9 @@ void launch_residual(int64_t n, int32_t nrhs, const double* b, int64_t ldb, doub
 
 #define CAE_APPLY_INST(T)                                                                                        \
   template void launch_ap_rotate<T>(const ApplyArgs<T>&, int32_t, double*, int, int, hipStream_t);               \
-  template void launch_ap_fwd<T>(const ApplyArgs<T>&, int32_t, int32_t, double*, int, hipStream_t);              \
-  template void launch_ap_bwd<T>(const ApplyArgs<T>&, int32_t, int32_t, double*, int, hipStream_t);              \
+  template void launch_ap_fwd<T>(const ApplyArgs<T>&, const WaveRange&, double*, int, hipStream_t);            \
+  template void launch_ap_bwd<T>(const ApplyArgs<T>&, const WaveRange&, double*, int, double*, hipStream_t);   \
+  template bool ap_split<T>(const WaveRange&, int);                                                            \
   template void launch_mul_w<T>(const ApplyArgs<T>&, int32_t, const double*, double*, int, hipStream_t);         \
   template void launch_mul_lw<T>(const ApplyArgs<T>&, int32_t, int32_t, const double*, double*, int, hipStream_t);
 CAE_APPLY_INST(double)

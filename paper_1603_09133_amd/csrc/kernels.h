@@ -64,6 +64,7 @@ struct WaveRange {
   int32_t r0, r1;   // rotation items
   int32_t t0, t1;   // triangular-solve items
   int32_t p0, p1;   // Schur targets
+  int32_t maxclose; // most close views of one step
 };
 
 template <typename T>
@@ -116,10 +117,16 @@ struct ApplyArgs {
 template <typename T>
 void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir, int bmax, hipStream_t stream);
 // forward / backward block solves of one wave
+// (waves of few steps update their close blocks one workgroup per (step,
+// view); the backward pass then needs `part`, ap_part_elems doubles, else
+// nullptr selects the one-workgroup-per-step form)
 template <typename T>
-void launch_ap_fwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream);
+void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, hipStream_t stream);
 template <typename T>
-void launch_ap_bwd(const ApplyArgs<T>& A, int32_t s0, int32_t s1, double* y, int bmax, hipStream_t stream);
+void launch_ap_bwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, double* part, hipStream_t stream);
+template <typename T>
+bool ap_split(const WaveRange& w, int bmax);
+size_t ap_part_elems(const WaveRange& w, int bmax, int nrhs);
 // multiply: w = Lcheck^T z (all steps), out += Lcheck w (one wave)
 template <typename T>
 void launch_mul_w(const ApplyArgs<T>& A, int32_t nsteps, const double* z, double* w, int bmax,

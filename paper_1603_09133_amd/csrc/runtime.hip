@@ -205,6 +205,7 @@ struct cae_factor_s {
   int32_t vec_nrhs = 0;
   std::vector<DevBuf> ybuf, wbuf, obuf;
   DevBuf ctmp;
+  DevBuf apart;   // close-block products of the split backward apply
   int32_t pcg_nrhs = 0;
   DevBuf pr, pz, pp, pq, sc, act, partial;
   DevBuf mr[7], mst;   // MINRES vectors and per-column scalars
@@ -277,8 +278,10 @@ void level_layout(const cae::LevelSym& L, NumLevel& N, size_t esize, hipStream_t
   N.dim = N.dof_off[L.M];
   N.waves.resize(L.nwaves);
   for (int32_t w = 0; w < L.nwaves; ++w) {
+    int32_t mc = 0;
+    for (int32_t k = L.wave_ptr[w]; k < L.wave_ptr[w + 1]; ++k) mc = std::max(mc, L.steps[k].nclose);
     N.waves[w] = cae::WaveRange{L.wave_ptr[w], L.wave_ptr[w + 1], L.rot_ptr[w], L.rot_ptr[w + 1],
-                                L.trsm_ptr[w], L.trsm_ptr[w + 1], L.pair_ptr[w], L.pair_ptr[w + 1]};
+                                L.trsm_ptr[w], L.trsm_ptr[w + 1], L.pair_ptr[w], L.pair_ptr[w + 1], mc};
   }
   upload(N.bsz, N.sizes, s);
   upload(N.d_slot_off, N.slot_off, s);
@@ -594,6 +597,13 @@ void ensure_vectors(cae_factor_s* h, int32_t nrhs) {
     h->obuf[l].alloc(b);
   }
   h->ctmp.alloc((size_t)std::max<int64_t>(h->coarse_dim, 1) * nrhs * sizeof(double));
+  size_t part = 0;
+  for (int l = 0; l < h->K; ++l)
+    for (const auto& w : h->lev[l].waves)
+      if (cae::ap_split<double>(w, h->lev[l].bmax))
+        part = std::max(part, cae::ap_part_elems(w, h->lev[l].bmax, nrhs));
+  h->apart.release();
+  if (part > 0) h->apart.alloc(part * sizeof(double));
   h->vec_nrhs = nrhs;
 }
 
@@ -609,7 +619,7 @@ void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, 
     auto A = apply_args<T>(h, l, nrhs);
     double* y = h->ybuf[l].as<double>();
     cae::launch_ap_rotate<T>(A, L.M, y, 0, N.bmax, s);
-    for (auto& w : N.waves) cae::launch_ap_fwd<T>(A, w.s0, w.s1, y, N.bmax, s);
+    for (auto& w : N.waves) cae::launch_ap_fwd<T>(A, w, y, N.bmax, s);
     cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
                         N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
                         h->ybuf[l + 1].as<double>(), 0, s);
@@ -628,7 +638,7 @@ void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, 
                         N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
                         h->ybuf[l + 1].as<double>(), 1, s);
     for (int w = (int)N.waves.size() - 1; w >= 0; --w)
-      cae::launch_ap_bwd<T>(A, N.waves[w].s0, N.waves[w].s1, y, N.bmax, s);
+      cae::launch_ap_bwd<T>(A, N.waves[w], y, N.bmax, h->apart.as<double>(), s);
     cae::launch_ap_rotate<T>(A, L.M, y, 1, N.bmax, s);
   }
   cae::launch_perm_out(a.n, nrhs, h->an->perm.as<int32_t>(), h->ybuf[0].as<double>(), z, ldz, s);
