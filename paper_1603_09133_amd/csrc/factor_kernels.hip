@@ -1811,58 +1811,95 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One-sided Jacobi on the ma rows R[row[k]] (64 coordinates, zero beyond b)
-// by one wavefront: LP lanes per row pair, 64 / LP pairs per pass, the
-// round-robin pairing of the rows, the rotation tests of jacobi_basis_wg.
 // ---------------------------------------------------------------------------
-// Elimination of the trailing n_i unknowns of a step (eq. (sm_L)) by one
-// wavefront, FP64 arithmetic: the left-looking Cholesky S_ii = L L^T and the
-// forward substitution L [X | P] = [I | D(n, basis)] in one pass over k, so
-// that X = L^{-1} and the panel P = L(basis_i, n_i)^T come out together.
-// Lane j owns row j of L and column j of [X | P] (n + r = b <= 64 columns);
-// step k needs only the broadcast row k of L, so the pivot chain has no
-// workgroup barrier.  LDS: one 64 x 64 array of (L column m, [X | P] row m)
-// pairs, read as one 16-byte load per lane per term.
+// Elimination of the trailing n_i unknowns of a step (eq. (sm_L)), FP64
+// arithmetic: the left-looking Cholesky S_ii = L L^T and the forward
+// substitution L [X | P] = [I | D(n, basis)] in one pass over k, so that
+// X = L^{-1} and the panel P = L(basis_i, n_i)^T come out together.  Lane j
+// owns row j of L and column j of [X | P] (n + r = b <= 64 columns).  LDS:
+// one 64 x 64 array W of (L column m, [X | P] row m) pairs, read as one
+// 16-byte load per lane per term.
 // ---------------------------------------------------------------------------
 constexpr int PW_LDS = 64 * 64 * 2 * 8;
 
-// The pass over k of one wavefront on W (n <= 64 rows filled with
-// (S(l, m), RHS(m, l))): on exit W[m * 64 + l] = (L(l, m), L^{-1} RHS (m, l)).
-// The sums over m take eight terms per round of LDS loads (two partial sums
-// per quantity).  emit(k, lv, xv) receives each finished step; returns false
-// on a non-positive pivot, mp = smallest L_kk.
-template <typename Emit>
-__device__ bool chol_fwd_wave(double2* W, int n, double& mp, Emit emit) {
-  const int lane = threadIdx.x & 63;
+// Four wavefronts of one workgroup share W (its LDS allows two blocks per
+// compute unit, so a single wavefront per block would leave half of the
+// SIMDs idle): for column k, wavefront w sums the
+// terms m = w, w + 4, ... < k of both quantities, the four partial sums meet
+// in LDS (two alternating buffers, one barrier per column) and are combined
+// in wavefront order by every wavefront; row k of W is then written by
+// wavefront k mod 4, the only one that reads it again.
+constexpr int PW4_LDS = PW_LDS + 2 * 4 * 64 * 16;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_potrf_w(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b > 64) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* W = reinterpret_cast<double2*>(smem_raw);   // W[m * 64 + l] = (L(l, m), [X | P](m, l))
+  double2* Pp = W + 64 * 64;                            // [2][4][64] partial sums
+  T* D = A.arena + A.slot_off[i];
+  T* Lig = A.Li + A.u_off[i];
+  // row k of S_ii (lanes < n, from its lower triangle: column k) and of
+  // D(n, basis) (lanes n .. b-1), sixteen loads in flight per thread
+  for (int e0 = 0; e0 < n * 64; e0 += 16 * NT) {
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + tid + NT * u, k = e >> 6, l = e & 63;
+      v[u] = (k < n) ? (l < n ? D[(int64_t)(r + l) * b + r + k] : (l < b ? D[(int64_t)(r + k) * b + l - n] : T(0)))
+                     : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + tid + NT * u, k = e >> 6, l = e & 63;
+      if (k < n) {
+        const double sv = (double)v[u];
+        W[e] = make_double2(l < n ? sv : 0.0, l < n ? (l == k ? 1.0 : 0.0) : sv);
+      }
+    }
+  }
+  __syncthreads();
   bool ok = true;
-  mp = 1e300;
+  double mp = 1e300;
   for (int k = 0; k < n; ++k) {
-    const double2 sx = W[k * 64 + lane];
-    double s0 = sx.x, x0 = sx.y, s1 = 0.0, x1 = 0.0;
-    int m = 0;
-    for (; m + 8 <= k; m += 8) {
+    const double2 sx = W[k * 64 + lane];   // read by all before any wavefront rewrites row k
+    double s0 = 0.0, x0 = 0.0, s1 = 0.0, x1 = 0.0;
+    int m = wv;
+    for (; m + 28 < k; m += 32) {
       double2 w[8];
       double bk[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        w[u] = W[(m + u) * 64 + lane];
-        bk[u] = W[(m + u) * 64 + k].x;
+        w[u] = W[(m + 4 * u) * 64 + lane];
+        bk[u] = W[(m + 4 * u) * 64 + k].x;
       }
 #pragma unroll
       for (int u = 0; u < 8; u += 2) {
-        s0 -= w[u].x * bk[u];
-        x0 -= bk[u] * w[u].y;
-        s1 -= w[u + 1].x * bk[u + 1];
-        x1 -= bk[u + 1] * w[u + 1].y;
+        s0 += w[u].x * bk[u];
+        x0 += bk[u] * w[u].y;
+        s1 += w[u + 1].x * bk[u + 1];
+        x1 += bk[u + 1] * w[u + 1].y;
       }
     }
-    for (; m < k; ++m) {
+    for (; m < k; m += 4) {
       const double2 w0 = W[m * 64 + lane];
       const double b0 = W[m * 64 + k].x;
-      s0 -= w0.x * b0;
-      x0 -= b0 * w0.y;
+      s0 += w0.x * b0;
+      x0 += b0 * w0.y;
     }
-    const double s = s0 + s1, x = x0 + x1;
+    double2* pb = Pp + (k & 1) * 256;
+    pb[wv * 64 + lane] = make_double2(s0 + s1, x0 + x1);
+    __syncthreads();
+    const double2 p0 = pb[lane], p1 = pb[64 + lane], p2 = pb[128 + lane], p3 = pb[192 + lane];
+    const double s = sx.x - ((p0.x + p1.x) + (p2.x + p3.x));
+    const double x = sx.y - ((p0.y + p1.y) + (p2.y + p3.y));
     const double d = rdl(s, k);
     double inv = 0.0, lkk = 0.0;
     if (d > 0.0) {
@@ -1872,58 +1909,27 @@ __device__ bool chol_fwd_wave(double2* W, int n, double& mp, Emit emit) {
       ok = false;
     }
     mp = fmin(mp, lkk);
-    const double lv = (lane > k && lane < n) ? s * inv : (lane == k ? lkk : 0.0);
-    const double xv = x * inv;
-    W[k * 64 + lane] = make_double2(lv, xv);
-    emit(k, lv, xv);
-    wave_sync();
-  }
-  return ok;
-}
-
-template <typename T>
-__global__ __launch_bounds__(WV) void k_potrf_w(LevelArgs<T> A, int32_t s0) {
-  const Step st = A.steps[s0 + blockIdx.x];
-  const int i = st.blk;
-  const int b = A.bsz[i];
-  if (b > 64) return;
-  const int r = A.rank[i];
-  const int n = b - r;
-  if (n <= 0) return;
-  const int lane = threadIdx.x;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2* W = reinterpret_cast<double2*>(smem_raw);   // W[m * 64 + l] = (L(l, m), [X | P](m, l))
-  T* D = A.arena + A.slot_off[i];
-  T* Lig = A.Li + A.u_off[i];
-  // row k of S_ii (lanes < n) and of D(n, basis) (lanes n .. b-1)
-  // (all loads in flight before the first use); S_ii is read from its lower
-  // triangle, column k for step k
-  T pre[64];
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    const int kk = min(k, n - 1);
-    pre[k] = lane < n ? D[(int64_t)(r + lane) * b + r + kk] : (lane < b ? D[(int64_t)(r + kk) * b + lane - n] : T(0));
-  }
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    if (k < n) {
-      const double s = (double)pre[k];
-      W[k * 64 + lane] = make_double2(lane < n ? s : 0.0, lane < n ? (lane == k ? 1.0 : 0.0) : s);
+    if (wv == (k & 3)) {
+      const double lv = (lane > k && lane < n) ? s * inv : (lane == k ? lkk : 0.0);
+      W[k * 64 + lane] = make_double2(lv, x * inv);
     }
   }
-  wave_sync();
-  double mp;
-  const bool ok = chol_fwd_wave(W, n, mp, [&](int k, double lv, double xv) {
-    if (lane < n) {
-      D[(int64_t)(r + lane) * b + r + k] = (T)lv;
-      Lig[k * n + lane] = (T)xv;
-    } else if (lane < b) {
-      D[(int64_t)(r + k) * b + (lane - n)] = (T)xv;
+  // results leave through W after the last column: a global store inside the
+  // loop would make every barrier wait for its completion
+  __syncthreads();
+  for (int e = tid; e < n * 64; e += NT) {
+    const int k = e >> 6, l = e & 63;
+    const double2 w = W[e];
+    if (l < n) {
+      D[(int64_t)(r + l) * b + r + k] = (T)w.x;
+      Lig[k * n + l] = (T)w.y;
+    } else if (l < b) {
+      D[(int64_t)(r + k) * b + (l - n)] = (T)w.y;
     }
-  });
+  }
   // the basis rows of the eliminated columns are zero after the elimination
-  for (int e = lane; e < r * n; e += WV) D[(int64_t)(e / n) * b + r + e % n] = T(0);
-  if (lane == 0) {
+  for (int e = tid; e < r * n; e += NT) D[(int64_t)(e / n) * b + r + e % n] = T(0);
+  if (tid == 0) {
     A.minpiv[i] = mp;
     if (!ok && atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
   }
@@ -3606,9 +3612,9 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream, bmax);
   if (A.compensate && w.s1 > w.s0)
     hipLaunchKernelGGL(k_compensate<T>, dim3(w.s1 - w.s0), dim3(NT), 0, stream, A, w.s0);
-  const bool ptiled = tiled && (size_t)PW_LDS <= max_lds_bytes();
+  const bool ptiled = tiled && (size_t)PW4_LDS <= max_lds_bytes();
   if (ptiled && w.s1 > w.s0)
-    hipLaunchKernelGGL(k_potrf_w<T>, dim3(w.s1 - w.s0), dim3(WV), PW_LDS, stream, B, w.s0);
+    hipLaunchKernelGGL(k_potrf_w<T>, dim3(w.s1 - w.s0), dim3(NT), PW4_LDS, stream, B, w.s0);
   if (!ptiled)
     launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
   else if (generic)
