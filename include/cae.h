@@ -91,9 +91,10 @@ typedef struct {
                               2.6, when ranks are about half the block) */
   int32_t graphs;          /* 1 (default): the iterative solvers (cae_pcg_solve,
                               cae_minres_solve) capture the preconditioner apply of a
-                              handle once into a HIP graph and replay it every iteration
-                              (the same kernels, launched as one graph); 0 = launch the
-                              kernels one by one */
+                              handle into a HIP graph after its first three applies with
+                              the same vectors and replay it from then on (the same
+                              kernels, launched as one graph); 0 = launch the kernels one
+                              by one */
 } cae_options_t;
 
 #define CAE_RECORD_WIDTH 17

@@ -217,6 +217,7 @@ struct cae_factor_s {
   // alternates two input vectors, hence a few entries)
   struct ApGraph {
     hipGraphExec_t exec = nullptr;
+    int32_t uses = 0;   // eager applies with this key so far
     int32_t nrhs = 0;
     const double* r = nullptr;
     double* z = nullptr;
@@ -697,9 +698,13 @@ void solver_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, d
     do_apply(h, nrhs, r, ldr, z, ldz);
     return;
   }
+  // the first applies of a key run eagerly: capturing and instantiating the
+  // graph costs more than a couple of replays save (a factor used for one
+  // short solve never captures)
+  constexpr int32_t kEagerApplies = 3;
   cae_factor_s::ApGraph* hit = nullptr;
   for (auto& g : h->ap)
-    if (g.exec && g.nrhs == nrhs && g.r == r && g.z == z && g.ldr == ldr && g.ldz == ldz) hit = &g;
+    if (g.uses > 0 && g.nrhs == nrhs && g.r == r && g.z == z && g.ldr == ldr && g.ldz == ldz) hit = &g;
   if (!hit) {
     hit = &h->ap[h->ap_next];
     h->ap_next = (h->ap_next + 1) % 4;
@@ -707,6 +712,19 @@ void solver_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, d
       HIPCHK(hipGraphExecDestroy(hit->exec));
       hit->exec = nullptr;
     }
+    hit->uses = 0;
+    hit->nrhs = nrhs;
+    hit->r = r;
+    hit->z = z;
+    hit->ldr = ldr;
+    hit->ldz = ldz;
+  }
+  if (!hit->exec && hit->uses < kEagerApplies) {
+    ++hit->uses;
+    do_apply(h, nrhs, r, ldr, z, ldz);
+    return;
+  }
+  if (!hit->exec) {
     ensure_vectors(h, nrhs);
     if (!h->ap_stream) HIPCHK(hipStreamCreateWithFlags(&h->ap_stream, hipStreamNonBlocking));
     hipStream_t keep = h->stream;
@@ -726,11 +744,6 @@ void solver_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, d
     const hipError_t e = hipGraphInstantiate(&hit->exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HIPCHK(e);
-    hit->nrhs = nrhs;
-    hit->r = r;
-    hit->z = z;
-    hit->ldr = ldr;
-    hit->ldz = ldz;
   }
   HIPCHK(hipGraphLaunch(hit->exec, h->stream));
 }
