@@ -2910,26 +2910,50 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
   const bool far = (item.view - st.view0) >= st.nclose;
   const int r = A.rank[i];
   T* base = A.arena + A.slot_off[v.slot];
+  // U^T X on the FP64 matrix cores: wavefront w owns rows 16 w .. 16 w + 15
+  // of the product as four 16 x 16 tiles (v_mfma_f64_16x16x4f64 lanes:
+  // A (row l % 16, k l / 16), B (k l / 16, column l % 16); result register j
+  // of lane l: (row 4 j + l / 16, column l % 16)); rows b .. b4 - 1 of both
+  // operands are zero so the k loop runs in whole steps of four
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int b4 = (b + 3) & ~3;
+  for (int e = threadIdx.x; e < (b4 - b) * 64; e += NT) Us[(b + (e >> 6)) * TLD + (e & 63)] = T(0);
+  // a far view keeps only its rows < r_i (E_i is dropped): wavefronts whose
+  // rows all lie beyond r_i skip the product (with compensation k_compensate
+  // reads E_i and zeroes it afterwards)
+  const bool drop = far && !A.compensate;
   for (int c0 = 0; c0 < bx; c0 += 64) {
     const int tc = min(64, bx - c0);
     __syncthreads();
     load_view_tile(X, base, v.trans, b, bx, 0, b, c0, tc);
+    for (int e = threadIdx.x; e < (b4 - b) * 64; e += NT) X[(b + (e >> 6)) * TLD + (e & 63)] = T(0);
     __syncthreads();
-    zero_acc(acc);
-    // a far view keeps only its rows < r_i (E_i is dropped): wavefronts whose
-    // rows all lie beyond r_i skip the product (with compensation k_compensate
-    // reads E_i and zeroes it afterwards)
-    const bool drop = far && !A.compensate;
-    if (!drop || 4 * ty < r) gemm_tn_4x4(Us, X, b, acc);
-    if (drop) {
+    dbl4 dacc[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
-        if (4 * ty + p >= r)
+    for (int tj = 0; tj < 4; ++tj) dacc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    if (!drop || 16 * wv < r) {
+      const T* fa = Us + fk * TLD + 16 * wv + fr;
+      const T* fb = X + fk * TLD + fr;
+#pragma unroll 2
+      for (int k0 = 0; k0 < b4; k0 += 4) {
+        const double av = (double)fa[k0 * TLD];
+        double bv[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+        for (int tj = 0; tj < 4; ++tj) bv[tj] = (double)fb[k0 * TLD + 16 * tj];
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+          dacc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], dacc[tj], 0, 0, 0);
+      }
     }
     __syncthreads();
-    acc_to_lds(acc, X);
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * wv + 4 * j + fk;
+        X[row * TLD + 16 * tj + fr] = (drop && row >= r) ? T(0) : (T)dacc[tj][j];
+      }
     __syncthreads();
     store_view_tile(X, base, v.trans, b, bx, 0, b, c0, tc);
   }
