@@ -762,15 +762,6 @@ __global__ void k_perm_out(int64_t n, int32_t nrhs, const int32_t* perm, const d
 // y = A x for all right-hand sides: one thread per row, the row's entries
 // read once per group of eight right-hand sides (the matrix is streamed
 // nrhs / 8 times, not nrhs times).
-// Workgroup b of nb (dispatched round-robin over the eight XCDs, each with
-// its own L2) mapped to a contiguous range of logical workgroups per XCD, so
-// that rows close in index (grid neighbours) share an L2.  A bijection of
-// [0, nb).
-__device__ inline int64_t xcd_swizzle(int64_t b, int64_t nb) {
-  const int64_t q = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
-  return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
-}
-
 // y = A x for nrhs columns, one thread per row, eight columns per pass.
 __global__ void k_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                        int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {

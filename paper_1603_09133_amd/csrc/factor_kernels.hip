@@ -2864,7 +2864,8 @@ __global__ __launch_bounds__(NT) void k_compress_rand(LevelArgs<T> A, int32_t s0
 // V_ix <- U_i^T V_ix (far views keep rows 0..r_i-1), D_i <- U_i^T D_i U_i.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
-  const Item item = A.items[it0 + blockIdx.x];
+  // the items of one step (consecutive) on one XCD: U_i is fetched into one L2
+  const Item item = A.items[it0 + xcd_swizzle(blockIdx.x, gridDim.x)];
   const Step st = A.steps[item.step];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -2962,7 +2963,8 @@ __global__ __launch_bounds__(NT) void k_rotate_t(LevelArgs<T> A, int32_t it0) {
 // L(c, n_i)^T = L_nn^{-1} V_ic[n_i, live_c] as a product with the stored inverse.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_trsm_t(LevelArgs<T> A, int32_t it0) {
-  const Item item = A.items[it0 + blockIdx.x];
+  // the items of one step (consecutive) on one XCD: L_nn^{-1} is fetched into one L2
+  const Item item = A.items[it0 + xcd_swizzle(blockIdx.x, gridDim.x)];
   const Step st = A.steps[item.step];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -2998,7 +3000,9 @@ __global__ __launch_bounds__(NT) void k_trsm_t(LevelArgs<T> A, int32_t it0) {
 // T(a, c) -= P_a^T P_c, P_a = rows n_i of panel a (0 = basis columns of D_i).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_schur_t(LevelArgs<T> A, int32_t p0) {
-  const Pair pr = A.pairs[p0 + blockIdx.x];
+  // the pairs of one step (consecutive) on one XCD: their panels are fetched
+  // into one L2 and reused there
+  const Pair pr = A.pairs[p0 + xcd_swizzle(blockIdx.x, gridDim.x)];
   const Step st = A.steps[pr.step];
   const int i = st.blk;
   const int b = A.bsz[i];

@@ -59,6 +59,15 @@ constexpr int MLP_OFF_MEAN = 0, MLP_OFF_STD = 16, MLP_OFF_W1 = 32, MLP_OFF_B1 = 
               MLP_OFF_W3 = MLP_OFF_B2 + MLP_H, MLP_OFF_B3 = MLP_OFF_W3 + MLP_H, MLP_NPARAM = MLP_OFF_B3 + 1;
 constexpr int SKETCH_OVERSAMPLE = 8;
 
+// Workgroup b of nb (dispatched round-robin over the eight XCDs, each with
+// its own L2) mapped to a contiguous range of logical workgroups per XCD, so
+// that work items adjacent in index (grid neighbours, the items of one
+// elimination step) share an L2.  A bijection of [0, nb).
+__device__ inline int64_t xcd_swizzle(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
+  return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+}
+
 struct WaveRange {
   int32_t s0, s1;   // steps
   int32_t r0, r1;   // rotation items
