@@ -95,11 +95,17 @@ typedef struct {
                               the same vectors and replay it from then on (the same
                               kernels, launched as one graph); 0 = launch the kernels one
                               by one */
+  int32_t apply_split_steps; /* elimination waves with fewer steps than this (default 1024)
+                              update the close blocks in the apply one workgroup per
+                              (step, close block), larger waves one workgroup per step;
+                              0 = always one workgroup per step.  Only the order of the
+                              FP64 sums in the backward pass differs */
 } cae_options_t;
 
 #define CAE_RECORD_WIDTH 17
 
-/* Fill *opt with the defaults (CE(eps), FP64, MULTICOLOUR, coarse 2048, graphs on). */
+/* Fill *opt with the defaults (CE(eps), FP64, MULTICOLOUR, coarse 2048, graphs on,
+   apply split below 1024 steps). */
 void cae_default_options(cae_options_t* opt);
 
 typedef struct cae_analysis_s* cae_analysis_t;

@@ -64,11 +64,13 @@ def graph_order(indptr, indices, B):
 
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
              coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None,
-             compensate=False, graphs=True):
+             compensate=False, graphs=True, apply_split_steps=None):
     o = _lib.Options()
     lib().cae_default_options(C.byref(o))
     o.compensate = 1 if compensate else 0
     o.graphs = 1 if graphs else 0
+    if apply_split_steps is not None:
+        o.apply_split_steps = int(apply_split_steps)
     o.mlp_params = None if mlp_params is None else mlp_params.data_ptr()
     o.seed = int(seed)
     o.record = None if record is None else record.data_ptr()
@@ -170,12 +172,14 @@ class Factor:
 
     def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
                  max_levels=0, coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0,
-                 record=None, compensate=False, graphs=True):
+                 record=None, compensate=False, graphs=True, apply_split_steps=None):
         """``rank_mode=RANK_LEARNED`` needs ``mlp_params`` (float32 CUDA tensor of
         ``learned.param_count()`` entries); ``record`` (float32 CUDA tensor of
         shape ``(rows, RECORD_WIDTH)``) receives the training records;
         ``graphs=False`` makes the iterative solvers launch the apply kernels
-        one by one instead of replaying a captured HIP graph."""
+        one by one instead of replaying a captured HIP graph;
+        ``apply_split_steps`` overrides the wave size below which the apply
+        updates close blocks one workgroup per (step, block) (0 = never)."""
         import torch
         if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.float64):
             raise TypeError("vals must be a float64 CUDA tensor")
@@ -191,7 +195,7 @@ class Factor:
         self._opts = _options(order=analysis.order, precision=precision, rank_mode=rank_mode,
                               fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
                               stream=sptr, timing=timing, mlp_params=mlp_params, seed=seed, record=record,
-                              compensate=compensate, graphs=graphs)
+                              compensate=compensate, graphs=graphs, apply_split_steps=apply_split_steps)
         h = C.c_void_p()
         self._vals = vals.contiguous()
         check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),

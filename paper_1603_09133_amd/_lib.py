@@ -34,7 +34,7 @@ class Options(C.Structure):
                 ("timing", C.c_int32), ("compensate", C.c_int32),
                 ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p), ("mlp_params", C.c_void_p),
                 ("seed", C.c_uint64), ("record", C.c_void_p), ("record_cap", C.c_int64), ("coarsen", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("apply_split_steps", C.c_int32)]
 
 
 class LevelInfo(C.Structure):

@@ -929,14 +929,12 @@ void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir,
   if (nsteps <= 0) return;
   hipLaunchKernelGGL(k_ap_rot2<T>, dim3(nsteps), dim3(NT), (size_t)bmax * RCP * sizeof(double), stream, A, y, dir);
 }
-// Waves with fewer steps than this run their close-block updates as one
-// workgroup per (step, view) (k_ap_fview / k_ap_bpart).
-constexpr int32_t AP_SPLIT_STEPS = 1024;
-
+// Waves with fewer steps than split_steps run their close-block updates as
+// one workgroup per (step, view) (k_ap_fview / k_ap_bpart).
 template <typename T>
-bool ap_split(const WaveRange& w, int bmax) {
+bool ap_split(const WaveRange& w, int bmax, int32_t split_steps) {
   const size_t lds = (size_t)2 * bmax * RCP * sizeof(double) + sizeof(ViewDesc);
-  return w.s1 - w.s0 < AP_SPLIT_STEPS && w.maxclose > 0 && lds <= max_lds_bytes();
+  return w.s1 - w.s0 < split_steps && w.maxclose > 0 && lds <= max_lds_bytes();
 }
 
 size_t ap_part_elems(const WaveRange& w, int bmax, int nrhs) {
@@ -944,12 +942,13 @@ size_t ap_part_elems(const WaveRange& w, int bmax, int nrhs) {
 }
 
 template <typename T>
-void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, hipStream_t stream) {
+void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, int32_t split_steps,
+                   hipStream_t stream) {
   const int32_t s0 = w.s0, s1 = w.s1;
   if (s1 <= s0) return;
   const size_t lds = (size_t)2 * bmax * RCP * sizeof(double) + sizeof(ViewDesc);
   if (lds <= max_lds_bytes()) {
-    const bool split = ap_split<T>(w, bmax);
+    const bool split = ap_split<T>(w, bmax, split_steps);
     hipLaunchKernelGGL(k_ap_fwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax, split ? 0 : 1);
     if (split)
       hipLaunchKernelGGL(k_ap_fview<T>, dim3(s1 - s0, w.maxclose), dim3(NT), (size_t)bmax * RCP * sizeof(double),
@@ -960,12 +959,13 @@ void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bma
   }
 }
 template <typename T>
-void launch_ap_bwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, double* part, hipStream_t stream) {
+void launch_ap_bwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, double* part,
+                   int32_t split_steps, hipStream_t stream) {
   const int32_t s0 = w.s0, s1 = w.s1;
   if (s1 <= s0) return;
   const size_t lds = (size_t)(bmax + 64) * RCP * sizeof(double) + sizeof(ViewDesc);
   if (lds <= max_lds_bytes()) {
-    const bool split = part != nullptr && ap_split<T>(w, bmax);
+    const bool split = part != nullptr && ap_split<T>(w, bmax, split_steps);
     if (split)
       hipLaunchKernelGGL(k_ap_bpart<T>, dim3(s1 - s0, w.maxclose), dim3(NT), (size_t)(bmax + 64) * RCP * sizeof(double),
                          stream, A, s0, (const double*)y, part, bmax, (int)w.maxclose);
@@ -1081,9 +1081,10 @@ void launch_residual(int64_t n, int32_t nrhs, const double* b, int64_t ldb, doub
 
 #define CAE_APPLY_INST(T)                                                                                        \
   template void launch_ap_rotate<T>(const ApplyArgs<T>&, int32_t, double*, int, int, hipStream_t);               \
-  template void launch_ap_fwd<T>(const ApplyArgs<T>&, const WaveRange&, double*, int, hipStream_t);            \
-  template void launch_ap_bwd<T>(const ApplyArgs<T>&, const WaveRange&, double*, int, double*, hipStream_t);   \
-  template bool ap_split<T>(const WaveRange&, int);                                                            \
+  template void launch_ap_fwd<T>(const ApplyArgs<T>&, const WaveRange&, double*, int, int32_t, hipStream_t);   \
+  template void launch_ap_bwd<T>(const ApplyArgs<T>&, const WaveRange&, double*, int, double*, int32_t,       \
+                                 hipStream_t);                                                               \
+  template bool ap_split<T>(const WaveRange&, int, int32_t);                                                   \
   template void launch_mul_w<T>(const ApplyArgs<T>&, int32_t, const double*, double*, int, hipStream_t);         \
   template void launch_mul_lw<T>(const ApplyArgs<T>&, int32_t, int32_t, const double*, double*, int, hipStream_t);
 CAE_APPLY_INST(double)

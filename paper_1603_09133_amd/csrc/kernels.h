@@ -126,15 +126,17 @@ struct ApplyArgs {
 template <typename T>
 void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir, int bmax, hipStream_t stream);
 // forward / backward block solves of one wave
-// (waves of few steps update their close blocks one workgroup per (step,
-// view); the backward pass then needs `part`, ap_part_elems doubles, else
-// nullptr selects the one-workgroup-per-step form)
+// (waves of fewer than split_steps steps update their close blocks one
+// workgroup per (step, view); the backward pass then needs `part`,
+// ap_part_elems doubles, else nullptr selects the one-workgroup-per-step form)
 template <typename T>
-void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, hipStream_t stream);
+void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, int32_t split_steps,
+                   hipStream_t stream);
 template <typename T>
-void launch_ap_bwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, double* part, hipStream_t stream);
+void launch_ap_bwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bmax, double* part,
+                   int32_t split_steps, hipStream_t stream);
 template <typename T>
-bool ap_split(const WaveRange& w, int bmax);
+bool ap_split(const WaveRange& w, int bmax, int32_t split_steps);
 size_t ap_part_elems(const WaveRange& w, int bmax, int nrhs);
 // multiply: w = Lcheck^T z (all steps), out += Lcheck w (one wave)
 template <typename T>

@@ -601,7 +601,7 @@ void ensure_vectors(cae_factor_s* h, int32_t nrhs) {
   size_t part = 0;
   for (int l = 0; l < h->K; ++l)
     for (const auto& w : h->lev[l].waves)
-      if (cae::ap_split<double>(w, h->lev[l].bmax))
+      if (cae::ap_split<double>(w, h->lev[l].bmax, h->opt.apply_split_steps))
         part = std::max(part, cae::ap_part_elems(w, h->lev[l].bmax, nrhs));
   h->apart.release();
   if (part > 0) h->apart.alloc(part * sizeof(double));
@@ -620,7 +620,7 @@ void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, 
     auto A = apply_args<T>(h, l, nrhs);
     double* y = h->ybuf[l].as<double>();
     cae::launch_ap_rotate<T>(A, L.M, y, 0, N.bmax, s);
-    for (auto& w : N.waves) cae::launch_ap_fwd<T>(A, w, y, N.bmax, s);
+    for (auto& w : N.waves) cae::launch_ap_fwd<T>(A, w, y, N.bmax, h->opt.apply_split_steps, s);
     cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
                         N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
                         h->ybuf[l + 1].as<double>(), 0, s);
@@ -639,7 +639,7 @@ void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, 
                         N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
                         h->ybuf[l + 1].as<double>(), 1, s);
     for (int w = (int)N.waves.size() - 1; w >= 0; --w)
-      cae::launch_ap_bwd<T>(A, N.waves[w], y, N.bmax, h->apart.as<double>(), s);
+      cae::launch_ap_bwd<T>(A, N.waves[w], y, N.bmax, h->apart.as<double>(), h->opt.apply_split_steps, s);
     cae::launch_ap_rotate<T>(A, L.M, y, 1, N.bmax, s);
   }
   cae::launch_perm_out(a.n, nrhs, h->an->perm.as<int32_t>(), h->ybuf[0].as<double>(), z, ldz, s);
@@ -768,6 +768,7 @@ void cae_default_options(cae_options_t* opt) {
   opt->max_levels = 0;
   opt->coarse_max_dim = 2048;
   opt->graphs = 1;
+  opt->apply_split_steps = 1024;
   opt->stream = nullptr;
 }
 

@@ -112,6 +112,40 @@ def test_factor_matches_oracle_fp64(dims, patch, eps, order, coarse):
     assert abs(st["dropped_sq"] - d_o) <= 1e-10 * d_o + bound
 
 
+@pytest.mark.parametrize("dims,patch,eps,order,coarse,prec", [
+    ((40, 24), (8, 8), 1e-6, "multicolour", 0, "fp64"),
+    ((7, 9, 6), (2, 2, 2), 1e-4, "paper", 0, "fp64"),
+    ((64, 64), (4, 4), 1e-8, "multicolour", 2048, "fp64"),
+    ((40, 24), (8, 8), 1e-6, "multicolour", 0, "fp32"),
+])
+def test_apply_one_workgroup_per_step_matches_oracle(dims, patch, eps, order, coarse, prec):
+    """Both forms of the apply's close-block updates against the oracle's
+    M^{-1} X: one workgroup per step (apply_split_steps = 0, the form large
+    waves take) and one per (step, close block) (apply_split_steps large,
+    every wave); FP64 to the parity bar, FP32 within 1e-3 (the FP32 factor's
+    1e-7 probe error times the preconditioner's condition), and the two forms
+    within rounding of each other (only the order of FP64 sums differs)."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup(dims, patch)
+    print(f"case dims={dims} patch={patch} eps={eps} order={order} coarse={coarse} {prec}", flush=True)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order=order, coarse_max_dim=coarse))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co,
+                      order=cae.ORDER_PAPER if order == "paper" else cae.ORDER_MULTICOLOUR)
+    vals = torch.from_numpy(csr[2]).cuda()
+    precision = cae.FP64 if prec == "fp64" else cae.FP32
+    X = _probes(A.shape[0])
+    Zo = ce_solve(fo, X)
+    Z = {}
+    for split in (0, 1 << 30):
+        f = cae.Factor(an, vals, eps, precision=precision, coarse_max_dim=coarse, apply_split_steps=split)
+        Z[split] = _from_gpu_cols(f.apply(_to_gpu_cols(X)))
+        f.close()
+    tol = 1e-10 if prec == "fp64" else 1e-3
+    for split, Zg in Z.items():
+        assert np.linalg.norm(Zg - Zo) <= tol * np.linalg.norm(Zo), split
+    assert np.linalg.norm(Z[0] - Z[1 << 30]) <= 1e-12 * np.linalg.norm(Z[0])
+
+
 def test_eps_zero_exact_and_frobenius_identity_on_gpu():
     cae = _cae()
     A, csr, perm, bp, co = _setup((20, 20), (4, 4))
