@@ -147,6 +147,27 @@ void upload(DevBuf& d, const std::vector<U>& h, hipStream_t s) {
   if (!h.empty()) HIPCHK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice, s));
 }
 
+// A pinned host buffer of this thread for the factorization's small
+// read-backs (grown on demand; every read-back is waited for before the
+// buffer is used again; kept until the process ends, when the runtime that
+// would free it may already be gone).
+char* pinned_readback(size_t bytes) {
+  struct Pinned {
+    char* p = nullptr;
+    size_t cap = 0;
+  };
+  static thread_local Pinned pb;
+  if (bytes > pb.cap) {
+    if (pb.p) HIPCHK(hipHostFree(pb.p));
+    pb.p = nullptr;
+    pb.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, (size_t)1 << 20);
+    HIPCHK(hipHostMalloc((void**)&pb.p, cap, hipHostMallocDefault));
+    pb.cap = cap;
+  }
+  return pb.p;
+}
+
 void init_device_limits() {
   static bool done = false;
   if (done) return;
@@ -201,6 +222,7 @@ struct cae_factor_s {
   int64_t factor_bytes = 0;
   int32_t compress_launches = 0, compressions = 0;
   double compress_ms = 0, compress_flops = 0;
+  bool flops_pending = false;   // compress_flops / compressions not yet counted
   // apply / multiply / PCG work vectors
   int32_t vec_nrhs = 0;
   std::vector<DevBuf> ybuf, wbuf, obuf;
@@ -477,15 +499,23 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
                 l + 1, cnt, sum[0] / cnt, mx[0], sum[1] / cnt, mx[1], sum[2] / cnt, mx[2], sum[3] / cnt,
                 sum[4] / cnt, mx[4], sum[5] / cnt, mx[5], sum[6] / cnt, mx[6], sum[7] / cnt, mx[7]);
     }
-    // the ranks decide the sizes of the next level
+    // the ranks decide the sizes of the next level (read back through pinned
+    // memory: a copy into pageable memory costs a staged transfer each)
     N.ranks.resize(L.M);
-    std::vector<double> ed(L.M), mp(L.M);
     int32_t herr[2];
-    HIPCHK(hipMemcpyAsync(N.ranks.data(), N.rank.p, L.M * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(ed.data(), N.edrop.p, L.M * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(mp.data(), N.minpiv.p, L.M * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(herr, h->err.p, sizeof(herr), hipMemcpyDeviceToHost, s));
+    char* pin = pinned_readback((size_t)L.M * (sizeof(int32_t) + 2 * sizeof(double)) + 2 * sizeof(int32_t));
+    double* ed = reinterpret_cast<double*>(pin);
+    double* mp = ed + L.M;
+    int32_t* hr = reinterpret_cast<int32_t*>(mp + L.M);
+    int32_t* he = hr + L.M;
+    HIPCHK(hipMemcpyAsync(hr, N.rank.p, L.M * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ed, N.edrop.p, L.M * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(mp, N.minpiv.p, L.M * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(he, h->err.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    std::copy(hr, hr + L.M, N.ranks.begin());
+    herr[0] = he[0];
+    herr[1] = he[1];
     if (herr[0]) {
       char buf[160];
       snprintf(buf, sizeof buf, "non-SPD pivot block at level %d, block %d", l + 1, herr[1]);
@@ -504,19 +534,9 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
         (void)hipEventDestroy(evs[k]);
         (void)hipEventDestroy(evs[k + 1]);
       }
-      // algorithmic flops of the compressions of this level
-      for (const cae::Step& stp : L.steps) {
-        if (stp.nfar == 0) continue;
-        const double b = N.sizes[stp.blk];
-        double w = 0;
-        for (int v = stp.nclose; v < stp.nclose + stp.nfar; ++v) {
-          const cae::View& vw = L.views[stp.view0 + v];
-          w += vw.proc ? N.ranks[vw.x] : N.sizes[vw.x];
-        }
-        const double qr = w >= b ? 2 * w * b * b - 2 * b * b * b / 3 : 2 * b * w * w - 2 * w * w * w / 3;
-        h->compress_flops += qr + 12 * b * b * b;
-        h->compressions += 1;
-      }
+      // (the algorithmic flops of the compressions are counted when the
+      // statistics are read, outside the factorization)
+      h->flops_pending = true;
     }
     h->lev.emplace_back();
     NumLevel& Nn = h->lev[l + 1];
@@ -1155,8 +1175,35 @@ int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
   return CAE_OK;
 }
 
+// Algorithmic flops of the compressions of every factored level (the model
+// of the compression's work: QR-equivalent of the b x w far row plus 12 b^3
+// for the SVD), from the recorded sizes and ranks.
+void count_compress_flops(cae_factor_s* h) {
+  h->compress_flops = 0;
+  h->compressions = 0;
+  const cae::Analysis& a = h->an->a;
+  for (int l = 0; l < h->K; ++l) {
+    const cae::LevelSym& L = a.levels[l];
+    const NumLevel& N = h->lev[l];
+    for (const cae::Step& stp : L.steps) {
+      if (stp.nfar == 0) continue;
+      const double b = N.sizes[stp.blk];
+      double w = 0;
+      for (int v = stp.nclose; v < stp.nclose + stp.nfar; ++v) {
+        const cae::View& vw = L.views[stp.view0 + v];
+        w += vw.proc ? N.ranks[vw.x] : N.sizes[vw.x];
+      }
+      const double qr = w >= b ? 2 * w * b * b - 2 * b * b * b / 3 : 2 * b * w * w - 2 * w * w * w / 3;
+      h->compress_flops += qr + 12 * b * b * b;
+      h->compressions += 1;
+    }
+  }
+  h->flops_pending = false;
+}
+
 int cae_get_stats(cae_handle_t h, cae_stats_t* st) {
   if (check_handle(h) || !st) return fail(CAE_EINVAL, "null argument");
+  if (h->flops_pending) count_compress_flops(h);
   st->nlevels = h->K;
   st->coarse_dim = h->coarse_dim;
   st->tau = h->tau;
