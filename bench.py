@@ -187,6 +187,9 @@ def main():
     def step():
         a = cae.Analysis(ip, ix, perm, bp, co, order=order, coarsen=coarsen) if args.with_analysis else an
         f = cae.Factor(a, vals, args.eps, precision=prec, timing=True, **fkw)
+        if args.config in ("c3", "c5"):   # long steps: the factorization reports its end
+            torch.cuda.synchronize()
+            _log("factorization done")
         _, it, rel = f.pcg(b, rtol=1e-8, maxit=1000, x=x)
         return f, it, rel
 
