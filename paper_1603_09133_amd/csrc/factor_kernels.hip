@@ -3315,8 +3315,10 @@ constexpr int GJ = 64;
 constexpr int GJP = 4;                            // pivot inverse: a GJP x GJP tile per thread
 constexpr int GJT = (64 / GJP) * (64 / GJP);      // its threads
 
-__global__ __launch_bounds__(GJT) void k_gj_pivot(double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv,
-                                                  int32_t* err) {
+static_assert(GJT == NT, "the pivot inverse runs inside the 256-thread update kernel too");
+
+__device__ void gj_pivot_block(const double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv, int32_t* err,
+                               double* Sy) {
   // Gauss-Jordan elimination without pivoting of the kb x kb pivot block
   // (read from its lower triangle), in place: after step k the leading k + 1
   // rows and columns hold the inverse of the leading block, the rest its Schur
@@ -3329,8 +3331,7 @@ __global__ __launch_bounds__(GJT) void k_gj_pivot(double* Ad, int64_t dim, int64
   // exactly when the block is positive definite.
   constexpr int TS = 64 / GJP;
   __shared__ double Rb[2][64], Cb[2][64];
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Sy = reinterpret_cast<double*>(smem_raw);   // 64 x TLD, the result before symmetrisation
+  // Sy: 64 x TLD doubles of LDS, the result before symmetrisation
   const int tid = threadIdx.x, ty = tid / TS, tx = tid % TS;
   double a[GJP][GJP];
 #pragma unroll
@@ -3395,6 +3396,13 @@ __global__ __launch_bounds__(GJT) void k_gj_pivot(double* Ad, int64_t dim, int64
   if (tid == 0 && bad) {
     if (atomicCAS(err, 0, 1) == 0) err[1] = -1;
   }
+}
+
+// The pivot inverse of the first panel (later ones run inside k_gj_update).
+__global__ __launch_bounds__(GJT) void k_gj_pivot(double* Ad, int64_t dim, int64_t k0, int kb, double* Pinv,
+                                                  int32_t* err) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  gj_pivot_block(Ad, dim, k0, kb, Pinv, err, reinterpret_cast<double*>(smem_raw));
 }
 
 // W = Pinv * A[k-block, :] and R0 = A[k-block, :]  (kb x dim each, ld dim);
@@ -3467,7 +3475,8 @@ __device__ inline void stage_panel64(double* S, const double* src, int64_t ld, i
 // lanes: A (row l % 16, k l / 16), B (k l / 16, column l % 16); result
 // register j of lane l: (row 4 j + l / 16, column l % 16)).
 __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64_t k0, int kb,
-                                                  const double* Pinv, const double* W, const double* R0) {
+                                                  const double* Pinv, const double* W, const double* R0,
+                                                  double* Pnext, int32_t* err) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Ri = reinterpret_cast<double*>(smem_raw);
   double* Wj = Ri + 64 * TLD;
@@ -3521,6 +3530,13 @@ __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64
         v = old[c][j] - acc[c][j];
       Ad[i * dim + jj] = v;
     }
+  // the workgroup holding the next pivot block inverts it as soon as it is
+  // written (into the other pivot buffer): no separate launch per panel
+  const int64_t kn = k0 + kb;
+  if (Pnext && i0 == kn && j0 == kn) {
+    __syncthreads();   // the block's entries, written by all threads, visible to all
+    gj_pivot_block(Ad, dim, kn, (int)min<int64_t>(GJ, dim - kn), Pnext, err, Ri);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -3700,15 +3716,22 @@ void launch_coarse_assemble(const int32_t* slot_p, const int32_t* slot_q, int32_
 
 void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double* R0, int32_t* err,
                        hipStream_t stream) {
+  // Pinv holds two 64 x 64 pivot inverses: panel p uses half p % 2, and its
+  // update kernel writes the next panel's into the other half
   const unsigned nt = (unsigned)((dim + GJ - 1) / GJ);
-  for (int64_t k0 = 0; k0 < dim; k0 += GJ) {
+  const size_t lds = (size_t)2 * 64 * TLD * sizeof(double);
+  if (dim > 0)
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(GJT), lds, stream, Ad, dim, (int64_t)0, (int)std::min<int64_t>(GJ, dim),
+                       Pinv, err);
+  int p = 0;
+  for (int64_t k0 = 0; k0 < dim; k0 += GJ, ++p) {
     const int kb = (int)std::min<int64_t>(GJ, dim - k0);
-    const size_t lds = (size_t)2 * 64 * TLD * sizeof(double);
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(GJT), lds, stream, Ad, dim, k0, kb, Pinv, err);
+    double* Pc = Pinv + (size_t)(p & 1) * GJ * GJ;
+    double* Pn = k0 + kb < dim ? Pinv + (size_t)((p + 1) & 1) * GJ * GJ : nullptr;
     hipLaunchKernelGGL(k_gj_rows, dim3(nt), dim3(NT), lds, stream, (const double*)Ad, dim, k0, kb,
-                       (const double*)Pinv, W, R0);
-    hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(NT), lds, stream, Ad, dim, k0, kb, (const double*)Pinv,
-                       (const double*)W, (const double*)R0);
+                       (const double*)Pc, W, R0);
+    hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(NT), lds, stream, Ad, dim, k0, kb, (const double*)Pc,
+                       (const double*)W, (const double*)R0, Pn, err);
   }
 }
 

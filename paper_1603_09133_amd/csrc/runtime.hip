@@ -571,7 +571,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
                                    N.d_slot_off.as<int64_t>(), N.bsz.as<int32_t>(), N.d_dof_off.as<int64_t>(),
                                    h->Ainv.as<double>(), dim, s);
     HIPCHK(hipMemcpyAsync(h->Acopy.p, h->Ainv.p, (size_t)dim * dim * sizeof(double), hipMemcpyDeviceToDevice, s));
-    h->gj_p.alloc(64 * 64 * sizeof(double));
+    h->gj_p.alloc(2 * 64 * 64 * sizeof(double));   // two pivot inverses (this panel's, the next one's)
     h->gj_w.alloc((size_t)64 * dim * sizeof(double));
     h->gj_r.alloc((size_t)64 * dim * sizeof(double));
     cae::launch_gj_inverse(h->Ainv.as<double>(), dim, h->gj_p.as<double>(), h->gj_w.as<double>(),
