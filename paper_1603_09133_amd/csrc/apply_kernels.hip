@@ -136,11 +136,12 @@ __global__ __launch_bounds__(NT) void k_ap_bwd_generic(ApplyArgs<T> A, int32_t s
 // ---------------------------------------------------------------------------
 // Lean block-solve kernels: four threads share one output row and split the
 // reduction index four ways, each keeping 16 FP64 accumulators (one per
-// right-hand side of the pass); a two-step shuffle sums the quarters.  Factor
-// entries are read straight from global memory (each quarter walks its own
-// addresses, consecutive rows on consecutive lanes), only the 16-wide vector
-// tiles live in LDS, so a step needs 16 KB of LDS at b = 64 and many steps
-// run on one compute unit at once.
+// right-hand side of the pass); a reduce-scatter over the four lanes leaves
+// each with the totals of four right-hand sides.  Factor entries are read
+// straight from global memory, eight at a time per thread (each quarter
+// walks its own addresses, consecutive rows on consecutive lanes), only the
+// 16-wide vector tiles live in LDS, so a step needs 16 KB of LDS at b = 64
+// and many steps run on one compute unit at once.
 // ---------------------------------------------------------------------------
 __device__ inline void axpy16(double s[RC], double p, const double* v) {
 #pragma unroll

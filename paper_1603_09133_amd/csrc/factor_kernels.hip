@@ -1445,13 +1445,16 @@ __global__ __launch_bounds__(NT) void k_schur(LevelArgs<T> A, int32_t p0, T* gsc
 }
 
 // ---------------------------------------------------------------------------
-// Register-tiled variants of rotation, triangular solve and Schur update for
-// steps with b_i <= 64.  Every product is C = A^T B with A (K x 64) and B
-// (K x 64) staged in LDS (row stride TLD); thread (ty, tx) = (tid / 16,
-// tid % 16) accumulates the 4 x 4 tile rows 4ty.., columns 4tx.. in registers,
-// so one k step costs 8 LDS reads for 16 FMAs.  Global tiles are moved with
-// the thread mapping that makes consecutive threads touch consecutive
-// addresses for either storage orientation of a view.
+// Tiled variants of rotation, triangular solve and Schur update for steps
+// with b_i <= 64.  Every product is C = A^T B with A (K x 64) and B (K x 64)
+// staged in LDS (row stride TLD).  The Schur update, the view rotation and
+// the coarse Gauss-Jordan products run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64, one 16-row strip of C per wavefront, accumulators
+// in dbl4); the others use register tiles: thread (ty, tx) = (tid / 16,
+// tid % 16) accumulates the 4 x 4 tile rows 4ty.., columns 4tx.., so one k
+// step costs 8 LDS reads for 16 FMAs.  Global tiles are moved with the thread
+// mapping that makes consecutive threads touch consecutive addresses for
+// either storage orientation of a view.
 // ---------------------------------------------------------------------------
 constexpr int TLD = 68;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
