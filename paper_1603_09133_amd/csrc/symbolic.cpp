@@ -58,10 +58,6 @@ void build_adjacency(int32_t M, const std::vector<int32_t>& pairs,
   for (int32_t i = 0; i < M; ++i) std::sort(adj.begin() + ptr[i], adj.begin() + ptr[i + 1]);
 }
 
-bool is_close(const LevelSym& L, int32_t a, int32_t c) {
-  return std::binary_search(L.cadj.begin() + L.cptr[a], L.cadj.begin() + L.cptr[a + 1], c);
-}
-
 // Colouring at distance 2 by a lattice pattern of the block coordinates when
 // it is valid on this graph ((x + 2y) mod 5 / (x + 2y + 3z) mod 7, then the
 // product of coordinates mod 3), else greedy in block index order.
@@ -181,10 +177,15 @@ void simulate(LevelSym& L, std::vector<std::vector<int32_t>>& far_at_step) {
     for (int32_t ka = L.cptr[i]; ka < L.cptr[i + 1]; ++ka) {
       int32_t a = L.cadj[ka];
       if (L.removed[a]) continue;
+      // the candidates c (ascending) against a's sorted close list, walked
+      // together instead of searched one by one
+      int32_t ma = L.cptr[a];
+      const int32_t ea = L.cptr[a + 1];
       for (int32_t kc = ka + 1; kc < L.cptr[i + 1]; ++kc) {
         int32_t c = L.cadj[kc];
+        while (ma < ea && L.cadj[ma] < c) ++ma;
         if (L.removed[c]) continue;
-        if (is_close(L, a, c)) continue;
+        if (ma < ea && L.cadj[ma] == c) continue;   // (a, c) is close
         if (!farset.insert(pkey(a, c)).second) continue;
         far[a].push_back(c);
         far[c].push_back(a);
@@ -245,6 +246,14 @@ void build_items(LevelSym& L, const std::vector<std::vector<int32_t>>& far_at_st
   L.rot_ptr.assign(L.nwaves + 1, 0);
   L.trsm_ptr.assign(L.nwaves + 1, 0);
   L.pair_ptr.assign(L.nwaves + 1, 0);
+  {
+    size_t np = 0;   // Schur targets of every step, at most (nclose + 1)(nclose + 2) / 2
+    for (int32_t i = 0; i < L.M; ++i) {
+      const size_t c = (size_t)(L.cptr[i + 1] - L.cptr[i]);
+      np += (c + 1) * (c + 2) / 2;
+    }
+    L.pairs.reserve(np);
+  }
   int32_t cur_wave = 0;
   auto close_wave = [&](int32_t upto) {
     while (cur_wave < upto) {
@@ -285,6 +294,10 @@ void build_items(LevelSym& L, const std::vector<std::vector<int32_t>>& far_at_st
     for (int32_t a = 0; a <= st.nclose; ++a) {
       int32_t xa = a ? L.views[st.view0 + a - 1].x : i;
       if (a && gone(xa)) continue;
+      // slots (xa, xc) with xc > xa: the close views come in ascending block
+      // order, so one walk along xa's sorted upper neighbours finds them all
+      int32_t u = a ? L.up_ptr[xa] : 0;
+      const int32_t ue = a ? L.up_ptr[xa + 1] : 0;
       for (int32_t c = a; c <= st.nclose; ++c) {
         int32_t xc = c ? L.views[st.view0 + c - 1].x : i;
         if (c && gone(xc)) continue;
@@ -297,9 +310,12 @@ void build_items(LevelSym& L, const std::vector<std::vector<int32_t>>& far_at_st
         if (a > 0) {
           if (a == c) {
             pr.slot = xa;
+          } else if (xc > xa) {
+            while (u < ue && L.up_q[u] < xc) ++u;
+            pr.slot = (u < ue && L.up_q[u] == xc) ? L.up_slot[u] : -1;
           } else {
             pr.slot = L.slot_of(xa, xc);
-            pr.trans = xc < xa ? 1 : 0;
+            pr.trans = 1;
           }
         }
         L.pairs.push_back(pr);
