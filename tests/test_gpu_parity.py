@@ -270,6 +270,37 @@ def test_indefinite_matrix_reports_not_spd():
     assert e.value.code == -3
 
 
+@pytest.mark.parametrize("dims,late", [((16, 16), False), ((16, 16), True), ((12, 9), True)])
+def test_indefinite_dense_remainder_reports_not_spd(dims, late):
+    """A matrix that goes whole into the dense remainder (no level is
+    factored) and is indefinite: the pivot inverses of the Gauss-Jordan sweep
+    meet a non-positive pivot -- in the first 64-unknown panel (its own
+    kernel; every diagonal shifted) or only in a later one (inverted inside
+    the previous panel's update; diagonals shifted from the second panel
+    on) -- and the factorization reports CAE_ENOTSPD; the unshifted matrix
+    factors and solves."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup(dims, (4, 4))
+    n = A.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(csr[0]))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    vals = csr[2].copy()
+    shift = np.ones(n, bool)
+    if late:
+        shift[:] = False
+        shift[np.asarray(perm)[64:]] = True   # unknowns after the first panel of the level order
+    vals[(csr[1] == rows) & shift[rows]] -= 5.0
+    with pytest.raises(cae.CAEError) as e:
+        cae.Factor(an, torch.from_numpy(vals).cuda(), 1e-6, coarse_max_dim=4096)
+    assert e.value.code == -3
+    f = cae.Factor(an, torch.from_numpy(csr[2]).cuda(), 1e-6, coarse_max_dim=4096)
+    assert f.stats()["nlevels"] == 0 and f.stats()["coarse_dim"] == n
+    X = _probes(n, 2)
+    Z = _from_gpu_cols(f.apply(_to_gpu_cols(X)))
+    Ad = A.toarray()
+    assert np.linalg.norm(Ad @ Z - X) <= 1e-12 * np.linalg.norm(X) * np.linalg.cond(Ad)
+
+
 def test_fixed_rank_mode_matches_oracle():
     """CE(r) element parity where every kept subspace is unique (r = 3 on
     4x4 patches: the smallest relative gap sigma_r - sigma_{r+1} is 4e-4)."""
