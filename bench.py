@@ -98,8 +98,8 @@ def main():
                          "(reference dispatch for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "how the factorization would shard is a design, not code", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
