@@ -93,6 +93,8 @@ def main():
                     help="c2: 2D Laplacian 1024^2 (default, the headline); c3: 3D Laplacian 128^3, B=64, eps=1e-4, "
                          "1 RHS, BF16 Schur, learned ranks; c4: 2D diffusion with a random coefficient 2048^2, "
                          "eps=1e-5, 64 RHS; c5: 256 independent 2D/3D problems in one factorization, 4 RHS each")
+    ap.add_argument("--coarsen", choices=["siblings", "pairs"], default=None,
+                    help="3D coarsening (default: pairs for c3, siblings otherwise)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size before the timed steps "
                          "(reference dispatch for the HBM byte counters)")
@@ -153,6 +155,8 @@ def main():
         workload = (f"256 independent Laplacians (2D side 64..512 with 8x8 patches, 3D side 16..64 with 2x2x4 "
                     f"patches; draws default_rng(3)), N={A.shape[0]} in one joint factorization, eps=1e-6, FP32 "
                     f"factor, 4 RHS per problem, PCG FP64 to 1e-8")
+    if args.coarsen:
+        coarsen = args.coarsen
     ip, ix, dv = problems.to_csr_arrays(A)
     N = A.shape[0]
     if args.config != "c5":

@@ -11,7 +11,7 @@
  *   (eq. (rreav), Remark 2.1) -- and the trailing b_i - r_i rotated unknowns
  *   are eliminated by block Cholesky (eq. (sm_L)).  The remaining (basis)
  *   unknowns of 2^d Morton siblings form the blocks of the next level
- *   (Section 2.6, eq. (bsp)); the last remainder is factored densely.  The
+ *   (Section 2.5, eq. (bsp)); the last remainder is factored densely.  The
  *   result is A ~ Q^T L L^T Q (Proposition 2.1); the solve is
  *   x = Q^T L^{-T} L^{-1} Q b (Proposition 2.2).
  *
@@ -88,7 +88,7 @@ typedef struct {
   int32_t coarsen;         /* cae_analyze with coordinates: 0 = the 2^d Morton siblings form a
                               block of the next level; 1 = pairs of blocks along the Morton
                               curve (axis x, y, z in turn: J = 2, keeping J r ~ B, Section
-                              2.6, when ranks are about half the block) */
+                              2.5, when ranks are about half the block) */
   int32_t graphs;          /* 1 (default): the iterative solvers (cae_pcg_solve,
                               cae_minres_solve) capture the preconditioner apply of a
                               handle into a HIP graph after its first three applies with
@@ -113,7 +113,7 @@ typedef struct cae_factor_s* cae_handle_t;
 
 /*
  * Initial permutation for a tensor grid (Section 2, eq. (init_perm); Section
- * 2.9 on the choice of P): patches of patch[k] points per axis, visited in
+ * 2.8 on the choice of P): patches of patch[k] points per axis, visited in
  * Z (Morton) order of their coordinates; x fastest inside a patch.  The grid
  * is numbered naturally with axis 0 fastest.  Partial patches at the high end
  * of an axis keep their smaller size.
@@ -128,7 +128,7 @@ int cae_grid_order(int32_t ndim, const int32_t* dims, const int32_t* patch,
 /*
  * Ordering for a general sparse SPD matrix with no grid (robustness and
  * generality option, not in the paper, which orders grids geometrically,
- * Section 2.9): nested bisection of the graph of A -- each part split into
+ * Section 2.8): nested bisection of the graph of A -- each part split into
  * halves along the breadth-first order from a pseudo-peripheral vertex --
  * to a uniform depth so that every block has at most B unknowns.  The halves
  * of a part are consecutive, so cae_analyze with coords = NULL and ndim = 1
@@ -145,7 +145,7 @@ int cae_graph_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, i
  * (close blocks, Section 2), elimination order and dependency waves of every
  * level, the far blocks created by the eliminations (eq. (A_st); remark after
  * eq. (sm_L)), blocks eliminated whole (empty far row: the first-row
- * elimination of Section 2.1), and the Morton coarsening (Section 2.6).
+ * elimination of Section 2.1), and the Morton coarsening (Section 2.5, eq. (bsp)).
  *   n, row_ptr (n+1), col_idx (row_ptr[n]): host CSR structure of the full
  *   symmetric matrix A (both triangles, sorted columns, diagonal present).
  *   perm: host, n entries, A0[i][j] = A[perm[i]][perm[j]].
@@ -219,7 +219,7 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
                   int32_t* iters, double* relres);
 
 /*
- * FP64 preconditioned MINRES (the Krylov method of the paper's Section 4),
+ * FP64 preconditioned MINRES (the Krylov method of the paper's Section 3),
  * with M^{-1} as the symmetric positive definite preconditioner, x0 = 0.  The
  * iterate minimises ||b - A x||_{M^{-1}} over the preconditioned Krylov space
  * (Paige-Saunders recurrences: three-term Lanczos with M^{-1}, Givens QR of

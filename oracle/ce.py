@@ -26,9 +26,9 @@ for every block row ``i`` of the level, in the elimination order:
    Schur complement into the close neighbours, which creates the far blocks.
 
 After a level the remaining (basis) unknowns of ``2^d`` Morton siblings form
-one super-block of the next level (Section 2.6, eq. (bsp)); when one block is
+one super-block of the next level (Section 2.5, eq. (bsp)); when one block is
 left or the remaining dimension is small the remainder is factored by a
-dense Cholesky (Section 2.7, Proposition 2.1).  The solve is
+dense Cholesky (Section 2.6, Algorithm 1, Proposition 2.1).  The solve is
 ``x = Q^T L^{-T} L^{-1} Q b`` (Proposition 2.2).
 
 Readings where the paper is silent (the same ones the GPU path implements):
@@ -552,7 +552,7 @@ def pcg(A, b, apply_prec, tol=1e-8, maxit=1000):
 
 def minres(A, b, apply_prec, tol=1e-10, maxit=1000):
     """Preconditioned MINRES from ``x0 = 0`` for one column (the Krylov method
-    of the paper's Section 4; Paige-Saunders recurrences).  ``apply_prec`` is
+    of the paper's Section 3; Paige-Saunders recurrences).  ``apply_prec`` is
     ``M^{-1}`` (symmetric positive definite).  The iterate ``x_k`` minimises
     ``||b - A x||_{M^{-1}}`` over the preconditioned Krylov space of
     dimension ``k``.  Stops when that norm (``phibar``) is at most

@@ -14,8 +14,8 @@ Everything here is plain Python over integers, written for readability.
 * Close blocks are the nonzero blocks of the current level matrix
   (Section 2, definition of close/far before Section 2.1).
 * Coarsening joins the ``J = 2^d`` Morton siblings of a level into one
-  super-block (Section 2.6 "combine the blocks into super-blocks", and
-  Section 2.9, Proposition on tensor grids: at least two nodes per direction).
+  super-block (Section 2.5, eq. (bsp), and
+  Section 2.8, Proposition 2.4 on tensor grids: at least two nodes per direction).
 * Far blocks are created by the Schur complement of an elimination step
   between two close neighbours of the eliminated block that are not close to
   each other (eq. (A_st) and the remark after eq. (sm_L): the far pattern is

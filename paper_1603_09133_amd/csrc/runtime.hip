@@ -525,6 +525,15 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       dropped += ed[i];
       minpiv = std::min(minpiv, mp[i]);
     }
+    // optional progress report per level (environment CAE_VERBOSE=1)
+    static const bool verbose = getenv("CAE_VERBOSE") != nullptr;
+    if (verbose) {
+      int64_t rs = 0;
+      for (int32_t i = 0; i < L.M; ++i) rs += N.ranks[i];
+      fprintf(stderr, "[cae] level %d: %d blocks, b max %d, dim %lld -> %lld kept, %d waves, %.1f ms\n", l + 1, L.M,
+              N.bmax, (long long)N.dim, (long long)rs, L.nwaves,
+              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
     if (h->opt.timing) {
       for (size_t k = 0; k < evs.size(); k += 2) {
         float ms = 0;
@@ -603,8 +612,20 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
   return CAE_OK;
 }
 
+// The captured solver applies bake in the addresses of the work vectors:
+// whenever those are released and allocated again, every graph is dropped
+// (the next solver apply runs eagerly and captures afresh).
+void drop_graphs(cae_factor_s* h) {
+  for (auto& g : h->ap) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = cae_factor_s::ApGraph{};
+  }
+  h->ap_next = 0;
+}
+
 void ensure_vectors(cae_factor_s* h, int32_t nrhs) {
   if (h->vec_nrhs >= nrhs && (int)h->ybuf.size() == h->K + 1) return;
+  drop_graphs(h);
   h->ybuf.clear();
   h->wbuf.clear();
   h->obuf.clear();
@@ -722,6 +743,7 @@ void solver_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, d
   // graph costs more than a couple of replays save (a factor used for one
   // short solve never captures)
   constexpr int32_t kEagerApplies = 3;
+  ensure_vectors(h, nrhs);   // (may drop every graph: before the lookup)
   cae_factor_s::ApGraph* hit = nullptr;
   for (auto& g : h->ap)
     if (g.uses > 0 && g.nrhs == nrhs && g.r == r && g.z == z && g.ldr == ldr && g.ldz == ldz) hit = &g;
@@ -745,7 +767,6 @@ void solver_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, d
     return;
   }
   if (!hit->exec) {
-    ensure_vectors(h, nrhs);
     if (!h->ap_stream) HIPCHK(hipStreamCreateWithFlags(&h->ap_stream, hipStreamNonBlocking));
     hipStream_t keep = h->stream;
     h->stream = h->ap_stream;

@@ -2,7 +2,7 @@
 //
 // Everything here is integer work on the block graph:
 //   * the initial permutation of a tensor grid: patches in Z (Morton) order
-//     (Section 2, eq. (init_perm); Section 2.9 on the choice of P);
+//     (Section 2, eq. (init_perm); Section 2.8 on the choice of P);
 //   * the close pattern of every level (structural nonzero blocks);
 //   * the elimination order (block order, or a distance-2 colouring) and the
 //     dependency waves: two steps whose blocks are at graph distance <= 2
@@ -13,7 +13,7 @@
 //     neighbours of the eliminated block that are not close to each other;
 //     a block whose far row is empty when it is processed is eliminated
 //     whole (Section 2.1) and leaves the graph (Section 2.4, node 1);
-//   * the coarsening of 2^d Morton siblings into super-blocks (Section 2.6);
+//   * the coarsening of 2^d Morton siblings into super-blocks (Section 2.5, eq. (bsp));
 //   * the work lists of the numeric kernels (slots, views, Schur targets).
 #include "symbolic.h"
 

@@ -14,7 +14,7 @@ boundary nodes are not unknowns, mesh factor h^2 removed):
   harmonic-mean stencil and ``k = exp(g)``, ``g`` a Gaussian random field with
   squared-exponential covariance, sampled exactly through the separable
   Kronecker factorisation of the covariance.
-* ``anisotropic_diffusion_3d(n)``: the paper's test problem of Section 4:
+* ``anisotropic_diffusion_3d(n)``: the paper's test problem of Section 3:
   3D ``div(k grad u)`` on the unit cube with ``k = diag(x1^2+0.5, x2^2+0.5,
   x3^2+0.5)`` (equidistant grid, face-centred coefficients).
 
@@ -117,7 +117,7 @@ def grf_diffusion_2d(n: int, length: float = 0.05, sigma: float = 1.0,
 
 
 def anisotropic_diffusion_3d(n) -> sp.csr_matrix:
-    """The paper's Section 4 problem, div(k grad u)=f on [0,1]^3, Dirichlet,
+    """The paper's Section 3 problem, div(k grad u)=f on [0,1]^3, Dirichlet,
     k = diag(x1^2+0.5, x2^2+0.5, x3^2+0.5), on the equidistant interior grid
     ``n`` (an int for n^3, or ``(n1, n2, n3)``, x fastest; spacing h_a =
     1/(n_a+1) per axis).  Written with the sign that makes the matrix SPD;

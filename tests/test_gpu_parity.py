@@ -258,6 +258,58 @@ def test_solver_apply_graph_replays_equal_eager_launches():
     assert np.array_equal(_from_gpu_cols(xg), _from_gpu_cols(xe))
 
 
+def test_graphs_dropped_when_work_vectors_grow():
+    """A captured solver apply holds the addresses of the handle's work
+    vectors.  An apply with more right-hand sides releases and reallocates
+    them (the old blocks go back to the device cache, where another
+    factorization can take them); the next PCG must capture afresh instead of
+    replaying into released memory, and stay bitwise equal to eager launches."""
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((96, 80), (8, 8))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    vals = torch.from_numpy(csr[2]).cuda()
+    fg = cae.Factor(an, vals, 1e-3, precision=cae.FP32, coarse_max_dim=0)
+    fe = cae.Factor(an, vals, 1e-3, precision=cae.FP32, coarse_max_dim=0, graphs=False)
+    b = _to_gpu_cols(problems.rhs_normal(A.shape[0], 1, seed=7))
+    xg, itg, _ = fg.pcg(b, rtol=1e-11)
+    assert int(itg[0]) > 4   # enough applies to capture and replay a graph
+    fg.apply(_to_gpu_cols(problems.rhs_normal(A.shape[0], 16, seed=8)))
+    other = cae.Factor(an, vals, 1e-5, precision=cae.FP32, coarse_max_dim=0)
+    other.apply(_to_gpu_cols(problems.rhs_normal(A.shape[0], 16, seed=9)))
+    for f in (fg, fe):
+        f.pcg(b, rtol=1e-11)
+    xg, itg, relg = fg.pcg(b, rtol=1e-11)
+    xe, ite, rele = fe.pcg(b, rtol=1e-11)
+    other.close()
+    assert itg.tolist() == ite.tolist()
+    assert np.array_equal(_from_gpu_cols(xg), _from_gpu_cols(xe))
+    assert np.all(relg <= 1.0001e-11)
+
+
+def test_solvers_report_no_convergence_at_maxit():
+    """maxit = 1 on a system that needs more iterations: PCG and MINRES
+    return CAE_ENOCONV through the C ABI (the iterate of the last iteration
+    is kept, iters = maxit, the true residual is reported)."""
+    import ctypes as C
+    cae = _cae()
+    A, csr, perm, bp, co = _setup((64, 48), (8, 8))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    f = cae.Factor(an, torch.from_numpy(csr[2]).cuda(), 1e-2, coarse_max_dim=0)
+    n = A.shape[0]
+    b = _to_gpu_cols(problems.rhs_normal(n, 2, seed=3))
+    x = torch.empty_like(b)
+    it = np.zeros(2, np.int32)
+    rel = np.zeros(2)
+    for fn in (cae.lib().cae_pcg_solve, cae.lib().cae_minres_solve):
+        rc = fn(f._h, 2, b.data_ptr(), n, x.data_ptr(), n, C.c_double(1e-12), 1, it.ctypes.data, rel.ctypes.data)
+        assert rc == -4, rc
+        assert b"did not converge" in cae.lib().cae_last_error()
+        assert it.tolist() == [1, 1]
+        assert np.all(rel > 1e-12) and np.all(rel < 1.0)
+    xx, it2, rel2 = f.pcg(b, rtol=1e-12, maxit=1)
+    assert not f.converged and it2.tolist() == [1, 1]
+
+
 def test_indefinite_matrix_reports_not_spd():
     cae = _cae()
     A, csr, perm, bp, co = _setup((16, 16), (4, 4))

@@ -68,7 +68,80 @@ def test_mlp_gradient_finite_differences():
         fd = (L.mlp_loss_grad(pp, X, y)[0] - L.mlp_loss_grad(pm, X, y)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
     assert np.all(g[:L.OFF_W1] == 0.0)
-    assert np.allclose(L.mlp_forward(p, X), X.shape[0] * 0 + L.mlp_forward(p, X))
+    # the loss evaluates the same network as the forward pass: zero at the
+    # forward pass's own outputs, 0.5 mean(z^2) against zero targets
+    z = L.mlp_forward(p, X)
+    assert L.mlp_loss_grad(p, X, z)[0] == 0.0
+    assert abs(L.mlp_loss_grad(p, X, np.zeros(20))[0] - 0.5 * np.mean(z * z)) <= 1e-14 * np.mean(z * z)
+
+
+def _hand_network():
+    """A network with a handful of nonzero parameters whose output is worked
+    out by hand below (normalisation (x - mean) / std, then W1 indexed
+    [hidden][feature], ReLU, W2 indexed [out][in], ReLU, w3, b3)."""
+    p = np.zeros(L.NPARAM, dtype=np.float32)
+    p[L.OFF_STD:L.OFF_W1] = 1.0
+    p[L.OFF_MEAN + 3], p[L.OFF_STD + 3] = 1.0, 2.0
+    p[L.OFF_MEAN + 7], p[L.OFF_STD + 7] = -2.0, 0.5
+    W1 = lambda h, f: L.OFF_W1 + h * L.NFEAT + f
+    p[W1(0, 3)] = 1.0
+    p[W1(1, 7)] = -1.0
+    p[W1(2, 3)] = 1.0
+    p[W1(2, 7)] = 1.0
+    p[L.OFF_B1 + 0], p[L.OFF_B1 + 1], p[L.OFF_B1 + 2] = 0.5, 0.25, -1.0
+    W2 = lambda o, i: L.OFF_W2 + o * L.H + i
+    p[W2(0, 0)], p[W2(0, 1)], p[W2(1, 0)], p[W2(5, 2)] = 2.0, 3.0, 1.0, 4.0
+    p[L.OFF_B2 + 1] = -1.0
+    p[L.OFF_W3 + 0], p[L.OFF_W3 + 1], p[L.OFF_W3 + 5] = 1.0, 10.0, -0.5
+    p[L.OFF_B3] = 0.125
+    return p
+
+
+def test_mlp_forward_hand_worked_network():
+    """Input 1: x3 = 5, x7 = -1.5 -> normalised 2, 1 -> hidden-1 (2.5, 0, 2)
+    -> hidden-2 h0 = 2*2.5 = 5, h1 = 2.5 - 1 = 1.5, h5 = 4*2 = 8 -> z = 5 +
+    15 - 4 + 0.125 = 16.125.  Input 2: x3 = -3, x7 = -2.25 -> normalised -2,
+    -0.5 -> hidden-1 (0, 0.75, 0) -> hidden-2 h0 = 2.25 -> z = 2.375.  The
+    other features carry zero weights."""
+    p = _hand_network()
+    X = np.full((2, L.NFEAT), 7.0)
+    X[0, 3], X[0, 7] = 5.0, -1.5
+    X[1, 3], X[1, 7] = -3.0, -2.25
+    assert np.array_equal(L.mlp_forward(p, X), np.array([16.125, 2.375]))
+
+
+def test_features_of_a_constructed_far_row():
+    """A 4 x 6 far row of three far blocks of widths 2, 3, 1 with squared
+    Frobenius norms 8 (all ones), 9 (one entry 3) and 0.01 (one entry 0.1):
+    the whole row has ||F||_F^2 = 17.01, the largest block norm is 3 and two
+    of the three blocks exceed theta = 0.5.  The expected features are the
+    definitions evaluated on these norms (not on F)."""
+    F = np.zeros((4, 6))
+    F[:, 0:2] = 1.0
+    F[0, 2] = 3.0
+    F[2, 5] = 0.1
+    x = L.features(F, 0.5, level=2, nclose=5, nfar=3, nfar_proc=2, proc_rank_sum=6, proc_size_sum=8,
+                   widths=[2, 3, 1])
+    fro = math.sqrt(17.01)
+    want = [math.log2(5), math.log2(7), 2, 3, 5,
+            math.log10(fro / 0.5), math.log10(fro / 2 / 0.5), math.log10(6.0), math.log10(fro / math.sqrt(6) / 0.5),
+            2 / 3, (64 + 81 + 1e-4) / 17.01 ** 2, 17.01 / 27, 2 / 3, 0.75, 4 / 64, 1.0]
+    assert np.allclose(x, want, rtol=1e-13, atol=1e-15)
+    # invariant under orthogonal changes of basis inside a far block's
+    # columns and inside the rows (kept bases are defined up to rotations)
+    rng = np.random.default_rng(0)
+    Qr, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    Qa, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+    Qb, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    G = Qr @ F
+    G[:, 0:2] = G[:, 0:2] @ Qa
+    G[:, 2:5] = G[:, 2:5] @ Qb
+    y = L.features(G, 0.5, level=2, nclose=5, nfar=3, nfar_proc=2, proc_rank_sum=6, proc_size_sum=8,
+                   widths=[2, 3, 1])
+    assert np.allclose(y, x, rtol=1e-12, atol=1e-13)
+    # a row far below theta clips its logarithms at -30
+    z = L.features(F * 1e-40, 0.5, 2, 5, 3, 2, 6, 8, widths=[2, 3, 1])
+    assert z[5] == z[6] == z[7] == z[8] == -30.0
 
 
 def _low_rank_far_row(b, w, ranks_sig, seed):

@@ -1,4 +1,4 @@
-"""Pins of the oracle's MINRES and of the paper's Section 4 problem.
+"""Pins of the oracle's MINRES and of the paper's Section 3 problem.
 
 MINRES is fixed by its definition: the k-th iterate minimises the residual
 norm over a Krylov space.  Brute force on small matrices (explicit Krylov

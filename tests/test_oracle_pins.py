@@ -254,6 +254,7 @@ def test_level_counts_64x64(order):
     coords = co
     # close pairs of the 5-point (level 1) and at most the 9-point graph later
     bound_close = [480, 210, 42, 6]
+    Ms = [M]
     for lev in range(4):
         assert len(pairs) == bound_close[lev] if lev == 0 else len(pairs) <= bound_close[lev]
         adj = adjacency(M, pairs)
@@ -269,9 +270,20 @@ def test_level_counts_64x64(order):
         assert set(far) <= d2
         if lev == 0:
             assert len(d2) == _far_superset_count_2d(16) == 898
+        prev = np.asarray(coords)
         parent, coords = coarsen(coords)
+        # every super-block joins exactly the 2^2 Morton siblings: the blocks
+        # whose patch coordinates agree after dropping the lowest bit
+        for P in range(int(parent.max()) + 1):
+            kids = np.flatnonzero(parent == P)
+            assert len(kids) == 4 and np.all(np.diff(kids) == 1)
+            assert np.all((prev[kids] >> 1) == coords[P])
+            assert sorted(map(tuple, prev[kids] & 1)) == [(0, 0), (0, 1), (1, 0), (1, 1)]
         pairs = coarse_pattern(parent, live_pairs(sorted(set(pairs) | set(far)), removed))
         M = int(parent.max()) + 1
+        Ms.append(M)
+    # 16^2 patches -> 8^2 -> 4^2 -> 2^2 -> 1 (J = 4 siblings per level)
+    assert Ms == [256, 64, 16, 4, 1]
 
 
 def test_far_blocks_are_in_block_pattern_of_A_squared():
