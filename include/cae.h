@@ -17,8 +17,9 @@
  *
  * Conventions for every entry point:
  *   - Return value: 0 (CAE_OK) or a negative cae_status_t.  On error no
- *     output handle is created and nothing leaks; cae_last_error() returns a
- *     description (thread-local, valid until the next call on the thread).
+ *     output handle is created and nothing leaks; cae_last_error(NULL)
+ *     returns a description (thread-local), cae_last_error(h) the last one of
+ *     a call on handle h.
  *   - "host" pointers are read during the call only and never retained.
  *   - "device" pointers are HIP device memory owned by the caller.  They
  *     must stay valid until the call returns; work is issued on the stream
@@ -100,6 +101,13 @@ typedef struct {
                               (step, close block), larger waves one workgroup per step;
                               0 = always one workgroup per step.  Only the order of the
                               FP64 sums in the backward pass differs */
+  void* workspace;         /* DEVICE or NULL: caller-owned arena (256-byte aligned) that
+                              holds every device buffer of the numeric factorization (level
+                              blocks, bases, factors, dense remainder, scratch), so that
+                              cae_factor_numeric allocates no device memory; it must outlive
+                              the handle.  Size it with cae_workspace_query.  The analysis'
+                              own device arrays and the solvers' work vectors are not in it */
+  size_t workspace_bytes;  /* size of workspace */
 } cae_options_t;
 
 #define CAE_RECORD_WIDTH 17
@@ -198,6 +206,34 @@ void cae_analysis_destroy(cae_analysis_t a);
 int cae_factor_numeric(cae_analysis_t a, const double* vals, double eps,
                        const cae_options_t* opt, cae_handle_t* out);
 
+/*
+ * Bytes of device workspace a cae_factor_numeric of these values and options
+ * carves when given cae_options_t.workspace (the options' own workspace fields
+ * are ignored here).  The level sizes after the first depend on the ranks, so
+ * the figure is exact for these values: the call runs the factorization with
+ * the library's own memory, counts, and releases it.  It also uploads the
+ * analysis' device arrays, which a factorization into a workspace requires.
+ *   vals: DEVICE, as for cae_factor_numeric.  bytes: host, one size_t.
+ *   Errors: as cae_factor_numeric.  A factorization whose workspace is too
+ *   small returns CAE_ENOMEM and names the bytes it had reached.
+ */
+int cae_workspace_query(cae_analysis_t a, const double* vals, double eps, const cae_options_t* opt,
+                        size_t* bytes);
+
+/*
+ * One call from the statement of the problem (Section 2: A x = b with A sparse
+ * SPD, the permutation P of eq. (init_perm), the block size, the tolerance; the
+ * result A ~ Q^T L L^T Q of Proposition 2.1): cae_analyze followed by
+ * cae_factor_numeric.  Arguments as for cae_analyze, plus vals: HOST, row_ptr[n]
+ * FP64 values in the CSR order (copied to the device), and eps.  The handle
+ * owns the analysis (cae_destroy releases both); with cae_options_t.workspace
+ * the numeric factorization is carved from it as in cae_factor_numeric.
+ */
+int cae_factor(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+               const int32_t* perm, const int32_t* block_ptr, int32_t nblocks, int32_t B,
+               const int32_t* coords, int32_t ndim, double eps, const cae_options_t* opt,
+               cae_handle_t* out);
+
 /* z = M^{-1} r, M = Q^T L L^T Q (Proposition 2.2).  r, z: device, n x nrhs. */
 int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr,
                       double* z, int64_t ldz);
@@ -244,20 +280,52 @@ typedef struct {
   /* with cae_options_t.timing: the compression kernels (far row -> U_i, r_i) */
   int32_t compress_launches;
   double compress_ms;       /* summed device time of those launches */
-  double compress_flops;    /* algorithmic flops: per far row b x w,
+  double compress_flops;    /* (always counted) algorithmic flops: per far row b x w,
                                2 w b^2 - 2 b^3 / 3 (QR, w >= b; else 2 b w^2 - 2 w^3 / 3)
                                + 12 b^3 (SVD of the triangular factor) */
   int32_t compressions;     /* far rows compressed (steps with a non-empty far row) */
   int32_t sketch_accepted;  /* LEARNED: steps the sketch settled */
   int32_t sketch_rejected;  /* LEARNED: steps that failed the check and took the exact SVD */
   int64_t record_rows;      /* rows written to cae_options_t.record */
+  /* algorithmic flops of the other block operations of the factorization, from
+     the recorded sizes and ranks (b = b_i, r = r_i, n = b - r, s_c live widths
+     of the close blocks, w far width; see compress_flops for the compression):
+     rotation 4 b^3 + 2 b^2 sum_c b_c + 2 r b w (steps with a far row),
+     elimination n^3 / 3 + n^2 (r + sum_c s_c), Schur sum_{a <= c} 2 n s_a s_c
+     over the panel widths {r, s_c}, dense remainder dim^3 / 3 */
+  double rotate_flops;
+  double elim_flops;
+  double schur_flops;
+  double coarse_flops;
 } cae_stats_t;
 
 int cae_get_stats(cae_handle_t h, cae_stats_t* s);
+/* Host wall time of one level of the last factorization (level < K: from the
+ * end of the previous level until its ranks were read back; level = K: the
+ * dense remainder and the final read-backs).  The levels sum to factor_ms. */
+int cae_get_level_ms(cae_handle_t h, int32_t level, double* ms);
 /* Ranks r_i of a factored level (host, M entries, block index order). */
 int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks);
 /* Block sizes b_i of a factored level (host, M entries). */
 int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes);
+/*
+ * Write the factor to a file for parity checks and offline inspection
+ * (little-endian binary; T = float or double as the factor's precision, int32
+ * unless noted): "CAEFACT1"; esize (4 | 8), K; int64 n, int64 coarse_dim;
+ * double tau; perm[n]; then per factored level l < K: M, nslots; sizes[M],
+ * ranks[M]; slot_p[nslots], slot_q[nslots]; int64 slot_off[nslots + 1]; T
+ * arena[slot_off[nslots]] (the in-place factor: slot (p, q), p <= q, is a
+ * row-major b_p x b_q block; after step i the rows n_i = b_i - r_i (trailing)
+ * of block i's close views hold L(c, n_i)^T and the trailing n_i x n_i part of
+ * the diagonal slot L_nn, lower triangle); int64 u_off[M + 1]; T U[u_off[M]]
+ * (U_i row-major b_i x b_i, columns by decreasing singular value); T
+ * Li[u_off[M]] (L_nn^{-1}, n_i x n_i, row-major); parent[M],
+ * off_in_parent[M] (where block i's r_i basis unknowns sit in the next level);
+ * order[M] (elimination order); finally the dense remainder A_K and -A_K^{-1}
+ * (double, coarse_dim^2 each, row-major).  Errors: CAE_EINVAL when the file
+ * cannot be written.
+ */
+int cae_export_factor(cae_handle_t h, const char* path);
 void cae_destroy(cae_handle_t h);
 
 /*
@@ -282,7 +350,11 @@ int cae_mlp_loss_grad(const float* params, const float* records, int64_t n, floa
 /* z for every record (DEVICE, n floats), FP64 arithmetic as in the factorization. */
 int cae_mlp_predict(const float* params, const float* records, int64_t n, float* z, void* stream);
 
-const char* cae_last_error(void);
+/* Message of the last failing call: h = NULL gives the calling thread's last
+ * failure (any entry point, valid until the thread's next failing call);
+ * otherwise the last failure of a call on that handle (empty if none), valid
+ * until the handle's next failing call or its destruction. */
+const char* cae_last_error(cae_handle_t h);
 
 #ifdef __cplusplus
 }

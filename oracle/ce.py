@@ -43,6 +43,8 @@ from __future__ import annotations
 import itertools
 from dataclasses import dataclass, field
 
+import time
+
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
@@ -77,6 +79,9 @@ class CEOptions:
     coarse_max_dim: int = 2048
     max_levels: int = 0             # 0 = no limit
     keep_far_rows: bool = False     # record F_i of every step (tests only)
+    dense_remainder: bool = True    # False: stop after the levels (bounded timing samples only)
+    max_steps: int = 0              # > 0: only the first max_steps steps of level 1 and nothing
+                                    # after them (bounded timing samples only)
 
 
 @dataclass
@@ -96,6 +101,7 @@ class LevelFactor:
     panel: list = field(default_factory=list)       # dict x -> rows_x x n_i
     parent: np.ndarray = None
     min_pivot: float = np.inf
+    seconds: float = 0.0            # wall time of the level (timing of bounded samples)
     features: list = field(default_factory=list)    # learned: features of every compressed step
     exact_rank: list = field(default_factory=list)  # learned: the exact-SVD rank of that step
     label: list = field(default_factory=list)       # learned: sketch width an ideal sketch needs
@@ -192,7 +198,9 @@ def _factor_level(level_no, sizes, W: _Blocks, close_pairs, order, theta, opts):
     lf.features = [None] * M
     lf.exact_rank = [None] * M
     lf.label = [None] * M
-    for i in order:
+    for step_no, i in enumerate(order):
+        if opts.max_steps and step_no >= opts.max_steps:
+            break
         b = int(sizes[i])
         fl = sorted(far[i])
         # 1. far row F_i (full block widths; eliminated columns are zero)
@@ -363,7 +371,13 @@ def ce_factor(indptr, indices, data, perm, block_ptr, coords, opts: CEOptions, J
             break
         adj = sym.adjacency(M, close_pairs)
         order = sym.element_order(adj, opts.order, coords)
+        t_level = time.perf_counter()
         lf = _factor_level(level_no, sizes, W, close_pairs, order, theta, opts)
+        lf.seconds = time.perf_counter() - t_level
+        if opts.max_steps:
+            levels.append(lf)
+            return CEFactor(N=N, perm=perm, block_ptr=block_ptr, theta=theta, levels=levels,
+                            coarse_L=None, coarse_sizes=np.asarray(sizes))
         axis = None
         if opts.coarsen == "pairs" and coords is not None:
             axis = (level_no - 1) % np.asarray(coords).shape[1]
@@ -375,6 +389,9 @@ def ce_factor(indptr, indices, data, perm, block_ptr, coords, opts: CEOptions, J
         close_pairs = sym.coarse_pattern(parent, all_pairs)
         sizes, W = _next_level(sizes, lf.r, W, parent, Mn, lf.removed)
         level_no += 1
+    if not opts.dense_remainder:
+        return CEFactor(N=N, perm=perm, block_ptr=block_ptr, theta=theta, levels=levels,
+                        coarse_L=None, coarse_sizes=np.asarray(sizes))
     # dense Cholesky of the remainder
     offs = np.concatenate([[0], np.cumsum(sizes)])
     dim = int(offs[-1])

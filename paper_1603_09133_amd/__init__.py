@@ -64,9 +64,12 @@ def graph_order(indptr, indices, B):
 
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
              coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None,
-             compensate=False, graphs=True, apply_split_steps=None):
+             compensate=False, graphs=True, apply_split_steps=None, workspace=None):
     o = _lib.Options()
     lib().cae_default_options(C.byref(o))
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
     o.compensate = 1 if compensate else 0
     o.graphs = 1 if graphs else 0
     if apply_split_steps is not None:
@@ -172,14 +175,17 @@ class Factor:
 
     def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
                  max_levels=0, coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0,
-                 record=None, compensate=False, graphs=True, apply_split_steps=None):
+                 record=None, compensate=False, graphs=True, apply_split_steps=None, workspace=None):
         """``rank_mode=RANK_LEARNED`` needs ``mlp_params`` (float32 CUDA tensor of
         ``learned.param_count()`` entries); ``record`` (float32 CUDA tensor of
         shape ``(rows, RECORD_WIDTH)``) receives the training records;
         ``graphs=False`` makes the iterative solvers launch the apply kernels
         one by one instead of replaying a captured HIP graph;
         ``apply_split_steps`` overrides the wave size below which the apply
-        updates close blocks one workgroup per (step, block) (0 = never)."""
+        updates close blocks one workgroup per (step, block) (0 = never);
+        ``workspace`` (a 256-byte aligned CUDA tensor of at least
+        :func:`workspace_bytes` bytes, kept alive by the factor) holds every
+        device buffer of the numeric factorization."""
         import torch
         if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.float64):
             raise TypeError("vals must be a float64 CUDA tensor")
@@ -190,12 +196,13 @@ class Factor:
         self.analysis = analysis
         self.n = analysis.n
         self._stream = stream
-        self._keep = (mlp_params, record)
+        self._keep = (mlp_params, record, workspace)
         sptr = None if stream is None else stream.cuda_stream
         self._opts = _options(order=analysis.order, precision=precision, rank_mode=rank_mode,
                               fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
                               stream=sptr, timing=timing, mlp_params=mlp_params, seed=seed, record=record,
-                              compensate=compensate, graphs=graphs, apply_split_steps=apply_split_steps)
+                              compensate=compensate, graphs=graphs, apply_split_steps=apply_split_steps,
+                              workspace=workspace)
         h = C.c_void_p()
         self._vals = vals.contiguous()
         check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),
@@ -206,6 +213,17 @@ class Factor:
         s = _lib.Stats()
         check(lib().cae_get_stats(self._h, C.byref(s)))
         return {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
+
+    def level_ms(self):
+        """Host wall time of every factored level and of the dense remainder
+        (``cae_get_level_ms``, K + 1 values)."""
+        K = self.stats()["nlevels"]
+        out = []
+        for l in range(K + 1):
+            v = C.c_double()
+            check(lib().cae_get_level_ms(self._h, l, C.byref(v)))
+            out.append(v.value)
+        return out
 
     def ranks(self, level):
         M = self.analysis.level_info(level)["M"]
@@ -264,6 +282,11 @@ class Factor:
         self.converged = rc == _lib.CAE_OK
         return (x.reshape(-1) if sq else x), it, rel
 
+    def export(self, path):
+        """Write the factor to ``path`` (``cae_export_factor``); read it back
+        with :func:`read_export`."""
+        check(lib().cae_export_factor(self._h, str(path).encode()))
+
     def solve(self, b):
         """Direct approximate solve ``x = M^{-1} b`` (CE(eps) used as a direct
         solver, no Krylov iterations)."""
@@ -279,3 +302,75 @@ class Factor:
             self.close()
         except Exception:
             pass
+
+
+def workspace_bytes(analysis: Analysis, vals, eps, **opts):
+    """Device bytes a :class:`Factor` of these values and options takes from a
+    ``workspace`` (``cae_workspace_query``: the factorization is run once with
+    the library's own memory and counted)."""
+    o = _options(order=analysis.order, **opts)
+    nb = C.c_size_t()
+    check(lib().cae_workspace_query(analysis.handle, vals.data_ptr(), float(eps), C.byref(o), C.byref(nb)))
+    return nb.value
+
+
+class OneCallFactor(Factor):
+    """``cae_factor``: analysis and numeric factorization in one call from a
+    host CSR matrix (the handle owns its analysis)."""
+
+    def __init__(self, indptr, indices, data, perm, block_ptr, coords, eps, order=ORDER_MULTICOLOUR,
+                 precision=FP64, coarse_max_dim=2048, workspace=None):
+        ip, ix = _i64(indptr), _i32(indices)
+        dv = np.ascontiguousarray(data, dtype=np.float64)
+        pm, bp, co = _i32(perm), _i32(block_ptr), _i32(coords)
+        ndim = co.shape[1] if co.ndim == 2 else 1
+        self.analysis = None
+        self.n = len(ip) - 1
+        self._stream = None
+        self._keep = (workspace,)
+        self._opts = _options(order=order, precision=precision, coarse_max_dim=coarse_max_dim, workspace=workspace)
+        h = C.c_void_p()
+        check(lib().cae_factor(self.n, ptr(ip), ptr(ix), ptr(dv), ptr(pm), ptr(bp), len(bp) - 1, 0, ptr(co), ndim,
+                               float(eps), C.byref(self._opts), C.byref(h)))
+        self._h = h
+
+
+def read_export(path):
+    """Parse a file written by ``cae_export_factor`` into NumPy arrays (the
+    layout is documented with ``cae_export_factor`` in ``include/cae.h``)."""
+    buf = open(path, "rb").read()
+    pos = 0
+
+    def take(dtype, count):
+        nonlocal pos
+        a = np.frombuffer(buf, dtype=dtype, count=count, offset=pos)
+        pos += a.nbytes
+        return a.copy()
+
+    if buf[:8] != b"CAEFACT1":
+        raise ValueError("not a CAE factor export")
+    pos = 8
+    esize, K = take(np.int32, 2)
+    n, coarse_dim = take(np.int64, 2)
+    tau = float(take(np.float64, 1)[0])
+    T = np.float64 if esize == 8 else np.float32
+    out = {"esize": int(esize), "K": int(K), "n": int(n), "coarse_dim": int(coarse_dim), "tau": tau,
+           "perm": take(np.int32, n), "levels": []}
+    for _ in range(K):
+        M, ns = take(np.int32, 2)
+        lv = {"sizes": take(np.int32, M), "ranks": take(np.int32, M), "slot_p": take(np.int32, ns),
+              "slot_q": take(np.int32, ns), "slot_off": take(np.int64, ns + 1)}
+        lv["arena"] = take(T, int(lv["slot_off"][-1]))
+        lv["u_off"] = take(np.int64, M + 1)
+        lv["U"] = take(T, int(lv["u_off"][-1]))
+        lv["Li"] = take(T, int(lv["u_off"][-1]))
+        lv["parent"] = take(np.int32, M)
+        lv["off_in_parent"] = take(np.int32, M)
+        lv["order"] = take(np.int32, M)
+        out["levels"].append(lv)
+    d = int(coarse_dim)
+    out["A_K"] = take(np.float64, d * d).reshape(d, d)
+    out["neg_inv_A_K"] = take(np.float64, d * d).reshape(d, d)
+    if pos != len(buf):
+        raise ValueError("trailing bytes in the export")
+    return out

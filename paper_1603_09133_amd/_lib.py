@@ -34,7 +34,8 @@ class Options(C.Structure):
                 ("timing", C.c_int32), ("compensate", C.c_int32),
                 ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p), ("mlp_params", C.c_void_p),
                 ("seed", C.c_uint64), ("record", C.c_void_p), ("record_cap", C.c_int64), ("coarsen", C.c_int32),
-                ("graphs", C.c_int32), ("apply_split_steps", C.c_int32)]
+                ("graphs", C.c_int32), ("apply_split_steps", C.c_int32), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
 
 
 class LevelInfo(C.Structure):
@@ -47,7 +48,8 @@ class Stats(C.Structure):
                 ("dropped_sq", C.c_double), ("min_pivot", C.c_double), ("factor_bytes", C.c_int64),
                 ("factor_ms", C.c_double), ("compress_launches", C.c_int32), ("compress_ms", C.c_double),
                 ("compress_flops", C.c_double), ("compressions", C.c_int32), ("sketch_accepted", C.c_int32),
-                ("sketch_rejected", C.c_int32), ("record_rows", C.c_int64)]
+                ("sketch_rejected", C.c_int32), ("record_rows", C.c_int64), ("rotate_flops", C.c_double),
+                ("elim_flops", C.c_double), ("schur_flops", C.c_double), ("coarse_flops", C.c_double)]
 
 
 _lib = None
@@ -55,9 +57,9 @@ _lib = None
 EXPORTS = [
     "cae_default_options", "cae_last_error", "cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels",
     "cae_analysis_level_info", "cae_analysis_level_arrays", "cae_analysis_perm", "cae_analysis_destroy",
-    "cae_factor_numeric", "cae_apply_precond", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
+    "cae_factor_numeric", "cae_workspace_query", "cae_factor", "cae_apply_precond", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
     "cae_get_stats",
-    "cae_get_ranks", "cae_get_sizes", "cae_destroy", "cae_mlp_param_count", "cae_mlp_train", "cae_mlp_loss_grad",
+    "cae_get_ranks", "cae_get_sizes", "cae_get_level_ms", "cae_export_factor", "cae_destroy", "cae_mlp_param_count", "cae_mlp_train", "cae_mlp_loss_grad",
     "cae_mlp_predict",
 ]
 
@@ -73,7 +75,7 @@ def lib():
     p, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.cae_default_options.argtypes = [C.POINTER(Options)]
     L.cae_default_options.restype = None
-    L.cae_last_error.argtypes = []
+    L.cae_last_error.argtypes = [p]
     L.cae_last_error.restype = C.c_char_p
     L.cae_grid_order.argtypes = [i32, p, p, p, p, p, p]
     L.cae_graph_order.argtypes = [i64, p, p, i32, p, p, p]
@@ -85,6 +87,8 @@ def lib():
     L.cae_analysis_destroy.argtypes = [p]
     L.cae_analysis_destroy.restype = None
     L.cae_factor_numeric.argtypes = [p, p, dbl, C.POINTER(Options), C.POINTER(p)]
+    L.cae_workspace_query.argtypes = [p, p, dbl, C.POINTER(Options), C.POINTER(C.c_size_t)]
+    L.cae_factor.argtypes = [i64, p, p, p, p, p, i32, i32, p, i32, dbl, C.POINTER(Options), C.POINTER(p)]
     L.cae_apply_precond.argtypes = [p, i32, p, i64, p, i64]
     L.cae_apply_factor.argtypes = [p, i32, p, i64, p, i64]
     L.cae_pcg_solve.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
@@ -92,6 +96,8 @@ def lib():
     L.cae_get_stats.argtypes = [p, C.POINTER(Stats)]
     L.cae_get_ranks.argtypes = [p, i32, p]
     L.cae_get_sizes.argtypes = [p, i32, p]
+    L.cae_export_factor.argtypes = [p, C.c_char_p]
+    L.cae_get_level_ms.argtypes = [p, i32, C.POINTER(dbl)]
     L.cae_destroy.argtypes = [p]
     L.cae_destroy.restype = None
     L.cae_mlp_param_count.argtypes = []
@@ -100,9 +106,10 @@ def lib():
     L.cae_mlp_loss_grad.argtypes = [p, p, i64, p, C.POINTER(C.c_float), p]
     L.cae_mlp_predict.argtypes = [p, p, i64, p, p]
     for name in ["cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels", "cae_analysis_level_info",
-                 "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_apply_precond",
+                 "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_workspace_query", "cae_factor",
+                 "cae_apply_precond",
                  "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
-                 "cae_get_sizes", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:
+                 "cae_get_sizes", "cae_get_level_ms", "cae_export_factor", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -110,7 +117,7 @@ def lib():
 
 def check(rc, allow=()):
     if rc != CAE_OK and rc not in allow:
-        raise CAEError(rc, lib().cae_last_error().decode())
+        raise CAEError(rc, lib().cae_last_error(None).decode())
     return rc
 
 

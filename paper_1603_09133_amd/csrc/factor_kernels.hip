@@ -2080,7 +2080,8 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
     const int i = st.blk;
     if (A.need_exact && !A.need_exact[i]) return;   // taken by the sketch kernel
     const int b = A.bsz[i];
-    if (b > BM || b <= BM - 64) return;
+    // size class (BM - 64, BM]; the first class also takes empty blocks
+    if (b > BM || (b <= BM - 64 && !(BM == 64 && b == 0))) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ty = tid >> 4, tx = tid & 15;
     T* Ug = A.U + A.u_off[i];
     if (st.nfar == 0 || b == 0) {

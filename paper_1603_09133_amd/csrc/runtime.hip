@@ -102,44 +102,93 @@ BlockCache& block_cache() {
   return *c;
 }
 
+// A caller-provided device arena (cae_options_t.workspace) of one numeric
+// factorization: while it is installed on the thread, device buffers are
+// carved from it in allocation order (256-byte aligned) instead of taken from
+// the block cache, and releasing a carved buffer gives nothing back (the
+// arena belongs to the caller).  In counting mode (cae_workspace_query) the
+// buffers come from the cache as usual and `used` adds up what the carves
+// would have taken, so a factorization of the same values in an arena of that
+// size carves exactly the same sequence.
+struct Carver {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool counting = false;
+};
+thread_local Carver* g_carve = nullptr;
+
+struct WorkspaceFull {
+  size_t need;
+};
+
 struct DevBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;   // capacity of the block
+  size_t req = 0;     // bytes requested by the last allocation
+  bool carved = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), req(o.req), carved(o.carved) {
     o.p = nullptr;
-    o.bytes = 0;
+    o.bytes = o.req = 0;
+    o.carved = false;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       bytes = o.bytes;
+      req = o.req;
+      carved = o.carved;
       o.p = nullptr;
-      o.bytes = 0;
+      o.bytes = o.req = 0;
+      o.carved = false;
     }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) block_cache().put(p, bytes);
+    if (p && !carved) block_cache().put(p, bytes);
     p = nullptr;
-    bytes = 0;
+    bytes = req = 0;
+    carved = false;
   }
   void alloc(size_t b) {
-    if (b <= bytes && p) return;
-    release();
     if (b == 0) b = 8;
-    p = block_cache().get(b);
-    bytes = b;
+    // (inside a factorization with an arena, or counting for one, a buffer is
+    // reused only up to the size it was requested with, as a carve would be)
+    if (p && b <= (g_carve ? req : bytes)) return;
+    release();
+    const size_t a = (b + 255) & ~(size_t)255;
+    if (g_carve && !g_carve->counting) {
+      if (g_carve->used + a > g_carve->cap) throw WorkspaceFull{g_carve->used + a};
+      p = g_carve->base + g_carve->used;
+      g_carve->used += a;
+      bytes = req = b;
+      carved = true;
+      return;
+    }
+    if (g_carve) g_carve->used += a;
+    size_t cap = b;
+    p = block_cache().get(cap);
+    bytes = cap;
+    req = b;
   }
   template <typename U>
   U* as() const {
     return static_cast<U*>(p);
   }
 };
+
+// Optional check for reads of memory that no kernel has written (environment
+// CAE_DEBUG_POISON=1): floating-point work buffers are filled with all-ones
+// bytes (NaN in FP32 and FP64) when they are handed out, so such a read shows
+// up as NaN in the results instead of depending on what the block held before.
+void poison(DevBuf& d, hipStream_t s) {
+  static const bool on = getenv("CAE_DEBUG_POISON") != nullptr;
+  if (on && d.p) HIPCHK(hipMemsetAsync(d.p, 0xFF, d.bytes, s));
+}
 
 template <typename U>
 void upload(DevBuf& d, const std::vector<U>& h, hipStream_t s) {
@@ -204,11 +253,14 @@ struct NumLevel {
   std::vector<cae::WaveRange> waves;
   DevBuf arena, U, Li, bsz, d_slot_off, d_u_off, d_dof_off, d_off_in_parent, rank, edrop, minpiv;
   DevBuf need_exact;   // learned ranks: steps the exact compression takes
+  double end_ms = 0;   // host time since the factorization began when the level's ranks were back
 };
 
 }  // namespace
 
 struct cae_factor_s {
+  // (declared first, destroyed last: the analysis of a one-call cae_factor)
+  std::unique_ptr<cae_analysis_s> owned_an;
   cae_analysis_t an = nullptr;
   int precision = 0;
   size_t esize = 8;
@@ -222,7 +274,8 @@ struct cae_factor_s {
   int64_t factor_bytes = 0;
   int32_t compress_launches = 0, compressions = 0;
   double compress_ms = 0, compress_flops = 0;
-  bool flops_pending = false;   // compress_flops / compressions not yet counted
+  double rotate_flops = 0, elim_flops = 0, schur_flops = 0, coarse_flops = 0;
+  bool flops_pending = false;   // the flop counts are not yet computed
   // apply / multiply / PCG work vectors
   int32_t vec_nrhs = 0;
   std::vector<DevBuf> ybuf, wbuf, obuf;
@@ -246,6 +299,7 @@ struct cae_factor_s {
     int64_t ldr = 0, ldz = 0;
   };
   ApGraph ap[4];
+  std::string last_err;   // message of the last failing call on this handle
   int32_t ap_next = 0;
   hipStream_t ap_stream = nullptr;   // non-blocking stream the captures run on
   ~cae_factor_s() {
@@ -412,6 +466,9 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     N.Li.alloc((size_t)N.u_off[L.M] * sizeof(T));
     N.rank.alloc((size_t)L.M * sizeof(int32_t));
     N.edrop.alloc((size_t)L.M * sizeof(double));
+    poison(N.U, s);
+    poison(N.Li, s);
+    poison(N.edrop, s);
     N.minpiv.alloc((size_t)L.M * sizeof(double));
     cae::launch_fill(N.minpiv.as<double>(), L.M, 1e300, s);
     // per-workgroup global scratch when a kernel's operands exceed the LDS
@@ -423,6 +480,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     if (cae::factor_needs_global<T>(N.bmax)) {
       maxitems = std::min(maxitems, (size_t)cae::scratch_group<T>(N.bmax));
       h->gscratch.alloc(maxitems * cae::factor_scratch_elems<T>(N.bmax) * sizeof(T));
+      poison(h->gscratch, s);
       gs = h->gscratch.as<T>();
     }
     cae::LevelArgs<T> A = level_args<T>(h, l);
@@ -514,6 +572,13 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     HIPCHK(hipMemcpyAsync(he, h->err.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     std::copy(hr, hr + L.M, N.ranks.begin());
+    for (int32_t i = 0; i < L.M; ++i)
+      if (N.ranks[i] < 0 || N.ranks[i] > N.sizes[i]) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "internal: rank %d of block %d (size %d) at level %d was not computed", N.ranks[i],
+                 i, N.sizes[i], l + 1);
+        return fail(CAE_EDEVICE, buf);
+      }
     herr[0] = he[0];
     herr[1] = he[1];
     if (herr[0]) {
@@ -525,6 +590,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       dropped += ed[i];
       minpiv = std::min(minpiv, mp[i]);
     }
+    N.end_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     // optional progress report per level (environment CAE_VERBOSE=1)
     static const bool verbose = getenv("CAE_VERBOSE") != nullptr;
     if (verbose) {
@@ -543,9 +609,6 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
         (void)hipEventDestroy(evs[k]);
         (void)hipEventDestroy(evs[k + 1]);
       }
-      // (the algorithmic flops of the compressions are counted when the
-      // statistics are read, outside the factorization)
-      h->flops_pending = true;
     }
     h->lev.emplace_back();
     NumLevel& Nn = h->lev[l + 1];
@@ -583,16 +646,26 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
     h->gj_p.alloc(2 * 64 * 64 * sizeof(double));   // two pivot inverses (this panel's, the next one's)
     h->gj_w.alloc((size_t)64 * dim * sizeof(double));
     h->gj_r.alloc((size_t)64 * dim * sizeof(double));
+    poison(h->gj_p, s);
+    poison(h->gj_w, s);
+    poison(h->gj_r, s);
     cae::launch_gj_inverse(h->Ainv.as<double>(), dim, h->gj_p.as<double>(), h->gj_w.as<double>(),
                            h->gj_r.as<double>(), h->err.as<int32_t>(), s);
     HIPCHK(hipGetLastError());
   }
-  int32_t herr[2];
-  double th[2];
-  HIPCHK(hipMemcpyAsync(herr, h->err.p, sizeof(herr), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(th, h->theta.p, sizeof(th), hipMemcpyDeviceToHost, s));
+  // error flag and threshold through the pinned read-back buffer
+  char* pin = pinned_readback(2 * sizeof(double) + 2 * sizeof(int32_t));
+  double* th = reinterpret_cast<double*>(pin);
+  int32_t* herr = reinterpret_cast<int32_t*>(th + 2);
+  HIPCHK(hipMemcpyAsync(herr, h->err.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(th, h->theta.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (herr[0]) return fail(CAE_ENOTSPD, "non-SPD pivot in the dense remainder");
+  if (herr[0]) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "non-SPD pivot in the dense remainder (dimension %lld, flag %d, block %d)",
+             (long long)dim, herr[0], herr[1]);
+    return fail(CAE_ENOTSPD, buf);
+  }
   h->tau = th[1];
   h->dropped = dropped;
   h->min_pivot = minpiv;
@@ -602,13 +675,16 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
   bytes += dim * dim * (int64_t)sizeof(double);
   h->factor_bytes = bytes;
   {
-    int32_t lc[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(lc, h->lcount.p, sizeof(lc), hipMemcpyDeviceToHost, s));
+    int32_t* lc = reinterpret_cast<int32_t*>(pinned_readback(2 * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(lc, h->lcount.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     h->sketch_acc = lc[0];
     h->sketch_rej = lc[1];
   }
   h->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  // (the algorithmic flop counts are computed when the statistics are read,
+  // outside the factorization)
+  h->flops_pending = true;
   return CAE_OK;
 }
 
@@ -637,6 +713,9 @@ void ensure_vectors(cae_factor_s* h, int32_t nrhs) {
     h->ybuf[l].alloc(b);
     h->wbuf[l].alloc(b);
     h->obuf[l].alloc(b);
+    poison(h->ybuf[l], g_cur_stream);
+    poison(h->wbuf[l], g_cur_stream);
+    poison(h->obuf[l], g_cur_stream);
   }
   h->ctmp.alloc((size_t)std::max<int64_t>(h->coarse_dim, 1) * nrhs * sizeof(double));
   size_t part = 0;
@@ -646,44 +725,55 @@ void ensure_vectors(cae_factor_s* h, int32_t nrhs) {
         part = std::max(part, cae::ap_part_elems(w, h->lev[l].bmax, nrhs));
   h->apart.release();
   if (part > 0) h->apart.alloc(part * sizeof(double));
+  poison(h->ctmp, g_cur_stream);
+  poison(h->apart, g_cur_stream);
   h->vec_nrhs = nrhs;
 }
 
+// Work vectors of one preconditioner apply: the level vectors y[l]
+// (dim_l x nrhs, l = 0..K), the coarse product (coarse_dim x nrhs) and the
+// partial products of the split backward pass (ap_part_elems of the largest
+// split wave).  Every entry the apply reads has been written by it first.
+struct ApplyBufs {
+  double* const* y;
+  double* ctmp;
+  double* apart;
+};
+
 template <typename T>
-void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
-  hipStream_t s = h->stream;
+void apply_precond(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz,
+                   const ApplyBufs& B, hipStream_t s) {
   const cae::Analysis& a = h->an->a;
-  ensure_vectors(h, nrhs);
-  cae::launch_perm_in(a.n, nrhs, h->an->perm.as<int32_t>(), r, ldr, h->ybuf[0].as<double>(), s);
+  cae::launch_perm_in(a.n, nrhs, h->an->perm.as<int32_t>(), r, ldr, B.y[0], s);
   for (int l = 0; l < h->K; ++l) {
     NumLevel& N = h->lev[l];
     const cae::LevelSym& L = a.levels[l];
     auto A = apply_args<T>(h, l, nrhs);
-    double* y = h->ybuf[l].as<double>();
+    double* y = B.y[l];
     cae::launch_ap_rotate<T>(A, L.M, y, 0, N.bmax, s);
     for (auto& w : N.waves) cae::launch_ap_fwd<T>(A, w, y, N.bmax, h->opt.apply_split_steps, s);
     cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
-                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
-                        h->ybuf[l + 1].as<double>(), 0, s);
+                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y, B.y[l + 1],
+                        0, s);
   }
   const int64_t dim = h->coarse_dim;
   if (dim > 0) {
-    cae::launch_coarse_apply(h->Ainv.as<double>(), dim, nrhs, h->ybuf[h->K].as<double>(), h->ctmp.as<double>(), s);
-    cae::launch_copy_cols(dim * nrhs, 1, h->ctmp.as<double>(), dim * nrhs, h->ybuf[h->K].as<double>(), dim * nrhs, s);
+    cae::launch_coarse_apply(h->Ainv.as<double>(), dim, nrhs, B.y[h->K], B.ctmp, s);
+    cae::launch_copy_cols(dim * nrhs, 1, B.ctmp, dim * nrhs, B.y[h->K], dim * nrhs, s);
   }
   for (int l = h->K - 1; l >= 0; --l) {
     NumLevel& N = h->lev[l];
     const cae::LevelSym& L = a.levels[l];
     auto A = apply_args<T>(h, l, nrhs);
-    double* y = h->ybuf[l].as<double>();
+    double* y = B.y[l];
     cae::launch_to_next(L.M, N.d_dof_off.as<int64_t>(), N.rank.as<int32_t>(), h->an->dlev[l].parent.as<int32_t>(),
-                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y,
-                        h->ybuf[l + 1].as<double>(), 1, s);
+                        N.d_off_in_parent.as<int32_t>(), h->lev[l + 1].d_dof_off.as<int64_t>(), nrhs, y, B.y[l + 1],
+                        1, s);
     for (int w = (int)N.waves.size() - 1; w >= 0; --w)
-      cae::launch_ap_bwd<T>(A, N.waves[w], y, N.bmax, h->apart.as<double>(), h->opt.apply_split_steps, s);
+      cae::launch_ap_bwd<T>(A, N.waves[w], y, N.bmax, B.apart, h->opt.apply_split_steps, s);
     cae::launch_ap_rotate<T>(A, L.M, y, 1, N.bmax, s);
   }
-  cae::launch_perm_out(a.n, nrhs, h->an->perm.as<int32_t>(), h->ybuf[0].as<double>(), z, ldz, s);
+  cae::launch_perm_out(a.n, nrhs, h->an->perm.as<int32_t>(), B.y[0], z, ldz, s);
   HIPCHK(hipGetLastError());
 }
 
@@ -723,11 +813,16 @@ void apply_factor(cae_factor_s* h, int32_t nrhs, const double* x, int64_t ldx, d
   HIPCHK(hipGetLastError());
 }
 
+// The apply with the handle's own work vectors, on the handle's stream.
 void do_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+  ensure_vectors(h, nrhs);
+  std::vector<double*> y(h->K + 1);
+  for (int l = 0; l <= h->K; ++l) y[l] = h->ybuf[l].as<double>();
+  const ApplyBufs B{y.data(), h->ctmp.as<double>(), h->apart.as<double>()};
   if (h->precision != CAE_FP64)
-    apply_precond<float>(h, nrhs, r, ldr, z, ldz);
+    apply_precond<float>(h, nrhs, r, ldr, z, ldz, B, h->stream);
   else
-    apply_precond<double>(h, nrhs, r, ldr, z, ldz);
+    apply_precond<double>(h, nrhs, r, ldr, z, ldz, B, h->stream);
 }
 
 // The apply of an iterative solver: with cae_options_t.graphs, its kernel
@@ -794,6 +889,12 @@ int check_handle(cae_factor_s* h) {
   return CAE_OK;
 }
 
+// A failing call on a handle also leaves its message with the handle.
+int keep_error(cae_factor_s* h, int rc) {
+  if (h && rc != CAE_OK) h->last_err = g_err;
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -813,7 +914,7 @@ void cae_default_options(cae_options_t* opt) {
   opt->stream = nullptr;
 }
 
-const char* cae_last_error(void) { return g_err.c_str(); }
+const char* cae_last_error(cae_handle_t h) { return h ? h->last_err.c_str() : g_err.c_str(); }
 
 int cae_graph_order(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t B, int32_t* perm,
                     int32_t* block_ptr, int32_t* nblocks) {
@@ -915,13 +1016,13 @@ int cae_analysis_perm(cae_analysis_t a, int32_t* perm, int32_t* block_ptr) {
 
 void cae_analysis_destroy(cae_analysis_t a) { delete a; }
 
-int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const cae_options_t* opt,
-                       cae_handle_t* out) {
-  if (!out) return fail(CAE_EINVAL, "out is required");
-  *out = nullptr;
-  if (!an || !vals) return fail(CAE_EINVAL, "analysis and vals are required");
+}  // extern "C"
+
+namespace {
+
+// Options with defaults, validated against the analysis.
+int checked_options(cae_analysis_t an, double eps, const cae_options_t* opt, cae_options_t& o) {
   if (!(eps >= 0.0)) return fail(CAE_EINVAL, "eps must be >= 0");
-  cae_options_t o;
   cae_default_options(&o);
   if (opt) {
     if (opt->struct_size != (int32_t)sizeof(cae_options_t)) return fail(CAE_EINVAL, "options struct_size mismatch");
@@ -937,21 +1038,115 @@ int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const 
     return fail(CAE_EINVAL, "record needs record_cap > 0 and a threshold rank mode");
   if (o.rank_mode == CAE_RANK_FIXED && o.fixed_rank < 0) return fail(CAE_EINVAL, "fixed_rank must be >= 0");
   if (o.order != an->a.order_kind) return fail(CAE_EINVAL, "order differs from the analysis");
+  if (o.workspace && o.workspace_bytes == 0) return fail(CAE_EINVAL, "workspace given with workspace_bytes = 0");
+  return CAE_OK;
+}
+
+// The numeric factorization with validated options; `carve` installs an arena
+// (or a counter) for the handle's device buffers.
+int factor_checked(cae_analysis_t an, const double* vals, double eps, const cae_options_t& o, Carver* carve,
+                   cae_handle_t* out) {
+  struct Uninstall {
+    ~Uninstall() { g_carve = nullptr; }
+  } uninstall;
+  hipStream_t stream = (hipStream_t)o.stream;
   try {
     init_device_limits();
+    g_cur_stream = stream;
+    // the analysis' device arrays belong to the analysis, never to an arena
+    upload_symbolic(an, stream);
+    g_carve = carve;
     std::unique_ptr<cae_factor_s> h(new cae_factor_s);
     h->an = an;
     h->opt = o;
     h->precision = o.precision;
-    h->stream = (hipStream_t)o.stream;
-    g_cur_stream = h->stream;
+    h->stream = stream;
     int rc = o.precision != CAE_FP64 ? factor_numeric<float>(h.get(), vals, eps)
                                      : factor_numeric<double>(h.get(), vals, eps);
+    g_carve = nullptr;
     if (rc != CAE_OK) {
       (void)hipStreamSynchronize(h->stream);
       return rc;
     }
     *out = h.release();
+  } catch (const WorkspaceFull& e) {
+    g_carve = nullptr;
+    (void)hipStreamSynchronize(stream);
+    char buf[200];
+    snprintf(buf, sizeof buf, "workspace of %zu bytes is too small: this factorization needs more than %zu",
+             carve ? carve->cap : (size_t)0, e.need);
+    return fail(CAE_ENOMEM, buf);
+  } catch (const HipError& e) {
+    g_carve = nullptr;
+    (void)hipStreamSynchronize(stream);
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    g_carve = nullptr;
+    return fail(CAE_ENOMEM, "host allocation failed");
+  }
+  return CAE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const cae_options_t* opt,
+                       cae_handle_t* out) {
+  if (!out) return fail(CAE_EINVAL, "out is required");
+  *out = nullptr;
+  if (!an || !vals) return fail(CAE_EINVAL, "analysis and vals are required");
+  cae_options_t o;
+  if (int rc = checked_options(an, eps, opt, o)) return rc;
+  if (!o.workspace) return factor_checked(an, vals, eps, o, nullptr, out);
+  Carver carve;
+  carve.base = static_cast<char*>(o.workspace);
+  carve.cap = o.workspace_bytes;
+  if ((reinterpret_cast<uintptr_t>(carve.base) & 255) != 0) return fail(CAE_EINVAL, "workspace must be 256-byte aligned");
+  return factor_checked(an, vals, eps, o, &carve, out);
+}
+
+int cae_workspace_query(cae_analysis_t an, const double* vals, double eps, const cae_options_t* opt, size_t* bytes) {
+  if (!an || !vals || !bytes) return fail(CAE_EINVAL, "analysis, vals and bytes are required");
+  cae_options_t o;
+  if (int rc = checked_options(an, eps, opt, o)) return rc;
+  o.workspace = nullptr;
+  o.workspace_bytes = 0;
+  Carver count;
+  count.counting = true;
+  cae_handle_t h = nullptr;
+  if (int rc = factor_checked(an, vals, eps, o, &count, &h)) return rc;
+  cae_destroy(h);
+  *bytes = count.used;
+  return CAE_OK;
+}
+
+int cae_factor(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals, const int32_t* perm,
+               const int32_t* block_ptr, int32_t nblocks, int32_t B, const int32_t* coords, int32_t ndim, double eps,
+               const cae_options_t* opt, cae_handle_t* out) {
+  if (!out) return fail(CAE_EINVAL, "out is required");
+  *out = nullptr;
+  if (!vals || !row_ptr) return fail(CAE_EINVAL, "row_ptr and vals are required");
+  cae_analysis_t an = nullptr;
+  if (int rc = cae_analyze(n, row_ptr, col_idx, perm, block_ptr, nblocks, B, coords, ndim, opt, &an)) return rc;
+  std::unique_ptr<cae_analysis_s> own(an);
+  cae_options_t o;
+  if (int rc = checked_options(an, eps, opt, o)) return rc;
+  try {
+    g_cur_stream = (hipStream_t)o.stream;
+    const int64_t nnz = row_ptr[n];
+    DevBuf dv;
+    dv.alloc((size_t)nnz * sizeof(double));
+    HIPCHK(hipMemcpyAsync(dv.p, vals, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice, (hipStream_t)o.stream));
+    cae_handle_t h = nullptr;
+    Carver carve;
+    carve.base = static_cast<char*>(o.workspace);
+    carve.cap = o.workspace_bytes;
+    if (o.workspace && (reinterpret_cast<uintptr_t>(carve.base) & 255) != 0)
+      return fail(CAE_EINVAL, "workspace must be 256-byte aligned");
+    if (int rc = factor_checked(an, dv.as<double>(), eps, o, o.workspace ? &carve : nullptr, &h)) return rc;
+    h->owned_an.reset(own.release());   // the handle owns the analysis it was made with
+    *out = h;
   } catch (const HipError& e) {
     return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
   } catch (const std::bad_alloc&) {
@@ -960,7 +1155,7 @@ int cae_factor_numeric(cae_analysis_t an, const double* vals, double eps, const 
   return CAE_OK;
 }
 
-int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+static int cae_apply_precond_impl(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
   if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
   const int64_t n = h->an->a.n;
@@ -974,7 +1169,7 @@ int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr
   return CAE_OK;
 }
 
-int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
+static int cae_apply_factor_impl(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
   if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
   const int64_t n = h->an->a.n;
@@ -991,7 +1186,7 @@ int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx,
   return CAE_OK;
 }
 
-int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
+static int cae_pcg_solve_impl(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
                   int32_t maxit, int32_t* iters, double* relres) {
   if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
@@ -1006,6 +1201,10 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, do
     h->pz.alloc(vb);
     h->pp.alloc(vb);
     h->pq.alloc(vb);
+    poison(h->pr, s);
+    poison(h->pz, s);
+    poison(h->pp, s);
+    poison(h->pq, s);
     h->sc.alloc((size_t)8 * nrhs * sizeof(double));
     h->act.alloc((size_t)nrhs * sizeof(int32_t));
     h->partial.alloc((size_t)nrhs * 1024 * sizeof(double));
@@ -1082,7 +1281,7 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, do
   return CAE_OK;
 }
 
-int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+static int cae_minres_solve_impl(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
                      double rtol, int32_t maxit, int32_t* iters, double* relres) {
   if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
@@ -1196,35 +1395,69 @@ int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
   return CAE_OK;
 }
 
-// Algorithmic flops of the compressions of every factored level (the model
-// of the compression's work: QR-equivalent of the b x w far row plus 12 b^3
-// for the SVD), from the recorded sizes and ranks.
-void count_compress_flops(cae_factor_s* h) {
-  h->compress_flops = 0;
+// Algorithmic flops of the block operations of every factored level (the
+// work the method must do, not what a kernel happens to execute), from the
+// recorded sizes and ranks.  Per step with b = b_i, r = r_i, n = b - r, live
+// widths s_c of the close views (r_c for processed neighbours, b_c otherwise)
+// and far width w (the same rule over the far views):
+//   compression  2 w b^2 - 2 b^3 / 3 (QR of the b x w far row; w < b: the
+//                transposed count) + 12 b^3 (SVD of the triangular factor)
+//   rotation     4 b^3 (U^T D U) + 2 b^2 sum_close b_c (U^T V, stored factor
+//                rows included) + 2 r b w (kept rows of the far views)
+//   elimination  n^3 / 3 (Cholesky of S_ii) + n^2 (r + sum_close s_c)
+//                (triangular solves of the panels)
+//   Schur        sum over panel pairs a <= c of 2 n s_a s_c (panel widths r
+//                and s_c)
+// compression and rotation only for steps with a non-empty far row; the dense
+// remainder counts dim^3 / 3 (its Cholesky).
+void count_block_flops(cae_factor_s* h) {
+  h->compress_flops = h->rotate_flops = h->elim_flops = h->schur_flops = 0;
   h->compressions = 0;
   const cae::Analysis& a = h->an->a;
   for (int l = 0; l < h->K; ++l) {
     const cae::LevelSym& L = a.levels[l];
     const NumLevel& N = h->lev[l];
+    std::vector<double> sw;
     for (const cae::Step& stp : L.steps) {
-      if (stp.nfar == 0) continue;
-      const double b = N.sizes[stp.blk];
-      double w = 0;
-      for (int v = stp.nclose; v < stp.nclose + stp.nfar; ++v) {
+      const double b = N.sizes[stp.blk], r = N.ranks[stp.blk], n = b - r;
+      double w = 0, bclose = 0;
+      sw.assign(1, r);
+      for (int v = 0; v < stp.nclose + stp.nfar; ++v) {
         const cae::View& vw = L.views[stp.view0 + v];
-        w += vw.proc ? N.ranks[vw.x] : N.sizes[vw.x];
+        const double live = vw.proc ? N.ranks[vw.x] : N.sizes[vw.x];
+        if (v < stp.nclose) {
+          sw.push_back(live);
+          bclose += N.sizes[vw.x];
+        } else {
+          w += live;
+        }
       }
-      const double qr = w >= b ? 2 * w * b * b - 2 * b * b * b / 3 : 2 * b * w * w - 2 * w * w * w / 3;
-      h->compress_flops += qr + 12 * b * b * b;
-      h->compressions += 1;
+      if (stp.nfar > 0) {
+        const double qr = w >= b ? 2 * w * b * b - 2 * b * b * b / 3 : 2 * b * w * w - 2 * w * w * w / 3;
+        h->compress_flops += qr + 12 * b * b * b;
+        h->compressions += 1;
+        h->rotate_flops += 4 * b * b * b + 2 * b * b * bclose + 2 * r * b * w;
+      }
+      if (n > 0) {
+        double ssum = 0, pairs = 0, pre = 0;
+        for (double x : sw) {
+          ssum += x;
+          pre += x;
+          pairs += x * pre;   // sum over a <= c of s_a s_c
+        }
+        h->elim_flops += n * n * n / 3 + n * n * ssum;
+        h->schur_flops += 2 * n * pairs;
+      }
     }
   }
+  const double d = (double)h->coarse_dim;
+  h->coarse_flops = d * d * d / 3;
   h->flops_pending = false;
 }
 
-int cae_get_stats(cae_handle_t h, cae_stats_t* st) {
+static int cae_get_stats_impl(cae_handle_t h, cae_stats_t* st) {
   if (check_handle(h) || !st) return fail(CAE_EINVAL, "null argument");
-  if (h->flops_pending) count_compress_flops(h);
+  if (h->flops_pending) count_block_flops(h);
   st->nlevels = h->K;
   st->coarse_dim = h->coarse_dim;
   st->tau = h->tau;
@@ -1236,6 +1469,10 @@ int cae_get_stats(cae_handle_t h, cae_stats_t* st) {
   st->compress_ms = h->compress_ms;
   st->compress_flops = h->compress_flops;
   st->compressions = h->compressions;
+  st->rotate_flops = h->rotate_flops;
+  st->elim_flops = h->elim_flops;
+  st->schur_flops = h->schur_flops;
+  st->coarse_flops = h->coarse_flops;
   st->sketch_accepted = h->sketch_acc;
   st->sketch_rejected = h->sketch_rej;
   st->record_rows = h->rec_rows;
@@ -1317,17 +1554,110 @@ int cae_mlp_predict(const float* params, const float* records, int64_t n, float*
   return CAE_OK;
 }
 
-int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks) {
+static int cae_get_ranks_impl(cae_handle_t h, int32_t level, int32_t* ranks) {
   if (check_handle(h) || !ranks) return fail(CAE_EINVAL, "null argument");
   if (level < 0 || level >= h->K) return fail(CAE_EINVAL, "level out of range");
   std::memcpy(ranks, h->lev[level].ranks.data(), h->lev[level].ranks.size() * sizeof(int32_t));
   return CAE_OK;
 }
 
-int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes) {
+static int cae_get_sizes_impl(cae_handle_t h, int32_t level, int32_t* sizes) {
   if (check_handle(h) || !sizes) return fail(CAE_EINVAL, "null argument");
   if (level < 0 || level > h->K) return fail(CAE_EINVAL, "level out of range");
   std::memcpy(sizes, h->lev[level].sizes.data(), h->lev[level].sizes.size() * sizeof(int32_t));
+  return CAE_OK;
+}
+
+int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
+  return keep_error(h, cae_apply_precond_impl(h, nrhs, r, ldr, z, ldz));
+}
+
+int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
+  return keep_error(h, cae_apply_factor_impl(h, nrhs, x, ldx, y, ldy));
+}
+
+int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
+                  int32_t maxit, int32_t* iters, double* relres) {
+  return keep_error(h, cae_pcg_solve_impl(h, nrhs, b, ldb, x, ldx, rtol, maxit, iters, relres));
+}
+
+int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                     double rtol, int32_t maxit, int32_t* iters, double* relres) {
+  return keep_error(h, cae_minres_solve_impl(h, nrhs, b, ldb, x, ldx, rtol, maxit, iters, relres));
+}
+
+int cae_get_stats(cae_handle_t h, cae_stats_t* st) {
+  return keep_error(h, cae_get_stats_impl(h, st));
+}
+
+int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks) {
+  return keep_error(h, cae_get_ranks_impl(h, level, ranks));
+}
+
+int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes) {
+  return keep_error(h, cae_get_sizes_impl(h, level, sizes));
+}
+
+int cae_get_level_ms(cae_handle_t h, int32_t level, double* ms) {
+  if (check_handle(h) || !ms) return fail(CAE_EINVAL, "null argument");
+  if (level < 0 || level > h->K) return keep_error(h, fail(CAE_EINVAL, "level out of range"));
+  const double start = level > 0 ? h->lev[level - 1].end_ms : 0.0;
+  *ms = (level < h->K ? h->lev[level].end_ms : h->factor_ms) - start;
+  return CAE_OK;
+}
+
+int cae_export_factor(cae_handle_t h, const char* path) {
+  if (check_handle(h) || !path) return fail(CAE_EINVAL, "handle and path are required");
+  FILE* fp = fopen(path, "wb");
+  if (!fp) return keep_error(h, fail(CAE_EINVAL, std::string("cannot open ") + path));
+  std::unique_ptr<FILE, int (*)(FILE*)> closer(fp, fclose);
+  bool ok = true;
+  auto put = [&](const void* p, size_t bytes) { ok = ok && (bytes == 0 || fwrite(p, 1, bytes, fp) == bytes); };
+  auto put_vec = [&](const auto& v) { put(v.data(), v.size() * sizeof(v[0])); };
+  std::vector<char> host;
+  auto put_dev = [&](const DevBuf& d, size_t bytes) {
+    host.resize(bytes);
+    if (bytes) HIPCHK(hipMemcpy(host.data(), d.p, bytes, hipMemcpyDeviceToHost));
+    put(host.data(), bytes);
+  };
+  try {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const cae::Analysis& a = h->an->a;
+    const int32_t esize = h->precision == CAE_FP64 ? 8 : 4;
+    put("CAEFACT1", 8);
+    const int32_t hdr[2] = {esize, h->K};
+    put(hdr, sizeof hdr);
+    const int64_t dims[2] = {a.n, h->coarse_dim};
+    put(dims, sizeof dims);
+    put(&h->tau, sizeof(double));
+    put_vec(a.perm);
+    for (int l = 0; l < h->K; ++l) {
+      const cae::LevelSym& L = a.levels[l];
+      const NumLevel& N = h->lev[l];
+      const int32_t ms[2] = {L.M, L.nslots};
+      put(ms, sizeof ms);
+      put_vec(N.sizes);
+      put_vec(N.ranks);
+      put_vec(L.slot_p);
+      put_vec(L.slot_q);
+      put_vec(N.slot_off);
+      put_dev(N.arena, (size_t)N.slot_off.back() * esize);
+      put_vec(N.u_off);
+      put_dev(N.U, (size_t)N.u_off.back() * esize);
+      put_dev(N.Li, (size_t)N.u_off.back() * esize);
+      put_vec(L.parent);
+      put_vec(N.off_in_parent);
+      put_vec(L.order);
+    }
+    const size_t dd = (size_t)h->coarse_dim * h->coarse_dim * sizeof(double);
+    put_dev(h->Acopy, h->coarse_dim > 0 ? dd : 0);
+    put_dev(h->Ainv, h->coarse_dim > 0 ? dd : 0);
+  } catch (const HipError& e) {
+    return keep_error(h, fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e)));
+  } catch (const std::bad_alloc&) {
+    return keep_error(h, fail(CAE_ENOMEM, "host allocation failed"));
+  }
+  if (!ok) return keep_error(h, fail(CAE_EINVAL, std::string("write to ") + path + " failed"));
   return CAE_OK;
 }
 

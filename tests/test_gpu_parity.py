@@ -303,7 +303,8 @@ def test_solvers_report_no_convergence_at_maxit():
     for fn in (cae.lib().cae_pcg_solve, cae.lib().cae_minres_solve):
         rc = fn(f._h, 2, b.data_ptr(), n, x.data_ptr(), n, C.c_double(1e-12), 1, it.ctypes.data, rel.ctypes.data)
         assert rc == -4, rc
-        assert b"did not converge" in cae.lib().cae_last_error()
+        assert b"did not converge" in cae.lib().cae_last_error(None)
+        assert b"did not converge" in cae.lib().cae_last_error(f._h)   # kept with the handle too
         assert it.tolist() == [1, 1]
         assert np.all(rel > 1e-12) and np.all(rel < 1.0)
     xx, it2, rel2 = f.pcg(b, rtol=1e-12, maxit=1)
