@@ -238,6 +238,28 @@ int cae_factor(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const 
 int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr,
                       double* z, int64_t ldz);
 
+/*
+ * z = M^{-1} r exactly as cae_apply_precond computes it (the same kernels in
+ * the same order, bitwise the same result), for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The level vectors, the coarse product and the
+ * partial products live in a 64 MiB array of static device memory that every
+ * GPU loading the library holds until the process ends; this entry point
+ * calls no hipMalloc, hipFree or other allocating routine.
+ *   r, z: device, n x nrhs (ldr, ldz >= n).  stream: hipStream_t to enqueue
+ *   on, NULL = the handle's stream.  The work is enqueued and the call
+ *   returns without waiting for it.
+ *   Errors: CAE_EINVAL when the work vectors of this factor and nrhs exceed
+ *   the 64 MiB (the message states the bytes needed) or the factor has more
+ *   than 63 levels; nothing is enqueued then.
+ *   Every call on one GPU shares that GPU's array, which keeps the last
+ *   call's contents (nothing in it needs to start at zero): calls that
+ *   overlap on one GPU (other streams, other threads) race; calls enqueued on
+ *   one stream are ordered by it.
+ */
+int cae_apply_precond_noalloc(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr,
+                              double* z, int64_t ldz, void* stream);
+
 /* y = M x with the stored factor (the approximation of A itself). */
 int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx,
                      double* y, int64_t ldy);

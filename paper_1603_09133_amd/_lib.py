@@ -57,7 +57,7 @@ _lib = None
 EXPORTS = [
     "cae_default_options", "cae_last_error", "cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels",
     "cae_analysis_level_info", "cae_analysis_level_arrays", "cae_analysis_perm", "cae_analysis_destroy",
-    "cae_factor_numeric", "cae_workspace_query", "cae_factor", "cae_apply_precond", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
+    "cae_factor_numeric", "cae_workspace_query", "cae_factor", "cae_apply_precond", "cae_apply_precond_noalloc", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
     "cae_get_stats",
     "cae_get_ranks", "cae_get_sizes", "cae_get_level_ms", "cae_export_factor", "cae_destroy", "cae_mlp_param_count", "cae_mlp_train", "cae_mlp_loss_grad",
     "cae_mlp_predict",
@@ -90,6 +90,7 @@ def lib():
     L.cae_workspace_query.argtypes = [p, p, dbl, C.POINTER(Options), C.POINTER(C.c_size_t)]
     L.cae_factor.argtypes = [i64, p, p, p, p, p, i32, i32, p, i32, dbl, C.POINTER(Options), C.POINTER(p)]
     L.cae_apply_precond.argtypes = [p, i32, p, i64, p, i64]
+    L.cae_apply_precond_noalloc.argtypes = [p, i32, p, i64, p, i64, p]
     L.cae_apply_factor.argtypes = [p, i32, p, i64, p, i64]
     L.cae_pcg_solve.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
     L.cae_minres_solve.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
@@ -108,7 +109,7 @@ def lib():
     for name in ["cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels", "cae_analysis_level_info",
                  "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_workspace_query", "cae_factor",
                  "cae_apply_precond",
-                 "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
+                 "cae_apply_precond_noalloc", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
                  "cae_get_sizes", "cae_get_level_ms", "cae_export_factor", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:
         getattr(L, name).restype = C.c_int
     _lib = L

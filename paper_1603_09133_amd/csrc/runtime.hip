@@ -884,6 +884,56 @@ void solver_apply(cae_factor_s* h, int32_t nrhs, const double* r, int64_t ldr, d
   HIPCHK(hipGraphLaunch(hit->exec, h->stream));
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free apply (cae_apply_precond_noalloc): the level
+// vectors, the coarse product and the split backward's partial products of
+// one call live in this array instead of the handle's work vectors.  Every
+// GPU that loads the library holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns on that
+// device (the array's name in host code is not a device address).
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxLevels = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` on the current device, looked up once per device.
+void* noalloc_scratch() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw HipError{hipErrorInvalidDevice, "device index beyond the scratch table"};
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
+
+// Byte layout of the allocation-free apply's work vectors for nrhs columns:
+// every vector starts on a 256-byte boundary.  Returns the bytes needed.
+size_t noalloc_layout(const cae_factor_s* h, int32_t nrhs, size_t* y_off, size_t* ctmp_off, size_t* part_off) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off = 0;
+  for (int l = 0; l <= h->K; ++l) {
+    y_off[l] = off;
+    off = up(off + (size_t)std::max<int64_t>(h->lev[l].dim, 1) * nrhs * sizeof(double));
+  }
+  *ctmp_off = off;
+  off = up(off + (size_t)std::max<int64_t>(h->coarse_dim, 1) * nrhs * sizeof(double));
+  size_t part = 0;
+  for (int l = 0; l < h->K; ++l)
+    for (const auto& w : h->lev[l].waves)
+      if (cae::ap_split<double>(w, h->lev[l].bmax, h->opt.apply_split_steps))
+        part = std::max(part, cae::ap_part_elems(w, h->lev[l].bmax, nrhs));
+  *part_off = off;
+  off = up(off + part * sizeof(double));
+  return off;
+}
+
 int check_handle(cae_factor_s* h) {
   if (!h) return fail(CAE_EINVAL, "null handle");
   return CAE_OK;
@@ -1163,6 +1213,37 @@ static int cae_apply_precond_impl(cae_handle_t h, int32_t nrhs, const double* r,
   try {
     do_apply(h, nrhs, r, ldr, z, ldz);
     HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return CAE_OK;
+}
+
+static int cae_apply_precond_noalloc_impl(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz,
+                              void* stream) {
+  if (check_handle(h)) return CAE_EINVAL;
+  const int64_t n = h->an->a.n;
+  if (nrhs <= 0 || !r || !z || ldr < n || ldz < n) return fail(CAE_EINVAL, "bad vector arguments");
+  if (h->K + 1 > kNoAllocMaxLevels) return fail(CAE_EINVAL, "too many levels for the allocation-free apply");
+  size_t y_off[kNoAllocMaxLevels], ctmp_off = 0, part_off = 0;
+  const size_t need = noalloc_layout(h, nrhs, y_off, &ctmp_off, &part_off);
+  if (need > kNoAllocScratchBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "the allocation-free apply needs %zu bytes of scratch for %d right-hand sides; its limit is %zu bytes",
+             need, nrhs, kNoAllocScratchBytes);
+    return fail(CAE_EINVAL, buf);
+  }
+  try {
+    char* base = static_cast<char*>(noalloc_scratch());
+    double* y[kNoAllocMaxLevels];
+    for (int l = 0; l <= h->K; ++l) y[l] = reinterpret_cast<double*>(base + y_off[l]);
+    const ApplyBufs B{y, reinterpret_cast<double*>(base + ctmp_off), reinterpret_cast<double*>(base + part_off)};
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    if (h->precision != CAE_FP64)
+      apply_precond<float>(h, nrhs, r, ldr, z, ldz, B, s);
+    else
+      apply_precond<double>(h, nrhs, r, ldr, z, ldz, B, s);
   } catch (const HipError& e) {
     return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
   }
@@ -1570,6 +1651,11 @@ static int cae_get_sizes_impl(cae_handle_t h, int32_t level, int32_t* sizes) {
 
 int cae_apply_precond(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
   return keep_error(h, cae_apply_precond_impl(h, nrhs, r, ldr, z, ldz));
+}
+
+int cae_apply_precond_noalloc(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz,
+                              void* stream) {
+  return keep_error(h, cae_apply_precond_noalloc_impl(h, nrhs, r, ldr, z, ldz, stream));
 }
 
 int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy) {
