@@ -48,7 +48,7 @@ typedef enum {
   CAE_EDEVICE = -5    /* a HIP call failed */
 } cae_status_t;
 
-typedef enum { CAE_RANK_EPS = 0, CAE_RANK_FIXED = 1, CAE_RANK_LEARNED = 2 } cae_rank_mode_t;
+typedef enum { CAE_RANK_EPS = 0, CAE_RANK_FIXED = 1, CAE_RANK_LEARNED = 2, CAE_RANK_LEARNED_CAP = 3 } cae_rank_mode_t;
 /* FP32_BF16: FP32 factor whose Schur-complement products take BF16 inputs
  * with FP32 accumulation on the matrix cores */
 typedef enum { CAE_FP64 = 0, CAE_FP32 = 1, CAE_FP32_BF16 = 2 } cae_precision_t;
@@ -61,7 +61,13 @@ typedef struct {
                               paper's conclusion proposes -- an MLP predicts the rank, a
                               Gaussian sketch of that width (plus 8) gives the range, an
                               a-posteriori check guarantees ||E_i||_2 <= eps * tau and
-                              steps that fail it take the exact SVD (blocks <= 64) */
+                              steps that fail it take the exact SVD (blocks <= 64);
+                              LEARNED_CAP: CE(eps) where the MLP's width (plus 8) caps the
+                              pivoted Cholesky of the far row's Gram matrix in the exact
+                              compression (any block size); a capped step is kept only if
+                              the energy left out cannot change the rank (sigma_{r+1}^2 +
+                              bound <= (eps tau)^2, so its rank is the exact one and
+                              ||E_i||_2 <= eps * tau), else it is redone without the cap */
   int32_t fixed_rank;      /* r for CE(r) */
   int32_t precision;       /* arithmetic of the block factorization; the coarse
                               remainder, the apply vectors and PCG are FP64 */

@@ -150,19 +150,27 @@ class _Blocks:
 
 
 def _level1_blocks(A0: sp.csr_matrix, block_ptr):
-    """Dense copies of the nonzero blocks of A0."""
+    """Dense copies of the nonzero blocks of A0 (blocks (p, q), p <= q): the
+    entries are grouped by block, then each group is added into its block."""
     coo = A0.tocoo()
     M = len(block_ptr) - 1
     owner = np.repeat(np.arange(M), np.diff(block_ptr))
     bi, bj = owner[coo.row], owner[coo.col]
-    li, lj = coo.row - block_ptr[bi], coo.col - block_ptr[bj]
+    keep = bi <= bj
+    bi, bj, rows, cols, vals = bi[keep], bj[keep], coo.row[keep], coo.col[keep], coo.data[keep]
+    li, lj = rows - block_ptr[bi], cols - block_ptr[bj]
     W = _Blocks()
     sizes = np.diff(block_ptr)
-    keep = bi <= bj
-    for p, q, a, c, v in zip(bi[keep], bj[keep], li[keep], lj[keep], coo.data[keep]):
-        if not W.has(p, q):
-            W.put(p, q, np.zeros((sizes[p], sizes[q])))
-        W.get(p, q)[a, c] += v
+    key = bi.astype(np.int64) * M + bj
+    order = np.argsort(key, kind="stable")
+    key, li, lj, vals = key[order], li[order], lj[order], vals[order]
+    starts = np.flatnonzero(np.r_[True, key[1:] != key[:-1]])
+    ends = np.r_[starts[1:], len(key)]
+    for s0, s1 in zip(starts, ends):
+        p, q = int(key[s0] // M), int(key[s0] % M)
+        X = np.zeros((sizes[p], sizes[q]))
+        np.add.at(X, (li[s0:s1], lj[s0:s1]), vals[s0:s1])
+        W.put(p, q, X)
     for p in range(M):
         if not W.has(p, p):
             W.put(p, p, np.zeros((sizes[p], sizes[p])))

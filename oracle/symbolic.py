@@ -79,17 +79,13 @@ def level1_pattern(indptr, indices, perm, block_ptr):
     N = len(perm)
     pos = np.empty(N, dtype=np.int64)
     pos[np.asarray(perm)] = np.arange(N)
-    owner = np.empty(N, dtype=np.int64)
-    for b in range(len(block_ptr) - 1):
-        owner[block_ptr[b]:block_ptr[b + 1]] = b
-    pairs = set()
-    for i in range(N):
-        bi = owner[pos[i]]
-        for k in range(indptr[i], indptr[i + 1]):
-            bj = owner[pos[indices[k]]]
-            if bi != bj:
-                pairs.add((min(bi, bj), max(bi, bj)))
-    return sorted(pairs)
+    owner = np.repeat(np.arange(len(block_ptr) - 1, dtype=np.int64), np.diff(np.asarray(block_ptr)))
+    rows = np.repeat(np.arange(N, dtype=np.int64), np.diff(np.asarray(indptr)))
+    bi, bj = owner[pos[rows]], owner[pos[np.asarray(indices, dtype=np.int64)]]
+    off = bi != bj
+    lo, hi = np.minimum(bi[off], bj[off]), np.maximum(bi[off], bj[off])
+    pairs = np.unique(np.stack([lo, hi], axis=1), axis=0)
+    return [(int(p), int(q)) for p, q in pairs]
 
 
 def adjacency(M, pairs):

@@ -19,6 +19,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (CAEError, FP32, FP32_BF16, FP64, ORDER_MULTICOLOUR, ORDER_PAPER, RANK_EPS, RANK_FIXED, RANK_LEARNED,
+                   RANK_LEARNED_CAP,
                    RECORD_WIDTH, check, lib, ptr)
 
 __all__ = ["grid_order", "graph_order", "Analysis", "Factor", "CAEError", "FP64", "FP32", "FP32_BF16", "ORDER_PAPER",

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcae.so")
 
 CAE_OK, CAE_EINVAL, CAE_ENOMEM, CAE_ENOTSPD, CAE_ENOCONV, CAE_EDEVICE = 0, -1, -2, -3, -4, -5
-RANK_EPS, RANK_FIXED, RANK_LEARNED = 0, 1, 2
+RANK_EPS, RANK_FIXED, RANK_LEARNED, RANK_LEARNED_CAP = 0, 1, 2, 3
 RECORD_WIDTH = 17
 FP64, FP32, FP32_BF16 = 0, 1, 2
 ORDER_PAPER, ORDER_MULTICOLOUR = 0, 1

@@ -58,6 +58,9 @@ __device__ inline T* dyn_work(T* gscratch, int64_t per_wg) {
 // singular vectors of F_i.  U_i = V with columns sorted by decreasing sigma.
 // ---------------------------------------------------------------------------
 constexpr int QR_CH = 64;
+// blocks of BG_MIN..BG_MAXB unknowns: big-block compression of the FP32
+// factor (k_bg_gram / k_bg_eig), at most BG_MA pivoted Cholesky rows
+constexpr int BG_MIN = 129, BG_MAXB = 512, BG_MA = 128;
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* gscratch, int64_t per_wg) {
@@ -66,6 +69,7 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
   const int b = A.bsz[i];
   const int tid = threadIdx.x;
   if (A.small_by_wave && b <= A.small_by_wave) return;   // done by the wavefront kernel
+  if (A.big_retry && b >= BG_MIN && b <= BG_MAXB && !A.big_fail[i]) return;   // settled by the big-block kernels
   T* Ug = A.U + A.u_off[i];
   if (st.nfar == 0 || b == 0) {
     for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
@@ -2223,6 +2227,9 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
 #pragma unroll
       for (int h = 0; h < NL; ++h) chosen[h] = false;
       double inactive = 0.0;
+      // learned cap (LEARNED_CAP): at most the predicted width of pivots
+      const int cap = A.lwidth ? A.lwidth[i] : b;
+      bool capped = false;
       int k = 0;
       for (; k < b; ++k) {
         double rsl = 0.0, cv = -1.0;
@@ -2241,6 +2248,11 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
         wave_argmax_u(cv, ci);
         if (rs <= stop2 || !(cv > 0.0)) {
           inactive = rs;
+          break;
+        }
+        if (k >= cap) {
+          inactive = rs;
+          capped = true;
           break;
         }
         const int p = ci;
@@ -2322,6 +2334,20 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
         cnt += __popcll(__ballot(q0 < ma && sgl[h] > theta));
       }
       const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
+      // a capped step is kept only if the energy the cap left out (the
+      // trailing trace, G - R^T R being positive semidefinite) cannot change
+      // the rank: sigma_{r+1}^2 + inactive <= theta^2 gives sigma_{r+1}(F) <=
+      // theta (Weyl), so r is the rank of F_i and ||E_i||_2 <= theta
+      if (capped && A.rank_mode == 0) {
+        double s1 = 0.0;
+#pragma unroll
+        for (int h = 0; h < NL; ++h)
+          if (lane + 64 * h < ma && pos[h] == r) s1 = sgl[h] * sgl[h];
+        s1 = wave_sum_u(s1);
+        if (lane == 0) shi[3] = s1 + inactive > theta * theta ? 1 : 0;
+      } else if (lane == 0) {
+        shi[3] = 0;
+      }
 #pragma unroll
       for (int h = 0; h < NL; ++h)
         if (lane + 64 * h < ma && pos[h] >= r) edl += sgl[h] * sgl[h];
@@ -2435,6 +2461,14 @@ __global__ __launch_bounds__(NT) void k_compress_gram(LevelArgs<T> A, int32_t s0
     }
     __syncthreads();
 
+    if (A.lwidth) {
+      // learned cap: a rejected step is redone without the cap
+      if (tid == 0) {
+        if (shi[3]) A.big_fail[i] = 1;
+        atomicAdd(A.lcount + (shi[3] ? 1 : 0), 1);
+      }
+      if (shi[3]) return;
+    }
     // ---- 5. U_i = H_0 ... H_{kb-1}: 4 lanes per column, BM / 4 coordinates
     // per lane, 16 columns per wavefront and pass --------------------------------
     const int kb = shi[0];
@@ -3544,6 +3578,1038 @@ __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64
 }
 
 // ---------------------------------------------------------------------------
+// Compression of blocks of BG_MIN..BG_MAXB unknowns (FP32 factor: the coarse
+// levels of 3D problems with sibling coarsening, whose blocks join the kept
+// unknowns of eight children).  The far row F_i (b x w) is reduced to its
+// Gram matrix G = F F^T in FP64 on the matrix cores by many workgroups
+// (k_bg_gram, one 64 x 64 tile of G each: the products of FP32 entries are
+// exact in FP64).  One workgroup per step then (k_bg_eig):
+//   1. pivoted Cholesky G ~ X^T X, stopped at the rounding level the smaller
+//      blocks use (at most BG_MA rows);
+//   2. S = X X^T (ma x ma): its eigenvalues are those of G, sigma_k(F)^2, and
+//      an eigenvector w_k gives the left singular vector v_k = X^T w_k /
+//      sigma_k of F;
+//   3. one-sided Jacobi on the rows of S (the rows converge to lambda_k w_k^T);
+//   4. r_i = #{sigma_k > theta}, the dropped energy, the kept v_k;
+//   5. Householder reflectors of the kept directions and U_i = H_0 ... H_{r-1},
+//      one wavefront per column of U_i.
+// A step whose Gram matrix needs more than BG_MA pivots is flagged in big_fail
+// for the generic kernel.
+// ---------------------------------------------------------------------------
+constexpr int BG_SLD = BG_MA + 4;   // row stride of S in LDS
+
+int64_t bg_stride(int bmax) { return (int64_t)bmax * bmax + (int64_t)BG_MA * bmax; }
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b < BG_MIN || b > BG_MAXB || st.nfar == 0) return;
+  if (A.need_exact && !A.need_exact[i]) return;
+  // tile pair (ti <= tj) of this workgroup
+  const int nt = (b + 63) / 64;
+  int t = blockIdx.y, ti = 0;
+  while (ti < nt && t >= nt - ti) {
+    t -= nt - ti;
+    ++ti;
+  }
+  if (ti >= nt) return;
+  const int tj = ti + t;
+  const int ra = 64 * ti, rb = 64 * tj;
+  const int na = min(64, b - ra), nb = min(64, b - rb);
+  double* G = A.big + (int64_t)blockIdx.x * A.big_stride;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Sa = reinterpret_cast<T*>(smem_raw);   // Sa[k][a] = F(ra + a, column k of the chunk)
+  T* Sb = Sa + 64 * TLD;                     // Sb[k][a] = F(rb + a, column k of the chunk)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, fr = lane & 15, fk = lane >> 4;
+  dbl4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    for (int c0 = 0; c0 < w; c0 += 64) {
+      const int mc = min(64, w - c0), mc4 = (mc + 3) & ~3;
+      __syncthreads();
+      // rows of the chunk k < mc4 (zero from mc on), 64 coordinates (zero
+      // beyond na / nb); the unit-stride index on consecutive threads
+      for (int e = threadIdx.x; e < 64 * mc4; e += NT) {
+        const int k = v.trans ? (e >> 6) : (e % mc4);
+        const int a = v.trans ? (e & 63) : (e / mc4);
+        T xa = T(0), xb = T(0);
+        if (k < mc) {
+          if (a < na) xa = v.trans ? base[(int64_t)(c0 + k) * b + ra + a] : base[(int64_t)(ra + a) * bx + c0 + k];
+          if (a < nb) xb = v.trans ? base[(int64_t)(c0 + k) * b + rb + a] : base[(int64_t)(rb + a) * bx + c0 + k];
+        }
+        Sa[k * TLD + a] = xa;
+        Sb[k * TLD + a] = xb;
+      }
+      __syncthreads();
+      // FP64 matrix cores: wavefront w owns rows 16 w .. 16 w + 15 of the tile
+      // as four 16 x 16 tiles (operand and result lanes as in k_schur_t)
+      const T* fa = Sa + fk * TLD + 16 * wv + fr;
+      const T* fb = Sb + fk * TLD + fr;
+      for (int k0 = 0; k0 < mc4; k0 += 4) {
+        const double av = (double)fa[k0 * TLD];
+        double bv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = (double)fb[k0 * TLD + 16 * c];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 16 * wv + 4 * j + fk, col = 16 * c + fr;
+      if (row < na && col < nb) {
+        G[(int64_t)(ra + row) * b + rb + col] = acc[c][j];
+        if (ti != tj) G[(int64_t)(rb + col) * b + ra + row] = acc[c][j];
+      }
+    }
+}
+
+template <typename T>
+size_t work_bg_eig() {
+  return (size_t)BG_MA * BG_SLD * sizeof(double) + (size_t)BG_MAXB * sizeof(double) +
+         (size_t)4 * BG_MA * sizeof(double) + (size_t)3 * BG_MA * sizeof(int) + (size_t)BG_MAXB;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b < BG_MIN || b > BG_MAXB) return;
+  if (A.need_exact && !A.need_exact[i]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  T* Ug = A.U + A.u_off[i];
+  if (st.nfar == 0) {
+    for (int e = tid; e < b * b; e += NT) Ug[e] = (e / b == e % b) ? T(1) : T(0);
+    if (tid == 0) {
+      A.rank[i] = 0;
+      A.edrop[i] = 0.0;
+      if (A.rec) A.rec[(A.rec_off + i) * REC_W + NFEAT] = -1.0f;
+    }
+    return;
+  }
+  double* G = A.big + (int64_t)blockIdx.x * A.big_stride;   // b x b, later the kept directions
+  double* X = G + (int64_t)b * b;                              // BG_MA x b rows of the Cholesky factor
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* S = reinterpret_cast<double*>(smem_raw);   // BG_MA x BG_SLD
+  double* dg = S + BG_MA * BG_SLD;                   // trailing diagonal
+  double* xp = dg + BG_MAXB;                         // X(j, p) of the current pivot
+  double* sg = xp + BG_MA;                           // eigenvalues of S
+  double* tau = sg + BG_MA;                          // sorted eigenvalues, then reflector coefficients
+  double* isg = tau + BG_MA;
+  int* posv = reinterpret_cast<int*>(isg + BG_MA);
+  int* brow = posv + BG_MA;
+  int* rowix = brow + BG_MA;
+  unsigned char* chosen = reinterpret_cast<unsigned char*>(rowix + BG_MA);
+  __shared__ double rd[8];
+  __shared__ int ri[8];
+  __shared__ double shd[4];
+  __shared__ int shi[4];
+  const double theta = *A.theta;
+
+  // ---- 1. pivoted Cholesky (left-looking): row k of X from column p of G ----
+  double tr = 0.0;
+  for (int t = tid; t < b; t += NT) {
+    dg[t] = G[(int64_t)t * b + t];
+    chosen[t] = 0;
+    tr += dg[t];
+  }
+  tr = wave_sum_u(tr);
+  if (lane == 0) rd[wv] = tr;
+  __syncthreads();
+  const double fro2 = rd[0] + rd[1] + rd[2] + rd[3];
+  const double noise = (double)Eps<T>::v() * sqrt(fro2);
+  const double negl = A.rank_mode == 0 ? fmax(noise, theta / 64.0) : noise;
+  const double aerr = A.rank_mode == 0 ? fmax(noise, fmin((double)max(b, 16) * noise, theta / 32.0))
+                                       : (double)max(b, 16) * noise;
+  // CE(eps): pivots stop once the trailing energy is below (theta / 32)^2 at
+  // the latest (it shifts a sigma near theta by at most theta / 2048); an FP64
+  // factor would otherwise pivot down to its rounding level
+  const double stop2 = A.rank_mode == 0 ? fmax(aerr * aerr, theta * theta / 1024.0) : aerr * aerr;
+  double inactive = 0.0;
+  int k = 0;
+  bool truncated = false;
+  // at most BG_MA pivots (the learned width does not cap big blocks: their far
+  // rows carry long tails of singular values just below theta, which no cap
+  // below BG_MA can leave out with a certified rank)
+  const int cap = BG_MA;
+  for (;; ++k) {
+    __syncthreads();   // dg and chosen of the previous pivot, rd free
+    double rs = 0.0, cv = -1.0;
+    int ci = 0x7fffffff;
+    for (int t = tid; t < b; t += NT)
+      if (!chosen[t]) {
+        rs += dg[t];
+        if (dg[t] > cv) {
+          cv = dg[t];
+          ci = t;
+        }
+      }
+    rs = wave_sum_u(rs);
+    wave_argmax_u(cv, ci);
+    if (lane == 0) {
+      rd[wv] = rs;
+      rd[4 + wv] = cv;
+      ri[wv] = ci;
+    }
+    __syncthreads();
+    rs = (rd[0] + rd[1]) + (rd[2] + rd[3]);
+    cv = rd[4];
+    ci = ri[0];
+    for (int u = 1; u < 4; ++u) amax_step(cv, ci, rd[4 + u], ri[u]);
+    if (rs <= stop2 || !(cv > 0.0)) {
+      inactive = rs;
+      break;
+    }
+    if (k == cap) {
+      // truncated: the trailing energy rs stays outside X; the step is kept
+      // only if it cannot change the rank (checked once the ranks are known)
+      inactive = rs;
+      truncated = true;
+      break;
+    }
+    const int p = ci;
+    const double ilpp = 1.0 / sqrt(cv), lpp = cv * ilpp;
+    for (int j = tid; j < k; j += NT) xp[j] = X[(int64_t)j * b + p];
+    __syncthreads();
+    for (int t = tid; t < b; t += NT) {
+      double s = G[(int64_t)p * b + t];
+      int j = 0;
+      for (; j + 4 <= k; j += 4)
+        s -= (X[(int64_t)j * b + t] * xp[j] + X[(int64_t)(j + 1) * b + t] * xp[j + 1]) +
+             (X[(int64_t)(j + 2) * b + t] * xp[j + 2] + X[(int64_t)(j + 3) * b + t] * xp[j + 3]);
+      for (; j < k; ++j) s -= X[(int64_t)j * b + t] * xp[j];
+      const double lv = chosen[t] ? 0.0 : (t == p ? lpp : s * ilpp);
+      X[(int64_t)k * b + t] = lv;
+      if (!chosen[t] && t != p) dg[t] -= lv * lv;
+    }
+    __syncthreads();
+    if (tid == 0) chosen[p] = 1;
+  }
+  const int ma = k;
+  __syncthreads();
+
+  // ---- 2. S = X X^T (zero beyond ma), thread (ty, tx) an 8 x 8 block --------
+  {
+    const int ty = tid >> 4, tx = tid & 15;
+    double acc[8][8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
+    if (8 * ty < ma && 8 * tx < ma) {
+      for (int t = 0; t < b; ++t) {
+        double xa[8], xb[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          xa[p] = 8 * ty + p < ma ? X[(int64_t)(8 * ty + p) * b + t] : 0.0;
+          xb[p] = 8 * tx + p < ma ? X[(int64_t)(8 * tx + p) * b + t] : 0.0;
+        }
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[p][q] += xa[p] * xb[q];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) S[(8 * ty + p) * BG_SLD + 8 * tx + q] = acc[p][q];
+    if (tid < BG_MA) rowix[tid] = tid;
+  }
+  __syncthreads();
+
+  // ---- 3. one-sided Jacobi on the rows of S (one wavefront) ----------------
+  // the row norms are lambda = sigma^2: the thresholds of the sigma-scale
+  // tests squared
+  if (wv == 0 && ma > 1) {
+    const double tol = (double)max(b, 16) * DBL_EPSILON;
+    const int np = (ma + 1) / 2;
+    if (np <= 4) jacobi_rows_wave<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else if (np <= 8) jacobi_rows_wave<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else jacobi_rows_wave<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+  }
+  __syncthreads();
+
+  // ---- 4. eigenvalues, order, rank, dropped energy ---------------------------
+  if (tid < ma) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int q = 0; q < BG_MA; q += 2) {
+      s0 += S[tid * BG_SLD + q] * S[tid * BG_SLD + q];
+      s1 += S[tid * BG_SLD + q + 1] * S[tid * BG_SLD + q + 1];
+    }
+    sg[tid] = sqrt(s0 + s1);   // lambda_k = sigma_k(F)^2
+  }
+  __syncthreads();
+  int cnt = 0;
+  if (tid < ma) {
+    int pos = 0;
+    const double l0 = sg[tid];
+    for (int q = 0; q < ma; ++q) pos += (sg[q] > l0 || (sg[q] == l0 && q < tid)) ? 1 : 0;
+    posv[tid] = pos;
+    tau[pos] = l0;
+    cnt = sqrt(l0) > theta ? 1 : 0;
+  }
+  cnt = __syncthreads_count(cnt);
+  const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
+  const int kb = min(r, ma);
+  // a truncated Cholesky leaves G2 = G - X^T X (positive semidefinite); the
+  // step is kept if lambda_{r+1}(X^T X) + ||G2||_F <= theta^2: then
+  // lambda_{r+1}(G) <= theta^2 too (Weyl, ||G2||_2 <= ||G2||_F), so r is the
+  // rank of F_i and the dropped part has spectral norm <= theta; otherwise the
+  // generic kernel takes the step
+  if (truncated && A.rank_mode == 0) {
+    double f2 = 0.0;
+    for (int e = tid; e < b * b; e += NT) {
+      const int p = e / b, q = e % b;
+      if (q < p) continue;
+      double g = G[(int64_t)p * b + q];
+      for (int j = 0; j < ma; ++j) g -= X[(int64_t)j * b + p] * X[(int64_t)j * b + q];
+      f2 += (q == p ? 1.0 : 2.0) * g * g;
+    }
+    f2 = wave_sum_u(f2);
+    __syncthreads();
+    if (lane == 0) rd[wv] = f2;
+    __syncthreads();
+    const double g2n = sqrt((rd[0] + rd[1]) + (rd[2] + rd[3]));
+    if ((r < ma ? tau[r] : 0.0) + g2n > theta * theta) {
+      if (tid == 0) A.big_fail[i] = 1;
+      return;
+    }
+  }
+  if (tid == 0 && A.cap_retry) A.big_fail[i] = 0;   // settled by the uncapped pass
+  if (tid == 0) {
+    double ed = inactive;
+    for (int q = r; q < ma; ++q) ed += tau[q];
+    shd[0] = ed;
+    int label = 0;
+    if (A.rec) {
+      // the smallest sketch width that an ideal sketch would need to pass the
+      // a-posteriori check (as the other compression kernels record it)
+      const double th2 = theta * theta, sr2 = r < ma ? tau[r] : 0.0;
+      double tail = inactive;
+      int kf = ma;
+      for (int kk = ma; kk >= r; --kk) {
+        if (kk < ma) tail += tau[kk];
+        if (tail + (kk > r ? sr2 : 0.0) <= th2) kf = kk;
+      }
+      label = max(kf, r);
+    }
+    shi[0] = label;
+  }
+  if (tid < ma && posv[tid] < kb) {
+    brow[posv[tid]] = tid;
+    // v = X^T w / sigma with w = row / lambda: X^T row * lambda^{-3/2}
+    const double l0 = sg[tid];
+    isg[posv[tid]] = l0 > 0.0 ? 1.0 / (l0 * sqrt(l0)) : 0.0;
+  }
+  __syncthreads();
+
+  // ---- 5. kept directions v_k (b-vectors) into G's storage -----------------
+  double* V = G;
+  for (int t = tid; t < b; t += NT) {
+    for (int c0 = 0; c0 < kb; c0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      for (int j = 0; j < ma; ++j) {
+        const double x = X[(int64_t)j * b + t];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (c0 + u < kb) acc[u] += x * S[brow[c0 + u] * BG_SLD + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (c0 + u < kb) V[(int64_t)(c0 + u) * b + t] = acc[u] * isg[c0 + u];
+    }
+  }
+  __syncthreads();
+
+  // ---- 6. Householder reflectors of the kept directions ----------------------
+  for (int cv = 0; cv < kb; ++cv) {
+    double* vr = V + (int64_t)cv * b;
+    if (wv == 0) {
+      double xs = 0.0;
+      for (int t = cv + lane; t < b; t += 64) xs += vr[t] * vr[t];
+      const double nrm2 = wave_sum_u(xs);
+      const double x0 = vr[cv];
+      const double nrm = sqrt(nrm2);
+      const double alpha = x0 >= 0.0 ? -nrm : nrm;
+      const double v0 = x0 - alpha;
+      const double vv = v0 * v0 + (nrm2 - x0 * x0);
+      wave_sync();
+      for (int t = lane; t < cv; t += 64) vr[t] = 0.0;
+      if (lane == 0) {
+        vr[cv] = v0;
+        tau[cv] = vv > 0.0 ? 2.0 / vv : 0.0;
+      }
+    }
+    __syncthreads();
+    const double tc = tau[cv];
+    for (int c2 = cv + 1 + wv; c2 < kb; c2 += 4) {
+      double* br = V + (int64_t)c2 * b;
+      double dd = 0.0;
+      for (int t = cv + lane; t < b; t += 64) dd += vr[t] * br[t];
+      dd = wave_sum_u(dd);
+      for (int t = cv + lane; t < b; t += 64) br[t] -= tc * dd * vr[t];
+    }
+    __syncthreads();
+  }
+
+  // ---- 7. U_i = H_0 ... H_{kb-1}: one wavefront per column ------------------
+  for (int col = wv; col < b; col += 4) {
+    double q[BG_MAXB / 64];
+#pragma unroll
+    for (int u = 0; u < BG_MAXB / 64; ++u) q[u] = (lane + 64 * u == col) ? 1.0 : 0.0;
+    for (int cv = kb - 1; cv >= 0; --cv) {
+      const double* vr = V + (int64_t)cv * b;
+      double dd = 0.0;
+#pragma unroll
+      for (int u = 0; u < BG_MAXB / 64; ++u) {
+        const int t = lane + 64 * u;
+        if (t < b) dd += vr[t] * q[u];
+      }
+      dd = wave_sum_u(dd) * tau[cv];
+#pragma unroll
+      for (int u = 0; u < BG_MAXB / 64; ++u) {
+        const int t = lane + 64 * u;
+        if (t < b) q[u] -= dd * vr[t];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BG_MAXB / 64; ++u) {
+      const int t = lane + 64 * u;
+      if (t < b) Ug[(int64_t)t * b + col] = (T)q[u];
+    }
+  }
+  if (tid == 0) {
+    A.rank[i] = r;
+    A.edrop[i] = shd[0];
+    if (A.rec) A.rec[(A.rec_off + i) * REC_W + NFEAT] = (float)shi[0] / (float)b;
+  }
+}
+
+// Schur update for steps with 64 < b_i <= BG_MAXB (any n_i): T(a, c) -=
+// P_a^T P_c over the 64 x 64 target tiles in turn, the n_i rows of the two
+// panels staged in LDS 64 at a time, the products on the FP64 matrix cores
+// (operand and result lanes as in k_schur_t).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_big(LevelArgs<T> A, int32_t p0) {
+  const Pair pr = A.pairs[p0 + xcd_swizzle(blockIdx.x, gridDim.x)];
+  const Step st = A.steps[pr.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b <= 64 || b > BG_MAXB) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  T* D = A.arena + A.slot_off[i];
+  int la, lc, ba = b, bc = b, ta = 0, tcv = 0;
+  T* pa;
+  T* pc;
+  if (pr.a == 0) {
+    la = r;
+    pa = D;
+  } else {
+    const View va = A.views[st.view0 + pr.a - 1];
+    ba = A.bsz[va.x];
+    la = va.proc ? A.rank[va.x] : ba;
+    pa = A.arena + A.slot_off[va.slot];
+    ta = va.trans;
+  }
+  if (pr.c == 0) {
+    lc = r;
+    pc = D;
+  } else {
+    const View vc = A.views[st.view0 + pr.c - 1];
+    bc = A.bsz[vc.x];
+    lc = vc.proc ? A.rank[vc.x] : bc;
+    pc = A.arena + A.slot_off[vc.slot];
+    tcv = vc.trans;
+  }
+  if (la == 0 || lc == 0) return;
+  T* tbase;
+  int64_t ts_a, ts_c;
+  if (pr.a == 0) {
+    if (pr.c == 0) {
+      tbase = D;
+      ts_a = b;
+      ts_c = 1;
+    } else {
+      tbase = pc;
+      ts_a = tcv ? 1 : bc;
+      ts_c = tcv ? b : 1;
+    }
+  } else {
+    tbase = A.arena + A.slot_off[pr.slot];
+    if (pr.trans) {
+      ts_a = 1;
+      ts_c = ba;
+    } else {
+      ts_a = bc;
+      ts_c = 1;
+    }
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Pa = reinterpret_cast<T*>(smem_raw);
+  T* Pc = Pa + 64 * TLD;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const T* fa = Pa + fk * TLD + 16 * wv + fr;
+  const T* fc = Pc + fk * TLD + fr;
+  for (int a0 = 0; a0 < la; a0 += 64) {
+    const int tan = min(64, la - a0);
+    for (int c0 = 0; c0 < lc; c0 += 64) {
+      const int tcn = min(64, lc - c0);
+      T tv[4][4];
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int al = 16 * wv + 4 * j + fk, gm = 16 * tj + fr;
+          tv[tj][j] = (al < tan && gm < tcn) ? tbase[(a0 + al) * ts_a + (c0 + gm) * ts_c] : T(0);
+        }
+      dbl4 dacc[4];
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) dacc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < n; k0 += 64) {
+        const int nk = min(64, n - k0), nk4 = (nk + 3) & ~3;
+        __syncthreads();
+        load_tile_pair(Pa, pa, TileSrc{ta, b, ba, a0, tan}, pc, TileSrc{tcv, b, bc, c0, tcn}, r + k0, nk);
+        // rows nk .. nk4 - 1 of both tiles are zero: the k loop runs in steps of four
+        for (int e = threadIdx.x; e < (nk4 - nk) * 64; e += NT) {
+          Pa[(nk + (e >> 6)) * TLD + (e & 63)] = T(0);
+          Pc[(nk + (e >> 6)) * TLD + (e & 63)] = T(0);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k = 0; k < nk4; k += 4) {
+          const double av = (double)fa[k * TLD];
+          double bv[4];
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj) bv[tj] = (double)fc[k * TLD + 16 * tj];
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj) dacc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], dacc[tj], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int al = 16 * wv + 4 * j + fk, gm = 16 * tj + fr;
+          if (al < tan && gm < tcn)
+            tbase[(a0 + al) * ts_a + (c0 + gm) * ts_c] = (T)((double)tv[tj][j] - dacc[tj][j]);
+        }
+    }
+  }
+}
+
+// Strip products of the steps with 64 < b_i <= BG_MAXB.  A strip of SW
+// columns of a view (its rows row0 .. row0 + m; SW = 64 for an FP32 factor,
+// 32 for FP64, so that BG_MAXB rows fit in LDS) is staged in LDS and
+// multiplied from the left by an m x m matrix read from global memory (L2):
+// wavefront w owns the output row blocks 16 w, 16 (w + 4), ..., each as SW / 16
+// tiles of 16 x 16 on the FP64 matrix cores (lanes as in k_schur_t).  Rows m ..
+// m4 - 1 of the strip stay zero so the k loop runs in steps of four.
+template <typename T>
+struct Strip {
+  static constexpr int SW = sizeof(T) == sizeof(float) ? 64 : 32;   // columns
+  static constexpr int LD = SW + 4;                                  // LDS row stride
+  static constexpr int NTJ = SW / 16;                                // 16-column tiles
+};
+//   op = 0: out = M^T X with M row-major m x m (the rotation by U_i^T);
+//   op = 1: out = M X (the triangular solve by the stored L_nn^{-1}).
+// Output rows >= mout are not computed (far views keep their rows < r_i).
+template <typename T, int OP>
+__device__ void strip_product(const T* M, int m, const T* X, int mout, int tc, T* base, int trans, int bi, int bx,
+                              int row0, int c0) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, fr = lane & 15, fk = lane >> 4;
+  constexpr int NTJ = Strip<T>::NTJ, LD = Strip<T>::LD;
+  const int m4 = (m + 3) & ~3;
+  for (int rb = wv; 16 * rb < mout; rb += 4) {
+    dbl4 acc[NTJ];
+#pragma unroll
+    for (int tj = 0; tj < NTJ; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int row = 16 * rb + fr;
+#pragma unroll 4
+    for (int k0 = 0; k0 < m4; k0 += 4) {
+      const int k = k0 + fk;
+      double av = 0.0;
+      if (k < m && row < m) av = (double)(OP == 0 ? M[(int64_t)k * m + row] : M[(int64_t)row * m + k]);
+      double bv[NTJ];
+#pragma unroll
+      for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[k * LD + 16 * tj + fr];
+#pragma unroll
+      for (int tj = 0; tj < NTJ; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int tj = 0; tj < NTJ; ++tj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int a = 16 * rb + 4 * j + fk, c = 16 * tj + fr;
+        if (a < mout && c < tc) *view_ptr(base, trans, bi, bx, row0 + a, c0 + c) = (T)acc[tj][j];
+      }
+  }
+}
+
+// The strip X[a][c] = view(row0 + a, c0 + c), a < m, c < tc <= SW (rows m ..
+// m4 - 1 zero), the unit-stride index on consecutive threads.
+template <typename T>
+__device__ inline void load_strip(T* X, const T* base, int trans, int bi, int bx, int row0, int m, int c0, int tc) {
+  constexpr int SW = Strip<T>::SW, LD = Strip<T>::LD;
+  const int m4 = (m + 3) & ~3;
+  if (trans) {
+    for (int e = threadIdx.x; e < tc * m4; e += NT) {
+      const int c = e / m4, a = e % m4;
+      X[a * LD + c] = a < m ? base[(int64_t)(c0 + c) * bi + row0 + a] : T(0);
+    }
+  } else {
+    for (int e = threadIdx.x; e < m4 * SW; e += NT) {
+      const int a = e / SW, c = e % SW;
+      X[a * LD + c] = (a < m && c < tc) ? base[(int64_t)(row0 + a) * bx + c0 + c] : T(0);
+    }
+  }
+}
+
+template <typename T>
+size_t work_strip_big(int bmax) {
+  return (size_t)((std::min(bmax, BG_MAXB) + 3) & ~3) * Strip<T>::LD * sizeof(T);
+}
+
+// V_ix <- U_i^T V_ix for the close and far views of big steps (far views keep
+// rows < r_i; with compensation k_compensate reads E_i and zeroes it).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rot_big(LevelArgs<T> A, int32_t it0) {
+  const Item item = A.items[it0 + xcd_swizzle(blockIdx.x, gridDim.x)];
+  if (item.view < 0) return;
+  const Step st = A.steps[item.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b <= 64 || b > BG_MAXB) return;
+  const View v = A.views[item.view];
+  const int bx = A.bsz[v.x];
+  const bool drop = (item.view - st.view0) >= st.nclose && !A.compensate;
+  const int r = A.rank[i];
+  T* base = A.arena + A.slot_off[v.slot];
+  const T* Ug = A.U + A.u_off[i];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* X = reinterpret_cast<T*>(smem_raw);
+  constexpr int SW = Strip<T>::SW;
+  for (int c0 = 0; c0 < bx; c0 += SW) {
+    const int tc = min(SW, bx - c0);
+    __syncthreads();
+    load_strip(X, base, v.trans, b, bx, 0, b, c0, tc);
+    __syncthreads();
+    strip_product<T, 0>(Ug, b, X, drop ? r : b, tc, base, v.trans, b, bx, 0, c0);
+    if (drop)
+      for (int e = threadIdx.x; e < (b - r) * tc; e += NT)
+        *view_ptr(base, v.trans, b, bx, r + e / tc, c0 + e % tc) = T(0);
+  }
+}
+
+// D_i <- U_i^T D_i U_i for big steps, stored exactly symmetric: T1 = U^T D
+// into the step's FP64 scratch, then D = T1 U by column strips of U, the
+// entries (a, c) with a >= c written to both triangles.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rot_big_diag(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  if (st.nfar == 0) return;   // U_i = I
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b <= 64 || b > BG_MAXB) return;
+  T* D = A.arena + A.slot_off[i];
+  const T* Ug = A.U + A.u_off[i];
+  double* T1 = A.big + (int64_t)blockIdx.x * A.big_stride;   // b x b
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* X = reinterpret_cast<T*>(smem_raw);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, fr = lane & 15, fk = lane >> 4;
+  const int b4 = (b + 3) & ~3;
+  constexpr int SW = Strip<T>::SW, LD = Strip<T>::LD, NTJ = Strip<T>::NTJ;
+  // T1 = U^T D, column strips of D
+  for (int c0 = 0; c0 < b; c0 += SW) {
+    const int tc = min(SW, b - c0);
+    __syncthreads();
+    load_strip(X, D, 0, b, b, 0, b, c0, tc);
+    __syncthreads();
+    for (int rb = wv; 16 * rb < b; rb += 4) {
+      dbl4 acc[NTJ];
+#pragma unroll
+      for (int tj = 0; tj < NTJ; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+      const int row = 16 * rb + fr;
+#pragma unroll 4
+      for (int k0 = 0; k0 < b4; k0 += 4) {
+        const int k = k0 + fk;
+        const double av = (k < b && row < b) ? (double)Ug[(int64_t)k * b + row] : 0.0;
+        double bv[NTJ];
+#pragma unroll
+        for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[k * LD + 16 * tj + fr];
+#pragma unroll
+        for (int tj = 0; tj < NTJ; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
+      }
+#pragma unroll
+      for (int tj = 0; tj < NTJ; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = 16 * rb + 4 * j + fk, c = 16 * tj + fr;
+          if (a < b && c < tc) T1[(int64_t)a * b + c0 + c] = acc[tj][j];
+        }
+    }
+  }
+  __syncthreads();   // T1 complete (global writes of this workgroup)
+  // D = T1 U, column strips of U; the lower triangle mirrored
+  for (int c0 = 0; c0 < b; c0 += SW) {
+    const int tc = min(SW, b - c0);
+    __syncthreads();
+    load_strip(X, Ug, 0, b, b, 0, b, c0, tc);
+    __syncthreads();
+    for (int rb = wv; 16 * rb < b; rb += 4) {
+      if (16 * rb + 15 < c0) continue;   // a block entirely above the diagonal of this strip
+      dbl4 acc[NTJ];
+#pragma unroll
+      for (int tj = 0; tj < NTJ; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+      const int row = 16 * rb + fr;
+#pragma unroll 4
+      for (int k0 = 0; k0 < b4; k0 += 4) {
+        const int k = k0 + fk;
+        const double av = (k < b && row < b) ? T1[(int64_t)row * b + k] : 0.0;
+        double bv[NTJ];
+#pragma unroll
+        for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[k * LD + 16 * tj + fr];
+#pragma unroll
+        for (int tj = 0; tj < NTJ; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
+      }
+#pragma unroll
+      for (int tj = 0; tj < NTJ; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = 16 * rb + 4 * j + fk, c = c0 + 16 * tj + fr;
+          if (a < b && 16 * tj + fr < tc && a >= c) {
+            const T val = (T)acc[tj][j];
+            D[(int64_t)a * b + c] = val;
+            D[(int64_t)c * b + a] = val;
+          }
+        }
+    }
+  }
+}
+
+// L(c, n_i)^T = L_nn^{-1} V_ic[n_i, live_c] for the close views of big steps.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_trsm_big(LevelArgs<T> A, int32_t it0) {
+  const Item item = A.items[it0 + xcd_swizzle(blockIdx.x, gridDim.x)];
+  const Step st = A.steps[item.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b <= 64 || b > BG_MAXB) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const View v = A.views[item.view];
+  const int bx = A.bsz[v.x];
+  const int lc = v.proc ? A.rank[v.x] : bx;
+  if (lc == 0) return;
+  T* base = A.arena + A.slot_off[v.slot];
+  const T* Lig = A.Li + A.u_off[i];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* X = reinterpret_cast<T*>(smem_raw);
+  constexpr int SW = Strip<T>::SW;
+  for (int c0 = 0; c0 < lc; c0 += SW) {
+    const int tc = min(SW, lc - c0);
+    __syncthreads();
+    load_strip(X, base, v.trans, b, bx, r, n, c0, tc);
+    __syncthreads();
+    strip_product<T, 1>(Lig, n, X, n, tc, base, v.trans, b, bx, r, c0);
+  }
+}
+
+// Elimination of S_ii for steps with 64 < b_i <= BG_MAXB: blocked Cholesky in
+// FP64 of the n_i x n_i trailing block (one workgroup per step, the matrix W
+// in the step's scratch): per 64-column block the diagonal block is factored
+// in LDS with its inverse (chol_inv_lds), the panel below is multiplied by
+// L_kk^{-T} and the trailing lower triangle updated, 64 x 64 tiles on the FP64
+// matrix cores.  L_nn^{-1} by block columns, Li_IJ = -L_II^{-1} sum_{K=J}^{I-1}
+// L_IK Li_KJ (kept transposed in W's free upper triangle, the diagonal
+// inverses after W); then the basis panel L^{-1} D(n_i, basis) and the factor
+// are written as k_potrf writes them.
+template <typename T>
+size_t work_potrf_big(int bmax) {
+  const size_t a = (size_t)2 * 64 * TLD * sizeof(double), s = work_strip_big<T>(bmax);
+  return a > s ? a : s;
+}
+
+// C (64 x 64 in registers of the four wavefronts, rows 16 w..) += A B with
+// A(row, k) and B(k, col) given by accessors, k < K.
+template <typename FA, typename FB>
+__device__ inline void tile_product(dbl4 acc[4], int K, FA fa, FB fb) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, fr = lane & 15, fk = lane >> 4;
+  const int K4 = (K + 3) & ~3;
+#pragma unroll 2
+  for (int k0 = 0; k0 < K4; k0 += 4) {
+    const int k = k0 + fk;
+    const double av = k < K ? fa(16 * wv + fr, k) : 0.0;
+    double bv[4];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) bv[tj] = k < K ? fb(k, 16 * tj + fr) : 0.0;
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_potrf_big(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b <= 64 || b > BG_MAXB) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  T* D = A.arena + A.slot_off[i];
+  double* W = A.big + (int64_t)blockIdx.x * A.big_stride;   // n x n
+  double* DI = W + (int64_t)n * n;                           // inverses of the diagonal blocks, 64 x 64 each
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* S = reinterpret_cast<double*>(smem_raw);
+  double* X = S + 64 * TLD;
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < n * n; e += NT) W[e] = (double)D[(int64_t)(r + e / n) * b + r + e % n];
+  __syncthreads();
+  const int nt = (n + 63) / 64;
+  dbl4 acc[4];
+  auto zero = [&]() {
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+  };
+  // ---- blocked right-looking Cholesky ----------------------------------------
+  for (int kt = 0; kt < nt; ++kt) {
+    const int kb = 64 * kt, nb = min(64, n - kb);
+    for (int e = tid; e < 64 * 64; e += NT) {
+      const int a = e >> 6, c = e & 63;
+      S[a * TLD + c] = (a < nb && c < nb) ? W[(int64_t)(kb + a) * n + kb + c] : 0.0;
+      X[a * TLD + c] = a == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    chol_inv_lds(S, X, nb, &bad);
+    for (int e = tid; e < 64 * 64; e += NT) {
+      const int a = e >> 6, c = e & 63;
+      if (a < nb && c <= a) W[(int64_t)(kb + a) * n + kb + c] = S[a * TLD + c];
+      DI[(int64_t)kt * 4096 + e] = (a < nb && c <= a) ? X[a * TLD + c] : 0.0;
+    }
+    __syncthreads();
+    // panel: W[I, K] <- W[I, K] L_kk^{-T}; each wavefront its own 16 rows
+    for (int i0 = kb + nb; i0 < n; i0 += 64) {
+      zero();
+      tile_product(acc, nb, [&](int row, int k) { return i0 + row < n ? W[(int64_t)(i0 + row) * n + kb + k] : 0.0; },
+                   [&](int k, int col) { return col < nb ? X[col * TLD + k] : 0.0; });
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = i0 + 16 * wv + 4 * j + fk, col = 16 * tj + fr;
+          if (row < n && col < nb) W[(int64_t)row * n + kb + col] = acc[tj][j];
+        }
+    }
+    __syncthreads();
+    // trailing lower triangle: W[I, J] -= P_I P_J^T, P = W[:, K]
+    for (int ti = kt + 1; ti < nt; ++ti)
+      for (int tjb = kt + 1; tjb <= ti; ++tjb) {
+        const int i0 = 64 * ti, j0 = 64 * tjb;
+        zero();
+        tile_product(acc, nb, [&](int row, int k) { return i0 + row < n ? W[(int64_t)(i0 + row) * n + kb + k] : 0.0; },
+                     [&](int k, int col) { return j0 + col < n ? W[(int64_t)(j0 + col) * n + kb + k] : 0.0; });
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int row = i0 + 16 * wv + 4 * j + fk, col = j0 + 16 * tj + fr;
+            if (row < n && col < n && col <= row) W[(int64_t)row * n + col] -= acc[tj][j];
+          }
+      }
+    __syncthreads();
+  }
+  // ---- L^{-1} by block columns (Li_IJ^T into W's upper triangle) ------------
+  for (int jt = 0; jt < nt; ++jt) {
+    for (int it = jt + 1; it < nt; ++it) {
+      const int i0 = 64 * it, j0 = 64 * jt;
+      const int ni = min(64, n - i0);
+      // Z = sum_{K=J}^{I-1} L_IK Li_KJ
+      zero();
+      for (int kt = jt; kt < it; ++kt) {
+        const int k0 = 64 * kt, nk = min(64, n - k0);
+        if (kt == jt)
+          tile_product(acc, nk, [&](int row, int k) { return row < ni ? W[(int64_t)(i0 + row) * n + k0 + k] : 0.0; },
+                       [&](int k, int col) { return DI[(int64_t)jt * 4096 + k * 64 + col]; });
+        else
+          tile_product(acc, nk, [&](int row, int k) { return row < ni ? W[(int64_t)(i0 + row) * n + k0 + k] : 0.0; },
+                       [&](int k, int col) { return j0 + col < n ? W[(int64_t)(j0 + col) * n + k0 + k] : 0.0; });
+      }
+      // Z into LDS, then Li_IJ = -L_II^{-1} Z
+      __syncthreads();
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) S[(16 * wv + 4 * j + fk) * TLD + 16 * tj + fr] = acc[tj][j];
+      __syncthreads();
+      zero();
+      tile_product(acc, ni, [&](int row, int k) { return DI[(int64_t)it * 4096 + row * 64 + k]; },
+                   [&](int k, int col) { return S[k * TLD + col]; });
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = 16 * wv + 4 * j + fk, c = 16 * tj + fr;
+          if (a < ni && j0 + c < n) W[(int64_t)(j0 + c) * n + i0 + a] = -acc[tj][j];
+        }
+      __syncthreads();
+    }
+  }
+  // ---- L_nn^{-1} (T), min pivot, error ---------------------------------------
+  T* Lig = A.Li + A.u_off[i];
+  for (int e = tid; e < n * n; e += NT) {
+    const int j = e / n, k = e % n, jt = j >> 6, kt = k >> 6;
+    double v = 0.0;
+    if (k <= j) v = jt == kt ? DI[(int64_t)jt * 4096 + (j & 63) * 64 + (k & 63)] : W[(int64_t)k * n + j];
+    Lig[e] = (T)v;
+  }
+  if (tid == 0) {
+    double mp = 1e300;
+    for (int k = 0; k < n; ++k) mp = fmin(mp, W[(int64_t)k * n + k]);
+    A.minpiv[i] = mp;
+    if (bad && atomicCAS(A.err, 0, 1) == 0) A.err[1] = i;
+  }
+  __syncthreads();   // L_nn^{-1} written (global, this workgroup)
+  // ---- basis panel D(n, basis) <- L^{-1} D(n, basis), strips of 64 columns --
+  T* Xs = reinterpret_cast<T*>(smem_raw);
+  for (int c0 = 0; c0 < r; c0 += Strip<T>::SW) {
+    const int tc = min(Strip<T>::SW, r - c0);
+    __syncthreads();
+    load_strip(Xs, D, 0, b, b, r, n, c0, tc);
+    __syncthreads();
+    strip_product<T, 1>(Lig, n, Xs, n, tc, D, 0, b, b, r, c0);
+  }
+  __syncthreads();
+  // ---- the factor: rows n of D hold [L^{-1} D(n, basis) | L], D(basis, n) = 0
+  for (int e = tid; e < n * n; e += NT) {
+    const int j = e / n, c = e % n;
+    D[(int64_t)(r + j) * b + r + c] = c <= j ? (T)W[(int64_t)j * n + c] : T(0);
+  }
+  for (int e = tid; e < r * n; e += NT) D[(int64_t)(e / n) * b + r + e % n] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Learned ranks by a capped rank-revealing factorization (rank_mode
+// LEARNED_CAP, any block size): the MLP's width l = min(k + 8, b) caps the
+// pivoted Cholesky of the far row's Gram matrix in the exact kernels
+// (k_compress_gram, k_bg_eig); a capped step is kept only if the energy the
+// cap leaves out cannot change the rank (lambda_{r+1} + bound <= theta^2),
+// otherwise it is redone without the cap.  This kernel computes the features
+// of every far row (Frobenius norms of the row and of its far blocks against
+// theta, widths, counts, neighbour ranks: the same 16 as k_compress_rand) and
+// evaluates the MLP: one workgroup per step.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_feat_mlp(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (A.rec && tid < REC_W) A.rec[(A.rec_off + i) * REC_W + tid] = tid < NFEAT ? 0.0f : -1.0f;
+  if (st.nfar == 0 || b == 0) {
+    if (tid == 0) A.lwidth[i] = b;   // nothing to compress: no cap
+    return;
+  }
+  __shared__ double red[NT / WV];
+  __shared__ double xf[NFEAT];
+  __shared__ double hbuf[MLP_H];
+  const double theta = *A.theta;
+  double fro2 = 0.0, cmax2 = 0.0, bsum4 = 0.0, prs = 0.0, pss = 0.0;
+  int ccnt = 0, wtot = 0, nproc = 0;
+  for (int f = st.nclose; f < st.nclose + st.nfar; ++f) {
+    const View v = A.views[st.view0 + f];
+    const int bx = A.bsz[v.x];
+    const int w = v.proc ? A.rank[v.x] : bx;
+    const T* base = A.arena + A.slot_off[v.slot];
+    wtot += w;
+    if (v.proc) {
+      ++nproc;
+      prs += A.rank[v.x];
+      pss += bx;
+    }
+    double s2 = 0.0;
+    for (int e = tid; e < b * w; e += NT) {
+      // the unit-stride index on consecutive threads for either storage
+      const int a = v.trans ? e % b : e / w, c = v.trans ? e / b : e % w;
+      const double x = (double)*view_ptr(base, v.trans, b, bx, a, c);
+      s2 += x * x;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) red[wv] = s2;
+    __syncthreads();
+    const double bn2 = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    fro2 += bn2;
+    cmax2 = fmax(cmax2, bn2);
+    ccnt += bn2 > theta * theta ? 1 : 0;
+    bsum4 += bn2 * bn2;
+  }
+  if (tid == 0) {
+    const double cmax = sqrt(cmax2), fro = sqrt(fro2);
+    xf[0] = log2((double)b + 1.0);
+    xf[1] = log2((double)wtot + 1.0);
+    xf[2] = (double)A.level;
+    xf[3] = (double)st.nfar;
+    xf[4] = (double)st.nclose;
+    xf[5] = clog10(fro, theta);
+    xf[6] = clog10(sqrt(fro2 / max(b, 1)), theta);
+    xf[7] = clog10(cmax, theta);
+    xf[8] = clog10(sqrt(fro2 / max(wtot, 1)), theta);
+    xf[9] = (double)ccnt / (double)max(st.nfar, 1);
+    xf[10] = fro2 > 0.0 ? bsum4 / (fro2 * fro2) : 0.0;
+    xf[11] = cmax2 > 0.0 ? fro2 / (cmax2 * st.nfar) : 0.0;
+    xf[12] = (double)nproc / (double)max(st.nfar, 1);
+    xf[13] = pss > 0.0 ? prs / pss : 0.0;
+    xf[14] = b / 64.0;
+    xf[15] = 1.0;
+  }
+  __syncthreads();
+  if (A.rec && tid < NFEAT) A.rec[(A.rec_off + i) * REC_W + tid] = (float)xf[tid];
+  if (A.feat_only || !A.mlp) {
+    if (tid == 0) A.lwidth[i] = b;
+    return;
+  }
+  if (wv == 0) {
+    const float* P = A.mlp;
+    double h = P[MLP_OFF_B1 + lane];
+    for (int k = 0; k < NFEAT; ++k)
+      h += (double)P[MLP_OFF_W1 + lane * NFEAT + k] * ((xf[k] - (double)P[MLP_OFF_MEAN + k]) / (double)P[MLP_OFF_STD + k]);
+    hbuf[lane] = fmax(h, 0.0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double h2 = P[MLP_OFF_B2 + lane];
+    for (int k = 0; k < MLP_H; ++k) h2 += (double)P[MLP_OFF_W2 + lane * MLP_H + k] * hbuf[k];
+    h2 = fmax(h2, 0.0);
+    const double z = wave_sum((double)P[MLP_OFF_W3 + lane] * h2) + (double)P[MLP_OFF_B3];
+    if (lane == 0) {
+      const double bz = z * b;
+      const int k = (bz == bz) ? (int)fmin(fmax(ceil(bz), 0.0), (double)b) : b;
+      A.lwidth[i] = min(k + SKETCH_OVERSAMPLE, b);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -3610,40 +4676,85 @@ bool factor_needs_global(int bmax) {
   return factor_scratch_elems<T>(bmax) * sizeof(T) > max_lds_bytes();
 }
 
+// The exact compression of a wave (or, with A.lwidth, its capped first pass):
+// the size classes in turn, the generic kernel for what they leave.  With
+// retry = true only the steps flagged in big_fail are redone, uncapped, and the
+// big-block Gram matrices are not formed again (a rejected step leaves its own
+// intact).
+template <typename T>
+static void compress_pass(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs, hipStream_t stream,
+                          bool retry) {
+  const int ns = w.s1 - w.s0;
+  const size_t wg = work_compress_wg<T>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
+  const size_t wgr = work_compress_gram<T, 64>(), wgr2 = work_compress_gram<T, 128>();
+  const bool gram = sizeof(T) < sizeof(double) && wgr <= max_lds_bytes();
+  const bool gram2 = gram && wgr2 <= max_lds_bytes();
+  const bool bigc = A.big && work_bg_eig<T>() <= max_lds_bytes() &&
+                    (size_t)2 * 64 * TLD * sizeof(T) <= max_lds_bytes();
+  auto big_pass = [&](int small) {
+    LevelArgs<T> C = A;
+    C.small_by_wave = small;
+    if (bigc && bmax >= BG_MIN) {
+      // big blocks: Gram tiles on many workgroups, then one workgroup per
+      // step; the generic kernel takes only what they leave (blocks above
+      // BG_MAXB, Gram matrices whose rank cannot be settled within BG_MA pivots)
+      const int nt = (std::min(bmax, BG_MAXB) + 63) / 64;
+      if (!retry)
+        hipLaunchKernelGGL(k_bg_gram<T>, dim3(ns, nt * (nt + 1) / 2), dim3(NT), (size_t)2 * 64 * TLD * sizeof(T),
+                           stream, A, w.s0);
+      hipLaunchKernelGGL(k_bg_eig<T>, dim3(ns), dim3(NT), work_bg_eig<T>(), stream, A, w.s0);
+      C.big_retry = 1;
+      C.need_exact = nullptr;
+      C.lwidth = nullptr;
+    }
+    // (the first pass of LEARNED_CAP leaves the generic kernel to the retry)
+    if (!A.lwidth || retry) launch<T>(k_compress<T>, C, w.s0, ns, work_compress<T>(bmax), gs, stream, bmax);
+  };
+  if (gram)
+    hipLaunchKernelGGL((k_compress_gram<T, 64>), dim3(ns), dim3(NT), wgr, stream, A, w.s0);
+  else if (!retry)
+    hipLaunchKernelGGL(k_compress_wg<T>, dim3(ns), dim3(NT), wg, stream, A, w.s0);
+  if (bmax > 64 && gram2) {
+    hipLaunchKernelGGL((k_compress_gram<T, 128>), dim3(ns), dim3(NT), wgr2, stream, A, w.s0);
+    if (bmax > 128) big_pass(128);
+  } else if (bmax > 64) {
+    const bool wave128 = w128 <= max_lds_bytes();
+    if (wave128 && !retry) hipLaunchKernelGGL((k_compress_wave<T, 128>), dim3(ns), dim3(WV), w128, stream, A, w.s0);
+    if (bmax > 128 || !wave128) big_pass(wave128 ? 128 : 64);
+  }
+}
+
 template <typename T>
 void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
-  T* gs = gscratch;
-  if (w.s1 > w.s0) {
-    const int ns = w.s1 - w.s0;
-    // learned ranks (or feature recording): the sketch kernel first; the exact
-    // kernels then take only the steps it flags in need_exact
-    if (A.mlp || A.feat_only)
-      hipLaunchKernelGGL(k_compress_rand<T>, dim3(ns), dim3(NT), work_compress_rand<T>(), stream, A, w.s0);
-    const size_t wg = work_compress_wg<T>() * sizeof(T), w128 = work_compress_wave<T, 128>() * sizeof(T);
-    const size_t wgr = work_compress_gram<T, 64>(), wgr2 = work_compress_gram<T, 128>();
-    const bool gram = sizeof(T) < sizeof(double) && wgr <= max_lds_bytes();
-    const bool gram2 = gram && wgr2 <= max_lds_bytes();
-    if (gram)
-      hipLaunchKernelGGL((k_compress_gram<T, 64>), dim3(ns), dim3(NT), wgr, stream, A, w.s0);
-    else
-      hipLaunchKernelGGL(k_compress_wg<T>, dim3(ns), dim3(NT), wg, stream, A, w.s0);
-    if (bmax > 64 && gram2) {
-      hipLaunchKernelGGL((k_compress_gram<T, 128>), dim3(ns), dim3(NT), wgr2, stream, A, w.s0);
-      if (bmax > 128) {
-        LevelArgs<T> C = A;
-        C.small_by_wave = 128;
-        launch<T>(k_compress<T>, C, w.s0, ns, work_compress<T>(bmax), gs, stream, bmax);
-      }
-    } else if (bmax > 64) {
-      if (bmax <= 128 && w128 <= max_lds_bytes()) {
-        hipLaunchKernelGGL((k_compress_wave<T, 128>), dim3(ns), dim3(WV), w128, stream, A, w.s0);
-      } else {
-        LevelArgs<T> C = A;
-        C.small_by_wave = 64;
-        launch<T>(k_compress<T>, C, w.s0, ns, work_compress<T>(bmax), gs, stream, bmax);
-      }
-    }
+  if (w.s1 <= w.s0) return;
+  const int ns = w.s1 - w.s0;
+  if (A.lwidth) {
+    // learned ranks by a capped rank-revealing factorization: features and
+    // MLP width, the capped pass, then the rejected steps without the cap
+    hipLaunchKernelGGL(k_feat_mlp<T>, dim3(ns), dim3(NT), 0, stream, A, w.s0);
+    compress_pass<T>(A, w, bmax, gscratch, stream, false);
+    LevelArgs<T> R = A;
+    R.lwidth = nullptr;
+    R.need_exact = A.big_fail;
+    R.cap_retry = 1;
+    compress_pass<T>(R, w, bmax, gscratch, stream, true);
+    return;
   }
+  if (A.feat_only) {
+    // training records: the features of every far row (any block size), then
+    // the exact compression of every step, which writes the labels
+    LevelArgs<T> F = A;
+    F.lwidth = A.need_exact;   // scratch for the widths (not used)
+    hipLaunchKernelGGL(k_feat_mlp<T>, dim3(ns), dim3(NT), 0, stream, F, w.s0);
+    LevelArgs<T> E = A;
+    E.need_exact = nullptr;
+    compress_pass<T>(E, w, bmax, gscratch, stream, false);
+    return;
+  }
+  // learned ranks by sketches: the sketch kernel first; the exact kernels
+  // then take only the steps it flags in need_exact
+  if (A.mlp) hipLaunchKernelGGL(k_compress_rand<T>, dim3(ns), dim3(NT), work_compress_rand<T>(), stream, A, w.s0);
+  compress_pass<T>(A, w, bmax, gscratch, stream, false);
 }
 
 template <typename T>
@@ -3653,31 +4764,51 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   const bool tiled = wt <= max_lds_bytes();
   LevelArgs<T> B = A;
   if (tiled) B.small_by_wave = 64;   // the generic kernels skip the steps the tiled ones take
-  const bool generic = !tiled || bmax > 64;
+  // steps of 65..BG_MAXB unknowns: tiled big-block kernels (strips of the
+  // views in LDS, products on the FP64 matrix cores); the generic kernels then
+  // take only larger blocks
+  const size_t wsb = work_strip_big<T>(bmax);
+  const bool big = tiled && bmax > 64 && A.big && wsb <= max_lds_bytes();
+  LevelArgs<T> G = B;
+  if (big) G.small_by_wave = BG_MAXB;
+  const bool generic = !tiled || (bmax > 64 && (!big || bmax > BG_MAXB));
   B.items = A.rot;
+  G.items = A.rot;
   if (tiled && w.r1 > w.r0)
     hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
-  if (generic) launch<T>(k_rotate<T>, B, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream, bmax);
+  if (big && w.r1 > w.r0) {
+    hipLaunchKernelGGL(k_rot_big<T>, dim3(w.r1 - w.r0), dim3(NT), wsb, stream, B, w.r0);
+    hipLaunchKernelGGL(k_rot_big_diag<T>, dim3(w.s1 - w.s0), dim3(NT), wsb, stream, B, w.s0);
+  }
+  if (generic) launch<T>(k_rotate<T>, G, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream, bmax);
   if (A.compensate && w.s1 > w.s0)
     hipLaunchKernelGGL(k_compensate<T>, dim3(w.s1 - w.s0), dim3(NT), 0, stream, A, w.s0);
   const bool ptiled = tiled && (size_t)PW4_LDS <= max_lds_bytes();
   if (ptiled && w.s1 > w.s0)
     hipLaunchKernelGGL(k_potrf_w<T>, dim3(w.s1 - w.s0), dim3(NT), PW4_LDS, stream, B, w.s0);
-  if (!ptiled)
+  const size_t wpb = work_potrf_big<T>(bmax);
+  if (!ptiled) {
     launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
-  else if (generic)
-    launch<T>(k_potrf<T>, B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
+  } else if (bmax > 64) {
+    const bool pbig = big && wpb <= max_lds_bytes();
+    if (pbig && w.s1 > w.s0) hipLaunchKernelGGL(k_potrf_big<T>, dim3(w.s1 - w.s0), dim3(NT), wpb, stream, B, w.s0);
+    if (!pbig || bmax > BG_MAXB)
+      launch<T>(k_potrf<T>, pbig ? G : B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
+  }
   B.items = A.trsm;
+  G.items = A.trsm;
   if (tiled && w.t1 > w.t0)
     hipLaunchKernelGGL(k_trsm_t<T>, dim3(w.t1 - w.t0), dim3(NT), wt, stream, B, w.t0);
-  if (generic) launch<T>(k_trsm<T>, B, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream, bmax);
+  if (big && w.t1 > w.t0) hipLaunchKernelGGL(k_trsm_big<T>, dim3(w.t1 - w.t0), dim3(NT), wsb, stream, B, w.t0);
+  if (generic) launch<T>(k_trsm<T>, G, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream, bmax);
   if (tiled && w.p1 > w.p0) {
     if (A.bf16_schur && sizeof(T) == sizeof(float))
       hipLaunchKernelGGL(k_schur_bf16<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
     else
       hipLaunchKernelGGL(k_schur_t<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
   }
-  if (generic) launch<T>(k_schur<T>, B, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream, bmax);
+  if (big && w.p1 > w.p0) hipLaunchKernelGGL(k_schur_big<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+  if (generic) launch<T>(k_schur<T>, G, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream, bmax);
 }
 
 template <typename T>

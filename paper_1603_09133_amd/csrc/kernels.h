@@ -47,7 +47,20 @@ struct LevelArgs {
   int32_t* lcount;          // [0] sketches accepted, [1] sketches rejected
   int32_t bf16_schur;       // FP32 factor: Schur products with BF16 inputs on the matrix cores
   int32_t compensate;       // add |E_i| to the diagonals (k_compensate) instead of plain dropping
+  // big-block compression (FP32 factor, blocks above 128 unknowns): per-step
+  // scratch of the wave (Gram matrix, then kept directions; pivoted Cholesky
+  // rows), bg_stride(bmax) doubles per step of the wave, or null
+  double* big;
+  int64_t big_stride;
+  int32_t* big_fail;        // per block: 1 = left to the generic compression
+  int32_t big_retry;        // generic compression: only the blocks flagged in big_fail
+  // learned ranks by a capped rank-revealing factorization (LEARNED_CAP)
+  int32_t* lwidth;          // per block: the MLP's width, caps the pivoted Cholesky; or null
+  int32_t cap_retry;        // uncapped pass over the steps a capped pass rejected
 };
+
+// doubles of big-block compression scratch per step of a wave
+int64_t bg_stride(int bmax);
 
 // learned rank: feature count, record width, MLP parameter layout (floats):
 // mean[16], std[16], W1[64x16], b1[64], W2[64x64], b2[64], w3[64], b3

@@ -253,6 +253,8 @@ struct NumLevel {
   std::vector<cae::WaveRange> waves;
   DevBuf arena, U, Li, bsz, d_slot_off, d_u_off, d_dof_off, d_off_in_parent, rank, edrop, minpiv;
   DevBuf need_exact;   // learned ranks: steps the exact compression takes
+  DevBuf big_fail;     // steps left to a later compression pass
+  DevBuf lwidth;       // LEARNED_CAP: the MLP's width of every step
   double end_ms = 0;   // host time since the factorization began when the level's ranks were back
 };
 
@@ -269,7 +271,7 @@ struct cae_factor_s {
   std::vector<NumLevel> lev;      // lev[0..K]; lev[K] is the dense remainder
   int32_t K = 0;                  // factored levels
   int64_t coarse_dim = 0;
-  DevBuf Ainv, Acopy, vals, theta, err, gscratch, gj_p, gj_w, gj_r;
+  DevBuf Ainv, Acopy, vals, theta, err, gscratch, gj_p, gj_w, gj_r, bigbuf;
   double tau = 0, dropped = 0, min_pivot = 0, factor_ms = 0;
   int64_t factor_bytes = 0;
   int32_t compress_launches = 0, compressions = 0;
@@ -404,6 +406,12 @@ cae::LevelArgs<T> level_args(cae_factor_s* h, int l) {
   A.lcount = nullptr;
   A.bf16_schur = h->precision == CAE_FP32_BF16 ? 1 : 0;
   A.compensate = h->opt.compensate ? 1 : 0;
+  A.big = nullptr;
+  A.big_stride = 0;
+  A.big_fail = nullptr;
+  A.big_retry = 0;
+  A.lwidth = nullptr;
+  A.cap_retry = 0;
   return A;
 }
 
@@ -484,6 +492,27 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       gs = h->gscratch.as<T>();
     }
     cae::LevelArgs<T> A = level_args<T>(h, l);
+    // steps left to a later compression pass (big blocks, learned caps)
+    N.big_fail.alloc((size_t)L.M * sizeof(int32_t));
+    HIPCHK(hipMemsetAsync(N.big_fail.p, 0, (size_t)L.M * sizeof(int32_t), s));
+    A.big_fail = N.big_fail.as<int32_t>();
+    if (N.bmax > 64) {
+      // big-block scratch (compression, rotation of the diagonal blocks,
+      // elimination): the steps of the largest wave
+      size_t wmax = 0;
+      for (auto& w : N.waves) wmax = std::max(wmax, (size_t)(w.s1 - w.s0));
+      const int64_t stride = cae::bg_stride(std::min(N.bmax, 512));
+      h->bigbuf.alloc(wmax * (size_t)stride * sizeof(double));
+      A.big = h->bigbuf.as<double>();
+      A.big_stride = stride;
+    }
+    if (h->opt.rank_mode == CAE_RANK_LEARNED_CAP) {
+      N.lwidth.alloc((size_t)L.M * sizeof(int32_t));
+      A.lwidth = N.lwidth.as<int32_t>();
+      A.mlp = h->opt.mlp_params;
+      A.lcount = h->lcount.as<int32_t>();
+      A.rank_mode = 0;   // the kept rank is the threshold rank
+    }
     if (h->opt.rank_mode == CAE_RANK_LEARNED || h->opt.record) {
       N.need_exact.alloc((size_t)L.M * sizeof(int32_t));
       A.need_exact = N.need_exact.as<int32_t>();
@@ -1080,10 +1109,13 @@ int checked_options(cae_analysis_t an, double eps, const cae_options_t* opt, cae
   }
   if (o.precision != CAE_FP64 && o.precision != CAE_FP32 && o.precision != CAE_FP32_BF16)
     return fail(CAE_EINVAL, "unknown precision");
-  if (o.rank_mode != CAE_RANK_EPS && o.rank_mode != CAE_RANK_FIXED && o.rank_mode != CAE_RANK_LEARNED)
+  if (o.rank_mode != CAE_RANK_EPS && o.rank_mode != CAE_RANK_FIXED && o.rank_mode != CAE_RANK_LEARNED &&
+      o.rank_mode != CAE_RANK_LEARNED_CAP)
     return fail(CAE_EINVAL, "unknown rank mode");
-  if (o.rank_mode == CAE_RANK_LEARNED && (!o.mlp_params || !(eps > 0.0)))
+  if ((o.rank_mode == CAE_RANK_LEARNED || o.rank_mode == CAE_RANK_LEARNED_CAP) && (!o.mlp_params || !(eps > 0.0)))
     return fail(CAE_EINVAL, "learned ranks need mlp_params and eps > 0");
+  if (o.rank_mode == CAE_RANK_LEARNED_CAP && o.record)
+    return fail(CAE_EINVAL, "training records come from CE(eps) or LEARNED factorizations");
   if (o.record && (o.record_cap <= 0 || o.rank_mode == CAE_RANK_FIXED))
     return fail(CAE_EINVAL, "record needs record_cap > 0 and a threshold rank mode");
   if (o.rank_mode == CAE_RANK_FIXED && o.fixed_rank < 0) return fail(CAE_EINVAL, "fixed_rank must be >= 0");

@@ -220,3 +220,93 @@ def test_training_lowers_rejections_and_keeps_iterations():
     assert res["trained"][0] < 0.3
     assert np.all(res["trained"][1] <= it_e + 1)
     an.close()
+
+
+def test_learned_cap_wide_equals_exact_and_trained_keeps_exact_ranks():
+    """LEARNED_CAP (the MLP's width caps the pivoted Cholesky of the far rows'
+    Gram matrices, FP32 factor): a predictor that asks for the full width
+    gives bitwise the exact factor; a trained predictor caps most steps, and
+    every kept capped step has the exact rank (the acceptance test bounds
+    sigma_{r+1} by theta), so level 1, whose far rows are the exact
+    factorization's, has the exact ranks wherever no singular value lies at
+    the FP32 rounding level of theta; PCG needs at most one iteration more.
+    The 3D problem with sibling coarsening holds blocks of up to 215
+    unknowns at level 2 (the big-block compression capped as well)."""
+    cae = _cae()
+    from paper_1603_09133_amd import learned
+    eps = 1e-4
+    A, csr, perm, bp, co = _setup((20, 20, 20), (4, 4, 4))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    vals = torch.from_numpy(csr[2]).cuda()
+    n = A.shape[0]
+    X = torch.from_numpy(np.random.default_rng(12345).standard_normal((4, n))).cuda()
+    fe = cae.Factor(an, vals, eps, precision=cae.FP32, coarse_max_dim=0)
+    Me = fe.multiply(X).cpu().numpy()
+    # width = b: the cap never binds
+    wide = learned.init_params(3)
+    wide[cae._lib.lib().cae_mlp_param_count() - 1] = 1e3
+    fw = cae.Factor(an, vals, eps, precision=cae.FP32, coarse_max_dim=0, rank_mode=cae.RANK_LEARNED_CAP,
+                    mlp_params=wide)
+    assert np.array_equal(fw.multiply(X).cpu().numpy(), Me)
+    fw.close()
+    # trained on the records of a 24^3 problem
+    A2, csr2, p2, b2, c2 = _setup((24, 24, 24), (4, 4, 4))
+    an2 = cae.Analysis(csr2[0], csr2[1], p2, b2, c2)
+    rec = learned.record(an2, torch.from_numpy(csr2[2]).cuda(), eps, precision=cae.FP32, coarse_max_dim=0)
+    an2.close()
+    params, _ = learned.train(rec, epochs=600, lr=1e-3)
+    f = cae.Factor(an, vals, eps, precision=cae.FP32, coarse_max_dim=0, rank_mode=cae.RANK_LEARNED_CAP,
+                   mlp_params=params)
+    st = f.stats()
+    print("capped steps kept / redone:", st["sketch_accepted"], st["sketch_rejected"])
+    assert st["sketch_accepted"] > st["sketch_rejected"]
+    fo = oracle.ce_factor(*csr, perm, bp, co, oracle.CEOptions(eps=eps, order="multicolour", coarse_max_dim=0))
+    rg, lf = f.ranks(0), fo.levels[0]
+    for i in np.nonzero(rg != lf.r)[0]:
+        s = lf.sigma[i]
+        k = min(rg[i], lf.r[i])
+        assert abs(s[k] - fo.theta) <= 1e-5 * s[0], (i, rg[i], lf.r[i])
+    b = torch.from_numpy(problems.rhs_normal(n, 2, seed=4).T.copy()).cuda()
+    _, it_e, _ = fe.pcg(b, rtol=1e-8)
+    _, it, rel = f.pcg(b, rtol=1e-8)
+    assert f.converged and np.all(rel <= 1.0001e-8)
+    assert np.all(it <= it_e + 1)
+    f.close()
+    fe.close()
+    an.close()
+
+
+def test_c3_arithmetic_against_oracle():
+    """The mixed-precision arithmetic of the 128^3 workload on a 20^3 grid:
+    FP32 factor with BF16-input Schur products, learned ranks by the capped
+    rank-revealing factorization, sibling coarsening (blocks of up to 215
+    unknowns at level 2).  Against the FP64 oracle's exact CE(eps): M X within
+    the BF16 input rounding bound (2e-3, as for the exact-rank BF16 factor),
+    and PCG to 1e-8 converges in at most a few iterations more."""
+    cae = _cae()
+    from paper_1603_09133_amd import learned
+    eps = 1e-4
+    A2, csr2, p2, b2, c2 = _setup((24, 24, 24), (4, 4, 4))
+    an2 = cae.Analysis(csr2[0], csr2[1], p2, b2, c2)
+    rec = learned.record(an2, torch.from_numpy(csr2[2]).cuda(), eps, precision=cae.FP32, coarse_max_dim=0)
+    an2.close()
+    params, _ = learned.train(rec, epochs=600, lr=1e-3)
+    A, csr, perm, bp, co = _setup((20, 20, 20), (4, 4, 4))
+    fo = oracle.ce_factor(*csr, perm, bp, co, oracle.CEOptions(eps=eps, order="multicolour", coarse_max_dim=0))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co)
+    f = cae.Factor(an, torch.from_numpy(csr[2]).cuda(), eps, precision=cae.FP32_BF16, coarse_max_dim=0,
+                   rank_mode=cae.RANK_LEARNED_CAP, mlp_params=params)
+    assert max(int(f.sizes(l).max()) for l in range(f.stats()["nlevels"])) > 128
+    X = np.random.default_rng(12345).standard_normal((A.shape[0], 8))
+    Mo = oracle.ce_multiply(fo, X)
+    Mg = f.multiply(torch.from_numpy(np.ascontiguousarray(X.T)).cuda()).cpu().numpy().T
+    err = np.linalg.norm(Mg - Mo) / np.linalg.norm(Mo)
+    print(f"FP32/BF16 + learned caps probe error vs oracle: {err:.3e}")
+    assert err <= 2e-3
+    b = problems.rhs_normal(A.shape[0], 1, seed=0)[:, 0]
+    _, it, rel = f.pcg(torch.from_numpy(b.copy()).cuda(), rtol=1e-8)
+    _, ito, _ = oracle.pcg(A, b, lambda r: oracle.ce_solve(fo, r), tol=1e-8)
+    assert f.converged and rel[0] <= 1.0001e-8
+    assert it[0] <= ito + 6, (it[0], ito)
+    f.close()
+    an.close()

@@ -231,6 +231,75 @@ def test_fp32_factor_with_blocks_above_64():
     assert err <= 1e-5
 
 
+def test_fp32_factor_with_blocks_above_128():
+    """FP32 factor of a 3D Laplacian with the paper's coarsening (the eight
+    Morton siblings join, Section 2.5): the second level holds blocks of up to
+    215 unknowns, which take the big-block kernels (Gram tiles on the FP64
+    matrix cores, pivoted Cholesky, Jacobi on X X^T, reflectors).  Probe error
+    against the FP64 oracle within the FP32 bound, and that level's ranks equal
+    to the oracle's wherever the oracle's singular values are not within the
+    FP32 rounding level of the threshold."""
+    cae = _cae()
+    dims, patch, eps = (20, 20, 20), (4, 4, 4), 1e-4
+    A, csr, perm, bp, co = _setup(dims, patch)
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order="multicolour", coarse_max_dim=0))
+    an, f = _gpu_factor(cae, csr, perm, bp, co, eps, "multicolour", precision=cae.FP32, coarse=0)
+    big = [l for l in range(len(fo.levels)) if int(f.sizes(l).max()) > 128 and fo.levels[l].sigma]
+    assert big, "no level with blocks above 128 unknowns"
+    for l in big:
+        rg, lf, sz = f.ranks(l), fo.levels[l], f.sizes(l)
+        assert np.array_equal(sz, np.asarray(lf.sizes))
+        for i in np.nonzero(rg != lf.r)[0]:
+            s = lf.sigma[i]
+            k = min(rg[i], lf.r[i])
+            assert abs(s[k] - fo.theta) <= 1e-5 * s[0], (l, i, rg[i], lf.r[i])
+    X = _probes(A.shape[0])
+    Mo = ce_multiply(fo, X)
+    M32 = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    err = np.linalg.norm(M32 - Mo) / np.linalg.norm(Mo)
+    print(f"fp32 (b > 128) probe error vs oracle: {err:.3e}")
+    assert err <= 1e-5
+    # the dropped energy: every dropped sigma (<= theta) of an FP32 far row is
+    # perturbed by about u_32 ||F_i||, so sigma^2 by about 2 theta u_32 ||F_i||:
+    # relative to the total, ~2 u_32 ||F|| / theta (a few 1e-3 here)
+    st = f.stats()
+    ed_o = sum(float(np.sum(l.e)) for l in fo.levels)
+    print(f"dropped energy {st['dropped_sq']:.6e} vs oracle {ed_o:.6e}")
+    assert abs(st["dropped_sq"] - ed_o) <= 1e-2 * ed_o
+
+
+def test_random_coefficient_diffusion_fp32_matches_oracle():
+    """The 2D diffusion with a log-normal random coefficient (the 2048^2
+    workload's matrix family, here on 128^2: k = exp(GRF), harmonic-mean
+    faces, 8 x 8 patches, eps = 1e-5): the FP32 factor against the FP64
+    oracle, probe error within the FP32 bound, level-1 ranks equal except at
+    FP32-level ties, and PCG to 1e-8 in at most one iteration more."""
+    cae = _cae()
+    Ag, _ = problems.grf_diffusion_2d(128)
+    A, csr, perm, bp, co = _setup((128, 128), (8, 8), A=Ag)
+    eps = 1e-5
+    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order="multicolour"))
+    an, f = _gpu_factor(cae, csr, perm, bp, co, eps, "multicolour", precision=cae.FP32)
+    rg, lf = f.ranks(0), fo.levels[0]
+    for i in np.nonzero(rg != lf.r)[0]:
+        sv = lf.sigma[i]
+        k = min(rg[i], lf.r[i])
+        assert abs(sv[k] - fo.theta) <= 1e-5 * sv[0], (i, rg[i], lf.r[i])
+    X = _probes(A.shape[0])
+    Mo = ce_multiply(fo, X)
+    M32 = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    err = np.linalg.norm(M32 - Mo) / np.linalg.norm(Mo)
+    print(f"random-coefficient fp32 probe error vs oracle: {err:.3e}")
+    assert err <= 1e-5
+    B = problems.rhs_normal(A.shape[0], 2, seed=2)
+    its_o = [oracle.pcg(A, B[:, k], lambda r: ce_solve(fo, r), tol=1e-8)[1] for k in range(2)]
+    _, it, rel = f.pcg(_to_gpu_cols(B), rtol=1e-8)
+    assert f.converged and np.all(rel <= 1.0001e-8)
+    assert np.all(it <= np.array(its_o) + 1), (it, its_o)
+    f.close()
+    an.close()
+
+
 def test_solver_apply_graph_replays_equal_eager_launches():
     """The iterative solvers replay the captured apply graph: three PCG solves
     on one handle (the later ones replaying the graph captured by the first,
