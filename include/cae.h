@@ -114,6 +114,11 @@ typedef struct {
                               the handle.  Size it with cae_workspace_query.  The analysis'
                               own device arrays and the solvers' work vectors are not in it */
   size_t workspace_bytes;  /* size of workspace */
+  int32_t big_pivot_cap;   /* blocks of 129..512 unknowns: most rows of the pivoted Cholesky
+                              of the far row's Gram matrix (1..128; 0 = 128).  A step that
+                              needs more is certified by a spectral bound on its dropped
+                              part, or redone by the generic kernel (counted in
+                              cae_stats_t.big_*); a smaller cap sends more steps there */
 } cae_options_t;
 
 #define CAE_RECORD_WIDTH 17
@@ -325,6 +330,15 @@ typedef struct {
   double elim_flops;
   double schur_flops;
   double coarse_flops;
+  /* compressions of blocks of 129..512 unknowns, by how their rank was settled:
+     the pivoted Cholesky ran to the rounding level; it was truncated and the
+     energy left out (Frobenius norm) cannot change the rank; the spectral norm
+     of the dropped part was bounded by repeated squaring of its Gram matrix;
+     the generic kernel redid the step */
+  int32_t big_untruncated;
+  int32_t big_frobenius;
+  int32_t big_certified;
+  int32_t big_generic;
 } cae_stats_t;
 
 int cae_get_stats(cae_handle_t h, cae_stats_t* s);
@@ -336,6 +350,12 @@ int cae_get_level_ms(cae_handle_t h, int32_t level, double* ms);
 int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks);
 /* Block sizes b_i of a factored level (host, M entries). */
 int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes);
+/* Dropped energy ||E_i||_F^2 of every step of a factored level (host, M
+ * doubles, block index order; 0 where nothing was compressed): the terms of
+ * cae_stats_t.dropped_sq, for which ||A0 - M||_F^2 = 2 sum_i ||E_i||_F^2
+ * (every step is an orthogonal change of basis followed by an exact
+ * elimination, Proposition 2.1). */
+int cae_get_drops(cae_handle_t h, int32_t level, double* e);
 /*
  * Write the factor to a file for parity checks and offline inspection
  * (little-endian binary; T = float or double as the factor's precision, int32

@@ -65,7 +65,7 @@ def graph_order(indptr, indices, B):
 
 def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0, max_levels=0,
              coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0, record=None,
-             compensate=False, graphs=True, apply_split_steps=None, workspace=None):
+             compensate=False, graphs=True, apply_split_steps=None, workspace=None, big_pivot_cap=0):
     o = _lib.Options()
     lib().cae_default_options(C.byref(o))
     if workspace is not None:
@@ -87,6 +87,7 @@ def _options(order=ORDER_MULTICOLOUR, precision=FP64, rank_mode=RANK_EPS, fixed_
     o.coarse_max_dim = coarse_max_dim
     o.stream = stream
     o.timing = 1 if timing else 0
+    o.big_pivot_cap = int(big_pivot_cap)
     return o
 
 
@@ -176,7 +177,8 @@ class Factor:
 
     def __init__(self, analysis: Analysis, vals, eps, precision=FP64, rank_mode=RANK_EPS, fixed_rank=0,
                  max_levels=0, coarse_max_dim=2048, stream=None, timing=False, mlp_params=None, seed=0,
-                 record=None, compensate=False, graphs=True, apply_split_steps=None, workspace=None):
+                 record=None, compensate=False, graphs=True, apply_split_steps=None, workspace=None,
+                 big_pivot_cap=0):
         """``rank_mode=RANK_LEARNED`` needs ``mlp_params`` (float32 CUDA tensor of
         ``learned.param_count()`` entries); ``record`` (float32 CUDA tensor of
         shape ``(rows, RECORD_WIDTH)``) receives the training records;
@@ -186,7 +188,8 @@ class Factor:
         updates close blocks one workgroup per (step, block) (0 = never);
         ``workspace`` (a 256-byte aligned CUDA tensor of at least
         :func:`workspace_bytes` bytes, kept alive by the factor) holds every
-        device buffer of the numeric factorization."""
+        device buffer of the numeric factorization; ``big_pivot_cap`` (1..128,
+        0 = 128) bounds the pivoted Cholesky of blocks above 128 unknowns."""
         import torch
         if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.float64):
             raise TypeError("vals must be a float64 CUDA tensor")
@@ -203,7 +206,7 @@ class Factor:
                               fixed_rank=fixed_rank, max_levels=max_levels, coarse_max_dim=coarse_max_dim,
                               stream=sptr, timing=timing, mlp_params=mlp_params, seed=seed, record=record,
                               compensate=compensate, graphs=graphs, apply_split_steps=apply_split_steps,
-                              workspace=workspace)
+                              workspace=workspace, big_pivot_cap=big_pivot_cap)
         h = C.c_void_p()
         self._vals = vals.contiguous()
         check(lib().cae_factor_numeric(analysis.handle, self._vals.data_ptr(), float(eps), C.byref(self._opts),
@@ -236,6 +239,13 @@ class Factor:
         M = self.analysis.level_info(level)["M"]
         out = np.empty(M, np.int32)
         check(lib().cae_get_sizes(self._h, level, ptr(out)))
+        return out
+
+    def drops(self, level):
+        """``||E_i||_F^2`` of every step of a factored level (``cae_get_drops``)."""
+        M = self.analysis.level_info(level)["M"]
+        out = np.empty(M, np.float64)
+        check(lib().cae_get_drops(self._h, level, ptr(out)))
         return out
 
     def apply(self, r):

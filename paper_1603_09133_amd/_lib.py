@@ -35,7 +35,7 @@ class Options(C.Structure):
                 ("coarse_max_dim", C.c_int64), ("stream", C.c_void_p), ("mlp_params", C.c_void_p),
                 ("seed", C.c_uint64), ("record", C.c_void_p), ("record_cap", C.c_int64), ("coarsen", C.c_int32),
                 ("graphs", C.c_int32), ("apply_split_steps", C.c_int32), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t)]
+                ("workspace_bytes", C.c_size_t), ("big_pivot_cap", C.c_int32)]
 
 
 class LevelInfo(C.Structure):
@@ -49,7 +49,9 @@ class Stats(C.Structure):
                 ("factor_ms", C.c_double), ("compress_launches", C.c_int32), ("compress_ms", C.c_double),
                 ("compress_flops", C.c_double), ("compressions", C.c_int32), ("sketch_accepted", C.c_int32),
                 ("sketch_rejected", C.c_int32), ("record_rows", C.c_int64), ("rotate_flops", C.c_double),
-                ("elim_flops", C.c_double), ("schur_flops", C.c_double), ("coarse_flops", C.c_double)]
+                ("elim_flops", C.c_double), ("schur_flops", C.c_double), ("coarse_flops", C.c_double),
+                ("big_untruncated", C.c_int32), ("big_frobenius", C.c_int32), ("big_certified", C.c_int32),
+                ("big_generic", C.c_int32)]
 
 
 _lib = None
@@ -59,7 +61,7 @@ EXPORTS = [
     "cae_analysis_level_info", "cae_analysis_level_arrays", "cae_analysis_perm", "cae_analysis_destroy",
     "cae_factor_numeric", "cae_workspace_query", "cae_factor", "cae_apply_precond", "cae_apply_precond_noalloc", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
     "cae_get_stats",
-    "cae_get_ranks", "cae_get_sizes", "cae_get_level_ms", "cae_export_factor", "cae_destroy", "cae_mlp_param_count", "cae_mlp_train", "cae_mlp_loss_grad",
+    "cae_get_ranks", "cae_get_sizes", "cae_get_drops", "cae_get_level_ms", "cae_export_factor", "cae_destroy", "cae_mlp_param_count", "cae_mlp_train", "cae_mlp_loss_grad",
     "cae_mlp_predict",
 ]
 
@@ -97,6 +99,7 @@ def lib():
     L.cae_get_stats.argtypes = [p, C.POINTER(Stats)]
     L.cae_get_ranks.argtypes = [p, i32, p]
     L.cae_get_sizes.argtypes = [p, i32, p]
+    L.cae_get_drops.argtypes = [p, i32, p]
     L.cae_export_factor.argtypes = [p, C.c_char_p]
     L.cae_get_level_ms.argtypes = [p, i32, C.POINTER(dbl)]
     L.cae_destroy.argtypes = [p]
@@ -110,7 +113,7 @@ def lib():
                  "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_workspace_query", "cae_factor",
                  "cae_apply_precond",
                  "cae_apply_precond_noalloc", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
-                 "cae_get_sizes", "cae_get_level_ms", "cae_export_factor", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:
+                 "cae_get_sizes", "cae_get_drops", "cae_get_level_ms", "cae_export_factor", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -64,6 +64,9 @@ constexpr int BG_MIN = 129, BG_MAXB = 512, BG_MA = 128;
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* gscratch, int64_t per_wg) {
+  // FP64 arithmetic for either storage type (an FP32 far row is read into
+  // FP64); the rounding levels below are those of the stored entries
+  using W = double;
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -79,13 +82,13 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
     }
     return;
   }
-  T* work = dyn_work<T>(gscratch, per_wg);
+  W* work = reinterpret_cast<W*>(dyn_work<T>(gscratch, per_wg));
   const int ld = b + 1;
-  T* R = work;                       // b x ld
-  T* C = R + (int64_t)b * ld;        // max(QR_CH, b) x ld  (chunk, then V)
-  T* part = C + (int64_t)max(QR_CH, b) * ld;   // 4 x b partial dots, then sigma
-  T* cf = part + 4 * b;                        // b reflector coefficients
-  for (int e = tid; e < b * ld; e += NT) R[e] = T(0);
+  W* R = work;                       // b x ld
+  W* C = R + (int64_t)b * ld;        // max(QR_CH, b) x ld  (chunk, then V)
+  W* part = C + (int64_t)max(QR_CH, b) * ld;   // 4 x b partial dots, then sigma
+  W* cf = part + 4 * b;                        // b reflector coefficients
+  for (int e = tid; e < b * ld; e += NT) R[e] = W(0);
   __syncthreads();
 
   const int jl = tid & 63, g = tid >> 6;   // column lane, row group (4 groups)
@@ -99,29 +102,29 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
       // chunk row t = column c0 + t of F_i (row j of the chunk = unknown j of block i)
       for (int e = tid; e < m * b; e += NT) {
         int t = e % m, j = e / m;
-        C[t * ld + j] = *view_ptr(base, v.trans, b, bx, j, c0 + t);
+        C[t * ld + j] = (W)*view_ptr(base, v.trans, b, bx, j, c0 + t);
       }
       __syncthreads();
       for (int k = 0; k < b; ++k) {
         // (a) partial dots of column k with columns j >= k over rows t = g mod 4
         for (int j = k + jl; j < b; j += 64) {
-          T s = 0;
+          W s = 0;
           for (int t = g; t < m; t += 4) s += C[t * ld + k] * C[t * ld + j];
           part[g * b + j] = s;
         }
         __syncthreads();
         // (b) reflector H = I - tau v v^T with v = [R_kk - alpha; C(:,k)]
-        const T xn2 = part[k] + part[b + k] + part[2 * b + k] + part[3 * b + k];
-        const bool reflect = xn2 > Eps<T>::tiny();
+        const W xn2 = part[k] + part[b + k] + part[2 * b + k] + part[3 * b + k];
+        const bool reflect = xn2 > Eps<W>::tiny();
         if (reflect) {
-          const T rkk = R[k * ld + k];
-          const T nrm = sqrt(rkk * rkk + xn2);
-          const T alpha = rkk >= T(0) ? -nrm : nrm;
-          const T v0 = rkk - alpha;
-          const T tau = T(2) / (v0 * v0 + xn2);
+          const W rkk = R[k * ld + k];
+          const W nrm = sqrt(rkk * rkk + xn2);
+          const W alpha = rkk >= W(0) ? -nrm : nrm;
+          const W v0 = rkk - alpha;
+          const W tau = W(2) / (v0 * v0 + xn2);
           for (int j = k + 1 + jl; j < b; j += 64) {
-            const T s = v0 * R[k * ld + j] + part[j] + part[b + j] + part[2 * b + j] + part[3 * b + j];
-            const T coef = tau * s;
+            const W s = v0 * R[k * ld + j] + part[j] + part[b + j] + part[2 * b + j] + part[3 * b + j];
+            const W coef = tau * s;
             if (g == 0) cf[j] = coef;
             for (int t = g; t < m; t += 4) C[t * ld + j] -= coef * C[t * ld + k];
           }
@@ -130,10 +133,10 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
         // (c) row k of R: every thread has read it; wave 0 updates it while
         // the other waves start the next column (they touch C and part only)
         if (g == 0 && reflect) {
-          const T rkk = R[k * ld + k];
-          const T nrm = sqrt(rkk * rkk + xn2);
-          const T alpha = rkk >= T(0) ? -nrm : nrm;
-          const T v0 = rkk - alpha;
+          const W rkk = R[k * ld + k];
+          const W nrm = sqrt(rkk * rkk + xn2);
+          const W alpha = rkk >= W(0) ? -nrm : nrm;
+          const W v0 = rkk - alpha;
           for (int j = k + 1 + jl; j < b; j += 64) R[k * ld + j] -= cf[j] * v0;
           if (jl == 0) R[k * ld + k] = alpha;
         }
@@ -143,40 +146,41 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
   }
 
   // one-sided Jacobi on the columns of R; V accumulates the rotations
-  T* V = C;
-  for (int e = tid; e < b * ld; e += NT) V[e] = (e / ld == e % ld) ? T(1) : T(0);
+  W* V = C;
+  for (int e = tid; e < b * ld; e += NT) V[e] = (e / ld == e % ld) ? W(1) : W(0);
   // ||R||_F^2: columns below eps * ||R||_F are rounding noise of the QR; a
   // pair of two such columns is left alone (their mixing only touches
   // directions far below any resolvable singular value)
   {
-    T s = 0;
+    W s = 0;
     for (int e = tid; e < b * b; e += NT) {
-      const T x = R[(e / b) * ld + e % b];
+      const W x = R[(e / b) * ld + e % b];
       s += x * x;
     }
     part[tid] = s;     // the part/cf area holds at least NT entries
   }
   __syncthreads();
-  __shared__ T sh_norm2;
+  __shared__ W sh_norm2;
   if (tid == 0) {
-    T s = 0;
+    W s = 0;
     for (int k = 0; k < NT; ++k) s += part[k];
     sh_norm2 = s;
   }
   __syncthreads();
-  const T noise = Eps<T>::v() * sqrt(sh_norm2);
+  const W noise = (W)Eps<T>::v() * sqrt(sh_norm2);
   // two rows that both stay below theta/64 end in the dropped set whatever
   // their mutual rotation; they are left alone
-  const T negl = A.rank_mode == 0 ? max(noise, (T)(*A.theta / 64.0)) : noise;
+  const W negl = A.rank_mode == 0 ? max(noise, (W)(*A.theta / 64.0)) : noise;
   const int nb = b + (b & 1);
   const int npair = nb / 2;
   // rotation threshold: the computed a_p^T a_q of exactly orthogonal columns
   // carries a rounding error of a few b*eps, so the threshold must be above it
-  const T tol = T(max(b, 16)) * Eps<T>::v();
+  const W tol = W(max(b, 16)) * Eps<W>::v();
   // a rotation moves the smaller row of a pair by about |d| / max(na, nc);
-  // below the QR's own absolute rounding level (tol * ||R||) it is skipped
-  const T aerr = A.rank_mode == 0 ? max(noise, min(T(max(b, 16)) * noise, (T)(*A.theta / 32.0)))
-                                  : T(max(b, 16)) * noise;
+  // below the absolute rounding level of the stored entries and of the FP64
+  // QR it is skipped (then the singular values near theta, and so the rank,
+  // are those of the stored far row to that level)
+  const W aerr = max(noise, W(max(b, 16)) * Eps<W>::v() * sqrt(sh_norm2));
   const int lane8 = tid & 7;
   for (int sweep = 0; sweep < 60; ++sweep) {
     int rotated = 0;
@@ -191,9 +195,9 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
           q = (round - pp + (nb - 1)) % (nb - 1);
         }
         if (p >= b || q >= b) continue;
-        T a = 0, c = 0, d = 0;
+        W a = 0, c = 0, d = 0;
         for (int l = lane8; l < b; l += 8) {
-          const T x = R[l * ld + p], y = R[l * ld + q];
+          const W x = R[l * ld + p], y = R[l * ld + q];
           a += x * x;
           c += y * y;
           d += x * y;
@@ -203,21 +207,21 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
           c += __shfl_xor(c, o, 8);
           d += __shfl_xor(d, o, 8);
         }
-        const T na = sqrt(a), nc = sqrt(c);
-        if (d != T(0) && fabs(d) > tol * na * nc && (na > negl || nc > negl) &&
+        const W na = sqrt(a), nc = sqrt(c);
+        if (d != W(0) && fabs(d) > tol * na * nc && (na > negl || nc > negl) &&
             fabs(d) > aerr * max(na, nc)) {
-          const T zeta = (c - a) / (T(2) * d);
-          T t;
-          if (fabs(zeta) > T(1e15))
-            t = T(0.5) / zeta;
+          const W zeta = (c - a) / (W(2) * d);
+          W t;
+          if (fabs(zeta) > W(1e15))
+            t = W(0.5) / zeta;
           else
-            t = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
-          const T cs = T(1) / sqrt(T(1) + t * t), sn = cs * t;
+            t = (zeta >= W(0) ? W(1) : W(-1)) / (fabs(zeta) + sqrt(W(1) + zeta * zeta));
+          const W cs = W(1) / sqrt(W(1) + t * t), sn = cs * t;
           for (int l = lane8; l < b; l += 8) {
-            const T x = R[l * ld + p], y = R[l * ld + q];
+            const W x = R[l * ld + p], y = R[l * ld + q];
             R[l * ld + p] = cs * x - sn * y;
             R[l * ld + q] = sn * x + cs * y;
-            const T u = V[l * ld + p], z = V[l * ld + q];
+            const W u = V[l * ld + p], z = V[l * ld + q];
             V[l * ld + p] = cs * u - sn * z;
             V[l * ld + q] = sn * u + cs * z;
           }
@@ -229,9 +233,9 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
     if (!__syncthreads_or(rotated)) break;
   }
   // singular values = column norms; sort decreasing (ties by index)
-  T* sig = part;
+  W* sig = part;
   for (int j = tid; j < b; j += NT) {
-    T s = 0;
+    W s = 0;
     for (int l = 0; l < b; ++l) s += R[l * ld + j] * R[l * ld + j];
     sig[j] = sqrt(s);
   }
@@ -246,11 +250,11 @@ __global__ __launch_bounds__(NT) void k_compress(LevelArgs<T> A, int32_t s0, T* 
     r = min(A.fixed_rank, b);
   }
   for (int j = tid; j < b; j += NT) {
-    const T sj = sig[j];
+    const W sj = sig[j];
     int pos = 0;
     for (int k = 0; k < b; ++k) pos += (sig[k] > sj || (sig[k] == sj && k < j)) ? 1 : 0;
-    for (int l = 0; l < b; ++l) Ug[(int64_t)l * b + pos] = V[l * ld + j];
-    part[b + j] = (T)pos;
+    for (int l = 0; l < b; ++l) Ug[(int64_t)l * b + pos] = (T)V[l * ld + j];
+    part[b + j] = (W)pos;
   }
   __syncthreads();
   if (tid == 0) {
@@ -3598,7 +3602,8 @@ __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64
 // ---------------------------------------------------------------------------
 constexpr int BG_SLD = BG_MA + 4;   // row stride of S in LDS
 
-int64_t bg_stride(int bmax) { return (int64_t)bmax * bmax + (int64_t)BG_MA * bmax; }
+// per step: G (b x b), X (BG_MA x b), U in FP64 (b x b), work (b x b)
+int64_t bg_stride(int bmax) { return (int64_t)3 * bmax * bmax + (int64_t)BG_MA * bmax; }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0) {
@@ -3698,8 +3703,10 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
     }
     return;
   }
-  double* G = A.big + (int64_t)blockIdx.x * A.big_stride;   // b x b, later the kept directions
+  double* G = A.big + (int64_t)blockIdx.x * A.big_stride;   // b x b, left intact
   double* X = G + (int64_t)b * b;                              // BG_MA x b rows of the Cholesky factor
+  double* U64 = X + (int64_t)BG_MA * b;                        // U_i in FP64 (steps left to k_bg_cert)
+  double* V = U64 + (int64_t)b * b;                            // kept directions, then reflectors
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* S = reinterpret_cast<double*>(smem_raw);   // BG_MA x BG_SLD
   double* dg = S + BG_MA * BG_SLD;                   // trailing diagonal
@@ -3739,10 +3746,9 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   double inactive = 0.0;
   int k = 0;
   bool truncated = false;
-  // at most BG_MA pivots (the learned width does not cap big blocks: their far
-  // rows carry long tails of singular values just below theta, which no cap
-  // below BG_MA can leave out with a certified rank)
-  const int cap = BG_MA;
+  // at most bg_cap <= BG_MA pivots (the learned width does not cap big blocks:
+  // their far rows carry long tails of singular values just below theta)
+  const int cap = min(max(A.bg_cap, 1), BG_MA);
   for (;; ++k) {
     __syncthreads();   // dg and chosen of the previous pivot, rd free
     double rs = 0.0, cv = -1.0;
@@ -3866,8 +3872,11 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   // a truncated Cholesky leaves G2 = G - X^T X (positive semidefinite); the
   // step is kept if lambda_{r+1}(X^T X) + ||G2||_F <= theta^2: then
   // lambda_{r+1}(G) <= theta^2 too (Weyl, ||G2||_2 <= ||G2||_F), so r is the
-  // rank of F_i and the dropped part has spectral norm <= theta; otherwise the
-  // generic kernel takes the step
+  // rank of F_i and the dropped part has spectral norm <= theta; otherwise
+  // k_bg_cert bounds the dropped part's spectral norm itself (big_fail = 2)
+  // from the basis this kernel still writes (lambda_r(G) >= lambda_r(X^T X) >
+  // theta^2 holds in any case, as G - X^T X is positive semidefinite)
+  bool cert = false;
   if (truncated && A.rank_mode == 0) {
     double f2 = 0.0;
     for (int e = tid; e < b * b; e += NT) {
@@ -3883,11 +3892,11 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
     __syncthreads();
     const double g2n = sqrt((rd[0] + rd[1]) + (rd[2] + rd[3]));
     if ((r < ma ? tau[r] : 0.0) + g2n > theta * theta) {
-      if (tid == 0) A.big_fail[i] = 1;
-      return;
+      cert = true;
+      if (tid == 0) A.big_fail[i] = 2;
     }
   }
-  if (tid == 0 && A.cap_retry) A.big_fail[i] = 0;   // settled by the uncapped pass
+  if (tid == 0 && A.bg_count && !cert) atomicAdd(A.bg_count + (truncated ? 1 : 0), 1);
   if (tid == 0) {
     double ed = inactive;
     for (int q = r; q < ma; ++q) ed += tau[q];
@@ -3915,8 +3924,7 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   }
   __syncthreads();
 
-  // ---- 5. kept directions v_k (b-vectors) into G's storage -----------------
-  double* V = G;
+  // ---- 5. kept directions v_k (b-vectors) ----------------------------------
   for (int t = tid; t < b; t += NT) {
     for (int c0 = 0; c0 < kb; c0 += 16) {
       double acc[16];
@@ -3934,6 +3942,26 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
     }
   }
   __syncthreads();
+  if (truncated && !cert && A.rank_mode == 0) {
+    // a truncated step's dropped energy against G itself (the eigenvalues
+    // leave G - X^T X out): ||E_i||_F^2 = ||F_i||_F^2 - sum_k v_k^T G v_k,
+    // G read by columns (it is symmetric) so that the lanes' loads coalesce
+    double kept = 0.0;
+    for (int c = wv; c < kb; c += 4) {
+      const double* vc = V + (int64_t)c * b;
+      double part = 0.0;
+      for (int t = lane; t < b; t += 64) {
+        double y = 0.0;
+        for (int u = 0; u < b; ++u) y += G[(int64_t)u * b + t] * vc[u];
+        part += vc[t] * y;
+      }
+      kept += wave_sum_u(part);
+    }
+    if (lane == 0) rd[wv] = kept;
+    __syncthreads();
+    if (tid == 0) shd[0] = fmax(fro2 - ((rd[0] + rd[1]) + (rd[2] + rd[3])), 0.0);
+    __syncthreads();
+  }
 
   // ---- 6. Householder reflectors of the kept directions ----------------------
   for (int cv = 0; cv < kb; ++cv) {
@@ -3989,13 +4017,177 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
 #pragma unroll
     for (int u = 0; u < BG_MAXB / 64; ++u) {
       const int t = lane + 64 * u;
-      if (t < b) Ug[(int64_t)t * b + col] = (T)q[u];
+      if (t < b) {
+        Ug[(int64_t)t * b + col] = (T)q[u];
+        if (cert) U64[(int64_t)t * b + col] = q[u];
+      }
     }
   }
   if (tid == 0) {
     A.rank[i] = r;
     A.edrop[i] = shd[0];
     if (A.rec) A.rec[(A.rec_off + i) * REC_W + NFEAT] = (float)shi[0] / (float)b;
+  }
+}
+
+// C (m x n, row stride ldc) = alpha op(A) B by one workgroup on the FP64
+// matrix cores: 64 x 64 output tiles in turn, 64 columns of the inner
+// dimension at a time staged in LDS (Sa, Sb: 64 x TLD doubles each); operand
+// and result lanes as in k_bg_gram.  op(A)(p, q) = A[p lda + q], or
+// A[q lda + p] with ta.  With sym the product is known to be symmetric: only
+// the tiles on and above the diagonal are formed, and mirrored.  Returns, to
+// every thread, the sum of squares of C and its trace.
+__device__ double2 wg_gemm_f64(const double* A, int lda, bool ta, const double* B, int ldb, double* C, int ldc,
+                               int m, int n, int kd, bool sym, double alpha, double* Sa, double* Sb, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+  const int mt = (m + 63) / 64, nt = (n + 63) / 64;
+  double f2 = 0.0, trc = 0.0;
+  for (int ti = 0; ti < mt; ++ti)
+    for (int tj = sym ? ti : 0; tj < nt; ++tj) {
+      const int ra = 64 * ti, rb = 64 * tj, na = min(64, m - ra), nb = min(64, n - rb);
+      dbl4 acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int kc = 0; kc < kd; kc += 64) {
+        const int mc = min(64, kd - kc), mc4 = (mc + 3) & ~3;
+        __syncthreads();   // the previous chunk's operands consumed
+        // the unit-stride index of each operand on consecutive threads
+        for (int e = tid; e < 64 * 64; e += NT) {
+          const int k = ta ? (e >> 6) : (e & 63);
+          const int a = ta ? (e & 63) : (e >> 6);
+          double x = 0.0;
+          if (k < mc && a < na)
+            x = ta ? A[(int64_t)(kc + k) * lda + ra + a] : A[(int64_t)(ra + a) * lda + kc + k];
+          Sa[k * TLD + a] = x;
+          const int kq = e >> 6, c = e & 63;
+          Sb[kq * TLD + c] = (kq < mc && c < nb) ? B[(int64_t)(kc + kq) * ldb + rb + c] : 0.0;
+        }
+        __syncthreads();
+        const double* fa = Sa + fk * TLD + 16 * wv + fr;
+        const double* fb = Sb + fk * TLD + fr;
+        for (int k0 = 0; k0 < mc4; k0 += 4) {
+          const double av = fa[k0 * TLD];
+          double bv[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) bv[c] = fb[k0 * TLD + 16 * c];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c], 0, 0, 0);
+        }
+      }
+      const double wgt = (sym && ti != tj) ? 2.0 : 1.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = 16 * wv + 4 * j + fk, col = 16 * c + fr;
+          if (row < na && col < nb) {
+            const double v = alpha * acc[c][j];
+            C[(int64_t)(ra + row) * ldc + rb + col] = v;
+            if (sym && ti != tj) C[(int64_t)(rb + col) * ldc + ra + row] = v;
+            f2 += wgt * v * v;
+            if (ra + row == rb + col) trc += v;
+          }
+        }
+    }
+  f2 = wave_sum_u(f2);
+  trc = wave_sum_u(trc);
+  __syncthreads();   // red free
+  if (lane == 0) {
+    red[wv] = f2;
+    red[4 + wv] = trc;
+  }
+  __syncthreads();
+  const double2 out = {(red[0] + red[1]) + (red[2] + red[3]), (red[4] + red[5]) + (red[6] + red[7])};
+  // C visible to the whole workgroup before it is read as an operand
+  __threadfence();
+  __syncthreads();
+  return out;
+}
+
+// Certificate for a big-block step whose truncated pivoted Cholesky did not
+// settle its rank (big_fail = 2; k_bg_eig has written r_i and U_i, and U_i in
+// FP64).  With U_2 the last b - r columns of U_i, the dropped part of the far
+// row is U_2^T F_i, and C = U_2^T G U_2 is its Gram matrix.  For any r-column
+// orthonormal basis, lambda_{r+1}(G) <= lambda_max(C) (Courant-Fischer), and
+// lambda_r(G) > theta^2 already holds; so r_i is the rank of F_i at theta (eq.
+// (rreav)) once lambda_max(C) <= theta^2, which also bounds the dropped part's
+// spectral norm by theta as the compression requires (Section 2.3).  The
+// bound: for symmetric C of order n and q >= 0,
+//   ||C^(2^q)||_F^(1/2^q) / n^(1/2^(q+1)) <= lambda_max(C) <= ||C^(2^q)||_F^(1/2^q),
+// with C^(2^q) formed by repeated squaring (each square normalized to unit
+// Frobenius norm, the logarithm of the scale carried alongside).  Certified:
+// big_fail = 0 and the dropped energy is trace(C).  Refuted, or undecided
+// after BG_QMAX squarings: big_fail = 1, and the generic kernel redoes the
+// step.
+constexpr int BG_QMAX = 7;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bg_cert(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b < BG_MIN || b > BG_MAXB || st.nfar == 0) return;
+  if (A.need_exact && !A.need_exact[i]) return;
+  if (A.big_fail[i] != 2) return;
+  const int r = A.rank[i], n2 = b - r;
+  double* G = A.big + (int64_t)blockIdx.x * A.big_stride;
+  const double* U64 = G + (int64_t)b * b + (int64_t)BG_MA * b;
+  double* Y = const_cast<double*>(U64) + (int64_t)b * b;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Sa = reinterpret_cast<double*>(smem_raw);
+  double* Sb = Sa + 64 * TLD;
+  __shared__ double red[8];
+  const double theta = *A.theta, th2 = theta * theta;
+  if (n2 <= 0) {
+    if (threadIdx.x == 0) {
+      A.big_fail[i] = 0;
+      A.edrop[i] = 0.0;
+      if (A.bg_count) atomicAdd(A.bg_count + 2, 1);
+    }
+    return;
+  }
+  // Y = G U_2 (b x n2), then C = U_2^T Y (n2 x n2) over G's storage
+  wg_gemm_f64(G, b, false, U64 + r, b, Y, n2, b, n2, b, false, 1.0, Sa, Sb, red);
+  const double2 ft = wg_gemm_f64(U64 + r, b, true, Y, n2, G, n2, n2, n2, b, true, 1.0, Sa, Sb, red);
+  const double tol = 1e-6;   // far above the rounding of the products
+  int verdict = 0;           // 1 certified, -1 refuted
+  if (ft.x > 0.0) {
+    double ell = 0.5 * log(ft.x);   // log ||C^(2^q)||_F
+    double* M = G;
+    double* P = Y;
+    double scale = exp(-ell);        // 1 / ||M||_F
+    const double ln = log((double)n2);
+    for (int q = 0;; ++q) {
+      const double ub = exp(ell / (double)(1 << q));
+      const double lb = exp(ell / (double)(1 << q) - ln / (double)(2 << q));
+      if (ub * (1.0 + tol) <= th2) {
+        verdict = 1;
+        break;
+      }
+      if (lb * (1.0 - tol) > th2 || q == BG_QMAX) {
+        verdict = -1;
+        break;
+      }
+      // P = (M / ||M||_F)^2: its norm g gives log ||C^(2^(q+1))||_F = 2 ell + log g
+      const double2 pg = wg_gemm_f64(M, n2, false, M, n2, P, n2, n2, n2, n2, true, scale * scale, Sa, Sb, red);
+      if (!(pg.x > 0.0)) {
+        verdict = -1;   // not possible for a symmetric M of unit norm: left to the generic kernel
+        break;
+      }
+      const double lg = 0.5 * log(pg.x);
+      ell = 2.0 * ell + lg;
+      scale = exp(-lg);
+      double* tmp = M;
+      M = P;
+      P = tmp;
+    }
+  } else {
+    verdict = 1;   // nothing dropped
+  }
+  if (threadIdx.x == 0) {
+    A.big_fail[i] = verdict > 0 ? 0 : 1;
+    if (verdict > 0) A.edrop[i] = fmax(ft.y, 0.0);
+    if (A.bg_count) atomicAdd(A.bg_count + (verdict > 0 ? 2 : 3), 1);
   }
 }
 
@@ -4632,8 +4824,10 @@ static void launch(void (*kern)(LevelArgs<T>, int32_t, T*, int64_t), const Level
 
 template <typename T>
 size_t work_compress(int bmax) {
-  return (size_t)bmax * (bmax + 1) + (size_t)(bmax > QR_CH ? bmax : QR_CH) * (bmax + 1) +
-         (5 * (size_t)bmax > (size_t)NT ? 5 * (size_t)bmax : (size_t)NT) + 8;
+  // FP64 work in units of T
+  const size_t nd = (size_t)bmax * (bmax + 1) + (size_t)(bmax > QR_CH ? bmax : QR_CH) * (bmax + 1) +
+                    (5 * (size_t)bmax > (size_t)NT ? 5 * (size_t)bmax : (size_t)NT) + 8;
+  return nd * (sizeof(double) / sizeof(T));
 }
 template <typename T>
 size_t work_rotate(int bmax) {
@@ -4690,7 +4884,7 @@ static void compress_pass(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
   const bool gram = sizeof(T) < sizeof(double) && wgr <= max_lds_bytes();
   const bool gram2 = gram && wgr2 <= max_lds_bytes();
   const bool bigc = A.big && work_bg_eig<T>() <= max_lds_bytes() &&
-                    (size_t)2 * 64 * TLD * sizeof(T) <= max_lds_bytes();
+                    (size_t)2 * 64 * TLD * sizeof(double) <= max_lds_bytes();
   auto big_pass = [&](int small) {
     LevelArgs<T> C = A;
     C.small_by_wave = small;
@@ -4698,11 +4892,15 @@ static void compress_pass(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
       // big blocks: Gram tiles on many workgroups, then one workgroup per
       // step; the generic kernel takes only what they leave (blocks above
       // BG_MAXB, Gram matrices whose rank cannot be settled within BG_MA pivots)
+      // (the big-block kernels take no width cap, so a retry pass has
+      // nothing to redo there: its flagged big steps go to the generic kernel)
       const int nt = (std::min(bmax, BG_MAXB) + 63) / 64;
-      if (!retry)
+      if (!retry) {
         hipLaunchKernelGGL(k_bg_gram<T>, dim3(ns, nt * (nt + 1) / 2), dim3(NT), (size_t)2 * 64 * TLD * sizeof(T),
                            stream, A, w.s0);
-      hipLaunchKernelGGL(k_bg_eig<T>, dim3(ns), dim3(NT), work_bg_eig<T>(), stream, A, w.s0);
+        hipLaunchKernelGGL(k_bg_eig<T>, dim3(ns), dim3(NT), work_bg_eig<T>(), stream, A, w.s0);
+        hipLaunchKernelGGL(k_bg_cert<T>, dim3(ns), dim3(NT), (size_t)2 * 64 * TLD * sizeof(double), stream, A, w.s0);
+      }
       C.big_retry = 1;
       C.need_exact = nullptr;
       C.lwidth = nullptr;
@@ -4736,7 +4934,6 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
     LevelArgs<T> R = A;
     R.lwidth = nullptr;
     R.need_exact = A.big_fail;
-    R.cap_retry = 1;
     compress_pass<T>(R, w, bmax, gscratch, stream, true);
     return;
   }

@@ -47,16 +47,17 @@ struct LevelArgs {
   int32_t* lcount;          // [0] sketches accepted, [1] sketches rejected
   int32_t bf16_schur;       // FP32 factor: Schur products with BF16 inputs on the matrix cores
   int32_t compensate;       // add |E_i| to the diagonals (k_compensate) instead of plain dropping
-  // big-block compression (FP32 factor, blocks above 128 unknowns): per-step
-  // scratch of the wave (Gram matrix, then kept directions; pivoted Cholesky
-  // rows), bg_stride(bmax) doubles per step of the wave, or null
+  // big-block compression (blocks above 128 unknowns): per-step scratch of
+  // the wave (Gram matrix, pivoted Cholesky rows, U_i in FP64, work),
+  // bg_stride(bmax) doubles per step of the wave, or null
   double* big;
   int64_t big_stride;
-  int32_t* big_fail;        // per block: 1 = left to the generic compression
+  int32_t* big_fail;        // per block: 1 = left to the generic compression, 2 = to k_bg_cert
+  int32_t bg_cap;           // most pivoted Cholesky rows (<= BG_MA)
+  int32_t* bg_count;        // [0] untruncated, [1] Frobenius-accepted, [2] certified, [3] generic
   int32_t big_retry;        // generic compression: only the blocks flagged in big_fail
   // learned ranks by a capped rank-revealing factorization (LEARNED_CAP)
   int32_t* lwidth;          // per block: the MLP's width, caps the pivoted Cholesky; or null
-  int32_t cap_retry;        // uncapped pass over the steps a capped pass rejected
 };
 
 // doubles of big-block compression scratch per step of a wave

@@ -248,6 +248,7 @@ struct NumLevel {
   int32_t M = 0, bmax = 0;
   int64_t dim = 0;
   std::vector<int32_t> sizes, ranks;
+  std::vector<double> drops;   // ||E_i||_F^2 per block
   std::vector<int64_t> slot_off, u_off, dof_off;
   std::vector<int32_t> off_in_parent;
   std::vector<cae::WaveRange> waves;
@@ -289,6 +290,7 @@ struct cae_factor_s {
   DevBuf lcount;       // sketches accepted / rejected
   int64_t rec_rows = 0;
   int32_t sketch_acc = 0, sketch_rej = 0;
+  int32_t big_count[4] = {0, 0, 0, 0};   // big-block compressions by outcome
   // the preconditioner apply of the iterative solvers, captured once per
   // (right-hand sides, vectors) and replayed every iteration (MINRES
   // alternates two input vectors, hence a few entries)
@@ -410,8 +412,9 @@ cae::LevelArgs<T> level_args(cae_factor_s* h, int l) {
   A.big_stride = 0;
   A.big_fail = nullptr;
   A.big_retry = 0;
+  A.bg_cap = 128;
+  A.bg_count = nullptr;
   A.lwidth = nullptr;
-  A.cap_retry = 0;
   return A;
 }
 
@@ -447,8 +450,8 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
   h->theta.alloc(2 * sizeof(double));
   h->err.alloc(2 * sizeof(int32_t));
   HIPCHK(hipMemsetAsync(h->err.p, 0, 2 * sizeof(int32_t), s));
-  h->lcount.alloc(2 * sizeof(int32_t));
-  HIPCHK(hipMemsetAsync(h->lcount.p, 0, 2 * sizeof(int32_t), s));
+  h->lcount.alloc(6 * sizeof(int32_t));   // sketches accepted / rejected, big-block outcomes
+  HIPCHK(hipMemsetAsync(h->lcount.p, 0, 6 * sizeof(int32_t), s));
   h->rec_rows = 0;
   cae::launch_theta(h->vals.as<double>(), AN->diag_pos.as<int64_t>(), a.n, eps, h->theta.as<double>(), s);
 
@@ -505,6 +508,8 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       h->bigbuf.alloc(wmax * (size_t)stride * sizeof(double));
       A.big = h->bigbuf.as<double>();
       A.big_stride = stride;
+      A.bg_cap = h->opt.big_pivot_cap > 0 ? h->opt.big_pivot_cap : 128;
+      A.bg_count = h->lcount.as<int32_t>() + 2;
     }
     if (h->opt.rank_mode == CAE_RANK_LEARNED_CAP) {
       N.lwidth.alloc((size_t)L.M * sizeof(int32_t));
@@ -615,6 +620,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       snprintf(buf, sizeof buf, "non-SPD pivot block at level %d, block %d", l + 1, herr[1]);
       return fail(CAE_ENOTSPD, buf);
     }
+    N.drops.assign(ed, ed + L.M);
     for (int32_t i = 0; i < L.M; ++i) {
       dropped += ed[i];
       minpiv = std::min(minpiv, mp[i]);
@@ -704,11 +710,12 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
   bytes += dim * dim * (int64_t)sizeof(double);
   h->factor_bytes = bytes;
   {
-    int32_t* lc = reinterpret_cast<int32_t*>(pinned_readback(2 * sizeof(int32_t)));
-    HIPCHK(hipMemcpyAsync(lc, h->lcount.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t* lc = reinterpret_cast<int32_t*>(pinned_readback(6 * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(lc, h->lcount.p, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     h->sketch_acc = lc[0];
     h->sketch_rej = lc[1];
+    for (int k = 0; k < 4; ++k) h->big_count[k] = lc[2 + k];
   }
   h->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   // (the algorithmic flop counts are computed when the statistics are read,
@@ -1121,6 +1128,7 @@ int checked_options(cae_analysis_t an, double eps, const cae_options_t* opt, cae
   if (o.rank_mode == CAE_RANK_FIXED && o.fixed_rank < 0) return fail(CAE_EINVAL, "fixed_rank must be >= 0");
   if (o.order != an->a.order_kind) return fail(CAE_EINVAL, "order differs from the analysis");
   if (o.workspace && o.workspace_bytes == 0) return fail(CAE_EINVAL, "workspace given with workspace_bytes = 0");
+  if (o.big_pivot_cap < 0 || o.big_pivot_cap > 128) return fail(CAE_EINVAL, "big_pivot_cap must be in 0..128");
   return CAE_OK;
 }
 
@@ -1589,6 +1597,10 @@ static int cae_get_stats_impl(cae_handle_t h, cae_stats_t* st) {
   st->sketch_accepted = h->sketch_acc;
   st->sketch_rejected = h->sketch_rej;
   st->record_rows = h->rec_rows;
+  st->big_untruncated = h->big_count[0];
+  st->big_frobenius = h->big_count[1];
+  st->big_certified = h->big_count[2];
+  st->big_generic = h->big_count[3];
   return CAE_OK;
 }
 
@@ -1674,6 +1686,13 @@ static int cae_get_ranks_impl(cae_handle_t h, int32_t level, int32_t* ranks) {
   return CAE_OK;
 }
 
+static int cae_get_drops_impl(cae_handle_t h, int32_t level, double* e) {
+  if (check_handle(h) || !e) return fail(CAE_EINVAL, "null argument");
+  if (level < 0 || level >= h->K) return fail(CAE_EINVAL, "level out of range");
+  std::memcpy(e, h->lev[level].drops.data(), h->lev[level].drops.size() * sizeof(double));
+  return CAE_OK;
+}
+
 static int cae_get_sizes_impl(cae_handle_t h, int32_t level, int32_t* sizes) {
   if (check_handle(h) || !sizes) return fail(CAE_EINVAL, "null argument");
   if (level < 0 || level > h->K) return fail(CAE_EINVAL, "level out of range");
@@ -1714,6 +1733,10 @@ int cae_get_ranks(cae_handle_t h, int32_t level, int32_t* ranks) {
 
 int cae_get_sizes(cae_handle_t h, int32_t level, int32_t* sizes) {
   return keep_error(h, cae_get_sizes_impl(h, level, sizes));
+}
+
+int cae_get_drops(cae_handle_t h, int32_t level, double* e) {
+  return keep_error(h, cae_get_drops_impl(h, level, e));
 }
 
 int cae_get_level_ms(cae_handle_t h, int32_t level, double* ms) {

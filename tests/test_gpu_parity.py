@@ -231,41 +231,166 @@ def test_fp32_factor_with_blocks_above_64():
     assert err <= 1e-5
 
 
-def test_fp32_factor_with_blocks_above_128():
-    """FP32 factor of a 3D Laplacian with the paper's coarsening (the eight
-    Morton siblings join, Section 2.5): the second level holds blocks of up to
-    215 unknowns, which take the big-block kernels (Gram tiles on the FP64
-    matrix cores, pivoted Cholesky, Jacobi on X X^T, reflectors).  Probe error
-    against the FP64 oracle within the FP32 bound, and that level's ranks equal
-    to the oracle's wherever the oracle's singular values are not within the
-    FP32 rounding level of the threshold."""
+_BIG = {}
+
+
+def _big_oracle():
+    """The oracle's factor of the 20^3 Laplacian with sibling coarsening (its
+    second level holds blocks of up to 215 unknowns), computed once."""
+    if not _BIG:
+        dims, patch, eps = (20, 20, 20), (4, 4, 4), 1e-4
+        A, csr, perm, bp, co = _setup(dims, patch)
+        fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order="multicolour", coarse_max_dim=0,
+                                                     keep_far_rows=True))
+        _BIG.update(A=A, csr=csr, perm=perm, bp=bp, co=co, eps=eps, fo=fo, Mo=oracle.ce_dense(fo))
+    return _BIG
+
+
+def _dense_M(f, n, chunk=2000):
+    cols = []
+    for c0 in range(0, n, chunk):
+        E = torch.zeros((min(chunk, n - c0), n), dtype=torch.float64, device="cuda")
+        E[torch.arange(E.shape[0]), torch.arange(c0, c0 + E.shape[0])] = 1.0
+        cols.append(f.multiply(E).cpu().numpy())
+    return np.concatenate(cols, axis=0).T
+
+
+@pytest.mark.parametrize("prec,cap", [("fp32", 0), ("fp32", 1), ("fp32", 24), ("fp32", 12), ("fp64", 24),
+                                      ("fp64", 12)])
+def test_factor_with_blocks_above_128(prec, cap):
+    """Factor of a 3D Laplacian with the paper's coarsening (the eight Morton
+    siblings join, Section 2.5): the second level holds blocks of up to 215
+    unknowns, which take the big-block kernels (Gram tiles on the FP64 matrix
+    cores, pivoted Cholesky, Jacobi on X X^T, reflectors).
+
+    Default cap, and cap 1 (which sends every big step of rank above 1 to
+    the generic kernel): probe error against the FP64 oracle within the FP32
+    bound, every level's ranks equal to the oracle's wherever the oracle's
+    singular values are not within the FP32 rounding level of the threshold,
+    and every step's dropped energy equal to the oracle's.
+
+    A pivot cap below the default truncates the pivoted Cholesky, so that the
+    other ways of settling a rank run too: the Frobenius bound, the spectral
+    certificate by repeated squaring, and the generic kernel (each asserted to
+    occur for some cap).  A truncated step keeps the Ritz basis of its pivoted
+    rows instead of the exact singular vectors -- another valid CE(eps) basis
+    with the same rank -- so the later far rows, and near-threshold ranks
+    after it, differ from the oracle's.  Such a factor is checked by what
+    holds for any CE(eps) factorization: the ranks of the levels before the
+    first big one equal the oracle's; the Frobenius identity ||A0 - M||_F^2 =
+    2 sum e_i of its own drops; M within the two drop bounds of the oracle's
+    M; PCG iterations."""
     cae = _cae()
-    dims, patch, eps = (20, 20, 20), (4, 4, 4), 1e-4
-    A, csr, perm, bp, co = _setup(dims, patch)
-    fo = ce_factor(*csr, perm, bp, co, CEOptions(eps=eps, order="multicolour", coarse_max_dim=0))
-    an, f = _gpu_factor(cae, csr, perm, bp, co, eps, "multicolour", precision=cae.FP32, coarse=0)
-    big = [l for l in range(len(fo.levels)) if int(f.sizes(l).max()) > 128 and fo.levels[l].sigma]
-    assert big, "no level with blocks above 128 unknowns"
-    for l in big:
-        rg, lf, sz = f.ranks(l), fo.levels[l], f.sizes(l)
-        assert np.array_equal(sz, np.asarray(lf.sizes))
+    d = _big_oracle()
+    A, csr, perm, bp, co, eps, fo = (d[k] for k in ("A", "csr", "perm", "bp", "co", "eps", "fo"))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co, order=cae.ORDER_MULTICOLOUR)
+    vals = torch.from_numpy(csr[2]).cuda()
+    f = cae.Factor(an, vals, eps, precision=cae.FP32 if prec == "fp32" else cae.FP64, coarse_max_dim=0,
+                   big_pivot_cap=cap)
+    st = f.stats()
+    K = min(st["nlevels"], len(fo.levels))
+    # the levels whose blocks are those of the oracle (a different rank
+    # changes the sizes of the levels after it)
+    same = []
+    for l in range(K):
+        if len(f.sizes(l)) != len(fo.levels[l].sizes) or not np.array_equal(f.sizes(l), fo.levels[l].sizes):
+            break
+        same.append(l)
+    big = [l for l in same if int(f.sizes(l).max()) > 128 and fo.levels[l].sigma]
+    first_big = min(big) if big else K
+    nbig = 0
+    rank_diff = []
+    for l in same:
+        rg, sz, lf = f.ranks(l), f.sizes(l), fo.levels[l]
         for i in np.nonzero(rg != lf.r)[0]:
             s = lf.sigma[i]
             k = min(rg[i], lf.r[i])
-            assert abs(s[k] - fo.theta) <= 1e-5 * s[0], (l, i, rg[i], lf.r[i])
+            rank_diff.append((l, int(i), int(rg[i]), int(lf.r[i]), float(s[k] / fo.theta)))
+    for l in range(K):
+        sz = f.sizes(l)
+        nbig += int(np.count_nonzero(sz > 128))
+    cls = [st[k] for k in ("big_untruncated", "big_frobenius", "big_certified", "big_generic")]
     X = _probes(A.shape[0])
     Mo = ce_multiply(fo, X)
-    M32 = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
-    err = np.linalg.norm(M32 - Mo) / np.linalg.norm(Mo)
-    print(f"fp32 (b > 128) probe error vs oracle: {err:.3e}")
-    assert err <= 1e-5
-    # the dropped energy: every dropped sigma (<= theta) of an FP32 far row is
-    # perturbed by about u_32 ||F_i||, so sigma^2 by about 2 theta u_32 ||F_i||:
-    # relative to the total, ~2 u_32 ||F|| / theta (a few 1e-3 here)
-    st = f.stats()
+    Mg = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    err = np.linalg.norm(Mg - Mo) / np.linalg.norm(Mo)
     ed_o = sum(float(np.sum(l.e)) for l in fo.levels)
-    print(f"dropped energy {st['dropped_sq']:.6e} vs oracle {ed_o:.6e}")
-    assert abs(st["dropped_sq"] - ed_o) <= 1e-2 * ed_o
+    # per-step dropped energy against the oracle's, on the levels whose far
+    # rows are the oracle's (before the first big level; every level for the
+    # exact caps); the worst step relative to the level's total
+    th2 = fo.theta ** 2
+    worst = []
+    for l in same:
+        if cap not in (0, 1) and l >= first_big:
+            break
+        dg, do = f.drops(l), np.asarray(fo.levels[l].e)
+        k = int(np.argmax(np.abs(dg - do)))
+        worst.append((l, k, int(f.sizes(l)[k]), float(dg[k] / th2), float(do[k] / th2)))
+    print(f"{prec} cap {cap}: levels with the oracle's blocks {same}, first big {first_big}, blocks above 128 "
+          f"{nbig}, untruncated/Frobenius/certified/generic {cls}, probe error vs oracle {err:.3e}, dropped "
+          f"energy {st['dropped_sq']:.6e} vs oracle {ed_o:.6e}, rank differences (level, block, gpu, oracle, "
+          f"sigma/theta) {rank_diff[:8]}, worst step drop (level, block, b, gpu/theta^2, oracle/theta^2) {worst}")
+    assert big, "no level with blocks above 128 unknowns"
+    assert 0 < sum(cls) <= nbig
+    # (in units of theta^2) FP64: a big step's pivoted Cholesky stops once the
+    # trailing energy is below (theta / 32)^2, which its dropped energy may
+    # miss; FP32: the far row's entries carry the rounding of the FP32 factor
+    # so far (about u_32 times the Schur terms that formed them, ~1e-5 in
+    # ||dF||_2 against theta = 6e-4), which moves a dropped sigma^2 near
+    # theta^2 by a few per cent
+    for l, k, b, eg, eo in worst:
+        tol = 0.1 + 2e-2 * eo if prec == "fp32" else 1e-6 * eo + (1.0 / 1024 if b > 128 else 1e-12)
+        assert abs(eg - eo) <= tol, (l, k, b, eg, eo)
+    if cap in (0, 1):
+        if cap == 0:
+            assert cls[1:] == [0, 0, 0]
+        else:
+            assert cls[3] > 0
+        assert len(same) == K == len(fo.levels)
+        # every block above 128 unknowns with a far row is counted once
+        assert sum(cls) == sum(1 for lf in fo.levels for i, F in enumerate(lf.F)
+                               if lf.sizes[i] > 128 and F is not None and F.shape[1] > 0)
+        for l, i, rg_i, ro_i, q in rank_diff:
+            assert abs(q - 1.0) <= 1e-5 * fo.levels[l].sigma[i][0] / fo.theta, (l, i, rg_i, ro_i)
+        # FP32: the rounding of the far rows; FP64: the pivoted Cholesky stops
+        # once the trailing energy is below (theta / 32)^2, which moves the
+        # basis by O(that / gap) -- measured 1e-8
+        assert err <= (1e-5 if prec == "fp32" else 1e-7)
+        # every dropped sigma (<= theta) of an FP32 far row is perturbed by
+        # about u_32 ||F_i||, so sigma^2 by about 2 theta u_32 ||F_i||:
+        # relative to the total, ~2 u_32 ||F|| / theta (a few 1e-3 here)
+        assert abs(st["dropped_sq"] - ed_o) <= 1e-2 * ed_o
+    else:
+        if cap == 24:
+            assert cls[2] > 0
+        if cap == 12:
+            assert cls[3] > 0
+        n = A.shape[0]
+        A0 = A.toarray()
+        M = _dense_M(f, n)
+        Mo_d = d["Mo"]
+        err2 = np.linalg.norm(A0 - M) ** 2
+        dM = np.linalg.norm(M - Mo_d)
+        bound = np.sqrt(2 * st["dropped_sq"]) + np.sqrt(2 * ed_o)
+        b = torch.from_numpy(problems.rhs_uniform(n, seed=0)).cuda()
+        _, it, rel = f.pcg(b, rtol=1e-10)
+        _, it_o, _ = oracle.pcg(A, problems.rhs_uniform(n, seed=0), lambda r: ce_solve(fo, r), tol=1e-10)
+        print(f"   ||A0 - M||_F^2 {err2:.6e} vs 2 sum e_i {2 * st['dropped_sq']:.6e}; ||M - M_orc||_F {dM:.3e} "
+              f"<= {bound:.3e}; PCG {int(it[0])} vs oracle {it_o}")
+        for l, i, rg_i, ro_i, q in rank_diff:
+            if l < first_big:
+                assert abs(q - 1.0) <= 1e-5 * fo.levels[l].sigma[i][0] / fo.theta, (l, i, rg_i, ro_i)
+        # the identity to rounding, but for the (theta / 32)^2 a big step's
+        # dropped energy may miss; FP32: M's entries also carry the FP32
+        # rounding of the factor (u_32 ||A||_F per entry block), against
+        # ||A0 - M||_F of about sqrt(2 sum e_i)
+        tol = 1e-8 if prec == "fp64" else 3e-2
+        assert abs(err2 - 2 * st["dropped_sq"]) <= tol * err2 + 2 * nbig * th2 / 1024
+        assert dM <= bound * (1 + 1e-6) + 1e-6 * np.linalg.norm(A0)
+        assert f.converged and rel[0] <= 1e-9
+        assert int(it[0]) <= it_o + 1
+    f.close()
+    an.close()
 
 
 def test_random_coefficient_diffusion_fp32_matches_oracle():
