@@ -2036,6 +2036,80 @@ __device__ int jacobi_rows_wave(double* R, int ld, const int* row, int ma, doubl
   return nsweep;
 }
 
+// The same rotations by the four wavefronts of a workgroup: the pairs of a
+// round are split over the wavefronts, one workgroup barrier per round (every
+// thread of the workgroup must call it).  Returns the number of sweeps.
+template <int LP, int BM>
+__device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double negl, double aerr, double tol) {
+  constexpr int NC = BM / LP, PPASS = 64 / LP;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, sub = lane % LP;
+  const int mm = ma + (ma & 1), np = mm / 2, m1 = mm - 1;
+  const double negl2 = negl * negl, aerr2 = aerr * aerr, tol2 = tol * tol;
+  int nsweep = 0;
+  for (int sweep = 0; sweep < 40 && ma > 1; ++sweep) {
+    ++nsweep;
+    int rotated = 0;
+    for (int rho = 0; rho < m1; ++rho) {
+      for (int pb = wv * PPASS; pb < np; pb += 4 * PPASS) {
+        const int pp = pb + lane / LP;
+        int p = -1, q = -1;
+        if (pp < np) {
+          if (pp == 0) {
+            p = m1;
+            q = rho;
+          } else {
+            p = rho + pp;
+            if (p >= m1) p -= m1;
+            q = rho - pp;
+            if (q < 0) q += m1;
+          }
+          if (p > q) {
+            const int tmp = p;
+            p = q;
+            q = tmp;
+          }
+          if (q >= ma) p = -1;
+        }
+        double x[NC], y[NC];
+        double a = 0.0, c = 0.0, d = 0.0;
+        double* xr = R;
+        double* yr = R;
+        if (p >= 0) {
+          xr = R + row[p] * ld;
+          yr = R + row[q] * ld;
+#pragma unroll
+          for (int u = 0; u < NC; ++u) {
+            x[u] = xr[sub + LP * u];
+            y[u] = yr[sub + LP * u];
+            a += x[u] * x[u];
+            c += y[u] * y[u];
+            d += x[u] * y[u];
+          }
+        }
+        a = group_sum<LP>(a);
+        c = group_sum<LP>(c);
+        d = group_sum<LP>(d);
+        const double d2 = d * d;
+        if (p >= 0 && d != 0.0 && d2 > tol2 * a * c && (a > negl2 || c > negl2) && d2 > aerr2 * fmax(a, c)) {
+          const double e = c - a, f = 2.0 * d;
+          const double h = sqrt(e * e + f * f);
+          const double tt = (e >= 0.0 ? f : -f) / (fabs(e) + h);
+          const double cs = rsqrt_nr(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+          for (int u = 0; u < NC; ++u) {
+            xr[sub + LP * u] = cs * x[u] - sn * y[u];
+            yr[sub + LP * u] = sn * x[u] + cs * y[u];
+          }
+          rotated = 1;
+        }
+      }
+      __syncthreads();   // the rows of this round rotated before the next pairing
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  return nsweep;
+}
+
 // C[TM x TM tile of thread (ty, tx)] += A^T A over K rows of the staged chunk
 // S (row stride ld, BM = 16 TM columns), FP64 accumulation.
 template <int TM, typename T>
@@ -3581,6 +3655,91 @@ __global__ __launch_bounds__(NT) void k_gj_update(double* Ad, int64_t dim, int64
   }
 }
 
+// C (m x n, row stride ldc) = alpha op(A) op(B) + diag I by one workgroup on
+// the FP64 matrix cores: 64 x 64 output tiles in turn, 64 columns of the
+// inner dimension at a time staged in LDS (Sa, Sb: 64 x TLD doubles each);
+// operand and result lanes as in k_bg_gram.  op(A)(p, q) = A[p lda + q], or
+// A[q lda + p] with ta; op(B)(q, c) = B[q ldb + c], or B[c ldb + q] with tb.
+// With sym the product is known to be symmetric: only the tiles on and above
+// the diagonal are formed, and mirrored.  C takes the result in its own type,
+// C2 (if not null, same layout) in FP64.  Returns, to every thread, the sum
+// of squares of the result and its trace.
+template <typename TO>
+__device__ double2 wg_gemm_f64(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, TO* C, int ldc,
+                               int m, int n, int kd, bool sym, double alpha, double diag, double* C2, double* Sa,
+                               double* Sb, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+  const int mt = (m + 63) / 64, nt = (n + 63) / 64;
+  double f2 = 0.0, trc = 0.0;
+  for (int ti = 0; ti < mt; ++ti)
+    for (int tj = sym ? ti : 0; tj < nt; ++tj) {
+      const int ra = 64 * ti, rb = 64 * tj, na = min(64, m - ra), nb = min(64, n - rb);
+      dbl4 acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int kc = 0; kc < kd; kc += 64) {
+        const int mc = min(64, kd - kc), mc4 = (mc + 3) & ~3;
+        __syncthreads();   // the previous chunk's operands consumed
+        // the unit-stride index of each operand on consecutive threads
+        for (int e = tid; e < 64 * 64; e += NT) {
+          const int k = ta ? (e >> 6) : (e & 63);
+          const int a = ta ? (e & 63) : (e >> 6);
+          double x = 0.0;
+          if (k < mc && a < na)
+            x = ta ? A[(int64_t)(kc + k) * lda + ra + a] : A[(int64_t)(ra + a) * lda + kc + k];
+          Sa[k * TLD + a] = x;
+          const int kq = tb ? (e & 63) : (e >> 6), c = tb ? (e >> 6) : (e & 63);
+          double yv = 0.0;
+          if (kq < mc && c < nb) yv = tb ? B[(int64_t)(rb + c) * ldb + kc + kq] : B[(int64_t)(kc + kq) * ldb + rb + c];
+          Sb[kq * TLD + c] = yv;
+        }
+        __syncthreads();
+        const double* fa = Sa + fk * TLD + 16 * wv + fr;
+        const double* fb = Sb + fk * TLD + fr;
+        for (int k0 = 0; k0 < mc4; k0 += 4) {
+          const double av = fa[k0 * TLD];
+          double bv[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) bv[c] = fb[k0 * TLD + 16 * c];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c], 0, 0, 0);
+        }
+      }
+      const double wgt = (sym && ti != tj) ? 2.0 : 1.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = 16 * wv + 4 * j + fk, col = 16 * c + fr;
+          if (row < na && col < nb) {
+            const bool dgl = ra + row == rb + col;
+            const double v = alpha * acc[c][j] + (dgl ? diag : 0.0);
+            C[(int64_t)(ra + row) * ldc + rb + col] = (TO)v;
+            if (C2) C2[(int64_t)(ra + row) * ldc + rb + col] = v;
+            if (sym && ti != tj) {
+              C[(int64_t)(rb + col) * ldc + ra + row] = (TO)v;
+              if (C2) C2[(int64_t)(rb + col) * ldc + ra + row] = v;
+            }
+            f2 += wgt * v * v;
+            if (dgl) trc += v;
+          }
+        }
+    }
+  f2 = wave_sum_u(f2);
+  trc = wave_sum_u(trc);
+  __syncthreads();   // red free
+  if (lane == 0) {
+    red[wv] = f2;
+    red[4 + wv] = trc;
+  }
+  __syncthreads();
+  const double2 out = {(red[0] + red[1]) + (red[2] + red[3]), (red[4] + red[5]) + (red[6] + red[7])};
+  // C visible to the whole workgroup before it is read as an operand
+  __threadfence();
+  __syncthreads();
+  return out;
+}
+
 // ---------------------------------------------------------------------------
 // Compression of blocks of BG_MIN..BG_MAXB unknowns (FP32 factor: the coarse
 // levels of 3D problems with sibling coarsening, whose blocks join the kept
@@ -3723,6 +3882,7 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   __shared__ double shd[4];
   __shared__ int shi[4];
   const double theta = *A.theta;
+  const int64_t t_start = clock64();
 
   // ---- 1. pivoted Cholesky (left-looking): row k of X from column p of G ----
   double tr = 0.0;
@@ -3804,48 +3964,55 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   }
   const int ma = k;
   __syncthreads();
+  const int64_t t_chol = clock64();
+  // the products' LDS staging shares the region of S (never live together)
+  double* Sa = S;
+  double* Sb = S + 64 * TLD;
 
-  // ---- 2. S = X X^T (zero beyond ma), thread (ty, tx) an 8 x 8 block --------
-  {
-    const int ty = tid >> 4, tx = tid & 15;
-    double acc[8][8];
-#pragma unroll
-    for (int p = 0; p < 8; ++p)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
-    if (8 * ty < ma && 8 * tx < ma) {
-      for (int t = 0; t < b; ++t) {
-        double xa[8], xb[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-          xa[p] = 8 * ty + p < ma ? X[(int64_t)(8 * ty + p) * b + t] : 0.0;
-          xb[p] = 8 * tx + p < ma ? X[(int64_t)(8 * tx + p) * b + t] : 0.0;
-        }
-#pragma unroll
-        for (int p = 0; p < 8; ++p)
-#pragma unroll
-          for (int q = 0; q < 8; ++q) acc[p][q] += xa[p] * xb[q];
-      }
+  // a truncated Cholesky leaves G2 = G - X^T X (positive semidefinite); the
+  // step is kept if lambda_{r+1}(X^T X) + ||G2||_F <= theta^2: then
+  // lambda_{r+1}(G) <= theta^2 too (Weyl, ||G2||_2 <= ||G2||_F), so r is the
+  // rank of F_i and the dropped part has spectral norm <= theta; otherwise
+  // k_bg_cert bounds the dropped part's spectral norm itself (big_fail = 2)
+  // from the basis this kernel still writes (lambda_r(G) >= lambda_r(X^T X) >
+  // theta^2 holds in any case, as G - X^T X is positive semidefinite).
+  // ||G2||_F from X^T X formed on the matrix cores (in U64's storage).
+  double g2n = 0.0;
+  if (truncated && A.rank_mode == 0) {
+    wg_gemm_f64<double>(X, b, true, X, b, false, U64, b, b, b, ma, true, 1.0, 0.0, nullptr, Sa, Sb, rd);
+    double f2 = 0.0;
+    for (int e = tid; e < b * b; e += NT) {
+      const double g = G[e] - U64[e];
+      f2 += g * g;
     }
-#pragma unroll
-    for (int p = 0; p < 8; ++p)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) S[(8 * ty + p) * BG_SLD + 8 * tx + q] = acc[p][q];
-    if (tid < BG_MA) rowix[tid] = tid;
+    f2 = wave_sum_u(f2);
+    if (lane == 0) rd[wv] = f2;
+    __syncthreads();
+    g2n = sqrt((rd[0] + rd[1]) + (rd[2] + rd[3]));
+    __syncthreads();   // rd free
   }
+
+  // ---- 2. S = X X^T (ma x ma) on the matrix cores, through V's storage ------
+  wg_gemm_f64<double>(X, b, false, X, b, true, V, ma, ma, ma, b, true, 1.0, 0.0, nullptr, Sa, Sb, rd);
+  for (int e = tid; e < BG_MA * BG_MA; e += NT) {
+    const int p = e / BG_MA, q = e % BG_MA;
+    S[p * BG_SLD + q] = (p < ma && q < ma) ? V[p * ma + q] : 0.0;
+  }
+  if (tid < BG_MA) rowix[tid] = tid;
   __syncthreads();
 
-  // ---- 3. one-sided Jacobi on the rows of S (one wavefront) ----------------
+  // ---- 3. one-sided Jacobi on the rows of S (the four wavefronts) -----------
   // the row norms are lambda = sigma^2: the thresholds of the sigma-scale
   // tests squared
-  if (wv == 0 && ma > 1) {
+  if (ma > 1) {
     const double tol = (double)max(b, 16) * DBL_EPSILON;
     const int np = (ma + 1) / 2;
-    if (np <= 4) jacobi_rows_wave<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
-    else if (np <= 8) jacobi_rows_wave<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
-    else jacobi_rows_wave<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    if (np <= 4) jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else if (np <= 8) jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
   }
   __syncthreads();
+  const int64_t t_eig = clock64();
 
   // ---- 4. eigenvalues, order, rank, dropped energy ---------------------------
   if (tid < ma) {
@@ -3869,33 +4036,8 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   cnt = __syncthreads_count(cnt);
   const int r = A.rank_mode == 0 ? cnt : min(A.fixed_rank, b);
   const int kb = min(r, ma);
-  // a truncated Cholesky leaves G2 = G - X^T X (positive semidefinite); the
-  // step is kept if lambda_{r+1}(X^T X) + ||G2||_F <= theta^2: then
-  // lambda_{r+1}(G) <= theta^2 too (Weyl, ||G2||_2 <= ||G2||_F), so r is the
-  // rank of F_i and the dropped part has spectral norm <= theta; otherwise
-  // k_bg_cert bounds the dropped part's spectral norm itself (big_fail = 2)
-  // from the basis this kernel still writes (lambda_r(G) >= lambda_r(X^T X) >
-  // theta^2 holds in any case, as G - X^T X is positive semidefinite)
-  bool cert = false;
-  if (truncated && A.rank_mode == 0) {
-    double f2 = 0.0;
-    for (int e = tid; e < b * b; e += NT) {
-      const int p = e / b, q = e % b;
-      if (q < p) continue;
-      double g = G[(int64_t)p * b + q];
-      for (int j = 0; j < ma; ++j) g -= X[(int64_t)j * b + p] * X[(int64_t)j * b + q];
-      f2 += (q == p ? 1.0 : 2.0) * g * g;
-    }
-    f2 = wave_sum_u(f2);
-    __syncthreads();
-    if (lane == 0) rd[wv] = f2;
-    __syncthreads();
-    const double g2n = sqrt((rd[0] + rd[1]) + (rd[2] + rd[3]));
-    if ((r < ma ? tau[r] : 0.0) + g2n > theta * theta) {
-      cert = true;
-      if (tid == 0) A.big_fail[i] = 2;
-    }
-  }
+  const bool cert = truncated && A.rank_mode == 0 && (r < ma ? tau[r] : 0.0) + g2n > theta * theta;
+  if (tid == 0 && cert) A.big_fail[i] = 2;
   if (tid == 0 && A.bg_count && !cert) atomicAdd(A.bg_count + (truncated ? 1 : 0), 1);
   if (tid == 0) {
     double ed = inactive;
@@ -3941,27 +4083,21 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
         if (c0 + u < kb) V[(int64_t)(c0 + u) * b + t] = acc[u] * isg[c0 + u];
     }
   }
-  __syncthreads();
+  __syncthreads();   // S consumed: its LDS is free from here on
   if (truncated && !cert && A.rank_mode == 0) {
     // a truncated step's dropped energy against G itself (the eigenvalues
     // leave G - X^T X out): ||E_i||_F^2 = ||F_i||_F^2 - sum_k v_k^T G v_k,
-    // G read by columns (it is symmetric) so that the lanes' loads coalesce
+    // with V G formed on the matrix cores (in U64's storage)
+    wg_gemm_f64<double>(V, b, false, G, b, false, U64, b, kb, b, b, false, 1.0, 0.0, nullptr, Sa, Sb, rd);
     double kept = 0.0;
-    for (int c = wv; c < kb; c += 4) {
-      const double* vc = V + (int64_t)c * b;
-      double part = 0.0;
-      for (int t = lane; t < b; t += 64) {
-        double y = 0.0;
-        for (int u = 0; u < b; ++u) y += G[(int64_t)u * b + t] * vc[u];
-        part += vc[t] * y;
-      }
-      kept += wave_sum_u(part);
-    }
+    for (int e = tid; e < kb * b; e += NT) kept += V[e] * U64[e];
+    kept = wave_sum_u(kept);
     if (lane == 0) rd[wv] = kept;
     __syncthreads();
     if (tid == 0) shd[0] = fmax(fro2 - ((rd[0] + rd[1]) + (rd[2] + rd[3])), 0.0);
     __syncthreads();
   }
+  const int64_t t_dirs = clock64();
 
   // ---- 6. Householder reflectors of the kept directions ----------------------
   for (int cv = 0; cv < kb; ++cv) {
@@ -3994,114 +4130,68 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
     __syncthreads();
   }
 
-  // ---- 7. U_i = H_0 ... H_{kb-1}: one wavefront per column ------------------
-  for (int col = wv; col < b; col += 4) {
-    double q[BG_MAXB / 64];
-#pragma unroll
-    for (int u = 0; u < BG_MAXB / 64; ++u) q[u] = (lane + 64 * u == col) ? 1.0 : 0.0;
-    for (int cv = kb - 1; cv >= 0; --cv) {
-      const double* vr = V + (int64_t)cv * b;
-      double dd = 0.0;
-#pragma unroll
-      for (int u = 0; u < BG_MAXB / 64; ++u) {
-        const int t = lane + 64 * u;
-        if (t < b) dd += vr[t] * q[u];
-      }
-      dd = wave_sum_u(dd) * tau[cv];
-#pragma unroll
-      for (int u = 0; u < BG_MAXB / 64; ++u) {
-        const int t = lane + 64 * u;
-        if (t < b) q[u] -= dd * vr[t];
-      }
+  // ---- 7. U_i = H_0 ... H_{kb-1} = I - V T V^T (compact WY form, T upper
+  // triangular: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j),
+  // then U_i = I - V (T V^T) on the matrix cores ---------------------------
+  double* Tm = S;   // kb x kb in LDS, stride BG_SLD: T above the diagonal, v_l^T v_j below
+  for (int pq = wv; pq < kb * kb; pq += 4) {
+    const int l = pq / kb, j = pq % kb;
+    if (l >= j) continue;
+    const double* vl = V + (int64_t)l * b;
+    const double* vj = V + (int64_t)j * b;
+    double dd = 0.0;
+    for (int t = j + lane; t < b; t += 64) dd += vl[t] * vj[t];   // v_j is zero above row j
+    dd = wave_sum_u(dd);
+    if (lane == 0) Tm[j * BG_SLD + l] = dd;
+  }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    // T(l, j) for l < j from the finished columns 0..j-1
+    if (tid < j) {
+      double s = 0.0;
+      for (int q = tid; q < j; ++q) s += Tm[tid * BG_SLD + q] * Tm[j * BG_SLD + q];
+      Tm[tid * BG_SLD + j] = -tau[j] * s;
     }
+    if (tid == 0) Tm[j * BG_SLD + j] = tau[j];
+    __syncthreads();
+  }
+  // Z = T V^T (kb x b) into X's storage: thread t, 16 rows of Z at a time
+  double* Z = X;
+  for (int t = tid; t < b; t += NT) {
+    for (int j0 = 0; j0 < kb; j0 += 16) {
+      double acc[16];
 #pragma unroll
-    for (int u = 0; u < BG_MAXB / 64; ++u) {
-      const int t = lane + 64 * u;
-      if (t < b) {
-        Ug[(int64_t)t * b + col] = (T)q[u];
-        if (cert) U64[(int64_t)t * b + col] = q[u];
+      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      for (int l = j0; l < kb; ++l) {
+        const double x = V[(int64_t)l * b + t];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (j0 + u <= l) acc[u] += Tm[(j0 + u) * BG_SLD + l] * x;
       }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (j0 + u < kb) Z[(int64_t)(j0 + u) * b + t] = acc[u];
     }
   }
+  __syncthreads();   // Z complete, T consumed: the LDS holds the staging again
+  wg_gemm_f64<T>(V, b, true, Z, b, false, Ug, b, b, b, kb, false, -1.0, 1.0, cert ? U64 : nullptr, Sa, Sb, rd);
   if (tid == 0) {
     A.rank[i] = r;
     A.edrop[i] = shd[0];
     if (A.rec) A.rec[(A.rec_off + i) * REC_W + NFEAT] = (float)shi[0] / (float)b;
-  }
-}
-
-// C (m x n, row stride ldc) = alpha op(A) B by one workgroup on the FP64
-// matrix cores: 64 x 64 output tiles in turn, 64 columns of the inner
-// dimension at a time staged in LDS (Sa, Sb: 64 x TLD doubles each); operand
-// and result lanes as in k_bg_gram.  op(A)(p, q) = A[p lda + q], or
-// A[q lda + p] with ta.  With sym the product is known to be symmetric: only
-// the tiles on and above the diagonal are formed, and mirrored.  Returns, to
-// every thread, the sum of squares of C and its trace.
-__device__ double2 wg_gemm_f64(const double* A, int lda, bool ta, const double* B, int ldb, double* C, int ldc,
-                               int m, int n, int kd, bool sym, double alpha, double* Sa, double* Sb, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
-  const int mt = (m + 63) / 64, nt = (n + 63) / 64;
-  double f2 = 0.0, trc = 0.0;
-  for (int ti = 0; ti < mt; ++ti)
-    for (int tj = sym ? ti : 0; tj < nt; ++tj) {
-      const int ra = 64 * ti, rb = 64 * tj, na = min(64, m - ra), nb = min(64, n - rb);
-      dbl4 acc[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
-      for (int kc = 0; kc < kd; kc += 64) {
-        const int mc = min(64, kd - kc), mc4 = (mc + 3) & ~3;
-        __syncthreads();   // the previous chunk's operands consumed
-        // the unit-stride index of each operand on consecutive threads
-        for (int e = tid; e < 64 * 64; e += NT) {
-          const int k = ta ? (e >> 6) : (e & 63);
-          const int a = ta ? (e & 63) : (e >> 6);
-          double x = 0.0;
-          if (k < mc && a < na)
-            x = ta ? A[(int64_t)(kc + k) * lda + ra + a] : A[(int64_t)(ra + a) * lda + kc + k];
-          Sa[k * TLD + a] = x;
-          const int kq = e >> 6, c = e & 63;
-          Sb[kq * TLD + c] = (kq < mc && c < nb) ? B[(int64_t)(kc + kq) * ldb + rb + c] : 0.0;
-        }
-        __syncthreads();
-        const double* fa = Sa + fk * TLD + 16 * wv + fr;
-        const double* fb = Sb + fk * TLD + fr;
-        for (int k0 = 0; k0 < mc4; k0 += 4) {
-          const double av = fa[k0 * TLD];
-          double bv[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) bv[c] = fb[k0 * TLD + 16 * c];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c], 0, 0, 0);
-        }
-      }
-      const double wgt = (sym && ti != tj) ? 2.0 : 1.0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int row = 16 * wv + 4 * j + fk, col = 16 * c + fr;
-          if (row < na && col < nb) {
-            const double v = alpha * acc[c][j];
-            C[(int64_t)(ra + row) * ldc + rb + col] = v;
-            if (sym && ti != tj) C[(int64_t)(rb + col) * ldc + ra + row] = v;
-            f2 += wgt * v * v;
-            if (ra + row == rb + col) trc += v;
-          }
-        }
+    if (A.dbg) {
+      // phase cycles: pivoted Cholesky, X X^T and Jacobi, truncation checks
+      // and kept directions, reflectors and U_i
+      int64_t* dd = A.dbg + 72 * (int64_t)i;
+      dd[0] = ma;
+      dd[1] = (truncated ? 1 : 0) + (cert ? 2 : 0);
+      dd[3] = b;
+      dd[4] = t_chol - t_start;
+      dd[5] = t_eig - t_chol;
+      dd[6] = t_dirs - t_eig;
+      dd[7] = clock64() - t_dirs;
     }
-  f2 = wave_sum_u(f2);
-  trc = wave_sum_u(trc);
-  __syncthreads();   // red free
-  if (lane == 0) {
-    red[wv] = f2;
-    red[4 + wv] = trc;
   }
-  __syncthreads();
-  const double2 out = {(red[0] + red[1]) + (red[2] + red[3]), (red[4] + red[5]) + (red[6] + red[7])};
-  // C visible to the whole workgroup before it is read as an operand
-  __threadfence();
-  __syncthreads();
-  return out;
 }
 
 // Certificate for a big-block step whose truncated pivoted Cholesky did not
@@ -4147,8 +4237,9 @@ __global__ __launch_bounds__(NT) void k_bg_cert(LevelArgs<T> A, int32_t s0) {
     return;
   }
   // Y = G U_2 (b x n2), then C = U_2^T Y (n2 x n2) over G's storage
-  wg_gemm_f64(G, b, false, U64 + r, b, Y, n2, b, n2, b, false, 1.0, Sa, Sb, red);
-  const double2 ft = wg_gemm_f64(U64 + r, b, true, Y, n2, G, n2, n2, n2, b, true, 1.0, Sa, Sb, red);
+  wg_gemm_f64<double>(G, b, false, U64 + r, b, false, Y, n2, b, n2, b, false, 1.0, 0.0, nullptr, Sa, Sb, red);
+  const double2 ft =
+      wg_gemm_f64<double>(U64 + r, b, true, Y, n2, false, G, n2, n2, n2, b, true, 1.0, 0.0, nullptr, Sa, Sb, red);
   const double tol = 1e-6;   // far above the rounding of the products
   int verdict = 0;           // 1 certified, -1 refuted
   if (ft.x > 0.0) {
@@ -4169,7 +4260,8 @@ __global__ __launch_bounds__(NT) void k_bg_cert(LevelArgs<T> A, int32_t s0) {
         break;
       }
       // P = (M / ||M||_F)^2: its norm g gives log ||C^(2^(q+1))||_F = 2 ell + log g
-      const double2 pg = wg_gemm_f64(M, n2, false, M, n2, P, n2, n2, n2, n2, true, scale * scale, Sa, Sb, red);
+      const double2 pg = wg_gemm_f64<double>(M, n2, false, M, n2, false, P, n2, n2, n2, n2, true, scale * scale, 0.0,
+                                             nullptr, Sa, Sb, red);
       if (!(pg.x > 0.0)) {
         verdict = -1;   // not possible for a symmetric M of unit norm: left to the generic kernel
         break;
