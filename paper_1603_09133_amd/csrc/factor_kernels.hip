@@ -4398,6 +4398,273 @@ __global__ __launch_bounds__(NT) void k_schur_big(LevelArgs<T> A, int32_t p0) {
   }
 }
 
+// The two panels and the target block of a Schur pair (a, c) of step i: the
+// basis rows (index 0, width r_i) or close view a - 1 (live width), and the
+// strides of the target T(a, c) within its slot; the panels are exchanged
+// where that gives the target unit stride along c.
+template <typename T>
+struct SchurPair {
+  const T* pa;
+  const T* pc;
+  T* tbase;
+  int64_t ts_a, ts_c;
+  int la, lc, ba, bc, ta, tcv;
+};
+
+template <typename T>
+__device__ inline SchurPair<T> schur_pair(const LevelArgs<T>& A, const Pair& pr, const Step& st, int b, int r) {
+  SchurPair<T> o;
+  T* D = A.arena + A.slot_off[st.blk];
+  o.ba = b;
+  o.bc = b;
+  o.ta = 0;
+  o.tcv = 0;
+  if (pr.a == 0) {
+    o.la = r;
+    o.pa = D;
+  } else {
+    const View va = A.views[st.view0 + pr.a - 1];
+    o.ba = A.bsz[va.x];
+    o.la = va.proc ? A.rank[va.x] : o.ba;
+    o.pa = A.arena + A.slot_off[va.slot];
+    o.ta = va.trans;
+  }
+  T* pcw;
+  if (pr.c == 0) {
+    o.lc = r;
+    pcw = D;
+  } else {
+    const View vc = A.views[st.view0 + pr.c - 1];
+    o.bc = A.bsz[vc.x];
+    o.lc = vc.proc ? A.rank[vc.x] : o.bc;
+    pcw = A.arena + A.slot_off[vc.slot];
+    o.tcv = vc.trans;
+  }
+  o.pc = pcw;
+  if (pr.a == 0) {
+    if (pr.c == 0) {
+      o.tbase = D;
+      o.ts_a = b;
+      o.ts_c = 1;
+    } else {
+      o.tbase = pcw;
+      o.ts_a = o.tcv ? 1 : o.bc;
+      o.ts_c = o.tcv ? b : 1;
+    }
+  } else {
+    o.tbase = A.arena + A.slot_off[pr.slot];
+    if (pr.trans) {
+      o.ts_a = 1;
+      o.ts_c = o.ba;
+    } else {
+      o.ts_a = o.bc;
+      o.ts_c = 1;
+    }
+  }
+  if (o.ts_c != 1) {
+    // T(a, c)^T = P_c^T P_a: with the roles of the panels exchanged the
+    // target's unit stride runs along the lanes of an output row
+    const T* tp = o.pa;
+    o.pa = o.pc;
+    o.pc = tp;
+    int t = o.la;
+    o.la = o.lc;
+    o.lc = t;
+    t = o.ba;
+    o.ba = o.bc;
+    o.bc = t;
+    t = o.ta;
+    o.ta = o.tcv;
+    o.tcv = t;
+    const int64_t u = o.ts_a;
+    o.ts_a = o.ts_c;
+    o.ts_c = u;
+  }
+  return o;
+}
+
+// Schur update of the FP32 factor with BF16-input products for steps with
+// 64 < b_i <= BG_MAXB: T(a, c) -= P_a^T P_c.  Pairs of two panels wider than
+// 64 columns (k_schur_big_bf16w): output blocks of 128 x 128
+// (wavefront w the 64 x 64 quarter (w / 2, w % 2), as 2 x 2 tiles of 32 x 32 on
+// v_mfma_f32_32x32x8bf16_1k with FP32 accumulation, lanes as in
+// k_schur_bf16), the n_i panel rows staged 32 at a time in LDS as FP32; each
+// thread holds its share of the next chunk in registers while the current one
+// is multiplied.  Other pairs (k_schur_big_bf16): 64 x 64 tiles, 64 panel
+// rows at a time.
+constexpr int SB_W = 128, SB_K = 32, SB_LD = SB_W + 4;
+
+template <typename T>
+size_t work_schur_big_bf16() {
+  return (size_t)2 * SB_K * SB_LD * sizeof(T);
+}
+
+// Element u of this thread's share of a chunk: (row k, column c) of the two
+// panels (u < 16: P_a, else P_c), the unit-stride index on consecutive threads.
+template <typename T>
+__device__ inline T sb_load(const SchurPair<T>& P, int b, int u, int row0, int nk, int a0, int tan, int c0, int tcn) {
+  const bool q = u >= 16;
+  const int e = threadIdx.x + NT * (u & 15);
+  const int trans = q ? P.tcv : P.ta;
+  const int k = trans ? (e & (SB_K - 1)) : (e / SB_W), c = trans ? (e / SB_K) : (e & (SB_W - 1));
+  const int tw = q ? tcn : tan, col0 = q ? c0 : a0, bx = q ? P.bc : P.ba;
+  const T* base = q ? P.pc : P.pa;
+  if (k >= nk || c >= tw) return T(0);
+  return trans ? base[(int64_t)(col0 + c) * b + row0 + k] : base[(int64_t)(row0 + k) * bx + col0 + c];
+}
+
+template <typename T>
+__device__ inline int sb_slot(const SchurPair<T>& P, int u) {
+  const bool q = u >= 16;
+  const int e = threadIdx.x + NT * (u & 15);
+  const int trans = q ? P.tcv : P.ta;
+  const int k = trans ? (e & (SB_K - 1)) : (e / SB_W), c = trans ? (e / SB_K) : (e & (SB_W - 1));
+  return (q ? SB_K * SB_LD : 0) + k * SB_LD + c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_big_bf16(LevelArgs<T> A, int32_t p0) {
+  const Pair pr = A.pairs[p0 + xcd_swizzle(blockIdx.x, gridDim.x)];
+  const Step st = A.steps[pr.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b <= 64 || b > BG_MAXB) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const SchurPair<T> P = schur_pair(A, pr, st, b, r);
+  if (P.la == 0 || P.lc == 0) return;
+  if (P.la > 64 && P.lc > 64) return;   // k_schur_big_bf16w
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l32 = lane & 31, kh = 4 * (lane >> 5);
+  // a narrow panel: 64 x 64 output tiles, the four wavefronts 2 x 2 tiles of
+  // 32 x 32, panel rows staged 64 at a time (stride TLD)
+  T* Qa = reinterpret_cast<T*>(smem_raw);
+  T* Qc = Qa + 64 * TLD;
+  const int si = wv >> 1, sj = wv & 1;
+  const int ia = si * 32 + l32, jb = sj * 32 + l32;
+  for (int a0 = 0; a0 < P.la; a0 += 64) {
+    const int tan = min(64, P.la - a0);
+    for (int c0 = 0; c0 < P.lc; c0 += 64) {
+      const int tcn = min(64, P.lc - c0);
+      f32x16_t acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      for (int k0 = 0; k0 < n; k0 += 64) {
+        const int nk = min(64, n - k0), nk8 = (nk + 7) & ~7;
+        __syncthreads();
+        load_tile_pair(Qa, P.pa, TileSrc{P.ta, b, P.ba, a0, tan}, P.pc, TileSrc{P.tcv, b, P.bc, c0, tcn}, r + k0,
+                       nk);
+        // rows nk .. nk8 - 1 of both tiles are zero: the k loop runs in steps of eight
+        for (int e = threadIdx.x; e < (nk8 - nk) * 64; e += NT) {
+          Qa[(nk + (e >> 6)) * TLD + (e & 63)] = T(0);
+          Qc[(nk + (e >> 6)) * TLD + (e & 63)] = T(0);
+        }
+        __syncthreads();
+        for (int k = 0; k < nk8; k += 8) {
+          bf16x4_t av, bv;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            av[t] = to_bf16((float)Qa[(k + kh + t) * TLD + ia]);
+            bv[t] = to_bf16((float)Qc[(k + kh + t) * TLD + jb]);
+          }
+          acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int al = si * 32 + 8 * (v >> 2) + kh + (v & 3);
+        const int gm = sj * 32 + l32;
+        if (al < tan && gm < tcn) {
+          T* tp = P.tbase + (int64_t)(a0 + al) * P.ts_a + (int64_t)(c0 + gm) * P.ts_c;
+          *tp = (T)((float)*tp - acc[v]);
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_big_bf16w(LevelArgs<T> A, int32_t p0) {
+  const Pair pr = A.pairs[p0 + xcd_swizzle(blockIdx.x, gridDim.x)];
+  const Step st = A.steps[pr.step];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b <= 64 || b > BG_MAXB) return;
+  const int r = A.rank[i];
+  const int n = b - r;
+  if (n <= 0) return;
+  const SchurPair<T> P = schur_pair(A, pr, st, b, r);
+  if (P.la == 0 || P.lc == 0) return;
+  if (P.la <= 64 || P.lc <= 64) return;   // k_schur_big_bf16
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l32 = lane & 31, kh = 4 * (lane >> 5);
+  T* Pa = reinterpret_cast<T*>(smem_raw);   // [k][a], SB_K x SB_LD
+  T* Pc = Pa + SB_K * SB_LD;                 // [k][c]
+  const int ra = 64 * (wv >> 1), rc = 64 * (wv & 1);
+  for (int a0 = 0; a0 < P.la; a0 += SB_W) {
+    const int tan = min(SB_W, P.la - a0);
+    for (int c0 = 0; c0 < P.lc; c0 += SB_W) {
+      const int tcn = min(SB_W, P.lc - c0);
+      f32x16_t acc[2][2];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[ti][tj][v] = 0.0f;
+      T nxt[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) nxt[u] = sb_load(P, b, u, r, min(SB_K, n), a0, tan, c0, tcn);
+      for (int k0 = 0; k0 < n; k0 += SB_K) {
+        __syncthreads();   // the previous chunk consumed
+#pragma unroll
+        for (int u = 0; u < 32; ++u) Pa[sb_slot(P, u)] = nxt[u];   // P_c's slots follow P_a's
+        __syncthreads();
+        if (k0 + SB_K < n) {
+          const int nk2 = min(SB_K, n - k0 - SB_K);
+#pragma unroll
+          for (int u = 0; u < 32; ++u) nxt[u] = sb_load(P, b, u, r + k0 + SB_K, nk2, a0, tan, c0, tcn);
+        }
+        // rows beyond the chunk's end are zero (loaded as zero), so the k
+        // loop always runs over SB_K
+#pragma unroll
+        for (int kk = 0; kk < SB_K; kk += 8) {
+          bf16x4_t av[2], bv[2];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              av[h][t] = to_bf16((float)Pa[(kk + kh + t) * SB_LD + ra + 32 * h + l32]);
+              bv[h][t] = to_bf16((float)Pc[(kk + kh + t) * SB_LD + rc + 32 * h + l32]);
+            }
+          }
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+              acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int al = ra + 32 * ti + 8 * (v >> 2) + kh + (v & 3);
+            const int gm = rc + 32 * tj + l32;
+            if (al < tan && gm < tcn) {
+              T* tp = P.tbase + (int64_t)(a0 + al) * P.ts_a + (int64_t)(c0 + gm) * P.ts_c;
+              *tp = (T)((float)*tp - acc[ti][tj][v]);
+            }
+          }
+    }
+  }
+}
+
 // Strip products of the steps with 64 < b_i <= BG_MAXB.  A strip of SW
 // columns of a view (its rows row0 .. row0 + m; SW = 64 for an FP32 factor,
 // 32 for FP64, so that BG_MAXB rows fit in LDS) is staged in LDS and
@@ -4809,8 +5076,10 @@ __global__ __launch_bounds__(NT) void k_feat_mlp(LevelArgs<T> A, int32_t s0) {
   const int b = A.bsz[i];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (A.rec && tid < REC_W) A.rec[(A.rec_off + i) * REC_W + tid] = tid < NFEAT ? 0.0f : -1.0f;
-  if (st.nfar == 0 || b == 0) {
-    if (tid == 0) A.lwidth[i] = b;   // nothing to compress: no cap
+  // nothing to compress, or (capped ranks) a block the Gram kernels do not
+  // take: no cap, and no features to compute
+  if (st.nfar == 0 || b == 0 || (!A.feat_only && b > 128)) {
+    if (tid == 0) A.lwidth[i] = b;
     return;
   }
   __shared__ double red[NT / WV];
@@ -5096,7 +5365,16 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
     else
       hipLaunchKernelGGL(k_schur_t<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
   }
-  if (big && w.p1 > w.p0) hipLaunchKernelGGL(k_schur_big<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+  if (big && w.p1 > w.p0) {
+    if (A.bf16_schur && sizeof(T) == sizeof(float)) {
+      // pairs with a narrow panel, then pairs of two wide ones (kernels of
+      // their own: the wide one's registers would cost the narrow one occupancy)
+      hipLaunchKernelGGL(k_schur_big_bf16<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+      hipLaunchKernelGGL(k_schur_big_bf16w<T>, dim3(w.p1 - w.p0), dim3(NT), work_schur_big_bf16<T>(), stream, B,
+                         w.p0);
+    } else
+      hipLaunchKernelGGL(k_schur_big<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
+  }
   if (generic) launch<T>(k_schur<T>, G, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream, bmax);
 }
 

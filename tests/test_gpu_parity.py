@@ -610,6 +610,36 @@ def test_bf16_schur_factor(dims, patch, eps):
     an.close()
 
 
+def test_bf16_schur_factor_with_blocks_above_128():
+    """The configured 3D arithmetic (FP32 factor, BF16-input Schur products)
+    on the 20^3 Laplacian with sibling coarsening, whose second level holds
+    blocks of up to 215 unknowns (the big-block Schur kernel on BF16 matrix
+    cores): M within the BF16 bar of the FP64 oracle, every block above 128
+    unknowns compressed, and PCG to 1e-8 within a few iterations of the
+    oracle's."""
+    cae = _cae()
+    d = _big_oracle()
+    A, csr, perm, bp, co, eps, fo = (d[k] for k in ("A", "csr", "perm", "bp", "co", "eps", "fo"))
+    an = cae.Analysis(csr[0], csr[1], perm, bp, co, order=cae.ORDER_MULTICOLOUR)
+    f = cae.Factor(an, torch.from_numpy(csr[2]).cuda(), eps, precision=cae.FP32_BF16, coarse_max_dim=0)
+    st = f.stats()
+    X = _probes(A.shape[0])
+    MX = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
+    MXo = ce_multiply(fo, X)
+    rel = np.linalg.norm(MX - MXo) / np.linalg.norm(MXo)
+    b = problems.rhs_uniform(A.shape[0], seed=0)
+    _, it, relr = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-8)
+    _, ito, _ = oracle.pcg(A, b, lambda r: ce_solve(fo, r), tol=1e-8)
+    nbig = sum(st[k] for k in ("big_untruncated", "big_frobenius", "big_certified", "big_generic"))
+    print(f"bf16 (b > 128): probe error vs oracle {rel:.3e}, big compressions {nbig}, PCG {int(it[0])} vs {ito}")
+    assert nbig > 0
+    assert rel <= 2e-3, rel
+    assert f.converged and relr[0] <= 1.0001e-8
+    assert it[0] <= ito + 6, (it[0], ito)
+    f.close()
+    an.close()
+
+
 def test_compensation_matches_oracle_and_prevents_breakdown():
     """Diagonal compensation on the biharmonic operator, which breaks the
     plain method at eps = 1e-3: the GPU reports CAE_ENOTSPD without it, and
