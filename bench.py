@@ -8,7 +8,9 @@ residual of 1e-8.  The configured factor is the mixed-precision one: FP32
 blocks, Schur products with BF16 inputs and FP32 accumulation on the matrix
 cores, learned ranks (an MLP trained on a 48^3 problem before timing), the
 dense remainder, the apply vectors and PCG in FP64.  The same workload with
-the FP64 factor (exact ranks) is timed as a second leg in the same line.
+the FP64 factor (exact ranks) is timed as a second leg in the same line, and
+the configured arithmetic with exact ranks as a third (what the learned
+ranks gain or lose).
 ``--config c2``: the 2D Laplacian on 1024^2 with 8 x 8 patches, eps = 1e-6,
 16 right-hand sides, FP32 factor and the FP64 leg.
 
@@ -54,7 +56,9 @@ def _cpu_baseline(work, gpu_level1_steps_per_s, max_steps):
     the first k block steps of level 1 (Algorithm 2 on the same matrix,
     permutation, blocks, eps, coarsening and elimination order), nothing after
     them.  Measured, not scaled: once with one BLAS thread, once with a pool of
-    all host cores (the oracle's step loop itself is sequential)."""
+    all host cores on a shorter sample of the same steps (the oracle's step
+    loop itself is sequential, and a thread pool only slows its small LAPACK
+    calls down)."""
     from threadpoolctl import threadpool_limits
 
     import oracle
@@ -65,15 +69,16 @@ def _cpu_baseline(work, gpu_level1_steps_per_s, max_steps):
     # the steps of the first colour have empty far rows (nothing processed
     # yet: no compression); the sample runs through it and max_steps more
     k = int(min(work["M1"], work["first_colour"] + max_steps))
+    k_all = int(min(work["M1"], work["first_colour"] + max(max_steps // 8, 1)))
     runs, setup = {}, {}
-    for threads in (1, nproc):
+    for threads, kk in ((1, k), (nproc, k_all)):
         with threadpool_limits(limits=threads):
             t0 = time.perf_counter()
-            f = oracle.ce_factor(ip, ix, dv, perm, bp, co, oracle.CEOptions(max_steps=k, **opts))
+            f = oracle.ce_factor(ip, ix, dv, perm, bp, co, oracle.CEOptions(max_steps=kk, **opts))
             total = time.perf_counter() - t0
         runs[threads] = f.levels[0].seconds
         setup[threads] = total - runs[threads]
-        _log(f"oracle: {k} level-1 steps in {runs[threads]:.1f} s with {threads} BLAS thread(s)")
+        _log(f"oracle: {kk} level-1 steps in {runs[threads]:.1f} s with {threads} BLAS thread(s)")
     return {
         "value": runs[1], "unit": "s", "cores": 1, "kind": "oracle",
         "sample": (f"the first {k} of the {work['M1']} level-1 block steps of this workload's factorization "
@@ -84,8 +89,10 @@ def _cpu_baseline(work, gpu_level1_steps_per_s, max_steps):
                    f"(permutation, level-1 blocks, symbolic pattern, {setup[1]:.1f} s) is not included"),
         "steps": k,
         "steps_per_s": k / runs[1],
-        "all_cores": {"value": runs[nproc], "unit": "s", "cores": nproc, "steps_per_s": k / runs[nproc],
-                      "note": "BLAS pool of all host cores; the step loop is sequential"},
+        "all_cores": {"value": runs[nproc], "unit": "s", "cores": nproc, "steps": k_all,
+                      "steps_per_s": k_all / runs[nproc],
+                      "note": (f"the first {k_all} steps of the same sample with a BLAS pool of all host cores; "
+                               "the step loop is sequential")},
         "nproc": nproc,
         "cpu_model": _cpu_model(),
         "gpu_level1_steps_per_s": gpu_level1_steps_per_s,
@@ -176,6 +183,8 @@ def main():
     ap.add_argument("--exact-ranks", action="store_true", help="c3: exact ranks instead of learned ones")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the FP64 leg (at most --steps)")
     ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--exact-steps", type=int, default=2,
+                    help="learned ranks: timed steps of the same arithmetic with exact ranks (0 = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1024,
                     help="compressing level-1 steps of the oracle baseline sample")
@@ -266,6 +275,9 @@ def main():
         return res
 
     main_leg = leg("configured", work["precision"], fkw, args.steps, args.warmup)
+    exact = None
+    if fkw and args.exact_steps > 0:
+        exact = leg("exact ranks", work["precision"], {}, min(args.steps, args.exact_steps), min(args.warmup, 1))
     f64 = None
     if not args.no_fp64_leg:
         n64 = min(args.steps, args.fp64_steps)
@@ -314,6 +326,14 @@ def main():
         out["config"]["sketch_accepted"] = st["sketch_accepted"]
         out["config"]["sketch_rejected"] = st["sketch_rejected"]
         out["config"]["mlp_training_s"] = train_s
+    if exact is not None:
+        out["config"]["exact_ranks_leg"] = {
+            "s_per_step": exact["s_per_step"], "steps": exact["steps"],
+            "factor_ms_mean": float(np.mean(exact["factor_ms"])), "level_ms": exact["level_ms"],
+            "pcg_iters": exact["it"].tolist(), "relres_max": float(np.max(exact["rel"])),
+            "learned_speedup": exact["s_per_step"] / value,
+            "note": "the configured arithmetic with exact ranks: learned_speedup > 1 means the learned ranks save time",
+        }
     if f64 is not None:
         s64 = f64["stats"]
         out["config"]["fp64_leg"] = {

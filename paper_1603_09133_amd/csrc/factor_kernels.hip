@@ -3761,8 +3761,8 @@ __device__ double2 wg_gemm_f64(const double* A, int lda, bool ta, const double* 
 // ---------------------------------------------------------------------------
 constexpr int BG_SLD = BG_MA + 4;   // row stride of S in LDS
 
-// per step: G (b x b), X (BG_MA x b), U in FP64 (b x b), work (b x b)
-int64_t bg_stride(int bmax) { return (int64_t)3 * bmax * bmax + (int64_t)BG_MA * bmax; }
+// per step: G (b x b), X (BG_MA x b), U in FP64 (b x b), two work areas (b x b)
+int64_t bg_stride(int bmax) { return (int64_t)4 * bmax * bmax + (int64_t)BG_MA * bmax; }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0) {
@@ -3838,6 +3838,74 @@ __global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0) {
     }
 }
 
+// Left-looking pivoted Cholesky G ~ X^T X of a b x b Gram matrix (row
+// stride b): row k of X (stride ldx, columns in G's order) from column p of G,
+// p the largest trailing diagonal entry, until the trailing trace is at most
+// stop2 or cap rows are written.  dg (b doubles, G's diagonal on entry) and
+// chosen (b bytes, zero on entry) in LDS, xp (cap doubles), rd / ri (8
+// slots); every thread of the workgroup calls it.  Returns the number of rows;
+// *inactive = the trailing trace, *truncated = stopped by the cap.
+__device__ int gram_pivoted_chol(const double* G, double* X, int ldx, int b, double stop2, int cap, double* dg,
+                                 double* xp, unsigned char* chosen, double* rd, int* ri, double* inactive,
+                                 bool* truncated) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int k = 0;
+  *truncated = false;
+  for (;; ++k) {
+    __syncthreads();   // dg and chosen of the previous pivot, rd free
+    double rs = 0.0, cv = -1.0;
+    int ci = 0x7fffffff;
+    for (int t = tid; t < b; t += NT)
+      if (!chosen[t]) {
+        rs += dg[t];
+        if (dg[t] > cv) {
+          cv = dg[t];
+          ci = t;
+        }
+      }
+    rs = wave_sum_u(rs);
+    wave_argmax_u(cv, ci);
+    if (lane == 0) {
+      rd[wv] = rs;
+      rd[4 + wv] = cv;
+      ri[wv] = ci;
+    }
+    __syncthreads();
+    rs = (rd[0] + rd[1]) + (rd[2] + rd[3]);
+    cv = rd[4];
+    ci = ri[0];
+    for (int u = 1; u < 4; ++u) amax_step(cv, ci, rd[4 + u], ri[u]);
+    if (rs <= stop2 || !(cv > 0.0)) {
+      *inactive = rs;
+      break;
+    }
+    if (k == cap) {
+      // truncated: the trailing energy rs stays outside X
+      *inactive = rs;
+      *truncated = true;
+      break;
+    }
+    const int p = ci;
+    const double ilpp = 1.0 / sqrt(cv), lpp = cv * ilpp;
+    for (int j = tid; j < k; j += NT) xp[j] = X[(int64_t)j * ldx + p];
+    __syncthreads();
+    for (int t = tid; t < b; t += NT) {
+      double s = G[(int64_t)p * b + t];
+      int j = 0;
+      for (; j + 4 <= k; j += 4)
+        s -= (X[(int64_t)j * ldx + t] * xp[j] + X[(int64_t)(j + 1) * ldx + t] * xp[j + 1]) +
+             (X[(int64_t)(j + 2) * ldx + t] * xp[j + 2] + X[(int64_t)(j + 3) * ldx + t] * xp[j + 3]);
+      for (; j < k; ++j) s -= X[(int64_t)j * ldx + t] * xp[j];
+      const double lv = chosen[t] ? 0.0 : (t == p ? lpp : s * ilpp);
+      X[(int64_t)k * ldx + t] = lv;
+      if (!chosen[t] && t != p) dg[t] -= lv * lv;
+    }
+    __syncthreads();
+    if (tid == 0) chosen[p] = 1;
+  }
+  return k;
+}
+
 template <typename T>
 size_t work_bg_eig() {
   return (size_t)BG_MA * BG_SLD * sizeof(double) + (size_t)BG_MAXB * sizeof(double) +
@@ -3904,64 +3972,11 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   // factor would otherwise pivot down to its rounding level
   const double stop2 = A.rank_mode == 0 ? fmax(aerr * aerr, theta * theta / 1024.0) : aerr * aerr;
   double inactive = 0.0;
-  int k = 0;
   bool truncated = false;
   // at most bg_cap <= BG_MA pivots (the learned width does not cap big blocks:
   // their far rows carry long tails of singular values just below theta)
-  const int cap = min(max(A.bg_cap, 1), BG_MA);
-  for (;; ++k) {
-    __syncthreads();   // dg and chosen of the previous pivot, rd free
-    double rs = 0.0, cv = -1.0;
-    int ci = 0x7fffffff;
-    for (int t = tid; t < b; t += NT)
-      if (!chosen[t]) {
-        rs += dg[t];
-        if (dg[t] > cv) {
-          cv = dg[t];
-          ci = t;
-        }
-      }
-    rs = wave_sum_u(rs);
-    wave_argmax_u(cv, ci);
-    if (lane == 0) {
-      rd[wv] = rs;
-      rd[4 + wv] = cv;
-      ri[wv] = ci;
-    }
-    __syncthreads();
-    rs = (rd[0] + rd[1]) + (rd[2] + rd[3]);
-    cv = rd[4];
-    ci = ri[0];
-    for (int u = 1; u < 4; ++u) amax_step(cv, ci, rd[4 + u], ri[u]);
-    if (rs <= stop2 || !(cv > 0.0)) {
-      inactive = rs;
-      break;
-    }
-    if (k == cap) {
-      // truncated: the trailing energy rs stays outside X; the step is kept
-      // only if it cannot change the rank (checked once the ranks are known)
-      inactive = rs;
-      truncated = true;
-      break;
-    }
-    const int p = ci;
-    const double ilpp = 1.0 / sqrt(cv), lpp = cv * ilpp;
-    for (int j = tid; j < k; j += NT) xp[j] = X[(int64_t)j * b + p];
-    __syncthreads();
-    for (int t = tid; t < b; t += NT) {
-      double s = G[(int64_t)p * b + t];
-      int j = 0;
-      for (; j + 4 <= k; j += 4)
-        s -= (X[(int64_t)j * b + t] * xp[j] + X[(int64_t)(j + 1) * b + t] * xp[j + 1]) +
-             (X[(int64_t)(j + 2) * b + t] * xp[j + 2] + X[(int64_t)(j + 3) * b + t] * xp[j + 3]);
-      for (; j < k; ++j) s -= X[(int64_t)j * b + t] * xp[j];
-      const double lv = chosen[t] ? 0.0 : (t == p ? lpp : s * ilpp);
-      X[(int64_t)k * b + t] = lv;
-      if (!chosen[t] && t != p) dg[t] -= lv * lv;
-    }
-    __syncthreads();
-    if (tid == 0) chosen[p] = 1;
-  }
+  const int k = gram_pivoted_chol(G, X, b, b, stop2, min(max(A.bg_cap, 1), BG_MA), dg, xp, chosen, rd, ri,
+                                  &inactive, &truncated);
   const int ma = k;
   __syncthreads();
   const int64_t t_chol = clock64();
@@ -4220,9 +4235,10 @@ __global__ __launch_bounds__(NT) void k_bg_cert(LevelArgs<T> A, int32_t s0) {
   if (A.need_exact && !A.need_exact[i]) return;
   if (A.big_fail[i] != 2) return;
   const int r = A.rank[i], n2 = b - r;
-  double* G = A.big + (int64_t)blockIdx.x * A.big_stride;
+  const double* G = A.big + (int64_t)blockIdx.x * A.big_stride;   // left intact (k_bg_full)
   const double* U64 = G + (int64_t)b * b + (int64_t)BG_MA * b;
   double* Y = const_cast<double*>(U64) + (int64_t)b * b;
+  double* W = Y + (int64_t)b * b;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Sa = reinterpret_cast<double*>(smem_raw);
   double* Sb = Sa + 64 * TLD;
@@ -4236,15 +4252,15 @@ __global__ __launch_bounds__(NT) void k_bg_cert(LevelArgs<T> A, int32_t s0) {
     }
     return;
   }
-  // Y = G U_2 (b x n2), then C = U_2^T Y (n2 x n2) over G's storage
+  // Y = G U_2 (b x n2), then C = U_2^T Y (n2 x n2) into W
   wg_gemm_f64<double>(G, b, false, U64 + r, b, false, Y, n2, b, n2, b, false, 1.0, 0.0, nullptr, Sa, Sb, red);
   const double2 ft =
-      wg_gemm_f64<double>(U64 + r, b, true, Y, n2, false, G, n2, n2, n2, b, true, 1.0, 0.0, nullptr, Sa, Sb, red);
+      wg_gemm_f64<double>(U64 + r, b, true, Y, n2, false, W, n2, n2, n2, b, true, 1.0, 0.0, nullptr, Sa, Sb, red);
   const double tol = 1e-6;   // far above the rounding of the products
   int verdict = 0;           // 1 certified, -1 refuted
   if (ft.x > 0.0) {
     double ell = 0.5 * log(ft.x);   // log ||C^(2^q)||_F
-    double* M = G;
+    double* M = W;
     double* P = Y;
     double scale = exp(-ell);        // 1 / ||M||_F
     const double ln = log((double)n2);
@@ -4279,7 +4295,168 @@ __global__ __launch_bounds__(NT) void k_bg_cert(LevelArgs<T> A, int32_t s0) {
   if (threadIdx.x == 0) {
     A.big_fail[i] = verdict > 0 ? 0 : 1;
     if (verdict > 0) A.edrop[i] = fmax(ft.y, 0.0);
-    if (A.bg_count) atomicAdd(A.bg_count + (verdict > 0 ? 2 : 3), 1);
+    if (A.bg_count && verdict > 0) atomicAdd(A.bg_count + 2, 1);
+  }
+}
+
+// A big step the certificate refuted (big_fail = 1): the exact rank without a
+// pivot cap.  The pivoted Cholesky of its Gram matrix runs to the end (up to b
+// rows, the trailing energy of k_bg_eig), then a one-sided Jacobi on the rows
+// of X (four wavefronts, rows of BM coordinates in global memory): X^T X ~ G
+// is kept by the rotations and the rows converge to sigma_k u_k^T, u_k the
+// left singular vectors of F_i, so r_i = #{sigma_k > theta}, the kept
+// directions are the normalised leading rows, and reflectors complete them to
+// U_i.  Settles the step (big_fail = 0).
+template <int BM>
+__device__ void bg_full_jacobi(double* Xr, const int* rowix, int ma, double negl, double aerr, double tol) {
+  constexpr int LP = BM / 32;   // 32 coordinates per lane
+  jacobi_rows_wg<LP, BM>(Xr, BM, rowix, ma, negl, aerr, tol);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bg_full(LevelArgs<T> A, int32_t s0) {
+  const Step st = A.steps[s0 + blockIdx.x];
+  const int i = st.blk;
+  const int b = A.bsz[i];
+  if (b < BG_MIN || b > BG_MAXB || st.nfar == 0) return;
+  if (A.need_exact && !A.need_exact[i]) return;
+  if (A.big_fail[i] != 1) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int BMr = b <= 256 ? 256 : 512;   // row length of X in the Jacobi
+  const double* G = A.big + (int64_t)blockIdx.x * A.big_stride;
+  double* Vk = const_cast<double*>(G) + (int64_t)b * b + (int64_t)BG_MA * b;   // kept directions (U64's area)
+  double* Xr = Vk + (int64_t)b * b;                                           // ma x BMr rows (the two work areas)
+  T* Ug = A.U + A.u_off[i];
+  __shared__ double dg[BG_MAXB], xp[BG_MAXB], sg[BG_MAXB], tau[BG_MAXB];
+  __shared__ int rowix[BG_MAXB], posv[BG_MAXB];
+  __shared__ unsigned char chosen[BG_MAXB];
+  __shared__ double rd[8];
+  __shared__ int ri[8];
+  const double theta = *A.theta;
+  double tr = 0.0;
+  for (int t = tid; t < b; t += NT) {
+    dg[t] = G[(int64_t)t * b + t];
+    chosen[t] = 0;
+    tr += dg[t];
+  }
+  tr = wave_sum_u(tr);
+  if (lane == 0) rd[wv] = tr;
+  __syncthreads();
+  const double fro2 = rd[0] + rd[1] + rd[2] + rd[3];
+  const double noise = (double)Eps<T>::v() * sqrt(fro2);
+  const double negl = A.rank_mode == 0 ? fmax(noise, theta / 64.0) : noise;
+  const double aerr = A.rank_mode == 0 ? fmax(noise, fmin((double)max(b, 16) * noise, theta / 32.0))
+                                       : (double)max(b, 16) * noise;
+  const double stop2 = A.rank_mode == 0 ? fmax(aerr * aerr, theta * theta / 1024.0) : aerr * aerr;
+  double inactive = 0.0;
+  bool truncated = false;
+  const int ma = gram_pivoted_chol(G, Xr, BMr, b, stop2, b, dg, xp, chosen, rd, ri, &inactive, &truncated);
+  // zero coordinates b .. BMr - 1 of every row
+  for (int e = tid; e < ma * (BMr - b); e += NT) Xr[(int64_t)(e / (BMr - b)) * BMr + b + e % (BMr - b)] = 0.0;
+  for (int t = tid; t < ma; t += NT) rowix[t] = t;
+  __syncthreads();
+  if (ma > 1) {
+    // rotations are skipped only below the rounding level of the stored
+    // entries and of FP64 (the rows are on the sigma scale: a coarser level
+    // would move a sigma near theta by that much)
+    const double tol = (double)max(b, 16) * DBL_EPSILON;
+    const double aerr_r = fmax(noise, tol * sqrt(fro2));
+    if (BMr == 256) bg_full_jacobi<256>(Xr, rowix, ma, negl, aerr_r, tol);
+    else bg_full_jacobi<512>(Xr, rowix, ma, negl, aerr_r, tol);
+  }
+  __syncthreads();
+  // singular values, order, rank, dropped energy
+  for (int k = tid; k < ma; k += NT) {
+    double s2 = 0.0;
+    for (int t = 0; t < b; ++t) s2 += Xr[(int64_t)k * BMr + t] * Xr[(int64_t)k * BMr + t];
+    sg[k] = sqrt(s2);
+  }
+  __syncthreads();
+  double cnt = 0.0;
+  for (int k = tid; k < ma; k += NT) {
+    int pos = 0;
+    const double l0 = sg[k];
+    for (int q = 0; q < ma; ++q) pos += (sg[q] > l0 || (sg[q] == l0 && q < k)) ? 1 : 0;
+    posv[k] = pos;
+    cnt += l0 > theta ? 1.0 : 0.0;
+  }
+  cnt = wave_sum_u(cnt);
+  if (lane == 0) rd[4 + wv] = cnt;
+  __syncthreads();
+  const int r = A.rank_mode == 0 ? (int)((rd[4] + rd[5]) + (rd[6] + rd[7])) : min(A.fixed_rank, ma);
+  if (tid == 0) {
+    double ed = inactive;
+    for (int k = 0; k < ma; ++k)
+      if (posv[k] >= r) ed += sg[k] * sg[k];
+    rd[0] = ed;
+  }
+  // kept directions: row k / sigma_k at position posv[k]
+  for (int e = tid; e < ma * b; e += NT) {
+    const int k = e / b, t = e % b;
+    if (posv[k] < r) Vk[(int64_t)posv[k] * b + t] = sg[k] > 0.0 ? Xr[(int64_t)k * BMr + t] / sg[k] : 0.0;
+  }
+  __syncthreads();
+  // reflectors of the kept directions (as in k_bg_eig)
+  for (int cv = 0; cv < r; ++cv) {
+    double* vr = Vk + (int64_t)cv * b;
+    if (wv == 0) {
+      double xs = 0.0;
+      for (int t = cv + lane; t < b; t += 64) xs += vr[t] * vr[t];
+      const double nrm2 = wave_sum_u(xs);
+      const double x0 = vr[cv];
+      const double nrm = sqrt(nrm2);
+      const double alpha = x0 >= 0.0 ? -nrm : nrm;
+      const double v0 = x0 - alpha;
+      const double vv = v0 * v0 + (nrm2 - x0 * x0);
+      wave_sync();
+      for (int t = lane; t < cv; t += 64) vr[t] = 0.0;
+      if (lane == 0) {
+        vr[cv] = v0;
+        tau[cv] = vv > 0.0 ? 2.0 / vv : 0.0;
+      }
+    }
+    __syncthreads();
+    const double tc = tau[cv];
+    for (int c2 = cv + 1 + wv; c2 < r; c2 += 4) {
+      double* br = Vk + (int64_t)c2 * b;
+      double dd = 0.0;
+      for (int t = cv + lane; t < b; t += 64) dd += vr[t] * br[t];
+      dd = wave_sum_u(dd);
+      for (int t = cv + lane; t < b; t += 64) br[t] -= tc * dd * vr[t];
+    }
+    __syncthreads();
+  }
+  // U_i = H_0 ... H_{r-1}: one wavefront per column
+  for (int col = wv; col < b; col += 4) {
+    double q[BG_MAXB / 64];
+#pragma unroll
+    for (int u = 0; u < BG_MAXB / 64; ++u) q[u] = (lane + 64 * u == col) ? 1.0 : 0.0;
+    for (int cv = r - 1; cv >= 0; --cv) {
+      const double* vr = Vk + (int64_t)cv * b;
+      double dd = 0.0;
+#pragma unroll
+      for (int u = 0; u < BG_MAXB / 64; ++u) {
+        const int t = lane + 64 * u;
+        if (t < b) dd += vr[t] * q[u];
+      }
+      dd = wave_sum_u(dd) * tau[cv];
+#pragma unroll
+      for (int u = 0; u < BG_MAXB / 64; ++u) {
+        const int t = lane + 64 * u;
+        if (t < b) q[u] -= dd * vr[t];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BG_MAXB / 64; ++u) {
+      const int t = lane + 64 * u;
+      if (t < b) Ug[(int64_t)t * b + col] = (T)q[u];
+    }
+  }
+  if (tid == 0) {
+    A.rank[i] = r;
+    A.edrop[i] = rd[0];
+    A.big_fail[i] = 0;
+    if (A.bg_count) atomicAdd(A.bg_count + 3, 1);
   }
 }
 
@@ -5261,6 +5438,7 @@ static void compress_pass(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
                            stream, A, w.s0);
         hipLaunchKernelGGL(k_bg_eig<T>, dim3(ns), dim3(NT), work_bg_eig<T>(), stream, A, w.s0);
         hipLaunchKernelGGL(k_bg_cert<T>, dim3(ns), dim3(NT), (size_t)2 * 64 * TLD * sizeof(double), stream, A, w.s0);
+        hipLaunchKernelGGL(k_bg_full<T>, dim3(ns), dim3(NT), 0, stream, A, w.s0);
       }
       C.big_retry = 1;
       C.need_exact = nullptr;

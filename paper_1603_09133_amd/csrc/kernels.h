@@ -52,7 +52,7 @@ struct LevelArgs {
   // bg_stride(bmax) doubles per step of the wave, or null
   double* big;
   int64_t big_stride;
-  int32_t* big_fail;        // per block: 1 = left to the generic compression, 2 = to k_bg_cert
+  int32_t* big_fail;        // per block: 1 = left to k_bg_full (then the generic kernel), 2 = to k_bg_cert
   int32_t bg_cap;           // most pivoted Cholesky rows (<= BG_MA)
   int32_t* bg_count;        // [0] untruncated, [1] Frobenius-accepted, [2] certified, [3] generic
   int32_t big_retry;        // generic compression: only the blocks flagged in big_fail
