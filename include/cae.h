@@ -117,7 +117,7 @@ typedef struct {
   int32_t big_pivot_cap;   /* blocks of 129..512 unknowns: most rows of the pivoted Cholesky
                               of the far row's Gram matrix (1..128; 0 = 128).  A step that
                               needs more is certified by a spectral bound on its dropped
-                              part, or redone by the generic kernel (counted in
+                              part, or redone with an uncapped pivoted Cholesky (counted in
                               cae_stats_t.big_*); a smaller cap sends more steps there */
 } cae_options_t;
 
@@ -334,11 +334,12 @@ typedef struct {
      the pivoted Cholesky ran to the rounding level; it was truncated and the
      energy left out (Frobenius norm) cannot change the rank; the spectral norm
      of the dropped part was bounded by repeated squaring of its Gram matrix;
-     the generic kernel redid the step */
+     the bound failed and the step was redone with an uncapped pivoted
+     Cholesky and a Jacobi on its rows */
   int32_t big_untruncated;
   int32_t big_frobenius;
   int32_t big_certified;
-  int32_t big_generic;
+  int32_t big_uncapped;
 } cae_stats_t;
 
 int cae_get_stats(cae_handle_t h, cae_stats_t* s);

@@ -1617,7 +1617,7 @@ static int cae_get_stats_impl(cae_handle_t h, cae_stats_t* st) {
   st->big_untruncated = h->big_count[0];
   st->big_frobenius = h->big_count[1];
   st->big_certified = h->big_count[2];
-  st->big_generic = h->big_count[3];
+  st->big_uncapped = h->big_count[3];
   return CAE_OK;
 }
 

@@ -263,16 +263,16 @@ def test_factor_with_blocks_above_128(prec, cap):
     unknowns, which take the big-block kernels (Gram tiles on the FP64 matrix
     cores, pivoted Cholesky, Jacobi on X X^T, reflectors).
 
-    Default cap, and cap 1 (which sends every big step of rank above 1 to
-    the generic kernel): probe error against the FP64 oracle within the FP32
-    bound, every level's ranks equal to the oracle's wherever the oracle's
-    singular values are not within the FP32 rounding level of the threshold,
-    and every step's dropped energy equal to the oracle's.
+    Default cap, and cap 1 (which sends every big step of rank above 1 to an
+    uncapped pivoted Cholesky): probe error against the FP64 oracle within
+    the FP32 bound, every level's ranks equal to the oracle's wherever the
+    oracle's singular values are not within the FP32 rounding level of the
+    threshold, and every step's dropped energy equal to the oracle's.
 
     A pivot cap below the default truncates the pivoted Cholesky, so that the
     other ways of settling a rank run too: the Frobenius bound, the spectral
-    certificate by repeated squaring, and the generic kernel (each asserted to
-    occur for some cap).  A truncated step keeps the Ritz basis of its pivoted
+    certificate by repeated squaring, and the uncapped pivoted Cholesky (each
+    asserted to occur for some cap).  A truncated step keeps the Ritz basis of its pivoted
     rows instead of the exact singular vectors -- another valid CE(eps) basis
     with the same rank -- so the later far rows, and near-threshold ranks
     after it, differ from the oracle's.  Such a factor is checked by what
@@ -309,7 +309,7 @@ def test_factor_with_blocks_above_128(prec, cap):
     for l in range(K):
         sz = f.sizes(l)
         nbig += int(np.count_nonzero(sz > 128))
-    cls = [st[k] for k in ("big_untruncated", "big_frobenius", "big_certified", "big_generic")]
+    cls = [st[k] for k in ("big_untruncated", "big_frobenius", "big_certified", "big_uncapped")]
     X = _probes(A.shape[0])
     Mo = ce_multiply(fo, X)
     Mg = _from_gpu_cols(f.multiply(_to_gpu_cols(X)))
@@ -327,7 +327,7 @@ def test_factor_with_blocks_above_128(prec, cap):
         k = int(np.argmax(np.abs(dg - do)))
         worst.append((l, k, int(f.sizes(l)[k]), float(dg[k] / th2), float(do[k] / th2)))
     print(f"{prec} cap {cap}: levels with the oracle's blocks {same}, first big {first_big}, blocks above 128 "
-          f"{nbig}, untruncated/Frobenius/certified/generic {cls}, probe error vs oracle {err:.3e}, dropped "
+          f"{nbig}, untruncated/Frobenius/certified/uncapped {cls}, probe error vs oracle {err:.3e}, dropped "
           f"energy {st['dropped_sq']:.6e} vs oracle {ed_o:.6e}, rank differences (level, block, gpu, oracle, "
           f"sigma/theta) {rank_diff[:8]}, worst step drop (level, block, b, gpu/theta^2, oracle/theta^2) {worst}")
     assert big, "no level with blocks above 128 unknowns"
@@ -630,7 +630,7 @@ def test_bf16_schur_factor_with_blocks_above_128():
     b = problems.rhs_uniform(A.shape[0], seed=0)
     _, it, relr = f.pcg(torch.from_numpy(b).cuda(), rtol=1e-8)
     _, ito, _ = oracle.pcg(A, b, lambda r: ce_solve(fo, r), tol=1e-8)
-    nbig = sum(st[k] for k in ("big_untruncated", "big_frobenius", "big_certified", "big_generic"))
+    nbig = sum(st[k] for k in ("big_untruncated", "big_frobenius", "big_certified", "big_uncapped"))
     print(f"bf16 (b > 128): probe error vs oracle {rel:.3e}, big compressions {nbig}, PCG {int(it[0])} vs {ito}")
     assert nbig > 0
     assert rel <= 2e-3, rel
