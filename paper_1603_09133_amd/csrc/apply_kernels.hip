@@ -143,16 +143,26 @@ __global__ __launch_bounds__(NT) void k_ap_bwd_generic(ApplyArgs<T> A, int32_t s
 // 16-wide vector tiles live in LDS, so a step needs 16 KB of LDS at b = 64
 // and many steps run on one compute unit at once.
 // ---------------------------------------------------------------------------
-__device__ inline void axpy16(double s[RC], double p, const double* v) {
+// Right-hand sides per pass R of the lean kernels: 16 (accumulators per
+// thread), or 1 for a single right-hand side (no idle accumulators, the LDS
+// vector tiles contiguous); RhsPass<R>::P is the row stride of those tiles.
+template <int R>
+struct RhsPass {
+  static constexpr int P = R == 1 ? 1 : R + 2;
+  static constexpr int NO = R == 1 ? 1 : 4;   // totals per lane after the reduce-scatter
+};
+
+template <int R>
+__device__ inline void axpyR(double (&s)[R], double p, const double* v) {
 #pragma unroll
-  for (int k = 0; k < RC; ++k) s[k] += p * v[k];
+  for (int k = 0; k < R; ++k) s[k] += p * v[k];
 }
 
-// s += sum over t = t0, t0 + 4, ... < tend of P[t * stride] V[t * RCP]: the
+// s += sum over t = t0, t0 + 4, ... < tend of P[t * stride] V[t * P]: the
 // panel entries loaded eight at a time (all in flight before the first is
 // used), the LDS rows of V read only for t < tend.
-template <typename T>
-__device__ inline void axpy_run(double s[RC], const T* P, int64_t stride, int t0, int tend, const double* V) {
+template <int R, typename T>
+__device__ inline void axpy_run(double (&s)[R], const T* P, int64_t stride, int t0, int tend, const double* V) {
   for (int t = t0; t < tend; t += 32) {
     T pv[8];
 #pragma unroll
@@ -163,73 +173,121 @@ __device__ inline void axpy_run(double s[RC], const T* P, int64_t stride, int t0
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int tu = t + 4 * u;
-      if (tu < tend) axpy16(s, (double)pv[u], V + tu * RCP);
+      if (tu < tend) axpyR<R>(s, (double)pv[u], V + tu * RhsPass<R>::P);
     }
   }
 }
 
-// Sum of the RC partial sums over the four lanes of a row (lanes 4 rl + q),
-// reduce-scattered: lane q returns in o[0..3] the totals of columns
-// 4 q .. 4 q + 3 (12 exchanges instead of a 32-exchange butterfly).
-__device__ inline void quad_rs16(const double s[RC], int q, double o[4]) {
-  const bool hi2 = (q & 2) != 0, hi1 = (q & 1) != 0;
-  double h[8];
+// Sum of the R partial sums over the four lanes of a row (lanes 4 rl + q).
+// R = 16: reduce-scattered, lane q returns in o[0..3] the totals of columns
+// 4 q .. 4 q + 3 (12 exchanges instead of a 32-exchange butterfly); R = 1:
+// every lane returns the total in o[0].
+template <int R>
+__device__ inline void quad_rs(const double (&s)[R], int q, double (&o)[RhsPass<R>::NO]) {
+  if constexpr (R == 1) {
+    double v = s[0];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    o[0] = v;
+  } else {
+    const bool hi2 = (q & 2) != 0, hi1 = (q & 1) != 0;
+    double h[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const double send = hi2 ? s[j] : s[8 + j];
-    h[j] = (hi2 ? s[8 + j] : s[j]) + __shfl_xor(send, 2, 64);
-  }
+    for (int j = 0; j < 8; ++j) {
+      const double send = hi2 ? s[j] : s[8 + j];
+      h[j] = (hi2 ? s[8 + j] : s[j]) + __shfl_xor(send, 2, 64);
+    }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const double send = hi1 ? h[j] : h[4 + j];
-    o[j] = (hi1 ? h[4 + j] : h[j]) + __shfl_xor(send, 1, 64);
+    for (int j = 0; j < 4; ++j) {
+      const double send = hi1 ? h[j] : h[4 + j];
+      o[j] = (hi1 ? h[4 + j] : h[j]) + __shfl_xor(send, 1, 64);
+    }
   }
 }
 
 // y[4 q + j] (op)= o[j] for the columns 4 q + j < kc of one RHS row (y at
-// column k0 of that row): two 16-byte accesses when the row chunk is whole.
-__device__ inline void store_row4(double* y, int q, int kc, const double o[4]) {
-  double* p = y + 4 * q;
-  if (4 * q + 4 <= kc) {
-    reinterpret_cast<double2*>(p)[0] = make_double2(o[0], o[1]);
-    reinterpret_cast<double2*>(p)[1] = make_double2(o[2], o[3]);
+// column k0 of that row): two 16-byte accesses when the row chunk is whole;
+// R = 1: lane q = 0 alone.
+template <int R>
+__device__ inline void store_out(double* y, int q, int kc, const double (&o)[RhsPass<R>::NO]) {
+  if constexpr (R == 1) {
+    if (q == 0) y[0] = o[0];
   } else {
+    double* p = y + 4 * q;
+    if (4 * q + 4 <= kc) {
+      reinterpret_cast<double2*>(p)[0] = make_double2(o[0], o[1]);
+      reinterpret_cast<double2*>(p)[1] = make_double2(o[2], o[3]);
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (4 * q + j < kc) p[j] = o[j];
+      for (int j = 0; j < 4; ++j)
+        if (4 * q + j < kc) p[j] = o[j];
+    }
   }
 }
-__device__ inline void sub_row4(double* y, int q, int kc, const double o[4]) {
-  double* p = y + 4 * q;
-  if (4 * q + 4 <= kc) {
-    double2 a = reinterpret_cast<double2*>(p)[0], c = reinterpret_cast<double2*>(p)[1];
-    a.x -= o[0];
-    a.y -= o[1];
-    c.x -= o[2];
-    c.y -= o[3];
-    reinterpret_cast<double2*>(p)[0] = a;
-    reinterpret_cast<double2*>(p)[1] = c;
+template <int R>
+__device__ inline void sub_out(double* y, int q, int kc, const double (&o)[RhsPass<R>::NO]) {
+  if constexpr (R == 1) {
+    if (q == 0) y[0] -= o[0];
   } else {
+    double* p = y + 4 * q;
+    if (4 * q + 4 <= kc) {
+      double2 a = reinterpret_cast<double2*>(p)[0], c = reinterpret_cast<double2*>(p)[1];
+      a.x -= o[0];
+      a.y -= o[1];
+      c.x -= o[2];
+      c.y -= o[3];
+      reinterpret_cast<double2*>(p)[0] = a;
+      reinterpret_cast<double2*>(p)[1] = c;
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (4 * q + j < kc) p[j] -= o[j];
+      for (int j = 0; j < 4; ++j)
+        if (4 * q + j < kc) p[j] -= o[j];
+    }
+  }
+}
+// The same for one row of an LDS vector tile (all R columns): set, or add
+// sign * o.
+template <int R>
+__device__ inline void lds_set(double* row, int q, const double (&o)[RhsPass<R>::NO]) {
+  if constexpr (R == 1) {
+    if (q == 0) row[0] = o[0];
+  } else {
+    *reinterpret_cast<double2*>(row + 4 * q) = make_double2(o[0], o[1]);
+    *reinterpret_cast<double2*>(row + 4 * q + 2) = make_double2(o[2], o[3]);
+  }
+}
+template <int R>
+__device__ inline void lds_add(double* row, int q, const double (&o)[RhsPass<R>::NO], double sign) {
+  if constexpr (R == 1) {
+    if (q == 0) row[0] += sign * o[0];
+  } else {
+    double2* tp = reinterpret_cast<double2*>(row + 4 * q);
+    double2 a0 = tp[0], a1 = tp[1];
+    a0.x += sign * o[0];
+    a0.y += sign * o[1];
+    a1.x += sign * o[2];
+    a1.y += sign * o[3];
+    tp[0] = a0;
+    tp[1] = a1;
   }
 }
 
-// Y[t][0..RC) = y[(row0 + t) * nrhs + k0 + k] (0 beyond kc), t < m, row
-// stride RCP; eight loads in flight per thread.
+// Y[t][0..R) = y[(row0 + t) * nrhs + k0 + k] (0 beyond kc), t < m, row
+// stride RhsPass<R>::P; eight loads in flight per thread.
+template <int R>
 __device__ inline void load_vec_tile(double* Y, const double* y, int row0, int m, int nrhs, int k0, int kc) {
-  for (int e0 = 0; e0 < m * RC; e0 += 8 * NT) {
+  constexpr int RP = RhsPass<R>::P;
+  for (int e0 = 0; e0 < m * R; e0 += 8 * NT) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = e0 + threadIdx.x + NT * u, t = e / RC, k = e % RC;
-      v[u] = (e < m * RC && k < kc) ? y[(int64_t)(row0 + t) * nrhs + k0 + k] : 0.0;
+      const int e = e0 + threadIdx.x + NT * u, t = e / R, k = e % R;
+      v[u] = (e < m * R && k < kc) ? y[(int64_t)(row0 + t) * nrhs + k0 + k] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + threadIdx.x + NT * u;
-      if (e < m * RC) Y[(e / RC) * RCP + e % RC] = v[u];
+      if (e < m * R) Y[(e / R) * RP + e % R] = v[u];
     }
   }
 }
@@ -277,8 +335,9 @@ __device__ inline void view_desc(const ApplyArgs<T>& A, const Step& st, const Vi
   }
 }
 
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(NT) void k_ap_rot2(ApplyArgs<T> A, double* y, int dir) {
+  constexpr int RP = RhsPass<R>::P;
   const Step st = A.steps[blockIdx.x];
   if (st.nfar == 0) return;
   const int i = st.blk;
@@ -288,27 +347,27 @@ __global__ __launch_bounds__(NT) void k_ap_rot2(ApplyArgs<T> A, double* y, int d
   const T* U = A.U + A.u_off[i];
   double* yi = y + A.dof_off[i] * nrhs;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Ys = reinterpret_cast<double*>(smem_raw);   // b x RC
+  double* Ys = reinterpret_cast<double*>(smem_raw);   // b x R
   const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int kc = min(RC, nrhs - k0);
+  for (int k0 = 0; k0 < nrhs; k0 += R) {
+    const int kc = min(R, nrhs - k0);
     __syncthreads();
-    load_vec_tile(Ys, yi, 0, b, nrhs, k0, kc);
+    load_vec_tile<R>(Ys, yi, 0, b, nrhs, k0, kc);
     __syncthreads();
     for (int a0 = 0; a0 < b; a0 += 64) {
       const int a = a0 + rl;
-      double s[RC];
+      double s[R];
 #pragma unroll
-      for (int k = 0; k < RC; ++k) s[k] = 0.0;
+      for (int k = 0; k < R; ++k) s[k] = 0.0;
       if (a < b) {
         if (dir == 0)
-          axpy_run(s, U + a, b, q, b, Ys);
+          axpy_run<R>(s, U + a, b, q, b, Ys);
         else
-          axpy_run(s, U + (int64_t)a * b, 1, q, b, Ys);
+          axpy_run<R>(s, U + (int64_t)a * b, 1, q, b, Ys);
       }
-      double o[4];
-      quad_rs16(s, q, o);
-      if (a < b) store_row4(yi + (int64_t)a * nrhs + k0, q, kc, o);
+      double o[RhsPass<R>::NO];
+      quad_rs<R>(s, q, o);
+      if (a < b) store_out<R>(yi + (int64_t)a * nrhs + k0, q, kc, o);
     }
   }
 }
@@ -316,8 +375,9 @@ __global__ __launch_bounds__(NT) void k_ap_rot2(ApplyArgs<T> A, double* y, int d
 // Forward block solve of one step: t = L_nn^{-1} y_i[n], y_i[n] = t, and
 // y_c -= L(c, n) t for the basis of i and (views != 0) every close block c;
 // with views = 0 the close blocks are left to k_ap_fview.
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax, int views) {
+  constexpr int RP = RhsPass<R>::P;
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -326,31 +386,30 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
   if (n <= 0) return;
   const int nrhs = A.nrhs;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* yn = reinterpret_cast<double*>(smem_raw);   // n x RC
-  double* tn = yn + (size_t)nmax * RCP;                // n x RC, row stride RCP
-  ViewDesc* vd = reinterpret_cast<ViewDesc*>(tn + (size_t)nmax * RCP);
+  double* yn = reinterpret_cast<double*>(smem_raw);   // n x R
+  double* tn = yn + (size_t)nmax * RP;                // n x R, row stride RP
+  ViewDesc* vd = reinterpret_cast<ViewDesc*>(tn + (size_t)nmax * RP);
   const T* Li = A.Li + A.u_off[i];
   const T* D = A.arena + A.slot_off[i];
   double* yi = y + A.dof_off[i] * nrhs;
   const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
   stage_views(A, st, vd);
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int kc = min(RC, nrhs - k0);
+  for (int k0 = 0; k0 < nrhs; k0 += R) {
+    const int kc = min(R, nrhs - k0);
     __syncthreads();
-    load_vec_tile(yn, yi, r, n, nrhs, k0, kc);
+    load_vec_tile<R>(yn, yi, r, n, nrhs, k0, kc);
     __syncthreads();
     for (int row0 = 0; row0 < n; row0 += 64) {
       const int row = row0 + rl;
-      double s[RC];
+      double s[R];
 #pragma unroll
-      for (int k = 0; k < RC; ++k) s[k] = 0.0;
-      if (row < n) axpy_run(s, Li + (int64_t)row * n, 1, q, row + 1, yn);
-      double o[4];
-      quad_rs16(s, q, o);
+      for (int k = 0; k < R; ++k) s[k] = 0.0;
+      if (row < n) axpy_run<R>(s, Li + (int64_t)row * n, 1, q, row + 1, yn);
+      double o[RhsPass<R>::NO];
+      quad_rs<R>(s, q, o);
       if (row < n) {
-        *reinterpret_cast<double2*>(tn + row * RCP + 4 * q) = make_double2(o[0], o[1]);
-        *reinterpret_cast<double2*>(tn + row * RCP + 4 * q + 2) = make_double2(o[2], o[3]);
-        store_row4(yi + (int64_t)(r + row) * nrhs + k0, q, kc, o);
+        lds_set<R>(tn + row * RP, q, o);
+        store_out<R>(yi + (int64_t)(r + row) * nrhs + k0, q, kc, o);
       }
     }
     __syncthreads();
@@ -373,18 +432,18 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
       }
       for (int g0 = 0; g0 < lc; g0 += 64) {
         const int g = g0 + rl;
-        double s[RC];
+        double s[R];
 #pragma unroll
-        for (int k = 0; k < RC; ++k) s[k] = 0.0;
+        for (int k = 0; k < R; ++k) s[k] = 0.0;
         if (g < lc) {
           if (trans)
-            axpy_run(s, P + (int64_t)g * b + r, 1, q, n, tn);
+            axpy_run<R>(s, P + (int64_t)g * b + r, 1, q, n, tn);
           else
-            axpy_run(s, P + (int64_t)r * bx + g, bx, q, n, tn);
+            axpy_run<R>(s, P + (int64_t)r * bx + g, bx, q, n, tn);
         }
-        double o[4];
-        quad_rs16(s, q, o);
-        if (g < lc) sub_row4(yx + (int64_t)g * nrhs + k0, q, kc, o);
+        double o[RhsPass<R>::NO];
+        quad_rs<R>(s, q, o);
+        if (g < lc) sub_out<R>(yx + (int64_t)g * nrhs + k0, q, kc, o);
       }
     }
   }
@@ -394,9 +453,10 @@ __global__ __launch_bounds__(NT) void k_ap_fwd2(ApplyArgs<T> A, int32_t s0, doub
 // basis of i and the close blocks, then y_i[n] = L_nn^{-T} t.  With part the
 // close blocks' products come precomputed (k_ap_bpart, maxclose slots of
 // nmax x nrhs per step).
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, double* y, int nmax, const double* part,
                                                 int maxclose) {
+  constexpr int RP = RhsPass<R>::P;
   const Step st = A.steps[s0 + blockIdx.x];
   const int i = st.blk;
   const int b = A.bsz[i];
@@ -405,18 +465,18 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
   if (n <= 0) return;
   const int nrhs = A.nrhs;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* tn = reinterpret_cast<double*>(smem_raw);   // n x RC
-  double* zt = tn + (size_t)nmax * RCP;                // 64 x RC, row stride RCP
-  ViewDesc* vd = reinterpret_cast<ViewDesc*>(zt + (size_t)64 * RCP);
+  double* tn = reinterpret_cast<double*>(smem_raw);   // n x R
+  double* zt = tn + (size_t)nmax * RP;                // 64 x R, row stride RP
+  ViewDesc* vd = reinterpret_cast<ViewDesc*>(zt + (size_t)64 * RP);
   const T* Li = A.Li + A.u_off[i];
   const T* D = A.arena + A.slot_off[i];
   double* yi = y + A.dof_off[i] * nrhs;
   const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
   stage_views(A, st, vd);
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int kc = min(RC, nrhs - k0);
+  for (int k0 = 0; k0 < nrhs; k0 += R) {
+    const int kc = min(R, nrhs - k0);
     __syncthreads();
-    load_vec_tile(tn, yi, r, n, nrhs, k0, kc);
+    load_vec_tile<R>(tn, yi, r, n, nrhs, k0, kc);
     const int nv = part ? 0 : st.nclose;
     for (int v = -1; v < nv; ++v) {
       const T* P;
@@ -437,31 +497,22 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
       for (int g0 = 0; g0 < lc; g0 += 64) {
         const int gc = min(64, lc - g0);
         __syncthreads();
-        load_vec_tile(zt, zx, g0, gc, nrhs, k0, kc);
+        load_vec_tile<R>(zt, zx, g0, gc, nrhs, k0, kc);
         __syncthreads();
         for (int t0 = 0; t0 < n; t0 += 64) {
           const int t = t0 + rl;
-          double s[RC];
+          double s[R];
 #pragma unroll
-          for (int k = 0; k < RC; ++k) s[k] = 0.0;
+          for (int k = 0; k < R; ++k) s[k] = 0.0;
           if (t < n) {
             if (trans)
-              axpy_run(s, P + (int64_t)g0 * b + r + t, b, q, gc, zt);
+              axpy_run<R>(s, P + (int64_t)g0 * b + r + t, b, q, gc, zt);
             else
-              axpy_run(s, P + (int64_t)(r + t) * bx + g0, 1, q, gc, zt);
+              axpy_run<R>(s, P + (int64_t)(r + t) * bx + g0, 1, q, gc, zt);
           }
-          double o[4];
-          quad_rs16(s, q, o);
-          if (t < n) {
-            double2* tp = reinterpret_cast<double2*>(tn + t * RCP + 4 * q);
-            double2 a0 = tp[0], a1 = tp[1];
-            a0.x -= o[0];
-            a0.y -= o[1];
-            a1.x -= o[2];
-            a1.y -= o[3];
-            tp[0] = a0;
-            tp[1] = a1;
-          }
+          double o[RhsPass<R>::NO];
+          quad_rs<R>(s, q, o);
+          if (t < n) lds_add<R>(tn + t * RP, q, o, -1.0);
         }
       }
     }
@@ -471,10 +522,10 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
       // in view order (eight loads in flight per element)
       const double* pp = part + (int64_t)blockIdx.x * maxclose * nmax * nrhs;
       const int64_t pstride = (int64_t)nmax * nrhs;
-      for (int e = threadIdx.x; e < n * RC; e += NT) {
-        const int t = e / RC, k = e % RC;
+      for (int e = threadIdx.x; e < n * R; e += NT) {
+        const int t = e / R, k = e % R;
         if (k >= kc) continue;
-        double acc = tn[t * RCP + k];
+        double acc = tn[t * RP + k];
         for (int v0 = 0; v0 < st.nclose; v0 += 8) {
           double pv[8];
 #pragma unroll
@@ -483,19 +534,19 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
           for (int u = 0; u < 8; ++u)
             if (v0 + u < st.nclose) acc -= pv[u];
         }
-        tn[t * RCP + k] = acc;
+        tn[t * RP + k] = acc;
       }
       __syncthreads();
     }
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int c = c0 + rl;
-      double s[RC];
+      double s[R];
 #pragma unroll
-      for (int k = 0; k < RC; ++k) s[k] = 0.0;
-      if (c < n) axpy_run(s, Li + c, n, c + q, n, tn);
-      double o[4];
-      quad_rs16(s, q, o);
-      if (c < n) store_row4(yi + (int64_t)(r + c) * nrhs + k0, q, kc, o);
+      for (int k = 0; k < R; ++k) s[k] = 0.0;
+      if (c < n) axpy_run<R>(s, Li + c, n, c + q, n, tn);
+      double o[RhsPass<R>::NO];
+      quad_rs<R>(s, q, o);
+      if (c < n) store_out<R>(yi + (int64_t)(r + c) * nrhs + k0, q, kc, o);
     }
   }
 }
@@ -506,8 +557,9 @@ __global__ __launch_bounds__(NT) void k_ap_bwd2(ApplyArgs<T> A, int32_t s0, doub
 // workgroups of a launch write disjoint rows; a step's views run in parallel
 // instead of one after another (the waves of the upper levels hold too few
 // steps to hide that chain of memory round trips).
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(NT) void k_ap_fview(ApplyArgs<T> A, int32_t s0, double* y, int nmax) {
+  constexpr int RP = RhsPass<R>::P;
   const Step st = A.steps[s0 + blockIdx.x];
   const int v = blockIdx.y;
   if (v >= st.nclose) return;
@@ -525,27 +577,27 @@ __global__ __launch_bounds__(NT) void k_ap_fview(ApplyArgs<T> A, int32_t s0, dou
   const double* yi = y + A.dof_off[i] * nrhs;
   double* yx = y + A.dof_off[vw.x] * nrhs;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* tn = reinterpret_cast<double*>(smem_raw);   // n x RC, row stride RCP
+  double* tn = reinterpret_cast<double*>(smem_raw);   // n x R, row stride RP
   const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int kc = min(RC, nrhs - k0);
+  for (int k0 = 0; k0 < nrhs; k0 += R) {
+    const int kc = min(R, nrhs - k0);
     __syncthreads();
-    load_vec_tile(tn, yi, r, n, nrhs, k0, kc);
+    load_vec_tile<R>(tn, yi, r, n, nrhs, k0, kc);
     __syncthreads();
     for (int g0 = 0; g0 < lc; g0 += 64) {
       const int g = g0 + rl;
-      double s[RC];
+      double s[R];
 #pragma unroll
-      for (int k = 0; k < RC; ++k) s[k] = 0.0;
+      for (int k = 0; k < R; ++k) s[k] = 0.0;
       if (g < lc) {
         if (vw.trans)
-          axpy_run(s, P + (int64_t)g * b + r, 1, q, n, tn);
+          axpy_run<R>(s, P + (int64_t)g * b + r, 1, q, n, tn);
         else
-          axpy_run(s, P + (int64_t)r * bx + g, bx, q, n, tn);
+          axpy_run<R>(s, P + (int64_t)r * bx + g, bx, q, n, tn);
       }
-      double o[4];
-      quad_rs16(s, q, o);
-      if (g < lc) sub_row4(yx + (int64_t)g * nrhs + k0, q, kc, o);
+      double o[RhsPass<R>::NO];
+      quad_rs<R>(s, q, o);
+      if (g < lc) sub_out<R>(yx + (int64_t)g * nrhs + k0, q, kc, o);
     }
   }
 }
@@ -554,9 +606,10 @@ __global__ __launch_bounds__(NT) void k_ap_fview(ApplyArgs<T> A, int32_t s0, dou
 // views): part = L(c, n)^T z_c (n x nrhs, zero when c has no live rows), in
 // slot (step, view) of maxclose per step; k_ap_bwd2 subtracts them in view
 // order.
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(NT) void k_ap_bpart(ApplyArgs<T> A, int32_t s0, const double* y, double* part, int nmax,
                                                  int maxclose) {
+  constexpr int RP = RhsPass<R>::P;
   const Step st = A.steps[s0 + blockIdx.x];
   const int v = blockIdx.y;
   if (v >= st.nclose) return;
@@ -573,47 +626,38 @@ __global__ __launch_bounds__(NT) void k_ap_bpart(ApplyArgs<T> A, int32_t s0, con
   const double* zx = y + A.dof_off[vw.x] * nrhs;
   double* pp = part + ((int64_t)blockIdx.x * maxclose + v) * nmax * nrhs;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* pt = reinterpret_cast<double*>(smem_raw);   // n x RC, row stride RCP
-  double* zt = pt + (size_t)nmax * RCP;                // 64 x RC, row stride RCP
+  double* pt = reinterpret_cast<double*>(smem_raw);   // n x R, row stride RP
+  double* zt = pt + (size_t)nmax * RP;                // 64 x R, row stride RP
   const int rl = threadIdx.x >> 2, q = threadIdx.x & 3;
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int kc = min(RC, nrhs - k0);
+  for (int k0 = 0; k0 < nrhs; k0 += R) {
+    const int kc = min(R, nrhs - k0);
     __syncthreads();
-    for (int e = threadIdx.x; e < n * RCP; e += NT) pt[e] = 0.0;
+    for (int e = threadIdx.x; e < n * RP; e += NT) pt[e] = 0.0;
     for (int g0 = 0; g0 < lc; g0 += 64) {
       const int gc = min(64, lc - g0);
       __syncthreads();
-      load_vec_tile(zt, zx, g0, gc, nrhs, k0, kc);
+      load_vec_tile<R>(zt, zx, g0, gc, nrhs, k0, kc);
       __syncthreads();
       for (int t0 = 0; t0 < n; t0 += 64) {
         const int t = t0 + rl;
-        double s[RC];
+        double s[R];
 #pragma unroll
-        for (int k = 0; k < RC; ++k) s[k] = 0.0;
+        for (int k = 0; k < R; ++k) s[k] = 0.0;
         if (t < n) {
           if (vw.trans)
-            axpy_run(s, P + (int64_t)g0 * b + r + t, b, q, gc, zt);
+            axpy_run<R>(s, P + (int64_t)g0 * b + r + t, b, q, gc, zt);
           else
-            axpy_run(s, P + (int64_t)(r + t) * bx + g0, 1, q, gc, zt);
+            axpy_run<R>(s, P + (int64_t)(r + t) * bx + g0, 1, q, gc, zt);
         }
-        double o[4];
-        quad_rs16(s, q, o);
-        if (t < n) {
-          double2* tp = reinterpret_cast<double2*>(pt + t * RCP + 4 * q);
-          double2 a0 = tp[0], a1 = tp[1];
-          a0.x += o[0];
-          a0.y += o[1];
-          a1.x += o[2];
-          a1.y += o[3];
-          tp[0] = a0;
-          tp[1] = a1;
-        }
+        double o[RhsPass<R>::NO];
+        quad_rs<R>(s, q, o);
+        if (t < n) lds_add<R>(pt + t * RP, q, o, 1.0);
       }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n * RC; e += NT) {
-      const int t = e / RC, k = e % RC;
-      if (k < kc) pp[t * nrhs + k0 + k] = pt[t * RCP + k];
+    for (int e = threadIdx.x; e < n * R; e += NT) {
+      const int t = e / R, k = e % R;
+      if (k < kc) pp[t * nrhs + k0 + k] = pt[t * RP + k];
     }
   }
 }
@@ -925,10 +969,17 @@ static unsigned grid1(int64_t work) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// The lean kernels run with R = 1 right-hand side per pass for a single
+// right-hand side, else with R = 16.
 template <typename T>
 void launch_ap_rotate(const ApplyArgs<T>& A, int32_t nsteps, double* y, int dir, int bmax, hipStream_t stream) {
   if (nsteps <= 0) return;
-  hipLaunchKernelGGL(k_ap_rot2<T>, dim3(nsteps), dim3(NT), (size_t)bmax * RCP * sizeof(double), stream, A, y, dir);
+  if (A.nrhs == 1)
+    hipLaunchKernelGGL((k_ap_rot2<T, 1>), dim3(nsteps), dim3(NT), (size_t)bmax * RhsPass<1>::P * sizeof(double), stream,
+                       A, y, dir);
+  else
+    hipLaunchKernelGGL((k_ap_rot2<T, RC>), dim3(nsteps), dim3(NT), (size_t)bmax * RCP * sizeof(double), stream, A, y,
+                       dir);
 }
 // Waves with fewer steps than split_steps run their close-block updates as
 // one workgroup per (step, view) (k_ap_fview / k_ap_bpart).
@@ -950,10 +1001,18 @@ void launch_ap_fwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bma
   const size_t lds = (size_t)2 * bmax * RCP * sizeof(double) + sizeof(ViewDesc);
   if (lds <= max_lds_bytes()) {
     const bool split = ap_split<T>(w, bmax, split_steps);
-    hipLaunchKernelGGL(k_ap_fwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax, split ? 0 : 1);
-    if (split)
-      hipLaunchKernelGGL(k_ap_fview<T>, dim3(s1 - s0, w.maxclose), dim3(NT), (size_t)bmax * RCP * sizeof(double),
-                         stream, A, s0, y, bmax);
+    if (A.nrhs == 1) {
+      const size_t l1 = (size_t)2 * bmax * RhsPass<1>::P * sizeof(double) + sizeof(ViewDesc);
+      hipLaunchKernelGGL((k_ap_fwd2<T, 1>), dim3(s1 - s0), dim3(NT), l1, stream, A, s0, y, bmax, split ? 0 : 1);
+      if (split)
+        hipLaunchKernelGGL((k_ap_fview<T, 1>), dim3(s1 - s0, w.maxclose), dim3(NT),
+                           (size_t)bmax * RhsPass<1>::P * sizeof(double), stream, A, s0, y, bmax);
+    } else {
+      hipLaunchKernelGGL((k_ap_fwd2<T, RC>), dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax, split ? 0 : 1);
+      if (split)
+        hipLaunchKernelGGL((k_ap_fview<T, RC>), dim3(s1 - s0, w.maxclose), dim3(NT), (size_t)bmax * RCP * sizeof(double),
+                           stream, A, s0, y, bmax);
+    }
   } else {
     hipLaunchKernelGGL(k_ap_fwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
                        s0, y);
@@ -967,11 +1026,21 @@ void launch_ap_bwd(const ApplyArgs<T>& A, const WaveRange& w, double* y, int bma
   const size_t lds = (size_t)(bmax + 64) * RCP * sizeof(double) + sizeof(ViewDesc);
   if (lds <= max_lds_bytes()) {
     const bool split = part != nullptr && ap_split<T>(w, bmax, split_steps);
-    if (split)
-      hipLaunchKernelGGL(k_ap_bpart<T>, dim3(s1 - s0, w.maxclose), dim3(NT), (size_t)(bmax + 64) * RCP * sizeof(double),
-                         stream, A, s0, (const double*)y, part, bmax, (int)w.maxclose);
-    hipLaunchKernelGGL(k_ap_bwd2<T>, dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax,
-                       split ? (const double*)part : (const double*)nullptr, (int)w.maxclose);
+    if (A.nrhs == 1) {
+      const size_t l1 = (size_t)(bmax + 64) * RhsPass<1>::P * sizeof(double);
+      if (split)
+        hipLaunchKernelGGL((k_ap_bpart<T, 1>), dim3(s1 - s0, w.maxclose), dim3(NT), l1, stream, A, s0,
+                           (const double*)y, part, bmax, (int)w.maxclose);
+      hipLaunchKernelGGL((k_ap_bwd2<T, 1>), dim3(s1 - s0), dim3(NT), l1 + sizeof(ViewDesc), stream, A, s0, y, bmax,
+                         split ? (const double*)part : (const double*)nullptr, (int)w.maxclose);
+    } else {
+      if (split)
+        hipLaunchKernelGGL((k_ap_bpart<T, RC>), dim3(s1 - s0, w.maxclose), dim3(NT),
+                           (size_t)(bmax + 64) * RCP * sizeof(double), stream, A, s0, (const double*)y, part, bmax,
+                           (int)w.maxclose);
+      hipLaunchKernelGGL((k_ap_bwd2<T, RC>), dim3(s1 - s0), dim3(NT), lds, stream, A, s0, y, bmax,
+                         split ? (const double*)part : (const double*)nullptr, (int)w.maxclose);
+    }
   } else {
     hipLaunchKernelGGL(k_ap_bwd_generic<T>, dim3(s1 - s0), dim3(NT), (size_t)bmax * RC * sizeof(double), stream, A,
                        s0, y);
