@@ -4849,52 +4849,62 @@ __global__ __launch_bounds__(NT) void k_schur_big_bf16w(LevelArgs<T> A, int32_t 
 // wavefront w owns the output row blocks 16 w, 16 (w + 4), ..., each as SW / 16
 // tiles of 16 x 16 on the FP64 matrix cores (lanes as in k_schur_t).  Rows m ..
 // m4 - 1 of the strip stay zero so the k loop runs in steps of four.
-template <typename T>
+template <typename T, int W = (sizeof(T) == sizeof(float) ? 64 : 32)>
 struct Strip {
-  static constexpr int SW = sizeof(T) == sizeof(float) ? 64 : 32;   // columns
-  static constexpr int LD = SW + 4;                                  // LDS row stride
-  static constexpr int NTJ = SW / 16;                                // 16-column tiles
+  static constexpr int SW = W;         // columns
+  static constexpr int LD = SW + 4;    // LDS row stride
+  static constexpr int NTJ = SW / 16;  // 16-column tiles
 };
 //   op = 0: out = M^T X with M row-major m x m (the rotation by U_i^T);
 //   op = 1: out = M X (the triangular solve by the stored L_nn^{-1}).
 // Output rows >= mout are not computed (far views keep their rows < r_i).
-template <typename T, int OP>
+// NS strips side by side (the second at X + m4 LD, columns c0 + SW ..): each
+// entry of M loaded from L2 feeds NS times as many products.
+template <typename T, int OP, int NS = 1, int W = Strip<T>::SW>
 __device__ void strip_product(const T* M, int m, const T* X, int mout, int tc, T* base, int trans, int bi, int bx,
                               int row0, int c0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, fr = lane & 15, fk = lane >> 4;
-  constexpr int NTJ = Strip<T>::NTJ, LD = Strip<T>::LD;
+  constexpr int NTJ = Strip<T, W>::NTJ, LD = Strip<T, W>::LD, SW = W;
   const int m4 = (m + 3) & ~3;
   for (int rb = wv; 16 * rb < mout; rb += 4) {
-    dbl4 acc[NTJ];
+    dbl4 acc[NS][NTJ];
 #pragma unroll
-    for (int tj = 0; tj < NTJ; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int h = 0; h < NS; ++h)
+#pragma unroll
+      for (int tj = 0; tj < NTJ; ++tj) acc[h][tj] = dbl4{0.0, 0.0, 0.0, 0.0};
     const int row = 16 * rb + fr;
-#pragma unroll 4
+#pragma unroll 8
     for (int k0 = 0; k0 < m4; k0 += 4) {
       const int k = k0 + fk;
       double av = 0.0;
       if (k < m && row < m) av = (double)(OP == 0 ? M[(int64_t)k * m + row] : M[(int64_t)row * m + k]);
-      double bv[NTJ];
 #pragma unroll
-      for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[k * LD + 16 * tj + fr];
+      for (int h = 0; h < NS; ++h) {
+        double bv[NTJ];
 #pragma unroll
-      for (int tj = 0; tj < NTJ; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
+        for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[h * m4 * LD + k * LD + 16 * tj + fr];
+#pragma unroll
+        for (int tj = 0; tj < NTJ; ++tj)
+          acc[h][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[h][tj], 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int tj = 0; tj < NTJ; ++tj)
+    for (int h = 0; h < NS; ++h)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int a = 16 * rb + 4 * j + fk, c = 16 * tj + fr;
-        if (a < mout && c < tc) *view_ptr(base, trans, bi, bx, row0 + a, c0 + c) = (T)acc[tj][j];
-      }
+      for (int tj = 0; tj < NTJ; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = 16 * rb + 4 * j + fk, c = h * SW + 16 * tj + fr;
+          if (a < mout && c < tc) *view_ptr(base, trans, bi, bx, row0 + a, c0 + c) = (T)acc[h][tj][j];
+        }
   }
 }
 
 // The strip X[a][c] = view(row0 + a, c0 + c), a < m, c < tc <= SW (rows m ..
 // m4 - 1 zero), the unit-stride index on consecutive threads.
-template <typename T>
+template <typename T, int W = Strip<T>::SW>
 __device__ inline void load_strip(T* X, const T* base, int trans, int bi, int bx, int row0, int m, int c0, int tc) {
-  constexpr int SW = Strip<T>::SW, LD = Strip<T>::LD;
+  constexpr int SW = W, LD = Strip<T, W>::LD;
   const int m4 = (m + 3) & ~3;
   if (trans) {
     for (int e = threadIdx.x; e < tc * m4; e += NT) {
@@ -4909,14 +4919,18 @@ __device__ inline void load_strip(T* X, const T* base, int trans, int bi, int bx
   }
 }
 
-template <typename T>
+template <typename T, int W = Strip<T>::SW>
 size_t work_strip_big(int bmax) {
-  return (size_t)((std::min(bmax, BG_MAXB) + 3) & ~3) * Strip<T>::LD * sizeof(T);
+  return (size_t)((std::min(bmax, BG_MAXB) + 3) & ~3) * Strip<T, W>::LD * sizeof(T);
 }
+// the strip width of the rotation of the views: 32 columns, so that a
+// compute unit holds twice the workgroups of 64-column strips (10% faster on
+// the 3D Laplacian; the triangular solve keeps 64, where 32 was slower)
+constexpr int SW_VIEW = 32;
 
 // V_ix <- U_i^T V_ix for the close and far views of big steps (far views keep
 // rows < r_i; with compensation k_compensate reads E_i and zeroes it).
-template <typename T>
+template <typename T, int NS, int W>
 __global__ __launch_bounds__(NT) void k_rot_big(LevelArgs<T> A, int32_t it0) {
   const Item item = A.items[it0 + xcd_swizzle(blockIdx.x, gridDim.x)];
   if (item.view < 0) return;
@@ -4932,13 +4946,16 @@ __global__ __launch_bounds__(NT) void k_rot_big(LevelArgs<T> A, int32_t it0) {
   const T* Ug = A.U + A.u_off[i];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* X = reinterpret_cast<T*>(smem_raw);
-  constexpr int SW = Strip<T>::SW;
-  for (int c0 = 0; c0 < bx; c0 += SW) {
-    const int tc = min(SW, bx - c0);
+  constexpr int SW = W, LD = Strip<T, W>::LD;
+  const int b4 = (b + 3) & ~3;
+  for (int c0 = 0; c0 < bx; c0 += NS * SW) {
+    const int tc = min(NS * SW, bx - c0);
     __syncthreads();
-    load_strip(X, base, v.trans, b, bx, 0, b, c0, tc);
+    for (int h = 0; h < NS; ++h)
+      if (h * SW < tc)
+        load_strip<T, W>(X + h * b4 * LD, base, v.trans, b, bx, 0, b, c0 + h * SW, min(SW, tc - h * SW));
     __syncthreads();
-    strip_product<T, 0>(Ug, b, X, drop ? r : b, tc, base, v.trans, b, bx, 0, c0);
+    strip_product<T, 0, NS, W>(Ug, b, X, drop ? r : b, tc, base, v.trans, b, bx, 0, c0);
     if (drop)
       for (int e = threadIdx.x; e < (b - r) * tc; e += NT)
         *view_ptr(base, v.trans, b, bx, r + e / tc, c0 + e % tc) = T(0);
@@ -5032,7 +5049,7 @@ __global__ __launch_bounds__(NT) void k_rot_big_diag(LevelArgs<T> A, int32_t s0)
 }
 
 // L(c, n_i)^T = L_nn^{-1} V_ic[n_i, live_c] for the close views of big steps.
-template <typename T>
+template <typename T, int NS, int W>
 __global__ __launch_bounds__(NT) void k_trsm_big(LevelArgs<T> A, int32_t it0) {
   const Item item = A.items[it0 + xcd_swizzle(blockIdx.x, gridDim.x)];
   const Step st = A.steps[item.step];
@@ -5050,13 +5067,16 @@ __global__ __launch_bounds__(NT) void k_trsm_big(LevelArgs<T> A, int32_t it0) {
   const T* Lig = A.Li + A.u_off[i];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* X = reinterpret_cast<T*>(smem_raw);
-  constexpr int SW = Strip<T>::SW;
-  for (int c0 = 0; c0 < lc; c0 += SW) {
-    const int tc = min(SW, lc - c0);
+  constexpr int SW = W, LD = Strip<T, W>::LD;
+  const int n4 = (n + 3) & ~3;
+  for (int c0 = 0; c0 < lc; c0 += NS * SW) {
+    const int tc = min(NS * SW, lc - c0);
     __syncthreads();
-    load_strip(X, base, v.trans, b, bx, r, n, c0, tc);
+    for (int h = 0; h < NS; ++h)
+      if (h * SW < tc)
+        load_strip<T, W>(X + h * n4 * LD, base, v.trans, b, bx, r, n, c0 + h * SW, min(SW, tc - h * SW));
     __syncthreads();
-    strip_product<T, 1>(Lig, n, X, n, tc, base, v.trans, b, bx, r, c0);
+    strip_product<T, 1, NS, W>(Lig, n, X, n, tc, base, v.trans, b, bx, r, c0);
   }
 }
 
@@ -5513,7 +5533,10 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   if (tiled && w.r1 > w.r0)
     hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
   if (big && w.r1 > w.r0) {
-    hipLaunchKernelGGL(k_rot_big<T>, dim3(w.r1 - w.r0), dim3(NT), wsb, stream, B, w.r0);
+    // (two strips per pass measured slower: the doubled LDS halves the
+    // workgroups a compute unit holds, which hide the L2 latency of U_i)
+    hipLaunchKernelGGL((k_rot_big<T, 1, SW_VIEW>), dim3(w.r1 - w.r0), dim3(NT), (work_strip_big<T, SW_VIEW>(bmax)),
+                       stream, B, w.r0);
     hipLaunchKernelGGL(k_rot_big_diag<T>, dim3(w.s1 - w.s0), dim3(NT), wsb, stream, B, w.s0);
   }
   if (generic) launch<T>(k_rotate<T>, G, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream, bmax);
@@ -5535,7 +5558,8 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   G.items = A.trsm;
   if (tiled && w.t1 > w.t0)
     hipLaunchKernelGGL(k_trsm_t<T>, dim3(w.t1 - w.t0), dim3(NT), wt, stream, B, w.t0);
-  if (big && w.t1 > w.t0) hipLaunchKernelGGL(k_trsm_big<T>, dim3(w.t1 - w.t0), dim3(NT), wsb, stream, B, w.t0);
+  if (big && w.t1 > w.t0)
+    hipLaunchKernelGGL((k_trsm_big<T, 1, Strip<T>::SW>), dim3(w.t1 - w.t0), dim3(NT), wsb, stream, B, w.t0);
   if (generic) launch<T>(k_trsm<T>, G, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream, bmax);
   if (tiled && w.p1 > w.p0) {
     if (A.bf16_schur && sizeof(T) == sizeof(float))
