@@ -4015,16 +4015,18 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   }
   if (tid < BG_MA) rowix[tid] = tid;
   __syncthreads();
+  const int64_t t_s = clock64();
 
   // ---- 3. one-sided Jacobi on the rows of S (the four wavefronts) -----------
   // the row norms are lambda = sigma^2: the thresholds of the sigma-scale
   // tests squared
+  int nsweep = 0;
   if (ma > 1) {
     const double tol = (double)max(b, 16) * DBL_EPSILON;
     const int np = (ma + 1) / 2;
-    if (np <= 4) jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
-    else if (np <= 8) jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
-    else jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    if (np <= 4) nsweep = jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else if (np <= 8) nsweep = jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else nsweep = jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
   }
   __syncthreads();
   const int64_t t_eig = clock64();
@@ -4200,7 +4202,9 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
       int64_t* dd = A.dbg + 72 * (int64_t)i;
       dd[0] = ma;
       dd[1] = (truncated ? 1 : 0) + (cert ? 2 : 0);
+      dd[2] = nsweep;
       dd[3] = b;
+      dd[8] = t_s - t_chol;   // of which X X^T
       dd[4] = t_chol - t_start;
       dd[5] = t_eig - t_chol;
       dd[6] = t_dirs - t_eig;
@@ -4669,34 +4673,73 @@ __device__ inline SchurPair<T> schur_pair(const LevelArgs<T>& A, const Pair& pr,
 // thread holds its share of the next chunk in registers while the current one
 // is multiplied.  Other pairs (k_schur_big_bf16): 64 x 64 tiles, 64 panel
 // rows at a time.
-constexpr int SB_W = 128, SB_K = 32, SB_LD = SB_W + 4;
+// (an odd LDS row stride: the transposed views' stores, consecutive rows on
+// consecutive lanes, fall on different banks; the products read along rows)
+constexpr int SB_W = 128, SB_K = 16, SB_LD = SB_W + 1, SB_U = SB_K * SB_W / NT;
 
 template <typename T>
 size_t work_schur_big_bf16() {
   return (size_t)2 * SB_K * SB_LD * sizeof(T);
 }
 
-// Element u of this thread's share of a chunk: (row k, column c) of the two
-// panels (u < 16: P_a, else P_c), the unit-stride index on consecutive threads.
+// This thread's share of a chunk of one panel: SB_U entries (row k, column
+// c), k = kt + u kstep, c = ct + u cstep (u < SB_U), the unit-stride index on
+// consecutive threads (rows for a transposed view, columns otherwise), so
+// that one offset and one stride per panel address all of them.
 template <typename T>
-__device__ inline T sb_load(const SchurPair<T>& P, int b, int u, int row0, int nk, int a0, int tan, int c0, int tcn) {
-  const bool q = u >= 16;
-  const int e = threadIdx.x + NT * (u & 15);
-  const int trans = q ? P.tcv : P.ta;
-  const int k = trans ? (e & (SB_K - 1)) : (e / SB_W), c = trans ? (e / SB_K) : (e & (SB_W - 1));
-  const int tw = q ? tcn : tan, col0 = q ? c0 : a0, bx = q ? P.bc : P.ba;
-  const T* base = q ? P.pc : P.pa;
-  if (k >= nk || c >= tw) return T(0);
-  return trans ? base[(int64_t)(col0 + c) * b + row0 + k] : base[(int64_t)(row0 + k) * bx + col0 + c];
+struct SbShare {
+  const T* p;       // panel base
+  int64_t off;      // offset of u = 0 at chunk row 0
+  int64_t step;     // offset between u and u + 1
+  int64_t rstep;    // offset of one chunk row
+  int kt, ct, kstep, cstep, tw;
+};
+
+template <typename T>
+__device__ inline SbShare<T> sb_share(const T* p, int trans, int b, int bx, int col0, int tw, int row0) {
+  SbShare<T> s;
+  const int tid = threadIdx.x;
+  s.p = p;
+  s.tw = tw;
+  if (trans) {
+    s.kt = tid & (SB_K - 1);
+    s.ct = tid / SB_K;
+    s.kstep = 0;
+    s.cstep = NT / SB_K;
+    s.off = (int64_t)(col0 + s.ct) * b + row0 + s.kt;
+    s.step = (int64_t)s.cstep * b;
+    s.rstep = 1;
+  } else {
+    s.kt = tid / SB_W;
+    s.ct = tid & (SB_W - 1);
+    s.kstep = NT / SB_W;
+    s.cstep = 0;
+    s.off = (int64_t)(row0 + s.kt) * bx + col0 + s.ct;
+    s.step = (int64_t)s.kstep * bx;
+    s.rstep = bx;
+  }
+  return s;
+}
+
+// the SB_U entries of chunk row k0 (nk rows valid), zero outside the panel
+// (the loads are unconditional, entries outside the panel read its first
+// entry and are replaced by zero: a predicated load per entry would be a
+// branch of its own)
+template <typename T>
+__device__ inline void sb_fetch(const SbShare<T>& s, int k0, int nk, T (&v)[SB_U]) {
+  const int64_t o = s.off + (int64_t)k0 * s.rstep;
+#pragma unroll
+  for (int u = 0; u < SB_U; ++u) {
+    const bool ok = s.kt + u * s.kstep < nk && s.ct + u * s.cstep < s.tw;
+    const T x = s.p[ok ? o + u * s.step : 0];
+    v[u] = ok ? x : T(0);
+  }
 }
 
 template <typename T>
-__device__ inline int sb_slot(const SchurPair<T>& P, int u) {
-  const bool q = u >= 16;
-  const int e = threadIdx.x + NT * (u & 15);
-  const int trans = q ? P.tcv : P.ta;
-  const int k = trans ? (e & (SB_K - 1)) : (e / SB_W), c = trans ? (e / SB_K) : (e & (SB_W - 1));
-  return (q ? SB_K * SB_LD : 0) + k * SB_LD + c;
+__device__ inline void sb_store(const SbShare<T>& s, T* L, const T (&v)[SB_U]) {
+#pragma unroll
+  for (int u = 0; u < SB_U; ++u) L[(s.kt + u * s.kstep) * SB_LD + s.ct + u * s.cstep] = v[u];
 }
 
 template <typename T>
@@ -4792,22 +4835,24 @@ __global__ __launch_bounds__(NT) void k_schur_big_bf16w(LevelArgs<T> A, int32_t 
         for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
           for (int v = 0; v < 16; ++v) acc[ti][tj][v] = 0.0f;
-      T nxt[32];
-#pragma unroll
-      for (int u = 0; u < 32; ++u) nxt[u] = sb_load(P, b, u, r, min(SB_K, n), a0, tan, c0, tcn);
+      const SbShare<T> sa = sb_share(P.pa, P.ta, b, P.ba, a0, tan, r);
+      const SbShare<T> sc = sb_share(P.pc, P.tcv, b, P.bc, c0, tcn, r);
+      T na[SB_U], nc[SB_U];
+      sb_fetch(sa, 0, min(SB_K, n), na);
+      sb_fetch(sc, 0, min(SB_K, n), nc);
       for (int k0 = 0; k0 < n; k0 += SB_K) {
         __syncthreads();   // the previous chunk consumed
-#pragma unroll
-        for (int u = 0; u < 32; ++u) Pa[sb_slot(P, u)] = nxt[u];   // P_c's slots follow P_a's
+        sb_store(sa, Pa, na);
+        sb_store(sc, Pc, nc);
         __syncthreads();
         if (k0 + SB_K < n) {
           const int nk2 = min(SB_K, n - k0 - SB_K);
-#pragma unroll
-          for (int u = 0; u < 32; ++u) nxt[u] = sb_load(P, b, u, r + k0 + SB_K, nk2, a0, tan, c0, tcn);
+          sb_fetch(sa, k0 + SB_K, nk2, na);
+          sb_fetch(sc, k0 + SB_K, nk2, nc);
         }
         // rows beyond the chunk's end are zero (loaded as zero), so the k
         // loop always runs over SB_K
-#pragma unroll
+#pragma unroll 1
         for (int kk = 0; kk < SB_K; kk += 8) {
           bf16x4_t av[2], bv[2];
 #pragma unroll
@@ -4825,18 +4870,19 @@ __global__ __launch_bounds__(NT) void k_schur_big_bf16w(LevelArgs<T> A, int32_t 
               acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
         }
       }
+      // the target's unit stride runs along the lanes (ts_c = 1, see schur_pair)
+      T* const tb = P.tbase + (int64_t)(a0 + ra + kh) * P.ts_a + c0 + rc + l32;
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const int al = ra + 32 * ti + 8 * (v >> 2) + kh + (v & 3);
-            const int gm = rc + 32 * tj + l32;
-            if (al < tan && gm < tcn) {
-              T* tp = P.tbase + (int64_t)(a0 + al) * P.ts_a + (int64_t)(c0 + gm) * P.ts_c;
-              *tp = (T)((float)*tp - acc[ti][tj][v]);
-            }
+            const int dr = 32 * ti + 8 * (v >> 2) + (v & 3);
+            const bool ok = ra + kh + dr < tan && rc + 32 * tj + l32 < tcn;
+            T* tp = ok ? tb + (int64_t)dr * P.ts_a + 32 * tj : P.tbase;   // (an entry of the target)
+            const T old = *tp;
+            if (ok) *tp = (T)((float)old - acc[ti][tj][v]);
           }
     }
   }

@@ -567,7 +567,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       double sum[8] = {0}, mx[8] = {0};
       int cnt = 0;
       int worst = -1;
-      double bsum[8] = {0}, bmx[8] = {0};
+      double bsum[8] = {0}, bmx[8] = {0}, bs_sum = 0.0;
       int bcnt = 0;
       for (int32_t b2 = 0; b2 < L.M; ++b2) {
         if (hd[72 * b2 + 3] == 0) continue;
@@ -578,6 +578,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
             bsum[k] += (double)hd[72 * b2 + k];
             bmx[k] = std::max(bmx[k], (double)hd[72 * b2 + k]);
           }
+          bs_sum += (double)hd[72 * b2 + 8];
           continue;
         }
         ++cnt;
@@ -603,10 +604,10 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
                 sum[4] / cnt, mx[4], sum[5] / cnt, mx[5], sum[6] / cnt, mx[6], sum[7] / cnt, mx[7]);
       if (bcnt)
         fprintf(stderr,
-                "[cae] level %d: %d big compressions | ma %.1f/%.0f b %.0f/%.0f | cycles chol %.0f/%.0f eig "
-                "%.0f/%.0f checks+dirs %.0f/%.0f basis %.0f/%.0f\n",
-                l + 1, bcnt, bsum[0] / bcnt, bmx[0], bsum[3] / bcnt, bmx[3], bsum[4] / bcnt, bmx[4],
-                bsum[5] / bcnt, bmx[5], bsum[6] / bcnt, bmx[6], bsum[7] / bcnt, bmx[7]);
+                "[cae] level %d: %d big compressions | ma %.1f/%.0f b %.0f/%.0f sweeps %.1f/%.0f | cycles chol "
+                "%.0f/%.0f eig %.0f/%.0f (X X^T %.0f) checks+dirs %.0f/%.0f basis %.0f/%.0f\n",
+                l + 1, bcnt, bsum[0] / bcnt, bmx[0], bsum[3] / bcnt, bmx[3], bsum[2] / bcnt, bmx[2], bsum[4] / bcnt,
+                bmx[4], bsum[5] / bcnt, bmx[5], bs_sum / bcnt, bsum[6] / bcnt, bmx[6], bsum[7] / bcnt, bmx[7]);
     }
     // the ranks decide the sizes of the next level (read back through pinned
     // memory: a copy into pageable memory costs a staged transfer each)
