@@ -168,7 +168,10 @@ __device__ inline void axpy_run(double (&s)[R], const T* P, int64_t stride, int 
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int tu = t + 4 * u;
-      pv[u] = tu < tend ? P[(int64_t)tu * stride] : T(0);
+      // unconditional load (P[0] past the end), then zero: a predicated
+      // load would be a branch per entry
+      const T x = P[tu < tend ? (int64_t)tu * stride : 0];
+      pv[u] = tu < tend ? x : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {

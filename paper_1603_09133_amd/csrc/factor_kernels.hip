@@ -1578,6 +1578,8 @@ struct TileSrc {
 };
 template <typename T>
 __device__ inline void load_tile_pair(T* S, const T* pb, TileSrc P, const T* qb, TileSrc Q, int row0, int na) {
+  // (predicated loads here: unconditional ones with clamped addresses
+  // measured slower, holding more registers for the sixteen in flight)
   const int tp = P.nc > 0 ? na * P.nc : 0;
   const int tot = tp + (Q.nc > 0 ? na * Q.nc : 0);
   for (int e0 = 0; e0 < tot; e0 += 16 * NT) {
@@ -3803,13 +3805,12 @@ __global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0) {
       for (int e = threadIdx.x; e < 64 * mc4; e += NT) {
         const int k = v.trans ? (e >> 6) : (e % mc4);
         const int a = v.trans ? (e & 63) : (e / mc4);
-        T xa = T(0), xb = T(0);
-        if (k < mc) {
-          if (a < na) xa = v.trans ? base[(int64_t)(c0 + k) * b + ra + a] : base[(int64_t)(ra + a) * bx + c0 + k];
-          if (a < nb) xb = v.trans ? base[(int64_t)(c0 + k) * b + rb + a] : base[(int64_t)(rb + a) * bx + c0 + k];
-        }
-        Sa[k * TLD + a] = xa;
-        Sb[k * TLD + a] = xb;
+        // unconditional loads (the view's first entry outside the chunk)
+        const bool oka = k < mc && a < na, okb = k < mc && a < nb;
+        const T xa = base[oka ? (v.trans ? (int64_t)(c0 + k) * b + ra + a : (int64_t)(ra + a) * bx + c0 + k) : 0];
+        const T xb = base[okb ? (v.trans ? (int64_t)(c0 + k) * b + rb + a : (int64_t)(rb + a) * bx + c0 + k) : 0];
+        Sa[k * TLD + a] = oka ? xa : T(0);
+        Sb[k * TLD + a] = okb ? xb : T(0);
       }
       __syncthreads();
       // FP64 matrix cores: wavefront w owns rows 16 w .. 16 w + 15 of the tile
@@ -4922,8 +4923,11 @@ __device__ void strip_product(const T* M, int m, const T* X, int mout, int tc, T
 #pragma unroll 8
     for (int k0 = 0; k0 < m4; k0 += 4) {
       const int k = k0 + fk;
-      double av = 0.0;
-      if (k < m && row < m) av = (double)(OP == 0 ? M[(int64_t)k * m + row] : M[(int64_t)row * m + k]);
+      // unconditional load (M[0] outside the matrix), then zero: a
+      // predicated load would be a branch per k step
+      const bool ok = k < m && row < m;
+      const T mv = M[ok ? (OP == 0 ? (int64_t)k * m + row : (int64_t)row * m + k) : 0];
+      const double av = ok ? (double)mv : 0.0;
 #pragma unroll
       for (int h = 0; h < NS; ++h) {
         double bv[NTJ];
@@ -4955,12 +4959,15 @@ __device__ inline void load_strip(T* X, const T* base, int trans, int bi, int bx
   if (trans) {
     for (int e = threadIdx.x; e < tc * m4; e += NT) {
       const int c = e / m4, a = e % m4;
-      X[a * LD + c] = a < m ? base[(int64_t)(c0 + c) * bi + row0 + a] : T(0);
+      const T x = base[a < m ? (int64_t)(c0 + c) * bi + row0 + a : 0];
+      X[a * LD + c] = a < m ? x : T(0);
     }
   } else {
     for (int e = threadIdx.x; e < m4 * SW; e += NT) {
       const int a = e / SW, c = e % SW;
-      X[a * LD + c] = (a < m && c < tc) ? base[(int64_t)(row0 + a) * bx + c0 + c] : T(0);
+      const bool ok = a < m && c < tc;
+      const T x = base[ok ? (int64_t)(row0 + a) * bx + c0 + c : 0];
+      X[a * LD + c] = ok ? x : T(0);
     }
   }
 }
