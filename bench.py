@@ -353,10 +353,10 @@ def main():
         per_launch_s = main_leg["compress_ms"] / main_leg["compress_launches"] / 1e3
         flops_per_launch = main_leg["compress_flops"] / main_leg["compress_launches"]
         ach = flops_per_launch / per_launch_s / 1e12
-        kname = ("compress (k_compress_rand / k_compress_gram / k_bg_gram + k_bg_eig)" if fkw else
-                 "compress (k_compress_gram<float,64|128> / k_bg_gram + k_bg_eig)")
+        kname = ("compress: one wave's far-row compressions (k_feat_mlp, k_compress_gram<float,64|128>, k_bg_gram, "
+                 "k_bg_eig, k_bg_cert, k_bg_full, k_compress)")
         out["roofline"] = {"bound": "alu", "kernel": kname, "achieved": ach, "peak": FP64_PEAK, "unit": "TFLOP/s",
-                           "frac": ach / FP64_PEAK, "traffic": _traffic("k_compress_gram<float,64>"),
+                           "frac": ach / FP64_PEAK, "traffic": _traffic("compress"),
                            "launches_per_step": main_leg["compress_launches"] / args.steps,
                            "avg_launch_us": per_launch_s * 1e6, "algorithmic_flops_per_launch": flops_per_launch}
     if not args.no_cpu_baseline:
