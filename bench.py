@@ -155,18 +155,22 @@ def _workload(args, cae, problems):
             mats.append(problems.laplacian(d))
             dl.append(d)
             pl.append((8, 8) if k == 0 else (2, 2, 4))
-        A, perm, bp, co, _ = batched.assemble(mats, dl, pl)
+        mats = [m.tocsr() for m in mats]
+        for m in mats:
+            m.sort_indices()
+        N = int(sum(m.shape[0] for m in mats))
         B = np.concatenate([rng.standard_normal((4, m.shape[0])) for m in mats], axis=1).T
         w.update(dims=None, patch=None, eps=1e-6, nrhs=4, coarsen=args.coarsen or "siblings", precision=cae.FP32,
-                 learned=False, B=B,
+                 learned=False, B=B, N=N, batch=(mats, dl, pl),
                  text=(f"256 independent Laplacians (2D side 64..512 with 8x8 patches, 3D side 16..64 with 2x2x4 "
-                       f"patches; draws default_rng(3)), N={A.shape[0]} in one joint factorization, eps=1e-6, "
-                       f"FP32 factor, exact ranks, 4 RHS per problem, PCG FP64 to 1e-8"))
-        w.update(A=A, csr=problems.to_csr_arrays(A), perm=perm, bp=bp, co=co, M1=len(bp) - 1)
+                       f"patches; draws default_rng(3)), N={N} in one joint factorization (cae_analyze_batched), "
+                       f"eps=1e-6, FP32 factor, exact ranks, 4 RHS per problem, an independent FP64 PCG per "
+                       f"problem to 1e-8 (cae_pcg_solve_batched)"))
         return w
     else:
         raise SystemExit(f"unknown config {args.config}")
     w["A"] = A
+    w["N"] = A.shape[0]
     w["csr"] = problems.to_csr_arrays(A)
     perm, bp, co = cae.grid_order(w["dims"], w["patch"])
     w.update(perm=perm, bp=bp, co=co, M1=len(bp) - 1)
@@ -205,17 +209,23 @@ def main():
 
     dev = torch.device("cuda:0")
     work = _workload(args, cae, problems)
-    ip, ix, dv = work["csr"]
-    N = work["A"].shape[0]
+    N = work["N"]
     order = cae.ORDER_MULTICOLOUR
+    batch = work.get("batch")
     _log(f"{args.config}: N={N}, symbolic analysis")
     t = time.perf_counter()
-    an = cae.Analysis(ip, ix, work["perm"], work["bp"], work["co"], order=order, coarsen=work["coarsen"])
+    if batch:
+        from paper_1603_09133_amd import batched
+        an = batched.analyze(*batch, order=order, coarsen=work["coarsen"])
+    else:
+        ip, ix, dv = work["csr"]
+        an = cae.Analysis(ip, ix, work["perm"], work["bp"], work["co"], order=order, coarsen=work["coarsen"])
     analysis_ms = (time.perf_counter() - t) * 1e3
     _log(f"analysis {analysis_ms:.0f} ms, {an.nlevels()} levels")
     wave1 = an.level_arrays(0)["wave"]
     work["first_colour"] = int(np.sum(wave1 == 0))
-    vals = torch.from_numpy(dv).to(dev)
+    work["M1"] = len(wave1)
+    vals = batched.stacked_values(batch[0], dev) if batch else torch.from_numpy(dv).to(dev)
     b = torch.from_numpy(np.ascontiguousarray(work["B"].T)).to(dev)
     x = torch.empty_like(b)
     fkw = {}
@@ -245,6 +255,10 @@ def main():
     def leg(name, prec, kw, steps, warmup):
         def step():
             f = cae.Factor(an, vals, work["eps"], precision=prec, timing=True, **kw)
+            if batch:
+                # an independent PCG per problem; per column the most iterations over the problems
+                _, it, rel = f.pcg_batched(b, rtol=1e-8, maxit=1000, x=x)
+                return f, it.max(axis=0), rel.max(axis=0)
             _, it, rel = f.pcg(b, rtol=1e-8, maxit=1000, x=x)
             return f, it, rel
 
@@ -359,7 +373,7 @@ def main():
                            "frac": ach / FP64_PEAK, "traffic": _traffic("compress"),
                            "launches_per_step": main_leg["compress_launches"] / args.steps,
                            "avg_launch_us": per_launch_s * 1e6, "algorithmic_flops_per_launch": flops_per_launch}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not batch:
         lv1_s = main_leg["level_ms"][0] / 1e3
         out["cpu_baseline"] = _cpu_baseline(work, work["M1"] / lv1_s if lv1_s > 0 else None, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -288,6 +288,67 @@ int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
                   int32_t* iters, double* relres);
 
 /*
+ * A batch of independent problems in one factorization (Algorithms 1 and 2
+ * applied to each problem; the problems share every level's launches).  A
+ * problem is a sparse SPD matrix on a tensor grid whose unknowns are numbered
+ * lexicographically with the first axis fastest; its level-1 blocks are
+ * patches of the given shape in Morton order (Section 2.5, eq. (bsp)).
+ */
+typedef struct {
+  int64_t n;                /* unknowns: the product of dims */
+  const int64_t* row_ptr;   /* HOST, n+1 (row_ptr[0] may be nonzero) */
+  const int32_t* col_idx;   /* HOST, both triangles, sorted, diagonal present */
+  const double* vals;       /* DEVICE, FP64 values in that CSR order */
+  int32_t ndim;             /* 2 or 3 */
+  int32_t dims[3];          /* grid sizes (dims[2] ignored for ndim 2) */
+  int32_t patch[3];         /* patch shape; all zero = 8 x 8 (2D) or 4 x 4 x 4 (3D) */
+} cae_problem_t;
+
+/*
+ * Symbolic analysis (host only) of nprob problems joined into one block-
+ * diagonal matrix: problem t's rows follow those of problems 0..t-1 in the
+ * joint ordering.  Problem t's block coordinates are offset by t's binary
+ * digits dealt to the three axes in turn above 8 bits, so the Morton order of
+ * the joint blocks runs problem by problem and the coarsening never joins
+ * blocks of two problems before each is one block; a problem may have at
+ * most 256 patches along an axis.  vals may be NULL here.  A numeric
+ * factorization of the analysis (values: the problems' values stacked in the
+ * joint CSR order) supports cae_pcg_solve_batched.
+ *   Errors: CAE_EINVAL (the message names the problem), CAE_ENOMEM.
+ */
+int cae_analyze_batched(int32_t nprob, const cae_problem_t* probs, const cae_options_t* opt,
+                        cae_analysis_t* out);
+
+/* Problems of an analysis and their first rows (row_off: host, nprob+1
+ * entries, or NULL); an analysis of one matrix reports one problem. */
+int cae_analysis_batch_rows(cae_analysis_t a, int32_t* nprob, int64_t* row_off);
+
+/*
+ * cae_analyze_batched followed by the numeric factorization of the stacked
+ * values (copied from the problems' device arrays), in one handle that owns
+ * the joint analysis.  The threshold is eps * the largest diagonal entry of
+ * the whole batch.  Every other call on handles works on the joint vectors
+ * (problems stacked).  The host arrays may be freed after the call.
+ *   Errors: as cae_analyze_batched and cae_factor_numeric.
+ */
+int cae_factor_batched(int32_t nprob, const cae_problem_t* probs, double eps,
+                       const cae_options_t* opt, cae_handle_t* out);
+
+/*
+ * PCG as cae_pcg_solve, run independently on every problem of a batched
+ * handle: each (problem, column) pair has its own step lengths and stops when
+ * its residual over the problem's rows satisfies ||r|| <= rtol ||b|| there.
+ * The sums over a problem's rows are formed in tiles of 4096 rows added in a
+ * fixed order (the result does not depend on the launch).
+ *   b, x: device, joint n x nrhs.  iters, relres: host, nprob * nrhs entries,
+ *   entry t * nrhs + k for problem t and column k.  CAE_ENOCONV when a pair
+ *   did not converge; CAE_EINVAL for a handle not made from a batch.
+ */
+int cae_pcg_solve_batched(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb,
+                          double* x, int64_t ldx, double rtol, int32_t maxit,
+                          int32_t* iters, double* relres);
+
+/*
  * FP64 preconditioned MINRES (the Krylov method of the paper's Section 3),
  * with M^{-1} as the symmetric positive definite preconditioner, x0 = 0.  The
  * iterate minimises ||b - A x||_{M^{-1}} over the preconditioned Krylov space

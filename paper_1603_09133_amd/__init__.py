@@ -119,9 +119,25 @@ class Analysis:
                                 ndim, C.byref(o), C.byref(h)))
         self._h = h
 
+    @classmethod
+    def _adopt(cls, h, n, order, keep=()):
+        """Wrap an analysis handle made by another entry point (owned)."""
+        self = cls.__new__(cls)
+        self._h, self.n, self.order, self._keep = h, n, order, keep
+        return self
+
     @property
     def handle(self):
         return self._h
+
+    def batch_rows(self):
+        """First row of every problem of a batched analysis (``nprob + 1``
+        entries; one problem for an analysis of one matrix)."""
+        k = C.c_int32()
+        check(lib().cae_analysis_batch_rows(self._h, C.byref(k), None))
+        out = np.empty(k.value + 1, np.int64)
+        check(lib().cae_analysis_batch_rows(self._h, C.byref(k), ptr(out)))
+        return out
 
     def nlevels(self):
         v = C.c_int32()
@@ -278,6 +294,25 @@ class Factor:
                                        int(maxit), ptr(it), ptr(rel)), allow=(_lib.CAE_ENOCONV,))
         self.converged = rc == _lib.CAE_OK
         return (x.reshape(-1) if sq else x), it, rel
+
+    def pcg_batched(self, b, rtol=1e-8, maxit=1000, x=None):
+        """Independent FP64 PCG on every problem of a batched factor
+        (``cae_pcg_solve_batched``); returns ``(x, iters, relres)`` with
+        ``iters`` and ``relres`` of shape ``(nprob, nrhs)``."""
+        import torch
+        bb, k, sq = _as_cols(b)
+        if x is None:
+            x = torch.empty_like(bb)
+        nprob = len(self._rows()) - 1
+        it = np.zeros((nprob, k), np.int32)
+        rel = np.zeros((nprob, k), np.float64)
+        rc = check(lib().cae_pcg_solve_batched(self._h, k, bb.data_ptr(), self.n, x.data_ptr(), self.n, float(rtol),
+                                               int(maxit), ptr(it), ptr(rel)), allow=(_lib.CAE_ENOCONV,))
+        self.converged = rc == _lib.CAE_OK
+        return (x.reshape(-1) if sq else x), it, rel
+
+    def _rows(self):
+        return self.row_off if getattr(self, "row_off", None) is not None else self.analysis.batch_rows()
 
     def minres(self, b, rtol=1e-10, maxit=1000, x=None):
         """FP64 preconditioned MINRES (``cae_minres_solve``); returns ``(x, iters,

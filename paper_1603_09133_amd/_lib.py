@@ -38,6 +38,11 @@ class Options(C.Structure):
                 ("workspace_bytes", C.c_size_t), ("big_pivot_cap", C.c_int32)]
 
 
+class Problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("vals", C.c_void_p),
+                ("ndim", C.c_int32), ("dims", C.c_int32 * 3), ("patch", C.c_int32 * 3)]
+
+
 class LevelInfo(C.Structure):
     _fields_ = [("M", C.c_int32), ("nclose", C.c_int32), ("nfar", C.c_int32), ("nremoved", C.c_int32),
                 ("nwaves", C.c_int32), ("Mnext", C.c_int32)]
@@ -59,6 +64,7 @@ _lib = None
 EXPORTS = [
     "cae_default_options", "cae_last_error", "cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels",
     "cae_analysis_level_info", "cae_analysis_level_arrays", "cae_analysis_perm", "cae_analysis_destroy",
+    "cae_analyze_batched", "cae_analysis_batch_rows", "cae_factor_batched", "cae_pcg_solve_batched",
     "cae_factor_numeric", "cae_workspace_query", "cae_factor", "cae_apply_precond", "cae_apply_precond_noalloc", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve",
     "cae_get_stats",
     "cae_get_ranks", "cae_get_sizes", "cae_get_drops", "cae_get_level_ms", "cae_export_factor", "cae_destroy", "cae_mlp_param_count", "cae_mlp_train", "cae_mlp_loss_grad",
@@ -95,6 +101,10 @@ def lib():
     L.cae_apply_precond_noalloc.argtypes = [p, i32, p, i64, p, i64, p]
     L.cae_apply_factor.argtypes = [p, i32, p, i64, p, i64]
     L.cae_pcg_solve.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
+    L.cae_analyze_batched.argtypes = [i32, C.POINTER(Problem), C.POINTER(Options), C.POINTER(p)]
+    L.cae_analysis_batch_rows.argtypes = [p, C.POINTER(i32), p]
+    L.cae_factor_batched.argtypes = [i32, C.POINTER(Problem), dbl, C.POINTER(Options), C.POINTER(p)]
+    L.cae_pcg_solve_batched.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
     L.cae_minres_solve.argtypes = [p, i32, p, i64, p, i64, dbl, i32, p, p]
     L.cae_get_stats.argtypes = [p, C.POINTER(Stats)]
     L.cae_get_ranks.argtypes = [p, i32, p]
@@ -111,7 +121,8 @@ def lib():
     L.cae_mlp_predict.argtypes = [p, p, i64, p, p]
     for name in ["cae_grid_order", "cae_graph_order", "cae_analyze", "cae_analysis_levels", "cae_analysis_level_info",
                  "cae_analysis_level_arrays", "cae_analysis_perm", "cae_factor_numeric", "cae_workspace_query", "cae_factor",
-                 "cae_apply_precond",
+                 "cae_apply_precond", "cae_analyze_batched", "cae_analysis_batch_rows", "cae_factor_batched",
+                 "cae_pcg_solve_batched",
                  "cae_apply_precond_noalloc", "cae_apply_factor", "cae_pcg_solve", "cae_minres_solve", "cae_get_stats", "cae_get_ranks",
                  "cae_get_sizes", "cae_get_drops", "cae_get_level_ms", "cae_export_factor", "cae_mlp_train", "cae_mlp_loss_grad", "cae_mlp_predict"]:
         getattr(L, name).restype = C.c_int

@@ -876,7 +876,7 @@ __global__ void k_pcg_xr(int64_t n, int32_t nrhs, const double* rz, const double
 }
 
 __global__ void k_pcg_beta(int32_t nrhs, double* rz, const double* rz_new, const int32_t* active, double* beta) {
-  const int k = threadIdx.x;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nrhs) return;
   beta[k] = active[k] ? rz_new[k] / rz[k] : 0.0;
   if (active[k]) rz[k] = rz_new[k];
@@ -887,6 +887,61 @@ __global__ void k_pcg_p(int64_t n, const int32_t* active, const double* beta, co
   const int k = blockIdx.y;
   if (i >= n || !active[k]) return;
   p[i + k * n] = z[i + k * n] + beta[k] * p[i + k * n];
+}
+
+// Segmented forms for the problems of a batch: one workgroup per (tile,
+// column); a tile lies inside one segment, so its lane is uniform.
+__global__ __launch_bounds__(NT) void k_seg_dot_part(SegTiles sg, const double* a, int64_t lda, const double* b,
+                                                     int64_t ldb, double* partial) {
+  __shared__ double red[NT];
+  const int t = blockIdx.x, k = blockIdx.y;
+  const double* ak = a + k * lda;
+  const double* bk = b + k * ldb;
+  double s = 0;
+  for (int64_t i = sg.tb[t] + threadIdx.x; i < sg.te[t]; i += NT) s += ak[i] * bk[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)k * sg.ntiles + t] = red[0];
+}
+
+__global__ __launch_bounds__(NT) void k_seg_dot_final(SegTiles sg, const double* partial, double* out) {
+  __shared__ double red[NT];
+  const int sgm = blockIdx.x, k = blockIdx.y;
+  double s = 0;
+  for (int t = sg.sfirst[sgm] + threadIdx.x; t < sg.sfirst[sgm + 1]; t += NT) s += partial[(int64_t)k * sg.ntiles + t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k * sg.nseg + sgm] = red[0];
+}
+
+__global__ __launch_bounds__(NT) void k_seg_pcg_xr(SegTiles sg, int64_t n, const double* rz, const double* pq,
+                                                   const int32_t* active, double* x, int64_t ldx, const double* p,
+                                                   double* r, const double* q) {
+  const int t = blockIdx.x, k = blockIdx.y;
+  const int lane = k * sg.nseg + sg.ts[t];
+  if (!active[lane]) return;
+  const double alpha = rz[lane] / pq[lane];
+  for (int64_t i = sg.tb[t] + threadIdx.x; i < sg.te[t]; i += NT) {
+    x[i + k * ldx] += alpha * p[i + k * n];
+    r[i + k * n] -= alpha * q[i + k * n];
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_seg_pcg_p(SegTiles sg, int64_t n, const int32_t* active, const double* beta,
+                                                  const double* z, double* p) {
+  const int t = blockIdx.x, k = blockIdx.y;
+  const int lane = k * sg.nseg + sg.ts[t];
+  if (!active[lane]) return;
+  const double bt = beta[lane];
+  for (int64_t i = sg.tb[t] + threadIdx.x; i < sg.te[t]; i += NT) p[i + k * n] = z[i + k * n] + bt * p[i + k * n];
 }
 
 // ---------------------------------------------------------------- MINRES ----
@@ -1114,8 +1169,31 @@ void launch_pcg_xr(int64_t n, int32_t nrhs, const double* rz, const double* pq, 
 
 void launch_pcg_p(int64_t n, int32_t nrhs, double* rz, const double* rz_new, const int32_t* active,
                   const double* z, double* p, double* beta, hipStream_t stream) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(NT), 0, stream, nrhs, rz, rz_new, active, beta);
+  hipLaunchKernelGGL(k_pcg_beta, dim3((unsigned)((nrhs + NT - 1) / NT)), dim3(NT), 0, stream, nrhs, rz, rz_new, active,
+                     beta);
   hipLaunchKernelGGL(k_pcg_p, dim3((unsigned)((n + NT - 1) / NT), nrhs), dim3(NT), 0, stream, n, active,
+                     (const double*)beta, z, p);
+}
+
+void launch_seg_dots(const SegTiles& sg, int32_t nrhs, const double* a, int64_t lda, const double* b, int64_t ldb,
+                     double* partial, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_seg_dot_part, dim3((unsigned)sg.ntiles, nrhs), dim3(NT), 0, stream, sg, a, lda, b, ldb, partial);
+  hipLaunchKernelGGL(k_seg_dot_final, dim3((unsigned)sg.nseg, nrhs), dim3(NT), 0, stream, sg, (const double*)partial,
+                     out);
+}
+
+void launch_seg_pcg_xr(const SegTiles& sg, int64_t n, int32_t nrhs, const double* rz, const double* pq,
+                       const int32_t* active, double* x, int64_t ldx, const double* p, double* r, const double* q,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(k_seg_pcg_xr, dim3((unsigned)sg.ntiles, nrhs), dim3(NT), 0, stream, sg, n, rz, pq, active, x, ldx,
+                     p, r, q);
+}
+
+void launch_seg_pcg_p(const SegTiles& sg, int64_t n, int32_t nrhs, double* rz, const double* rz_new,
+                      const int32_t* active, const double* z, double* p, double* beta, hipStream_t stream) {
+  const int32_t L = nrhs * sg.nseg;
+  hipLaunchKernelGGL(k_pcg_beta, dim3((unsigned)((L + NT - 1) / NT)), dim3(NT), 0, stream, L, rz, rz_new, active, beta);
+  hipLaunchKernelGGL(k_seg_pcg_p, dim3((unsigned)sg.ntiles, nrhs), dim3(NT), 0, stream, sg, n, active,
                      (const double*)beta, z, p);
 }
 

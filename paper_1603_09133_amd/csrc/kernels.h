@@ -186,6 +186,27 @@ void launch_pcg_xr(int64_t n, int32_t nrhs, const double* rz, const double* pq, 
 // p = z + beta p with beta[k] = rz_new[k] / rz[k] (active columns), then rz = rz_new
 void launch_pcg_p(int64_t n, int32_t nrhs, double* rz, const double* rz_new, const int32_t* active,
                   const double* z, double* p, double* beta, hipStream_t stream);
+// Independent PCG runs of the problems of a batch: the rows of the joint
+// vectors split into tiles that never straddle two problems (segments), and
+// every (segment, column) lane has its own scalars, lane = k * nseg + segment.
+struct SegTiles {
+  const int64_t* tb;       // first row of every tile
+  const int64_t* te;       // one past its last row
+  const int32_t* ts;       // segment of every tile
+  const int32_t* sfirst;   // first tile of every segment (nseg + 1)
+  int32_t ntiles = 0, nseg = 0;
+};
+constexpr int SEG_TILE_ROWS = 4096;
+// out[k * nseg + s] = sum over the rows of segment s of a .* b (column k), the
+// tiles' partial sums added in tile order; partial: nrhs * ntiles doubles
+void launch_seg_dots(const SegTiles& sg, int32_t nrhs, const double* a, int64_t lda, const double* b, int64_t ldb,
+                     double* partial, double* out, hipStream_t stream);
+// launch_pcg_xr / launch_pcg_p with the scalars of each row's lane
+void launch_seg_pcg_xr(const SegTiles& sg, int64_t n, int32_t nrhs, const double* rz, const double* pq,
+                       const int32_t* active, double* x, int64_t ldx, const double* p, double* r, const double* q,
+                       hipStream_t stream);
+void launch_seg_pcg_p(const SegTiles& sg, int64_t n, int32_t nrhs, double* rz, const double* rz_new,
+                      const int32_t* active, const double* z, double* p, double* beta, hipStream_t stream);
 // ----------------------------------------------------------------- MINRES ---
 // fields of the per-column MINRES state st[f * nrhs + k]
 enum {

@@ -237,6 +237,7 @@ struct DevLevelSym {
 
 struct cae_analysis_s {
   cae::Analysis a;
+  std::vector<int64_t> batch_off;   // first row of every problem of a batch (empty: one problem)
   bool uploaded = false;
   std::vector<DevLevelSym> dlev;
   DevBuf row_ptr, col_idx, perm, a0_dst, diag_pos;
@@ -286,6 +287,10 @@ struct cae_factor_s {
   DevBuf apart;   // close-block products of the split backward apply
   int32_t pcg_nrhs = 0;
   DevBuf pr, pz, pp, pq, sc, act, partial;
+  // a batch of independent problems: the row tiles of the per-problem PCG
+  // reductions (nseg = 0 for one problem)
+  DevBuf seg_tiles;
+  cae::SegTiles sg{};
   DevBuf mr[7], mst;   // MINRES vectors and per-column scalars
   DevBuf lcount;       // sketches accepted / rejected
   int64_t rec_rows = 0;
@@ -1152,6 +1157,42 @@ int checked_options(cae_analysis_t an, double eps, const cae_options_t* opt, cae
 
 // The numeric factorization with validated options; `carve` installs an arena
 // (or a counter) for the handle's device buffers.
+// Row tiles of the per-problem PCG reductions of a batch, none straddling
+// two problems.
+void setup_batch(cae_factor_s* h) {
+  const std::vector<int64_t>& off = h->an->batch_off;
+  const int nprob = (int)off.size() - 1;
+  std::vector<int64_t> tb, te;
+  std::vector<int32_t> ts, sfirst(nprob + 1, 0);
+  for (int t = 0; t < nprob; ++t) {
+    sfirst[t] = (int32_t)tb.size();
+    for (int64_t r = off[t]; r < off[t + 1]; r += cae::SEG_TILE_ROWS) {
+      tb.push_back(r);
+      te.push_back(std::min(off[t + 1], r + (int64_t)cae::SEG_TILE_ROWS));
+      ts.push_back(t);
+    }
+  }
+  sfirst[nprob] = (int32_t)tb.size();
+  const size_t nt = tb.size();
+  const size_t o_te = nt * sizeof(int64_t), o_ts = 2 * o_te, o_sf = o_ts + nt * sizeof(int32_t);
+  const size_t bytes = o_sf + (nprob + 1) * sizeof(int32_t);
+  std::vector<char> host(bytes);
+  std::memcpy(host.data(), tb.data(), nt * sizeof(int64_t));
+  std::memcpy(host.data() + o_te, te.data(), nt * sizeof(int64_t));
+  std::memcpy(host.data() + o_ts, ts.data(), nt * sizeof(int32_t));
+  std::memcpy(host.data() + o_sf, sfirst.data(), (nprob + 1) * sizeof(int32_t));
+  h->seg_tiles.alloc(bytes);
+  HIPCHK(hipMemcpyAsync(h->seg_tiles.p, host.data(), bytes, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const char* base = static_cast<const char*>(h->seg_tiles.p);
+  h->sg.tb = reinterpret_cast<const int64_t*>(base);
+  h->sg.te = reinterpret_cast<const int64_t*>(base + o_te);
+  h->sg.ts = reinterpret_cast<const int32_t*>(base + o_ts);
+  h->sg.sfirst = reinterpret_cast<const int32_t*>(base + o_sf);
+  h->sg.ntiles = (int32_t)nt;
+  h->sg.nseg = nprob;
+}
+
 int factor_checked(cae_analysis_t an, const double* vals, double eps, const cae_options_t& o, Carver* carve,
                    cae_handle_t* out) {
   struct Uninstall {
@@ -1176,6 +1217,7 @@ int factor_checked(cae_analysis_t an, const double* vals, double eps, const cae_
       (void)hipStreamSynchronize(h->stream);
       return rc;
     }
+    if (!an->batch_off.empty()) setup_batch(h.get());
     *out = h.release();
   } catch (const WorkspaceFull& e) {
     g_carve = nullptr;
@@ -1263,6 +1305,150 @@ int cae_factor(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const 
   return CAE_OK;
 }
 
+// ---------------------------------------------------------------- batches ---
+// Independent problems in one factorization: the joint matrix is block
+// diagonal, each problem keeps its Morton patch order, and problem t's block
+// coordinates are offset by t's binary digits dealt to the three axes in turn
+// above kBatchCoordBits bits, so the Morton interleave of the joint
+// coordinates orders the blocks problem by problem and the coarsening
+// (Section 2.5: parent = coordinate >> 1) never joins blocks of two problems
+// before each is reduced to one block.  Every dependency wave then holds the
+// independent steps of all problems, one launch per wave for the batch.
+namespace {
+constexpr int kBatchCoordBits = 8;
+
+static void batch_offset(int32_t t, int32_t out[3]) {
+  out[0] = out[1] = out[2] = 0;
+  for (int bit = 0; (t >> bit) != 0; ++bit) out[bit % 3] |= ((t >> bit) & 1) << (bit / 3);
+  for (int a = 0; a < 3; ++a) out[a] <<= kBatchCoordBits;
+}
+
+// first row and first stored entry of every problem; CAE_OK or an error
+static int batch_sizes(int32_t nprob, const cae_problem_t* probs, bool need_vals, std::vector<int64_t>& row_off,
+                std::vector<int64_t>& nz_off) {
+  if (nprob <= 0 || !probs) return fail(CAE_EINVAL, "nprob > 0 problems are required");
+  if (nprob > (1 << 21)) return fail(CAE_EINVAL, "too many problems for the block-coordinate budget");
+  row_off.assign(nprob + 1, 0);
+  nz_off.assign(nprob + 1, 0);
+  for (int t = 0; t < nprob; ++t) {
+    const cae_problem_t& P = probs[t];
+    const std::string who = "problem " + std::to_string(t) + ": ";
+    if (P.ndim != 2 && P.ndim != 3) return fail(CAE_EINVAL, who + "ndim must be 2 or 3");
+    int64_t cells = 1;
+    for (int a = 0; a < P.ndim; ++a) cells *= P.dims[a] > 0 ? P.dims[a] : 0;
+    if (P.n <= 0 || cells != P.n) return fail(CAE_EINVAL, who + "n must be the product of dims");
+    if (!P.row_ptr || !P.col_idx || (need_vals && !P.vals))
+      return fail(CAE_EINVAL, who + "row_ptr, col_idx and vals are required");
+    row_off[t + 1] = row_off[t] + P.n;
+    nz_off[t + 1] = nz_off[t] + (P.row_ptr[P.n] - P.row_ptr[0]);
+  }
+  if (row_off[nprob] >= ((int64_t)1 << 31)) return fail(CAE_EINVAL, "the joint matrix needs 32-bit column indices");
+  return CAE_OK;
+}
+}  // namespace
+
+int cae_analyze_batched(int32_t nprob, const cae_problem_t* probs, const cae_options_t* opt, cae_analysis_t* out) {
+  if (!out) return fail(CAE_EINVAL, "out is required");
+  *out = nullptr;
+  try {
+    std::vector<int64_t> row_off, nz_off;
+    if (int rc = batch_sizes(nprob, probs, false, row_off, nz_off)) return rc;
+    const int64_t n = row_off[nprob], nnz = nz_off[nprob];
+    std::vector<int64_t> rp(n + 1);
+    std::vector<int32_t> ci(nnz), perm(n), bptr, coords;
+    for (int t = 0; t < nprob; ++t) {
+      const cae_problem_t& P = probs[t];
+      const std::string who = "problem " + std::to_string(t) + ": ";
+      const int64_t r0 = row_off[t], z0 = nz_off[t];
+      for (int64_t i = 0; i < P.n; ++i) rp[r0 + i] = z0 + P.row_ptr[i] - P.row_ptr[0];
+      for (int64_t e = 0; e < nz_off[t + 1] - z0; ++e) {
+        const int32_t c = P.col_idx[P.row_ptr[0] + e];
+        if (c < 0 || c >= P.n) return fail(CAE_EINVAL, who + "column index out of range");
+        ci[z0 + e] = (int32_t)(c + r0);
+      }
+      int32_t patch[3] = {P.patch[0], P.patch[1], P.patch[2]};
+      if (patch[0] == 0 && patch[1] == 0 && patch[2] == 0)
+        for (int a = 0; a < P.ndim; ++a) patch[a] = P.ndim == 2 ? 8 : 4;
+      std::vector<int32_t> p, bp, co;
+      std::string e = cae::grid_order(P.ndim, P.dims, patch, p, bp, co);
+      if (!e.empty()) return fail(CAE_EINVAL, who + e);
+      int32_t off[3];
+      batch_offset(t, off);
+      for (int64_t i = 0; i < P.n; ++i) perm[r0 + i] = (int32_t)(p[i] + r0);
+      const size_t nb = bp.size() - 1;
+      for (size_t k = 0; k < nb; ++k) bptr.push_back((int32_t)(bp[k] + r0));
+      for (size_t k = 0; k < nb; ++k)
+        for (int a = 0; a < 3; ++a) {
+          const int32_t c = a < P.ndim ? co[k * P.ndim + a] : 0;
+          if (c >= (1 << kBatchCoordBits)) return fail(CAE_EINVAL, who + "more than 256 patches along an axis");
+          coords.push_back(c + off[a]);
+        }
+    }
+    rp[n] = nnz;
+    bptr.push_back((int32_t)n);
+    cae_analysis_t an = nullptr;
+    if (int rc = cae_analyze(n, rp.data(), ci.data(), perm.data(), bptr.data(), (int32_t)bptr.size() - 1, 0,
+                             coords.data(), 3, opt, &an))
+      return rc;
+    an->batch_off = row_off;
+    *out = an;
+  } catch (const std::bad_alloc&) {
+    return fail(CAE_ENOMEM, "host allocation failed");
+  }
+  return CAE_OK;
+}
+
+int cae_analysis_batch_rows(cae_analysis_t a, int32_t* nprob, int64_t* row_off) {
+  if (!a || !nprob) return fail(CAE_EINVAL, "analysis and nprob are required");
+  if (a->batch_off.empty()) {
+    *nprob = 1;
+    if (row_off) {
+      row_off[0] = 0;
+      row_off[1] = a->a.n;
+    }
+    return CAE_OK;
+  }
+  *nprob = (int32_t)a->batch_off.size() - 1;
+  if (row_off) std::memcpy(row_off, a->batch_off.data(), a->batch_off.size() * sizeof(int64_t));
+  return CAE_OK;
+}
+
+int cae_factor_batched(int32_t nprob, const cae_problem_t* probs, double eps, const cae_options_t* opt,
+                       cae_handle_t* out) {
+  if (!out) return fail(CAE_EINVAL, "out is required");
+  *out = nullptr;
+  try {
+    std::vector<int64_t> row_off, nz_off;
+    if (int rc = batch_sizes(nprob, probs, true, row_off, nz_off)) return rc;
+    cae_analysis_t an = nullptr;
+    if (int rc = cae_analyze_batched(nprob, probs, opt, &an)) return rc;
+    std::unique_ptr<cae_analysis_s> own(an);
+    cae_options_t o;
+    if (int rc = checked_options(an, eps, opt, o)) return rc;
+    hipStream_t st = (hipStream_t)o.stream;
+    g_cur_stream = st;
+    DevBuf dv;
+    dv.alloc((size_t)nz_off[nprob] * sizeof(double));
+    for (int t = 0; t < nprob; ++t)
+      HIPCHK(hipMemcpyAsync(dv.as<double>() + nz_off[t], probs[t].vals, (size_t)(nz_off[t + 1] - nz_off[t]) * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    Carver carve;
+    carve.base = static_cast<char*>(o.workspace);
+    carve.cap = o.workspace_bytes;
+    if (o.workspace && (reinterpret_cast<uintptr_t>(carve.base) & 255) != 0)
+      return fail(CAE_EINVAL, "workspace must be 256-byte aligned");
+    cae_handle_t h = nullptr;
+    if (int rc = factor_checked(an, dv.as<double>(), eps, o, o.workspace ? &carve : nullptr, &h)) return rc;
+    h->owned_an.reset(own.release());   // the handle owns the joint analysis
+    *out = h;
+  } catch (const HipError& e) {
+    return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    return fail(CAE_ENOMEM, "host allocation failed");
+  }
+  return CAE_OK;
+}
+
 static int cae_apply_precond_impl(cae_handle_t h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz) {
   if (h) g_cur_stream = h->stream;
   if (check_handle(h)) return CAE_EINVAL;
@@ -1325,13 +1511,15 @@ static int cae_apply_factor_impl(cae_handle_t h, int32_t nrhs, const double* x, 
   return CAE_OK;
 }
 
-static int cae_pcg_solve_impl(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
-                  int32_t maxit, int32_t* iters, double* relres) {
-  if (h) g_cur_stream = h->stream;
-  if (check_handle(h)) return CAE_EINVAL;
+// PCG (Algorithm of Hestenes and Stiefel with the preconditioner M^{-1} of
+// Proposition 2.2) on independent lanes: every column of every segment (one
+// problem of a batch; the whole matrix when sg is null) has its own scalars
+// and stopping test; lane = k * nseg + segment.  iters / relres per lane.
+static int pcg_lanes(cae_handle_t h, const cae::SegTiles* sg, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                     int64_t ldx, double rtol, int32_t maxit, int32_t* iters, double* relres) {
   const int64_t n = h->an->a.n;
-  if (nrhs <= 0 || !b || !x || ldb < n || ldx < n || !iters || !relres || maxit < 0 || !(rtol >= 0))
-    return fail(CAE_EINVAL, "bad PCG arguments");
+  const int nseg = sg ? sg->nseg : 1;
+  const int L = nrhs * nseg;
   hipStream_t s = h->stream;
   try {
     const cae_analysis_s* A = h->an;
@@ -1344,54 +1532,63 @@ static int cae_pcg_solve_impl(cae_handle_t h, int32_t nrhs, const double* b, int
     poison(h->pz, s);
     poison(h->pp, s);
     poison(h->pq, s);
-    h->sc.alloc((size_t)8 * nrhs * sizeof(double));
-    h->act.alloc((size_t)nrhs * sizeof(int32_t));
-    h->partial.alloc((size_t)nrhs * 1024 * sizeof(double));
+    h->sc.alloc((size_t)8 * L * sizeof(double));
+    h->act.alloc((size_t)L * sizeof(int32_t));
+    h->partial.alloc((size_t)nrhs * (sg ? (size_t)sg->ntiles : 1024) * sizeof(double));
     double* r = h->pr.as<double>();
     double* z = h->pz.as<double>();
     double* p = h->pp.as<double>();
     double* q = h->pq.as<double>();
     double* rz = h->sc.as<double>();
-    double* rz_new = rz + nrhs;
-    double* pq = rz + 2 * nrhs;
-    double* rr = rz + 3 * nrhs;
-    double* beta = rz + 4 * nrhs;
+    double* rz_new = rz + L;
+    double* pq = rz + 2 * L;
+    double* rr = rz + 3 * L;
+    double* beta = rz + 4 * L;
     double* part = h->partial.as<double>();
     int32_t* active = h->act.as<int32_t>();
     const int64_t* rp = A->row_ptr.as<int64_t>();
     const int32_t* ci = A->col_idx.as<int32_t>();
     const double* av = h->vals.as<double>();
+    auto dots = [&](const double* u, int64_t ldu, const double* v, int64_t ldv, double* out) {
+      if (sg)
+        cae::launch_seg_dots(*sg, nrhs, u, ldu, v, ldv, part, out, s);
+      else
+        cae::launch_dots(n, nrhs, u, ldu, v, ldv, part, out, s);
+    };
 
     for (int k = 0; k < nrhs; ++k) cae::launch_fill(x + k * ldx, n, 0.0, s);
     cae::launch_copy_cols(n, nrhs, b, ldb, r, n, s);
-    std::vector<double> bn(nrhs), hrr(nrhs);
-    cae::launch_dots(n, nrhs, b, ldb, b, ldb, part, rr, s);
-    HIPCHK(hipMemcpyAsync(bn.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> bn(L), hrr(L);
+    dots(b, ldb, b, ldb, rr);
+    HIPCHK(hipMemcpyAsync(bn.data(), rr, L * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<int32_t> hact(nrhs);
+    std::vector<int32_t> hact(L);
     int nact = 0;
-    for (int k = 0; k < nrhs; ++k) {
+    for (int k = 0; k < L; ++k) {
       bn[k] = std::sqrt(bn[k]);
       hact[k] = bn[k] > 0.0 ? 1 : 0;
       nact += hact[k];
       iters[k] = 0;
     }
-    HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(active, hact.data(), L * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (nact > 0) {
       solver_apply(h, nrhs, r, n, z, n);
       cae::launch_copy_cols(n, nrhs, z, n, p, n, s);
-      cae::launch_dots(n, nrhs, r, n, z, n, part, rz, s);
+      dots(r, n, z, n, rz);
     }
     int it = 0;
     while (nact > 0 && it < maxit) {
       cae::launch_spmv(n, rp, ci, av, nrhs, p, n, q, n, s);
-      cae::launch_dots(n, nrhs, p, n, q, n, part, pq, s);
-      cae::launch_pcg_xr(n, nrhs, rz, pq, active, x, ldx, p, r, q, s);
+      dots(p, n, q, n, pq);
+      if (sg)
+        cae::launch_seg_pcg_xr(*sg, n, nrhs, rz, pq, active, x, ldx, p, r, q, s);
+      else
+        cae::launch_pcg_xr(n, nrhs, rz, pq, active, x, ldx, p, r, q, s);
       ++it;
-      cae::launch_dots(n, nrhs, r, n, r, n, part, rr, s);
-      HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      dots(r, n, r, n, rr);
+      HIPCHK(hipMemcpyAsync(hrr.data(), rr, L * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int k = 0; k < nrhs; ++k) {
+      for (int k = 0; k < L; ++k) {
         if (hact[k] && std::sqrt(hrr[k]) <= rtol * bn[k]) {
           hact[k] = 0;
           iters[k] = it;
@@ -1399,25 +1596,62 @@ static int cae_pcg_solve_impl(cae_handle_t h, int32_t nrhs, const double* b, int
         }
       }
       if (nact == 0) break;
-      HIPCHK(hipMemcpyAsync(active, hact.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(active, hact.data(), L * sizeof(int32_t), hipMemcpyHostToDevice, s));
       solver_apply(h, nrhs, r, n, z, n);
-      cae::launch_dots(n, nrhs, r, n, z, n, part, rz_new, s);
-      cae::launch_pcg_p(n, nrhs, rz, rz_new, active, z, p, beta, s);
+      dots(r, n, z, n, rz_new);
+      if (sg)
+        cae::launch_seg_pcg_p(*sg, n, nrhs, rz, rz_new, active, z, p, beta, s);
+      else
+        cae::launch_pcg_p(n, nrhs, rz, rz_new, active, z, p, beta, s);
     }
-    for (int k = 0; k < nrhs; ++k)
+    for (int k = 0; k < L; ++k)
       if (hact[k]) iters[k] = it;
     // true residual
     cae::launch_spmv(n, rp, ci, av, nrhs, x, ldx, q, n, s);
     cae::launch_residual(n, nrhs, b, ldb, q, s);
-    cae::launch_dots(n, nrhs, q, n, q, n, part, rr, s);
-    HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    dots(q, n, q, n, rr);
+    HIPCHK(hipMemcpyAsync(hrr.data(), rr, L * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (int k = 0; k < nrhs; ++k) relres[k] = bn[k] > 0 ? std::sqrt(hrr[k]) / bn[k] : 0.0;
+    for (int k = 0; k < L; ++k) relres[k] = bn[k] > 0 ? std::sqrt(hrr[k]) / bn[k] : 0.0;
     if (nact > 0) return fail(CAE_ENOCONV, "PCG did not converge within maxit");
   } catch (const HipError& e) {
     return fail(CAE_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    return fail(CAE_ENOMEM, "host allocation failed");
   }
   return CAE_OK;
+}
+
+static int cae_pcg_solve_impl(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
+                  int32_t maxit, int32_t* iters, double* relres) {
+  if (h) g_cur_stream = h->stream;
+  if (check_handle(h)) return CAE_EINVAL;
+  const int64_t n = h->an->a.n;
+  if (nrhs <= 0 || !b || !x || ldb < n || ldx < n || !iters || !relres || maxit < 0 || !(rtol >= 0))
+    return fail(CAE_EINVAL, "bad PCG arguments");
+  return pcg_lanes(h, nullptr, nrhs, b, ldb, x, ldx, rtol, maxit, iters, relres);
+}
+
+static int cae_pcg_solve_batched_impl(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                                      int64_t ldx, double rtol, int32_t maxit, int32_t* iters, double* relres) {
+  if (h) g_cur_stream = h->stream;
+  if (check_handle(h)) return CAE_EINVAL;
+  if (h->sg.nseg == 0) return fail(CAE_EINVAL, "the handle was not made from a batch of problems");
+  const int64_t n = h->an->a.n;
+  if (nrhs <= 0 || !b || !x || ldb < n || ldx < n || !iters || !relres || maxit < 0 || !(rtol >= 0))
+    return fail(CAE_EINVAL, "bad PCG arguments");
+  const int nseg = h->sg.nseg;
+  if ((int64_t)nrhs * nseg > (int64_t)1 << 26) return fail(CAE_EINVAL, "too many (problem, column) pairs");
+  std::vector<int32_t> it((size_t)nrhs * nseg);
+  std::vector<double> rel((size_t)nrhs * nseg);
+  const int rc = pcg_lanes(h, &h->sg, nrhs, b, ldb, x, ldx, rtol, maxit, it.data(), rel.data());
+  if (rc == CAE_OK || rc == CAE_ENOCONV)
+    for (int t = 0; t < nseg; ++t)
+      for (int k = 0; k < nrhs; ++k) {
+        iters[(size_t)t * nrhs + k] = it[(size_t)k * nseg + t];
+        relres[(size_t)t * nrhs + k] = rel[(size_t)k * nseg + t];
+      }
+  return rc;
 }
 
 static int cae_minres_solve_impl(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
@@ -1734,6 +1968,11 @@ int cae_apply_factor(cae_handle_t h, int32_t nrhs, const double* x, int64_t ldx,
 int cae_pcg_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, double rtol,
                   int32_t maxit, int32_t* iters, double* relres) {
   return keep_error(h, cae_pcg_solve_impl(h, nrhs, b, ldb, x, ldx, rtol, maxit, iters, relres));
+}
+
+int cae_pcg_solve_batched(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                          double rtol, int32_t maxit, int32_t* iters, double* relres) {
+  return keep_error(h, cae_pcg_solve_batched_impl(h, nrhs, b, ldb, x, ldx, rtol, maxit, iters, relres));
 }
 
 int cae_minres_solve(cae_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,

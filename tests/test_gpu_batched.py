@@ -8,8 +8,8 @@ of up to 215 unknowns, whose compression decides the kept subspace from the
 Gram matrix with the pivots stopped at a trailing energy of (theta/32)^2, a
 perturbation of the kept subspaces of that order over the spectral gap
 (measured 1.1e-8)); every problem's PCG
-residual reaches the tolerance, and the autotuner picks and caches a patch
-shape."""
+residual reaches the tolerance in an independent PCG per problem, and the
+autotuner picks and caches a patch shape."""
 import json
 
 import numpy as np
@@ -46,10 +46,10 @@ def test_batch_equals_individual_factorizations():
     # only adds exact eliminations of single-block problems
     bt = batched.Batch(mats, dims, patches, eps, precision=cae.FP64, order=cae.ORDER_PAPER, coarse_max_dim=0)
     bt.factorize()
-    N = bt.A.shape[0]
+    N = int(bt.row_off[-1])
     X = np.random.default_rng(12345).standard_normal((N, 3))
     MX = bt.factor.multiply(torch.from_numpy(np.ascontiguousarray(X.T)).cuda()).cpu().numpy().T
-    tau = bt.A.diagonal().max()
+    tau = max(A.diagonal().max() for A in mats)
     for t, (A, d, patch) in enumerate(zip(mats, dims, patches)):
         s = slice(bt.row_off[t], bt.row_off[t + 1])
         perm, bp, co = cae.grid_order(d, patch)
@@ -71,8 +71,65 @@ def test_batch_equals_individual_factorizations():
         assert err <= (1e-10 if bmax <= 128 else 5e-8), (t, err)
     B = torch.from_numpy(np.ascontiguousarray(problems.rhs_normal(N, 4, seed=1).T)).cuda()
     x, it, rel = bt.pcg(B, rtol=1e-10)
+    assert it.shape == (len(mats), 4)
     res = bt.problem_residuals(B, x)
-    assert res.max() <= 1e-8, res.max()
+    # every (problem, column) stops at its own residual: the true residual
+    # over the problem's rows is at the tolerance (up to the gap between the
+    # recurrence and the true residual)
+    assert res.max() <= 2e-10, res.max()
+    assert np.allclose(rel, res, rtol=1e-3, atol=1e-14)
+    bt.close()
+
+
+def test_batched_pcg_runs_each_problem_as_alone():
+    """cae_factor_batched equals the numeric factorization of the batched
+    analysis with stacked values (M X bitwise), and cae_pcg_solve_batched
+    gives every problem the iteration count of a PCG on that problem alone
+    with its own factor (the joint factor's blocks equal the individual
+    factors to rounding; the count may move by one at the stopping test)."""
+    cae = _cae()
+    from paper_1603_09133_amd import batched
+    spec = [(0, 48, (8, 8)), (1, 16, (4, 4, 4)), (0, 20, (4, 4)), (1, 12, (2, 2, 4)), (0, 64, (8, 8))]
+    mats, dims, patches = [], [], []
+    for kind, side, patch in spec:
+        d = (side, side) if kind == 0 else (side,) * 3
+        mats.append(problems.laplacian(d).tocsr())
+        dims.append(d)
+        patches.append(patch)
+    eps = 1e-4
+    bt = batched.Batch(mats, dims, patches, eps, precision=cae.FP64)
+    f = bt.factorize()
+    N = int(bt.row_off[-1])
+    an = batched.analyze(mats, dims, patches)
+    g = cae.Factor(an, batched.stacked_values(mats), eps, precision=cae.FP64)
+    X = torch.from_numpy(np.random.default_rng(7).standard_normal((2, N))).cuda()
+    assert torch.equal(f.multiply(X), g.multiply(X))
+    g.close()
+    B = torch.from_numpy(np.ascontiguousarray(problems.rhs_normal(N, 3, seed=5).T)).cuda()
+    x, it, rel = bt.pcg(B, rtol=1e-8)
+    tau = max(A.diagonal().max() for A in mats)
+    for t, (A, d, patch) in enumerate(zip(mats, dims, patches)):
+        s = slice(bt.row_off[t], bt.row_off[t + 1])
+        perm, bp, co = cae.grid_order(d, patch)
+        ip, ix, dv = problems.to_csr_arrays(A)
+        a1 = cae.Analysis(ip, ix, perm, bp, co)
+        f1 = cae.Factor(a1, torch.from_numpy(dv).cuda(), eps * tau / A.diagonal().max(), precision=cae.FP64)
+        _, it1, rel1 = f1.pcg(B[:, s].contiguous(), rtol=1e-8)
+        print(f"problem {t} {d}: batched {it[t].tolist()} alone {it1.tolist()}")
+        assert np.all(np.abs(it[t] - it1) <= 1), (t, it[t], it1)
+        assert rel[t].max() <= 1.001e-8
+        f1.close()
+        a1.close()
+    # a handle of one matrix has no problems to run apart
+    ip, ix, dv = problems.to_csr_arrays(mats[0])
+    perm, bp, co = cae.grid_order(dims[0], patches[0])
+    a1 = cae.Analysis(ip, ix, perm, bp, co)
+    f1 = cae.Factor(a1, torch.from_numpy(dv).cuda(), eps, precision=cae.FP64)
+    with pytest.raises(cae.CAEError, match="batch"):
+        f1.row_off = np.array([0, mats[0].shape[0]])
+        f1.pcg_batched(B[:, :mats[0].shape[0]].contiguous())
+    f1.close()
+    a1.close()
     bt.close()
 
 
