@@ -97,11 +97,14 @@ def test_batched_pcg_runs_each_problem_as_alone():
         dims.append(d)
         patches.append(patch)
     eps = 1e-4
-    bt = batched.Batch(mats, dims, patches, eps, precision=cae.FP64)
+    # every level down to one block in the block order of Algorithm 2, alone
+    # and in the batch, so both see the same compressions
+    kw = dict(precision=cae.FP64, coarse_max_dim=0)
+    bt = batched.Batch(mats, dims, patches, eps, order=cae.ORDER_PAPER, **kw)
     f = bt.factorize()
     N = int(bt.row_off[-1])
-    an = batched.analyze(mats, dims, patches)
-    g = cae.Factor(an, batched.stacked_values(mats), eps, precision=cae.FP64)
+    an = batched.analyze(mats, dims, patches, order=cae.ORDER_PAPER)
+    g = cae.Factor(an, batched.stacked_values(mats), eps, **kw)
     X = torch.from_numpy(np.random.default_rng(7).standard_normal((2, N))).cuda()
     assert torch.equal(f.multiply(X), g.multiply(X))
     g.close()
@@ -112,8 +115,8 @@ def test_batched_pcg_runs_each_problem_as_alone():
         s = slice(bt.row_off[t], bt.row_off[t + 1])
         perm, bp, co = cae.grid_order(d, patch)
         ip, ix, dv = problems.to_csr_arrays(A)
-        a1 = cae.Analysis(ip, ix, perm, bp, co)
-        f1 = cae.Factor(a1, torch.from_numpy(dv).cuda(), eps * tau / A.diagonal().max(), precision=cae.FP64)
+        a1 = cae.Analysis(ip, ix, perm, bp, co, order=cae.ORDER_PAPER)
+        f1 = cae.Factor(a1, torch.from_numpy(dv).cuda(), eps * tau / A.diagonal().max(), **kw)
         _, it1, rel1 = f1.pcg(B[:, s].contiguous(), rtol=1e-8)
         print(f"problem {t} {d}: batched {it[t].tolist()} alone {it1.tolist()}")
         assert np.all(np.abs(it[t] - it1) <= 1), (t, it[t], it1)
