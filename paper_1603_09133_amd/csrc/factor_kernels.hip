@@ -2040,9 +2040,12 @@ __device__ int jacobi_rows_wave(double* R, int ld, const int* row, int ma, doubl
 
 // The same rotations by the four wavefronts of a workgroup: the pairs of a
 // round are split over the wavefronts, one workgroup barrier per round (every
-// thread of the workgroup must call it).  Returns the number of sweeps.
+// thread of the workgroup must call it).  Only the first ncol coordinates of a
+// row are touched (the rest are zero; ncol a multiple of LP, so the skip is
+// uniform over the lanes).  Returns the number of sweeps.
 template <int LP, int BM>
-__device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double negl, double aerr, double tol) {
+__device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double negl, double aerr, double tol,
+                              int ncol = BM) {
   constexpr int NC = BM / LP, PPASS = 64 / LP;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, sub = lane % LP;
   const int mm = ma + (ma & 1), np = mm / 2, m1 = mm - 1;
@@ -2081,6 +2084,7 @@ __device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double 
           yr = R + row[q] * ld;
 #pragma unroll
           for (int u = 0; u < NC; ++u) {
+            if (LP * u >= ncol) break;
             x[u] = xr[sub + LP * u];
             y[u] = yr[sub + LP * u];
             a += x[u] * x[u];
@@ -2099,6 +2103,7 @@ __device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double 
           const double cs = rsqrt_nr(1.0 + tt * tt), sn = cs * tt;
 #pragma unroll
           for (int u = 0; u < NC; ++u) {
+            if (LP * u >= ncol) break;
             xr[sub + LP * u] = cs * x[u] - sn * y[u];
             yr[sub + LP * u] = sn * x[u] + cs * y[u];
           }
@@ -3767,15 +3772,19 @@ constexpr int BG_SLD = BG_MA + 4;   // row stride of S in LDS
 int64_t bg_stride(int bmax) { return (int64_t)4 * bmax * bmax + (int64_t)BG_MA * bmax; }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0) {
-  const Step st = A.steps[s0 + blockIdx.x];
+__global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0, int32_t ntile) {
+  // the ntile tile pairs of one step on one XCD, dispatched together: the
+  // strips of F_i they share are fetched from HBM into that XCD's L2 once
+  const int64_t lg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int sx = (int)(lg / ntile);
+  const Step st = A.steps[s0 + sx];
   const int i = st.blk;
   const int b = A.bsz[i];
   if (b < BG_MIN || b > BG_MAXB || st.nfar == 0) return;
   if (A.need_exact && !A.need_exact[i]) return;
   // tile pair (ti <= tj) of this workgroup
   const int nt = (b + 63) / 64;
-  int t = blockIdx.y, ti = 0;
+  int t = (int)(lg % ntile), ti = 0;
   while (ti < nt && t >= nt - ti) {
     t -= nt - ti;
     ++ti;
@@ -3784,7 +3793,7 @@ __global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0) {
   const int tj = ti + t;
   const int ra = 64 * ti, rb = 64 * tj;
   const int na = min(64, b - ra), nb = min(64, b - rb);
-  double* G = A.big + (int64_t)blockIdx.x * A.big_stride;
+  double* G = A.big + (int64_t)sx * A.big_stride;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Sa = reinterpret_cast<T*>(smem_raw);   // Sa[k][a] = F(ra + a, column k of the chunk)
   T* Sb = Sa + 64 * TLD;                     // Sb[k][a] = F(rb + a, column k of the chunk)
@@ -3907,6 +3916,36 @@ __device__ int gram_pivoted_chol(const double* G, double* X, int ldx, int b, dou
   return k;
 }
 
+// Cholesky S = L L^T of a symmetric n x n matrix held in LDS (row stride ld)
+// by the workgroup, right-looking: step k updates the trailing lower triangle
+// with the unscaled column k, and every column is scaled once at the end
+// (dinv[k] = 1 / L(k, k)); the strict upper triangle is cleared.  Returns
+// false, with S partly overwritten, when a pivot is not above n * eps times
+// the largest diagonal entry (S numerically semidefinite).
+__device__ bool chol_lds(double* S, int ld, int n, double* dinv) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int k = 0; k < n; ++k) dmax = fmax(dmax, S[k * ld + k]);
+  const double dmin = (double)n * DBL_EPSILON * dmax;
+  for (int k = 0; k < n; ++k) {
+    const double d = S[k * ld + k];   // the same value in every thread
+    if (!(d > dmin)) return false;
+    const double id = 1.0 / d;
+    for (int i = k + 1 + (tid >> 4); i < n; i += NT / 16) {
+      const double sik = S[i * ld + k] * id;
+      for (int j = k + 1 + (tid & 15); j <= i; j += 16) S[i * ld + j] -= sik * S[j * ld + k];
+    }
+    if (tid == 0) dinv[k] = 1.0 / sqrt(d);
+    __syncthreads();
+  }
+  for (int i = tid >> 4; i < n; i += NT / 16)
+    for (int j = tid & 15; j < n; j += 16)
+      S[i * ld + j] = j < i ? S[i * ld + j] * dinv[j] : (j == i ? 1.0 / dinv[i] : 0.0);
+  __syncthreads();
+  return true;
+}
+
 template <typename T>
 size_t work_bg_eig() {
   return (size_t)BG_MA * BG_SLD * sizeof(double) + (size_t)BG_MAXB * sizeof(double) +
@@ -4008,26 +4047,46 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
     __syncthreads();   // rd free
   }
 
-  // ---- 2. S = X X^T (ma x ma) on the matrix cores, through V's storage ------
+  // ---- 2. S = X X^T (ma x ma) on the matrix cores, through V's storage, and
+  // its Cholesky factor L in LDS (a copy of L in W's storage) ----------------
   wg_gemm_f64<double>(X, b, false, X, b, true, V, ma, ma, ma, b, true, 1.0, 0.0, nullptr, Sa, Sb, rd);
-  for (int e = tid; e < BG_MA * BG_MA; e += NT) {
-    const int p = e / BG_MA, q = e % BG_MA;
-    S[p * BG_SLD + q] = (p < ma && q < ma) ? V[p * ma + q] : 0.0;
-  }
+  auto load_s = [&]() {
+    for (int e = tid; e < BG_MA * BG_MA; e += NT) {
+      const int p = e / BG_MA, q = e % BG_MA;
+      S[p * BG_SLD + q] = (p < ma && q < ma) ? V[p * ma + q] : 0.0;
+    }
+  };
+  load_s();
   if (tid < BG_MA) rowix[tid] = tid;
+  double* dinv = xp;                         // 1 / L(k, k)
+  double* Lg = V + (int64_t)b * b;           // L, row-major ma x ma
+  // X is the R factor of a pivoted QR of F^T (its Gram matrix is G), and L
+  // the triangular factor of a second QR of it, R = L Q: one-sided Jacobi on
+  // the rows of L (singular values sigma_k(F)) converges in a few sweeps,
+  // where the rows of S (sigma^4 spread) took about a dozen.  A numerically
+  // semidefinite S keeps the Jacobi on its own rows.
+  const bool lpath = chol_lds(S, BG_SLD, ma, dinv);
+  if (lpath) {
+    for (int e = tid; e < ma * ma; e += NT) Lg[e] = S[(e / ma) * BG_SLD + e % ma];
+    __threadfence();
+  } else {
+    __syncthreads();
+    load_s();
+  }
   __syncthreads();
   const int64_t t_s = clock64();
 
-  // ---- 3. one-sided Jacobi on the rows of S (the four wavefronts) -----------
-  // the row norms are lambda = sigma^2: the thresholds of the sigma-scale
-  // tests squared
+  // ---- 3. one-sided Jacobi on the rows of L (or S) by the four wavefronts ---
+  // (the row norms of S are lambda = sigma^2: the thresholds of the
+  // sigma-scale tests squared)
   int nsweep = 0;
   if (ma > 1) {
     const double tol = (double)max(b, 16) * DBL_EPSILON;
+    const double ng = lpath ? negl : negl * negl, ae = lpath ? aerr : aerr * aerr;
     const int np = (ma + 1) / 2;
-    if (np <= 4) nsweep = jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
-    else if (np <= 8) nsweep = jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
-    else nsweep = jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    if (np <= 4) nsweep = jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, ng, ae, tol, (ma + 15) & ~15);
+    else if (np <= 8) nsweep = jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, ng, ae, tol, (ma + 7) & ~7);
+    else nsweep = jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, ng, ae, tol, (ma + 3) & ~3);
   }
   __syncthreads();
   const int64_t t_eig = clock64();
@@ -4039,7 +4098,7 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
       s0 += S[tid * BG_SLD + q] * S[tid * BG_SLD + q];
       s1 += S[tid * BG_SLD + q + 1] * S[tid * BG_SLD + q + 1];
     }
-    sg[tid] = sqrt(s0 + s1);   // lambda_k = sigma_k(F)^2
+    sg[tid] = lpath ? s0 + s1 : sqrt(s0 + s1);   // lambda_k = sigma_k(F)^2
   }
   __syncthreads();
   int cnt = 0;
@@ -4078,11 +4137,31 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   }
   if (tid < ma && posv[tid] < kb) {
     brow[posv[tid]] = tid;
-    // v = X^T w / sigma with w = row / lambda: X^T row * lambda^{-3/2}
+    // v = X^T w / sigma: with w = row / lambda (rows of S) X^T row *
+    // lambda^{-3/2}; with w = L^{-T} row^T (rows of L) X^T w / sigma
     const double l0 = sg[tid];
-    isg[posv[tid]] = l0 > 0.0 ? 1.0 / (l0 * sqrt(l0)) : 0.0;
+    isg[posv[tid]] = l0 > 0.0 ? (lpath ? 1.0 / sqrt(l0) : 1.0 / (l0 * sqrt(l0))) : 0.0;
   }
   __syncthreads();
+  if (lpath) {
+    // the rotated rows z_k = (J L)_k: the eigenvector w_k of S is row k of J,
+    // w_k^T = z_k L^{-1}; L^T w_k = z_k^T by back substitution over the
+    // columns (after step i, z(i) is final and w(i) = z(i) / L(i, i))
+    for (int ii = ma - 1; ii > 0; --ii) {
+      const double* li = Lg + (int64_t)ii * ma;
+      for (int c = tid >> 4; c < kb; c += NT / 16) {
+        double* z = S + brow[c] * BG_SLD;
+        const double wi = z[ii] * dinv[ii];
+        for (int j = tid & 15; j < ii; j += 16) z[j] -= wi * li[j];
+      }
+      __syncthreads();
+    }
+    for (int c = tid >> 4; c < kb; c += NT / 16) {
+      double* z = S + brow[c] * BG_SLD;
+      for (int j = tid & 15; j < ma; j += 16) z[j] *= dinv[j];
+    }
+    __syncthreads();
+  }
 
   // ---- 5. kept directions v_k (b-vectors) ----------------------------------
   for (int t = tid; t < b; t += NT) {
@@ -5507,8 +5586,9 @@ static void compress_pass(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
       // nothing to redo there: its flagged big steps go to the generic kernel)
       const int nt = (std::min(bmax, BG_MAXB) + 63) / 64;
       if (!retry) {
-        hipLaunchKernelGGL(k_bg_gram<T>, dim3(ns, nt * (nt + 1) / 2), dim3(NT), (size_t)2 * 64 * TLD * sizeof(T),
-                           stream, A, w.s0);
+        const int ntile = nt * (nt + 1) / 2;
+        hipLaunchKernelGGL(k_bg_gram<T>, dim3(ns * ntile), dim3(NT), (size_t)2 * 64 * TLD * sizeof(T), stream, A,
+                           w.s0, ntile);
         hipLaunchKernelGGL(k_bg_eig<T>, dim3(ns), dim3(NT), work_bg_eig<T>(), stream, A, w.s0);
         hipLaunchKernelGGL(k_bg_cert<T>, dim3(ns), dim3(NT), (size_t)2 * 64 * TLD * sizeof(double), stream, A, w.s0);
         hipLaunchKernelGGL(k_bg_full<T>, dim3(ns), dim3(NT), 0, stream, A, w.s0);
