@@ -2040,12 +2040,9 @@ __device__ int jacobi_rows_wave(double* R, int ld, const int* row, int ma, doubl
 
 // The same rotations by the four wavefronts of a workgroup: the pairs of a
 // round are split over the wavefronts, one workgroup barrier per round (every
-// thread of the workgroup must call it).  Only the first ncol coordinates of a
-// row are touched (the rest are zero; ncol a multiple of LP, so the skip is
-// uniform over the lanes).  Returns the number of sweeps.
+// thread of the workgroup must call it).  Returns the number of sweeps.
 template <int LP, int BM>
-__device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double negl, double aerr, double tol,
-                              int ncol = BM) {
+__device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double negl, double aerr, double tol) {
   constexpr int NC = BM / LP, PPASS = 64 / LP;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, sub = lane % LP;
   const int mm = ma + (ma & 1), np = mm / 2, m1 = mm - 1;
@@ -2084,7 +2081,6 @@ __device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double 
           yr = R + row[q] * ld;
 #pragma unroll
           for (int u = 0; u < NC; ++u) {
-            if (LP * u >= ncol) break;
             x[u] = xr[sub + LP * u];
             y[u] = yr[sub + LP * u];
             a += x[u] * x[u];
@@ -2103,7 +2099,6 @@ __device__ int jacobi_rows_wg(double* R, int ld, const int* row, int ma, double 
           const double cs = rsqrt_nr(1.0 + tt * tt), sn = cs * tt;
 #pragma unroll
           for (int u = 0; u < NC; ++u) {
-            if (LP * u >= ncol) break;
             xr[sub + LP * u] = cs * x[u] - sn * y[u];
             yr[sub + LP * u] = sn * x[u] + cs * y[u];
           }
@@ -3916,36 +3911,6 @@ __device__ int gram_pivoted_chol(const double* G, double* X, int ldx, int b, dou
   return k;
 }
 
-// Cholesky S = L L^T of a symmetric n x n matrix held in LDS (row stride ld)
-// by the workgroup, right-looking: step k updates the trailing lower triangle
-// with the unscaled column k, and every column is scaled once at the end
-// (dinv[k] = 1 / L(k, k)); the strict upper triangle is cleared.  Returns
-// false, with S partly overwritten, when a pivot is not above n * eps times
-// the largest diagonal entry (S numerically semidefinite).
-__device__ bool chol_lds(double* S, int ld, int n, double* dinv) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  double dmax = 0.0;
-  for (int k = 0; k < n; ++k) dmax = fmax(dmax, S[k * ld + k]);
-  const double dmin = (double)n * DBL_EPSILON * dmax;
-  for (int k = 0; k < n; ++k) {
-    const double d = S[k * ld + k];   // the same value in every thread
-    if (!(d > dmin)) return false;
-    const double id = 1.0 / d;
-    for (int i = k + 1 + (tid >> 4); i < n; i += NT / 16) {
-      const double sik = S[i * ld + k] * id;
-      for (int j = k + 1 + (tid & 15); j <= i; j += 16) S[i * ld + j] -= sik * S[j * ld + k];
-    }
-    if (tid == 0) dinv[k] = 1.0 / sqrt(d);
-    __syncthreads();
-  }
-  for (int i = tid >> 4; i < n; i += NT / 16)
-    for (int j = tid & 15; j < n; j += 16)
-      S[i * ld + j] = j < i ? S[i * ld + j] * dinv[j] : (j == i ? 1.0 / dinv[i] : 0.0);
-  __syncthreads();
-  return true;
-}
-
 template <typename T>
 size_t work_bg_eig() {
   return (size_t)BG_MA * BG_SLD * sizeof(double) + (size_t)BG_MAXB * sizeof(double) +
@@ -4047,46 +4012,26 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
     __syncthreads();   // rd free
   }
 
-  // ---- 2. S = X X^T (ma x ma) on the matrix cores, through V's storage, and
-  // its Cholesky factor L in LDS (a copy of L in W's storage) ----------------
+  // ---- 2. S = X X^T (ma x ma) on the matrix cores, through V's storage ------
   wg_gemm_f64<double>(X, b, false, X, b, true, V, ma, ma, ma, b, true, 1.0, 0.0, nullptr, Sa, Sb, rd);
-  auto load_s = [&]() {
-    for (int e = tid; e < BG_MA * BG_MA; e += NT) {
-      const int p = e / BG_MA, q = e % BG_MA;
-      S[p * BG_SLD + q] = (p < ma && q < ma) ? V[p * ma + q] : 0.0;
-    }
-  };
-  load_s();
-  if (tid < BG_MA) rowix[tid] = tid;
-  double* dinv = xp;                         // 1 / L(k, k)
-  double* Lg = V + (int64_t)b * b;           // L, row-major ma x ma
-  // X is the R factor of a pivoted QR of F^T (its Gram matrix is G), and L
-  // the triangular factor of a second QR of it, R = L Q: one-sided Jacobi on
-  // the rows of L (singular values sigma_k(F)) converges in a few sweeps,
-  // where the rows of S (sigma^4 spread) took about a dozen.  A numerically
-  // semidefinite S keeps the Jacobi on its own rows.
-  const bool lpath = chol_lds(S, BG_SLD, ma, dinv);
-  if (lpath) {
-    for (int e = tid; e < ma * ma; e += NT) Lg[e] = S[(e / ma) * BG_SLD + e % ma];
-    __threadfence();
-  } else {
-    __syncthreads();
-    load_s();
+  for (int e = tid; e < BG_MA * BG_MA; e += NT) {
+    const int p = e / BG_MA, q = e % BG_MA;
+    S[p * BG_SLD + q] = (p < ma && q < ma) ? V[p * ma + q] : 0.0;
   }
+  if (tid < BG_MA) rowix[tid] = tid;
   __syncthreads();
   const int64_t t_s = clock64();
 
-  // ---- 3. one-sided Jacobi on the rows of L (or S) by the four wavefronts ---
-  // (the row norms of S are lambda = sigma^2: the thresholds of the
-  // sigma-scale tests squared)
+  // ---- 3. one-sided Jacobi on the rows of S (the four wavefronts) -----------
+  // the row norms are lambda = sigma^2: the thresholds of the sigma-scale
+  // tests squared
   int nsweep = 0;
   if (ma > 1) {
     const double tol = (double)max(b, 16) * DBL_EPSILON;
-    const double ng = lpath ? negl : negl * negl, ae = lpath ? aerr : aerr * aerr;
     const int np = (ma + 1) / 2;
-    if (np <= 4) nsweep = jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, ng, ae, tol, (ma + 15) & ~15);
-    else if (np <= 8) nsweep = jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, ng, ae, tol, (ma + 7) & ~7);
-    else nsweep = jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, ng, ae, tol, (ma + 3) & ~3);
+    if (np <= 4) nsweep = jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else if (np <= 8) nsweep = jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else nsweep = jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
   }
   __syncthreads();
   const int64_t t_eig = clock64();
@@ -4098,7 +4043,7 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
       s0 += S[tid * BG_SLD + q] * S[tid * BG_SLD + q];
       s1 += S[tid * BG_SLD + q + 1] * S[tid * BG_SLD + q + 1];
     }
-    sg[tid] = lpath ? s0 + s1 : sqrt(s0 + s1);   // lambda_k = sigma_k(F)^2
+    sg[tid] = sqrt(s0 + s1);   // lambda_k = sigma_k(F)^2
   }
   __syncthreads();
   int cnt = 0;
@@ -4137,31 +4082,11 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
   }
   if (tid < ma && posv[tid] < kb) {
     brow[posv[tid]] = tid;
-    // v = X^T w / sigma: with w = row / lambda (rows of S) X^T row *
-    // lambda^{-3/2}; with w = L^{-T} row^T (rows of L) X^T w / sigma
+    // v = X^T w / sigma with w = row / lambda: X^T row * lambda^{-3/2}
     const double l0 = sg[tid];
-    isg[posv[tid]] = l0 > 0.0 ? (lpath ? 1.0 / sqrt(l0) : 1.0 / (l0 * sqrt(l0))) : 0.0;
+    isg[posv[tid]] = l0 > 0.0 ? 1.0 / (l0 * sqrt(l0)) : 0.0;
   }
   __syncthreads();
-  if (lpath) {
-    // the rotated rows z_k = (J L)_k: the eigenvector w_k of S is row k of J,
-    // w_k^T = z_k L^{-1}; L^T w_k = z_k^T by back substitution over the
-    // columns (after step i, z(i) is final and w(i) = z(i) / L(i, i))
-    for (int ii = ma - 1; ii > 0; --ii) {
-      const double* li = Lg + (int64_t)ii * ma;
-      for (int c = tid >> 4; c < kb; c += NT / 16) {
-        double* z = S + brow[c] * BG_SLD;
-        const double wi = z[ii] * dinv[ii];
-        for (int j = tid & 15; j < ii; j += 16) z[j] -= wi * li[j];
-      }
-      __syncthreads();
-    }
-    for (int c = tid >> 4; c < kb; c += NT / 16) {
-      double* z = S + brow[c] * BG_SLD;
-      for (int j = tid & 15; j < ma; j += 16) z[j] *= dinv[j];
-    }
-    __syncthreads();
-  }
 
   // ---- 5. kept directions v_k (b-vectors) ----------------------------------
   for (int t = tid; t < b; t += NT) {
@@ -5094,89 +5019,65 @@ __global__ __launch_bounds__(NT) void k_rot_big(LevelArgs<T> A, int32_t it0) {
   }
 }
 
-// D_i <- U_i^T D_i U_i for big steps, stored exactly symmetric: T1 = U^T D
-// into the step's FP64 scratch, then D = T1 U by column strips of U, the
-// entries (a, c) with a >= c written to both triangles.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_rot_big_diag(LevelArgs<T> A, int32_t s0) {
-  const Step st = A.steps[s0 + blockIdx.x];
+// D_i <- U_i^T D_i U_i for big steps, stored exactly symmetric, in two
+// launches of one workgroup per (step, column strip), the strips of one step
+// on one XCD: PHASE 0 T1 = U^T D (a strip of D's columns) into the step's FP64
+// scratch; PHASE 1 D = T1 U (a strip of U's columns), the entries (a, c) with
+// a >= c written to both triangles (the strip that holds c writes both, so the
+// strips write disjoint entries).
+template <typename T, int PHASE>
+__global__ __launch_bounds__(NT) void k_rot_big_diag(LevelArgs<T> A, int32_t s0, int32_t nstrip) {
+  constexpr int SW = Strip<T>::SW, LD = Strip<T>::LD, NTJ = Strip<T>::NTJ;
+  const int64_t lg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int sx = (int)(lg / nstrip), c0 = (int)(lg % nstrip) * SW;
+  const Step st = A.steps[s0 + sx];
   if (st.nfar == 0) return;   // U_i = I
   const int i = st.blk;
   const int b = A.bsz[i];
-  if (b <= 64 || b > BG_MAXB) return;
+  if (b <= 64 || b > BG_MAXB || c0 >= b) return;
   T* D = A.arena + A.slot_off[i];
   const T* Ug = A.U + A.u_off[i];
-  double* T1 = A.big + (int64_t)blockIdx.x * A.big_stride;   // b x b
+  double* T1 = A.big + (int64_t)sx * A.big_stride;   // b x b
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* X = reinterpret_cast<T*>(smem_raw);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, fr = lane & 15, fk = lane >> 4;
   const int b4 = (b + 3) & ~3;
-  constexpr int SW = Strip<T>::SW, LD = Strip<T>::LD, NTJ = Strip<T>::NTJ;
-  // T1 = U^T D, column strips of D
-  for (int c0 = 0; c0 < b; c0 += SW) {
-    const int tc = min(SW, b - c0);
-    __syncthreads();
-    load_strip(X, D, 0, b, b, 0, b, c0, tc);
-    __syncthreads();
-    for (int rb = wv; 16 * rb < b; rb += 4) {
-      dbl4 acc[NTJ];
+  const int tc = min(SW, b - c0);
+  load_strip(X, PHASE == 0 ? (const T*)D : Ug, 0, b, b, 0, b, c0, tc);
+  __syncthreads();
+  for (int rb = wv; 16 * rb < b; rb += 4) {
+    if (PHASE == 1 && 16 * rb + 15 < c0) continue;   // a block entirely above the diagonal of this strip
+    dbl4 acc[NTJ];
 #pragma unroll
-      for (int tj = 0; tj < NTJ; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
-      const int row = 16 * rb + fr;
+    for (int tj = 0; tj < NTJ; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int row = 16 * rb + fr;
 #pragma unroll 4
-      for (int k0 = 0; k0 < b4; k0 += 4) {
-        const int k = k0 + fk;
-        const double av = (k < b && row < b) ? (double)Ug[(int64_t)k * b + row] : 0.0;
-        double bv[NTJ];
+    for (int k0 = 0; k0 < b4; k0 += 4) {
+      const int k = k0 + fk;
+      double av;
+      if (PHASE == 0)
+        av = (k < b && row < b) ? (double)Ug[(int64_t)k * b + row] : 0.0;   // U^T
+      else
+        av = (k < b && row < b) ? T1[(int64_t)row * b + k] : 0.0;
+      double bv[NTJ];
 #pragma unroll
-        for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[k * LD + 16 * tj + fr];
+      for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[k * LD + 16 * tj + fr];
 #pragma unroll
-        for (int tj = 0; tj < NTJ; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
-      }
-#pragma unroll
-      for (int tj = 0; tj < NTJ; ++tj)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int a = 16 * rb + 4 * j + fk, c = 16 * tj + fr;
-          if (a < b && c < tc) T1[(int64_t)a * b + c0 + c] = acc[tj][j];
-        }
+      for (int tj = 0; tj < NTJ; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
     }
-  }
-  __syncthreads();   // T1 complete (global writes of this workgroup)
-  // D = T1 U, column strips of U; the lower triangle mirrored
-  for (int c0 = 0; c0 < b; c0 += SW) {
-    const int tc = min(SW, b - c0);
-    __syncthreads();
-    load_strip(X, Ug, 0, b, b, 0, b, c0, tc);
-    __syncthreads();
-    for (int rb = wv; 16 * rb < b; rb += 4) {
-      if (16 * rb + 15 < c0) continue;   // a block entirely above the diagonal of this strip
-      dbl4 acc[NTJ];
 #pragma unroll
-      for (int tj = 0; tj < NTJ; ++tj) acc[tj] = dbl4{0.0, 0.0, 0.0, 0.0};
-      const int row = 16 * rb + fr;
-#pragma unroll 4
-      for (int k0 = 0; k0 < b4; k0 += 4) {
-        const int k = k0 + fk;
-        const double av = (k < b && row < b) ? T1[(int64_t)row * b + k] : 0.0;
-        double bv[NTJ];
+    for (int tj = 0; tj < NTJ; ++tj)
 #pragma unroll
-        for (int tj = 0; tj < NTJ; ++tj) bv[tj] = (double)X[k * LD + 16 * tj + fr];
-#pragma unroll
-        for (int tj = 0; tj < NTJ; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
-      }
-#pragma unroll
-      for (int tj = 0; tj < NTJ; ++tj)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int a = 16 * rb + 4 * j + fk, c = c0 + 16 * tj + fr;
-          if (a < b && 16 * tj + fr < tc && a >= c) {
-            const T val = (T)acc[tj][j];
-            D[(int64_t)a * b + c] = val;
-            D[(int64_t)c * b + a] = val;
-          }
+      for (int j = 0; j < 4; ++j) {
+        const int a = 16 * rb + 4 * j + fk, c = c0 + 16 * tj + fr;
+        if (PHASE == 0) {
+          if (a < b && 16 * tj + fr < tc) T1[(int64_t)a * b + c] = acc[tj][j];
+        } else if (a < b && 16 * tj + fr < tc && a >= c) {
+          const T val = (T)acc[tj][j];
+          D[(int64_t)a * b + c] = val;
+          D[(int64_t)c * b + a] = val;
         }
-    }
+      }
   }
 }
 
@@ -5670,7 +5571,10 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
     // workgroups a compute unit holds, which hide the L2 latency of U_i)
     hipLaunchKernelGGL((k_rot_big<T, 1, SW_VIEW>), dim3(w.r1 - w.r0), dim3(NT), (work_strip_big<T, SW_VIEW>(bmax)),
                        stream, B, w.r0);
-    hipLaunchKernelGGL(k_rot_big_diag<T>, dim3(w.s1 - w.s0), dim3(NT), wsb, stream, B, w.s0);
+    const int nstrip = (std::min(bmax, BG_MAXB) + Strip<T>::SW - 1) / Strip<T>::SW;
+    const dim3 gd((unsigned)((w.s1 - w.s0) * nstrip));
+    hipLaunchKernelGGL((k_rot_big_diag<T, 0>), gd, dim3(NT), wsb, stream, B, w.s0, nstrip);
+    hipLaunchKernelGGL((k_rot_big_diag<T, 1>), gd, dim3(NT), wsb, stream, B, w.s0, nstrip);
   }
   if (generic) launch<T>(k_rotate<T>, G, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream, bmax);
   if (A.compensate && w.s1 > w.s0)
