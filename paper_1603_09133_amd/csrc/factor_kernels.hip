@@ -5548,7 +5548,12 @@ void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T
 }
 
 template <typename T>
-void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
+hipError_t launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream,
+                            const SideStream* side) {
+  hipError_t err = hipSuccess;
+  auto keep = [&](hipError_t e) {
+    if (err == hipSuccess) err = e;
+  };
   T* gs = gscratch;
   const size_t wt = work_tiled<T>() * sizeof(T);
   const bool tiled = wt <= max_lds_bytes();
@@ -5564,6 +5569,29 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
   const bool generic = !tiled || (bmax > 64 && (!big || bmax > BG_MAXB));
   B.items = A.rot;
   G.items = A.rot;
+  const size_t wpb = work_potrf_big<T>(bmax);
+  const bool ptiled = tiled && (size_t)PW4_LDS <= max_lds_bytes();
+  const bool pbig = ptiled && bmax > 64 && big && wpb <= max_lds_bytes();
+  // the diagonal blocks of the big steps (U_i^T D_i U_i, then their Cholesky
+  // factor) depend on the compression only, the views' rotation touches no
+  // diagonal block and neither touches the step scratch the other uses: with
+  // a side stream the two run side by side, joined before the triangular
+  // solves (not with compensation, which updates the diagonal blocks, nor when
+  // generic kernels share the scratch)
+  const bool fork = side && side->s && big && pbig && !generic && !A.compensate && w.s1 > w.s0;
+  hipStream_t ds = fork ? side->s : stream;
+  if (fork) {
+    keep(hipEventRecord(side->fork, stream));
+    keep(hipStreamWaitEvent(side->s, side->fork, 0));
+  }
+  if (big && w.s1 > w.s0) {
+    const int nstrip = (std::min(bmax, BG_MAXB) + Strip<T>::SW - 1) / Strip<T>::SW;
+    const dim3 gd((unsigned)((w.s1 - w.s0) * nstrip));
+    hipLaunchKernelGGL((k_rot_big_diag<T, 0>), gd, dim3(NT), wsb, ds, B, w.s0, nstrip);
+    hipLaunchKernelGGL((k_rot_big_diag<T, 1>), gd, dim3(NT), wsb, ds, B, w.s0, nstrip);
+    if (fork) hipLaunchKernelGGL(k_potrf_big<T>, dim3(w.s1 - w.s0), dim3(NT), wpb, ds, B, w.s0);
+  }
+  if (fork) keep(hipEventRecord(side->join, ds));
   if (tiled && w.r1 > w.r0)
     hipLaunchKernelGGL(k_rotate_t<T>, dim3(w.r1 - w.r0), dim3(NT), wt, stream, B, w.r0);
   if (big && w.r1 > w.r0) {
@@ -5571,26 +5599,21 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
     // workgroups a compute unit holds, which hide the L2 latency of U_i)
     hipLaunchKernelGGL((k_rot_big<T, 1, SW_VIEW>), dim3(w.r1 - w.r0), dim3(NT), (work_strip_big<T, SW_VIEW>(bmax)),
                        stream, B, w.r0);
-    const int nstrip = (std::min(bmax, BG_MAXB) + Strip<T>::SW - 1) / Strip<T>::SW;
-    const dim3 gd((unsigned)((w.s1 - w.s0) * nstrip));
-    hipLaunchKernelGGL((k_rot_big_diag<T, 0>), gd, dim3(NT), wsb, stream, B, w.s0, nstrip);
-    hipLaunchKernelGGL((k_rot_big_diag<T, 1>), gd, dim3(NT), wsb, stream, B, w.s0, nstrip);
   }
   if (generic) launch<T>(k_rotate<T>, G, w.r0, w.r1 - w.r0, work_rotate<T>(bmax), gs, stream, bmax);
   if (A.compensate && w.s1 > w.s0)
     hipLaunchKernelGGL(k_compensate<T>, dim3(w.s1 - w.s0), dim3(NT), 0, stream, A, w.s0);
-  const bool ptiled = tiled && (size_t)PW4_LDS <= max_lds_bytes();
   if (ptiled && w.s1 > w.s0)
     hipLaunchKernelGGL(k_potrf_w<T>, dim3(w.s1 - w.s0), dim3(NT), PW4_LDS, stream, B, w.s0);
-  const size_t wpb = work_potrf_big<T>(bmax);
   if (!ptiled) {
     launch<T>(k_potrf<T>, A, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
   } else if (bmax > 64) {
-    const bool pbig = big && wpb <= max_lds_bytes();
-    if (pbig && w.s1 > w.s0) hipLaunchKernelGGL(k_potrf_big<T>, dim3(w.s1 - w.s0), dim3(NT), wpb, stream, B, w.s0);
+    if (pbig && !fork && w.s1 > w.s0)
+      hipLaunchKernelGGL(k_potrf_big<T>, dim3(w.s1 - w.s0), dim3(NT), wpb, stream, B, w.s0);
     if (!pbig || bmax > BG_MAXB)
       launch<T>(k_potrf<T>, pbig ? G : B, w.s0, w.s1 - w.s0, work_potrf<T>(bmax), gs, stream, bmax);
   }
+  if (fork) keep(hipStreamWaitEvent(stream, side->join, 0));
   B.items = A.trsm;
   G.items = A.trsm;
   if (tiled && w.t1 > w.t0)
@@ -5615,6 +5638,7 @@ void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gs
       hipLaunchKernelGGL(k_schur_big<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
   }
   if (generic) launch<T>(k_schur<T>, G, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream, bmax);
+  return err;
 }
 
 template <typename T>
@@ -5681,7 +5705,8 @@ void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double*
   template bool factor_needs_global<T>(int);                                                               \
   template int32_t scratch_group<T>(int);                                                                  \
   template void launch_wave_compress<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);      \
-  template void launch_wave_rest<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);          \
+  template hipError_t launch_wave_rest<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t,         \
+                                         const SideStream*);                                                \
   template void launch_scatter_a0<T>(T*, const double*, const int64_t*, int64_t, hipStream_t);             \
   template void launch_gather_next<T>(const Trans*, int32_t, const T*, const int64_t*, const int32_t*,     \
                                       const int32_t*, const int32_t*, const int32_t*, T*, const int64_t*,  \

@@ -100,8 +100,18 @@ int32_t scratch_group(int bmax);
 // the compression of a wave, then rotation, elimination and Schur update
 template <typename T>
 void launch_wave_compress(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);
+// A second stream for the diagonal blocks of big steps (their rotation and
+// Cholesky run while the main stream rotates the views), with the events that
+// fork it from and join it to the main stream.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+// Returns the first error of the side stream's event calls (kernel launch
+// errors are left to hipGetLastError).
 template <typename T>
-void launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);
+hipError_t launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream,
+                            const SideStream* side = nullptr);
 template <typename T>
 void launch_scatter_a0(T* arena, const double* vals, const int64_t* dst, int64_t nnz, hipStream_t stream);
 void launch_theta(const double* vals, const int64_t* diag_pos, int64_t n, double eps, double* out,

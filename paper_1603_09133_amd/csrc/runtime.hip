@@ -311,10 +311,14 @@ struct cae_factor_s {
   std::string last_err;   // message of the last failing call on this handle
   int32_t ap_next = 0;
   hipStream_t ap_stream = nullptr;   // non-blocking stream the captures run on
+  cae::SideStream side;              // the diagonal blocks of big steps during the factorization
   ~cae_factor_s() {
     for (auto& g : ap)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (ap_stream) (void)hipStreamDestroy(ap_stream);
+    if (side.fork) (void)hipEventDestroy(side.fork);
+    if (side.join) (void)hipEventDestroy(side.join);
+    if (side.s) (void)hipStreamDestroy(side.s);
   }
 };
 
@@ -515,6 +519,12 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       A.big_stride = stride;
       A.bg_cap = h->opt.big_pivot_cap > 0 ? h->opt.big_pivot_cap : 128;
       A.bg_count = h->lcount.as<int32_t>() + 2;
+      if (!h->side.s) {
+        // (default priority, no implicit synchronization with the null stream)
+        HIPCHK(hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming));
+      }
     }
     if (h->opt.rank_mode == CAE_RANK_LEARNED_CAP) {
       N.lwidth.alloc((size_t)L.M * sizeof(int32_t));
@@ -562,7 +572,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       } else {
         cae::launch_wave_compress<T>(A, w, N.bmax, gs, s);
       }
-      cae::launch_wave_rest<T>(A, w, N.bmax, gs, s);
+      HIPCHK(cae::launch_wave_rest<T>(A, w, N.bmax, gs, s, &h->side));
     }
     HIPCHK(hipGetLastError());
     if (dbg_on) {
