@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "factor+PCG time to 1e-8 residual (2D/3D Laplacian); block-op TFLOP/s vs peak"
 FP64_PEAK = 78.6     # MI355X FP64 vector and FP64 matrix-core peak, TFLOP/s
+FP32_PEAK = 157.3    # MI355X FP32 matrix-core (and vector) peak, TFLOP/s
+BF16_PEAK = 2500.0   # MI355X dense BF16 matrix-core peak, TFLOP/s
 
 
 def _log(msg):
@@ -271,7 +273,8 @@ def main():
                  f"PCG iterations max {int(np.max(it))}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = {"factor_ms": [], "compress_ms": 0.0, "compress_launches": 0, "compress_flops": 0.0}
+        res = {"factor_ms": [], "compress_ms": 0.0, "compress_launches": 0, "compress_flops": 0.0,
+               "schur_ms": 0.0, "schur_launches": 0, "schur_flops": 0.0}
         for k in range(steps):
             f, it, rel = step()
             st = f.stats()
@@ -279,6 +282,9 @@ def main():
             res["compress_ms"] += st["compress_ms"]
             res["compress_launches"] += st["compress_launches"]
             res["compress_flops"] += st["compress_flops"]
+            res["schur_ms"] += st["schur_ms"]
+            res["schur_launches"] += st["schur_launches"]
+            res["schur_flops"] += st["schur_flops"]
             if k + 1 < steps:
                 f.close()
             _log(f"{name} timed step {k + 1}/{steps} done")
@@ -373,6 +379,19 @@ def main():
                            "frac": ach / FP64_PEAK, "traffic": _traffic("compress"),
                            "launches_per_step": main_leg["compress_launches"] / args.steps,
                            "avg_launch_us": per_launch_s * 1e6, "algorithmic_flops_per_launch": flops_per_launch}
+    # the Schur updates (a7) the same way: products on the matrix cores in the
+    # configured arithmetic (BF16 inputs with FP32 accumulation, FP32 or FP64)
+    if main_leg["schur_launches"]:
+        per_launch_s = main_leg["schur_ms"] / main_leg["schur_launches"] / 1e3
+        flops_per_launch = main_leg["schur_flops"] / main_leg["schur_launches"]
+        ach = flops_per_launch / per_launch_s / 1e12
+        peak = {cae.FP32_BF16: BF16_PEAK, cae.FP32: FP32_PEAK, cae.FP64: FP64_PEAK}[work["precision"]]
+        out["roofline_schur"] = {
+            "bound": "mfma", "kernel": ("schur: one wave's Schur updates (k_schur_bf16, k_schur_big_bf16, "
+                                        "k_schur_big_bf16w, or the FP32 / FP64 forms)"),
+            "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "launches_per_step": main_leg["schur_launches"] / args.steps, "avg_launch_us": per_launch_s * 1e6,
+            "algorithmic_flops_per_launch": flops_per_launch}
     if not args.no_cpu_baseline and not batch:
         lv1_s = main_leg["level_ms"][0] / 1e3
         out["cpu_baseline"] = _cpu_baseline(work, work["M1"] / lv1_s if lv1_s > 0 else None, args.cpu_steps)

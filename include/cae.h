@@ -401,6 +401,10 @@ typedef struct {
   int32_t big_frobenius;
   int32_t big_certified;
   int32_t big_uncapped;
+  /* with cae_options_t.timing: the Schur updates of every wave (after the
+     triangular solves; their flops are schur_flops) */
+  int32_t schur_launches;
+  double schur_ms;          /* summed device time of those launches */
 } cae_stats_t;
 
 int cae_get_stats(cae_handle_t h, cae_stats_t* s);

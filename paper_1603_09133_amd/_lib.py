@@ -56,7 +56,7 @@ class Stats(C.Structure):
                 ("sketch_rejected", C.c_int32), ("record_rows", C.c_int64), ("rotate_flops", C.c_double),
                 ("elim_flops", C.c_double), ("schur_flops", C.c_double), ("coarse_flops", C.c_double),
                 ("big_untruncated", C.c_int32), ("big_frobenius", C.c_int32), ("big_certified", C.c_int32),
-                ("big_uncapped", C.c_int32)]
+                ("big_uncapped", C.c_int32), ("schur_launches", C.c_int32), ("schur_ms", C.c_double)]
 
 
 _lib = None

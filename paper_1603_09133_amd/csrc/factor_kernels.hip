@@ -5621,6 +5621,22 @@ hipError_t launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax,
   if (big && w.t1 > w.t0)
     hipLaunchKernelGGL((k_trsm_big<T, 1, Strip<T>::SW>), dim3(w.t1 - w.t0), dim3(NT), wsb, stream, B, w.t0);
   if (generic) launch<T>(k_trsm<T>, G, w.t0, w.t1 - w.t0, work_trsm<T>(bmax), gs, stream, bmax);
+  return err;
+}
+
+// The Schur updates of a wave (after its triangular solves).
+template <typename T>
+void launch_wave_schur(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream) {
+  T* gs = gscratch;
+  const size_t wt = work_tiled<T>() * sizeof(T);
+  const bool tiled = wt <= max_lds_bytes();
+  LevelArgs<T> B = A;
+  if (tiled) B.small_by_wave = 64;
+  const size_t wsb = work_strip_big<T>(bmax);
+  const bool big = tiled && bmax > 64 && A.big && wsb <= max_lds_bytes();
+  LevelArgs<T> G = B;
+  if (big) G.small_by_wave = BG_MAXB;
+  const bool generic = !tiled || (bmax > 64 && (!big || bmax > BG_MAXB));
   if (tiled && w.p1 > w.p0) {
     if (A.bf16_schur && sizeof(T) == sizeof(float))
       hipLaunchKernelGGL(k_schur_bf16<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
@@ -5638,7 +5654,6 @@ hipError_t launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax,
       hipLaunchKernelGGL(k_schur_big<T>, dim3(w.p1 - w.p0), dim3(NT), wt, stream, B, w.p0);
   }
   if (generic) launch<T>(k_schur<T>, G, w.p0, w.p1 - w.p0, work_schur<T>(bmax), gs, stream, bmax);
-  return err;
 }
 
 template <typename T>
@@ -5707,6 +5722,7 @@ void launch_gj_inverse(double* Ad, int64_t dim, double* Pinv, double* W, double*
   template void launch_wave_compress<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);      \
   template hipError_t launch_wave_rest<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t,         \
                                          const SideStream*);                                                \
+  template void launch_wave_schur<T>(const LevelArgs<T>&, const WaveRange&, int, T*, hipStream_t);         \
   template void launch_scatter_a0<T>(T*, const double*, const int64_t*, int64_t, hipStream_t);             \
   template void launch_gather_next<T>(const Trans*, int32_t, const T*, const int64_t*, const int32_t*,     \
                                       const int32_t*, const int32_t*, const int32_t*, T*, const int64_t*,  \

@@ -112,6 +112,9 @@ struct SideStream {
 template <typename T>
 hipError_t launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream,
                             const SideStream* side = nullptr);
+// The Schur updates of a wave, after launch_wave_rest.
+template <typename T>
+void launch_wave_schur(const LevelArgs<T>& A, const WaveRange& w, int bmax, T* gscratch, hipStream_t stream);
 template <typename T>
 void launch_scatter_a0(T* arena, const double* vals, const int64_t* dst, int64_t nnz, hipStream_t stream);
 void launch_theta(const double* vals, const int64_t* diag_pos, int64_t n, double eps, double* out,

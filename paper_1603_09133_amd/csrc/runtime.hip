@@ -276,8 +276,8 @@ struct cae_factor_s {
   DevBuf Ainv, Acopy, vals, theta, err, gscratch, gj_p, gj_w, gj_r, bigbuf;
   double tau = 0, dropped = 0, min_pivot = 0, factor_ms = 0;
   int64_t factor_bytes = 0;
-  int32_t compress_launches = 0, compressions = 0;
-  double compress_ms = 0, compress_flops = 0;
+  int32_t compress_launches = 0, compressions = 0, schur_launches = 0;
+  double compress_ms = 0, compress_flops = 0, schur_ms = 0;
   double rotate_flops = 0, elim_flops = 0, schur_flops = 0, coarse_flops = 0;
   bool flops_pending = false;   // the flop counts are not yet computed
   // apply / multiply / PCG work vectors
@@ -558,7 +558,7 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       HIPCHK(hipMemsetAsync(dbgbuf.p, 0, (size_t)72 * L.M * sizeof(int64_t), s));
       A.dbg = dbgbuf.as<int64_t>();
     }
-    std::vector<hipEvent_t> evs;
+    std::vector<hipEvent_t> evs, sevs;
     for (auto& w : N.waves) {
       if (h->opt.timing && w.s1 > w.s0) {
         hipEvent_t e0, e1;
@@ -573,6 +573,18 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
         cae::launch_wave_compress<T>(A, w, N.bmax, gs, s);
       }
       HIPCHK(cae::launch_wave_rest<T>(A, w, N.bmax, gs, s, &h->side));
+      if (h->opt.timing && w.p1 > w.p0) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+        cae::launch_wave_schur<T>(A, w, N.bmax, gs, s);
+        HIPCHK(hipEventRecord(e1, s));
+        sevs.push_back(e0);
+        sevs.push_back(e1);
+      } else {
+        cae::launch_wave_schur<T>(A, w, N.bmax, gs, s);
+      }
     }
     HIPCHK(hipGetLastError());
     if (dbg_on) {
@@ -676,6 +688,14 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
         h->compress_launches += 1;
         (void)hipEventDestroy(evs[k]);
         (void)hipEventDestroy(evs[k + 1]);
+      }
+      for (size_t k = 0; k < sevs.size(); k += 2) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, sevs[k], sevs[k + 1]));
+        h->schur_ms += ms;
+        h->schur_launches += 1;
+        (void)hipEventDestroy(sevs[k]);
+        (void)hipEventDestroy(sevs[k + 1]);
       }
     }
     h->lev.emplace_back();
@@ -1863,6 +1883,8 @@ static int cae_get_stats_impl(cae_handle_t h, cae_stats_t* st) {
   st->big_frobenius = h->big_count[1];
   st->big_certified = h->big_count[2];
   st->big_uncapped = h->big_count[3];
+  st->schur_launches = h->schur_launches;
+  st->schur_ms = h->schur_ms;
   return CAE_OK;
 }
 
