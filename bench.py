@@ -389,7 +389,7 @@ def main():
         out["roofline_schur"] = {
             "bound": "mfma", "kernel": ("schur: one wave's Schur updates (k_schur_bf16, k_schur_big_bf16, "
                                         "k_schur_big_bf16w, or the FP32 / FP64 forms)"),
-            "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": _traffic("schur"),
             "launches_per_step": main_leg["schur_launches"] / args.steps, "avg_launch_us": per_launch_s * 1e6,
             "algorithmic_flops_per_launch": flops_per_launch}
     if not args.no_cpu_baseline and not batch:
