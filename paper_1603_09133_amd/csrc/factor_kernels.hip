@@ -4681,10 +4681,15 @@ __device__ inline SchurPair<T> schur_pair(const LevelArgs<T>& A, const Pair& pr,
 // (an odd LDS row stride: the transposed views' stores, consecutive rows on
 // consecutive lanes, fall on different banks; the products read along rows)
 constexpr int SB_W = 128, SB_K = 16, SB_LD = SB_W + 1, SB_U = SB_K * SB_W / NT;
+// the wide kernel's chunks in LDS as BF16, [column][k] with k contiguous: one
+// 8-byte read gives a lane its four k values of an MFMA operand; the row
+// stride of 20 (10 dwords) puts the 32 columns of a half-wavefront on
+// distinct banks
+constexpr int SB_KS = SB_K + 4;
 
 template <typename T>
 size_t work_schur_big_bf16() {
-  return (size_t)2 * SB_K * SB_LD * sizeof(T);
+  return (size_t)2 * SB_W * SB_KS * sizeof(short);
 }
 
 // This thread's share of a chunk of one panel: SB_U entries (row k, column
@@ -4745,6 +4750,13 @@ template <typename T>
 __device__ inline void sb_store(const SbShare<T>& s, T* L, const T (&v)[SB_U]) {
 #pragma unroll
   for (int u = 0; u < SB_U; ++u) L[(s.kt + u * s.kstep) * SB_LD + s.ct + u * s.cstep] = v[u];
+}
+
+// the same entries rounded to BF16 once, into the [column][k] layout
+template <typename T>
+__device__ inline void sb_store_bf16(const SbShare<T>& s, short* L, const T (&v)[SB_U]) {
+#pragma unroll
+  for (int u = 0; u < SB_U; ++u) L[(s.ct + u * s.cstep) * SB_KS + s.kt + u * s.kstep] = to_bf16((float)v[u]);
 }
 
 template <typename T>
@@ -4826,8 +4838,8 @@ __global__ __launch_bounds__(NT) void k_schur_big_bf16w(LevelArgs<T> A, int32_t 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l32 = lane & 31, kh = 4 * (lane >> 5);
-  T* Pa = reinterpret_cast<T*>(smem_raw);   // [k][a], SB_K x SB_LD
-  T* Pc = Pa + SB_K * SB_LD;                 // [k][c]
+  short* Pa = reinterpret_cast<short*>(smem_raw);   // [a][k], SB_W x SB_KS (BF16)
+  short* Pc = Pa + SB_W * SB_KS;                     // [c][k]
   const int ra = 64 * (wv >> 1), rc = 64 * (wv & 1);
   for (int a0 = 0; a0 < P.la; a0 += SB_W) {
     const int tan = min(SB_W, P.la - a0);
@@ -4847,8 +4859,8 @@ __global__ __launch_bounds__(NT) void k_schur_big_bf16w(LevelArgs<T> A, int32_t 
       sb_fetch(sc, 0, min(SB_K, n), nc);
       for (int k0 = 0; k0 < n; k0 += SB_K) {
         __syncthreads();   // the previous chunk consumed
-        sb_store(sa, Pa, na);
-        sb_store(sc, Pc, nc);
+        sb_store_bf16(sa, Pa, na);
+        sb_store_bf16(sc, Pc, nc);
         __syncthreads();
         if (k0 + SB_K < n) {
           const int nk2 = min(SB_K, n - k0 - SB_K);
@@ -4861,12 +4873,9 @@ __global__ __launch_bounds__(NT) void k_schur_big_bf16w(LevelArgs<T> A, int32_t 
         for (int kk = 0; kk < SB_K; kk += 8) {
           bf16x4_t av[2], bv[2];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              av[h][t] = to_bf16((float)Pa[(kk + kh + t) * SB_LD + ra + 32 * h + l32]);
-              bv[h][t] = to_bf16((float)Pc[(kk + kh + t) * SB_LD + rc + 32 * h + l32]);
-            }
+          for (int h = 0; h < 2; ++h) {
+            av[h] = *reinterpret_cast<const bf16x4_t*>(Pa + (ra + 32 * h + l32) * SB_KS + kk + kh);
+            bv[h] = *reinterpret_cast<const bf16x4_t*>(Pc + (rc + 32 * h + l32) * SB_KS + kk + kh);
           }
 #pragma unroll
           for (int ti = 0; ti < 2; ++ti)
