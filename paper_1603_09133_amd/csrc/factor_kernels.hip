@@ -3804,11 +3804,13 @@ __global__ __launch_bounds__(NT) void k_bg_gram(LevelArgs<T> A, int32_t s0, int3
     for (int c0 = 0; c0 < w; c0 += 64) {
       const int mc = min(64, w - c0), mc4 = (mc + 3) & ~3;
       __syncthreads();
-      // rows of the chunk k < mc4 (zero from mc on), 64 coordinates (zero
-      // beyond na / nb); the unit-stride index on consecutive threads
-      for (int e = threadIdx.x; e < 64 * mc4; e += NT) {
-        const int k = v.trans ? (e >> 6) : (e % mc4);
-        const int a = v.trans ? (e & 63) : (e / mc4);
+      // rows of the chunk k < mc4 (zero from mc on; a row-major view stages
+      // all 64, so that the indices are shifts, not divisions), 64
+      // coordinates (zero beyond na / nb); the unit-stride index on
+      // consecutive threads
+      for (int e = threadIdx.x; e < (v.trans ? 64 * mc4 : 64 * 64); e += NT) {
+        const int k = v.trans ? (e >> 6) : (e & 63);
+        const int a = v.trans ? (e & 63) : (e >> 6);
         // unconditional loads (the view's first entry outside the chunk)
         const bool oka = k < mc && a < na, okb = k < mc && a < nb;
         const T xa = base[oka ? (v.trans ? (int64_t)(c0 + k) * b + ra + a : (int64_t)(ra + a) * bx + c0 + k) : 0];
@@ -5029,14 +5031,16 @@ __global__ __launch_bounds__(NT) void k_rot_big(LevelArgs<T> A, int32_t it0) {
 }
 
 // D_i <- U_i^T D_i U_i for big steps, stored exactly symmetric, in two
-// launches of one workgroup per (step, column strip), the strips of one step
-// on one XCD: PHASE 0 T1 = U^T D (a strip of D's columns) into the step's FP64
+// launches of one workgroup per (step, 32-column strip; the diagonal blocks
+// run on a side stream beside the views' rotation, and narrow strips let
+// their workgroups find room on the busy compute units), the strips of one
+// step on one XCD: PHASE 0 T1 = U^T D (a strip of D's columns) into the step's FP64
 // scratch; PHASE 1 D = T1 U (a strip of U's columns), the entries (a, c) with
 // a >= c written to both triangles (the strip that holds c writes both, so the
 // strips write disjoint entries).
 template <typename T, int PHASE>
 __global__ __launch_bounds__(NT) void k_rot_big_diag(LevelArgs<T> A, int32_t s0, int32_t nstrip) {
-  constexpr int SW = Strip<T>::SW, LD = Strip<T>::LD, NTJ = Strip<T>::NTJ;
+  constexpr int SW = Strip<T, 32>::SW, LD = Strip<T, 32>::LD, NTJ = Strip<T, 32>::NTJ;
   const int64_t lg = xcd_swizzle(blockIdx.x, gridDim.x);
   const int sx = (int)(lg / nstrip), c0 = (int)(lg % nstrip) * SW;
   const Step st = A.steps[s0 + sx];
@@ -5052,7 +5056,7 @@ __global__ __launch_bounds__(NT) void k_rot_big_diag(LevelArgs<T> A, int32_t s0,
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, fr = lane & 15, fk = lane >> 4;
   const int b4 = (b + 3) & ~3;
   const int tc = min(SW, b - c0);
-  load_strip(X, PHASE == 0 ? (const T*)D : Ug, 0, b, b, 0, b, c0, tc);
+  load_strip<T, 32>(X, PHASE == 0 ? (const T*)D : Ug, 0, b, b, 0, b, c0, tc);
   __syncthreads();
   for (int rb = wv; 16 * rb < b; rb += 4) {
     if (PHASE == 1 && 16 * rb + 15 < c0) continue;   // a block entirely above the diagonal of this strip
@@ -5594,10 +5598,11 @@ hipError_t launch_wave_rest(const LevelArgs<T>& A, const WaveRange& w, int bmax,
     keep(hipStreamWaitEvent(side->s, side->fork, 0));
   }
   if (big && w.s1 > w.s0) {
-    const int nstrip = (std::min(bmax, BG_MAXB) + Strip<T>::SW - 1) / Strip<T>::SW;
+    const int nstrip = (std::min(bmax, BG_MAXB) + 31) / 32;
     const dim3 gd((unsigned)((w.s1 - w.s0) * nstrip));
-    hipLaunchKernelGGL((k_rot_big_diag<T, 0>), gd, dim3(NT), wsb, ds, B, w.s0, nstrip);
-    hipLaunchKernelGGL((k_rot_big_diag<T, 1>), gd, dim3(NT), wsb, ds, B, w.s0, nstrip);
+    const size_t wsd = work_strip_big<T, 32>(bmax);
+    hipLaunchKernelGGL((k_rot_big_diag<T, 0>), gd, dim3(NT), wsd, ds, B, w.s0, nstrip);
+    hipLaunchKernelGGL((k_rot_big_diag<T, 1>), gd, dim3(NT), wsd, ds, B, w.s0, nstrip);
     if (fork) hipLaunchKernelGGL(k_potrf_big<T>, dim3(w.s1 - w.s0), dim3(NT), wpb, ds, B, w.s0);
   }
   if (fork) keep(hipEventRecord(side->join, ds));
