@@ -4033,6 +4033,10 @@ __global__ __launch_bounds__(NT) void k_bg_eig(LevelArgs<T> A, int32_t s0) {
     const int np = (ma + 1) / 2;
     if (np <= 4) nsweep = jacobi_rows_wg<16, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
     else if (np <= 8) nsweep = jacobi_rows_wg<8, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    // rows of 64, 96 or 128 coordinates (those beyond ma are zero): fewer LDS
+    // reads for the steps with fewer pivots, loops of a fixed trip count
+    else if (ma <= 64) nsweep = jacobi_rows_wg<4, 64>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
+    else if (ma <= 96) nsweep = jacobi_rows_wg<4, 96>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
     else nsweep = jacobi_rows_wg<4, BG_MA>(S, BG_SLD, rowix, ma, negl * negl, aerr * aerr, tol);
   }
   __syncthreads();
