@@ -559,6 +559,9 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
       A.dbg = dbgbuf.as<int64_t>();
     }
     std::vector<hipEvent_t> evs, sevs;
+    // (CAE_VERBOSE=2: a progress line every 8 waves, each after the wave has run)
+    static const bool wave_verbose = getenv("CAE_VERBOSE") && getenv("CAE_VERBOSE")[0] == '2';
+    int wave_no = 0;
     for (auto& w : N.waves) {
       if (h->opt.timing && w.s1 > w.s0) {
         hipEvent_t e0, e1;
@@ -584,6 +587,11 @@ int factor_numeric(cae_factor_s* h, const double* vals, double eps) {
         sevs.push_back(e1);
       } else {
         cae::launch_wave_schur<T>(A, w, N.bmax, gs, s);
+      }
+      if (wave_verbose && (++wave_no % 8 == 0 || wave_no == (int)N.waves.size())) {
+        HIPCHK(hipStreamSynchronize(s));
+        fprintf(stderr, "[cae] level %d: wave %d/%zu done, %.1f ms\n", l + 1, wave_no, N.waves.size(),
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
       }
     }
     HIPCHK(hipGetLastError());
