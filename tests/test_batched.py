@@ -115,3 +115,13 @@ def test_batched_analysis_rejects_bad_problems():
     big = problems.laplacian((1100, 4)).tocsr()
     with pytest.raises(cae.CAEError, match="256 patches"):
         batched.analyze([big], [(1100, 4)], [(4, 4)])
+
+
+def test_analysis_of_one_matrix_reports_one_problem():
+    import paper_1603_09133_amd as cae
+    A = problems.laplacian((16, 16))
+    ip, ix, _ = problems.to_csr_arrays(A)
+    perm, bp, co = cae.grid_order((16, 16), (4, 4))
+    an = cae.Analysis(ip, ix, perm, bp, co)
+    assert an.batch_rows().tolist() == [0, A.shape[0]]
+    an.close()
