@@ -12,13 +12,21 @@ the FP64 factor (exact ranks) is timed as a second leg in the same line, and
 the configured arithmetic with exact ranks as a third (what the learned
 ranks gain or lose).
 ``--config c2``: the 2D Laplacian on 1024^2 with 8 x 8 patches, eps = 1e-6,
-16 right-hand sides, FP32 factor and the FP64 leg.
+16 right-hand sides, FP32 factor and the FP64 leg.  ``--config c4``: the
+random-coefficient diffusion on 2048^2, 64 right-hand sides.  ``--config
+c5``: 256 independent 2D and 3D Laplacians in one batched factorization
+with an independent PCG per problem (``cae_factor_batched`` path; its 3D
+problems reach blocks above 512 unknowns at the fourth level).
 
 One step = numeric factorization (all levels, dense remainder) + PCG.  The
 matrix, permutation and right-hand sides are resident on the GPU before the
 timed region; the host symbolic analysis is timed separately
-(``analysis_ms``; ``ms_per_step_with_analysis`` adds it).  Prints ONE JSON
-line on stdout; progress goes to stderr.
+(``analysis_ms``; ``ms_per_step_with_analysis`` adds it).  Besides the
+line's ``roofline`` (the far-row compression, FP64 arithmetic) the line
+carries ``roofline_schur`` (the Schur updates against the matrix-core peak
+of the configured arithmetic), each with the HBM traffic per launch from the
+committed counter summary when it matches the kernel source.  Prints ONE
+JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
