@@ -1344,43 +1344,25 @@ int cae_factor(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const 
 }
 
 // ---------------------------------------------------------------- batches ---
-// Independent problems in one factorization: the joint matrix is block
-// diagonal, each problem keeps its Morton patch order, and problem t's block
-// coordinates are offset by t's binary digits dealt to the three axes in turn
-// above kBatchCoordBits bits, so the Morton interleave of the joint
-// coordinates orders the blocks problem by problem and the coarsening
-// (Section 2.5: parent = coordinate >> 1) never joins blocks of two problems
-// before each is reduced to one block.  Every dependency wave then holds the
-// independent steps of all problems, one launch per wave for the batch.
+// Independent problems in one factorization (the joint block-diagonal
+// problem of cae::batch_assemble): every dependency wave of the joint
+// analysis holds the independent steps of all problems, one launch per wave
+// for the batch.
 namespace {
-constexpr int kBatchCoordBits = 8;
-
-static void batch_offset(int32_t t, int32_t out[3]) {
-  out[0] = out[1] = out[2] = 0;
-  for (int bit = 0; (t >> bit) != 0; ++bit) out[bit % 3] |= ((t >> bit) & 1) << (bit / 3);
-  for (int a = 0; a < 3; ++a) out[a] <<= kBatchCoordBits;
-}
-
-// first row and first stored entry of every problem; CAE_OK or an error
-static int batch_sizes(int32_t nprob, const cae_problem_t* probs, bool need_vals, std::vector<int64_t>& row_off,
+// first row and first stored entry of every problem (after
+// cae::batch_assemble has validated them), and their values; CAE_OK or an error
+int batch_sizes(int32_t nprob, const cae_problem_t* probs, bool need_vals, std::vector<int64_t>& row_off,
                 std::vector<int64_t>& nz_off) {
   if (nprob <= 0 || !probs) return fail(CAE_EINVAL, "nprob > 0 problems are required");
-  if (nprob > (1 << 21)) return fail(CAE_EINVAL, "too many problems for the block-coordinate budget");
   row_off.assign(nprob + 1, 0);
   nz_off.assign(nprob + 1, 0);
   for (int t = 0; t < nprob; ++t) {
     const cae_problem_t& P = probs[t];
-    const std::string who = "problem " + std::to_string(t) + ": ";
-    if (P.ndim != 2 && P.ndim != 3) return fail(CAE_EINVAL, who + "ndim must be 2 or 3");
-    int64_t cells = 1;
-    for (int a = 0; a < P.ndim; ++a) cells *= P.dims[a] > 0 ? P.dims[a] : 0;
-    if (P.n <= 0 || cells != P.n) return fail(CAE_EINVAL, who + "n must be the product of dims");
-    if (!P.row_ptr || !P.col_idx || (need_vals && !P.vals))
-      return fail(CAE_EINVAL, who + "row_ptr, col_idx and vals are required");
+    if (P.n <= 0 || !P.row_ptr || (need_vals && !P.vals))
+      return fail(CAE_EINVAL, "problem " + std::to_string(t) + ": n > 0, row_ptr and vals are required");
     row_off[t + 1] = row_off[t] + P.n;
     nz_off[t + 1] = nz_off[t] + (P.row_ptr[P.n] - P.row_ptr[0]);
   }
-  if (row_off[nprob] >= ((int64_t)1 << 31)) return fail(CAE_EINVAL, "the joint matrix needs 32-bit column indices");
   return CAE_OK;
 }
 }  // namespace
@@ -1388,45 +1370,26 @@ static int batch_sizes(int32_t nprob, const cae_problem_t* probs, bool need_vals
 int cae_analyze_batched(int32_t nprob, const cae_problem_t* probs, const cae_options_t* opt, cae_analysis_t* out) {
   if (!out) return fail(CAE_EINVAL, "out is required");
   *out = nullptr;
+  if (nprob <= 0 || !probs) return fail(CAE_EINVAL, "nprob > 0 problems are required");
   try {
-    std::vector<int64_t> row_off, nz_off;
-    if (int rc = batch_sizes(nprob, probs, false, row_off, nz_off)) return rc;
-    const int64_t n = row_off[nprob], nnz = nz_off[nprob];
-    std::vector<int64_t> rp(n + 1);
-    std::vector<int32_t> ci(nnz), perm(n), bptr, coords;
+    std::vector<cae::BatchProblem> bp(nprob);
     for (int t = 0; t < nprob; ++t) {
-      const cae_problem_t& P = probs[t];
-      const std::string who = "problem " + std::to_string(t) + ": ";
-      const int64_t r0 = row_off[t], z0 = nz_off[t];
-      for (int64_t i = 0; i < P.n; ++i) rp[r0 + i] = z0 + P.row_ptr[i] - P.row_ptr[0];
-      for (int64_t e = 0; e < nz_off[t + 1] - z0; ++e) {
-        const int32_t c = P.col_idx[P.row_ptr[0] + e];
-        if (c < 0 || c >= P.n) return fail(CAE_EINVAL, who + "column index out of range");
-        ci[z0 + e] = (int32_t)(c + r0);
+      bp[t].n = probs[t].n;
+      bp[t].row_ptr = probs[t].row_ptr;
+      bp[t].col_idx = probs[t].col_idx;
+      bp[t].ndim = probs[t].ndim;
+      for (int a = 0; a < 3; ++a) {
+        bp[t].dims[a] = probs[t].dims[a];
+        bp[t].patch[a] = probs[t].patch[a];
       }
-      int32_t patch[3] = {P.patch[0], P.patch[1], P.patch[2]};
-      if (patch[0] == 0 && patch[1] == 0 && patch[2] == 0)
-        for (int a = 0; a < P.ndim; ++a) patch[a] = P.ndim == 2 ? 8 : 4;
-      std::vector<int32_t> p, bp, co;
-      std::string e = cae::grid_order(P.ndim, P.dims, patch, p, bp, co);
-      if (!e.empty()) return fail(CAE_EINVAL, who + e);
-      int32_t off[3];
-      batch_offset(t, off);
-      for (int64_t i = 0; i < P.n; ++i) perm[r0 + i] = (int32_t)(p[i] + r0);
-      const size_t nb = bp.size() - 1;
-      for (size_t k = 0; k < nb; ++k) bptr.push_back((int32_t)(bp[k] + r0));
-      for (size_t k = 0; k < nb; ++k)
-        for (int a = 0; a < 3; ++a) {
-          const int32_t c = a < P.ndim ? co[k * P.ndim + a] : 0;
-          if (c >= (1 << kBatchCoordBits)) return fail(CAE_EINVAL, who + "more than 256 patches along an axis");
-          coords.push_back(c + off[a]);
-        }
     }
-    rp[n] = nnz;
-    bptr.push_back((int32_t)n);
+    std::vector<int64_t> row_off, rp;
+    std::vector<int32_t> ci, perm, bptr, coords;
+    const std::string e = cae::batch_assemble(nprob, bp.data(), row_off, rp, ci, perm, bptr, coords);
+    if (!e.empty()) return fail(CAE_EINVAL, e);
     cae_analysis_t an = nullptr;
-    if (int rc = cae_analyze(n, rp.data(), ci.data(), perm.data(), bptr.data(), (int32_t)bptr.size() - 1, 0,
-                             coords.data(), 3, opt, &an))
+    if (int rc = cae_analyze(row_off[nprob], rp.data(), ci.data(), perm.data(), bptr.data(),
+                             (int32_t)bptr.size() - 1, 0, coords.data(), 3, opt, &an))
       return rc;
     an->batch_off = row_off;
     *out = an;
@@ -1456,11 +1419,12 @@ int cae_factor_batched(int32_t nprob, const cae_problem_t* probs, double eps, co
   if (!out) return fail(CAE_EINVAL, "out is required");
   *out = nullptr;
   try {
-    std::vector<int64_t> row_off, nz_off;
-    if (int rc = batch_sizes(nprob, probs, true, row_off, nz_off)) return rc;
+    // the analysis validates every problem's structure first
     cae_analysis_t an = nullptr;
     if (int rc = cae_analyze_batched(nprob, probs, opt, &an)) return rc;
     std::unique_ptr<cae_analysis_s> own(an);
+    std::vector<int64_t> row_off, nz_off;
+    if (int rc = batch_sizes(nprob, probs, true, row_off, nz_off)) return rc;
     cae_options_t o;
     if (int rc = checked_options(an, eps, opt, o)) return rc;
     hipStream_t st = (hipStream_t)o.stream;

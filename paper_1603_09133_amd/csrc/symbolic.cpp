@@ -655,4 +655,76 @@ std::string analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
   return "";
 }
 
+// ---------------------------------------------------------------- batches ---
+namespace {
+void batch_offset(int32_t t, int32_t out[3]) {
+  out[0] = out[1] = out[2] = 0;
+  for (int bit = 0; (t >> bit) != 0; ++bit) out[bit % 3] |= ((t >> bit) & 1) << (bit / 3);
+  for (int a = 0; a < 3; ++a) out[a] <<= kBatchCoordBits;
+}
+}  // namespace
+
+std::string batch_assemble(int32_t nprob, const BatchProblem* probs, std::vector<int64_t>& row_off,
+                           std::vector<int64_t>& row_ptr, std::vector<int32_t>& col_idx,
+                           std::vector<int32_t>& perm, std::vector<int32_t>& block_ptr,
+                           std::vector<int32_t>& coords) {
+  if (nprob <= 0 || !probs) return "nprob > 0 problems are required";
+  if (nprob > (1 << 21)) return "too many problems for the block-coordinate budget";
+  std::vector<int64_t> nz_off(nprob + 1, 0);
+  row_off.assign(nprob + 1, 0);
+  for (int t = 0; t < nprob; ++t) {
+    const BatchProblem& P = probs[t];
+    const std::string who = "problem " + std::to_string(t) + ": ";
+    if (P.ndim != 2 && P.ndim != 3) return who + "ndim must be 2 or 3";
+    int64_t cells = 1;
+    for (int a = 0; a < P.ndim; ++a) cells *= P.dims[a] > 0 ? P.dims[a] : 0;
+    if (P.n <= 0 || cells != P.n) return who + "n must be the product of dims";
+    if (!P.row_ptr || !P.col_idx) return who + "row_ptr and col_idx are required";
+    if (P.row_ptr[P.n] < P.row_ptr[0]) return who + "row_ptr is not ascending";
+    row_off[t + 1] = row_off[t] + P.n;
+    nz_off[t + 1] = nz_off[t] + (P.row_ptr[P.n] - P.row_ptr[0]);
+  }
+  const int64_t n = row_off[nprob], nnz = nz_off[nprob];
+  if (n >= ((int64_t)1 << 31)) return "the joint matrix needs 32-bit column indices";
+  row_ptr.assign(n + 1, 0);
+  col_idx.assign(nnz, 0);
+  perm.assign(n, 0);
+  block_ptr.clear();
+  coords.clear();
+  for (int t = 0; t < nprob; ++t) {
+    const BatchProblem& P = probs[t];
+    const std::string who = "problem " + std::to_string(t) + ": ";
+    const int64_t r0 = row_off[t], z0 = nz_off[t];
+    for (int64_t i = 0; i < P.n; ++i) {
+      if (P.row_ptr[i + 1] < P.row_ptr[i]) return who + "row_ptr is not ascending";
+      row_ptr[r0 + i] = z0 + P.row_ptr[i] - P.row_ptr[0];
+    }
+    for (int64_t e = 0; e < nz_off[t + 1] - z0; ++e) {
+      const int32_t c = P.col_idx[P.row_ptr[0] + e];
+      if (c < 0 || c >= P.n) return who + "column index out of range";
+      col_idx[z0 + e] = (int32_t)(c + r0);
+    }
+    int32_t patch[3] = {P.patch[0], P.patch[1], P.patch[2]};
+    if (patch[0] == 0 && patch[1] == 0 && patch[2] == 0)
+      for (int a = 0; a < P.ndim; ++a) patch[a] = P.ndim == 2 ? 8 : 4;
+    std::vector<int32_t> p, bp, co;
+    const std::string e = grid_order(P.ndim, P.dims, patch, p, bp, co);
+    if (!e.empty()) return who + e;
+    int32_t off[3];
+    batch_offset(t, off);
+    for (int64_t i = 0; i < P.n; ++i) perm[r0 + i] = (int32_t)(p[i] + r0);
+    const size_t nb = bp.size() - 1;
+    for (size_t k = 0; k < nb; ++k) block_ptr.push_back((int32_t)(bp[k] + r0));
+    for (size_t k = 0; k < nb; ++k)
+      for (int a = 0; a < 3; ++a) {
+        const int32_t c = a < P.ndim ? co[k * P.ndim + a] : 0;
+        if (c >= (1 << kBatchCoordBits)) return who + "more than 256 patches along an axis";
+        coords.push_back(c + off[a]);
+      }
+  }
+  row_ptr[n] = nnz;
+  block_ptr.push_back((int32_t)n);
+  return "";
+}
+
 }  // namespace cae

@@ -67,4 +67,28 @@ std::string analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                     int32_t B, const int32_t* coords, int32_t ndim, int32_t order_kind,
                     Analysis& out, int32_t coarsen_kind = 0);
 
+// One problem of a batch: a matrix on a tensor grid of ndim (2 or 3)
+// dimensions, unknowns numbered with the first axis fastest, level-1 blocks
+// are patches of the given shape (all zero: 8 x 8 or 4 x 4 x 4).
+struct BatchProblem {
+  int64_t n = 0;
+  const int64_t* row_ptr = nullptr;   // n + 1 (row_ptr[0] may be nonzero)
+  const int32_t* col_idx = nullptr;
+  int32_t ndim = 0;
+  int32_t dims[3] = {0, 0, 0};
+  int32_t patch[3] = {0, 0, 0};
+};
+// The joint block-diagonal problem of a batch: problem t's rows follow those
+// of problems 0..t-1 (row_off, nprob + 1 entries), its Morton patch order is
+// kept, and its block coordinates (3 per block) are offset by t's binary
+// digits dealt to the three axes in turn above kBatchCoordBits bits, so the
+// joint Morton order runs problem by problem and the coarsening never joins
+// blocks of two problems before each is one block.  Returns an empty string,
+// or an error that names the problem.
+constexpr int kBatchCoordBits = 8;
+std::string batch_assemble(int32_t nprob, const BatchProblem* probs, std::vector<int64_t>& row_off,
+                           std::vector<int64_t>& row_ptr, std::vector<int32_t>& col_idx,
+                           std::vector<int32_t>& perm, std::vector<int32_t>& block_ptr,
+                           std::vector<int32_t>& coords);
+
 }  // namespace cae

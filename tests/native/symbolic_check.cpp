@@ -109,6 +109,54 @@ int main() {
     CHECK(e.empty());
     check_analysis(A);
   }
+  // a batch of independent 2D and 3D problems joined into one analysis: the
+  // invariants above, and no close or far pair of the first level couples two
+  // problems; invalid problems are reported
+  {
+    const std::vector<std::vector<int>> probs = {{24, 24}, {8, 8, 8}, {17, 9}, {6, 6, 6}};
+    std::vector<std::vector<int64_t>> rps(probs.size());
+    std::vector<std::vector<int32_t>> cis(probs.size());
+    std::vector<cae::BatchProblem> bp(probs.size());
+    for (size_t t = 0; t < probs.size(); ++t) {
+      grid_csr(probs[t], rps[t], cis[t]);
+      bp[t].n = (int64_t)rps[t].size() - 1;
+      bp[t].row_ptr = rps[t].data();
+      bp[t].col_idx = cis[t].data();
+      bp[t].ndim = (int32_t)probs[t].size();
+      for (size_t a = 0; a < probs[t].size(); ++a) {
+        bp[t].dims[a] = probs[t][a];
+        bp[t].patch[a] = probs[t].size() == 2 ? 4 : 2;
+      }
+    }
+    std::vector<int64_t> off, rp;
+    std::vector<int32_t> ci, perm, bptr, co;
+    std::string e = cae::batch_assemble((int32_t)bp.size(), bp.data(), off, rp, ci, perm, bptr, co);
+    CHECK(e.empty());
+    cae::Analysis A;
+    e = cae::analyze(off.back(), rp.data(), ci.data(), perm.data(), bptr.data(), (int32_t)bptr.size() - 1, 0,
+                     co.data(), 3, 1, A, 0);
+    CHECK(e.empty());
+    check_analysis(A);
+    // problem of every level-1 block, from the row its first unknown came from
+    std::vector<int> prob(bptr.size() - 1);
+    for (size_t k = 0; k + 1 < bptr.size(); ++k) {
+      const int64_t row = perm[bptr[k]];
+      prob[k] = (int)(std::upper_bound(off.begin(), off.end(), row) - off.begin()) - 1;
+    }
+    const cae::LevelSym& L0 = A.levels[0];
+    for (size_t q = 0; q < L0.close_pairs.size(); q += 2)
+      CHECK(prob[L0.close_pairs[q]] == prob[L0.close_pairs[q + 1]]);
+    for (size_t q = 0; q < L0.far_pairs.size(); q += 2) CHECK(prob[L0.far_pairs[q]] == prob[L0.far_pairs[q + 1]]);
+    cae::BatchProblem bad = bp[1];
+    bad.dims[2] = 9;   // n is not the product of dims
+    CHECK(!cae::batch_assemble(1, &bad, off, rp, ci, perm, bptr, co).empty());
+    std::vector<int32_t> ci_bad = cis[0];
+    ci_bad[3] = 1 << 20;   // a column index out of range
+    bad = bp[0];
+    bad.col_idx = ci_bad.data();
+    CHECK(!cae::batch_assemble(1, &bad, off, rp, ci, perm, bptr, co).empty());
+    CHECK(!cae::batch_assemble(0, bp.data(), off, rp, ci, perm, bptr, co).empty());
+  }
   // invalid inputs are reported, not read out of bounds
   {
     std::vector<int64_t> rp = {0, 1, 2};

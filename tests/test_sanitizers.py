@@ -1,7 +1,8 @@
 """The host symbolic analysis (integer work on the block graph) built with
 AddressSanitizer and UndefinedBehaviorSanitizer by the host compiler and run
-on several grids, both elimination orders, both coarsenings and a general
-graph; every access out of bounds, use after free, overflow or other
+on several grids, both elimination orders, both coarsenings, a general
+graph and a joined batch of 2D and 3D problems (with invalid ones that must
+be reported); every access out of bounds, use after free, overflow or other
 undefined behaviour aborts the driver (CPU only, no HIP involved)."""
 import os
 import shutil
